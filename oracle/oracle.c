@@ -1,0 +1,326 @@
+/*
+ * FP64 CPU oracle for the hybrid lattice Boltzmann Bloch-Torrey scheme
+ * (Naughton, Tennyson, Georgiadis, arXiv:1907.00908).
+ *
+ * TEST INFRASTRUCTURE.  This file is the slow, plain reference that the HIP
+ * path is checked against.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may call it.  It shares no code with the
+ * HIP library.
+ *
+ * It follows the paper's own formulation: per time step t^k
+ *   1. zeroth moment M = sum_i g_i                      (Eq. M'summation)
+ *      signal E_k = mean of M over the domain             (Sec. 2.1)
+ *   2. BGK collision  ghat_i = g_i - (g_i - w_i M)/tau     (Eqs. collision_LBM,
+ *      g_eq, tau_def)
+ *   3. buffer rows at n = -1 and n = N filled from the post-collision values
+ *      (modified periodic BC, Eq. collision_BC; mirroring BC, Sec. 2.4.4)
+ *   4. streaming gbar_i(x + e_i) = ghat_i(x)             (Eq. streaming_LBM)
+ *      with the half-link membrane condition on links that join two
+ *      different compartments, in place of streaming  (Eqs. B5, P_def,
+ *      permeability_BC)
+ *   5. reaction g_i = g'_i exp(-i gamma (x.G0) f(t^k) dt) exp(-dt/T2)
+ *                                                  (Eqs. reaction_LBM, delta_phi)
+ * and after the last step the signal E_K and the magnetization M.
+ *
+ * Lattice: D3Q7 with eps_D = 1/4, w_0 = 1/4, w_{+-x,+-y,+-z} = 1/8.  The
+ * paper leaves the 3D weights implicit; eps_D = 1/4 is what its Fig. 11
+ * caption requires (tau = 0.58 at D = 2, dt = 0.01, dx = 1), and the weights
+ * extend the D2Q5 pattern w_0 = eps_D, w_i = eps_D/2 (Eq. omega_i) to 3D.
+ *
+ * Readings of the paper taken here:
+ *  - Half-link condition: the second line of Eq. permeability_BC has its
+ *    subscripts exchanged in print; the general form (Eq. B2b with the
+ *    coefficients of Eq. B5) gives
+ *        g'_alpha(x_e) = P/(1+P) ghat_alphabar(x_e) + 1/(1+P) ghat_alpha(x_i),
+ *    i.e. the share 1/(1+P) of the population heading at the membrane
+ *    crosses it and P/(1+P) is reflected back, on both sides.
+ *  - A membrane sits on every link joining two different compartments; its
+ *    permeability is looked up by the two phases (kappa = +inf: no membrane).
+ *  - Modified periodic BC in 3D with an oblique gradient: one phase
+ *    phi_a = L_a (gamma G0)_a F_k per axis, F_k = sum_{m<k} f_m dt
+ *    (Eqs. modified_periodic_BC, periodic_phi, collision_BC).
+ *  - Mirroring BC for a gradient normal to the face: the printed combined
+ *    equation loses a complex conjugate on one line; composing Eqs.
+ *    mirror_periodic_BC and mirror_periodic_BC2 gives
+ *        ghat_i(x_m) = conj( ghat_ibar(x_n) exp(i theta) ),
+ *        theta = gamma (x_n + x_m - 2 x_o).G0 F_k,  origin x_o = 0,
+ *    and for a gradient parallel to the face ghat_i(x_m) = ghat_ibar(x_n).
+ *    The buffer node lies one spacing beyond the face and has the geometry
+ *    of the boundary node.  An oblique gradient on a mirrored axis is not
+ *    defined by the paper; this routine rejects it (the Python wrapper runs
+ *    such cases on the literally reflected and doubled domain instead).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define Q 7
+typedef double complex cplx;
+
+static const int EX[Q][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0},
+                             {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+static const int OPP[Q] = {0, 2, 1, 4, 3, 6, 5};
+static const double W[Q] = {0.25, 0.125, 0.125, 0.125, 0.125, 0.125, 0.125};
+static const double EPS_D = 0.25;
+
+enum { BC_PERIODIC = 0, BC_MIRROR = 1 };
+
+/* direction i reflected in the plane normal to axis a */
+static int reflect_dir(int i, int a) {
+    if (i == 0) return 0;
+    int ax = (i - 1) / 2;
+    return ax == a ? OPP[i] : i;
+}
+
+/* pairwise sum of n complex values: rounding error O(log n) */
+static cplx pairwise_sum(const cplx *v, long n) {
+    if (n <= 8) {
+        cplx s = 0;
+        for (long i = 0; i < n; ++i) s += v[i];
+        return s;
+    }
+    long h = n / 2;
+    return pairwise_sum(v, h) + pairwise_sum(v + h, n - h);
+}
+
+/*
+ * Run K steps of the scheme for one gradient direction.
+ *
+ * n[3]        sites per axis (x fastest), comp[n2][n1][n0] compartment ids
+ * comp_phase  [n_comp] phase of each compartment
+ * bc[3]       0 periodic (modified), 1 mirroring
+ * off[3]      coordinate of node j is (j + off_a) * dx  (origin x_o = 0)
+ * D, T2       [n_phase]; T2 may be +inf
+ * kappa       [n_phase * n_phase] symmetric, um/ms; +inf = no membrane
+ * f           [K] waveform samples, gG0[3] = gamma * G0 in rad/(um ms)
+ * elo, ehi    the box [elo, ehi) over which the signal is averaged
+ * E           out [K+1] complex (interleaved re, im)
+ * M_out       out [n2][n1][n0] complex or NULL
+ * returns 0, or -1 for invalid input, -2 for an unsupported case, -3 OOM
+ */
+int oracle_run(const int32_t n[3], const uint32_t *comp, const uint8_t *comp_phase,
+               int32_t n_comp, int32_t n_phase, const int32_t bc[3],
+               const double off[3], double dx, double dt, int32_t K,
+               const double *D, const double *T2, const double *kappa,
+               const double *f, const double gG0[3], const int32_t elo[3],
+               const int32_t ehi[3], double *E, double *M_out, int32_t nthreads) {
+    const long n0 = n[0], n1 = n[1], n2 = n[2];
+    if (n0 < 1 || n1 < 1 || n2 < 1 || dx <= 0 || dt <= 0 || K < 0) return -1;
+    const long N = n0 * n1 * n2;
+    for (int a = 0; a < 3; ++a) {
+        if (bc[a] != BC_PERIODIC && bc[a] != BC_MIRROR) return -1;
+        if (elo[a] < 0 || ehi[a] > n[a] || elo[a] >= ehi[a]) return -1;
+        if (bc[a] == BC_MIRROR && gG0[a] != 0.0) {
+            for (int b = 0; b < 3; ++b)
+                if (b != a && gG0[b] != 0.0) return -2; /* oblique: not defined */
+        }
+    }
+    for (long s = 0; s < N; ++s)
+        if (comp[s] >= (uint32_t)n_comp) return -1;
+    for (int c = 0; c < n_comp; ++c)
+        if (comp_phase[c] >= n_phase) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+
+    for (int p = 0; p < n_phase; ++p)
+        if (!(D[p] > 0) || !(T2[p] > 0)) return -1;
+    for (int p = 0; p < n_phase * n_phase; ++p)
+        if (!(kappa[p] >= 0)) return -1;
+
+    /* per-phase constants: tau (Eq. tau_def), T2 decay (Eq. reaction_LBM) */
+    double *tau = malloc(sizeof(double) * n_phase);
+    double *decay = malloc(sizeof(double) * n_phase);
+    /* per phase-pair membrane split: reflected P/(1+P), transmitted 1/(1+P)
+       with P = eps_D dx / (2 kappa dt) (Eqs. B5, P_def) */
+    double *refl = malloc(sizeof(double) * n_phase * n_phase);
+    double *trans = malloc(sizeof(double) * n_phase * n_phase);
+    int *has_mem = malloc(sizeof(int) * n_phase * n_phase);
+    for (int p = 0; p < n_phase; ++p) {
+        tau[p] = 0.5 + dt * D[p] / (EPS_D * dx * dx);
+        decay[p] = isinf(T2[p]) ? 1.0 : exp(-dt / T2[p]);
+    }
+    for (int p = 0; p < n_phase * n_phase; ++p) {
+        double k = kappa[p];
+        if (isinf(k)) { has_mem[p] = 0; refl[p] = 0; trans[p] = 1; continue; }
+        has_mem[p] = 1;
+        if (k == 0.0) { refl[p] = 1.0; trans[p] = 0.0; continue; }
+        double P = EPS_D * dx / (2.0 * k * dt);
+        refl[p] = P / (1.0 + P);
+        trans[p] = 1.0 / (1.0 + P);
+    }
+
+    const long p0 = n0 + 2, p1 = n1 + 2, p2 = n2 + 2;
+    const long PN = p0 * p1 * p2;
+    cplx *g = malloc(sizeof(cplx) * Q * N);      /* g_i(x, t^k) */
+    cplx *gh = malloc(sizeof(cplx) * Q * PN);    /* ghat_i with buffer rows */
+    cplx *M = malloc(sizeof(cplx) * N);
+    if (!g || !gh || !M || !tau || !decay || !refl || !trans || !has_mem) return -3;
+    memset(gh, 0, sizeof(cplx) * Q * PN);
+#define IDX(j0, j1, j2) ((j0) + n0 * ((j1) + n1 * (long)(j2)))
+#define PIDX(j0, j1, j2) (((j0) + 1) + p0 * (((j1) + 1) + p1 * (long)((j2) + 1)))
+
+    /* initial condition M = 1 + 0i (Sec. 2.1) as equilibrium populations */
+    for (int i = 0; i < Q; ++i)
+        for (long s = 0; s < N; ++s) g[i * N + s] = W[i];
+
+    /* coordinate of node j on axis a */
+#define COORD(a, j) (((double)(j) + off[a]) * dx)
+    const long ecount = (long)(ehi[0] - elo[0]) * (ehi[1] - elo[1]) * (ehi[2] - elo[2]);
+    cplx *Ebuf = malloc(sizeof(cplx) * ecount);
+    double F = 0.0; /* F_k = sum_{m<k} f_m dt  (Eq. periodic_phi) */
+
+    for (int k = 0; k <= K; ++k) {
+        /* 1. zeroth moment and signal */
+#pragma omp parallel for schedule(static)
+        for (long s = 0; s < N; ++s) {
+            cplx m = 0;
+            for (int i = 0; i < Q; ++i) m += g[i * N + s];
+            M[s] = m;
+        }
+        {
+            long t = 0;
+            for (long j2 = elo[2]; j2 < ehi[2]; ++j2)
+                for (long j1 = elo[1]; j1 < ehi[1]; ++j1)
+                    for (long j0 = elo[0]; j0 < ehi[0]; ++j0) Ebuf[t++] = M[IDX(j0, j1, j2)];
+            cplx e = pairwise_sum(Ebuf, ecount) / (double)ecount;
+            E[2 * k] = creal(e);
+            E[2 * k + 1] = cimag(e);
+        }
+        if (k == K) break;
+
+        /* 2. collision into the interior of the padded array */
+#pragma omp parallel for schedule(static)
+        for (long j2 = 0; j2 < n2; ++j2)
+            for (long j1 = 0; j1 < n1; ++j1)
+                for (long j0 = 0; j0 < n0; ++j0) {
+                    long s = IDX(j0, j1, j2);
+                    int p = comp_phase[comp[s]];
+                    for (int i = 0; i < Q; ++i) {
+                        cplx gi = g[i * N + s];
+                        gh[i * PN + PIDX(j0, j1, j2)] = gi - (gi - W[i] * M[s]) / tau[p];
+                    }
+                }
+
+        /* 3. buffer rows, one axis at a time */
+        for (int a = 0; a < 3; ++a) {
+            const long na = n[a];
+            const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+            const long nb1 = n[b1], nb2 = n[b2];
+            const double phi = (double)na * dx * gG0[a] * F;   /* phi(L_a, t^k) */
+            const cplx wrap_lo = cexp(I * phi), wrap_hi = cexp(-I * phi);
+            const int normal = (gG0[a] != 0.0);  /* gradient normal to face a */
+#pragma omp parallel for schedule(static)
+            for (long u2 = 0; u2 < nb2; ++u2)
+                for (long u1 = 0; u1 < nb1; ++u1) {
+                    long jl[3], jh[3], bl[3], bh[3];
+                    jl[b1] = jh[b1] = bl[b1] = bh[b1] = u1;
+                    jl[b2] = jh[b2] = bl[b2] = bh[b2] = u2;
+                    bl[a] = -1;          /* buffer row below node 0 */
+                    bh[a] = na;          /* buffer row above node N-1 */
+                    for (int i = 0; i < Q; ++i) {
+                        cplx vlo, vhi;
+                        if (bc[a] == BC_PERIODIC) {
+                            /* ghat(x_-1) = e^{+i phi} ghat(x_{N-1});
+                               ghat(x_N) = e^{-i phi} ghat(x_0) */
+                            jl[a] = na - 1;
+                            jh[a] = 0;
+                            vlo = wrap_lo * gh[i * PN + PIDX(jl[0], jl[1], jl[2])];
+                            vhi = wrap_hi * gh[i * PN + PIDX(jh[0], jh[1], jh[2])];
+                        } else {
+                            const int ib = reflect_dir(i, a);
+                            jl[a] = 0;
+                            jh[a] = na - 1;
+                            cplx sl = gh[ib * PN + PIDX(jl[0], jl[1], jl[2])];
+                            cplx sh = gh[ib * PN + PIDX(jh[0], jh[1], jh[2])];
+                            if (normal) {
+                                /* conj(ghat_ibar(x_n) e^{i theta}),
+                                   theta = gamma (x_n + x_m - 2 x_o).G0 F */
+                                double th_lo = gG0[a] * (COORD(a, 0) + COORD(a, -1)) * F;
+                                double th_hi = gG0[a] * (COORD(a, na - 1) + COORD(a, na)) * F;
+                                vlo = conj(sl * cexp(I * th_lo));
+                                vhi = conj(sh * cexp(I * th_hi));
+                            } else {
+                                vlo = sl;
+                                vhi = sh;
+                            }
+                        }
+                        gh[i * PN + PIDX(bl[0], bl[1], bl[2])] = vlo;
+                        gh[i * PN + PIDX(bh[0], bh[1], bh[2])] = vhi;
+                    }
+                }
+        }
+
+        /* 4. streaming with membranes, then 5. reaction */
+        const double fk_dt = f[k] * dt;
+#pragma omp parallel for schedule(static)
+        for (long j2 = 0; j2 < n2; ++j2)
+            for (long j1 = 0; j1 < n1; ++j1)
+                for (long j0 = 0; j0 < n0; ++j0) {
+                    const long s = IDX(j0, j1, j2);
+                    const long jj[3] = {j0, j1, j2};
+                    const uint32_t cx = comp[s];
+                    const int px = comp_phase[cx];
+                    /* reaction factor: exp(-i gamma (x.G0) f_k dt) exp(-dt/T2) */
+                    const double xg = gG0[0] * COORD(0, j0) + gG0[1] * COORD(1, j1)
+                                    + gG0[2] * COORD(2, j2);
+                    const cplx react = cexp(-I * xg * fk_dt) * decay[px];
+                    for (int i = 0; i < Q; ++i) {
+                        long src[3];
+                        int crossed = -1;
+                        for (int a = 0; a < 3; ++a) {
+                            src[a] = jj[a] - EX[i][a];
+                            if (src[a] < 0 || src[a] >= n[a]) crossed = a;
+                        }
+                        cplx gin = gh[i * PN + PIDX(src[0], src[1], src[2])];
+                        /* compartment the streamed population comes from */
+                        uint32_t cs;
+                        if (crossed < 0) {
+                            cs = comp[IDX(src[0], src[1], src[2])];
+                        } else if (bc[crossed] == BC_PERIODIC) {
+                            long w[3] = {src[0], src[1], src[2]};
+                            w[crossed] = (w[crossed] + n[crossed]) % n[crossed];
+                            cs = comp[IDX(w[0], w[1], w[2])];
+                        } else {
+                            cs = cx; /* mirror: buffer node has the boundary node's geometry */
+                        }
+                        cplx gp;
+                        const int pair = px * n_phase + comp_phase[cs];
+                        if (cs != cx && has_mem[pair]) {
+                            /* half-link membrane: transmitted share of the
+                               incoming population plus reflected share of the
+                               outgoing one at this node */
+                            gp = trans[pair] * gin + refl[pair] * gh[OPP[i] * PN + PIDX(j0, j1, j2)];
+                        } else {
+                            gp = gin;
+                        }
+                        g[i * N + s] = gp * react;
+                    }
+                }
+        F += f[k] * dt;
+    }
+    if (M_out) {
+        for (long s = 0; s < N; ++s) {
+            M_out[2 * s] = creal(M[s]);
+            M_out[2 * s + 1] = cimag(M[s]);
+        }
+    }
+    free(g); free(gh); free(M); free(Ebuf);
+    free(tau); free(decay); free(refl); free(trans); free(has_mem);
+    return 0;
+#undef IDX
+#undef PIDX
+#undef COORD
+}
+
+/* relaxation time of Eq. tau_def for the D3Q7 lattice used above */
+double oracle_tau(double D, double dt, double dx) {
+    return 0.5 + dt * D / (EPS_D * dx * dx);
+}

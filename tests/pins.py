@@ -1,0 +1,175 @@
+"""Independent formulations used to pin the oracle (test code only).
+
+Neither function here calls the oracle; each restates the scheme of the
+paper in a different form:
+
+* `plane_wave_E`: in a homogeneous periodic medium the scheme keeps the
+  populations in the form g_i(x) = a_i exp(-i k.x) exactly, so K steps reduce
+  to a 7-vector recurrence (collision on a, pull multiplies a_i by
+  exp(+i k.e_i dx), reaction advances k by gamma G0 f_k dt).
+* `dense_step_matrices`: the whole step as an explicit real matrix of size
+  14N x 14N (real and imaginary parts) for a tiny lattice, built entry by
+  entry from the collision, the boundary/membrane streaming rules and the
+  reaction.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+EPS_D = 0.25
+W = np.array([0.25] + [0.125] * 6)
+E_DIR = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0],
+                  [0, 0, 1], [0, 0, -1]])
+OPP = [0, 2, 1, 4, 3, 6, 5]
+
+
+def _w(D, dt, dx):
+    return 1.0 / (0.5 + dt * D / (EPS_D * dx * dx))
+
+
+def dirichlet_mean(N, theta):
+    """(1/N) sum_{n<N} exp(-i theta n)."""
+    n = np.arange(N)
+    return np.mean(np.exp(-1j * theta * n))
+
+
+def plane_wave_E(n, dx, dt, D, T2, f, gG0):
+    """Signal of the uniform-IC homogeneous periodic problem, all steps."""
+    w = _w(D, dt, dx)
+    decay = 1.0 if math.isinf(T2) else math.exp(-dt / T2)
+    a = W.astype(np.complex128)
+    kvec = np.zeros(3)
+    gG0 = np.asarray(gG0, np.float64)
+    out = []
+    K = len(f)
+    for k in range(K + 1):
+        geo = 1.0 + 0j
+        for ax in range(3):
+            geo *= dirichlet_mean(n[ax], kvec[ax] * dx)
+        out.append(a.sum() * geo)
+        if k == K:
+            break
+        ah = a - w * (a - W * a.sum())
+        a = ah * np.exp(1j * (E_DIR @ kvec) * dx) * decay
+        kvec = kvec + gG0 * f[k] * dt
+    return np.array(out)
+
+
+def _cblock(c, conj=False):
+    cr, ci = c.real, c.imag
+    if conj:
+        return np.array([[cr, ci], [ci, -cr]])
+    return np.array([[cr, -ci], [ci, cr]])
+
+
+def dense_step_matrices(comp, comp_phase, bc, dx, dt, D, T2, kappa, f, gG0):
+    """Real step matrices A_k (one per step) for a tiny lattice.
+
+    State vector: index part*7N + i*N + s, part 0 = Re, 1 = Im, s the site
+    index with x fastest.  Mirror faces use the paper's rule for gradients
+    normal or parallel to the face only.
+    """
+    comp = np.asarray(comp)
+    n2, n1, n0 = comp.shape
+    n = (n0, n1, n2)
+    N = n0 * n1 * n2
+    S7 = 7 * N
+
+    def sidx(j):
+        return j[0] + n0 * (j[1] + n1 * j[2])
+
+    ph = np.asarray(comp_phase)[comp.reshape(-1)]
+    w = np.array([_w(D[p], dt, dx) for p in ph])
+    dec = np.array([1.0 if math.isinf(T2[p]) else math.exp(-dt / T2[p]) for p in ph])
+    # collision (acts identically on Re and Im)
+    C = np.zeros((S7, S7))
+    for s in range(N):
+        for i in range(7):
+            C[i * N + s, i * N + s] += 1.0 - w[s]
+            for j in range(7):
+                C[i * N + s, j * N + s] += w[s] * W[i]
+    Cr = np.kron(np.eye(2), C)
+    mats = []
+    F = 0.0
+    gG0 = np.asarray(gG0, np.float64)
+    for k in range(len(f)):
+        S = np.zeros((2 * S7, 2 * S7))
+
+        def add(dst, src, c, conj=False, scale=1.0):
+            blk = scale * _cblock(c, conj)
+            for pd in range(2):
+                for ps in range(2):
+                    S[pd * S7 + dst, ps * S7 + src] += blk[pd, ps]
+
+        for s in range(N):
+            j = (s % n0, (s // n0) % n1, s // (n0 * n1))
+            cx = comp.reshape(-1)[s]
+            for i in range(7):
+                src = [j[a] - E_DIR[i][a] for a in range(3)]
+                crossed = [a for a in range(3) if not 0 <= src[a] < n[a]]
+                terms = []      # (source flat index, coefficient, conj)
+                if not crossed:
+                    cs = comp.reshape(-1)[sidx(src)]
+                    terms.append((i * N + sidx(src), 1.0 + 0j, False))
+                else:
+                    a = crossed[0]
+                    if bc[a] == 0:
+                        wsrc = list(src)
+                        wsrc[a] %= n[a]
+                        phi = n[a] * dx * gG0[a] * F
+                        c = np.exp(1j * phi) if src[a] < 0 else np.exp(-1j * phi)
+                        cs = comp.reshape(-1)[sidx(wsrc)]
+                        terms.append((i * N + sidx(wsrc), c, False))
+                    else:
+                        cs = cx
+                        ib = OPP[i]          # i is along axis a here
+                        if gG0[a] != 0.0:
+                            xn = j[a] * dx
+                            xm = (j[a] - 1) * dx if src[a] < 0 else (j[a] + 1) * dx
+                            th = gG0[a] * (xn + xm) * F
+                            terms.append((ib * N + s, np.exp(-1j * th), True))
+                        else:
+                            terms.append((ib * N + s, 1.0 + 0j, False))
+                kap = kappa[comp_phase[cx], comp_phase[cs]]
+                if cs != cx and not math.isinf(kap):
+                    if kap == 0.0:
+                        t, r = 0.0, 1.0
+                    else:
+                        P = EPS_D * dx / (2.0 * kap * dt)
+                        t, r = 1.0 / (1.0 + P), P / (1.0 + P)
+                    for (src_i, c, cj) in terms:
+                        add(i * N + s, src_i, c, cj, t)
+                    add(i * N + s, OPP[i] * N + s, 1.0 + 0j, False, r)
+                else:
+                    for (src_i, c, cj) in terms:
+                        add(i * N + s, src_i, c, cj)
+        # reaction
+        R = np.zeros((2 * S7, 2 * S7))
+        for s in range(N):
+            j = (s % n0, (s // n0) % n1, s // (n0 * n1))
+            xg = sum(gG0[a] * j[a] * dx for a in range(3))
+            c = np.exp(-1j * xg * f[k] * dt) * dec[s]
+            blk = _cblock(c)
+            for i in range(7):
+                for pd in range(2):
+                    for ps in range(2):
+                        R[pd * S7 + i * N + s, ps * S7 + i * N + s] = blk[pd, ps]
+        mats.append(R @ S @ Cr)
+        F += f[k] * dt
+    return mats
+
+
+def dense_run(mats, N):
+    """E_k for the uniform initial state, all steps."""
+    S7 = 7 * N
+    v = np.zeros(2 * S7)
+    for i in range(7):
+        v[i * N:(i + 1) * N] = W[i]
+    out = []
+    for k in range(len(mats) + 1):
+        out.append((v[:S7].sum() + 1j * v[S7:].sum()) / N)
+        if k < len(mats):
+            v = mats[k] @ v
+    return np.array(out)

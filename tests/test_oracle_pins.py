@@ -1,0 +1,328 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: values the
+paper prints (tests/golden), closed forms, exact invariants, a plane-wave
+recurrence and a dense brute-force step matrix written independently in
+tests/pins.py, and limiting cases of the membrane condition.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+from tests import pins
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+INF = math.inf
+
+
+def _load(name):
+    with open(os.path.join(GOLD, name)) as fh:
+        return json.load(fh)
+
+
+def test_tau_matches_fig11_caption():
+    g = _load("fig11_tau.json")
+    assert oracle.tau(g["D"], g["dt"], g["dx"]) == pytest.approx(g["tau"], abs=1e-15)
+
+
+def _run(comp, cp, nph, bc, dx, dt, D, T2, kap, f, gG0, **kw):
+    return oracle.simulate(comp, cp, nph, bc, dx, dt, np.asarray(D, float),
+                           np.asarray(T2, float), np.asarray(kap, float), f, gG0, **kw)
+
+
+def test_plane_wave_periodic_oblique():
+    # homogeneous periodic box, non-cubic, oblique gradient, PGSE waveform
+    g = w.uniform((5, 4, 3), 0.5)
+    f = w.pgse_waveform(0.05, 0.2, 0.01)
+    gG0 = np.array([0.9, -0.5, 0.7])
+    E, _ = _run(g.comp, g.comp_phase, 1, [0, 0, 0], 0.5, 0.01, [2.5], [30.0],
+                [[INF]], f, gG0)
+    ref = pins.plane_wave_E((5, 4, 3), 0.5, 0.01, 2.5, 30.0, f, gG0)
+    assert np.max(np.abs(E - ref)) < 1e-13
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_plane_wave_mirror_axis_aligned(axis):
+    # mirroring on every face with an axis-aligned gradient keeps the plane
+    # wave exact: normal faces use the conjugate rule, parallel faces the
+    # plain direction mirror
+    g = w.uniform((6, 5, 4), 0.5)
+    f = w.pgse_waveform(0.04, 0.12, 0.01)
+    gG0 = np.zeros(3)
+    gG0[axis] = 1.3
+    E, _ = _run(g.comp, g.comp_phase, 1, [1, 1, 1], 0.5, 0.01, [1.7], [INF],
+                [[INF]], f, gG0, mirror="paper")
+    ref = pins.plane_wave_E((6, 5, 4), 0.5, 0.01, 1.7, INF, f, gG0)
+    assert np.max(np.abs(E - ref)) < 1e-13
+
+
+def test_uniform_ic_closed_form_cfg1():
+    # exact solution exp(-bD) exp(-TE/T2); the hybrid scheme is second order
+    # in dx, with leading relative error below 1e-3 at dx = 0.5 um
+    gold = _load("uniform_ic_exact.json")
+    cfg = w.make_config("cfg1", n=4)
+    E, _ = oracle.simulate_config(cfg)
+    e = E[0, -1]
+    assert abs(e.imag) < 1e-14
+    assert abs(e.real - gold["E_TE"]) / gold["E_TE"] < 1.5e-3
+    # apparent diffusivity recovered from the signal is the D put in
+    D_app = -math.log(e.real / math.exp(-gold["TE"] / gold["T2"])) / gold["b"]
+    assert D_app == pytest.approx(gold["D"], rel=5e-4)
+
+
+def test_second_order_in_dx_at_fixed_tau():
+    # halve dx with dt ~ dx^2 (tau fixed): the error falls by ~4
+    D, T2 = 2.5, 80.0
+    delta, Delta = 5.0, 20.0
+    exact = math.exp(-1.0 * D) * math.exp(-(delta + Delta) / T2)
+    errs = []
+    for dx in (0.5, 0.25, 0.125):
+        dt = 0.01 * (dx / 0.5) ** 2
+        f = w.pgse_waveform(delta, Delta, dt)
+        gG = w.gamma_g_for_b_pgse(1.0, delta, Delta)
+        g = w.uniform((2, 2, 2), dx)
+        E, _ = _run(g.comp, g.comp_phase, 1, [0, 0, 0], dx, dt, [D], [T2], [[INF]],
+                    f, [gG, 0, 0], want_M=False)
+        errs.append(abs(E[-1].real - exact))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(1.8 < r < 2.2 for r in rates), rates
+
+
+@pytest.mark.parametrize("bc", [[0, 0, 0], [1, 1, 1], [1, 0, 1]])
+def test_pure_T2_decay_any_geometry(bc):
+    # G = 0, one T2 everywhere: E_k = exp(-k dt / T2) for any D, kappa, BC
+    g = w.cylinders_z((12, 10, 3), 0.25, seed=11, vf_target=0.5)
+    f = np.zeros(60)
+    E, _ = _run(g.comp, g.comp_phase, 2, bc, 0.25, 0.004, [2.0, 1.0], [40.0, 40.0],
+                [[INF, 0.02], [0.02, INF]], f, [0, 0, 0])
+    k = np.arange(61)
+    assert np.max(np.abs(E - np.exp(-k * 0.004 / 40.0))) < 1e-14
+
+
+def test_T2_mixture_impermeable():
+    # G = 0, kappa = 0: compartments decay independently with their own T2
+    g = w.cylinders_z((12, 10, 2), 0.25, seed=12, vf_target=0.5)
+    v = g.phase_fractions()
+    f = np.zeros(50)
+    dt = 0.004
+    E, _ = _run(g.comp, g.comp_phase, 2, [0, 0, 0], 0.25, dt, [2.0, 1.0], [40.0, 15.0],
+                [[INF, 0.0], [0.0, INF]], f, [0, 0, 0])
+    k = np.arange(51)
+    ref = v[0] * np.exp(-k * dt / 40.0) + v[1] * np.exp(-k * dt / 15.0)
+    assert np.max(np.abs(E - ref)) < 1e-14
+
+
+@pytest.mark.parametrize("bc", [[0, 0, 0], [1, 1, 1]])
+def test_conservation_after_echo(bc):
+    # T2 = inf: once the PGSE pair has refocused (F = 0) and the gradient is
+    # off, total magnetization is conserved by collision, streaming,
+    # membranes and both outer boundary conditions
+    g = w.cylinders_z((10, 9, 4), 0.25, seed=13, vf_target=0.5)
+    f = np.concatenate([w.pgse_waveform(0.04, 0.1, 0.004), np.zeros(40)])
+    gG0 = [0.0, 3.0, 0.0] if bc[0] == 1 else [2.0, 3.0, -1.0]
+    E, _ = _run(g.comp, g.comp_phase, 2, bc, 0.25, 0.004, [2.0, 1.0], [INF, INF],
+                [[INF, 0.05], [0.05, INF]], f, gG0)
+    K0 = len(f) - 40
+    tail = E[K0:]
+    assert abs(E[K0] - 1.0) > 1e-6          # the gradient did something
+    assert np.max(np.abs(tail - tail[0])) < 1e-14
+
+
+def _tiny_geom():
+    comp = np.zeros((2, 3, 4), np.uint32)
+    comp[:, 1:, 1:3] = 1
+    comp[1, 0, 3] = 2
+    return comp, np.array([0, 1, 1], np.uint8)
+
+
+@pytest.mark.parametrize("case", ["periodic_oblique", "mirror_x", "mirror_mixed"])
+def test_dense_bruteforce(case):
+    comp, cp = _tiny_geom()
+    kap = np.array([[INF, 0.03], [0.03, 0.01]])
+    D, T2 = [2.0, 0.7], [30.0, 12.0]
+    dx, dt = 0.5, 0.01
+    f = np.array([1.0, 1.0, 0.3, 0.0, -0.5, -1.0, -1.0, 0.2])
+    if case == "periodic_oblique":
+        bc, gG0 = [0, 0, 0], np.array([1.1, -0.6, 0.8])
+    elif case == "mirror_x":
+        bc, gG0 = [1, 1, 1], np.array([1.4, 0.0, 0.0])
+    else:
+        bc, gG0 = [1, 0, 1], np.array([0.0, 0.9, 0.0])
+    mats = pins.dense_step_matrices(comp, cp, bc, dx, dt, D, T2, kap, f, gG0)
+    ref = pins.dense_run(mats, comp.size)
+    E, _ = _run(comp, cp, 2, bc, dx, dt, D, T2, kap, f, gG0, mirror="paper")
+    assert np.max(np.abs(E - ref)) < 1e-14
+
+
+def test_dense_matrix_conserves_mass_and_is_stable():
+    comp, cp = _tiny_geom()
+    kap = np.array([[INF, 0.03], [0.03, 0.0]])
+    mats = pins.dense_step_matrices(comp, cp, [0, 1, 0], 0.5, 0.01, [2.0, 0.7],
+                                    [INF, INF], kap, np.zeros(1), np.zeros(3))
+    A = mats[0]
+    S7 = 7 * comp.size
+    colsum = A[:S7, :].sum(axis=0)
+    assert np.allclose(colsum[:S7], 1.0, atol=1e-14)
+    assert np.allclose(colsum[S7:], 0.0, atol=1e-14)
+    assert np.max(np.abs(np.linalg.eigvals(A))) <= 1.0 + 1e-12
+
+
+def test_impermeable_plates_diffraction():
+    # two impermeable plates of width a = 20 dx (membranes on the middle link
+    # and on the periodic wrap), one-step pulses, long separation: the signal
+    # tends to |(1/n) sum_j exp(-i q x_j)|^2, the lattice form of the
+    # narrow-pulse plate result 2(1 - cos qa)/(qa)^2
+    n, dx, dt = 20, 0.25, 0.002
+    D = 2.3
+    g = w.slabs((2 * n, 1, 1), dx, [n])
+    Delta_steps = 50000
+    f = np.zeros(Delta_steps + 1)
+    f[0], f[-1] = 1.0, -1.0
+    a = n * dx
+    for qa in (0.5 * math.pi, math.pi, 2 * math.pi, 3 * math.pi):
+        q = qa / a
+        gG = q / dt
+        E, _ = _run(g.comp, g.comp_phase, 1, [0, 0, 0], dx, dt, [D], [INF],
+                    [[0.0]], f, [gG, 0, 0], want_M=False)
+        lat = abs(np.mean(np.exp(-1j * q * dx * np.arange(n)))) ** 2
+        cont = 2.0 * (1.0 - math.cos(qa)) / qa ** 2
+        assert abs(E[-1] - lat) < 1e-12
+        # lattice vs continuum differ by the factor (th/2)^2 / sin^2(th/2),
+        # th = q dx, i.e. by about th^2/12 relative
+        th = q * dx
+        assert abs(E[-1].real - cont) <= th * th / 8.0 * cont + 1e-14
+
+
+def test_plates_3d_equals_1d():
+    g1 = w.slabs((16, 1, 1), 0.25, [7])
+    g3 = w.slabs((16, 5, 3), 0.25, [7])
+    f = w.pgse_waveform(0.02, 0.1, 0.004)
+    args = ([0, 0, 0], 0.25, 0.004, [2.3], [50.0], [[0.05]], f, [4.0, 0, 0])
+    E1, _ = _run(g1.comp, g1.comp_phase, 1, *args)
+    E3, _ = _run(g3.comp, g3.comp_phase, 1, *args)
+    assert np.max(np.abs(E1 - E3)) < 1e-14
+
+
+def _axon_small(seed=21, shape=(10, 9, 4)):
+    g = w.cylinders_z(shape, 0.25, seed=seed, vf_target=0.5)
+    return g, [2.0, 1.0], [90.0, 70.0], np.array([[INF, 0.02], [0.02, INF]])
+
+
+def test_gradient_reversal_conjugates_signal():
+    g, D, T2, kap = _axon_small()
+    f = w.pgse_waveform(0.04, 0.12, 0.004)
+    G = np.array([3.0, -2.0, 1.0])
+    E1, _ = _run(g.comp, g.comp_phase, 2, [0, 0, 0], 0.25, 0.004, D, T2, kap, f, G)
+    E2, _ = _run(g.comp, g.comp_phase, 2, [0, 0, 0], 0.25, 0.004, D, T2, kap, f, -G)
+    assert np.max(np.abs(E2 - np.conj(E1))) < 1e-14
+
+
+def test_axis_swap_invariance():
+    # exchanging the x and y axes of geometry and gradient leaves E unchanged
+    g, D, T2, kap = _axon_small(shape=(9, 9, 3))
+    f = w.pgse_waveform(0.04, 0.12, 0.004)
+    G = np.array([3.0, -2.0, 1.0])
+    E1, _ = _run(g.comp, g.comp_phase, 2, [0, 0, 0], 0.25, 0.004, D, T2, kap, f, G)
+    comp_sw = np.ascontiguousarray(np.swapaxes(g.comp, 1, 2))
+    E2, _ = _run(comp_sw, g.comp_phase, 2, [0, 0, 0], 0.25, 0.004, D, T2, kap, f,
+                 G[[1, 0, 2]])
+    assert np.max(np.abs(E2 - E1)) < 1e-13
+
+
+def test_periodic_translation_at_echo():
+    # rolling the periodic medium by s rolls the solution by s up to the
+    # quasi-periodic wrap phases; at the echo (F = 0) these vanish, so the
+    # final magnetization is the rolled one and E(TE) is unchanged
+    g, D, T2, kap = _axon_small()
+    dt, dx = 0.004, 0.25
+    f = w.pgse_waveform(0.04, 0.12, dt)
+    G = np.array([3.0, -2.0, 1.5])
+    s = (1, 2, 3)                                  # (z, y, x) shifts
+    E1, M1 = _run(g.comp, g.comp_phase, 2, [0, 0, 0], dx, dt, D, T2, kap, f, G)
+    rolled = np.roll(g.comp, shift=s, axis=(0, 1, 2))
+    E2, M2 = _run(rolled, g.comp_phase, 2, [0, 0, 0], dx, dt, D, T2, kap, f, G)
+    assert abs(E2[-1] - E1[-1]) < 1e-14
+    assert np.max(np.abs(M2 - np.roll(M1, shift=s, axis=(0, 1, 2)))) < 1e-13
+
+
+def test_kappa_inf_equals_no_membrane():
+    g, _, _, _ = _axon_small()
+    f = w.pgse_waveform(0.04, 0.12, 0.004)
+    G = [2.0, 1.0, 0.5]
+    kap = np.full((2, 2), INF)
+    E1, M1 = _run(g.comp, g.comp_phase, 2, [0, 0, 0], 0.25, 0.004, [1.5, 1.5],
+                  [50.0, 50.0], kap, f, G)
+    u = np.zeros_like(g.comp)
+    E2, M2 = _run(u, np.zeros(1, np.uint8), 1, [0, 0, 0], 0.25, 0.004, [1.5], [50.0],
+                  [[INF]], f, G)
+    assert np.array_equal(E1, E2) and np.array_equal(M1, M2)
+
+
+def test_large_kappa_approaches_free_streaming():
+    g, _, _, _ = _axon_small()
+    f = w.pgse_waveform(0.04, 0.12, 0.004)
+    G = [2.0, 1.0, 0.5]
+    E1, _ = _run(g.comp, g.comp_phase, 2, [0, 0, 0], 0.25, 0.004, [1.5, 1.5],
+                 [50.0, 50.0], np.array([[INF, 1e9], [1e9, INF]]), f, G)
+    u = np.zeros_like(g.comp)
+    E2, _ = _run(u, np.zeros(1, np.uint8), 1, [0, 0, 0], 0.25, 0.004, [1.5], [50.0],
+                 [[INF]], f, G)
+    assert np.max(np.abs(E1 - E2)) < 1e-7
+
+
+def test_impermeable_isolates_compartments():
+    # kappa = 0: the extracellular field does not see intracellular D, T2
+    g, D, T2, _ = _axon_small()
+    f = w.pgse_waveform(0.04, 0.12, 0.004)
+    G = [2.0, 1.0, 0.5]
+    kap = np.array([[INF, 0.0], [0.0, INF]])
+    _, M1 = _run(g.comp, g.comp_phase, 2, [0, 0, 0], 0.25, 0.004, [2.0, 1.0],
+                 [90.0, 70.0], kap, f, G)
+    _, M2 = _run(g.comp, g.comp_phase, 2, [0, 0, 0], 0.25, 0.004, [2.0, 0.3],
+                 [90.0, 20.0], kap, f, G)
+    ex = g.phase_volume() == 0
+    assert np.array_equal(M1[ex], M2[ex])
+    assert not np.allclose(M1[~ex], M2[~ex])
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_mirror_rule_equals_reflected_doubling(axis):
+    # the paper's mirror rule (axis-aligned gradient) coincides with the
+    # medium reflected and doubled across every mirrored face
+    g, D, T2, kap = _axon_small(shape=(8, 7, 3))
+    f = w.pgse_waveform(0.04, 0.12, 0.004)
+    G = np.zeros(3)
+    G[axis] = 4.0
+    E1, M1 = _run(g.comp, g.comp_phase, 2, [1, 1, 1], 0.25, 0.004, D, T2, kap, f, G,
+                  mirror="paper")
+    E2, M2 = _run(g.comp, g.comp_phase, 2, [1, 1, 1], 0.25, 0.004, D, T2, kap, f, G,
+                  mirror="double")
+    assert np.max(np.abs(E1 - E2)) < 1e-13
+    assert np.max(np.abs(M1 - M2)) < 1e-13
+
+
+def test_oblique_mirror_is_rejected_by_paper_rule():
+    g, D, T2, kap = _axon_small(shape=(6, 6, 2))
+    with pytest.raises(NotImplementedError):
+        _run(g.comp, g.comp_phase, 2, [1, 1, 1], 0.25, 0.004, D, T2, kap,
+             np.ones(3), [1.0, 1.0, 0.0], mirror="paper")
+
+
+def test_z_invariance_oblique_gradient():
+    # z-aligned permeable cylinders, periodic on all faces, oblique gradient:
+    # |M| has no z dependence, and at the echo M itself has none (Sec. 3.2)
+    g = w.cylinders_z((11, 11, 5), 1.0, seed=31, vf_target=0.5, mean_r=2.5)
+    dt = 0.025
+    f = w.pgse_waveform(0.2, 0.6, dt)
+    G = np.ones(3) / math.sqrt(3.0) * 0.8
+    E, M = _run(g.comp, g.comp_phase, 2, [0, 0, 0], 1.0, dt, [2.0, 1.5], [10.0, 30.0],
+                np.array([[INF, 0.01], [0.01, INF]]), f, G)
+    assert np.max(np.abs(M - M[0:1])) < 1e-14
+    _, Mh = _run(g.comp, g.comp_phase, 2, [0, 0, 0], 1.0, dt, [2.0, 1.5], [10.0, 30.0],
+                 np.array([[INF, 0.01], [0.01, INF]]), f[:12], G)
+    assert np.max(np.abs(np.abs(Mh) - np.abs(Mh[0:1]))) < 1e-14

@@ -1,0 +1,321 @@
+"""Seeded compartment-label volumes (inputs only).
+
+A geometry is a volume of compartment ids (uint32, array shape (n2, n1, n0),
+x fastest) plus a table mapping each compartment to a phase (uint8).  A
+phase carries one set of material parameters (D, T2); every lattice link
+joining two different compartments carries a membrane whose permeability is
+looked up by the pair of phases.  This is how the paper's piecewise-uniform
+media with thin membranes (Sec. 2.1, Fig. 1) and its cell-to-cell membranes
+in histology-derived domains (Sec. 3.6) are represented on a label volume.
+
+Lattice node j along an axis sits at x = j*dx; a box of n nodes has length
+L = n*dx (the node at n is the periodic image of node 0, Sec. 2.4.3).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Geometry:
+    comp: np.ndarray            # uint32, shape (n2, n1, n0)
+    comp_phase: np.ndarray      # uint8, shape (C,)
+    n_phase: int
+    dx: float
+    info: dict = field(default_factory=dict)
+
+    @property
+    def shape_xyz(self):
+        n2, n1, n0 = self.comp.shape
+        return (n0, n1, n2)
+
+    @property
+    def n_sites(self) -> int:
+        return int(self.comp.size)
+
+    def phase_volume(self) -> np.ndarray:
+        return self.comp_phase[self.comp]
+
+    def phase_fractions(self) -> np.ndarray:
+        pv = self.phase_volume()
+        return np.bincount(pv.ravel(), minlength=self.n_phase) / pv.size
+
+
+def _shape3(n):
+    if np.isscalar(n):
+        return (int(n),) * 3
+    n = tuple(int(v) for v in n)
+    if len(n) != 3:
+        raise ValueError("n must be an int or (n0, n1, n2)")
+    return n
+
+
+def uniform(n, dx: float) -> Geometry:
+    """Single compartment, single phase."""
+    n0, n1, n2 = _shape3(n)
+    comp = np.zeros((n2, n1, n0), dtype=np.uint32)
+    return Geometry(comp, np.zeros(1, np.uint8), 1, float(dx),
+                    {"kind": "uniform"})
+
+
+def slabs(n, dx: float, cuts_x, phases=None) -> Geometry:
+    """Slabs stacked along x: compartment c covers cuts_x[c-1] <= j0 < cuts_x[c].
+
+    With a periodic x axis the last and first slab are also separated by the
+    wrap link; a single cut list [] gives one slab whose only membrane is the
+    wrap link when the two sides are given different compartments.
+    """
+    n0, n1, n2 = _shape3(n)
+    cuts = [0] + sorted(int(c) for c in cuts_x) + [n0]
+    comp1 = np.zeros(n0, dtype=np.uint32)
+    for c in range(len(cuts) - 1):
+        comp1[cuts[c]:cuts[c + 1]] = c
+    comp = np.broadcast_to(comp1[None, None, :], (n2, n1, n0)).copy()
+    nc = len(cuts) - 1
+    ph = np.zeros(nc, np.uint8) if phases is None else np.asarray(phases, np.uint8)
+    return Geometry(comp, ph, int(ph.max()) + 1, float(dx), {"kind": "slabs"})
+
+
+def _relax_disks(rng, L, radii, gap, periodic, max_iter=20000):
+    """Random positions, then push overlapping disks apart until every pair
+    is separated by at least `gap` (or give up and drop offenders)."""
+    n = len(radii)
+    pos = rng.uniform(0.0, 1.0, size=(n, 2)) * np.asarray(L)
+    r = np.asarray(radii)
+    need = r[:, None] + r[None, :] + gap
+    np.fill_diagonal(need, 0.0)
+    Lv = np.asarray(L, dtype=np.float64)
+    for _ in range(max_iter):
+        d = pos[None, :, :] - pos[:, None, :]          # j - i
+        if periodic:
+            d -= Lv * np.round(d / Lv)
+        dist = np.sqrt(np.sum(d * d, axis=-1))
+        np.fill_diagonal(dist, np.inf)
+        ov = need - dist
+        np.fill_diagonal(ov, -1.0)
+        if ov.max() <= 1e-9:
+            return pos, np.ones(n, bool)
+        m = ov > 0
+        with np.errstate(invalid="ignore", divide="ignore"):
+            u = d / dist[..., None]
+        u[~m] = 0.0
+        push = 0.5 * (ov * m)[..., None] * 1.01 * u
+        # i moves away from j: -push; j receives +push from i
+        disp = -push.sum(axis=1)
+        pos += disp
+        if periodic:
+            pos %= Lv
+        else:
+            pos = np.clip(pos, 0.0, Lv)
+    # could not separate everything: drop disks that still overlap
+    keep = np.ones(n, bool)
+    d = pos[None, :, :] - pos[:, None, :]
+    if periodic:
+        d -= Lv * np.round(d / Lv)
+    dist = np.sqrt(np.sum(d * d, axis=-1))
+    np.fill_diagonal(dist, np.inf)
+    ov = need - dist
+    for i in np.argsort(r):                             # smallest first
+        if not keep[i]:
+            continue
+        if np.any((ov[i] > 1e-9) & keep):
+            keep[i] = False
+    return pos, keep
+
+
+def _raster_disks(n0, n1, dx, pos, radii, periodic, ids):
+    """2D label image (n1, n0): site (j0, j1) at (j0*dx, j1*dx)."""
+    img = np.zeros((n1, n0), dtype=np.uint32)
+    L = np.array([n0 * dx, n1 * dx])
+    for (cx, cy), r, cid in zip(pos, radii, ids):
+        shifts = [(0.0, 0.0)]
+        if periodic:
+            shifts = [(sx * L[0], sy * L[1]) for sx in (-1, 0, 1) for sy in (-1, 0, 1)]
+        for sx, sy in shifts:
+            x0, y0 = cx + sx, cy + sy
+            i0 = max(0, int(math.floor((x0 - r) / dx)))
+            i1 = min(n0 - 1, int(math.ceil((x0 + r) / dx)))
+            k0 = max(0, int(math.floor((y0 - r) / dx)))
+            k1 = min(n1 - 1, int(math.ceil((y0 + r) / dx)))
+            if i0 > i1 or k0 > k1:
+                continue
+            xs = np.arange(i0, i1 + 1) * dx - x0
+            ys = np.arange(k0, k1 + 1) * dx - y0
+            inside = (xs[None, :] ** 2 + ys[:, None] ** 2) < r * r
+            sub = img[k0:k1 + 1, i0:i1 + 1]
+            sub[inside] = cid
+    return img
+
+
+def cylinders_z(n, dx: float, seed: int, vf_target: float = 0.6,
+                gamma_shape: float = 4.0, mean_r: float = 1.0,
+                periodic: bool = True, gap: float | None = None) -> Geometry:
+    """Parallel cylinders along z in an extracellular matrix.
+
+    Radii ~ Gamma(shape, mean) redrawn below 2*dx; disks are drawn until
+    their area reaches the target, placed at random and relaxed apart so that
+    surfaces are at least `gap` (default dx) apart, largest first when some
+    have to be dropped.  Phase 0 = extracellular, phase 1 = intracellular;
+    each cylinder is its own compartment (ids 1..).  With gap >= dx no two
+    cylinders share a lattice link, so every membrane link is in/ex.
+    """
+    n0, n1, n2 = _shape3(n)
+    rng = np.random.default_rng(seed)
+    gap = dx if gap is None else float(gap)
+    L = (n0 * dx, n1 * dx)
+    target = vf_target * L[0] * L[1]
+    radii = []
+    area = 0.0
+    scale = mean_r / gamma_shape
+    while area < target:
+        r = rng.gamma(gamma_shape, scale)
+        while r < 2.0 * dx:
+            r = rng.gamma(gamma_shape, scale)
+        radii.append(r)
+        area += math.pi * r * r
+    radii = np.sort(np.asarray(radii))[::-1]
+    # placement always uses periodic distances; a non-periodic (mirror) box
+    # then simply cuts the cylinders that cross its faces
+    pos, keep = _relax_disks(rng, L, radii, gap, True)
+    pos, radii = pos[keep], radii[keep]
+    ids = np.arange(1, len(radii) + 1, dtype=np.uint32)
+    img = _raster_disks(n0, n1, dx, pos, radii, periodic, ids)
+    comp = np.broadcast_to(img[None, :, :], (n2, n1, n0)).copy()
+    comp_phase = np.ones(len(radii) + 1, np.uint8)
+    comp_phase[0] = 0
+    g = Geometry(comp, comp_phase, 2, float(dx),
+                 {"kind": "cylinders_z", "seed": seed, "n_cyl": int(len(radii)),
+                  "vf_target": vf_target, "periodic": periodic})
+    g.info["vf_voxel"] = float(g.phase_fractions()[1])
+    return g
+
+
+def cylinders_spheres(n, dx: float, seed: int, vf_cyl: float = 0.4,
+                      vf_sph: float = 0.15, r_sph=(2.0, 6.0)) -> Geometry:
+    """Periodic z-cylinders (as `cylinders_z`) to vf_cyl, then spheres with
+    radius ~ U(r_sph) placed without mutual overlap until they add vf_sph;
+    a sphere replaces whatever it covers.  Phases: 0 extracellular,
+    1 cylinder interior, 2 sphere interior."""
+    n0, n1, n2 = _shape3(n)
+    base = cylinders_z((n0, n1, n2), dx, seed, vf_target=vf_cyl, periodic=True)
+    rng = np.random.default_rng(seed + 7919)
+    comp = base.comp.copy()
+    nc = len(base.comp_phase)
+    L = np.array([n0, n1, n2], dtype=np.float64) * dx
+    target = vf_sph * float(np.prod(L))
+    placed = []
+    vol = 0.0
+    tries = 0
+    while vol < target and tries < 200000:
+        tries += 1
+        r = rng.uniform(*r_sph)
+        c = rng.uniform(0.0, 1.0, 3) * L
+        ok = True
+        for (c2, r2) in placed:
+            d = c - c2
+            d -= L * np.round(d / L)
+            if np.sqrt(np.dot(d, d)) < r + r2 + dx:
+                ok = False
+                break
+        if ok:
+            placed.append((c, r))
+            vol += 4.0 / 3.0 * math.pi * r ** 3
+    ax = [np.arange(m) * dx for m in (n0, n1, n2)]
+    for s, (c, r) in enumerate(placed):
+        cid = nc + s
+        sl, coords = [], []
+        for a in range(3):
+            lo = int(math.floor((c[a] - r) / dx))
+            hi = int(math.ceil((c[a] + r) / dx))
+            idx = np.arange(lo, hi + 1)
+            coords.append(idx * dx - c[a])
+            sl.append(np.mod(idx, (n0, n1, n2)[a]))
+        inside = (coords[2][:, None, None] ** 2 + coords[1][None, :, None] ** 2
+                  + coords[0][None, None, :] ** 2) < r * r
+        zz, yy, xx = np.nonzero(inside)
+        comp[sl[2][zz], sl[1][yy], sl[0][xx]] = cid
+    comp_phase = np.concatenate([base.comp_phase,
+                                 np.full(len(placed), 2, np.uint8)])
+    g = Geometry(comp, comp_phase, 3, float(dx),
+                 {"kind": "cylinders_spheres", "seed": seed,
+                  "n_cyl": base.info["n_cyl"], "n_sph": len(placed)})
+    fr = g.phase_fractions()
+    g.info["vf_voxel"] = [float(v) for v in fr]
+    return g
+
+
+def _rand_rotation(rng):
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def ellipsoid_cells(n, dx: float, seed: int, vf_target: float = 0.5,
+                    semi=(3.0, 8.0), max_tries: int = 20000) -> Geometry:
+    """Randomly oriented ellipsoidal cells with a concentric nucleus of half
+    the semi-axes, periodic box, at least one empty voxel between cells.
+
+    Phases: 0 extracellular, 1 cytoplasm, 2 nucleus.  Cell c has cytoplasm
+    compartment 2c+1 and nucleus compartment 2c+2.
+    """
+    n0, n1, n2 = _shape3(n)
+    dims = (n0, n1, n2)
+    rng = np.random.default_rng(seed)
+    comp = np.zeros((n2, n1, n0), dtype=np.uint32)
+    occ = np.zeros((n2, n1, n0), dtype=bool)      # cells dilated by one voxel
+    L = np.array(dims, dtype=np.float64) * dx
+    target = vf_target * comp.size
+    filled = 0
+    ncell = 0
+    tries = 0
+    while filled < target and tries < max_tries:
+        tries += 1
+        ax = rng.uniform(semi[0], semi[1], 3)
+        R = _rand_rotation(rng)
+        c = rng.uniform(0.0, 1.0, 3) * L
+        A = R @ np.diag(1.0 / ax ** 2) @ R.T        # x^T A x < 1 inside
+        ext = np.sqrt(np.diag(np.linalg.inv(A)))     # bounding half-widths
+        idx, rel = [], []
+        for a in range(3):
+            lo = int(math.floor((c[a] - ext[a]) / dx)) - 1
+            hi = int(math.ceil((c[a] + ext[a]) / dx)) + 1
+            j = np.arange(lo, hi + 1)
+            idx.append(np.mod(j, dims[a]))
+            rel.append(j * dx - c[a])
+        X = rel[0][None, None, :]
+        Y = rel[1][None, :, None]
+        Z = rel[2][:, None, None]
+        qf = (A[0, 0] * X * X + A[1, 1] * Y * Y + A[2, 2] * Z * Z
+              + 2 * A[0, 1] * X * Y + 2 * A[0, 2] * X * Z + 2 * A[1, 2] * Y * Z)
+        inside = qf < 1.0
+        if not inside.any():
+            continue
+        sub = np.ix_(idx[2], idx[1], idx[0])
+        if np.any(occ[sub] & inside):
+            continue
+        nuc = qf < 0.25                                # half semi-axes
+        block = comp[sub]
+        block[inside] = 2 * ncell + 1
+        block[nuc] = 2 * ncell + 2
+        comp[sub] = block
+        dil = inside.copy()
+        for a in range(3):
+            dil |= np.roll(inside, 1, axis=a) | np.roll(inside, -1, axis=a)
+        o = occ[sub]
+        o |= dil
+        occ[sub] = o
+        filled += int(inside.sum())
+        ncell += 1
+    comp_phase = np.zeros(2 * ncell + 1, np.uint8)
+    comp_phase[1::2] = 1
+    comp_phase[2::2] = 2
+    g = Geometry(comp, comp_phase, 3, float(dx),
+                 {"kind": "ellipsoid_cells", "seed": seed, "n_cell": ncell})
+    g.info["vf_voxel"] = [float(v) for v in g.phase_fractions()]
+    return g
