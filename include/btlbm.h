@@ -1,0 +1,138 @@
+/*
+ * btlbm -- hybrid lattice Boltzmann solver of the Bloch-Torrey equation for
+ * diffusion MRI in multiphase tissue (Naughton, Tennyson, Georgiadis,
+ * arXiv:1907.00908), on AMD Instinct MI355X (gfx950).
+ *
+ * One call to btl_forward advances the complex transverse magnetization of
+ * Q gradient samples ("q-samples") for K time steps on a D3Q7 lattice and
+ * returns the signal after every step.  Each step is the paper's hybrid
+ * scheme (Sec. 2.3, Eq. LBM_process_list_2):
+ *   - BGK collision, g_eq = w_i M, tau = 1/2 + dt D / (eps_D dx^2),
+ *     eps_D = 1/4, w_0 = 1/4, w_1..6 = 1/8      (Eqs. collision_LBM, g_eq, tau_def)
+ *   - streaming                                  (Eq. streaming_LBM)
+ *     with modified periodic outer faces        (Sec. 2.4.3, Eq. collision_BC)
+ *     or mirroring outer faces                   (Sec. 2.4.4)
+ *     and the half-link membrane condition on every link that joins two
+ *     different compartments                    (Sec. 2.4.2, Eqs. B5, P_def,
+ *                                                 permeability_BC)
+ *   - reaction: gradient phase exp(-i gamma (x.G0) f_k dt) and T2 decay
+ *     exp(-dt/T2)                                (Eqs. reaction_LBM, delta_phi)
+ *   - signal E_k = mean over the REV of M = sum_i g_i  (Sec. 2.1, Eq. M'summation)
+ * with M = 1 + 0i at t = 0 (Sec. 2.1).
+ *
+ * Units: um, ms.  D in um^2/ms, T2 in ms, permeability kappa in um/ms, the
+ * gradient as gamma*G0 in rad/(um*ms).  Lattice node j on an axis sits at
+ * x = j*dx (the origin, where G0.x = 0, is node 0).
+ *
+ * Mirroring faces with a gradient that is oblique to them (a case the paper
+ * leaves open, Sec. 2.4.4) are computed as the reflected medium: the REV
+ * mirrored across the face and tiled periodically.  The solver carries the
+ * needed reflected copies of the field ("image fields", up to 4 per q-sample)
+ * internally; for a gradient normal or parallel to the face this reduces
+ * exactly to the paper's rule.
+ *
+ * Memory and streams: every pointer documented as "device" must be device
+ * memory of the current HIP device; all work is enqueued on the given
+ * hipStream_t (pass NULL for the null stream) and is asynchronous unless
+ * stated otherwise.  Host pointers are read before the call returns.
+ *
+ * Errors: functions return a btl_status; nothing unwinds across this
+ * interface.  btl_last_error returns a text describing the last failure of
+ * that simulator.  A simulator is not thread-safe: use one per host thread.
+ */
+#ifndef BTLBM_H
+#define BTLBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct btl_sim btl_sim;
+
+typedef enum {
+    BTL_OK = 0,
+    BTL_E_INVAL = 1,        /* invalid argument (message says which) */
+    BTL_E_UNSUPPORTED = 2,  /* valid request this build does not implement */
+    BTL_E_NOMEM = 3,        /* device memory exhausted */
+    BTL_E_HIP = 4,          /* a HIP runtime call failed */
+    BTL_E_NONFINITE = 5     /* a non-finite value was produced */
+} btl_status;
+
+enum { BTL_PERIODIC = 0, BTL_MIRROR = 1 };   /* outer boundary per axis */
+enum { BTL_F64 = 0, BTL_F32 = 1 };           /* population storage precision */
+
+/* One geometry: a compartment-label volume.  Every lattice link joining two
+ * different compartments carries a membrane whose permeability is chosen by
+ * the phases of the two compartments (Sec. 2.4.2; cell-to-cell membranes of
+ * Sec. 3.6 are links between different compartments of one phase).  The
+ * pointers are host memory and are copied by btl_create. */
+typedef struct {
+    int32_t n[3];               /* sites per axis, x fastest; each >= 2 */
+    double dx;                  /* lattice spacing, um, > 0 */
+    int32_t bc[3];              /* BTL_PERIODIC or BTL_MIRROR per axis */
+    int32_t n_comp;             /* number of compartments C >= 1 */
+    const uint32_t *comp_id;    /* host [n2][n1][n0], values < C */
+    const uint8_t *comp_phase;  /* host [C], values < n_phase */
+    int32_t n_phase;            /* number of material phases P, 1..64 */
+} btl_geom;
+
+/* Create a simulator for n_geom geometries (all with the same dx and
+ * n_phase; sizes may differ: q-samples of all geometries run in one batch).
+ * prec selects FP64 or FP32 population storage; arithmetic inside a step is
+ * FP64 in both, and the signal sums are FP64.  On success *out owns all
+ * device memory of the simulator; free it with btl_destroy.
+ * Errors: BTL_E_INVAL (bad geometry), BTL_E_NOMEM, BTL_E_HIP. */
+btl_status btl_create(const btl_geom *geoms, int32_t n_geom, int32_t prec,
+                      btl_sim **out);
+
+/* Run K steps for Q q-samples.
+ *   dt      time step, ms, > 0
+ *   D, T2   host [P] per-phase diffusivity (> 0) and T2 (> 0, +inf allowed)
+ *   kappa   host [P*P] symmetric membrane permeability per phase pair,
+ *           >= 0; +inf means no membrane between those phases
+ *   q_geom  host [Q] geometry index of each q-sample
+ *   gG0     host [Q][3] gamma*G0 of each q-sample
+ *   f       host [K] waveform sample f_k applied on [k dt, (k+1) dt)
+ *           (the same waveform for all q-samples)
+ *   E       device [Q][K+1][2] doubles, caller-allocated: E[q][k] is the
+ *           complex signal at t = k dt, E[q][0] = 1
+ *   M_final device or NULL: the magnetization at t = K dt of every q-sample,
+ *           complex in the storage precision (float2 or double2), q-samples
+ *           concatenated, each [n2][n1][n0]
+ *   ckpt_every  0: no adjoint tape; > 0: keep the state every ckpt_every
+ *           steps so that btl_backward can run afterwards
+ *   stream  hipStream_t or NULL
+ * Errors: BTL_E_INVAL, BTL_E_NOMEM, BTL_E_HIP. */
+btl_status btl_forward(btl_sim *s, double dt, int32_t K, const double *D,
+                       const double *T2, const double *kappa, int32_t Q,
+                       const int32_t *q_geom, const double *gG0, const double *f,
+                       double *E, void *M_final, int32_t ckpt_every, void *stream);
+
+/* Gradients of a real loss L with respect to the inputs of the last
+ * btl_forward that kept a tape (ckpt_every > 0).  dL_dE is device
+ * [Q][K+1][2] with dL/dE = dL/dRe E + i dL/dIm E.  Outputs are device
+ * doubles, overwritten (NULL = not wanted): dD [P], dT2 [P], dkappa [P*P]
+ * (the symmetric pair's gradient is reported in both [a][b] and [b][a],
+ * each holding the full value), df [K].
+ * Errors: BTL_E_INVAL (no tape), BTL_E_NOMEM, BTL_E_HIP. */
+btl_status btl_backward(btl_sim *s, const double *dL_dE, double *dD, double *dT2,
+                        double *dkappa, double *df, void *stream);
+
+/* Time the candidate launch shapes on Q q-samples for K_probe steps and keep
+ * the fastest for this simulator (synchronizes the stream). */
+btl_status btl_autotune(btl_sim *s, int32_t Q, int32_t K_probe, void *stream);
+
+/* Release all memory of the simulator (synchronizes the device). */
+void btl_destroy(btl_sim *s);
+
+/* Text of the last error of s (or of the last failed btl_create when s is
+ * NULL).  Owned by the library; valid until the next call on s. */
+const char *btl_last_error(const btl_sim *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BTLBM_H */

@@ -1,0 +1,219 @@
+"""Python binding of libbtlbm (hybrid LBM Bloch-Torrey solver for gfx950).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libbtlbm.so.  The functions `btl_create`, `btl_forward`,
+`btl_backward`, `btl_autotune`, `btl_destroy` and `btl_last_error` mirror the
+C ABI of include/btlbm.h one to one.  `Simulator` wraps them with torch
+tensors for device memory and the current torch stream.
+
+There is no CPU fallback: if libbtlbm.so is missing or fails to load, every
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbtlbm.so")
+
+BTL_OK, BTL_E_INVAL, BTL_E_UNSUPPORTED, BTL_E_NOMEM, BTL_E_HIP, BTL_E_NONFINITE = range(6)
+BTL_PERIODIC, BTL_MIRROR = 0, 1
+BTL_F64, BTL_F32 = 0, 1
+
+EXPORTED = ("btl_create", "btl_forward", "btl_backward", "btl_autotune",
+            "btl_destroy", "btl_last_error")
+
+
+class BtlError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"btl status {status}: {msg}")
+        self.status = status
+
+
+class btl_geom(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("dx", ctypes.c_double),
+                ("bc", ctypes.c_int32 * 3), ("n_comp", ctypes.c_int32),
+                ("comp_id", ctypes.c_void_p), ("comp_phase", ctypes.c_void_p),
+                ("n_phase", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libbtlbm.so and declare its signatures (raises if missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_1907_00908_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, i32, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    lib.btl_create.argtypes = [ctypes.POINTER(btl_geom), i32, i32, ctypes.POINTER(P)]
+    lib.btl_create.restype = ctypes.c_int
+    lib.btl_forward.argtypes = [P, d, i32, P, P, P, i32, P, P, P, P, P, i32, P]
+    lib.btl_forward.restype = ctypes.c_int
+    lib.btl_backward.argtypes = [P, P, P, P, P, P, P]
+    lib.btl_backward.restype = ctypes.c_int
+    lib.btl_autotune.argtypes = [P, i32, i32, P]
+    lib.btl_autotune.restype = ctypes.c_int
+    lib.btl_destroy.argtypes = [P]
+    lib.btl_destroy.restype = None
+    lib.btl_last_error.argtypes = [P]
+    lib.btl_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(st, handle):
+    if st != BTL_OK:
+        msg = load_library().btl_last_error(handle)
+        raise BtlError(st, msg.decode() if msg else "")
+
+
+# ---- one-to-one wrappers of the C ABI -------------------------------------
+
+def btl_create(geoms, prec: int):
+    """geoms: list of objects with comp (n2,n1,n0) uint32, comp_phase uint8,
+    n_phase, dx and a `bc` list.  Returns (handle, keepalive)."""
+    lib = load_library()
+    arr = (btl_geom * len(geoms))()
+    keep = []
+    for i, g in enumerate(geoms):
+        comp = np.ascontiguousarray(g.comp, dtype=np.uint32)
+        cp = np.ascontiguousarray(g.comp_phase, dtype=np.uint8)
+        keep += [comp, cp]
+        n2, n1, n0 = comp.shape
+        arr[i].n[:] = [n0, n1, n2]
+        arr[i].dx = float(g.dx)
+        arr[i].bc[:] = [int(b) for b in g.bc]
+        arr[i].n_comp = len(cp)
+        arr[i].comp_id = _np_ptr(comp)
+        arr[i].comp_phase = _np_ptr(cp)
+        arr[i].n_phase = int(g.n_phase)
+    h = ctypes.c_void_p()
+    _check(lib.btl_create(arr, len(geoms), int(prec), ctypes.byref(h)), None)
+    return h
+
+
+def btl_forward(h, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E_ptr, M_ptr,
+                ckpt_every, stream_ptr):
+    lib = load_library()
+    D = np.ascontiguousarray(D, np.float64)
+    T2 = np.ascontiguousarray(T2, np.float64)
+    kappa = np.ascontiguousarray(kappa, np.float64).reshape(-1)
+    q_geom = np.ascontiguousarray(q_geom, np.int32)
+    gG0 = np.ascontiguousarray(gG0, np.float64).reshape(-1)
+    f = np.ascontiguousarray(f, np.float64)
+    st = lib.btl_forward(h, float(dt), int(K), _np_ptr(D), _np_ptr(T2), _np_ptr(kappa),
+                         int(Q), _np_ptr(q_geom), _np_ptr(gG0), _np_ptr(f),
+                         ctypes.c_void_p(E_ptr), ctypes.c_void_p(M_ptr) if M_ptr else None,
+                         int(ckpt_every), ctypes.c_void_p(stream_ptr) if stream_ptr else None)
+    _check(st, h)
+
+
+def btl_backward(h, dLdE_ptr, dD_ptr, dT2_ptr, dkappa_ptr, df_ptr, stream_ptr):
+    lib = load_library()
+    V = lambda p: ctypes.c_void_p(p) if p else None  # noqa: E731
+    _check(lib.btl_backward(h, V(dLdE_ptr), V(dD_ptr), V(dT2_ptr), V(dkappa_ptr),
+                            V(df_ptr), V(stream_ptr)), h)
+
+
+def btl_autotune(h, Q, K_probe, stream_ptr):
+    lib = load_library()
+    _check(lib.btl_autotune(h, int(Q), int(K_probe),
+                            ctypes.c_void_p(stream_ptr) if stream_ptr else None), h)
+
+
+def btl_destroy(h):
+    load_library().btl_destroy(h)
+
+
+def btl_last_error(h):
+    m = load_library().btl_last_error(h)
+    return m.decode() if m else ""
+
+
+# ---- torch-facing convenience ----------------------------------------------
+
+class _GeomBC:
+    """A workloads.Geometry together with its per-axis outer boundary."""
+
+    def __init__(self, g, bc):
+        self.comp, self.comp_phase = g.comp, g.comp_phase
+        self.n_phase, self.dx, self.bc = g.n_phase, g.dx, list(bc)
+
+
+class Simulator:
+    """Owns one btl_sim.  Device memory for E and M_final comes from torch."""
+
+    def __init__(self, geoms, bc, prec: str = "f32"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("Simulator needs a HIP device")
+        self.torch = torch
+        self.prec = BTL_F32 if prec == "f32" else BTL_F64
+        self.geoms = list(geoms)
+        bcs = bc if isinstance(bc[0], (list, tuple)) else [bc] * len(self.geoms)
+        self._h = btl_create([_GeomBC(g, b) for g, b in zip(self.geoms, bcs)], self.prec)
+
+    def close(self):
+        if self._h is not None:
+            btl_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, dt, D, T2, kappa, f, gG0, q_geom=None, want_M=False,
+                ckpt_every=0):
+        """Returns E (Q, K+1) complex128 torch tensor on the device (and M)."""
+        torch = self.torch
+        gG0 = np.ascontiguousarray(gG0, np.float64).reshape(-1, 3)
+        Q = gG0.shape[0]
+        q_geom = np.zeros(Q, np.int32) if q_geom is None else np.asarray(q_geom, np.int32)
+        K = len(f)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        E = torch.empty((Q, K + 1, 2), dtype=torch.float64, device=dev)
+        M = None
+        if want_M:
+            tot = sum(self.geoms[int(g)].comp.size for g in q_geom)
+            dt_ = torch.float32 if self.prec == BTL_F32 else torch.float64
+            M = torch.empty((tot, 2), dtype=dt_, device=dev)
+        stream = torch.cuda.current_stream().cuda_stream
+        btl_forward(self._h, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E.data_ptr(),
+                    M.data_ptr() if M is not None else 0, ckpt_every, stream)
+        Ec = torch.view_as_complex(E)
+        if not want_M:
+            return Ec
+        Ms, off = [], 0
+        Mc = torch.view_as_complex(M)
+        for g in q_geom:
+            sh = self.geoms[int(g)].comp.shape
+            n = int(np.prod(sh))
+            Ms.append(Mc[off:off + n].reshape(sh))
+            off += n
+        return Ec, Ms
+
+
+def simulate_config(cfg: dict, prec: str = "f32", want_M: bool = False):
+    """Run a workloads config on the GPU: returns E (Q, K+1) complex (and M)."""
+    sim = Simulator(cfg["geoms"], cfg["bc"], prec)
+    try:
+        out = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"],
+                          cfg["gG0"], cfg["q_geom"], want_M=want_M)
+        sim.torch.cuda.synchronize()
+        return out
+    finally:
+        sim.close()

@@ -1,0 +1,69 @@
+// Internal declarations shared by the kernels and the host runtime of
+// libbtlbm.  Not part of the public interface (include/btlbm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace btl {
+
+constexpr int kQ = 7;          // D3Q7: 0 rest, 1 +x, 2 -x, 3 +y, 4 -y, 5 +z, 6 -z
+constexpr int kBlock = 256;    // threads per workgroup (4 wavefronts of 64)
+
+// Face f = 2*a + h of axis a: h = 0 the low face (node 0, pulls direction
+// +a), h = 1 the high face (node n_a - 1, pulls direction -a).
+enum FaceKind : int32_t {
+    kFacePeriodic = 0,   // same field, wrapped site, same direction
+    kFaceMirror = 1,     // source field at the same site, reflected direction
+    kFaceConj = 2        // OR-ed: take the complex conjugate of the source
+};
+
+// One field = one q-sample's magnetization (or one of its reflected image
+// copies when a mirrored axis sees an oblique gradient) on one geometry.
+struct FieldDesc {
+    int64_t pop;            // element offset of the direction-0 plane
+    int64_t words;          // offset of the geometry's site words
+    int32_t n[3];           // sites per axis
+    int32_t nsites;
+    int32_t blk0;           // first workgroup of this field in a step launch
+    int32_t nblk;           // workgroups of this field
+    int32_t q;              // signal row when this is a primary field, else -1
+    int32_t pad;
+    double c[3];            // reaction angle per unit step: -fdt*(c.j + cu)
+    double cu;
+    int64_t face_pop[6];    // direction-0 plane offset of each face's source field
+    double beta[6];         // face factor exp(i * beta * F_k)
+    int32_t face_kind[6];
+    int32_t pad2[2];
+};
+
+struct StepArgs {
+    const void* src;        // post-collision populations of step k (T*)
+    void* dst;              // post-collision populations of step k+1
+    const uint32_t* words;  // site words: bits 0-7 phase, bit 8+d-1 membrane on pull link d
+    const FieldDesc* fields;
+    const int32_t* blk_field;
+    const double* fdt;      // [K] f_k * dt
+    const double* Fk;       // [K+1] sum_{m<k} f_m dt
+    const double* w;        // [P] 1/tau
+    const double* decay;    // [P] exp(-dt/T2)
+    const double* trans;    // [P*P] transmitted share 1/(1+P) of a membrane link
+    double2* partial;       // [blocks] per-workgroup signal partial sums
+    uint32_t* counter;      // [fields] arrival counters for the last-block reduction
+    double* E;              // [Q][K+1][2]
+    int32_t n_phase;
+    int32_t k;
+    int32_t K;
+    int32_t pad;
+};
+
+// Launchers (btl_kernels.hip)
+hipError_t launch_init(int prec, void* pop, int64_t n_elem_per_dir_total,
+                       const FieldDesc* d_fields, int32_t n_fields,
+                       const FieldDesc* h_fields, double* E, int32_t Q, int32_t K,
+                       hipStream_t st);
+hipError_t launch_step(int prec, const StepArgs& a, int32_t n_blocks, hipStream_t st);
+hipError_t launch_mfinal(int prec, const void* pop, const FieldDesc* h_fields,
+                         int32_t n_fields, void* M_out, hipStream_t st);
+
+}  // namespace btl

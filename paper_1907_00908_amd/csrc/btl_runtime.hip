@@ -1,0 +1,449 @@
+// Host runtime and C ABI of libbtlbm (declared in include/btlbm.h).
+//
+// The runtime validates inputs, turns the per-phase material parameters into
+// the FP64 constants of one step (1/tau, T2 decay, membrane transmission),
+// builds the field table (one field per q-sample plus reflected image fields
+// where a mirrored face sees an oblique gradient), and enqueues one step
+// launch per time step on the caller's stream.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/btlbm.h"
+#include "btl_internal.h"
+
+using namespace btl;
+
+namespace {
+
+constexpr double kEpsD = 0.25;   // D3Q7 lattice constant in tau = 1/2 + dt D/(eps_D dx^2)
+
+struct GeomHost {
+    int32_t n[3];
+    int32_t bc[3];
+    int64_t nsites;
+    int64_t words_off;   // offset into the concatenated site-word array
+};
+
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t cap = 0;      // elements
+    hipError_t ensure(size_t n) {
+        if (n <= cap) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+        hipError_t e = hipMalloc(&p, n * sizeof(T));
+        if (e == hipSuccess) cap = n;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+std::string g_create_error;
+
+}  // namespace
+
+struct btl_sim {
+    int prec = BTL_F32;
+    int device = 0;
+    double dx = 1.0;
+    int32_t n_phase = 1;
+    std::vector<GeomHost> geoms;
+    DevBuf<uint32_t> words;
+    DevBuf<char> pop[2];
+    DevBuf<FieldDesc> fields;
+    DevBuf<int32_t> blk_field;
+    DevBuf<double> steps;        // fdt [K] then Fk [K+1]
+    DevBuf<double> consts;       // w [P], decay [P], trans [P*P]
+    DevBuf<double2> partial;
+    DevBuf<uint32_t> counter;
+    std::vector<FieldDesc> h_fields;
+    std::string err;
+};
+
+static btl_status fail(btl_sim* s, btl_status st, const std::string& msg) {
+    if (s)
+        s->err = msg;
+    else
+        g_create_error = msg;
+    return st;
+}
+
+static btl_status hip_fail(btl_sim* s, hipError_t e, const char* what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(s, e == hipErrorOutOfMemory ? BTL_E_NOMEM : BTL_E_HIP, m);
+}
+
+// Site word: bits 0-7 the phase, bit 8 + (d-1) set when the pull link of
+// direction d (from node x - e_d into x) joins two different compartments.
+// Links through a mirror face join a node with its own image: never a membrane.
+static void build_words(const btl_geom& g, std::vector<uint32_t>& out) {
+    const int64_t n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+    static const int ex[7][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0},
+                                 {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+    out.resize((size_t)(n0 * n1 * n2));
+    for (int64_t j2 = 0; j2 < n2; ++j2)
+        for (int64_t j1 = 0; j1 < n1; ++j1)
+            for (int64_t j0 = 0; j0 < n0; ++j0) {
+                const int64_t s = j0 + n0 * (j1 + n1 * j2);
+                const uint32_t c = g.comp_id[s];
+                uint32_t w = g.comp_phase[c];
+                const int64_t jj[3] = {j0, j1, j2};
+                for (int d = 1; d < 7; ++d) {
+                    int64_t src[3];
+                    bool mirror = false;
+                    for (int a = 0; a < 3; ++a) {
+                        src[a] = jj[a] - ex[d][a];
+                        if (src[a] < 0 || src[a] >= g.n[a]) {
+                            if (g.bc[a] == BTL_MIRROR)
+                                mirror = true;
+                            else
+                                src[a] = (src[a] + g.n[a]) % g.n[a];
+                        }
+                    }
+                    if (mirror) continue;
+                    const uint32_t cs = g.comp_id[src[0] + n0 * (src[1] + n1 * src[2])];
+                    if (cs != c) w |= 1u << (8 + d - 1);
+                }
+                out[(size_t)s] = w;
+            }
+}
+
+extern "C" btl_status btl_create(const btl_geom* geoms, int32_t n_geom, int32_t prec,
+                                 btl_sim** out) {
+    if (!out) return fail(nullptr, BTL_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!geoms || n_geom < 1) return fail(nullptr, BTL_E_INVAL, "need at least one geometry");
+    if (prec != BTL_F32 && prec != BTL_F64) return fail(nullptr, BTL_E_INVAL, "prec must be BTL_F32 or BTL_F64");
+    const double dx = geoms[0].dx;
+    const int32_t P = geoms[0].n_phase;
+    if (!(dx > 0) || !isfinite(dx)) return fail(nullptr, BTL_E_INVAL, "dx must be finite and > 0");
+    if (P < 1 || P > 64) return fail(nullptr, BTL_E_INVAL, "n_phase must be in 1..64");
+    for (int g = 0; g < n_geom; ++g) {
+        const btl_geom& G = geoms[g];
+        if (G.dx != dx || G.n_phase != P)
+            return fail(nullptr, BTL_E_INVAL, "all geometries must share dx and n_phase");
+        int64_t ns = 1;
+        for (int a = 0; a < 3; ++a) {
+            if (G.n[a] < 2) return fail(nullptr, BTL_E_INVAL, "each axis needs >= 2 sites");
+            if (G.bc[a] != BTL_PERIODIC && G.bc[a] != BTL_MIRROR)
+                return fail(nullptr, BTL_E_INVAL, "bc must be BTL_PERIODIC or BTL_MIRROR");
+            ns *= G.n[a];
+        }
+        if (ns > (int64_t)INT32_MAX / 8) return fail(nullptr, BTL_E_INVAL, "geometry too large (sites)");
+        if (G.n_comp < 1 || !G.comp_id || !G.comp_phase)
+            return fail(nullptr, BTL_E_INVAL, "comp_id/comp_phase missing");
+        for (int c = 0; c < G.n_comp; ++c)
+            if (G.comp_phase[c] >= P) return fail(nullptr, BTL_E_INVAL, "comp_phase value >= n_phase");
+        for (int64_t s = 0; s < ns; ++s)
+            if (G.comp_id[s] >= (uint32_t)G.n_comp)
+                return fail(nullptr, BTL_E_INVAL, "comp_id value >= n_comp");
+    }
+    btl_sim* s = new btl_sim();
+    s->prec = prec;
+    s->dx = dx;
+    s->n_phase = P;
+    (void)hipGetDevice(&s->device);
+    std::vector<uint32_t> all, one;
+    for (int g = 0; g < n_geom; ++g) {
+        GeomHost h;
+        for (int a = 0; a < 3; ++a) {
+            h.n[a] = geoms[g].n[a];
+            h.bc[a] = geoms[g].bc[a];
+        }
+        h.nsites = (int64_t)h.n[0] * h.n[1] * h.n[2];
+        h.words_off = (int64_t)all.size();
+        build_words(geoms[g], one);
+        all.insert(all.end(), one.begin(), one.end());
+        s->geoms.push_back(h);
+    }
+    hipError_t e = s->words.ensure(all.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(s->words.p, all.data(), all.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        btl_status st = hip_fail(nullptr, e, "uploading site words");
+        btl_destroy(s);
+        return st;
+    }
+    *out = s;
+    return BTL_OK;
+}
+
+// Field table of one q-sample.  A mirrored axis whose gradient component is
+// non-zero makes the reflected medium depend on the sign of that component,
+// so the q-sample carries one field per sign pattern sigma over those axes
+// (sigma_a = 1: the copy reflected in axis a).  When every axis with a
+// non-zero component is mirrored, the copy reflected in all of them is the
+// complex conjugate of the primary (times a uniform phase), which halves the
+// set: only patterns with sigma_{a*} = 0 (a* the first such axis) are kept.
+struct QFields {
+    std::vector<int> sigma;   // canonical sign patterns, sigma[0] = 0 (primary)
+    int amask = 0;
+    bool conj_pair = false;
+};
+
+static QFields plan_fields(const GeomHost& g, const double* G) {
+    QFields r;
+    bool all_mirrored = true;
+    int astar = -1;
+    for (int a = 0; a < 3; ++a) {
+        if (G[a] == 0.0) continue;
+        if (g.bc[a] == BTL_MIRROR) {
+            r.amask |= 1 << a;
+            if (astar < 0) astar = a;
+        } else {
+            all_mirrored = false;
+        }
+    }
+    r.conj_pair = (r.amask != 0) && all_mirrored;
+    for (int sg = 0; sg < 8; ++sg) {
+        if ((sg & ~r.amask) != 0) continue;
+        if (r.conj_pair && ((sg >> astar) & 1)) continue;
+        r.sigma.push_back(sg);
+    }
+    return r;
+}
+
+extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double* D,
+                                  const double* T2, const double* kappa, int32_t Q,
+                                  const int32_t* q_geom, const double* gG0, const double* f,
+                                  double* E, void* M_final, int32_t ckpt_every, void* stream) {
+    if (!s) return BTL_E_INVAL;
+    if (!(dt > 0) || !isfinite(dt)) return fail(s, BTL_E_INVAL, "dt must be finite and > 0");
+    if (K < 0) return fail(s, BTL_E_INVAL, "K must be >= 0");
+    if (Q < 1) return fail(s, BTL_E_INVAL, "Q must be >= 1");
+    if (!D || !T2 || !kappa || !q_geom || !gG0 || (K > 0 && !f) || !E)
+        return fail(s, BTL_E_INVAL, "NULL argument");
+    if (ckpt_every != 0) return fail(s, BTL_E_UNSUPPORTED, "adjoint tape not available in this build");
+    const int32_t P = s->n_phase;
+    for (int p = 0; p < P; ++p) {
+        if (!(D[p] > 0) || !isfinite(D[p])) return fail(s, BTL_E_INVAL, "D must be finite and > 0");
+        if (!(T2[p] > 0)) return fail(s, BTL_E_INVAL, "T2 must be > 0");
+    }
+    for (int a = 0; a < P; ++a)
+        for (int b = 0; b < P; ++b) {
+            const double k = kappa[a * P + b];
+            if (!(k >= 0)) return fail(s, BTL_E_INVAL, "kappa must be >= 0");
+            if (k != kappa[b * P + a]) return fail(s, BTL_E_INVAL, "kappa must be symmetric");
+        }
+    for (int k = 0; k < K; ++k)
+        if (!isfinite(f[k])) return fail(s, BTL_E_INVAL, "f must be finite");
+    for (int q = 0; q < Q; ++q) {
+        if (q_geom[q] < 0 || q_geom[q] >= (int)s->geoms.size())
+            return fail(s, BTL_E_INVAL, "q_geom out of range");
+        for (int a = 0; a < 3; ++a)
+            if (!isfinite(gG0[3 * q + a])) return fail(s, BTL_E_INVAL, "gG0 must be finite");
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const double dx = s->dx;
+
+    // per-phase and per-pair constants (FP64)
+    std::vector<double> consts(2 * P + P * P);
+    for (int p = 0; p < P; ++p) {
+        const double tau = 0.5 + dt * D[p] / (kEpsD * dx * dx);
+        consts[p] = 1.0 / tau;
+        consts[P + p] = isinf(T2[p]) ? 1.0 : exp(-dt / T2[p]);
+    }
+    for (int i = 0; i < P * P; ++i) {
+        const double k = kappa[i];
+        double t;
+        if (isinf(k))
+            t = 1.0;
+        else if (k == 0.0)
+            t = 0.0;
+        else {
+            const double Pm = kEpsD * dx / (2.0 * k * dt);
+            t = 1.0 / (1.0 + Pm);
+        }
+        consts[2 * P + i] = t;
+    }
+    // per-step waveform tables
+    std::vector<double> steps((size_t)K + (size_t)K + 1);
+    {
+        double F = 0.0;
+        for (int k = 0; k < K; ++k) {
+            steps[k] = f[k] * dt;
+            steps[(size_t)K + k] = F;
+            F += f[k] * dt;
+        }
+        steps[(size_t)2 * K] = F;
+    }
+
+    // field table
+    std::vector<FieldDesc>& fl = s->h_fields;
+    fl.clear();
+    int64_t pop_elems = 0;
+    int32_t nblk_total = 0;
+    for (int q = 0; q < Q; ++q) {
+        const GeomHost& g = s->geoms[q_geom[q]];
+        const double* G = gG0 + 3 * q;
+        QFields qf = plan_fields(g, G);
+        const int base = (int)fl.size();
+        auto slot_of = [&](int sg, int* cj) {
+            for (size_t i = 0; i < qf.sigma.size(); ++i)
+                if (qf.sigma[i] == sg) {
+                    *cj = 0;
+                    return base + (int)i;
+                }
+            const int sb = sg ^ qf.amask;
+            for (size_t i = 0; i < qf.sigma.size(); ++i)
+                if (qf.sigma[i] == sb) {
+                    *cj = 1;
+                    return base + (int)i;
+                }
+            *cj = -1;
+            return -1;
+        };
+        double gsum = 0.0;
+        for (int a = 0; a < 3; ++a) gsum += G[a];
+        for (size_t fi = 0; fi < qf.sigma.size(); ++fi) {
+            FieldDesc d;
+            memset(&d, 0, sizeof(d));
+            const int sg = qf.sigma[fi];
+            d.pop = pop_elems;
+            d.words = g.words_off;
+            for (int a = 0; a < 3; ++a) d.n[a] = g.n[a];
+            d.nsites = (int32_t)g.nsites;
+            d.blk0 = nblk_total;
+            d.nblk = (int32_t)((g.nsites + kBlock - 1) / kBlock);
+            d.q = fi == 0 ? q : -1;
+            d.cu = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const int sig = (sg >> a) & 1;
+                d.c[a] = G[a] * dx * (sig ? -1.0 : 1.0);
+                if (sig) d.cu -= dx * G[a];
+            }
+            fl.push_back(d);
+            pop_elems += (int64_t)kQ * g.nsites;
+            nblk_total += d.nblk;
+        }
+        // faces (needs all slots of this q allocated)
+        for (size_t fi = 0; fi < qf.sigma.size(); ++fi) {
+            FieldDesc& d = fl[base + fi];
+            const int sg = qf.sigma[fi];
+            for (int a = 0; a < 3; ++a) {
+                const double La = g.n[a] * dx;
+                if (g.bc[a] == BTL_PERIODIC) {
+                    // ghat(x_-1) = e^{+i phi} ghat(x_{N-1}), ghat(x_N) = e^{-i phi} ghat(x_0)
+                    d.face_kind[2 * a] = d.face_kind[2 * a + 1] = kFacePeriodic;
+                    d.face_pop[2 * a] = d.face_pop[2 * a + 1] = d.pop;
+                    d.beta[2 * a] = La * G[a];
+                    d.beta[2 * a + 1] = -La * G[a];
+                } else {
+                    const int sa = ((sg >> a) & 1) ? -1 : 1;
+                    const int sp = (qf.amask >> a) & 1 ? (sg ^ (1 << a)) : sg;
+                    int cj = 0;
+                    const int slot = slot_of(sp, &cj);
+                    const double gam = cj ? dx * gsum : 0.0;
+                    const int kind = kFaceMirror | (cj ? kFaceConj : 0);
+                    d.face_kind[2 * a] = d.face_kind[2 * a + 1] = kind;
+                    d.face_pop[2 * a] = d.face_pop[2 * a + 1] = fl[slot].pop;
+                    d.beta[2 * a] = gam;
+                    d.beta[2 * a + 1] = -sa * 2.0 * La * G[a] + gam;
+                }
+            }
+        }
+    }
+    const int32_t n_fields = (int32_t)fl.size();
+    std::vector<int32_t> blk(nblk_total);
+    for (int i = 0; i < n_fields; ++i)
+        for (int b = 0; b < fl[i].nblk; ++b) blk[fl[i].blk0 + b] = i;
+
+    const size_t esz = s->prec == BTL_F32 ? sizeof(float2) : sizeof(double2);
+    hipError_t e;
+    if ((e = s->pop[0].ensure((size_t)pop_elems * esz)) != hipSuccess ||
+        (e = s->pop[1].ensure((size_t)pop_elems * esz)) != hipSuccess)
+        return hip_fail(s, e, "allocating populations");
+    if ((e = s->fields.ensure(n_fields)) != hipSuccess ||
+        (e = s->blk_field.ensure(nblk_total)) != hipSuccess ||
+        (e = s->steps.ensure(steps.size())) != hipSuccess ||
+        (e = s->consts.ensure(consts.size())) != hipSuccess ||
+        (e = s->partial.ensure(nblk_total)) != hipSuccess ||
+        (e = s->counter.ensure(n_fields)) != hipSuccess)
+        return hip_fail(s, e, "allocating tables");
+    if ((e = hipMemcpyAsync(s->fields.p, fl.data(), n_fields * sizeof(FieldDesc),
+                            hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(s->blk_field.p, blk.data(), nblk_total * sizeof(int32_t),
+                            hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(s->steps.p, steps.data(), steps.size() * sizeof(double),
+                            hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(s->consts.p, consts.data(), consts.size() * sizeof(double),
+                            hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemsetAsync(s->counter.p, 0, n_fields * sizeof(uint32_t), st)) != hipSuccess)
+        return hip_fail(s, e, "uploading tables");
+    // the host vectors above are pageable: make sure the copies have consumed
+    // them before they go out of scope
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(s, e, "upload sync");
+
+    if ((e = launch_init(s->prec, s->pop[0].p, pop_elems, s->fields.p, n_fields, fl.data(), E,
+                         Q, K, st)) != hipSuccess)
+        return hip_fail(s, e, "init launch");
+    StepArgs a;
+    memset(&a, 0, sizeof(a));
+    a.words = s->words.p;
+    a.fields = s->fields.p;
+    a.blk_field = s->blk_field.p;
+    a.fdt = s->steps.p;
+    a.Fk = s->steps.p + K;
+    a.w = s->consts.p;
+    a.decay = s->consts.p + P;
+    a.trans = s->consts.p + 2 * P;
+    a.partial = s->partial.p;
+    a.counter = s->counter.p;
+    a.E = E;
+    a.n_phase = P;
+    a.K = K;
+    for (int k = 0; k < K; ++k) {
+        a.src = s->pop[k & 1].p;
+        a.dst = s->pop[(k + 1) & 1].p;
+        a.k = k;
+        if ((e = launch_step(s->prec, a, nblk_total, st)) != hipSuccess)
+            return hip_fail(s, e, "step launch");
+    }
+    if (M_final) {
+        if ((e = launch_mfinal(s->prec, s->pop[K & 1].p, fl.data(), n_fields, M_final, st)) !=
+            hipSuccess)
+            return hip_fail(s, e, "final magnetization launch");
+    }
+    return BTL_OK;
+}
+
+extern "C" btl_status btl_backward(btl_sim* s, const double*, double*, double*, double*,
+                                   double*, void*) {
+    if (!s) return BTL_E_INVAL;
+    return fail(s, BTL_E_UNSUPPORTED, "adjoint not available in this build");
+}
+
+extern "C" btl_status btl_autotune(btl_sim* s, int32_t, int32_t, void*) {
+    if (!s) return BTL_E_INVAL;
+    return BTL_OK;
+}
+
+extern "C" void btl_destroy(btl_sim* s) {
+    if (!s) return;
+    (void)hipDeviceSynchronize();
+    s->words.release();
+    s->pop[0].release();
+    s->pop[1].release();
+    s->fields.release();
+    s->blk_field.release();
+    s->steps.release();
+    s->consts.release();
+    s->partial.release();
+    s->counter.release();
+    delete s;
+}
+
+extern "C" const char* btl_last_error(const btl_sim* s) {
+    return s ? s->err.c_str() : g_create_error.c_str();
+}

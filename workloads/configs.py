@@ -142,7 +142,9 @@ def _cfg4(n=96, K=None, n_q=None, seed=4):
 
 def _cfg5(n=512, K=None, n_q=None, seed=5):
     dx, dt = 0.2, 0.002
-    g = geo.ellipsoid_cells(n, dx, seed)
+    # reduced boxes shrink the cells with the box (at least 3-8 voxels)
+    sc = max(n / 512.0, 0.2)
+    g = geo.ellipsoid_cells(n, dx, seed, semi=(3.0 * sc, 8.0 * sc))
     D = np.array([2.5, 1.5, 1.0])
     T2 = np.array([90.0, 70.0, 60.0])
     kap = _pair_table(3, {(0, 1): 0.03, (1, 2): 0.1})
