@@ -1,0 +1,215 @@
+"""Benchmark: q-batched lattice site-updates/s of the hybrid LBM Bloch-Torrey
+step on one MI355X, with the HBM roofline of the step kernel and the FP64
+CPU oracle timed on the host as a baseline.
+
+Workload: the two-phase axon model -- 128^3 lattice, dx = 0.25 um, mirroring
+outer faces, z-cylinders with Gamma(4, mean 1 um) radii packed to ~60 %,
+D 2.0/1.0 um^2/ms, T2 90/70 ms, kappa 0.02 um/ms, PGSE delta 10 Delta 30 ms,
+6 oblique directions at b = 1000 s/mm^2, dt = 0.004 ms.  Each oblique
+direction on mirrored faces carries two fields (the primary and one
+reflected image), so one step updates 12 fields of 2,097,152 sites.
+
+A benchmark step is one lattice time step of the whole q-batch: stream with
+boundaries and membranes, reaction, signal reduction and collision for
+every q-sample.  `value` counts q-sample site-updates (6 x 128^3 per step).
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "q-batched site-updates/s + % HBM peak, fwd & adjoint, at stated err vs FP64"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_FIELD_SITE_F32 = 112      # read 7 complex float + write 7 complex float
+BYTES_PER_FIELD_SITE_F64 = 224
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_f32_axon128_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1907_00908_amd", "csrc", "btl_kernels.hip")
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def workload(K: int):
+    import workloads as w
+    cfg = w.make_config("cfg2")
+    f = cfg["f"]
+    if K > len(f):
+        f = np.resize(f, K)
+    cfg["f"] = f[:K]
+    return cfg
+
+
+def n_fields(cfg) -> int:
+    # fields per q-sample: 2^(k-1) for k mirrored axes with non-zero gradient
+    # (all non-zero axes mirrored), else 2^k
+    tot = 0
+    for G in cfg["gG0"]:
+        nz = [a for a in range(3) if G[a] != 0.0]
+        mir = [a for a in nz if cfg["bc"][a] == 1]
+        k = len(mir)
+        if k == 0:
+            tot += 1
+        elif len(mir) == len(nz):
+            tot += 2 ** (k - 1)
+        else:
+            tot += 2 ** k
+    return tot
+
+
+def time_forward(sim, cfg, K, prec_bytes, reps=1):
+    import torch
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    best = None
+    E = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        E = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:K],
+                        cfg["gG0"], cfg["q_geom"])
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        best = ms if best is None else min(best, ms)
+    return best, E
+
+
+def cpu_baseline(cfg, budget_s: float = 15.0):
+    """The FP64 oracle on the host cores, a bounded number of full-size steps
+    of q-sample 0 (oblique gradient on mirrored faces: the oracle runs the
+    reflected, doubled domain)."""
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    g = cfg["geoms"][0]
+    args = (g.comp, g.comp_phase, g.n_phase, cfg["bc"], cfg["dx"], cfg["dt"], cfg["D"],
+            cfg["T2"], cfg["kappa"])
+    t0 = time.perf_counter()
+    oracle.simulate(*args, cfg["f"][:1], cfg["gG0"][0], threads=threads, want_M=False)
+    t1 = time.perf_counter()
+    per = max(t1 - t0, 1e-3)
+    n = int(max(1, min(200, budget_s / per)))
+    t0 = time.perf_counter()
+    oracle.simulate(*args, cfg["f"][:n], cfg["gG0"][0], threads=threads, want_M=False)
+    t1 = time.perf_counter()
+    sites = g.comp.size
+    return {"value": sites * n / (t1 - t0), "unit": "site-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"q-sample 0 of the workload, {n} full-size steps ({sites} REV sites; "
+                      f"the oracle steps the 2x2x2 reflected domain), {t1 - t0:.1f} s"}
+
+
+def traffic_for(kernel_avg_ms):
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except OSError:
+        return None
+    if t.get("kernel_sha") != kernel_hash():
+        return None
+    return t["bytes_per_launch"]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP64 comparison runs (profiling)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a device copy of known size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is "
+                                   "described in DESIGN.md but not implemented",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_1907_00908_amd as btl
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(1)
+    btl.load_library()
+
+    if args.calib_copy:
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": nbytes}), flush=True)
+        return
+
+    K, W = args.steps, args.warmup
+    cfg = workload(max(K, W))
+    Q = len(cfg["gG0"])
+    sites = cfg["geoms"][0].comp.size
+    nf = n_fields(cfg)
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], args.prec)
+    bpf = BYTES_PER_FIELD_SITE_F32 if args.prec == "f32" else BYTES_PER_FIELD_SITE_F64
+    if W > 0:
+        time_forward(sim, cfg, W, bpf)
+    ms, E = time_forward(sim, cfg, K, bpf)
+    ms_step = ms / K
+    value = Q * sites * K / (ms * 1e-3)
+    bytes_launch = nf * sites * bpf
+    achieved = bytes_launch / (ms_step * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(ms_step),
+            "kernel": f"k_step<{'float2' if args.prec == 'f32' else 'double2'}>",
+            "bytes_per_launch_algorithmic": bytes_launch}
+    out = {"metric": METRIC, "value": value, "unit": "site-updates/s", "n_gpus": 1,
+           "steps": K, "warmup": W, "ms_per_step": ms_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "two-phase axon model 128^3, mirror BC, 6 oblique "
+                                  "directions, b=1000 (cfg2)",
+                      "sites": sites, "q_samples": Q, "fields": nf,
+                      "storage": args.prec, "steps_per_forward": K},
+           "roofline": roof}
+    if not args.no_extras:
+        # stated error vs FP64 storage over the same steps, and the plain FP64
+        # one-sample-per-launch form as the speedup denominator
+        sim64 = btl.Simulator(cfg["geoms"], cfg["bc"], "f64")
+        ms64, E64 = time_forward(sim64, cfg, K, BYTES_PER_FIELD_SITE_F64)
+        e32 = E.cpu().numpy()
+        e64 = E64.cpu().numpy()
+        big = np.abs(e64) >= 1e-2
+        rel = np.max(np.abs(e32 - e64)[big] / np.abs(e64)[big])
+        out["err_vs_fp64"] = {"max_rel_E": float(rel), "steps": K}
+        one = dict(cfg)
+        one["gG0"] = cfg["gG0"][:1]
+        one["q_geom"] = cfg["q_geom"][:1]
+        ms1, _ = time_forward(sim64, one, K, BYTES_PER_FIELD_SITE_F64)
+        v1 = sites * K / (ms1 * 1e-3)
+        out["fp64_one_q_per_launch"] = {"value": v1, "unit": "site-updates/s",
+                                        "speedup_of_value": value / v1}
+        out["fp64_batched"] = {"value": Q * sites * K / (ms64 * 1e-3)}
+        sim64.close()
+    sim.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -75,7 +75,7 @@ typedef struct {
     int32_t n_comp;             /* number of compartments C >= 1 */
     const uint32_t *comp_id;    /* host [n2][n1][n0], values < C */
     const uint8_t *comp_phase;  /* host [C], values < n_phase */
-    int32_t n_phase;            /* number of material phases P, 1..64 */
+    int32_t n_phase;            /* number of material phases P, 1..8 */
 } btl_geom;
 
 /* Create a simulator for n_geom geometries (all with the same dx and

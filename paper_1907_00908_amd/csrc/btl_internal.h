@@ -9,6 +9,8 @@ namespace btl {
 
 constexpr int kQ = 7;          // D3Q7: 0 rest, 1 +x, 2 -x, 3 +y, 4 -y, 5 +z, 6 -z
 constexpr int kBlock = 256;    // threads per workgroup (4 wavefronts of 64)
+constexpr int kMaxZc = 64;     // longest z column one thread walks
+constexpr int kMaxPhase = 8;   // material phases (3-bit neighbour phase in the site word)
 
 // Face f = 2*a + h of axis a: h = 0 the low face (node 0, pulls direction
 // +a), h = 1 the high face (node n_a - 1, pulls direction -a).
@@ -26,9 +28,11 @@ struct FieldDesc {
     int32_t n[3];           // sites per axis
     int32_t nsites;
     int32_t blk0;           // first workgroup of this field in a step launch
-    int32_t nblk;           // workgroups of this field
+    int32_t nblk;           // workgroups of this field = tiles[0]*tiles[1]*tiles[2]
     int32_t q;              // signal row when this is a primary field, else -1
-    int32_t pad;
+    int32_t zc;             // sites per thread along z (tile depth)
+    int32_t tiles[3];       // tiles along x, y (of TX x TY sites) and z (of zc)
+    int32_t pad0;
     double c[3];            // reaction angle per unit step: -fdt*(c.j + cu)
     double cu;
     int64_t face_pop[6];    // direction-0 plane offset of each face's source field
@@ -57,12 +61,19 @@ struct StepArgs {
     int32_t pad;
 };
 
+// Workgroup tile shapes (TX x TY threads, one site column along z each).
+enum TileShape : int32_t { kTile64x4 = 0, kTile32x8 = 1, kTile16x16 = 2, kTileCount = 3 };
+inline void tile_dims(int shape, int* tx, int* ty) {
+    *tx = shape == kTile64x4 ? 64 : shape == kTile32x8 ? 32 : 16;
+    *ty = kBlock / *tx;
+}
+
 // Launchers (btl_kernels.hip)
 hipError_t launch_init(int prec, void* pop, int64_t n_elem_per_dir_total,
                        const FieldDesc* d_fields, int32_t n_fields,
                        const FieldDesc* h_fields, double* E, int32_t Q, int32_t K,
                        hipStream_t st);
-hipError_t launch_step(int prec, const StepArgs& a, int32_t n_blocks, hipStream_t st);
+hipError_t launch_step(int prec, int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st);
 hipError_t launch_mfinal(int prec, const void* pop, const FieldDesc* h_fields,
                          int32_t n_fields, void* M_out, hipStream_t st);
 

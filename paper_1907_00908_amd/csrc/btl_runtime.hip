@@ -68,8 +68,40 @@ struct btl_sim {
     DevBuf<double2> partial;
     DevBuf<uint32_t> counter;
     std::vector<FieldDesc> h_fields;
+    // pinned staging for the per-call tables, two slots so that a call can
+    // be prepared while the previous one's uploads are still queued
+    char* stage[2] = {nullptr, nullptr};
+    size_t stage_cap[2] = {0, 0};
+    hipEvent_t stage_ev[2] = {nullptr, nullptr};
+    bool stage_used[2] = {false, false};
+    int stage_slot = 0;
+    int tile_shape = -1;        // -1: pick per call from the geometry sizes
+    int zc = 16;                // sites per thread along z
     std::string err;
 };
+
+// Tile shape with the fewest idle lanes over the geometries of a call
+// (ties go to the wider x extent: longer contiguous rows per wavefront).
+static int pick_shape(const std::vector<GeomHost>& gs, const int32_t* q_geom, int Q) {
+    int best = kTile64x4;
+    int64_t best_waste = -1;
+    for (int sh = 0; sh < kTileCount; ++sh) {
+        int tx, ty;
+        tile_dims(sh, &tx, &ty);
+        int64_t waste = 0;
+        for (int q = 0; q < Q; ++q) {
+            const GeomHost& g = gs[q_geom[q]];
+            const int64_t cx = (g.n[0] + tx - 1) / tx * (int64_t)tx;
+            const int64_t cy = (g.n[1] + ty - 1) / ty * (int64_t)ty;
+            waste += (cx * cy - (int64_t)g.n[0] * g.n[1]) * g.n[2];
+        }
+        if (best_waste < 0 || waste < best_waste) {
+            best = sh;
+            best_waste = waste;
+        }
+    }
+    return best;
+}
 
 static btl_status fail(btl_sim* s, btl_status st, const std::string& msg) {
     if (s)
@@ -84,9 +116,10 @@ static btl_status hip_fail(btl_sim* s, hipError_t e, const char* what) {
     return fail(s, e == hipErrorOutOfMemory ? BTL_E_NOMEM : BTL_E_HIP, m);
 }
 
-// Site word: bits 0-7 the phase, bit 8 + (d-1) set when the pull link of
-// direction d (from node x - e_d into x) joins two different compartments.
-// Links through a mirror face join a node with its own image: never a membrane.
+// Site word: bits 0-3 the phase, bit 4 + (d-1) set when the pull link of
+// direction d (from node x - e_d into x) joins two different compartments,
+// and bits 10 + 3(d-1) .. +2 the phase of that neighbour.  Links through a
+// mirror face join a node with its own image: never a membrane.
 static void build_words(const btl_geom& g, std::vector<uint32_t>& out) {
     const int64_t n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
     static const int ex[7][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0},
@@ -113,7 +146,10 @@ static void build_words(const btl_geom& g, std::vector<uint32_t>& out) {
                     }
                     if (mirror) continue;
                     const uint32_t cs = g.comp_id[src[0] + n0 * (src[1] + n1 * src[2])];
-                    if (cs != c) w |= 1u << (8 + d - 1);
+                    if (cs != c) {
+                        w |= 1u << (4 + d - 1);
+                        w |= (uint32_t)g.comp_phase[cs] << (10 + 3 * (d - 1));
+                    }
                 }
                 out[(size_t)s] = w;
             }
@@ -128,7 +164,7 @@ extern "C" btl_status btl_create(const btl_geom* geoms, int32_t n_geom, int32_t 
     const double dx = geoms[0].dx;
     const int32_t P = geoms[0].n_phase;
     if (!(dx > 0) || !isfinite(dx)) return fail(nullptr, BTL_E_INVAL, "dx must be finite and > 0");
-    if (P < 1 || P > 64) return fail(nullptr, BTL_E_INVAL, "n_phase must be in 1..64");
+    if (P < 1 || P > 8) return fail(nullptr, BTL_E_INVAL, "n_phase must be in 1..8");
     for (int g = 0; g < n_geom; ++g) {
         const btl_geom& G = geoms[g];
         if (G.dx != dx || G.n_phase != P)
@@ -279,6 +315,12 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
         steps[(size_t)2 * K] = F;
     }
 
+    // launch shape
+    const int shape = s->tile_shape >= 0 ? s->tile_shape : pick_shape(s->geoms, q_geom, Q);
+    int TX, TY;
+    tile_dims(shape, &TX, &TY);
+    const int ZC = s->zc;
+
     // field table
     std::vector<FieldDesc>& fl = s->h_fields;
     fl.clear();
@@ -315,7 +357,11 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
             for (int a = 0; a < 3; ++a) d.n[a] = g.n[a];
             d.nsites = (int32_t)g.nsites;
             d.blk0 = nblk_total;
-            d.nblk = (int32_t)((g.nsites + kBlock - 1) / kBlock);
+            d.zc = ZC;
+            d.tiles[0] = (g.n[0] + TX - 1) / TX;
+            d.tiles[1] = (g.n[1] + TY - 1) / TY;
+            d.tiles[2] = (g.n[2] + ZC - 1) / ZC;
+            d.nblk = d.tiles[0] * d.tiles[1] * d.tiles[2];
             d.q = fi == 0 ? q : -1;
             d.cu = 0.0;
             for (int a = 0; a < 3; ++a) {
@@ -364,6 +410,7 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
     if ((e = s->pop[0].ensure((size_t)pop_elems * esz)) != hipSuccess ||
         (e = s->pop[1].ensure((size_t)pop_elems * esz)) != hipSuccess)
         return hip_fail(s, e, "allocating populations");
+    const size_t old_counter_cap = s->counter.cap;
     if ((e = s->fields.ensure(n_fields)) != hipSuccess ||
         (e = s->blk_field.ensure(nblk_total)) != hipSuccess ||
         (e = s->steps.ensure(steps.size())) != hipSuccess ||
@@ -371,19 +418,45 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
         (e = s->partial.ensure(nblk_total)) != hipSuccess ||
         (e = s->counter.ensure(n_fields)) != hipSuccess)
         return hip_fail(s, e, "allocating tables");
-    if ((e = hipMemcpyAsync(s->fields.p, fl.data(), n_fields * sizeof(FieldDesc),
-                            hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(s->blk_field.p, blk.data(), nblk_total * sizeof(int32_t),
-                            hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(s->steps.p, steps.data(), steps.size() * sizeof(double),
-                            hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(s->consts.p, consts.data(), consts.size() * sizeof(double),
-                            hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (e = hipMemsetAsync(s->counter.p, 0, n_fields * sizeof(uint32_t), st)) != hipSuccess)
+    if (s->counter.cap != old_counter_cap) {
+        // arrival counters start at zero; every step leaves them at zero
+        if ((e = hipMemset(s->counter.p, 0, s->counter.cap * sizeof(uint32_t))) != hipSuccess)
+            return hip_fail(s, e, "clearing counters");
+    }
+    // stage all tables in pinned memory and upload asynchronously
+    const size_t b_fields = (size_t)n_fields * sizeof(FieldDesc);
+    const size_t b_blk = (size_t)nblk_total * sizeof(int32_t);
+    const size_t b_steps = steps.size() * sizeof(double);
+    const size_t b_consts = consts.size() * sizeof(double);
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_blk = al(b_fields), o_steps = o_blk + al(b_blk), o_consts = o_steps + al(b_steps);
+    const size_t total = o_consts + al(b_consts);
+    const int slot = s->stage_slot;
+    if (!s->stage_ev[slot] && (e = hipEventCreateWithFlags(&s->stage_ev[slot], hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(s, e, "creating event");
+    if (s->stage_used[slot] && (e = hipEventSynchronize(s->stage_ev[slot])) != hipSuccess)
+        return hip_fail(s, e, "waiting for staging slot");
+    if (s->stage_cap[slot] < total) {
+        if (s->stage[slot]) (void)hipHostFree(s->stage[slot]);
+        s->stage[slot] = nullptr;
+        s->stage_cap[slot] = 0;
+        if ((e = hipHostMalloc((void**)&s->stage[slot], total, hipHostMallocDefault)) != hipSuccess)
+            return hip_fail(s, e, "allocating pinned staging");
+        s->stage_cap[slot] = total;
+    }
+    char* stg = s->stage[slot];
+    memcpy(stg, fl.data(), b_fields);
+    memcpy(stg + o_blk, blk.data(), b_blk);
+    memcpy(stg + o_steps, steps.data(), b_steps);
+    memcpy(stg + o_consts, consts.data(), b_consts);
+    if ((e = hipMemcpyAsync(s->fields.p, stg, b_fields, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(s->blk_field.p, stg + o_blk, b_blk, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(s->steps.p, stg + o_steps, b_steps, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(s->consts.p, stg + o_consts, b_consts, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipEventRecord(s->stage_ev[slot], st)) != hipSuccess)
         return hip_fail(s, e, "uploading tables");
-    // the host vectors above are pageable: make sure the copies have consumed
-    // them before they go out of scope
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(s, e, "upload sync");
+    s->stage_used[slot] = true;
+    s->stage_slot ^= 1;
 
     if ((e = launch_init(s->prec, s->pop[0].p, pop_elems, s->fields.p, n_fields, fl.data(), E,
                          Q, K, st)) != hipSuccess)
@@ -407,7 +480,7 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
         a.src = s->pop[k & 1].p;
         a.dst = s->pop[(k + 1) & 1].p;
         a.k = k;
-        if ((e = launch_step(s->prec, a, nblk_total, st)) != hipSuccess)
+        if ((e = launch_step(s->prec, shape, a, nblk_total, st)) != hipSuccess)
             return hip_fail(s, e, "step launch");
     }
     if (M_final) {
@@ -441,6 +514,10 @@ extern "C" void btl_destroy(btl_sim* s) {
     s->consts.release();
     s->partial.release();
     s->counter.release();
+    for (int i = 0; i < 2; ++i) {
+        if (s->stage[i]) (void)hipHostFree(s->stage[i]);
+        if (s->stage_ev[i]) (void)hipEventDestroy(s->stage_ev[i]);
+    }
     delete s;
 }
 
