@@ -120,8 +120,13 @@ btl_status btl_forward(btl_sim *s, double dt, int32_t K, const double *D,
 btl_status btl_backward(btl_sim *s, const double *dL_dE, double *dD, double *dT2,
                         double *dkappa, double *df, void *stream);
 
-/* Time the candidate launch shapes on Q q-samples for K_probe steps and keep
- * the fastest for this simulator (synchronizes the stream). */
+/* Choose the launch shape (workgroup tile and z-column length) of this
+ * simulator by timing every candidate on the inputs of the last btl_forward
+ * (its first Q q-samples, K_probe steps, waveform repeated if shorter) and
+ * keeping the fastest.  Synchronizes the stream.  Without autotuning a
+ * shape with the fewest idle lanes and whole z columns is used.
+ * Errors: BTL_E_INVAL (no previous forward, K_probe < 1), BTL_E_NOMEM,
+ * BTL_E_HIP. */
 btl_status btl_autotune(btl_sim *s, int32_t Q, int32_t K_probe, void *stream);
 
 /* Release all memory of the simulator (synchronizes the device). */

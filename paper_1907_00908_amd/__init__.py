@@ -44,11 +44,16 @@ class btl_geom(ctypes.Structure):
 _lib = None
 
 
-def load_library(path: str = LIB_PATH):
-    """Load libbtlbm.so and declare its signatures (raises if missing)."""
+def load_library(path: str = None):
+    """Load libbtlbm.so and declare its signatures (raises if missing).
+
+    The environment variable BTLBM_LIBRARY may name another build of the
+    same library (for example one compiled with different tile options)."""
     global _lib
     if _lib is not None:
         return _lib
+    if path is None:
+        path = os.environ.get("BTLBM_LIBRARY", LIB_PATH)
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run `python -m paper_1907_00908_amd.build`")
     lib = ctypes.CDLL(path)

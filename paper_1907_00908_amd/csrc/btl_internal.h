@@ -9,7 +9,8 @@ namespace btl {
 
 constexpr int kQ = 7;          // D3Q7: 0 rest, 1 +x, 2 -x, 3 +y, 4 -y, 5 +z, 6 -z
 constexpr int kBlock = 256;    // threads per workgroup (4 wavefronts of 64)
-constexpr int kMaxZc = 64;     // longest z column one thread walks
+constexpr int kMaxZc = 4096;   // longest z column one thread walks
+constexpr int kTabSteps = 32;  // steps whose phase tables one table launch computes
 constexpr int kMaxPhase = 8;   // material phases (3-bit neighbour phase in the site word)
 
 // Face f = 2*a + h of axis a: h = 0 the low face (node 0, pulls direction
@@ -32,7 +33,9 @@ struct FieldDesc {
     int32_t q;              // signal row when this is a primary field, else -1
     int32_t zc;             // sites per thread along z (tile depth)
     int32_t tiles[3];       // tiles along x, y (of TX x TY sites) and z (of zc)
-    int32_t pad0;
+    int32_t tab;            // offset of this field's phase table (double2 entries):
+                            //   [n0] exp(-i fdt c0 j0), [n1] exp(-i fdt c1 j1),
+                            //   [n2] exp(-i fdt (c2 j2 + cu)), [6] face factors
     double c[3];            // reaction angle per unit step: -fdt*(c.j + cu)
     double cu;
     int64_t face_pop[6];    // direction-0 plane offset of each face's source field
@@ -55,16 +58,19 @@ struct StepArgs {
     double2* partial;       // [blocks] per-workgroup signal partial sums
     uint32_t* counter;      // [fields] arrival counters for the last-block reduction
     double* E;              // [Q][K+1][2]
+    double2* tab;           // phase table of step k (T entries); the table kernel
+                            // fills kTabSteps consecutive steps from here
+    const int32_t* tab_field;  // [T] field of each table entry
+    int32_t T;              // entries per step
     int32_t n_phase;
     int32_t k;
     int32_t K;
-    int32_t pad;
 };
 
 // Workgroup tile shapes (TX x TY threads, one site column along z each).
-enum TileShape : int32_t { kTile64x4 = 0, kTile32x8 = 1, kTile16x16 = 2, kTileCount = 3 };
+enum TileShape : int32_t { kTile64x4 = 0, kTile32x8 = 1, kTile16x16 = 2, kTile128x2 = 3, kTileCount = 4 };
 inline void tile_dims(int shape, int* tx, int* ty) {
-    *tx = shape == kTile64x4 ? 64 : shape == kTile32x8 ? 32 : 16;
+    *tx = shape == kTile64x4 ? 64 : shape == kTile32x8 ? 32 : shape == kTile128x2 ? 128 : 16;
     *ty = kBlock / *tx;
 }
 
@@ -74,6 +80,8 @@ hipError_t launch_init(int prec, void* pop, int64_t n_elem_per_dir_total,
                        const FieldDesc* h_fields, double* E, int32_t Q, int32_t K,
                        hipStream_t st);
 hipError_t launch_step(int prec, int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st);
+// phase tables of steps a.k .. a.k + nsteps - 1 into a.tab[0 .. nsteps*T)
+hipError_t launch_tables(const StepArgs& a, int32_t nsteps, hipStream_t st);
 hipError_t launch_mfinal(int prec, const void* pop, const FieldDesc* h_fields,
                          int32_t n_fields, void* M_out, hipStream_t st);
 

@@ -39,6 +39,17 @@ __device__ __forceinline__ void store2(float2* p, double2 v) {
 }
 __device__ __forceinline__ void store2(double2* p, double2 v) { *p = v; }
 
+// Value that is the same in every lane, kept in scalar registers.
+__device__ __forceinline__ double uniform(double v) {
+    const unsigned long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(u & 0xffffffffu));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(u >> 32));
+    return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double2 uniform2(double2 v) {
+    return make_double2(uniform(v.x), uniform(v.y));
+}
+
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -86,6 +97,28 @@ __device__ __forceinline__ double2 expi(double th) {
     return make_double2(cs, sn);
 }
 
+// Entry e of the phase table of step k (see FieldDesc::tab).
+__device__ __forceinline__ double2 table_entry(const StepArgs& a, int32_t e, int32_t k) {
+    const int fi = a.tab_field[e];
+    const FieldDesc& fd = a.fields[fi];
+    const int32_t l = e - fd.tab;
+    const double fdt = a.fdt[k];
+    const int32_t n0 = fd.n[0], n1 = fd.n[1], n2 = fd.n[2];
+    if (l < n0) return expi(-fdt * fd.c[0] * (double)l);
+    if (l < n0 + n1) return expi(-fdt * fd.c[1] * (double)(l - n0));
+    if (l < n0 + n1 + n2) return expi(-fdt * (fd.c[2] * (double)(l - n0 - n1) + fd.cu));
+    const double beta = fd.beta[l - n0 - n1 - n2];
+    return beta != 0.0 ? expi(beta * a.Fk[k]) : make_double2(1.0, 0.0);
+}
+
+__global__ void __launch_bounds__(kBlock) k_tables(StepArgs a, int32_t nsteps) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= (int64_t)nsteps * a.T) return;
+    const int32_t ks = (int32_t)(i / a.T);
+    const int32_t e = (int32_t)(i - (int64_t)ks * a.T);
+    a.tab[i] = table_entry(a, e, a.k + ks);
+}
+
 // One step for a tile of TX x TY site columns, each thread walking fd.zc
 // sites along z.  Workgroup -> (field, tile) via blk_field and the field's
 // tile counts; no per-site integer division.
@@ -93,10 +126,19 @@ template <typename V, int TX>
 __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     constexpr int TY = kBlock / TX;
     __shared__ double2 lds[kBlock / 64];
-    __shared__ double2 face_fac[6];
-    __shared__ double2 ex[TX], ey[TY], ez[kMaxZc];
     __shared__ double c_w[kMaxPhase], c_dec[kMaxPhase], c_tr[kMaxPhase * kMaxPhase];
     __shared__ int last_flag;
+    // per-phase constants in LDS: lane-indexed lookups then go through the
+    // LDS counter and never wait on outstanding global loads or stores
+    {
+        const int t = threadIdx.x, P = a.n_phase;
+        if (t < P) {
+            c_w[t] = a.w[t];
+            c_dec[t] = a.decay[t];
+        }
+        if (t < P * P) c_tr[t] = a.trans[t];
+    }
+    __syncthreads();
     const int fi = a.blk_field[blockIdx.x];
     const FieldDesc& fd = a.fields[fi];
     const int32_t ns = fd.nsites;
@@ -106,35 +148,13 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     const int32_t rb = b / fd.tiles[0];
     const int32_t ty = rb % fd.tiles[1];
     const int32_t tz = rb / fd.tiles[1];
-    const double F = a.Fk[a.k];
-    const double fdt = a.fdt[a.k];
     const int32_t z0 = tz * fd.zc;
-    // Phase factors of this workgroup, computed once: the six face factors
-    // exp(i beta F_k) and the reaction factor exp(-i fdt (c.j + cu)) split
-    // per axis over the tile's x, y and z ranges.
-    {
-        const int t = threadIdx.x;
-        if (t < 6) {
-            const double beta = fd.beta[t];
-            face_fac[t] = beta != 0.0 ? expi(beta * F) : make_double2(1.0, 0.0);
-        } else if (t >= 64 && t < 64 + TX) {
-            const int l = t - 64;
-            ex[l] = expi(-fdt * fd.c[0] * (double)(tx * TX + l));
-        } else if (t >= 128 && t < 128 + TY) {
-            const int l = t - 128;
-            ey[l] = expi(-fdt * fd.c[1] * (double)(ty * TY + l));
-        } else if (t >= 192 && t < 192 + fd.zc) {
-            const int l = t - 192;
-            ez[l] = expi(-fdt * (fd.c[2] * (double)(z0 + l) + fd.cu));
-        }
-        const int P = a.n_phase;
-        if (t < P) {
-            c_w[t] = a.w[t];
-            c_dec[t] = a.decay[t];
-        }
-        if (t < P * P) c_tr[(t / P) * kMaxPhase + t % P] = a.trans[t];
-    }
-    __syncthreads();
+    const double2* __restrict__ tab = a.tab + fd.tab;
+    const double2* __restrict__ ez = tab + n0 + n1;
+    double2 face_fac[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) face_fac[f] = uniform2(tab[n0 + n1 + n2 + f]);
+    const int P = a.n_phase;
 
     const V* __restrict__ src = static_cast<const V*>(a.src);
     V* __restrict__ dst = static_cast<V*>(a.dst);
@@ -144,7 +164,7 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     const int32_t j1 = ty * TY + (int32_t)(threadIdx.x / TX);
     const int32_t z1 = min(n2, z0 + fd.zc);
     const int32_t st1 = n0, st2 = n0 * n1;
-    const double2 exy = cmul(ex[threadIdx.x % TX], ey[threadIdx.x / TX]);
+    const double2 exy = cmul(tab[min(j0, n0 - 1)], tab[n0 + min(j1, n1 - 1)]);
 
     // Source offset (relative to the site index s) of each pulled direction,
     // fixed for the whole z column for x and y; z faces switch per site.
@@ -171,80 +191,106 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     const int64_t o5i = pop + 5 * (int64_t)ns - st2, o5f = face_off(4, 5, (n2 - 1) * st2);
     const int64_t o6i = pop + 6 * (int64_t)ns + st2, o6f = face_off(5, 6, -(n2 - 1) * st2);
 
-    double2 Mv = make_double2(0.0, 0.0);
-    if (j0 < n0 && j1 < n1) {
-        for (int32_t j2 = z0; j2 < z1; ++j2) {
-            const int32_t s = j0 + st1 * j1 + st2 * j2;
-            const bool fz0 = j2 == 0, fz1 = j2 == n2 - 1;
-            // all loads of the site issued together
-            const uint32_t word = words[s];
-            double2 g[kQ];
-            g[0] = ld2(src + pop + s);
-            g[1] = ld2(src + o1 + s);
-            g[2] = ld2(src + o2 + s);
-            g[3] = ld2(src + o3 + s);
-            g[4] = ld2(src + o4 + s);
-            g[5] = ld2(src + (fz0 ? o5f : o5i) + s);
-            g[6] = ld2(src + (fz1 ? o6f : o6i) + s);
-            const int p = (int)(word & 0xfu);
-            const uint32_t mask = (word >> 4) & 0x3fu;
-            double2 own[kQ];
-            if (mask) {
-                // outgoing populations at this node, reflected at membranes
+    // Loads of one site: the site word, the seven pulled populations, the
+    // six outgoing populations of the node itself (reflected at membrane
+    // links) and the z phase factor.  The z column is software-pipelined:
+    // the loads of site j2 + 1 are issued before the stores of site j2, so
+    // waiting for a site's data never waits for earlier stores.
+    struct SiteLoads {
+        uint32_t word;
+        V g[kQ];
+        V own[kQ - 1];
+        double2 ez;
+    };
+    auto issue = [&](int32_t j2, SiteLoads& L) {
+        const int32_t s = j0 + st1 * j1 + st2 * j2;
+        L.word = words[s];
+        L.g[0] = src[pop + s];
+        L.g[1] = src[o1 + s];
+        L.g[2] = src[o2 + s];
+        L.g[3] = src[o3 + s];
+        L.g[4] = src[o4 + s];
+        L.g[5] = src[(j2 == 0 ? o5f : o5i) + s];
+        L.g[6] = src[(j2 == n2 - 1 ? o6f : o6i) + s];
 #pragma unroll
-                for (int d = 1; d < kQ; ++d) {
-                    const int od = (d & 1) ? d + 1 : d - 1;
-                    own[d] = ld2(src + pop + (int64_t)od * ns + s);
-                }
+        for (int d = 1; d < kQ; ++d) {
+            const int od = (d & 1) ? d + 1 : d - 1;
+            L.own[d - 1] = src[pop + (int64_t)od * ns + s];
+        }
+        L.ez = ez[j2];
+    };
+    auto compute = [&](int32_t j2, const SiteLoads& L, double2& Macc) {
+        const int32_t s = j0 + st1 * j1 + st2 * j2;
+        const bool fz0 = j2 == 0, fz1 = j2 == n2 - 1;
+        const uint32_t word = L.word;
+        const int p = (int)(word & 0xfu);
+        const uint32_t mask = (word >> 4) & 0x3fu;
+        double2 g[kQ];
+#pragma unroll
+        for (int d = 0; d < kQ; ++d) g[d] = ld2(&L.g[d]);
+        const bool face[6] = {fx0, fx1, fy0, fy1, fz0, fz1};
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            if (face[f]) {
+                double2 v = g[f + 1];
+                if (kind[f] & kFaceConj) v.y = -v.y;
+                g[f + 1] = cmul(v, face_fac[f]);
             }
-            const bool face[6] = {fx0, fx1, fy0, fy1, fz0, fz1};
+        }
+        if (mask) {
+            // half-link membrane: g' = ghat_opp(x) + t (incoming - ghat_opp(x))
 #pragma unroll
-            for (int f = 0; f < 6; ++f) {
-                if (face[f]) {
-                    double2 v = g[f + 1];
-                    if (kind[f] & kFaceConj) v.y = -v.y;
-                    g[f + 1] = cmul(v, face_fac[f]);
-                }
-            }
-            if (mask) {
-                // half-link membrane: g' = ghat_opp(x) + t (incoming - ghat_opp(x))
-#pragma unroll
-                for (int d = 1; d < kQ; ++d) {
-                    if ((mask >> (d - 1)) & 1u) {
-                        const int pn = (int)((word >> (10 + 3 * (d - 1))) & 0x7u);
-                        const double t = c_tr[p * kMaxPhase + pn];
-                        if (t < 1.0) {
-                            g[d].x = own[d].x + t * (g[d].x - own[d].x);
-                            g[d].y = own[d].y + t * (g[d].y - own[d].y);
-                        }
+            for (int d = 1; d < kQ; ++d) {
+                if ((mask >> (d - 1)) & 1u) {
+                    const int pn = (int)((word >> (10 + 3 * (d - 1))) & 0x7u);
+                    const double t = c_tr[p * P + pn];
+                    if (t < 1.0) {
+                        const double2 o = ld2(&L.own[d - 1]);
+                        g[d].x = o.x + t * (g[d].x - o.x);
+                        g[d].y = o.y + t * (g[d].y - o.y);
                     }
                 }
             }
-            // reaction: exp(-i fdt (c.j + cu)) exp(-dt/T2)
-            const double2 e = cmul(exy, ez[j2 - z0]);
-            const double dec = c_dec[p];
-            const double2 rf = make_double2(e.x * dec, e.y * dec);
-            double2 M = make_double2(0.0, 0.0);
-#pragma unroll
-            for (int d = 0; d < kQ; ++d) {
-                g[d] = cmul(g[d], rf);
-                M.x += g[d].x;
-                M.y += g[d].y;
-            }
-            Mv.x += M.x;
-            Mv.y += M.y;
-            // collision: ghat = g + w (w_d M - g)
-            const double w = c_w[p];
-            V* out = dst + pop + s;
-#pragma unroll
-            for (int d = 0; d < kQ; ++d) {
-                const double wd = d == 0 ? 0.25 : 0.125;
-                double2 h;
-                h.x = g[d].x + w * (wd * M.x - g[d].x);
-                h.y = g[d].y + w * (wd * M.y - g[d].y);
-                store2(out + (int64_t)d * ns, h);
-            }
         }
+        // reaction: exp(-i fdt (c.j + cu)) exp(-dt/T2)
+        const double2 e = cmul(exy, L.ez);
+        const double dec = c_dec[p];
+        const double2 rf = make_double2(e.x * dec, e.y * dec);
+        double2 M = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int d = 0; d < kQ; ++d) {
+            g[d] = cmul(g[d], rf);
+            M.x += g[d].x;
+            M.y += g[d].y;
+        }
+        Macc.x += M.x;
+        Macc.y += M.y;
+        // collision: ghat = g + w (w_d M - g)
+        const double w = c_w[p];
+        V* out = dst + pop + s;
+#pragma unroll
+        for (int d = 0; d < kQ; ++d) {
+            const double wd = d == 0 ? 0.25 : 0.125;
+            double2 h;
+            h.x = g[d].x + w * (wd * M.x - g[d].x);
+            h.y = g[d].y + w * (wd * M.y - g[d].y);
+            store2(out + (int64_t)d * ns, h);
+        }
+    };
+
+    double2 Mv = make_double2(0.0, 0.0);
+    if (j0 < n0 && j1 < n1 && z0 < z1) {
+        SiteLoads A, B;
+        issue(z0, A);
+        int32_t j2 = z0;
+        // two sites per trip so that A and B swap roles without copies
+        for (; j2 + 1 < z1; j2 += 2) {
+            issue(j2 + 1, B);
+            compute(j2, A, Mv);
+            if (j2 + 2 < z1) issue(j2 + 2, A);
+            compute(j2 + 1, B, Mv);
+        }
+        if (j2 < z1) compute(j2, A, Mv);
     }
 
     if (fd.q < 0) return;   // image fields do not enter the signal
@@ -318,6 +364,9 @@ static void launch_step_t(int shape, const StepArgs& a, int32_t n_blocks, hipStr
         case kTile32x8:
             hipLaunchKernelGGL((k_step<V, 32>), dim3(n_blocks), dim3(kBlock), 0, st, a);
             break;
+        case kTile128x2:
+            hipLaunchKernelGGL((k_step<V, 128>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+            break;
         default:
             hipLaunchKernelGGL((k_step<V, 16>), dim3(n_blocks), dim3(kBlock), 0, st, a);
             break;
@@ -329,6 +378,12 @@ hipError_t launch_step(int prec, int shape, const StepArgs& a, int32_t n_blocks,
         launch_step_t<float2>(shape, a, n_blocks, st);
     else
         launch_step_t<double2>(shape, a, n_blocks, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_tables(const StepArgs& a, int32_t nsteps, hipStream_t st) {
+    const int64_t n = (int64_t)nsteps * a.T;
+    if (n > 0) hipLaunchKernelGGL(k_tables, dim3(grid_for(n)), dim3(kBlock), 0, st, a, nsteps);
     return hipGetLastError();
 }
 

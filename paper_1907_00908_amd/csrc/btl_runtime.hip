@@ -7,6 +7,7 @@
 // launch per time step on the caller's stream.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -67,6 +68,8 @@ struct btl_sim {
     DevBuf<double> consts;       // w [P], decay [P], trans [P*P]
     DevBuf<double2> partial;
     DevBuf<uint32_t> counter;
+    DevBuf<double2> tab;         // [kTabSteps][T] per-step phase tables
+    DevBuf<int32_t> tab_field;   // [T]
     std::vector<FieldDesc> h_fields;
     // pinned staging for the per-call tables, two slots so that a call can
     // be prepared while the previous one's uploads are still queued
@@ -76,16 +79,27 @@ struct btl_sim {
     bool stage_used[2] = {false, false};
     int stage_slot = 0;
     int tile_shape = -1;        // -1: pick per call from the geometry sizes
-    int zc = 16;                // sites per thread along z
+    int zc = 0;                 // sites per thread along z; 0: whole column
+    // inputs of the last forward call (the autotuner replays them)
+    struct SimLastT {
+        bool valid = false;
+        double dt = 0;
+        std::vector<double> D, T2, kappa, gG0, f;
+        std::vector<int32_t> q_geom;
+    } last;
+    DevBuf<double> tune_E;
+    using SimLast = SimLastT;
     std::string err;
 };
 
 // Tile shape with the fewest idle lanes over the geometries of a call
 // (ties go to the wider x extent: longer contiguous rows per wavefront).
 static int pick_shape(const std::vector<GeomHost>& gs, const int32_t* q_geom, int Q) {
-    int best = kTile64x4;
+    static const int order[kTileCount] = {kTile128x2, kTile64x4, kTile32x8, kTile16x16};
+    int best = kTile128x2;
     int64_t best_waste = -1;
-    for (int sh = 0; sh < kTileCount; ++sh) {
+    for (int oi = 0; oi < kTileCount; ++oi) {
+        const int sh = order[oi];
         int tx, ty;
         tile_dims(sh, &tx, &ty);
         int64_t waste = 0;
@@ -282,6 +296,14 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const double dx = s->dx;
+    s->last.valid = true;
+    s->last.dt = dt;
+    s->last.D.assign(D, D + P);
+    s->last.T2.assign(T2, T2 + P);
+    s->last.kappa.assign(kappa, kappa + P * P);
+    s->last.gG0.assign(gG0, gG0 + 3 * Q);
+    s->last.f.assign(f, f + K);
+    s->last.q_geom.assign(q_geom, q_geom + Q);
 
     // per-phase and per-pair constants (FP64)
     std::vector<double> consts(2 * P + P * P);
@@ -319,7 +341,12 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
     const int shape = s->tile_shape >= 0 ? s->tile_shape : pick_shape(s->geoms, q_geom, Q);
     int TX, TY;
     tile_dims(shape, &TX, &TY);
-    const int ZC = s->zc;
+    int ZC = s->zc;
+    if (ZC <= 0) {
+        ZC = 1;
+        for (int q = 0; q < Q; ++q) ZC = std::max(ZC, s->geoms[q_geom[q]].n[2]);
+    }
+    ZC = std::min(ZC, kMaxZc);
 
     // field table
     std::vector<FieldDesc>& fl = s->h_fields;
@@ -401,6 +428,15 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
         }
     }
     const int32_t n_fields = (int32_t)fl.size();
+    // phase tables: per field [n0 + n1 + n2 + 6] entries
+    int32_t T = 0;
+    for (int i = 0; i < n_fields; ++i) {
+        fl[i].tab = T;
+        T += fl[i].n[0] + fl[i].n[1] + fl[i].n[2] + 6;
+    }
+    std::vector<int32_t> tabf(T);
+    for (int i = 0; i < n_fields; ++i)
+        for (int e = 0; e < fl[i].n[0] + fl[i].n[1] + fl[i].n[2] + 6; ++e) tabf[fl[i].tab + e] = i;
     std::vector<int32_t> blk(nblk_total);
     for (int i = 0; i < n_fields; ++i)
         for (int b = 0; b < fl[i].nblk; ++b) blk[fl[i].blk0 + b] = i;
@@ -416,7 +452,9 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
         (e = s->steps.ensure(steps.size())) != hipSuccess ||
         (e = s->consts.ensure(consts.size())) != hipSuccess ||
         (e = s->partial.ensure(nblk_total)) != hipSuccess ||
-        (e = s->counter.ensure(n_fields)) != hipSuccess)
+        (e = s->counter.ensure(n_fields)) != hipSuccess ||
+        (e = s->tab.ensure((size_t)kTabSteps * T)) != hipSuccess ||
+        (e = s->tab_field.ensure(T)) != hipSuccess)
         return hip_fail(s, e, "allocating tables");
     if (s->counter.cap != old_counter_cap) {
         // arrival counters start at zero; every step leaves them at zero
@@ -428,9 +466,11 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
     const size_t b_blk = (size_t)nblk_total * sizeof(int32_t);
     const size_t b_steps = steps.size() * sizeof(double);
     const size_t b_consts = consts.size() * sizeof(double);
+    const size_t b_tabf = (size_t)T * sizeof(int32_t);
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t o_blk = al(b_fields), o_steps = o_blk + al(b_blk), o_consts = o_steps + al(b_steps);
-    const size_t total = o_consts + al(b_consts);
+    const size_t o_tabf = o_consts + al(b_consts);
+    const size_t total = o_tabf + al(b_tabf);
     const int slot = s->stage_slot;
     if (!s->stage_ev[slot] && (e = hipEventCreateWithFlags(&s->stage_ev[slot], hipEventDisableTiming)) != hipSuccess)
         return hip_fail(s, e, "creating event");
@@ -449,10 +489,12 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
     memcpy(stg + o_blk, blk.data(), b_blk);
     memcpy(stg + o_steps, steps.data(), b_steps);
     memcpy(stg + o_consts, consts.data(), b_consts);
+    memcpy(stg + o_tabf, tabf.data(), b_tabf);
     if ((e = hipMemcpyAsync(s->fields.p, stg, b_fields, hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = hipMemcpyAsync(s->blk_field.p, stg + o_blk, b_blk, hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = hipMemcpyAsync(s->steps.p, stg + o_steps, b_steps, hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = hipMemcpyAsync(s->consts.p, stg + o_consts, b_consts, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(s->tab_field.p, stg + o_tabf, b_tabf, hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = hipEventRecord(s->stage_ev[slot], st)) != hipSuccess)
         return hip_fail(s, e, "uploading tables");
     s->stage_used[slot] = true;
@@ -476,7 +518,16 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
     a.E = E;
     a.n_phase = P;
     a.K = K;
+    a.tab_field = s->tab_field.p;
+    a.T = T;
     for (int k = 0; k < K; ++k) {
+        if (k % kTabSteps == 0) {
+            a.k = k;
+            a.tab = s->tab.p;
+            if ((e = launch_tables(a, std::min(kTabSteps, K - k), st)) != hipSuccess)
+                return hip_fail(s, e, "table launch");
+        }
+        a.tab = s->tab.p + (size_t)(k % kTabSteps) * T;
         a.src = s->pop[k & 1].p;
         a.dst = s->pop[(k + 1) & 1].p;
         a.k = k;
@@ -497,8 +548,73 @@ extern "C" btl_status btl_backward(btl_sim* s, const double*, double*, double*, 
     return fail(s, BTL_E_UNSUPPORTED, "adjoint not available in this build");
 }
 
-extern "C" btl_status btl_autotune(btl_sim* s, int32_t, int32_t, void*) {
+extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void* stream) {
     if (!s) return BTL_E_INVAL;
+    // fixed launch shape for measurements: BTLBM_TILE (0..3), BTLBM_ZC
+    const char* et = getenv("BTLBM_TILE");
+    const char* ez = getenv("BTLBM_ZC");
+    if (et || ez) {
+        if (et) s->tile_shape = std::max(0, std::min(kTileCount - 1, atoi(et)));
+        if (ez) s->zc = std::max(0, std::min(kMaxZc, atoi(ez)));
+        return BTL_OK;
+    }
+    if (!s->last.valid) return fail(s, BTL_E_INVAL, "btl_autotune replays the last btl_forward: call it first");
+    if (K_probe < 1) return fail(s, BTL_E_INVAL, "K_probe must be >= 1");
+    const btl_sim::SimLast& L = s->last;
+    const int32_t Qr = std::min<int32_t>(Q > 0 ? Q : (int32_t)L.q_geom.size(), (int32_t)L.q_geom.size());
+    std::vector<double> f(K_probe);
+    for (int k = 0; k < K_probe; ++k) f[k] = L.f.empty() ? 1.0 : L.f[k % L.f.size()];
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if ((e = s->tune_E.ensure((size_t)Qr * (K_probe + 1) * 2)) != hipSuccess)
+        return hip_fail(s, e, "autotune buffer");
+    hipEvent_t e0, e1;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+        return hip_fail(s, e, "autotune events");
+    int nz_max = 1;
+    for (int q = 0; q < Qr; ++q) nz_max = std::max(nz_max, s->geoms[L.q_geom[q]].n[2]);
+    std::vector<int> zcs = {0};
+    for (int z = 8; z < nz_max; z *= 2) zcs.push_back(z);
+    const btl_sim::SimLast saved = L;
+    float best = -1.0f;
+    int best_shape = -1, best_zc = 0;
+    btl_status rc = BTL_OK;
+    for (int sh = 0; sh < kTileCount && rc == BTL_OK; ++sh)
+        for (int zc : zcs) {
+            s->tile_shape = sh;
+            s->zc = zc;
+            rc = btl_forward(s, saved.dt, K_probe, saved.D.data(), saved.T2.data(), saved.kappa.data(),
+                             Qr, saved.q_geom.data(), saved.gG0.data(), f.data(), s->tune_E.p,
+                             nullptr, 0, stream);   // warm
+            if (rc != BTL_OK) break;
+            (void)hipEventRecord(e0, st);
+            rc = btl_forward(s, saved.dt, K_probe, saved.D.data(), saved.T2.data(), saved.kappa.data(),
+                             Qr, saved.q_geom.data(), saved.gG0.data(), f.data(), s->tune_E.p,
+                             nullptr, 0, stream);
+            if (rc != BTL_OK) break;
+            (void)hipEventRecord(e1, st);
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+                rc = hip_fail(s, e, "autotune timing");
+                break;
+            }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (best < 0.0f || ms < best) {
+                best = ms;
+                best_shape = sh;
+                best_zc = zc;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    s->last = saved;
+    if (rc != BTL_OK) {
+        s->tile_shape = -1;
+        s->zc = 0;
+        return rc;
+    }
+    s->tile_shape = best_shape;
+    s->zc = best_zc;
     return BTL_OK;
 }
 
@@ -514,6 +630,9 @@ extern "C" void btl_destroy(btl_sim* s) {
     s->consts.release();
     s->partial.release();
     s->counter.release();
+    s->tune_E.release();
+    s->tab.release();
+    s->tab_field.release();
     for (int i = 0; i < 2; ++i) {
         if (s->stage[i]) (void)hipHostFree(s->stage[i]);
         if (s->stage_ev[i]) (void)hipEventDestroy(s->stage_ev[i]);

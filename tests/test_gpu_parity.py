@@ -162,6 +162,23 @@ def test_deterministic_repeat():
     assert np.array_equal(E1, E2)
 
 
+def test_autotune_keeps_results():
+    btl = _gpu()
+    import torch
+    cfg = w.make_config("cfg4", n=(20, 18, 24), K=120, n_q=3)
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], "f64")
+    try:
+        args = (cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"])
+        E1 = sim.forward(*args).cpu().numpy()
+        btl.btl_autotune(sim._h, 3, 5, torch.cuda.current_stream().cuda_stream)
+        E2 = sim.forward(*args).cpu().numpy()
+    finally:
+        sim.close()
+    Eo, _ = oracle.simulate_config(cfg)
+    _check(E1, Eo, "f64", "before autotune")
+    _check(E2, Eo, "f64", "after autotune")
+
+
 def test_invalid_arguments_raise():
     btl = _gpu()
     cfg = w.make_config("cfg1", n=4, K=3)
