@@ -212,6 +212,71 @@ class Simulator:
         return Ec, Ms
 
 
+    def backward(self, dLdE, P: int, K: int):
+        """Gradients of a real loss from dL/dE (torch (Q, K+1, 2) float64 on
+        the device: dL/dRe E, dL/dIm E) for the last forward that kept a tape.
+        Returns device tensors dD [P], dT2 [P], dkappa [P, P], df [K]."""
+        torch = self.torch
+        dev = dLdE.device
+        g = dLdE.detach().to(torch.float64).contiguous()
+        dD = torch.empty(P, dtype=torch.float64, device=dev)
+        dT2 = torch.empty(P, dtype=torch.float64, device=dev)
+        dk = torch.empty((P, P), dtype=torch.float64, device=dev)
+        df = torch.empty(max(K, 1), dtype=torch.float64, device=dev)
+        stream = torch.cuda.current_stream().cuda_stream
+        btl_backward(self._h, g.data_ptr(), dD.data_ptr(), dT2.data_ptr(), dk.data_ptr(),
+                     df.data_ptr(), stream)
+        return dD, dT2, dk, df[:K]
+
+
+def _bt_function():
+    import torch
+
+    class BlochTorreySignal(torch.autograd.Function):
+        """E = signal(D, T2, kappa, f) as a real (Q, K+1, 2) tensor, with the
+        hand-written adjoint of libbtlbm as its backward.
+
+        forward(D [P], T2 [P], kappa [P, P], f [K], sim, dt, gG0 [Q, 3],
+        q_geom [Q], ckpt_every).  The parameters may live on any device; the
+        returned gradients are placed on the parameter's device."""
+
+        @staticmethod
+        def forward(ctx, D, T2, kappa, f, sim, dt, gG0, q_geom, ckpt_every):
+            Dn = D.detach().cpu().double().numpy()
+            T2n = T2.detach().cpu().double().numpy()
+            kn = kappa.detach().cpu().double().numpy()
+            fn = f.detach().cpu().double().numpy()
+            E = sim.forward(dt, Dn, T2n, kn, fn, gG0, q_geom, ckpt_every=max(1, int(ckpt_every)))
+            ctx.sim = sim
+            ctx.P = len(Dn)
+            ctx.K = len(fn)
+            ctx.devs = (D.device, T2.device, kappa.device, f.device)
+            return torch.view_as_real(E).clone()
+
+        @staticmethod
+        def backward(ctx, gE):
+            dD, dT2, dk, df = ctx.sim.backward(gE, ctx.P, ctx.K)
+            d0, d1, d2, d3 = ctx.devs
+            return (dD.to(d0), dT2.to(d1), dk.to(d2), df.to(d3),
+                    None, None, None, None, None)
+
+    return BlochTorreySignal
+
+
+_BTS = None
+
+
+def bloch_torrey_signal(D, T2, kappa, f, sim, dt, gG0, q_geom=None, ckpt_every=100):
+    """Differentiable signal (see BlochTorreySignal)."""
+    global _BTS
+    if _BTS is None:
+        _BTS = _bt_function()
+    gG0 = np.ascontiguousarray(gG0, np.float64).reshape(-1, 3)
+    if q_geom is None:
+        q_geom = np.zeros(len(gG0), np.int32)
+    return _BTS.apply(D, T2, kappa, f, sim, dt, gG0, q_geom, ckpt_every)
+
+
 def simulate_config(cfg: dict, prec: str = "f32", want_M: bool = False):
     """Run a workloads config on the GPU: returns E (Q, K+1) complex (and M)."""
     sim = Simulator(cfg["geoms"], cfg["bc"], prec)

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["btl_kernels.hip", "btl_runtime.hip"]
+SOURCES = ["btl_kernels.hip", "btl_adjoint.hip", "btl_runtime.hip"]
 LIB = os.path.join(HERE, "libbtlbm.so")
 ARCH = "gfx950"
 

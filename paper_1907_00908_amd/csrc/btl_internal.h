@@ -41,7 +41,42 @@ struct FieldDesc {
     int64_t face_pop[6];    // direction-0 plane offset of each face's source field
     double beta[6];         // face factor exp(i * beta * F_k)
     int32_t face_kind[6];
-    int32_t pad2[2];
+    // Adjoint pull through face f (f = 2a+1 for direction +a at node n_a-1,
+    // f = 2a for direction -a at node 0): the field whose adjoint is read,
+    // how (kind), and where its forward coefficient sits in a step table.
+    int32_t adj_kind[6];
+    int64_t adj_pop[6];
+    int32_t adj_fac[6];
+    int32_t pad3[2];
+};
+
+constexpr int kAdjMaxPhase = 4;
+// gradient accumulators per step: w[P], decay[P], trans[P*P], f, F
+constexpr int kNGMax = 2 * kAdjMaxPhase + kAdjMaxPhase * kAdjMaxPhase + 2;
+
+struct AdjArgs {
+    const void* lam_in;     // adjoint of the post-stream populations of step k (NULL: k = K)
+    void* lam_out;          // same for step k-1
+    const void* fwd;        // post-collision populations entering step k-1
+    const uint32_t* words;
+    const FieldDesc* fields;
+    const int32_t* blk_field;
+    const double2* tab_prev;  // phase tables of step k-1
+    const double2* tab_cur;   // phase tables of step k (face factors of its stream)
+    const double* w;
+    const double* decay;
+    const double* trans;
+    const double2* dLdE;    // [Q][K+1]
+    double* gpart;          // [blocks][NG] per-workgroup gradient sums
+    uint32_t* counter;      // [fields]
+    double* gfield;         // [K][fields][NG] per-step, per-field gradient sums
+    double dt;
+    int32_t n_fields;
+    int32_t n_phase;
+    int32_t k;
+    int32_t K;
+    int32_t top;            // 1 when k = K (no adjoint from later steps)
+    int32_t ng;
 };
 
 struct StepArgs {
@@ -74,7 +109,12 @@ inline void tile_dims(int shape, int* tx, int* ty) {
     *ty = kBlock / *tx;
 }
 
-// Launchers (btl_kernels.hip)
+// Launchers (btl_kernels.hip, btl_adjoint.hip)
+hipError_t launch_adj(int prec, int shape, const AdjArgs& a, int32_t n_blocks, hipStream_t st);
+hipError_t launch_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P,
+                            double dt, double dx, const double* w, const double* T2,
+                            const double* kappa, double* dD, double* dT2, double* dkappa,
+                            double* df, hipStream_t st);
 hipError_t launch_init(int prec, void* pop, int64_t n_elem_per_dir_total,
                        const FieldDesc* d_fields, int32_t n_fields,
                        const FieldDesc* h_fields, double* E, int32_t Q, int32_t K,

@@ -25,59 +25,9 @@
 // The signal of a step is reduced deterministically: each workgroup writes a
 // partial sum, and the last workgroup of a field to finish (arrival counter)
 // adds all partials of that field in a fixed order.
-#include "btl_internal.h"
+#include "btl_device.h"
 
 namespace btl {
-
-__device__ __forceinline__ double2 ld2(const float2* p) {
-    const float2 v = *p;
-    return make_double2((double)v.x, (double)v.y);
-}
-__device__ __forceinline__ double2 ld2(const double2* p) { return *p; }
-__device__ __forceinline__ void store2(float2* p, double2 v) {
-    *p = make_float2((float)v.x, (float)v.y);
-}
-__device__ __forceinline__ void store2(double2* p, double2 v) { *p = v; }
-
-// Value that is the same in every lane, kept in scalar registers.
-__device__ __forceinline__ double uniform(double v) {
-    const unsigned long long u = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readfirstlane((int)(u & 0xffffffffu));
-    const int hi = __builtin_amdgcn_readfirstlane((int)(u >> 32));
-    return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
-}
-__device__ __forceinline__ double2 uniform2(double2 v) {
-    return make_double2(uniform(v.x), uniform(v.y));
-}
-
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Fixed-order sum of v over the 256 threads of the workgroup; the result is
-// valid in thread 0.
-__device__ __forceinline__ double2 block_sum(double2 v, double2* lds) {
-    v.x = wave_sum(v.x);
-    v.y = wave_sum(v.y);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) lds[wv] = v;
-    __syncthreads();
-    double2 r = make_double2(0.0, 0.0);
-    if (threadIdx.x == 0) {
-        r = lds[0];
-        for (int i = 1; i < kBlock / 64; ++i) {
-            r.x += lds[i].x;
-            r.y += lds[i].y;
-        }
-    }
-    return r;
-}
 
 template <typename V>
 __global__ void __launch_bounds__(kBlock) k_init(V* pop, int64_t nsites, double2* E,
@@ -88,13 +38,6 @@ __global__ void __launch_bounds__(kBlock) k_init(V* pop, int64_t nsites, double2
         store2(pop + e, make_double2(d == 0 ? 0.25 : 0.125, 0.0));
     }
     if (E != nullptr && q >= 0 && e == 0) E[(int64_t)q * (K + 1)] = make_double2(1.0, 0.0);
-}
-
-// exp(i th) in FP64 (library sincos; used only in workgroup prologues).
-__device__ __forceinline__ double2 expi(double th) {
-    double sn, cs;
-    sincos(th, &sn, &cs);
-    return make_double2(cs, sn);
 }
 
 // Entry e of the phase table of step k (see FieldDesc::tab).

@@ -89,6 +89,21 @@ struct btl_sim {
     } last;
     DevBuf<double> tune_E;
     using SimLast = SimLastT;
+    // adjoint tape of the last forward that asked for one
+    struct Tape {
+        bool valid = false;
+        int32_t K = 0, C = 0, Q = 0, T = 0, n_fields = 0, nblk = 0, shape = 0;
+        double dt = 0;
+        int64_t state_elems = 0;   // V elements of one full state (all fields)
+    } tape;
+    DevBuf<char> ckpt;             // [ceil(K/C)] states: ghat^{mC}
+    DevBuf<char> seg;              // [C] states of the segment being reversed
+    DevBuf<char> lam[2];
+    DevBuf<double2> tab_b;         // [C+1][T] phase tables of a segment
+    DevBuf<double> gpart;
+    DevBuf<double> gfield;
+    DevBuf<uint32_t> adj_counter;
+    DevBuf<double> scratch_E;
     std::string err;
 };
 
@@ -274,7 +289,7 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
     if (Q < 1) return fail(s, BTL_E_INVAL, "Q must be >= 1");
     if (!D || !T2 || !kappa || !q_geom || !gG0 || (K > 0 && !f) || !E)
         return fail(s, BTL_E_INVAL, "NULL argument");
-    if (ckpt_every != 0) return fail(s, BTL_E_UNSUPPORTED, "adjoint tape not available in this build");
+    if (ckpt_every < 0) return fail(s, BTL_E_INVAL, "ckpt_every must be >= 0");
     const int32_t P = s->n_phase;
     for (int p = 0; p < P; ++p) {
         if (!(D[p] > 0) || !isfinite(D[p])) return fail(s, BTL_E_INVAL, "D must be finite and > 0");
@@ -306,7 +321,7 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
     s->last.q_geom.assign(q_geom, q_geom + Q);
 
     // per-phase and per-pair constants (FP64)
-    std::vector<double> consts(2 * P + P * P);
+    std::vector<double> consts(2 * P + P * P + P + P * P);
     for (int p = 0; p < P; ++p) {
         const double tau = 0.5 + dt * D[p] / (kEpsD * dx * dx);
         consts[p] = 1.0 / tau;
@@ -325,6 +340,8 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
         }
         consts[2 * P + i] = t;
     }
+    for (int p = 0; p < P; ++p) consts[2 * P + P * P + p] = T2[p];
+    for (int i = 0; i < P * P; ++i) consts[3 * P + P * P + i] = kappa[i];
     // per-step waveform tables
     std::vector<double> steps((size_t)K + (size_t)K + 1);
     {
@@ -426,6 +443,27 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
                 }
             }
         }
+        // adjoint pull through each face: periodic faces read the same field
+        // at the wrapped node with the forward factor of the opposite face;
+        // mirror faces read the partner field (the forward source of that
+        // face, an involution) with that partner's factor and conjugation
+        for (size_t fi = 0; fi < qf.sigma.size(); ++fi) {
+            FieldDesc& d = fl[base + fi];
+            for (int f = 0; f < 6; ++f) {
+                if ((d.face_kind[f] & kFaceMirror) == 0) {
+                    d.adj_kind[f] = kFacePeriodic;
+                    d.adj_pop[f] = d.pop;
+                    d.adj_fac[f] = -1 - (f ^ 1);          // own table, resolved below
+                } else {
+                    int partner = -1;
+                    for (size_t pj = 0; pj < qf.sigma.size(); ++pj)
+                        if (fl[base + pj].pop == d.face_pop[f]) partner = base + (int)pj;
+                    d.adj_kind[f] = fl[partner].face_kind[f];
+                    d.adj_pop[f] = fl[partner].pop;
+                    d.adj_fac[f] = -1000 - (partner * 6 + f);  // partner table, resolved below
+                }
+            }
+        }
     }
     const int32_t n_fields = (int32_t)fl.size();
     // phase tables: per field [n0 + n1 + n2 + 6] entries
@@ -434,6 +472,17 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
         fl[i].tab = T;
         T += fl[i].n[0] + fl[i].n[1] + fl[i].n[2] + 6;
     }
+    for (int i = 0; i < n_fields; ++i)
+        for (int f = 0; f < 6; ++f) {
+            const int32_t v = fl[i].adj_fac[f];
+            if (v <= -1000) {
+                const int partner = (-1000 - v) / 6, pf = (-1000 - v) % 6;
+                fl[i].adj_fac[f] = fl[partner].tab + fl[partner].n[0] + fl[partner].n[1] +
+                                   fl[partner].n[2] + pf;
+            } else {
+                fl[i].adj_fac[f] = fl[i].tab + fl[i].n[0] + fl[i].n[1] + fl[i].n[2] + (-1 - v);
+            }
+        }
     std::vector<int32_t> tabf(T);
     for (int i = 0; i < n_fields; ++i)
         for (int e = 0; e < fl[i].n[0] + fl[i].n[1] + fl[i].n[2] + 6; ++e) tabf[fl[i].tab + e] = i;
@@ -500,9 +549,31 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
     s->stage_used[slot] = true;
     s->stage_slot ^= 1;
 
+    s->tape.valid = false;
+    const size_t state_bytes = (size_t)pop_elems * esz;
+    if (ckpt_every > 0 && K > 0) {
+        if (P > kAdjMaxPhase) return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports n_phase <= 4");
+        const int32_t C = std::min(ckpt_every, K);
+        const int32_t nck = (K + C - 1) / C;
+        if ((e = s->ckpt.ensure((size_t)nck * state_bytes)) != hipSuccess)
+            return hip_fail(s, e, "allocating checkpoints");
+        s->tape.K = K;
+        s->tape.C = C;
+        s->tape.Q = Q;
+        s->tape.T = T;
+        s->tape.n_fields = n_fields;
+        s->tape.nblk = nblk_total;
+        s->tape.shape = shape;
+        s->tape.dt = dt;
+        s->tape.state_elems = pop_elems;
+    }
     if ((e = launch_init(s->prec, s->pop[0].p, pop_elems, s->fields.p, n_fields, fl.data(), E,
                          Q, K, st)) != hipSuccess)
         return hip_fail(s, e, "init launch");
+    if (ckpt_every > 0 && K > 0 &&
+        (e = hipMemcpyAsync(s->ckpt.p, s->pop[0].p, state_bytes, hipMemcpyDeviceToDevice, st)) !=
+            hipSuccess)
+        return hip_fail(s, e, "checkpoint copy");
     StepArgs a;
     memset(&a, 0, sizeof(a));
     a.words = s->words.p;
@@ -533,7 +604,14 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
         a.k = k;
         if ((e = launch_step(s->prec, shape, a, nblk_total, st)) != hipSuccess)
             return hip_fail(s, e, "step launch");
+        if (ckpt_every > 0 && (k + 1) % s->tape.C == 0 && k + 1 < K) {
+            const size_t m = (size_t)(k + 1) / s->tape.C;
+            if ((e = hipMemcpyAsync(s->ckpt.p + m * state_bytes, s->pop[(k + 1) & 1].p, state_bytes,
+                                    hipMemcpyDeviceToDevice, st)) != hipSuccess)
+                return hip_fail(s, e, "checkpoint copy");
+        }
     }
+    if (ckpt_every > 0 && K > 0) s->tape.valid = true;
     if (M_final) {
         if ((e = launch_mfinal(s->prec, s->pop[K & 1].p, fl.data(), n_fields, M_final, st)) !=
             hipSuccess)
@@ -542,10 +620,108 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
     return BTL_OK;
 }
 
-extern "C" btl_status btl_backward(btl_sim* s, const double*, double*, double*, double*,
-                                   double*, void*) {
+extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, double* dT2,
+                                   double* dkappa, double* df, void* stream) {
     if (!s) return BTL_E_INVAL;
-    return fail(s, BTL_E_UNSUPPORTED, "adjoint not available in this build");
+    if (!s->tape.valid) return fail(s, BTL_E_INVAL, "no adjoint tape: run btl_forward with ckpt_every > 0");
+    if (!dL_dE) return fail(s, BTL_E_INVAL, "dL_dE is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const btl_sim::Tape& tp = s->tape;
+    const int32_t K = tp.K, C = tp.C, T = tp.T, P = s->n_phase, nf = tp.n_fields;
+    const int NG = 2 * P + P * P + 2;
+    const size_t esz = s->prec == BTL_F32 ? sizeof(float2) : sizeof(double2);
+    const size_t state_bytes = (size_t)tp.state_elems * esz;
+    hipError_t e;
+    if ((e = s->seg.ensure((size_t)C * state_bytes)) != hipSuccess ||
+        (e = s->lam[0].ensure(state_bytes)) != hipSuccess ||
+        (e = s->lam[1].ensure(state_bytes)) != hipSuccess ||
+        (e = s->tab_b.ensure((size_t)(C + 1) * T)) != hipSuccess ||
+        (e = s->gpart.ensure((size_t)tp.nblk * NG)) != hipSuccess ||
+        (e = s->gfield.ensure((size_t)K * nf * NG)) != hipSuccess ||
+        (e = s->scratch_E.ensure((size_t)tp.Q * (K + 1) * 2)) != hipSuccess)
+        return hip_fail(s, e, "allocating adjoint buffers");
+    const size_t old_cap = s->adj_counter.cap;
+    if ((e = s->adj_counter.ensure(nf)) != hipSuccess) return hip_fail(s, e, "adjoint counters");
+    if (s->adj_counter.cap != old_cap &&
+        (e = hipMemset(s->adj_counter.p, 0, s->adj_counter.cap * sizeof(uint32_t))) != hipSuccess)
+        return hip_fail(s, e, "clearing adjoint counters");
+
+    StepArgs fa;   // forward recompute
+    memset(&fa, 0, sizeof(fa));
+    fa.words = s->words.p;
+    fa.fields = s->fields.p;
+    fa.blk_field = s->blk_field.p;
+    fa.fdt = s->steps.p;
+    fa.Fk = s->steps.p + K;
+    fa.w = s->consts.p;
+    fa.decay = s->consts.p + P;
+    fa.trans = s->consts.p + 2 * P;
+    fa.partial = s->partial.p;
+    fa.counter = s->counter.p;
+    fa.E = s->scratch_E.p;
+    fa.n_phase = P;
+    fa.K = K;
+    fa.tab_field = s->tab_field.p;
+    fa.T = T;
+
+    AdjArgs aa;
+    memset(&aa, 0, sizeof(aa));
+    aa.words = s->words.p;
+    aa.fields = s->fields.p;
+    aa.blk_field = s->blk_field.p;
+    aa.w = s->consts.p;
+    aa.decay = s->consts.p + P;
+    aa.trans = s->consts.p + 2 * P;
+    aa.dLdE = reinterpret_cast<const double2*>(dL_dE);
+    aa.gpart = s->gpart.p;
+    aa.counter = s->adj_counter.p;
+    aa.gfield = s->gfield.p;
+    aa.dt = tp.dt;
+    aa.n_fields = nf;
+    aa.n_phase = P;
+    aa.K = K;
+    aa.ng = NG;
+
+    const int32_t nseg = (K + C - 1) / C;
+    int lam_cur = 0;      // buffer holding Lambda^k on entry to adjoint step k
+    for (int32_t m = nseg - 1; m >= 0; --m) {
+        const int32_t k0 = m * C, k1 = std::min(K, k0 + C);
+        // phase tables of steps k0 .. k1 (the last only when k1 < K)
+        fa.k = k0;
+        fa.tab = s->tab_b.p;
+        if ((e = launch_tables(fa, (k1 - k0) + (k1 < K ? 1 : 0), st)) != hipSuccess)
+            return hip_fail(s, e, "adjoint table launch");
+        // recompute ghat^{k0+1} .. ghat^{k1-1} from the checkpoint
+        const char* ck = s->ckpt.p + (size_t)m * state_bytes;
+        if ((e = hipMemcpyAsync(s->seg.p, ck, state_bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+            return hip_fail(s, e, "segment copy");
+        for (int32_t k = k0; k < k1 - 1; ++k) {
+            fa.k = k;
+            fa.tab = s->tab_b.p + (size_t)(k - k0) * T;
+            fa.src = s->seg.p + (size_t)(k - k0) * state_bytes;
+            fa.dst = s->seg.p + (size_t)(k - k0 + 1) * state_bytes;
+            if ((e = launch_step(s->prec, tp.shape, fa, tp.nblk, st)) != hipSuccess)
+                return hip_fail(s, e, "recompute launch");
+        }
+        // reverse sweep over the segment
+        for (int32_t k = k1; k > k0; --k) {
+            aa.k = k;
+            aa.top = (k == K) ? 1 : 0;
+            aa.lam_in = aa.top ? nullptr : s->lam[lam_cur].p;
+            aa.lam_out = s->lam[lam_cur ^ 1].p;
+            aa.fwd = s->seg.p + (size_t)(k - 1 - k0) * state_bytes;
+            aa.tab_prev = s->tab_b.p + (size_t)(k - 1 - k0) * T;
+            aa.tab_cur = aa.top ? aa.tab_prev : s->tab_b.p + (size_t)(k - k0) * T;
+            if ((e = launch_adj(s->prec, tp.shape, aa, tp.nblk, st)) != hipSuccess)
+                return hip_fail(s, e, "adjoint launch");
+            lam_cur ^= 1;
+        }
+    }
+    if ((e = launch_adj_final(s->gfield.p, K, nf, P, tp.dt, s->dx, s->consts.p,
+                              s->consts.p + 2 * P + P * P, s->consts.p + 3 * P + P * P, dD, dT2,
+                              dkappa, df, st)) != hipSuccess)
+        return hip_fail(s, e, "adjoint final launch");
+    return BTL_OK;
 }
 
 extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void* stream) {
@@ -631,6 +807,15 @@ extern "C" void btl_destroy(btl_sim* s) {
     s->partial.release();
     s->counter.release();
     s->tune_E.release();
+    s->ckpt.release();
+    s->seg.release();
+    s->lam[0].release();
+    s->lam[1].release();
+    s->tab_b.release();
+    s->gpart.release();
+    s->gfield.release();
+    s->adj_counter.release();
+    s->scratch_E.release();
     s->tab.release();
     s->tab_field.release();
     for (int i = 0; i < 2; ++i) {

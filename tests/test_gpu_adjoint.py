@@ -1,0 +1,166 @@
+"""Adjoint (reverse-mode gradient) of the HIP path, through the C ABI.
+
+References: central finite differences of the FP64 CPU oracle (loss linear
+in E with random weights, so the only error of the difference quotient is
+its O(h^2) truncation), and the closed form dE_K/dT2 = (K dt / T2^2) E_K of
+pure T2 decay.  Bounds: FP64 storage within 1e-6 relative of the FD value,
+FP32 storage within 1e-3 relative (of the largest gradient component of
+the same kind).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+INF = math.inf
+
+
+def _gpu():
+    import torch
+    import paper_1907_00908_amd as btl
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    btl.load_library()
+    return btl, torch
+
+
+def _loss_weights(Q, K, seed=7):
+    r = np.random.default_rng(seed)
+    return r.normal(size=(Q, K + 1)), r.normal(size=(Q, K + 1))
+
+
+def _oracle_loss(cfg, D, T2, kap, f, a, b):
+    c = dict(cfg)
+    c.update(D=np.asarray(D, float), T2=np.asarray(T2, float), kappa=np.asarray(kap, float),
+             f=np.asarray(f, float))
+    E, _ = oracle.simulate_config(c, threads=8)
+    return float(np.sum(a * E.real + b * E.imag))
+
+
+def _fd(cfg, a, b, which, idx, h_rel=1e-5):
+    D, T2, kap, f = (np.array(cfg["D"], float), np.array(cfg["T2"], float),
+                     np.array(cfg["kappa"], float), np.array(cfg["f"], float))
+    arrs = {"D": D, "T2": T2, "kappa": kap, "f": f}
+    x = arrs[which]
+    base = x[idx]
+    h = h_rel * max(abs(base), 1e-3 if which != "f" else 1.0)
+    vals = []
+    for sgn in (1, -1):
+        y = x.copy()
+        y[idx] = base + sgn * h
+        if which == "kappa":
+            y[idx[::-1]] = base + sgn * h
+        args = dict(D=D, T2=T2, kap=kap, f=f)
+        args[{"D": "D", "T2": "T2", "kappa": "kap", "f": "f"}[which]] = y
+        vals.append(_oracle_loss(cfg, args["D"], args["T2"], args["kap"], args["f"], a, b))
+    return (vals[0] - vals[1]) / (2 * h)
+
+
+def _gpu_grads(cfg, prec, a, b, ckpt):
+    btl, torch = _gpu()
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], prec)
+    try:
+        E = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"],
+                        cfg["q_geom"], ckpt_every=ckpt)
+        g = torch.tensor(np.stack([a, b], axis=-1), dtype=torch.float64, device=E.device)
+        P = len(cfg["D"])
+        dD, dT2, dk, df = sim.backward(g, P, len(cfg["f"]))
+        torch.cuda.synchronize()
+        return dD.cpu().numpy(), dT2.cpu().numpy(), dk.cpu().numpy(), df.cpu().numpy()
+    finally:
+        sim.close()
+
+
+def _cfg_small(bc, seed=51, K=160, n=(12, 10, 8), gG=None):
+    g = w.cylinders_z(n, 0.25, seed=seed, vf_target=0.5, periodic=(bc[0] == 0))
+    f = w.pgse_waveform(0.12, 0.4, 0.004)[:K]
+    if gG is None:
+        gG = np.array([[9.0, 5.0, 3.0], [-4.0, 8.0, 0.0]])
+    return dict(name="adj", geoms=[g], bc=bc, dx=0.25, dt=0.004, D=np.array([2.0, 1.0]),
+                T2=np.array([40.0, 25.0]), kappa=np.array([[INF, 0.05], [0.05, INF]]),
+                f=f, gG0=gG, q_geom=np.zeros(len(gG), np.int32))
+
+
+def _compare(cfg, prec, ckpt, tol, fidx=(0, 20, 55, 120)):
+    Q, K = len(cfg["gG0"]), len(cfg["f"])
+    a, b = _loss_weights(Q, K)
+    dD, dT2, dk, df = _gpu_grads(cfg, prec, a, b, ckpt)
+    checks = [("D", (0,), dD[0]), ("D", (1,), dD[1]), ("T2", (0,), dT2[0]),
+              ("T2", (1,), dT2[1]), ("kappa", (0, 1), dk[0, 1])]
+    checks += [("f", (i,), df[i]) for i in fidx if i < K]
+    scale = {}
+    fds = []
+    for which, idx, gval in checks:
+        fd = _fd(cfg, a, b, which, idx if which != "D" and which != "T2" and which != "f"
+                 else idx[0])
+        fds.append((which, idx, gval, fd))
+        scale[which] = max(scale.get(which, 0.0), abs(fd))
+    for which, idx, gval, fd in fds:
+        err = abs(gval - fd) / max(scale[which], 1e-30)
+        print(f"{prec} {which}{idx}: adjoint {gval:.9e} fd {fd:.9e} rel {err:.2e}", flush=True)
+        assert err <= tol, (which, idx, gval, fd)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-6), ("f32", 1e-3)])
+def test_adjoint_periodic_vs_oracle_fd(prec, tol):
+    cfg = _cfg_small([0, 0, 0])
+    _compare(cfg, prec, ckpt=40, tol=tol)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-6), ("f32", 1e-3)])
+def test_adjoint_mirror_oblique_vs_oracle_fd(prec, tol):
+    # mirrored faces with oblique gradients: image fields and their
+    # conjugate couplings in the transposed stream
+    cfg = _cfg_small([1, 1, 1], seed=52, gG=np.array([[7.0, -5.0, 0.0], [3.0, 2.0, 6.0]]))
+    _compare(cfg, prec, ckpt=33, tol=tol)
+
+
+def test_adjoint_T2_closed_form():
+    # G = 0, one phase, uniform medium: E_K = exp(-K dt / T2), so
+    # dE_K/dT2 = (K dt / T2^2) E_K and dL/dD = dL/dkappa = 0
+    btl, torch = _gpu()
+    g = w.uniform((8, 8, 8), 0.5)
+    K, dt, T2 = 300, 0.01, 30.0
+    cfg = dict(geoms=[g], bc=[0, 0, 0], dt=dt, D=np.array([1.5]), T2=np.array([T2]),
+               kappa=np.array([[INF]]), f=np.zeros(K), gG0=np.zeros((1, 3)),
+               q_geom=np.zeros(1, np.int32))
+    a = np.zeros((1, K + 1))
+    a[0, K] = 1.0
+    dD, dT2, dk, df = _gpu_grads(cfg, "f64", a, np.zeros_like(a), ckpt=64)
+    EK = math.exp(-K * dt / T2)
+    assert abs(dT2[0] - K * dt / T2 ** 2 * EK) < 1e-12
+    assert abs(dD[0]) < 1e-13
+
+
+def test_checkpoint_interval_does_not_change_gradients():
+    cfg = _cfg_small([0, 0, 0], seed=53, K=90)
+    Q, K = len(cfg["gG0"]), len(cfg["f"])
+    a, b = _loss_weights(Q, K, seed=3)
+    r1 = _gpu_grads(cfg, "f64", a, b, ckpt=90)
+    r2 = _gpu_grads(cfg, "f64", a, b, ckpt=7)
+    for x, y in zip(r1, r2):
+        assert np.allclose(x, y, rtol=1e-12, atol=1e-15)
+
+
+def test_autograd_function():
+    btl, torch = _gpu()
+    cfg = _cfg_small([0, 0, 0], seed=54, K=80)
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], "f64")
+    try:
+        D = torch.tensor(cfg["D"], requires_grad=True)
+        T2 = torch.tensor(cfg["T2"], requires_grad=True)
+        kap = torch.tensor(cfg["kappa"], requires_grad=True)
+        samples = torch.tensor(np.asarray(cfg["f"])[::8], requires_grad=True)
+        f = samples.repeat_interleave(8)[:len(cfg["f"])]
+        E = btl.bloch_torrey_signal(D, T2, kap, f, sim, cfg["dt"], cfg["gG0"], ckpt_every=25)
+        loss = (E[:, -1, 0] ** 2 + E[:, -1, 1] ** 2).sum()
+        loss.backward()
+    finally:
+        sim.close()
+    assert D.grad.shape == (2,) and torch.isfinite(D.grad).all()
+    assert samples.grad.shape == samples.shape and torch.isfinite(samples.grad).all()
+    assert kap.grad[0, 1] == kap.grad[1, 0]
