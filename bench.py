@@ -115,6 +115,48 @@ def cpu_baseline(cfg, budget_s: float = 15.0):
                       f"the oracle steps the 2x2x2 reflected domain), {t1 - t0:.1f} s"}
 
 
+def bench_adjoint(btl, torch, sim, cfg, args, fwd_ms_step, nf, sites, Q):
+    """Reverse sweep of the same workload: forward with a checkpoint every
+    adj_ckpt steps, then btl_backward for a linear loss in E.  The end-to-end
+    rate counts q-sample site-updates of the reverse sweep (it recomputes
+    each segment forward and runs one adjoint step per forward step)."""
+    Kb, C = args.adj_steps, args.adj_ckpt
+    c = dict(cfg)
+    c["f"] = cfg["f"][:Kb]
+    stream = torch.cuda.current_stream()
+    E = sim.forward(c["dt"], c["D"], c["T2"], c["kappa"], c["f"], c["gG0"], c["q_geom"],
+                    ckpt_every=C)
+    gen = torch.Generator(device="cpu").manual_seed(0)
+    g = torch.randn((Q, Kb + 1, 2), generator=gen, dtype=torch.float64).to(E.device)
+    P = len(c["D"])
+    sim.backward(g, P, Kb)                      # warm
+    sim.forward(c["dt"], c["D"], c["T2"], c["kappa"], c["f"], c["gG0"], c["q_geom"],
+                ckpt_every=C)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    dD, dT2, dk, df = sim.backward(g, P, Kb)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    nseg = (Kb + C - 1) // C
+    recompute_ms = (Kb - nseg) * fwd_ms_step
+    adj_ms = max(ms - recompute_ms, 1e-9) / Kb
+    bpf = 168 if args.prec == "f32" else 336
+    ach = nf * sites * bpf / (adj_ms * 1e-3) / 1e9
+    finite = bool(torch.isfinite(dD).all() and torch.isfinite(df).all())
+    return {"value": Q * sites * Kb / (ms * 1e-3), "unit": "site-updates/s",
+            "what": "end-to-end reverse sweep (segment recompute + adjoint step)",
+            "steps": Kb, "ckpt_every": C, "ms_total": ms,
+            "adjoint_kernel": {"ms_per_step_est": adj_ms,
+                               "bytes_per_launch_algorithmic": nf * sites * bpf,
+                               "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS,
+                               "estimate": "backward time minus the recompute steps at the "
+                                           "measured forward step time"},
+            "gradients_finite": finite}
+
+
 def traffic_for(kernel_avg_ms):
     try:
         with open(TRAFFIC_FILE) as fh:
@@ -134,6 +176,9 @@ def main():
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adj-steps", type=int, default=400)
+    ap.add_argument("--adj-ckpt", type=int, default=20)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP64 comparison runs (profiling)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -212,6 +257,8 @@ def main():
                                         "speedup_of_value": value / v1}
         out["fp64_batched"] = {"value": Q * sites * K / (ms64 * 1e-3)}
         sim64.close()
+    if not args.no_adjoint:
+        out["adjoint"] = bench_adjoint(btl, torch, sim, cfg, args, ms_step, nf, sites, Q)
     sim.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
