@@ -24,8 +24,9 @@
 //   d/dt_pair   sum Re conj(Lambda_i) (pulled - own)         membrane links
 //   d/df_{k-1}  sum dt (c.j + cu) Im( conj(nu_i) g_i )      reaction phase
 //   d/dF_{k-1}  sum -beta t Im( conj(Lambda_i) pulled )      face factors
-// Each workgroup sums them in LDS (one row per thread, so the order is fixed)
-// and the last workgroup of a field sums the workgroup rows in a fixed order.
+// Per-phase sums are kept in registers (selected by the node's phase), the
+// membrane-pair sums in one LDS row per thread; workgroup and field sums are
+// formed in a fixed order, so the gradients are bitwise reproducible.
 #include "btl_device.h"
 
 namespace btl {
@@ -33,9 +34,13 @@ namespace btl {
 template <typename V, int TX>
 __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
     constexpr int TY = kBlock / TX;
-    constexpr int RS = kNGMax + 1;               // LDS row stride (odd: fewer bank conflicts)
+    constexpr int NT = kAdjMaxPhase * kAdjMaxPhase;   // membrane pair sums per thread (LDS row)
+    constexpr int RS = NT + 1;                         // odd row stride
     __shared__ double c_w[kAdjMaxPhase], c_dec[kAdjMaxPhase], c_tr[kAdjMaxPhase * kAdjMaxPhase];
     __shared__ double acc[kBlock * RS];
+    __shared__ double red[kNGMax];
+    __shared__ double2 ffac[6], afac[6];   // forward / adjoint face factors of this field
+    __shared__ double beta[6];
     __shared__ int last_flag;
     const int P = a.n_phase;
     const int NG = a.ng;
@@ -66,26 +71,31 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
     const int32_t j0 = tx * TX + (int32_t)(threadIdx.x % TX);
     const int32_t j1 = ty * TY + (int32_t)(threadIdx.x / TX);
     const int32_t st1 = n0, st2 = n0 * n1;
-    const int64_t pop = fd.pop;
-    const V* __restrict__ fwd = static_cast<const V*>(a.fwd);
-    const V* __restrict__ lam = static_cast<const V*>(a.lam_in);
-    V* __restrict__ out = static_cast<V*>(a.lam_out);
+    // one base pointer per buffer for this field; every access is a 32-bit
+    // element offset from it (image-field partners of the same q-sample
+    // lie within +-2^31 elements, checked on the host)
+    const V* __restrict__ fwd = static_cast<const V*>(a.fwd) + fd.pop;
+    const V* __restrict__ lam = a.top ? nullptr : static_cast<const V*>(a.lam_in) + fd.pop;
+    V* __restrict__ out = static_cast<V*>(a.lam_out) + fd.pop;
+    const int32_t pop = 0;
     const uint32_t* __restrict__ words = a.words + fd.words;
     const double2* __restrict__ tabp = a.tab_prev + fd.tab;
-    double2 ffac[6], afac[6];
-    double beta[6];
+    if (threadIdx.x < 6) {
+        const int f = threadIdx.x;
+        ffac[f] = tabp[n0 + n1 + n2 + f];
+        afac[f] = a.top ? make_double2(1.0, 0.0) : a.tab_cur[fd.adj_fac[f]];
+        beta[f] = fd.beta[f];
+    }
     int32_t kind[6], akind[6];
-    int64_t fpop[6], apop[6];
+    int32_t fpop[6], apop[6];
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
-        ffac[f] = uniform2(tabp[n0 + n1 + n2 + f]);
-        afac[f] = a.top ? make_double2(1.0, 0.0) : uniform2(a.tab_cur[fd.adj_fac[f]]);
-        beta[f] = fd.beta[f];
         kind[f] = fd.face_kind[f];
         akind[f] = fd.adj_kind[f];
-        fpop[f] = fd.face_pop[f];
-        apop[f] = fd.adj_pop[f];
+        fpop[f] = (int32_t)(fd.face_pop[f] - fd.pop);
+        apop[f] = (int32_t)(fd.adj_pop[f] - fd.pop);
     }
+    __syncthreads();
     const double cx0 = fd.c[0], cx1 = fd.c[1], cx2 = fd.c[2], cu = fd.cu;
     const double dt = a.dt;
     double2 mu = make_double2(0.0, 0.0);
@@ -93,72 +103,53 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
         const double2 m = a.dLdE[(int64_t)fd.q * (a.K + 1) + a.k];
         mu = make_double2(m.x / ns, m.y / ns);
     }
+    // register sums of the per-phase sensitivities (selected by phase)
+    double sw[kAdjMaxPhase] = {0.0, 0.0, 0.0, 0.0};
+    double sdec[kAdjMaxPhase] = {0.0, 0.0, 0.0, 0.0};
+    double sf = 0.0, sF = 0.0;
 
     if (j0 < n0 && j1 < n1) {
         const double2 exy = cmul(tabp[j0], tabp[n0 + j1]);
         const bool fx0 = j0 == 0, fx1 = j0 == n0 - 1, fy0 = j1 == 0, fy1 = j1 == n1 - 1;
+        // forward pull offsets (relative to the site index), as in k_step
+        auto face_off = [&](int f, int d, int32_t wrap) -> int32_t {
+            const int db = (d & 1) ? d + 1 : d - 1;
+            return (kind[f] & kFaceMirror) ? fpop[f] + db * ns : fpop[f] + d * ns + wrap;
+        };
+        // adjoint pull offsets: destination y + e_d
+        auto adj_off = [&](int f, int d, int32_t wrap) -> int32_t {
+            const int db = (d & 1) ? d + 1 : d - 1;
+            return (akind[f] & kFaceMirror) ? apop[f] + db * ns : apop[f] + d * ns + wrap;
+        };
+        const int32_t o1 = fx0 ? face_off(0, 1, n0 - 1) : pop + 1 * ns - 1;
+        const int32_t o2 = fx1 ? face_off(1, 2, -(n0 - 1)) : pop + 2 * ns + 1;
+        const int32_t o3 = fy0 ? face_off(2, 3, (n1 - 1) * st1) : pop + 3 * ns - st1;
+        const int32_t o4 = fy1 ? face_off(3, 4, -(n1 - 1) * st1) : pop + 4 * ns + st1;
+        const int32_t q1 = fx1 ? adj_off(1, 1, -(n0 - 1)) : pop + 1 * ns + 1;
+        const int32_t q2 = fx0 ? adj_off(0, 2, n0 - 1) : pop + 2 * ns - 1;
+        const int32_t q3 = fy1 ? adj_off(3, 3, -(n1 - 1) * st1) : pop + 3 * ns + st1;
+        const int32_t q4 = fy0 ? adj_off(2, 4, (n1 - 1) * st1) : pop + 4 * ns - st1;
+        // z offsets do not depend on the thread: wave-uniform
+        const int32_t o5i = pop + 5 * ns - st2;
+        const int32_t o6i = pop + 6 * ns + st2;
+        const int32_t q5i = pop + 5 * ns + st2;
+        const int32_t q6i = pop + 6 * ns - st2;
+        const int32_t o5f = face_off(4, 5, (n2 - 1) * st2);
+        const int32_t o6f = face_off(5, 6, -(n2 - 1) * st2);
+        const int32_t q5f = adj_off(5, 5, -(n2 - 1) * st2);
+        const int32_t q6f = adj_off(4, 6, (n2 - 1) * st2);
+
+#pragma nounroll
         for (int32_t j2 = z0; j2 < z1; ++j2) {
             const int32_t s = j0 + st1 * j1 + st2 * j2;
-            const int32_t jj[3] = {j0, j1, j2};
-            const int32_t nn[3] = {n0, n1, n2};
-            const int32_t stv[3] = {1, st1, st2};
             const bool fz0 = j2 == 0, fz1 = j2 == n2 - 1;
-            const bool lo[3] = {fx0, fy0, fz0}, hi[3] = {fx1, fy1, fz1};
+            // Two load phases per node keep the live register set small:
+            // first the adjoint (consumed into lhat), then the forward state.
             const uint32_t word = words[s];
             const int p = (int)(word & 0xfu);
             const uint32_t mask = (word >> 4) & 0x3fu;
             auto nbphase = [&](int d) { return (int)((word >> (10 + 3 * (d - 1))) & 0x7u); };
-
-            // ---- forward step k-1 recomputed at this node ----
-            double2 gp[kQ], v[kQ], own[kQ];
-            double tl[kQ];
-            gp[0] = ld2(fwd + pop + s);
-#pragma unroll
-            for (int d = 1; d < kQ; ++d) {
-                const int ax = (d - 1) >> 1;
-                const bool plus = (d & 1) != 0;
-                const bool face = plus ? lo[ax] : hi[ax];
-                const int od = plus ? d + 1 : d - 1;
-                double2 x;
-                if (!face) {
-                    x = ld2(fwd + pop + (int64_t)d * ns + (plus ? s - stv[ax] : s + stv[ax]));
-                } else {
-                    const int f = 2 * ax + (plus ? 0 : 1);
-                    if (kind[f] & kFaceMirror) {
-                        x = ld2(fwd + fpop[f] + (int64_t)od * ns + s);
-                    } else {
-                        const int32_t w = (nn[ax] - 1) * stv[ax];
-                        x = ld2(fwd + fpop[f] + (int64_t)d * ns + (plus ? s + w : s - w));
-                    }
-                    if (kind[f] & kFaceConj) x.y = -x.y;
-                    x = cmul(x, ffac[f]);
-                }
-                v[d] = x;
-                tl[d] = 1.0;
-                own[d] = ld2(fwd + pop + (int64_t)od * ns + s);
-                if ((mask >> (d - 1)) & 1u) {
-                    const double t = c_tr[p * P + nbphase(d)];
-                    if (t < 1.0) {
-                        tl[d] = t;
-                        x.x = own[d].x + t * (x.x - own[d].x);
-                        x.y = own[d].y + t * (x.y - own[d].y);
-                    }
-                }
-                gp[d] = x;
-            }
-            const double2 ezj = tabp[n0 + n1 + j2];
-            const double dec = c_dec[p];
-            const double2 e = cmul(exy, ezj);
-            const double2 c = make_double2(e.x * dec, e.y * dec);
-            double2 g[kQ];
-            double2 M = make_double2(0.0, 0.0);
-#pragma unroll
-            for (int d = 0; d < kQ; ++d) {
-                g[d] = cmul(gp[d], c);
-                M.x += g[d].x;
-                M.y += g[d].y;
-            }
-            const double w = c_w[p];
+            const bool flo[3] = {fx0, fy0, fz0}, fhi[3] = {fx1, fy1, fz1};
 
             // ---- adjoint pull of Lambda^k ----
             double2 lh[kQ];
@@ -166,45 +157,46 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
 #pragma unroll
                 for (int d = 0; d < kQ; ++d) lh[d] = make_double2(0.0, 0.0);
             } else {
-                lh[0] = ld2(lam + pop + s);
+                V rl[kQ], rlown[kQ];
+                rl[0] = lam[pop + s];
+                rl[1] = lam[q1 + s];
+                rl[2] = lam[q2 + s];
+                rl[3] = lam[q3 + s];
+                rl[4] = lam[q4 + s];
+                rl[5] = lam[(fz1 ? q5f : q5i) + s];
+                rl[6] = lam[(fz0 ? q6f : q6i) + s];
+#pragma unroll
+                for (int d = 1; d < kQ; ++d) {
+                    const int od = (d & 1) ? d + 1 : d - 1;
+                    rlown[d] = lam[pop + od * ns + s];
+                }
+                lh[0] = ld2(&rl[0]);
 #pragma unroll
                 for (int d = 1; d < kQ; ++d) {
                     const int ax = (d - 1) >> 1;
                     const bool plus = (d & 1) != 0;      // destination y + e_d
-                    const bool face = plus ? hi[ax] : lo[ax];
                     const int od = plus ? d + 1 : d - 1;
-                    double2 x;
-                    if (!face) {
-                        x = ld2(lam + pop + (int64_t)d * ns + (plus ? s + stv[ax] : s - stv[ax]));
-                    } else {
+                    double2 x = ld2(&rl[d]);
+                    if (plus ? fhi[ax] : flo[ax]) {
                         const int f = 2 * ax + (plus ? 1 : 0);
-                        if (akind[f] & kFaceMirror) {
-                            x = ld2(lam + apop[f] + (int64_t)od * ns + s);
-                        } else {
-                            const int32_t w = (nn[ax] - 1) * stv[ax];
-                            x = ld2(lam + apop[f] + (int64_t)d * ns + (plus ? s - w : s + w));
-                        }
-                        if (akind[f] & kFaceConj) {
+                        if (akind[f] & kFaceConj)
                             x = cmul(make_double2(x.x, -x.y), afac[f]);
-                        } else {
+                        else
                             x = cmul(make_double2(afac[f].x, -afac[f].y), x);
-                        }
                     }
-                    // link between this node and y + e_d: membrane bit of the
+                    // membrane between this node and y + e_d: bit of the
                     // opposite pull direction at this node
                     if ((mask >> (od - 1)) & 1u) {
                         const double t = c_tr[p * P + nbphase(od)];
                         if (t < 1.0) {
-                            const double2 lo_ = ld2(lam + pop + (int64_t)od * ns + s);
-                            x.x = lo_.x + t * (x.x - lo_.x);
-                            x.y = lo_.y + t * (x.y - lo_.y);
+                            const double2 lo = ld2(&rlown[d]);
+                            x.x = lo.x + t * (x.x - lo.x);
+                            x.y = lo.y + t * (x.y - lo.y);
                         }
                     }
                     lh[d] = x;
                 }
             }
-
-            // ---- transposed collision and reaction ----
             double2 sl = make_double2(0.0, 0.0);
 #pragma unroll
             for (int d = 0; d < kQ; ++d) {
@@ -212,55 +204,117 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
                 sl.x += wd * lh[d].x;
                 sl.y += wd * lh[d].y;
             }
-            double gw = 0.0, gdec = 0.0, gim = 0.0;
-            double2 lo2[kQ];
+            __builtin_amdgcn_sched_barrier(0);
+
+            // ---- forward state of step k-1 around this node ----
+            V rg[kQ], rown[kQ];
+            rg[0] = fwd[pop + s];
+            rg[1] = fwd[o1 + s];
+            rg[2] = fwd[o2 + s];
+            rg[3] = fwd[o3 + s];
+            rg[4] = fwd[o4 + s];
+            rg[5] = fwd[(fz0 ? o5f : o5i) + s];
+            rg[6] = fwd[(fz1 ? o6f : o6i) + s];
+#pragma unroll
+            for (int d = 1; d < kQ; ++d) {
+                const int od = (d & 1) ? d + 1 : d - 1;
+                rown[d] = fwd[pop + od * ns + s];
+            }
+            const double2 ezj = tabp[n0 + n1 + j2];
+            const double dec = c_dec[p];
+            const double w = c_w[p];
+            const double2 e = cmul(exy, ezj);
+            const double2 c = make_double2(e.x * dec, e.y * dec);
+            const double2 cc = make_double2(c.x, -c.y);
+
+            // ---- per direction: forward step k-1 recomputed, transposed
+            // collision and reaction, sensitivities ----
+            double2 M = make_double2(0.0, 0.0);
+            double glg = 0.0, gdec = 0.0, gim = 0.0;
 #pragma unroll
             for (int d = 0; d < kQ; ++d) {
-                const double wd = d == 0 ? 0.25 : 0.125;
-                // collision: d ghat_d / dw = w_d M - g_d
-                gw += lh[d].x * (wd * M.x - g[d].x) + lh[d].y * (wd * M.y - g[d].y);
+                const int ax = d > 0 ? (d - 1) >> 1 : 0;
+                const bool plus = (d & 1) != 0;
+                const bool face = d > 0 && (plus ? flo[ax] : fhi[ax]);
+                const int f = 2 * ax + (plus ? 0 : 1);
+                double2 vv = ld2(&rg[d]);
+                if (face) {
+                    if (kind[f] & kFaceConj) vv.y = -vv.y;
+                    vv = cmul(vv, ffac[f]);
+                }
+                double2 gpd = vv;
+                double tl = 1.0;
+                double2 dv = make_double2(0.0, 0.0);
+                if (d > 0 && ((mask >> (d - 1)) & 1u)) {
+                    const double t = c_tr[p * P + nbphase(d)];
+                    if (t < 1.0) {
+                        const double2 ow = ld2(&rown[d]);
+                        tl = t;
+                        dv = make_double2(vv.x - ow.x, vv.y - ow.y);
+                        gpd.x = ow.x + t * dv.x;
+                        gpd.y = ow.y + t * dv.y;
+                    }
+                }
+                const double2 g = cmul(gpd, c);
+                M.x += g.x;
+                M.y += g.y;
+                glg += lh[d].x * g.x + lh[d].y * g.y;
                 double2 nu;
                 nu.x = (1.0 - w) * lh[d].x + w * sl.x + mu.x;
                 nu.y = (1.0 - w) * lh[d].y + w * sl.y + mu.y;
-                // Re and Im of conj(nu) g
-                gdec += nu.x * g[d].x + nu.y * g[d].y;
-                gim += nu.x * g[d].y - nu.y * g[d].x;
-                lo2[d] = cmul(make_double2(c.x, -c.y), nu);
-                store2(out + pop + (int64_t)d * ns + s, lo2[d]);
+                gdec += nu.x * g.x + nu.y * g.y;
+                gim += nu.x * g.y - nu.y * g.x;
+                const double2 lo2 = cmul(cc, nu);
+                store2(out + pop + d * ns + s, lo2);
+                if (tl < 1.0) my[p * P + nbphase(d)] += lo2.x * dv.x + lo2.y * dv.y;
+                if (face) sF += -beta[f] * tl * (lo2.x * vv.y - lo2.y * vv.x);
             }
-            my[IW + p] += gw;
-            my[IDEC + p] += gdec / dec;
-            const double thp = cx0 * j0 + cx1 * j1 + cx2 * j2 + cu;
-            my[IF] += dt * thp * gim;
-            // stream sensitivities of step k-1: membranes and face factors
+            // collision: sum_d Re conj(lhat_d) (w_d M - g_d)
+            const double gw = sl.x * M.x + sl.y * M.y - glg;
 #pragma unroll
-            for (int d = 1; d < kQ; ++d) {
-                const int ax = (d - 1) >> 1;
-                const bool plus = (d & 1) != 0;
-                const bool face = plus ? lo[ax] : hi[ax];
-                if (tl[d] < 1.0) {
-                    const double2 df = make_double2(v[d].x - own[d].x, v[d].y - own[d].y);
-                    my[IT + p * P + nbphase(d)] += lo2[d].x * df.x + lo2[d].y * df.y;
-                }
-                if (face) {
-                    const int f = 2 * ax + (plus ? 0 : 1);
-                    if (beta[f] != 0.0) {
-                        const double im = lo2[d].x * v[d].y - lo2[d].y * v[d].x;
-                        my[IFF] += -beta[f] * tl[d] * im;
-                    }
-                }
+            for (int i = 0; i < kAdjMaxPhase; ++i) {
+                sw[i] += (p == i) ? gw : 0.0;
+                sdec[i] += (p == i) ? gdec / dec : 0.0;
             }
+            sf += dt * (cx0 * j0 + cx1 * j1 + cx2 * j2 + cu) * gim;
         }
     }
 
-    // ---- workgroup sums, then the last workgroup of the field ----
+    // ---- workgroup sums (fixed order), then the last workgroup of the field ----
+    if (threadIdx.x < NG) red[threadIdx.x] = 0.0;
     __syncthreads();
-    if (threadIdx.x < NG) {
+    // register sums: wave reduction, then the four waves in order
+    {
+        double v[2 * kAdjMaxPhase + 2];
+#pragma unroll
+        for (int i = 0; i < kAdjMaxPhase; ++i) {
+            v[i] = wave_sum(sw[i]);
+            v[kAdjMaxPhase + i] = wave_sum(sdec[i]);
+        }
+        v[2 * kAdjMaxPhase] = wave_sum(sf);
+        v[2 * kAdjMaxPhase + 1] = wave_sum(sF);
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        for (int wave = 0; wave < kBlock / 64; ++wave) {
+            if (wv == wave && lane == 0) {
+                for (int i = 0; i < P; ++i) {
+                    red[IW + i] += v[i];
+                    red[IDEC + i] += v[kAdjMaxPhase + i];
+                }
+                red[IF] += v[2 * kAdjMaxPhase];
+                red[IFF] += v[2 * kAdjMaxPhase + 1];
+            }
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x < P * P) {
         double sacc = 0.0;
         for (int t = 0; t < kBlock; ++t) sacc += acc[t * RS + threadIdx.x];
-        __hip_atomic_store(a.gpart + (int64_t)blockIdx.x * NG + threadIdx.x, sacc,
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        red[IT + threadIdx.x] = sacc;
     }
+    __syncthreads();
+    if (threadIdx.x < NG)
+        __hip_atomic_store(a.gpart + (int64_t)blockIdx.x * NG + threadIdx.x, red[threadIdx.x],
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();

@@ -99,10 +99,13 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     for (int f = 0; f < 6; ++f) face_fac[f] = uniform2(tab[n0 + n1 + n2 + f]);
     const int P = a.n_phase;
 
-    const V* __restrict__ src = static_cast<const V*>(a.src);
-    V* __restrict__ dst = static_cast<V*>(a.dst);
+    // one base pointer per buffer for this field; every access is a 32-bit
+    // element offset from it (image-field partners of the same q-sample lie
+    // within +-2^31 elements, checked on the host)
+    const V* __restrict__ src = static_cast<const V*>(a.src) + fd.pop;
+    V* __restrict__ dst = static_cast<V*>(a.dst) + fd.pop;
     const uint32_t* __restrict__ words = a.words + fd.words;
-    const int64_t pop = fd.pop;
+    const int32_t pop = 0;
     const int32_t j0 = tx * TX + (int32_t)(threadIdx.x % TX);
     const int32_t j1 = ty * TY + (int32_t)(threadIdx.x / TX);
     const int32_t z1 = min(n2, z0 + fd.zc);
@@ -115,24 +118,23 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     // wrapped site.  Mirror face: source field of that face, same site,
     // reflected direction.
     int32_t kind[6];
-    int64_t fpop[6];
+    int32_t fpop[6];
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
         kind[f] = fd.face_kind[f];
-        fpop[f] = fd.face_pop[f];
+        fpop[f] = (int32_t)(fd.face_pop[f] - fd.pop);
     }
-    auto face_off = [&](int f, int d, int32_t wrap) -> int64_t {
+    auto face_off = [&](int f, int d, int32_t wrap) -> int32_t {
         const int db = (d & 1) ? d + 1 : d - 1;
-        return (kind[f] & kFaceMirror) ? fpop[f] + (int64_t)db * ns
-                                       : fpop[f] + (int64_t)d * ns + wrap;
+        return (kind[f] & kFaceMirror) ? fpop[f] + db * ns : fpop[f] + d * ns + wrap;
     };
     const bool fx0 = j0 == 0, fx1 = j0 == n0 - 1, fy0 = j1 == 0, fy1 = j1 == n1 - 1;
-    const int64_t o1 = fx0 ? face_off(0, 1, n0 - 1) : pop + 1 * (int64_t)ns - 1;
-    const int64_t o2 = fx1 ? face_off(1, 2, -(n0 - 1)) : pop + 2 * (int64_t)ns + 1;
-    const int64_t o3 = fy0 ? face_off(2, 3, (n1 - 1) * st1) : pop + 3 * (int64_t)ns - st1;
-    const int64_t o4 = fy1 ? face_off(3, 4, -(n1 - 1) * st1) : pop + 4 * (int64_t)ns + st1;
-    const int64_t o5i = pop + 5 * (int64_t)ns - st2, o5f = face_off(4, 5, (n2 - 1) * st2);
-    const int64_t o6i = pop + 6 * (int64_t)ns + st2, o6f = face_off(5, 6, -(n2 - 1) * st2);
+    const int32_t o1 = fx0 ? face_off(0, 1, n0 - 1) : pop + 1 * ns - 1;
+    const int32_t o2 = fx1 ? face_off(1, 2, -(n0 - 1)) : pop + 2 * ns + 1;
+    const int32_t o3 = fy0 ? face_off(2, 3, (n1 - 1) * st1) : pop + 3 * ns - st1;
+    const int32_t o4 = fy1 ? face_off(3, 4, -(n1 - 1) * st1) : pop + 4 * ns + st1;
+    const int32_t o5i = pop + 5 * ns - st2, o5f = face_off(4, 5, (n2 - 1) * st2);
+    const int32_t o6i = pop + 6 * ns + st2, o6f = face_off(5, 6, -(n2 - 1) * st2);
 
     // Loads of one site: the site word, the seven pulled populations, the
     // six outgoing populations of the node itself (reflected at membrane
@@ -158,7 +160,7 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
 #pragma unroll
         for (int d = 1; d < kQ; ++d) {
             const int od = (d & 1) ? d + 1 : d - 1;
-            L.own[d - 1] = src[pop + (int64_t)od * ns + s];
+            L.own[d - 1] = src[pop + od * ns + s];
         }
         L.ez = ez[j2];
     };
@@ -210,14 +212,14 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
         Macc.y += M.y;
         // collision: ghat = g + w (w_d M - g)
         const double w = c_w[p];
-        V* out = dst + pop + s;
+        V* out = dst + s;
 #pragma unroll
         for (int d = 0; d < kQ; ++d) {
             const double wd = d == 0 ? 0.25 : 0.125;
             double2 h;
             h.x = g[d].x + w * (wd * M.x - g[d].x);
             h.y = g[d].y + w * (wd * M.y - g[d].y);
-            store2(out + (int64_t)d * ns, h);
+            store2(out + d * ns, h);
         }
     };
 

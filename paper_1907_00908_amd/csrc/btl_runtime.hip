@@ -466,6 +466,19 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
         }
     }
     const int32_t n_fields = (int32_t)fl.size();
+    // the kernels address a field's reads with 32-bit element offsets from
+    // its own base: every plane it reads must lie within +-2^31 elements
+    for (int i = 0; i < n_fields; ++i) {
+        int64_t lo = 0, hi = (int64_t)kQ * fl[i].nsites;
+        for (int f = 0; f < 6; ++f) {
+            lo = std::min(lo, fl[i].face_pop[f] - fl[i].pop);
+            hi = std::max(hi, fl[i].face_pop[f] - fl[i].pop + (int64_t)kQ * fl[i].nsites);
+            lo = std::min(lo, fl[i].adj_pop[f] - fl[i].pop);
+            hi = std::max(hi, fl[i].adj_pop[f] - fl[i].pop + (int64_t)kQ * fl[i].nsites);
+        }
+        if (lo < -(int64_t)INT32_MAX || hi > (int64_t)INT32_MAX)
+            return fail(s, BTL_E_UNSUPPORTED, "geometry too large for the image fields of one q-sample");
+    }
     // phase tables: per field [n0 + n1 + n2 + 6] entries
     int32_t T = 0;
     for (int i = 0; i < n_fields; ++i) {
