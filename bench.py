@@ -13,7 +13,9 @@ A benchmark step is one lattice time step of the whole q-batch: stream with
 boundaries and membranes, reaction, signal reduction and collision for
 every q-sample.  `value` counts q-sample site-updates (6 x 128^3 per step).
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload cfg2]
+(--workload selects one of the other synthetic workloads; the default is the
+one described above.)
 """
 from __future__ import annotations
 
@@ -43,9 +45,19 @@ def kernel_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def workload(K: int):
+WORKLOAD_NAMES = {
+    "cfg1": "uniform 32^3 periodic free diffusion, PGSE, G || x, b=1000 (plain case)",
+    "cfg2": "two-phase axon model 128^3, mirror BC, 6 oblique directions, b=1000",
+    "cfg3a": "cylinders+spheres 256^3 periodic, 64 directions x 4 b-values = 256 q",
+    "cfg3b": "16 cylinder geometries 96^3..192^3 (ragged batch), 6 directions each",
+    "cfg4": "two-phase cylinders 96^3 periodic, 30 directions",
+    "cfg5": "three-phase ellipsoid cells 512^3 periodic, cosine OGSE, 32 directions",
+}
+
+
+def workload(name: str, K: int):
     import workloads as w
-    cfg = w.make_config("cfg2")
+    cfg = w.make_config(name)
     f = cfg["f"]
     if K > len(f):
         f = np.resize(f, K)
@@ -53,21 +65,29 @@ def workload(K: int):
     return cfg
 
 
-def n_fields(cfg) -> int:
+def fields_of(G, bc) -> int:
     # fields per q-sample: 2^(k-1) for k mirrored axes with non-zero gradient
     # (all non-zero axes mirrored), else 2^k
-    tot = 0
-    for G in cfg["gG0"]:
-        nz = [a for a in range(3) if G[a] != 0.0]
-        mir = [a for a in nz if cfg["bc"][a] == 1]
-        k = len(mir)
-        if k == 0:
-            tot += 1
-        elif len(mir) == len(nz):
-            tot += 2 ** (k - 1)
-        else:
-            tot += 2 ** k
-    return tot
+    nz = [a for a in range(3) if G[a] != 0.0]
+    mir = [a for a in nz if bc[a] == 1]
+    k = len(mir)
+    if k == 0:
+        return 1
+    return 2 ** (k - 1) if len(mir) == len(nz) else 2 ** k
+
+
+def field_sites(cfg) -> int:
+    """Sum over all fields of the batch of their site counts."""
+    return sum(fields_of(G, cfg["bc"]) * cfg["geoms"][int(g)].comp.size
+               for G, g in zip(cfg["gG0"], cfg["q_geom"]))
+
+
+def q_sites(cfg) -> int:
+    return sum(cfg["geoms"][int(g)].comp.size for g in cfg["q_geom"])
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def time_forward(sim, cfg, K, prec_bytes, reps=1):
@@ -109,18 +129,20 @@ def cpu_baseline(cfg, budget_s: float = 15.0):
     oracle.simulate(*args, cfg["f"][:n], cfg["gG0"][0], threads=threads, want_M=False)
     t1 = time.perf_counter()
     sites = g.comp.size
+    note = ("; the oracle steps the reflected, doubled domain"
+            if oracle.needs_doubling(cfg["bc"], cfg["gG0"][0]) else "")
     return {"value": sites * n / (t1 - t0), "unit": "site-updates/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"q-sample 0 of the workload, {n} full-size steps ({sites} REV sites; "
-                      f"the oracle steps the 2x2x2 reflected domain), {t1 - t0:.1f} s"}
+            "sample": f"q-sample 0 of the workload, {n} full-size steps ({sites} REV sites"
+                      f"{note}), {t1 - t0:.1f} s"}
 
 
-def bench_adjoint(btl, torch, sim, cfg, args, fwd_ms_step, nf, sites, Q):
+def bench_adjoint(btl, torch, sim, cfg, args, fwd_ms_step, fs, qs, Q):
     """Reverse sweep of the same workload: forward with a checkpoint every
     adj_ckpt steps, then btl_backward for a linear loss in E.  The end-to-end
     rate counts q-sample site-updates of the reverse sweep (it recomputes
     each segment forward and runs one adjoint step per forward step)."""
-    Kb, C = args.adj_steps, args.adj_ckpt
+    Kb, C = min(args.adj_steps, len(cfg["f"])), args.adj_ckpt
     c = dict(cfg)
     c["f"] = cfg["f"][:Kb]
     stream = torch.cuda.current_stream()
@@ -144,13 +166,13 @@ def bench_adjoint(btl, torch, sim, cfg, args, fwd_ms_step, nf, sites, Q):
     recompute_ms = (Kb - nseg) * fwd_ms_step
     adj_ms = max(ms - recompute_ms, 1e-9) / Kb
     bpf = 168 if args.prec == "f32" else 336
-    ach = nf * sites * bpf / (adj_ms * 1e-3) / 1e9
+    ach = fs * bpf / (adj_ms * 1e-3) / 1e9
     finite = bool(torch.isfinite(dD).all() and torch.isfinite(df).all())
-    return {"value": Q * sites * Kb / (ms * 1e-3), "unit": "site-updates/s",
+    return {"value": qs * Kb / (ms * 1e-3), "unit": "site-updates/s",
             "what": "end-to-end reverse sweep (segment recompute + adjoint step)",
             "steps": Kb, "ckpt_every": C, "ms_total": ms,
             "adjoint_kernel": {"ms_per_step_est": adj_ms,
-                               "bytes_per_launch_algorithmic": nf * sites * bpf,
+                               "bytes_per_launch_algorithmic": fs * bpf,
                                "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS,
                                "estimate": "backward time minus the recompute steps at the "
                                            "measured forward step time"},
@@ -171,6 +193,7 @@ def traffic_for(kernel_avg_ms):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOAD_NAMES))
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
@@ -209,36 +232,45 @@ def main():
         return
 
     K, W = args.steps, args.warmup
-    cfg = workload(max(K, W))
+    log(f"building workload {args.workload}")
+    cfg = workload(args.workload, max(K, W))
     Q = len(cfg["gG0"])
+    qs = q_sites(cfg)
+    fs = field_sites(cfg)
     sites = cfg["geoms"][0].comp.size
-    nf = n_fields(cfg)
     sim = btl.Simulator(cfg["geoms"], cfg["bc"], args.prec)
     bpf = BYTES_PER_FIELD_SITE_F32 if args.prec == "f32" else BYTES_PER_FIELD_SITE_F64
+    log("first forward")
     time_forward(sim, cfg, max(W, 1), bpf)
     if not args.no_autotune:
         # launch shape chosen by timed probes of this workload (setup, untimed)
-        btl.btl_autotune(sim._h, Q, 20, torch.cuda.current_stream().cuda_stream)
+        probe = 20 if fs < 5e7 else 2
+        log(f"autotune ({probe} steps per candidate)")
+        btl.btl_autotune(sim._h, Q, probe, torch.cuda.current_stream().cuda_stream)
     if W > 0:
+        log("warmup")
         time_forward(sim, cfg, W, bpf)
+    log("timed forward")
     ms, E = time_forward(sim, cfg, K, bpf)
     ms_step = ms / K
-    value = Q * sites * K / (ms * 1e-3)
-    bytes_launch = nf * sites * bpf
+    value = qs * K / (ms * 1e-3)
+    bytes_launch = fs * bpf
     achieved = bytes_launch / (ms_step * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(ms_step),
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic_for(ms_step) if args.workload == "cfg2" and args.prec == "f32" else None,
             "kernel": f"k_step<{'float2' if args.prec == 'f32' else 'double2'}>",
             "bytes_per_launch_algorithmic": bytes_launch}
     out = {"metric": METRIC, "value": value, "unit": "site-updates/s", "n_gpus": 1,
            "steps": K, "warmup": W, "ms_per_step": ms_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "two-phase axon model 128^3, mirror BC, 6 oblique "
-                                  "directions, b=1000 (cfg2)",
-                      "sites": sites, "q_samples": Q, "fields": nf,
+           "config": {"workload": f"{WORKLOAD_NAMES[args.workload]} ({args.workload})",
+                      "q_sites": qs, "q_samples": Q, "field_sites": fs,
+                      "geometries": len(cfg["geoms"]),
                       "storage": args.prec, "steps_per_forward": K},
            "roofline": roof}
     if not args.no_extras:
+        log("FP64 comparison runs")
         # stated error vs FP64 storage over the same steps, and the plain FP64
         # one-sample-per-launch form as the speedup denominator
         sim64 = btl.Simulator(cfg["geoms"], cfg["bc"], "f64")
@@ -252,15 +284,21 @@ def main():
         one["gG0"] = cfg["gG0"][:1]
         one["q_geom"] = cfg["q_geom"][:1]
         ms1, _ = time_forward(sim64, one, K, BYTES_PER_FIELD_SITE_F64)
-        v1 = sites * K / (ms1 * 1e-3)
+        v1 = cfg["geoms"][int(cfg["q_geom"][0])].comp.size * K / (ms1 * 1e-3)
         out["fp64_one_q_per_launch"] = {"value": v1, "unit": "site-updates/s",
                                         "speedup_of_value": value / v1}
-        out["fp64_batched"] = {"value": Q * sites * K / (ms64 * 1e-3)}
+        out["fp64_batched"] = {"value": qs * K / (ms64 * 1e-3)}
         sim64.close()
-    if not args.no_adjoint:
-        out["adjoint"] = bench_adjoint(btl, torch, sim, cfg, args, ms_step, nf, sites, Q)
+    state_gb = fs * (8 if args.prec == "f32" else 16) * 7 / 1e9
+    adj_states = min(args.adj_steps, K) / args.adj_ckpt + args.adj_ckpt + 4
+    if not args.no_adjoint and state_gb * adj_states > 120.0:
+        out["adjoint"] = {"skipped": f"tape would need {state_gb * adj_states:.0f} GB"}
+    elif not args.no_adjoint:
+        log("reverse sweep")
+        out["adjoint"] = bench_adjoint(btl, torch, sim, cfg, args, ms_step, fs, qs, Q)
     sim.close()
     if not args.no_cpu_baseline:
+        log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)
 

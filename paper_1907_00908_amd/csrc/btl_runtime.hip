@@ -52,6 +52,15 @@ struct DevBuf {
 
 std::string g_create_error;
 
+constexpr int kGraphMinSteps = 16;   // forwards this long run from a cached hipGraph
+
+// Everything a captured forward depends on besides the contents of its
+// buffers; a forward replays the cached graph only when this matches.
+struct GraphKey {
+    int32_t prec, K, Q, n_fields, nblk, shape, T, ckpt;
+    const void* ptr[16];
+};
+
 }  // namespace
 
 struct btl_sim {
@@ -78,6 +87,11 @@ struct btl_sim {
     hipEvent_t stage_ev[2] = {nullptr, nullptr};
     bool stage_used[2] = {false, false};
     int stage_slot = 0;
+    // cached forward graph
+    hipGraphExec_t graph_exec = nullptr;
+    GraphKey graph_key;
+    hipStream_t cap_stream = nullptr;
+    DevBuf<double> E_int;
     int tile_shape = -1;        // -1: pick per call from the geometry sizes
     int zc = 0;                 // sites per thread along z; 0: whole column
     // inputs of the last forward call (the autotuner replays them)
@@ -279,10 +293,10 @@ static QFields plan_fields(const GeomHost& g, const double* G) {
     return r;
 }
 
-extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double* D,
-                                  const double* T2, const double* kappa, int32_t Q,
-                                  const int32_t* q_geom, const double* gG0, const double* f,
-                                  double* E, void* M_final, int32_t ckpt_every, void* stream) {
+static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D,
+                               const double* T2, const double* kappa, int32_t Q,
+                               const int32_t* q_geom, const double* gG0, const double* f,
+                               double* E, void* M_final, int32_t ckpt_every, void* stream) {
     if (!s) return BTL_E_INVAL;
     if (!(dt > 0) || !isfinite(dt)) return fail(s, BTL_E_INVAL, "dt must be finite and > 0");
     if (K < 0) return fail(s, BTL_E_INVAL, "K must be >= 0");
@@ -311,14 +325,6 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const double dx = s->dx;
-    s->last.valid = true;
-    s->last.dt = dt;
-    s->last.D.assign(D, D + P);
-    s->last.T2.assign(T2, T2 + P);
-    s->last.kappa.assign(kappa, kappa + P * P);
-    s->last.gG0.assign(gG0, gG0 + 3 * Q);
-    s->last.f.assign(f, f + K);
-    s->last.q_geom.assign(q_geom, q_geom + Q);
 
     // per-phase and per-pair constants (FP64)
     std::vector<double> consts(2 * P + P * P + P + P * P);
@@ -580,55 +586,183 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
         s->tape.dt = dt;
         s->tape.state_elems = pop_elems;
     }
-    if ((e = launch_init(s->prec, s->pop[0].p, pop_elems, s->fields.p, n_fields, fl.data(), E,
-                         Q, K, st)) != hipSuccess)
-        return hip_fail(s, e, "init launch");
-    if (ckpt_every > 0 && K > 0 &&
-        (e = hipMemcpyAsync(s->ckpt.p, s->pop[0].p, state_bytes, hipMemcpyDeviceToDevice, st)) !=
-            hipSuccess)
-        return hip_fail(s, e, "checkpoint copy");
-    StepArgs a;
-    memset(&a, 0, sizeof(a));
-    a.words = s->words.p;
-    a.fields = s->fields.p;
-    a.blk_field = s->blk_field.p;
-    a.fdt = s->steps.p;
-    a.Fk = s->steps.p + K;
-    a.w = s->consts.p;
-    a.decay = s->consts.p + P;
-    a.trans = s->consts.p + 2 * P;
-    a.partial = s->partial.p;
-    a.counter = s->counter.p;
-    a.E = E;
-    a.n_phase = P;
-    a.K = K;
-    a.tab_field = s->tab_field.p;
-    a.T = T;
-    for (int k = 0; k < K; ++k) {
-        if (k % kTabSteps == 0) {
+    // Everything a forward enqueues after the uploads: init, one table
+    // launch per kTabSteps steps, one step launch per step, checkpoint
+    // copies.  Replayed from a cached hipGraph when the call has the same
+    // shape and buffers as the previous one.
+    auto enqueue = [&](hipStream_t q, double* Eptr) -> btl_status {
+        hipError_t err;
+        if ((err = launch_init(s->prec, s->pop[0].p, pop_elems, s->fields.p, n_fields, fl.data(),
+                               Eptr, Q, K, q)) != hipSuccess)
+            return hip_fail(s, err, "init launch");
+        if (ckpt_every > 0 && K > 0 &&
+            (err = hipMemcpyAsync(s->ckpt.p, s->pop[0].p, state_bytes, hipMemcpyDeviceToDevice, q)) !=
+                hipSuccess)
+            return hip_fail(s, err, "checkpoint copy");
+        StepArgs a;
+        memset(&a, 0, sizeof(a));
+        a.words = s->words.p;
+        a.fields = s->fields.p;
+        a.blk_field = s->blk_field.p;
+        a.fdt = s->steps.p;
+        a.Fk = s->steps.p + K;
+        a.w = s->consts.p;
+        a.decay = s->consts.p + P;
+        a.trans = s->consts.p + 2 * P;
+        a.partial = s->partial.p;
+        a.counter = s->counter.p;
+        a.E = Eptr;
+        a.n_phase = P;
+        a.K = K;
+        a.tab_field = s->tab_field.p;
+        a.T = T;
+        for (int k = 0; k < K; ++k) {
+            if (k % kTabSteps == 0) {
+                a.k = k;
+                a.tab = s->tab.p;
+                if ((err = launch_tables(a, std::min(kTabSteps, K - k), q)) != hipSuccess)
+                    return hip_fail(s, err, "table launch");
+            }
+            a.tab = s->tab.p + (size_t)(k % kTabSteps) * T;
+            a.src = s->pop[k & 1].p;
+            a.dst = s->pop[(k + 1) & 1].p;
             a.k = k;
-            a.tab = s->tab.p;
-            if ((e = launch_tables(a, std::min(kTabSteps, K - k), st)) != hipSuccess)
-                return hip_fail(s, e, "table launch");
+            if ((err = launch_step(s->prec, shape, a, nblk_total, q)) != hipSuccess)
+                return hip_fail(s, err, "step launch");
+            if (ckpt_every > 0 && (k + 1) % s->tape.C == 0 && k + 1 < K) {
+                const size_t m = (size_t)(k + 1) / s->tape.C;
+                if ((err = hipMemcpyAsync(s->ckpt.p + m * state_bytes, s->pop[(k + 1) & 1].p,
+                                          state_bytes, hipMemcpyDeviceToDevice, q)) != hipSuccess)
+                    return hip_fail(s, err, "checkpoint copy");
+            }
         }
-        a.tab = s->tab.p + (size_t)(k % kTabSteps) * T;
-        a.src = s->pop[k & 1].p;
-        a.dst = s->pop[(k + 1) & 1].p;
-        a.k = k;
-        if ((e = launch_step(s->prec, shape, a, nblk_total, st)) != hipSuccess)
-            return hip_fail(s, e, "step launch");
-        if (ckpt_every > 0 && (k + 1) % s->tape.C == 0 && k + 1 < K) {
-            const size_t m = (size_t)(k + 1) / s->tape.C;
-            if ((e = hipMemcpyAsync(s->ckpt.p + m * state_bytes, s->pop[(k + 1) & 1].p, state_bytes,
-                                    hipMemcpyDeviceToDevice, st)) != hipSuccess)
-                return hip_fail(s, e, "checkpoint copy");
+        return BTL_OK;
+    };
+    const bool use_graph = K >= kGraphMinSteps && getenv("BTLBM_NO_GRAPH") == nullptr;
+    if (!use_graph) {
+        const btl_status rc = enqueue(st, E);
+        if (rc != BTL_OK) return rc;
+    } else {
+        const size_t ebytes = (size_t)Q * (K + 1) * 2 * sizeof(double);
+        if ((e = s->E_int.ensure((size_t)Q * (K + 1) * 2)) != hipSuccess)
+            return hip_fail(s, e, "allocating signal buffer");
+        GraphKey key;
+        memset(&key, 0, sizeof(key));
+        key.prec = s->prec;
+        key.K = K;
+        key.Q = Q;
+        key.n_fields = n_fields;
+        key.nblk = nblk_total;
+        key.shape = shape;
+        key.T = T;
+        key.ckpt = ckpt_every;
+        const void* ptrs[] = {s->pop[0].p, s->pop[1].p, s->fields.p, s->blk_field.p, s->steps.p,
+                              s->consts.p, s->partial.p, s->counter.p, s->tab.p, s->tab_field.p,
+                              s->E_int.p, s->ckpt.p, s->words.p};
+        static_assert(sizeof(ptrs) / sizeof(ptrs[0]) <= sizeof(key.ptr) / sizeof(key.ptr[0]),
+                      "graph key too small");
+        for (size_t i = 0; i < sizeof(ptrs) / sizeof(ptrs[0]); ++i) key.ptr[i] = ptrs[i];
+        if (!(s->graph_exec && memcmp(&key, &s->graph_key, sizeof(key)) == 0)) {
+            if (s->graph_exec) {
+                (void)hipGraphExecDestroy(s->graph_exec);
+                s->graph_exec = nullptr;
+            }
+            if (!s->cap_stream &&
+                (e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+                return hip_fail(s, e, "creating capture stream");
+            if ((e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                return hip_fail(s, e, "begin capture");
+            const btl_status rc = enqueue(s->cap_stream, s->E_int.p);
+            hipGraph_t graph = nullptr;
+            const hipError_t ec = hipStreamEndCapture(s->cap_stream, &graph);
+            if (rc != BTL_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            if (ec != hipSuccess) return hip_fail(s, ec, "end capture");
+            e = hipGraphInstantiate(&s->graph_exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                s->graph_exec = nullptr;
+                return hip_fail(s, e, "graph instantiate");
+            }
+            s->graph_key = key;
         }
+        if ((e = hipGraphLaunch(s->graph_exec, st)) != hipSuccess) return hip_fail(s, e, "graph launch");
+        if ((e = hipMemcpyAsync(E, s->E_int.p, ebytes, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+            return hip_fail(s, e, "signal copy");
     }
     if (ckpt_every > 0 && K > 0) s->tape.valid = true;
     if (M_final) {
         if ((e = launch_mfinal(s->prec, s->pop[K & 1].p, fl.data(), n_fields, M_final, st)) !=
             hipSuccess)
             return hip_fail(s, e, "final magnetization launch");
+    }
+    return BTL_OK;
+}
+
+// Fields of one q-sample: 2^(k-1) or 2^k image fields, see plan_fields.
+static int64_t q_state_elems(const btl_sim* s, int32_t g, const double* G) {
+    const GeomHost& gh = s->geoms[g];
+    return (int64_t)plan_fields(gh, G).sigma.size() * kQ * gh.nsites;
+}
+
+extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double* D,
+                                  const double* T2, const double* kappa, int32_t Q,
+                                  const int32_t* q_geom, const double* gG0, const double* f,
+                                  double* E, void* M_final, int32_t ckpt_every, void* stream) {
+    if (!s) return BTL_E_INVAL;
+    if (Q < 1 || !q_geom || !gG0) return forward_impl(s, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E,
+                                                      M_final, ckpt_every, stream);
+    for (int q = 0; q < Q; ++q)
+        if (q_geom[q] < 0 || q_geom[q] >= (int)s->geoms.size())
+            return fail(s, BTL_E_INVAL, "q_geom out of range");
+    if (D && T2 && kappa && (K == 0 || f)) {
+        const int32_t P = s->n_phase;
+        s->last.valid = true;
+        s->last.dt = dt;
+        s->last.D.assign(D, D + P);
+        s->last.T2.assign(T2, T2 + P);
+        s->last.kappa.assign(kappa, kappa + P * P);
+        s->last.gG0.assign(gG0, gG0 + 3 * Q);
+        s->last.f.assign(f, f + K);
+        s->last.q_geom.assign(q_geom, q_geom + Q);
+    }
+    // q-waves: when the two population copies of all q-samples do not fit
+    // in device memory, run consecutive subsets of the q-samples
+    const size_t esz = s->prec == BTL_F32 ? sizeof(float2) : sizeof(double2);
+    size_t free_b = 0, total_b = 0;
+    (void)hipMemGetInfo(&free_b, &total_b);
+    const size_t have = free_b + s->pop[0].cap + s->pop[1].cap;
+    double budget = 0.85 * (double)have;
+    // BTLBM_MEM_BUDGET (bytes) lowers the budget, to exercise q-waves on
+    // small problems
+    if (const char* v = getenv("BTLBM_MEM_BUDGET")) budget = std::min(budget, atof(v));
+    double need = 0.0;
+    for (int q = 0; q < Q; ++q) need += 2.0 * (double)q_state_elems(s, q_geom[q], gG0 + 3 * q) * esz;
+    if (need <= budget || ckpt_every > 0)
+        return forward_impl(s, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E, M_final, ckpt_every,
+                            stream);
+    int32_t q0 = 0;
+    int64_t m_off = 0;
+    while (q0 < Q) {
+        double acc = 0.0;
+        int32_t q1 = q0;
+        while (q1 < Q) {
+            const double b = 2.0 * (double)q_state_elems(s, q_geom[q1], gG0 + 3 * q1) * esz;
+            if (q1 > q0 && acc + b > budget) break;
+            acc += b;
+            ++q1;
+        }
+        if (acc > budget)
+            return fail(s, BTL_E_NOMEM, "one q-sample does not fit in device memory");
+        void* Mw = M_final ? static_cast<char*>(M_final) + m_off * esz : nullptr;
+        const btl_status rc =
+            forward_impl(s, dt, K, D, T2, kappa, q1 - q0, q_geom + q0, gG0 + 3 * q0, f,
+                         E + (size_t)q0 * (K + 1) * 2, Mw, 0, stream);
+        if (rc != BTL_OK) return rc;
+        for (int q = q0; q < q1; ++q) m_off += s->geoms[q_geom[q]].nsites;
+        q0 = q1;
     }
     return BTL_OK;
 }
@@ -762,8 +896,14 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
         return hip_fail(s, e, "autotune events");
     int nz_max = 1;
     for (int q = 0; q < Qr; ++q) nz_max = std::max(nz_max, s->geoms[L.q_geom[q]].n[2]);
+    // z-column lengths: whole columns, halves, thirds, quarters, and short
+    // columns for small lattices that need more workgroups
     std::vector<int> zcs = {0};
-    for (int z = 8; z < nz_max; z *= 2) zcs.push_back(z);
+    for (int div : {2, 3, 4}) zcs.push_back((nz_max + div - 1) / div);
+    for (int z : {1, 2, 4, 8, 16}) zcs.push_back(z);
+    std::sort(zcs.begin(), zcs.end());
+    zcs.erase(std::unique(zcs.begin(), zcs.end()), zcs.end());
+    zcs.erase(std::remove_if(zcs.begin(), zcs.end(), [&](int z) { return z >= nz_max; }), zcs.end());
     const btl_sim::SimLast saved = L;
     float best = -1.0f;
     int best_shape = -1, best_zc = 0;
@@ -820,6 +960,9 @@ extern "C" void btl_destroy(btl_sim* s) {
     s->partial.release();
     s->counter.release();
     s->tune_E.release();
+    if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    s->E_int.release();
     s->ckpt.release();
     s->seg.release();
     s->lam[0].release();

@@ -179,6 +179,52 @@ def test_autotune_keeps_results():
     _check(E2, Eo, "f64", "after autotune")
 
 
+def test_q_waves_match_single_batch(monkeypatch):
+    # a device-memory budget below the batch's population size splits the
+    # q-samples into consecutive waves; every field is computed exactly as
+    # in the single batch
+    btl = _gpu()
+    cfg = w.make_config("cfg4", n=(24, 20, 16), K=60, n_q=7)
+    E1 = btl.simulate_config(cfg, prec="f32").cpu().numpy()
+    per_q = 2 * 7 * 24 * 20 * 16 * 8
+    monkeypatch.setenv("BTLBM_MEM_BUDGET", str(int(2.5 * per_q)))
+    Eg, Mg = btl.simulate_config(cfg, prec="f32", want_M=True)
+    monkeypatch.delenv("BTLBM_MEM_BUDGET")
+    assert np.array_equal(E1, Eg.cpu().numpy())
+    _, M1 = btl.simulate_config(cfg, prec="f32", want_M=True)
+    for a, b in zip(M1, Mg):
+        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+def test_graph_replays_match_eager(monkeypatch):
+    # forwards of >= 16 steps run from a cached hipGraph; each replay, with
+    # eager work and synchronizations in between, must equal the eager run
+    btl = _gpu()
+    import torch
+    cfg = w.make_config("cfg2", n=(20, 18, 12), K=90, n_q=3)
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], "f32")
+    args = (cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"])
+    try:
+        monkeypatch.setenv("BTLBM_NO_GRAPH", "1")
+        E0 = sim.forward(*args, cfg["f"], cfg["gG0"]).cpu().numpy()
+        monkeypatch.delenv("BTLBM_NO_GRAPH")
+        for rep in range(3):
+            E = sim.forward(*args, cfg["f"], cfg["gG0"]).cpu().numpy()
+            assert np.array_equal(E, E0), rep
+            # eager work of another shape in between (10 steps: no graph)
+            sim.forward(*args, cfg["f"][:10], cfg["gG0"][:1])
+            torch.cuda.synchronize()
+        # changed parameters with the same shape replay the same graph
+        D2 = np.array(cfg["D"]) * 1.1
+        E2 = sim.forward(cfg["dt"], D2, cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"]).cpu().numpy()
+        monkeypatch.setenv("BTLBM_NO_GRAPH", "1")
+        E2e = sim.forward(cfg["dt"], D2, cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"]).cpu().numpy()
+        assert np.array_equal(E2, E2e)
+        assert not np.array_equal(E2, E0)
+    finally:
+        sim.close()
+
+
 def test_invalid_arguments_raise():
     btl = _gpu()
     cfg = w.make_config("cfg1", n=4, K=3)

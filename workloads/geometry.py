@@ -96,13 +96,13 @@ def _relax_disks(rng, L, radii, gap, periodic, max_iter=20000):
         np.fill_diagonal(dist, np.inf)
         ov = need - dist
         np.fill_diagonal(ov, -1.0)
-        if ov.max() <= 1e-9:
+        if ov.max() <= 1e-7:
             return pos, np.ones(n, bool)
         m = ov > 0
         with np.errstate(invalid="ignore", divide="ignore"):
             u = d / dist[..., None]
         u[~m] = 0.0
-        push = 0.5 * (ov * m)[..., None] * 1.01 * u
+        push = 0.5 * (ov * m)[..., None] * 1.05 * u
         # i moves away from j: -push; j receives +push from i
         disp = -push.sum(axis=1)
         pos += disp
@@ -121,7 +121,7 @@ def _relax_disks(rng, L, radii, gap, periodic, max_iter=20000):
     for i in np.argsort(r):                             # smallest first
         if not keep[i]:
             continue
-        if np.any((ov[i] > 1e-9) & keep):
+        if np.any((ov[i] > 1e-7) & keep):
             keep[i] = False
     return pos, keep
 
@@ -279,6 +279,10 @@ def ellipsoid_cells(n, dx: float, seed: int, vf_target: float = 0.5,
         ax = rng.uniform(semi[0], semi[1], 3)
         R = _rand_rotation(rng)
         c = rng.uniform(0.0, 1.0, 3) * L
+        # quick rejection: centre voxel already taken
+        ci = [int(round(c[a] / dx)) % dims[a] for a in range(3)]
+        if occ[ci[2], ci[1], ci[0]]:
+            continue
         A = R @ np.diag(1.0 / ax ** 2) @ R.T        # x^T A x < 1 inside
         ext = np.sqrt(np.diag(np.linalg.inv(A)))     # bounding half-widths
         idx, rel = [], []
