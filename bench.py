@@ -233,7 +233,7 @@ def main():
 
     K, W = args.steps, args.warmup
     log(f"building workload {args.workload}")
-    cfg = workload(args.workload, max(K, W))
+    cfg = workload(args.workload, max(K, W, 0 if args.no_adjoint else args.adj_steps))
     Q = len(cfg["gG0"])
     qs = q_sites(cfg)
     fs = field_sites(cfg)
