@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
                 gdec += nu.x * g.x + nu.y * g.y;
                 gim += nu.x * g.y - nu.y * g.x;
                 const double2 lo2 = cmul(cc, nu);
-                store2(out + pop + d * ns + s, lo2);
+                store2_stream(out + pop + d * ns + s, lo2);
                 if (tl < 1.0) my[p * P + nbphase(d)] += lo2.x * dv.x + lo2.y * dv.y;
                 if (face) sF += -beta[f] * tl * (lo2.x * vv.y - lo2.y * vv.x);
             }

@@ -14,6 +14,16 @@ __device__ __forceinline__ void store2(float2* p, double2 v) {
     *p = make_float2((float)v.x, (float)v.y);
 }
 __device__ __forceinline__ void store2(double2* p, double2 v) { *p = v; }
+// Streaming stores: the next step reads the whole state back, which does not
+// fit in the caches, so the written lines are not kept.
+__device__ __forceinline__ void store2_stream(float2* p, double2 v) {
+    __builtin_nontemporal_store((float)v.x, &p->x);
+    __builtin_nontemporal_store((float)v.y, &p->y);
+}
+__device__ __forceinline__ void store2_stream(double2* p, double2 v) {
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+}
 
 // Value that is the same in every lane, kept in scalar registers.
 __device__ __forceinline__ double uniform(double v) {

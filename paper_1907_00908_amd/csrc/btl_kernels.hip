@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
             double2 h;
             h.x = g[d].x + w * (wd * M.x - g[d].x);
             h.y = g[d].y + w * (wd * M.y - g[d].y);
-            store2(out + d * ns, h);
+            store2_stream(out + d * ns, h);
         }
     };
 
