@@ -113,9 +113,10 @@ btl_status btl_forward(btl_sim *s, double dt, int32_t K, const double *D,
 /* Gradients of a real loss L with respect to the inputs of the last
  * btl_forward that kept a tape (ckpt_every > 0).  dL_dE is device
  * [Q][K+1][2] with dL/dE = dL/dRe E + i dL/dIm E.  Outputs are device
- * doubles, overwritten (NULL = not wanted): dD [P], dT2 [P], dkappa [P*P]
- * (the symmetric pair's gradient is reported in both [a][b] and [b][a],
- * each holding the full value), df [K].
+ * doubles, overwritten (NULL = not wanted): dD [P], dT2 [P], dkappa [P*P],
+ * df [K].  dkappa is the gradient per matrix entry: for a != b the entries
+ * [a][b] and [b][a] each hold half of dL/dkappa_ab, so that a symmetric
+ * parametrization (both entries set from one value) gets the full value.
  * Errors: BTL_E_INVAL (no tape), BTL_E_NOMEM, BTL_E_HIP. */
 btl_status btl_backward(btl_sim *s, const double *dL_dE, double *dD, double *dT2,
                         double *dkappa, double *df, void *stream);

@@ -340,7 +340,8 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
 // user parameters:
 //   dL/dD_p   = G_w[p] * dw/dD,     w = 1/tau, tau = 1/2 + dt D/(eps_D dx^2)
 //   dL/dT2_p  = G_dec[p] * dec_p * dt / T2_p^2
-//   dL/dkappa = (G_t[a][b] + G_t[b][a]) * dt/dkappa, t = 1/(1 + eps_D dx/(2 kappa dt))
+//   dL/dkappa[a][b] = (G_t[a][b] + G_t[b][a]) / 2 * dt/dkappa (a != b),
+//                     t = 1/(1 + eps_D dx/(2 kappa dt))
 //   dL/df_m   = G_f[m] + dt * sum_{k>m} G_F[k]       (F_k = sum_{m<k} f_m dt)
 __global__ void k_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P,
                             double dt, double dx, const double* w, const double* T2,
@@ -368,8 +369,10 @@ __global__ void k_adj_final(const double* gfield, int32_t K, int32_t n_fields, i
     if (t < P * P && dkappa) {
         const int i = t / P, j = t % P;
         const double k = kappa[t];
+        // gradient per matrix entry: the two entries of a pair share the
+        // pair's derivative equally, so that they sum to dL/dkappa_pair
         double g = total(2 * P + i * P + j);
-        if (i != j) g += total(2 * P + j * P + i);
+        if (i != j) g = 0.5 * (g + total(2 * P + j * P + i));
         // t = 8 k dt / (dx + 8 k dt) for eps_D = 1/4
         const double den = dx + 8.0 * k * dt;
         dkappa[t] = isinf(k) ? 0.0 : g * 8.0 * dt * dx / (den * den);
