@@ -57,7 +57,8 @@ typedef enum {
     BTL_E_UNSUPPORTED = 2,  /* valid request this build does not implement */
     BTL_E_NOMEM = 3,        /* device memory exhausted */
     BTL_E_HIP = 4,          /* a HIP runtime call failed */
-    BTL_E_NONFINITE = 5     /* a non-finite value was produced */
+    BTL_E_NONFINITE = 5     /* reserved (calls are asynchronous; this build does not
+                               inspect results, check E on the caller's side) */
 } btl_status;
 
 enum { BTL_PERIODIC = 0, BTL_MIRROR = 1 };   /* outer boundary per axis */
