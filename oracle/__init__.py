@@ -50,7 +50,7 @@ def _load():
         P = ctypes.c_void_p
         lib.oracle_run.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_int32, P, P,
                                    ctypes.c_double, ctypes.c_double, ctypes.c_int32,
-                                   P, P, P, P, P, P, P, P, P, ctypes.c_int32]
+                                   P, P, P, P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32]
         lib.oracle_run.restype = ctypes.c_int
         lib.oracle_tau.argtypes = [ctypes.c_double] * 3
         lib.oracle_tau.restype = ctypes.c_double
@@ -63,7 +63,7 @@ def _ptr(a):
 
 
 def _run_core(comp, comp_phase, n_phase, bc, off, dx, dt, D, T2, kappa, f, gG0,
-              elo, ehi, threads, want_M):
+              elo, ehi, threads, want_M, scheme=0):
     lib = _load()
     comp = np.ascontiguousarray(comp, dtype=np.uint32)
     n2, n1, n0 = comp.shape
@@ -84,7 +84,7 @@ def _run_core(comp, comp_phase, n_phase, bc, off, dx, dt, D, T2, kappa, f, gG0,
     rc = lib.oracle_run(_ptr(n), _ptr(comp), _ptr(cp), len(cp), int(n_phase), _ptr(bc),
                         _ptr(off), float(dx), float(dt), K, _ptr(D), _ptr(T2),
                         _ptr(kappa), _ptr(f), _ptr(gG0), _ptr(elo), _ptr(ehi),
-                        _ptr(E), _ptr(M) if want_M else None, int(threads))
+                        _ptr(E), _ptr(M) if want_M else None, int(threads), int(scheme))
     if rc == -2:
         raise NotImplementedError("oblique gradient on a mirrored axis")
     if rc != 0:
@@ -109,8 +109,12 @@ def needs_doubling(bc, gG0) -> bool:
     return False
 
 
+HYBRID, CLASSICAL = 0, 1
+
+
 def simulate(comp, comp_phase, n_phase, bc, dx, dt, D, T2, kappa, f, gG0,
-             threads: int = 1, mirror: str = "auto", want_M: bool = True):
+             threads: int = 1, mirror: str = "auto", want_M: bool = True,
+             scheme: int = HYBRID):
     """Run the scheme for one gradient vector.
 
     comp (n2, n1, n0) compartment ids, comp_phase [C], bc[3] (0 periodic,
@@ -118,16 +122,24 @@ def simulate(comp, comp_phase, n_phase, bc, dx, dt, D, T2, kappa, f, gG0,
     mirror: "paper" uses the paper's buffer rule (axis-aligned gradients
     only), "double" reflects and doubles every mirrored axis and runs
     periodic, "auto" picks "paper" when it applies.
+    scheme: HYBRID (the paper's split scheme) or CLASSICAL (reaction term in
+    the collision, Eq. A12).  The conjugate mirror rule relies on an exact
+    symmetry of the split reaction; with the classical scheme a mirrored
+    axis with a gradient component always runs on the doubled domain.
     Returns E [K+1] complex and M at t_K, complex (n2, n1, n0).
     """
     comp = np.asarray(comp)
     bc = [int(b) for b in bc]
     if mirror == "auto":
-        mirror = "double" if needs_doubling(bc, gG0) else "paper"
+        g = np.asarray(gG0, np.float64)
+        classical_mirror = scheme == CLASSICAL and any(
+            bc[a] == MIRROR and g[a] != 0.0 for a in range(3))
+        mirror = "double" if (needs_doubling(bc, gG0) or classical_mirror) else "paper"
     if mirror == "paper" or MIRROR not in bc:
         n2, n1, n0 = comp.shape
         return _run_core(comp, comp_phase, n_phase, bc, [0.0, 0.0, 0.0], dx, dt,
-                         D, T2, kappa, f, gG0, [0, 0, 0], [n0, n1, n2], threads, want_M)
+                         D, T2, kappa, f, gG0, [0, 0, 0], [n0, n1, n2], threads, want_M,
+                         scheme)
     if mirror != "double":
         raise ValueError("mirror must be 'auto', 'paper' or 'double'")
     # reflect the REV across the lower face of every mirrored axis: the
@@ -147,14 +159,14 @@ def simulate(comp, comp_phase, n_phase, bc, dx, dt, D, T2, kappa, f, gG0,
         lo[a], hi[a] = na, 2 * na
     bce = [PERIODIC] * 3
     E, M = _run_core(ext, comp_phase, n_phase, bce, off, dx, dt, D, T2, kappa, f,
-                     gG0, lo, hi, threads, want_M)
+                     gG0, lo, hi, threads, want_M, scheme)
     if want_M:
         M = M[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].copy()
     return E, M
 
 
 def simulate_config(cfg: dict, q=None, threads: int = 1, mirror: str = "auto",
-                    want_M: bool = False):
+                    want_M: bool = False, scheme: int = None):
     """Run every q-sample (or the listed ones) of a workloads config."""
     qs = range(len(cfg["gG0"])) if q is None else q
     Es, Ms = [], []
@@ -162,7 +174,8 @@ def simulate_config(cfg: dict, q=None, threads: int = 1, mirror: str = "auto",
         g = cfg["geoms"][int(cfg["q_geom"][i])]
         E, M = simulate(g.comp, g.comp_phase, g.n_phase, cfg["bc"], cfg["dx"], cfg["dt"],
                         cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"][i],
-                        threads=threads, mirror=mirror, want_M=want_M)
+                        threads=threads, mirror=mirror, want_M=want_M,
+                        scheme=cfg.get("scheme", HYBRID) if scheme is None else scheme)
         Es.append(E)
         Ms.append(M)
     return np.array(Es), Ms

@@ -22,6 +22,12 @@
  *                                                  (Eqs. reaction_LBM, delta_phi)
  * and after the last step the signal E_K and the magnetization M.
  *
+ * With scheme = 1 the routine runs the classical LBM instead (Appendix A,
+ * Eq. A12): no reaction split; the collision carries the reaction term,
+ *   ghat_i = g_i - (g_i - w_i M)/tau + dt w_i R M,
+ *   R(x, t^k) = -i gamma (x.G0) f(t^k) - 1/T2,
+ * and the boundary and membrane rules are unchanged.
+ *
  * Lattice: D3Q7 with eps_D = 1/4, w_0 = 1/4, w_{+-x,+-y,+-z} = 1/8.  The
  * paper leaves the 3D weights implicit; eps_D = 1/4 is what its Fig. 11
  * caption requires (tau = 0.58 at D = 2, dt = 0.01, dx = 1), and the weights
@@ -108,9 +114,11 @@ int oracle_run(const int32_t n[3], const uint32_t *comp, const uint8_t *comp_pha
                const double off[3], double dx, double dt, int32_t K,
                const double *D, const double *T2, const double *kappa,
                const double *f, const double gG0[3], const int32_t elo[3],
-               const int32_t ehi[3], double *E, double *M_out, int32_t nthreads) {
+               const int32_t ehi[3], double *E, double *M_out, int32_t nthreads,
+               int32_t scheme) {
     const long n0 = n[0], n1 = n[1], n2 = n[2];
     if (n0 < 1 || n1 < 1 || n2 < 1 || dx <= 0 || dt <= 0 || K < 0) return -1;
+    if (scheme != 0 && scheme != 1) return -1;
     const long N = n0 * n1 * n2;
     for (int a = 0; a < 3; ++a) {
         if (bc[a] != BC_PERIODIC && bc[a] != BC_MIRROR) return -1;
@@ -203,9 +211,18 @@ int oracle_run(const int32_t n[3], const uint32_t *comp, const uint8_t *comp_pha
                 for (long j0 = 0; j0 < n0; ++j0) {
                     long s = IDX(j0, j1, j2);
                     int p = comp_phase[comp[s]];
+                    cplx RM = 0;
+                    if (scheme == 1) {
+                        /* reaction term of the classical collision (Eq. A12) */
+                        const double xg = gG0[0] * COORD(0, j0) + gG0[1] * COORD(1, j1)
+                                        + gG0[2] * COORD(2, j2);
+                        const double rdec = isinf(T2[p]) ? 0.0 : 1.0 / T2[p];
+                        RM = (-I * xg * f[k] - rdec) * M[s];
+                    }
                     for (int i = 0; i < Q; ++i) {
                         cplx gi = g[i * N + s];
-                        gh[i * PN + PIDX(j0, j1, j2)] = gi - (gi - W[i] * M[s]) / tau[p];
+                        gh[i * PN + PIDX(j0, j1, j2)] = gi - (gi - W[i] * M[s]) / tau[p]
+                                                      + dt * W[i] * RM;
                     }
                 }
 
@@ -271,7 +288,7 @@ int oracle_run(const int32_t n[3], const uint32_t *comp, const uint8_t *comp_pha
                     /* reaction factor: exp(-i gamma (x.G0) f_k dt) exp(-dt/T2) */
                     const double xg = gG0[0] * COORD(0, j0) + gG0[1] * COORD(1, j1)
                                     + gG0[2] * COORD(2, j2);
-                    const cplx react = cexp(-I * xg * fk_dt) * decay[px];
+                    const cplx react = scheme == 1 ? 1.0 : cexp(-I * xg * fk_dt) * decay[px];
                     for (int i = 0; i < Q; ++i) {
                         long src[3];
                         int crossed = -1;

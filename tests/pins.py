@@ -64,8 +64,11 @@ def _cblock(c, conj=False):
     return np.array([[cr, -ci], [ci, cr]])
 
 
-def dense_step_matrices(comp, comp_phase, bc, dx, dt, D, T2, kappa, f, gG0):
+def dense_step_matrices(comp, comp_phase, bc, dx, dt, D, T2, kappa, f, gG0, scheme=0):
     """Real step matrices A_k (one per step) for a tiny lattice.
+
+    scheme 1: classical LBM, the reaction term dt w_i R M inside the
+    collision and no reaction split.
 
     State vector: index part*7N + i*N + s, part 0 = Re, 1 = Im, s the site
     index with x fastest.  Mirror faces use the paper's rule for gradients
@@ -91,6 +94,7 @@ def dense_step_matrices(comp, comp_phase, bc, dx, dt, D, T2, kappa, f, gG0):
             for j in range(7):
                 C[i * N + s, j * N + s] += w[s] * W[i]
     Cr = np.kron(np.eye(2), C)
+    inv_t2 = np.array([0.0 if math.isinf(T2[p]) else 1.0 / T2[p] for p in ph])
     mats = []
     F = 0.0
     gG0 = np.asarray(gG0, np.float64)
@@ -145,6 +149,22 @@ def dense_step_matrices(comp, comp_phase, bc, dx, dt, D, T2, kappa, f, gG0):
                 else:
                     for (src_i, c, cj) in terms:
                         add(i * N + s, src_i, c, cj)
+        if scheme == 1:
+            # collision with dt w_i R M, R = -i (x.gG0) f_k - 1/T2
+            Ck = Cr.copy()
+            for s_ in range(N):
+                j = (s_ % n0, (s_ // n0) % n1, s_ // (n0 * n1))
+                xg = sum(gG0[a] * j[a] * dx for a in range(3))
+                Rc = (-1j * xg * f[k] - inv_t2[s_]) * dt
+                for i in range(7):
+                    for jj in range(7):
+                        blk = W[i] * _cblock(Rc)
+                        for pd in range(2):
+                            for ps in range(2):
+                                Ck[pd * S7 + i * N + s_, ps * S7 + jj * N + s_] += blk[pd, ps]
+            mats.append(S @ Ck)
+            F += f[k] * dt
+            continue
         # reaction
         R = np.zeros((2 * S7, 2 * S7))
         for s in range(N):

@@ -326,3 +326,46 @@ def test_z_invariance_oblique_gradient():
     _, Mh = _run(g.comp, g.comp_phase, 2, [0, 0, 0], 1.0, dt, [2.0, 1.5], [10.0, 30.0],
                  np.array([[INF, 0.01], [0.01, INF]]), f[:12], G)
     assert np.max(np.abs(np.abs(Mh) - np.abs(Mh[0:1]))) < 1e-14
+
+
+# ---- classical LBM (Appendix A, Eq. A12): reaction inside the collision ----
+
+@pytest.mark.parametrize("bc", [[0, 0, 0], [0, 1, 0]])
+def test_classical_dense_bruteforce(bc):
+    comp, cp = _tiny_geom()
+    kap = np.array([[INF, 0.03], [0.03, 0.01]])
+    D, T2 = [2.0, 0.7], [30.0, 12.0]
+    f = np.array([1.0, 1.0, 0.3, 0.0, -0.5, -1.0, -1.0, 0.2])
+    gG0 = np.array([1.1, 0.0 if bc[1] else -0.6, 0.8])
+    mats = pins.dense_step_matrices(comp, cp, bc, 0.5, 0.01, D, T2, kap, f, gG0, scheme=1)
+    ref = pins.dense_run(mats, comp.size)
+    E, _ = _run(comp, cp, 2, bc, 0.5, 0.01, D, T2, kap, f, gG0, mirror="double", scheme=1)
+    assert np.max(np.abs(E - ref)) < 1e-14
+
+
+def test_classical_T2_decay_closed_form():
+    # G = 0: the classical collision multiplies M by (1 - dt/T2) per step
+    g = w.cylinders_z((10, 9, 3), 0.25, seed=14, vf_target=0.5)
+    E, _ = _run(g.comp, g.comp_phase, 2, [0, 0, 0], 0.25, 0.004, [2.0, 1.0], [40.0, 40.0],
+                [[INF, 0.02], [0.02, INF]], np.zeros(50), [0, 0, 0], scheme=1)
+    k = np.arange(51)
+    assert np.max(np.abs(E - (1.0 - 0.004 / 40.0) ** k)) < 1e-14
+
+
+def test_hybrid_error_independent_of_domain_size_classical_not():
+    # Sec. 3.1 (uniform initial condition): the hybrid scheme's error does
+    # not depend on the REV size L, the classical scheme's grows with L
+    D, T2, dx, dt = 2.5, 80.0, 0.5, 0.01
+    f = w.pgse_waveform(5.0, 20.0, dt)
+    gG = w.gamma_g_for_b_pgse(1.0, 5.0, 20.0)
+    exact = math.exp(-D) * math.exp(-25.0 / T2)
+    err = {}
+    for L in (20, 100):
+        g = w.uniform((int(L / dx), 1, 1), dx)
+        for sch in (0, 1):
+            E, _ = _run(g.comp, g.comp_phase, 1, [0, 0, 0], dx, dt, [D], [T2], [[INF]], f,
+                        [gG, 0, 0], want_M=False, scheme=sch)
+            err[(L, sch)] = abs(E[-1] - exact) / exact
+    assert abs(err[(20, 0)] - err[(100, 0)]) < 1e-12 and err[(20, 0)] < 1e-3
+    assert err[(20, 1)] > 10 * err[(20, 0)]
+    assert err[(100, 1)] > 10 * err[(20, 1)]
