@@ -63,6 +63,7 @@ typedef enum {
 
 enum { BTL_PERIODIC = 0, BTL_MIRROR = 1 };   /* outer boundary per axis */
 enum { BTL_F64 = 0, BTL_F32 = 1 };           /* population storage precision */
+enum { BTL_HYBRID = 0, BTL_CLASSICAL = 1 };  /* time integration scheme */
 
 /* One geometry: a compartment-label volume.  Every lattice link joining two
  * different compartments carries a membrane whose permeability is chosen by
@@ -121,6 +122,16 @@ btl_status btl_forward(btl_sim *s, double dt, int32_t K, const double *D,
  * Errors: BTL_E_INVAL (no tape), BTL_E_NOMEM, BTL_E_HIP. */
 btl_status btl_backward(btl_sim *s, const double *dL_dE, double *dD, double *dT2,
                         double *dkappa, double *df, void *stream);
+
+/* Select the scheme of later btl_forward calls.  BTL_HYBRID (default) is
+ * the paper's split scheme (Sec. 2.3).  BTL_CLASSICAL is the classical LBM
+ * the paper compares it with (Appendix A, Eq. A12): no reaction split; the
+ * collision carries dt w_i R M with R = -i gamma (x.G0) f(t^k) - 1/T2, and the
+ * boundary and membrane rules are unchanged (mirrored faces with a gradient
+ * component use the reflected medium, without the conjugate pairing that
+ * only the split reaction makes exact).  btl_backward supports BTL_HYBRID
+ * only.  Errors: BTL_E_INVAL (unknown scheme). */
+btl_status btl_set_scheme(btl_sim *s, int32_t scheme);
 
 /* Choose the launch shape (workgroup tile and z-column length) of this
  * simulator by timing every candidate on the inputs of the last btl_forward

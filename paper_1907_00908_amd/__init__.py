@@ -2,7 +2,8 @@
 
 Argument marshalling only: every step of the computation runs in the HIP
 kernels of libbtlbm.so.  The functions `btl_create`, `btl_forward`,
-`btl_backward`, `btl_autotune`, `btl_destroy` and `btl_last_error` mirror the
+`btl_backward`, `btl_set_scheme`, `btl_autotune`, `btl_destroy` and
+`btl_last_error` mirror the
 C ABI of include/btlbm.h one to one.  `Simulator` wraps them with torch
 tensors for device memory and the current torch stream.
 
@@ -23,9 +24,10 @@ LIB_PATH = os.path.join(_HERE, "libbtlbm.so")
 BTL_OK, BTL_E_INVAL, BTL_E_UNSUPPORTED, BTL_E_NOMEM, BTL_E_HIP, BTL_E_NONFINITE = range(6)
 BTL_PERIODIC, BTL_MIRROR = 0, 1
 BTL_F64, BTL_F32 = 0, 1
+BTL_HYBRID, BTL_CLASSICAL = 0, 1
 
-EXPORTED = ("btl_create", "btl_forward", "btl_backward", "btl_autotune",
-            "btl_destroy", "btl_last_error")
+EXPORTED = ("btl_create", "btl_forward", "btl_backward", "btl_set_scheme",
+            "btl_autotune", "btl_destroy", "btl_last_error")
 
 
 class BtlError(RuntimeError):
@@ -64,6 +66,8 @@ def load_library(path: str = None):
     lib.btl_forward.restype = ctypes.c_int
     lib.btl_backward.argtypes = [P, P, P, P, P, P, P]
     lib.btl_backward.restype = ctypes.c_int
+    lib.btl_set_scheme.argtypes = [P, i32]
+    lib.btl_set_scheme.restype = ctypes.c_int
     lib.btl_autotune.argtypes = [P, i32, i32, P]
     lib.btl_autotune.restype = ctypes.c_int
     lib.btl_destroy.argtypes = [P]
@@ -132,6 +136,10 @@ def btl_backward(h, dLdE_ptr, dD_ptr, dT2_ptr, dkappa_ptr, df_ptr, stream_ptr):
                             V(df_ptr), V(stream_ptr)), h)
 
 
+def btl_set_scheme(h, scheme):
+    _check(load_library().btl_set_scheme(h, int(scheme)), h)
+
+
 def btl_autotune(h, Q, K_probe, stream_ptr):
     lib = load_library()
     _check(lib.btl_autotune(h, int(Q), int(K_probe),
@@ -160,7 +168,7 @@ class _GeomBC:
 class Simulator:
     """Owns one btl_sim.  Device memory for E and M_final comes from torch."""
 
-    def __init__(self, geoms, bc, prec: str = "f32"):
+    def __init__(self, geoms, bc, prec: str = "f32", scheme: int = BTL_HYBRID):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Simulator needs a HIP device")
@@ -169,6 +177,8 @@ class Simulator:
         self.geoms = list(geoms)
         bcs = bc if isinstance(bc[0], (list, tuple)) else [bc] * len(self.geoms)
         self._h = btl_create([_GeomBC(g, b) for g, b in zip(self.geoms, bcs)], self.prec)
+        if scheme != BTL_HYBRID:
+            btl_set_scheme(self._h, scheme)
 
     def close(self):
         if self._h is not None:
@@ -277,9 +287,12 @@ def bloch_torrey_signal(D, T2, kappa, f, sim, dt, gG0, q_geom=None, ckpt_every=1
     return _BTS.apply(D, T2, kappa, f, sim, dt, gG0, q_geom, ckpt_every)
 
 
-def simulate_config(cfg: dict, prec: str = "f32", want_M: bool = False):
-    """Run a workloads config on the GPU: returns E (Q, K+1) complex (and M)."""
-    sim = Simulator(cfg["geoms"], cfg["bc"], prec)
+def simulate_config(cfg: dict, prec: str = "f32", want_M: bool = False, scheme=None):
+    """Run a workloads config on the GPU: returns E (Q, K+1) complex (and M).
+    The scheme is `scheme`, else the config's "scheme" entry, else hybrid."""
+    if scheme is None:
+        scheme = cfg.get("scheme", BTL_HYBRID)
+    sim = Simulator(cfg["geoms"], cfg["bc"], prec, scheme)
     try:
         out = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"],
                           cfg["gG0"], cfg["q_geom"], want_M=want_M)

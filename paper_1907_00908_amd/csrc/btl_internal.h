@@ -93,6 +93,7 @@ struct StepArgs {
     double2* partial;       // [blocks] per-workgroup signal partial sums
     uint32_t* counter;      // [fields] arrival counters for the last-block reduction
     double* E;              // [Q][K+1][2]
+    const double* rdt;      // [P] dt/T2 (classical scheme)
     double2* tab;           // phase table of step k (T entries); the table kernel
                             // fills kTabSteps consecutive steps from here
     const int32_t* tab_field;  // [T] field of each table entry
@@ -100,6 +101,8 @@ struct StepArgs {
     int32_t n_phase;
     int32_t k;
     int32_t K;
+    int32_t classical;      // 1: reaction term in the collision, no split
+    int32_t pad1;
 };
 
 // Workgroup tile shapes (TX x TY threads, one site column along z each).
@@ -120,6 +123,11 @@ hipError_t launch_init(int prec, void* pop, int64_t n_elem_per_dir_total,
                        const FieldDesc* h_fields, double* E, int32_t Q, int32_t K,
                        hipStream_t st);
 hipError_t launch_step(int prec, int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st);
+// initial post-collision state of the classical scheme (depends on R at t^0)
+// (fdt: the waveform table f_k dt, of which the kernel reads entry 0)
+hipError_t launch_init_classical(int prec, void* pop, const FieldDesc* h_fields, int32_t n_fields,
+                                 const uint32_t* words, const double* fdt, const double* rdt,
+                                 hipStream_t st);
 // phase tables of steps a.k .. a.k + nsteps - 1 into a.tab[0 .. nsteps*T)
 hipError_t launch_tables(const StepArgs& a, int32_t nsteps, hipStream_t st);
 hipError_t launch_mfinal(int prec, const void* pop, const FieldDesc* h_fields,

@@ -17,7 +17,8 @@
 //      (Eq. M'summation; signal Sec. 2.1)
 //   4. ghat_i = g_i + w (w_i M - g_i), w = 1/tau       (Eq. collision_LBM)
 // which is the paper's collide -> stream -> react cycle (Eq.
-// LBM_process_list_2) started at the stream.  All arithmetic is FP64;
+// LBM_process_list_2) started at the stream.  The classical LBM of Appendix A
+// (Eq. A12) shares steps 1 and 3 and moves the reaction into step 4.  All arithmetic is FP64;
 // populations are stored as float2 or double2 (x fastest, one plane per
 // direction per field).  Per-step constants enter only through forms that
 // keep sum_i g_i exact for any rounded constant (g + w(wM - g), a + t(b - a)).
@@ -65,7 +66,13 @@ __global__ void __launch_bounds__(kBlock) k_tables(StepArgs a, int32_t nsteps) {
 // One step for a tile of TX x TY site columns, each thread walking fd.zc
 // sites along z.  Workgroup -> (field, tile) via blk_field and the field's
 // tile counts; no per-site integer division.
-template <typename V, int TX>
+//
+// CL = true runs the classical LBM (Appendix A, Eq. A12) with the same
+// streaming: step 2 is skipped and step 4 adds dt w_i R M with
+// R = -i gamma (x.G0) f_{k+1} - 1/T2, the reaction term of the collision that
+// follows the moment M(t^{k+1}).  The last step stores the plain collision,
+// whose moment is M(t^K).
+template <typename V, int TX, bool CL>
 __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     constexpr int TY = kBlock / TX;
     __shared__ double2 lds[kBlock / 64];
@@ -77,7 +84,7 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
         const int t = threadIdx.x, P = a.n_phase;
         if (t < P) {
             c_w[t] = a.w[t];
-            c_dec[t] = a.decay[t];
+            c_dec[t] = CL ? a.rdt[t] : a.decay[t];
         }
         if (t < P * P) c_tr[t] = a.trans[t];
     }
@@ -110,7 +117,13 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     const int32_t j1 = ty * TY + (int32_t)(threadIdx.x / TX);
     const int32_t z1 = min(n2, z0 + fd.zc);
     const int32_t st1 = n0, st2 = n0 * n1;
-    const double2 exy = cmul(tab[min(j0, n0 - 1)], tab[n0 + min(j1, n1 - 1)]);
+    const double2 exy = CL ? make_double2(0.0, 0.0)
+                           : cmul(tab[min(j0, n0 - 1)], tab[n0 + min(j1, n1 - 1)]);
+    // classical: dt R = ra + i rb with rb = -f_{k+1} dt (c.j + cu)
+    const bool cl_term = CL && a.k + 1 < a.K;
+    const double fdt1 = cl_term ? a.fdt[a.k + 1] : 0.0;
+    const double rb_xy = -fdt1 * (fd.c[0] * (double)j0 + fd.c[1] * (double)j1 + fd.cu);
+    const double rb_z = -fdt1 * fd.c[2];
 
     // Source offset (relative to the site index s) of each pulled direction,
     // fixed for the whole z column for x and y; z faces switch per site.
@@ -162,7 +175,7 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
             const int od = (d & 1) ? d + 1 : d - 1;
             L.own[d - 1] = src[pop + od * ns + s];
         }
-        L.ez = ez[j2];
+        if (!CL) L.ez = ez[j2];
     };
     auto compute = [&](int32_t j2, const SiteLoads& L, double2& Macc) {
         const int32_t s = j0 + st1 * j1 + st2 * j2;
@@ -197,20 +210,30 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
                 }
             }
         }
-        // reaction: exp(-i fdt (c.j + cu)) exp(-dt/T2)
-        const double2 e = cmul(exy, L.ez);
-        const double dec = c_dec[p];
-        const double2 rf = make_double2(e.x * dec, e.y * dec);
         double2 M = make_double2(0.0, 0.0);
+        if (!CL) {
+            // reaction: exp(-i fdt (c.j + cu)) exp(-dt/T2)
+            const double2 e = cmul(exy, L.ez);
+            const double dec = c_dec[p];
+            const double2 rf = make_double2(e.x * dec, e.y * dec);
+#pragma unroll
+            for (int d = 0; d < kQ; ++d) g[d] = cmul(g[d], rf);
+        }
 #pragma unroll
         for (int d = 0; d < kQ; ++d) {
-            g[d] = cmul(g[d], rf);
             M.x += g[d].x;
             M.y += g[d].y;
         }
         Macc.x += M.x;
         Macc.y += M.y;
-        // collision: ghat = g + w (w_d M - g)
+        // classical reaction term dt R M (zero on the last step)
+        double2 RM = make_double2(0.0, 0.0);
+        if (CL) {
+            const double ra = cl_term ? -c_dec[p] : 0.0;
+            const double rb = rb_xy + rb_z * (double)j2;
+            RM = make_double2(ra * M.x - rb * M.y, ra * M.y + rb * M.x);
+        }
+        // collision: ghat = g + w (w_d M - g)  [+ w_d dt R M]
         const double w = c_w[p];
         V* out = dst + s;
 #pragma unroll
@@ -219,6 +242,10 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
             double2 h;
             h.x = g[d].x + w * (wd * M.x - g[d].x);
             h.y = g[d].y + w * (wd * M.y - g[d].y);
+            if (CL) {
+                h.x += wd * RM.x;
+                h.y += wd * RM.y;
+            }
             store2_stream(out + d * ns, h);
         }
     };
@@ -268,6 +295,28 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     }
 }
 
+// ghat^0 of the classical scheme: the collision of the equilibrium state
+// g_i = w_i (M = 1) with its reaction term, ghat_i = w_i (1 + dt R(x, t^0)),
+// dt R = -dt/T2 - i f_0 dt (c.j + cu).
+template <typename V>
+__global__ void __launch_bounds__(kBlock) k_init_classical(V* pop, FieldDesc fd,
+                                                            const uint32_t* words,
+                                                            const double* fdt,
+                                                            const double* rdt) {
+    const int32_t s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= fd.nsites) return;
+    const int32_t n0 = fd.n[0], n1 = fd.n[1];
+    const int32_t j0 = s % n0, r = s / n0, j1 = r % n1, j2 = r / n1;
+    const int p = (int)(words[fd.words + s] & 0xfu);
+    const double ra = 1.0 - rdt[p];
+    const double rb = -fdt[0] * (fd.c[0] * j0 + fd.c[1] * j1 + fd.c[2] * j2 + fd.cu);
+#pragma unroll
+    for (int d = 0; d < kQ; ++d) {
+        const double wd = d == 0 ? 0.25 : 0.125;
+        store2(pop + fd.pop + (int64_t)d * fd.nsites + s, make_double2(wd * ra, wd * rb));
+    }
+}
+
 template <typename V>
 __global__ void __launch_bounds__(kBlock) k_mfinal(const V* pop, int64_t nsites, V* out) {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -300,29 +349,48 @@ hipError_t launch_init(int prec, void* pop, int64_t, const FieldDesc*, int32_t n
     return hipGetLastError();
 }
 
-template <typename V>
+template <typename V, bool CL>
 static void launch_step_t(int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st) {
     switch (shape) {
         case kTile64x4:
-            hipLaunchKernelGGL((k_step<V, 64>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL((k_step<V, 64, CL>), dim3(n_blocks), dim3(kBlock), 0, st, a);
             break;
         case kTile32x8:
-            hipLaunchKernelGGL((k_step<V, 32>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL((k_step<V, 32, CL>), dim3(n_blocks), dim3(kBlock), 0, st, a);
             break;
         case kTile128x2:
-            hipLaunchKernelGGL((k_step<V, 128>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL((k_step<V, 128, CL>), dim3(n_blocks), dim3(kBlock), 0, st, a);
             break;
         default:
-            hipLaunchKernelGGL((k_step<V, 16>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL((k_step<V, 16, CL>), dim3(n_blocks), dim3(kBlock), 0, st, a);
             break;
     }
 }
 
 hipError_t launch_step(int prec, int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st) {
-    if (prec == 1)
-        launch_step_t<float2>(shape, a, n_blocks, st);
-    else
-        launch_step_t<double2>(shape, a, n_blocks, st);
+    if (prec == 1) {
+        if (a.classical) launch_step_t<float2, true>(shape, a, n_blocks, st);
+        else launch_step_t<float2, false>(shape, a, n_blocks, st);
+    } else {
+        if (a.classical) launch_step_t<double2, true>(shape, a, n_blocks, st);
+        else launch_step_t<double2, false>(shape, a, n_blocks, st);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_init_classical(int prec, void* pop, const FieldDesc* h, int32_t n_fields,
+                                 const uint32_t* words, const double* fdt, const double* rdt,
+                                 hipStream_t st) {
+    for (int f = 0; f < n_fields; ++f) {
+        if (prec == 1)
+            hipLaunchKernelGGL(k_init_classical<float2>, dim3(grid_for(h[f].nsites)),
+                               dim3(kBlock), 0, st, static_cast<float2*>(pop), h[f], words, fdt,
+                               rdt);
+        else
+            hipLaunchKernelGGL(k_init_classical<double2>, dim3(grid_for(h[f].nsites)),
+                               dim3(kBlock), 0, st, static_cast<double2*>(pop), h[f], words, fdt,
+                               rdt);
+    }
     return hipGetLastError();
 }
 

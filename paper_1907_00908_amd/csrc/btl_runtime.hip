@@ -57,7 +57,7 @@ constexpr int kGraphMinSteps = 16;   // forwards this long run from a cached hip
 // Everything a captured forward depends on besides the contents of its
 // buffers; a forward replays the cached graph only when this matches.
 struct GraphKey {
-    int32_t prec, K, Q, n_fields, nblk, shape, T, ckpt;
+    int32_t prec, K, Q, n_fields, nblk, shape, T, ckpt, scheme;
     const void* ptr[16];
 };
 
@@ -65,6 +65,7 @@ struct GraphKey {
 
 struct btl_sim {
     int prec = BTL_F32;
+    int scheme = BTL_HYBRID;
     int device = 0;
     double dx = 1.0;
     int32_t n_phase = 1;
@@ -74,7 +75,7 @@ struct btl_sim {
     DevBuf<FieldDesc> fields;
     DevBuf<int32_t> blk_field;
     DevBuf<double> steps;        // fdt [K] then Fk [K+1]
-    DevBuf<double> consts;       // w [P], decay [P], trans [P*P]
+    DevBuf<double> consts;       // w [P], decay [P], trans [P*P], T2 [P], kappa [P*P], dt/T2 [P]
     DevBuf<double2> partial;
     DevBuf<uint32_t> counter;
     DevBuf<double2> tab;         // [kTabSteps][T] per-step phase tables
@@ -265,13 +266,15 @@ extern "C" btl_status btl_create(const btl_geom* geoms, int32_t n_geom, int32_t 
 // non-zero component is mirrored, the copy reflected in all of them is the
 // complex conjugate of the primary (times a uniform phase), which halves the
 // set: only patterns with sigma_{a*} = 0 (a* the first such axis) are kept.
+// That symmetry needs the reaction as an exact phase factor; the classical
+// scheme (reaction term inside the collision) keeps every pattern.
 struct QFields {
     std::vector<int> sigma;   // canonical sign patterns, sigma[0] = 0 (primary)
     int amask = 0;
     bool conj_pair = false;
 };
 
-static QFields plan_fields(const GeomHost& g, const double* G) {
+static QFields plan_fields(const GeomHost& g, const double* G, bool classical) {
     QFields r;
     bool all_mirrored = true;
     int astar = -1;
@@ -284,7 +287,7 @@ static QFields plan_fields(const GeomHost& g, const double* G) {
             all_mirrored = false;
         }
     }
-    r.conj_pair = (r.amask != 0) && all_mirrored;
+    r.conj_pair = (r.amask != 0) && all_mirrored && !classical;
     for (int sg = 0; sg < 8; ++sg) {
         if ((sg & ~r.amask) != 0) continue;
         if (r.conj_pair && ((sg >> astar) & 1)) continue;
@@ -327,7 +330,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     const double dx = s->dx;
 
     // per-phase and per-pair constants (FP64)
-    std::vector<double> consts(2 * P + P * P + P + P * P);
+    std::vector<double> consts(2 * P + P * P + P + P * P + P);
     for (int p = 0; p < P; ++p) {
         const double tau = 0.5 + dt * D[p] / (kEpsD * dx * dx);
         consts[p] = 1.0 / tau;
@@ -348,6 +351,8 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     }
     for (int p = 0; p < P; ++p) consts[2 * P + P * P + p] = T2[p];
     for (int i = 0; i < P * P; ++i) consts[3 * P + P * P + i] = kappa[i];
+    for (int p = 0; p < P; ++p) consts[3 * P + 2 * P * P + p] = isinf(T2[p]) ? 0.0 : dt / T2[p];
+    const bool classical = s->scheme == BTL_CLASSICAL;
     // per-step waveform tables
     std::vector<double> steps((size_t)K + (size_t)K + 1);
     {
@@ -379,7 +384,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     for (int q = 0; q < Q; ++q) {
         const GeomHost& g = s->geoms[q_geom[q]];
         const double* G = gG0 + 3 * q;
-        QFields qf = plan_fields(g, G);
+        QFields qf = plan_fields(g, G, s->scheme == BTL_CLASSICAL);
         const int base = (int)fl.size();
         auto slot_of = [&](int sg, int* cj) {
             for (size_t i = 0; i < qf.sigma.size(); ++i)
@@ -572,6 +577,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     const size_t state_bytes = (size_t)pop_elems * esz;
     if (ckpt_every > 0 && K > 0) {
         if (P > kAdjMaxPhase) return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports n_phase <= 4");
+        if (classical) return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports the hybrid scheme only");
         const int32_t C = std::min(ckpt_every, K);
         const int32_t nck = (K + C - 1) / C;
         if ((e = s->ckpt.ensure((size_t)nck * state_bytes)) != hipSuccess)
@@ -595,6 +601,11 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         if ((err = launch_init(s->prec, s->pop[0].p, pop_elems, s->fields.p, n_fields, fl.data(),
                                Eptr, Q, K, q)) != hipSuccess)
             return hip_fail(s, err, "init launch");
+        if (classical && K > 0 &&
+            (err = launch_init_classical(s->prec, s->pop[0].p, fl.data(), n_fields, s->words.p,
+                                         s->steps.p, s->consts.p + 3 * P + 2 * P * P, q)) !=
+                hipSuccess)
+            return hip_fail(s, err, "init launch");
         if (ckpt_every > 0 && K > 0 &&
             (err = hipMemcpyAsync(s->ckpt.p, s->pop[0].p, state_bytes, hipMemcpyDeviceToDevice, q)) !=
                 hipSuccess)
@@ -609,6 +620,8 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         a.w = s->consts.p;
         a.decay = s->consts.p + P;
         a.trans = s->consts.p + 2 * P;
+        a.rdt = s->consts.p + 3 * P + 2 * P * P;
+        a.classical = classical ? 1 : 0;
         a.partial = s->partial.p;
         a.counter = s->counter.p;
         a.E = Eptr;
@@ -656,6 +669,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         key.shape = shape;
         key.T = T;
         key.ckpt = ckpt_every;
+        key.scheme = s->scheme;
         const void* ptrs[] = {s->pop[0].p, s->pop[1].p, s->fields.p, s->blk_field.p, s->steps.p,
                               s->consts.p, s->partial.p, s->counter.p, s->tab.p, s->tab_field.p,
                               s->E_int.p, s->ckpt.p, s->words.p};
@@ -704,7 +718,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
 // Fields of one q-sample: 2^(k-1) or 2^k image fields, see plan_fields.
 static int64_t q_state_elems(const btl_sim* s, int32_t g, const double* G) {
     const GeomHost& gh = s->geoms[g];
-    return (int64_t)plan_fields(gh, G).sigma.size() * kQ * gh.nsites;
+    return (int64_t)plan_fields(gh, G, s->scheme == BTL_CLASSICAL).sigma.size() * kQ * gh.nsites;
 }
 
 extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double* D,
@@ -944,6 +958,15 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
     }
     s->tile_shape = best_shape;
     s->zc = best_zc;
+    return BTL_OK;
+}
+
+extern "C" btl_status btl_set_scheme(btl_sim* s, int32_t scheme) {
+    if (!s) return BTL_E_INVAL;
+    if (scheme != BTL_HYBRID && scheme != BTL_CLASSICAL)
+        return fail(s, BTL_E_INVAL, "scheme must be BTL_HYBRID or BTL_CLASSICAL");
+    s->scheme = scheme;
+    s->tape.valid = false;
     return BTL_OK;
 }
 
