@@ -50,8 +50,11 @@ def _load():
         P = ctypes.c_void_p
         lib.oracle_run.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_int32, P, P,
                                    ctypes.c_double, ctypes.c_double, ctypes.c_int32,
-                                   P, P, P, P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32]
+                                   P, P, P, P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32,
+                                   P, P]
         lib.oracle_run.restype = ctypes.c_int
+        lib.oracle_memb_coeffs.argtypes = [ctypes.c_double] * 3 + [P]
+        lib.oracle_memb_coeffs.restype = None
         lib.oracle_tau.argtypes = [ctypes.c_double] * 3
         lib.oracle_tau.restype = ctypes.c_double
         _lib = lib
@@ -63,7 +66,7 @@ def _ptr(a):
 
 
 def _run_core(comp, comp_phase, n_phase, bc, off, dx, dt, D, T2, kappa, f, gG0,
-              elo, ehi, threads, want_M, scheme=0):
+              elo, ehi, threads, want_M, scheme=0, link_delta=None, tile=None):
     lib = _load()
     comp = np.ascontiguousarray(comp, dtype=np.uint32)
     n2, n1, n0 = comp.shape
@@ -81,10 +84,17 @@ def _run_core(comp, comp_phase, n_phase, bc, off, dx, dt, D, T2, kappa, f, gG0,
     K = len(f)
     E = np.zeros(2 * (K + 1), np.float64)
     M = np.zeros(2 * comp.size, np.float64) if want_M else None
+    if link_delta is not None:
+        link_delta = np.ascontiguousarray(link_delta, dtype=np.float64)
+        if link_delta.shape != (3,) + comp.shape:
+            raise ValueError("link_delta must have shape (3, n2, n1, n0)")
+    tile = None if tile is None else np.ascontiguousarray(tile, dtype=np.int32)
     rc = lib.oracle_run(_ptr(n), _ptr(comp), _ptr(cp), len(cp), int(n_phase), _ptr(bc),
                         _ptr(off), float(dx), float(dt), K, _ptr(D), _ptr(T2),
                         _ptr(kappa), _ptr(f), _ptr(gG0), _ptr(elo), _ptr(ehi),
-                        _ptr(E), _ptr(M) if want_M else None, int(threads), int(scheme))
+                        _ptr(E), _ptr(M) if want_M else None, int(threads), int(scheme),
+                        _ptr(link_delta) if link_delta is not None else None,
+                        _ptr(tile) if tile is not None else None)
     if rc == -2:
         raise NotImplementedError("oblique gradient on a mirrored axis")
     if rc != 0:
@@ -92,6 +102,15 @@ def _run_core(comp, comp_phase, n_phase, bc, off, dx, dt, D, T2, kappa, f, gG0,
     Ec = E[0::2] + 1j * E[1::2]
     Mc = (M[0::2] + 1j * M[1::2]).reshape(comp.shape) if want_M else None
     return Ec, Mc
+
+
+def memb_coeffs(delta: float, kappa_dt: float, epsd_dx: float) -> np.ndarray:
+    """{A_1, A_2, A_3, B_1, B_2, B_3} of the theta = 0 membrane condition
+    (Eqs. B4a-B4c) for a membrane at `delta` (units of dx) from the
+    receiving node."""
+    out = np.zeros(6)
+    _load().oracle_memb_coeffs(float(delta), float(kappa_dt), float(epsd_dx), _ptr(out))
+    return out
 
 
 def tau(D: float, dt: float, dx: float) -> float:
@@ -114,7 +133,7 @@ HYBRID, CLASSICAL = 0, 1
 
 def simulate(comp, comp_phase, n_phase, bc, dx, dt, D, T2, kappa, f, gG0,
              threads: int = 1, mirror: str = "auto", want_M: bool = True,
-             scheme: int = HYBRID):
+             scheme: int = HYBRID, link_delta=None):
     """Run the scheme for one gradient vector.
 
     comp (n2, n1, n0) compartment ids, comp_phase [C], bc[3] (0 periodic,
@@ -126,6 +145,9 @@ def simulate(comp, comp_phase, n_phase, bc, dx, dt, D, T2, kappa, f, gG0,
     the collision, Eq. A12).  The conjugate mirror rule relies on an exact
     symmetry of the split reaction; with the classical scheme a mirrored
     axis with a gradient component always runs on the doubled domain.
+    link_delta: None (half-link membranes at mid-link) or (3, n2, n1, n0)
+    membrane positions along the +x, +y, +z links from each node (units of
+    dx) for the general theta = 0 membrane condition (oracle.c).
     Returns E [K+1] complex and M at t_K, complex (n2, n1, n0).
     """
     comp = np.asarray(comp)
@@ -137,29 +159,48 @@ def simulate(comp, comp_phase, n_phase, bc, dx, dt, D, T2, kappa, f, gG0,
         mirror = "double" if (needs_doubling(bc, gG0) or classical_mirror) else "paper"
     if mirror == "paper" or MIRROR not in bc:
         n2, n1, n0 = comp.shape
+        ld = None if link_delta is None else np.asarray(link_delta, np.float32)
         return _run_core(comp, comp_phase, n_phase, bc, [0.0, 0.0, 0.0], dx, dt,
                          D, T2, kappa, f, gG0, [0, 0, 0], [n0, n1, n2], threads, want_M,
-                         scheme)
+                         scheme, ld)
     if mirror != "double":
         raise ValueError("mirror must be 'auto', 'paper' or 'double'")
     # reflect the REV across the lower face of every mirrored axis: the
     # extended axis holds the mirror image at coordinates -N..-1 and the REV
     # at 0..N-1, and the doubled medium is tiled periodically
     ext = comp
+    # positions are single precision on input (as the HIP library stores
+    # them); complements 1 - d of the reflected copies are exact in FP64
+    ld = None if link_delta is None else np.asarray(link_delta, np.float32).astype(np.float64)
     off = [0.0, 0.0, 0.0]
     lo = [0, 0, 0]
     hi = list(comp.shape[::-1])
+    tile = list(comp.shape[::-1])
     for a in range(3):
         if bc[a] != MIRROR:
             continue
         ax = 2 - a                   # numpy axis of lattice axis a
         na = comp.shape[ax]
         ext = np.concatenate([np.flip(ext, axis=ax), ext], axis=ax)
+        if ld is not None:
+            # the image holds node n-1-k at k; its link k -> k+1 is the
+            # original link n-2-k -> n-1-k seen from the other end
+            img = np.flip(ld, axis=ax + 1).copy()
+            sl = [slice(None)] * 4
+            sl[0] = a
+            sl[ax + 1] = slice(0, na - 1)
+            src = [slice(None)] * 4
+            src[0] = a
+            src[ax + 1] = slice(1, na)
+            img[tuple(sl)] = 1.0 - np.flip(ld, axis=ax + 1)[tuple(src)]
+            sl[ax + 1] = slice(na - 1, na)
+            img[tuple(sl)] = 0.5     # image of node 0 -> node 0: no membrane
+            ld = np.concatenate([img, ld], axis=ax + 1)
         off[a] = -float(na)
         lo[a], hi[a] = na, 2 * na
     bce = [PERIODIC] * 3
     E, M = _run_core(ext, comp_phase, n_phase, bce, off, dx, dt, D, T2, kappa, f,
-                     gG0, lo, hi, threads, want_M, scheme)
+                     gG0, lo, hi, threads, want_M, scheme, ld, tile)
     if want_M:
         M = M[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].copy()
     return E, M

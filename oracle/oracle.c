@@ -28,6 +28,19 @@
  *   R(x, t^k) = -i gamma (x.G0) f(t^k) - 1/T2,
  * and the boundary and membrane rules are unchanged.
  *
+ * With link positions given (link_delta != NULL) a membrane link uses the
+ * theta = 0 form of the general membrane condition for a membrane at any
+ * distance Delta_m along the link (Eqs. B2a_text/B2b_text with the
+ * coefficients of Eqs. B4a-B4c and the Dirichlet/Neumann coefficients of
+ * Eqs. c_n, c_d): for the population g'_i arriving at x across the link from
+ * x - e_i, with ibar the opposite direction and Delta the distance from x to
+ * the membrane,
+ *   g'_i(x) = A_1 ghat_ibar(x) + A_2 ghat_ibar(x + e_i) + A_3 ghat_i(x)
+ *           + B_1 ghat_i(x - e_i) + B_2 ghat_i(x - 2e_i) + B_3 ghat_ibar(x - e_i).
+ * The two second nodes must belong to the compartments of their sides and,
+ * with x - e_i, lie in the same tile of the lattice as x (no outer face in
+ * the stencil); otherwise the link falls back to the half-link rule.
+ *
  * Lattice: D3Q7 with eps_D = 1/4, w_0 = 1/4, w_{+-x,+-y,+-z} = 1/8.  The
  * paper leaves the 3D weights implicit; eps_D = 1/4 is what its Fig. 11
  * caption requires (tau = 0.58 at D = 2, dt = 0.01, dx = 1), and the weights
@@ -83,6 +96,41 @@ static int reflect_dir(int i, int a) {
     return ax == a ? OPP[i] : i;
 }
 
+/*
+ * Coefficients A_1..A_3, B_1..B_3 of the general membrane condition for a
+ * straight membrane normal to the link (theta = 0, Eqs. B4a, B4c) at
+ * distance d (units of dx) from the receiving node; the other side's node is
+ * at 1 - d.  Own-side Dirichlet/Neumann coefficients c_dj, c_nj (Eqs. c_d,
+ * c_n) use d, the other side's (starred) use 1 - d.  kdt = kappa dt,
+ * edx = eps_D dx.
+ */
+static void memb_coeffs(double d, double kdt, double edx, double A[3], double B[3]) {
+    double cn[4], cd[4], cns[4], cds[4];
+    for (int side = 0; side < 2; ++side) {
+        const double D = side == 0 ? d : 1.0 - d;
+        double *n_ = side == 0 ? cn : cns, *d_ = side == 0 ? cd : cds;
+        const double h = 2.0 * D - 1.0, q = 2.0 * D + 1.0;
+        n_[0] = 1.0;
+        n_[1] = -h / q;
+        n_[2] = h / q;
+        n_[3] = 2.0 / q;
+        d_[0] = 2.0 * (D - 1.0);
+        d_[1] = -h * h / q;
+        d_[2] = 2.0 * h / q;
+        d_[3] = (3.0 - 2.0 * D) / q;
+    }
+    const double F = cd[3] * cds[3] * edx + (cd[3] * cns[3] + cn[3] * cds[3]) * kdt;
+    for (int j = 0; j < 3; ++j) {
+        A[j] = (cd[3] * cds[3] * cn[j] * edx + (cds[3] * cn[3] * cd[j] + cns[3] * cd[3] * cn[j]) * kdt) / F;
+        B[j] = cd[3] * cn[3] * (cns[j] - cds[j]) * kdt / F;
+    }
+}
+
+/* the coefficients above, for tests: out = {A_1, A_2, A_3, B_1, B_2, B_3} */
+void oracle_memb_coeffs(double d, double kappa_dt, double epsd_dx, double *out) {
+    memb_coeffs(d, kappa_dt, epsd_dx, out, out + 3);
+}
+
 /* pairwise sum of n complex values: rounding error O(log n) */
 static cplx pairwise_sum(const cplx *v, long n) {
     if (n <= 8) {
@@ -105,6 +153,10 @@ static cplx pairwise_sum(const cplx *v, long n) {
  * kappa       [n_phase * n_phase] symmetric, um/ms; +inf = no membrane
  * f           [K] waveform samples, gG0[3] = gamma * G0 in rad/(um ms)
  * elo, ehi    the box [elo, ehi) over which the signal is averaged
+ * link_delta  [3][n2][n1][n0] or NULL: for axis a, the distance (units of
+ *             dx) from node j to the membrane on the link j -> j + e_a,
+ *             0 < value < 1; read only on links joining two compartments
+ * tile[3]     stencil tiles of the general membrane rule (NULL: whole axes)
  * E           out [K+1] complex (interleaved re, im)
  * M_out       out [n2][n1][n0] complex or NULL
  * returns 0, or -1 for invalid input, -2 for an unsupported case, -3 OOM
@@ -115,7 +167,7 @@ int oracle_run(const int32_t n[3], const uint32_t *comp, const uint8_t *comp_pha
                const double *D, const double *T2, const double *kappa,
                const double *f, const double gG0[3], const int32_t elo[3],
                const int32_t ehi[3], double *E, double *M_out, int32_t nthreads,
-               int32_t scheme) {
+               int32_t scheme, const double *link_delta, const int32_t *tile) {
     const long n0 = n[0], n1 = n[1], n2 = n[2];
     if (n0 < 1 || n1 < 1 || n2 < 1 || dx <= 0 || dt <= 0 || K < 0) return -1;
     if (scheme != 0 && scheme != 1) return -1;
@@ -142,6 +194,20 @@ int oracle_run(const int32_t n[3], const uint32_t *comp, const uint8_t *comp_pha
         if (!(D[p] > 0) || !(T2[p] > 0)) return -1;
     for (int p = 0; p < n_phase * n_phase; ++p)
         if (!(kappa[p] >= 0)) return -1;
+    long tl[3];
+    for (int a = 0; a < 3; ++a) {
+        tl[a] = tile ? tile[a] : n[a];
+        if (tl[a] < 1 || n[a] % tl[a] != 0) return -1;
+    }
+    if (link_delta) /* every value the rule can read: links joining two compartments */
+        for (int a = 0; a < 3; ++a)
+            for (long s = 0; s < N; ++s) {
+                long j[3] = {s % n0, (s / n0) % n1, s / (n0 * n1)};
+                if (++j[a] == n[a]) j[a] = 0;
+                if (comp[s] != comp[j[0] + n0 * (j[1] + n1 * j[2])] &&
+                    !(link_delta[a * N + s] > 0.0 && link_delta[a * N + s] < 1.0))
+                    return -1;
+            }
 
     /* per-phase constants: tau (Eq. tau_def), T2 decay (Eq. reaction_LBM) */
     double *tau = malloc(sizeof(double) * n_phase);
@@ -310,7 +376,40 @@ int oracle_run(const int32_t n[3], const uint32_t *comp, const uint8_t *comp_pha
                         }
                         cplx gp;
                         const int pair = px * n_phase + comp_phase[cs];
-                        if (cs != cx && has_mem[pair]) {
+                        int general = 0;
+                        if (link_delta && cs != cx && has_mem[pair] && crossed < 0) {
+                            /* stencil x - 2e_i .. x + e_i along axis ax, in x's tile */
+                            const int ax = (i - 1) / 2, sg = EX[i][ax];
+                            const long j = jj[ax], t0 = j / tl[ax] * tl[ax];
+                            const long jm2 = j - 2 * sg, jp1 = j + sg;
+                            if (jm2 >= t0 && jm2 < t0 + tl[ax] && jp1 >= t0 && jp1 < t0 + tl[ax] &&
+                                src[ax] >= t0 && src[ax] < t0 + tl[ax]) {
+                                long a2[3] = {j0, j1, j2}, a1[3] = {j0, j1, j2};
+                                a2[ax] = jm2;
+                                a1[ax] = jp1;
+                                const long s2 = IDX(a2[0], a2[1], a2[2]);
+                                const long s1 = IDX(a1[0], a1[1], a1[2]);
+                                if (comp[s1] == cx && comp[s2] == cs) {
+                                    /* distance from x to the membrane: the link
+                                       value is measured from its lower node */
+                                    const long lower = sg > 0 ? IDX(src[0], src[1], src[2]) : s;
+                                    const double dl = link_delta[ax * N + lower];
+                                    const double d = sg > 0 ? 1.0 - dl : dl;
+                                    double A[3], B[3];
+                                    memb_coeffs(d, kappa[pair] * dt, EPS_D * dx, A, B);
+                                    const int ib = OPP[i];
+                                    gp = A[0] * gh[ib * PN + PIDX(j0, j1, j2)]
+                                       + A[1] * gh[ib * PN + PIDX(a1[0], a1[1], a1[2])]
+                                       + A[2] * gh[i * PN + PIDX(j0, j1, j2)]
+                                       + B[0] * gin
+                                       + B[1] * gh[i * PN + PIDX(a2[0], a2[1], a2[2])]
+                                       + B[2] * gh[ib * PN + PIDX(src[0], src[1], src[2])];
+                                    general = 1;
+                                }
+                            }
+                        }
+                        if (general) {
+                        } else if (cs != cx && has_mem[pair]) {
                             /* half-link membrane: transmitted share of the
                                incoming population plus reflected share of the
                                outgoing one at this node */

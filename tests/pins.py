@@ -193,3 +193,76 @@ def dense_run(mats, N):
         if k < len(mats):
             v = mats[k] @ v
     return np.array(out)
+
+
+def step_average_pgse(delta, Delta, dt, K):
+    """Per-step averages of the PGSE effective waveform (+1 on [0, delta),
+    -1 on [Delta, Delta + delta)) over [k dt, (k+1) dt)."""
+    t0 = np.arange(K) * dt
+    t1 = t0 + dt
+
+    def cover(a, b):
+        return np.clip(np.minimum(t1, b) - np.maximum(t0, a), 0.0, None) / dt
+
+    # rounded so that fully covered steps are exactly +-1 and runs of equal
+    # values can share one exponential in `slab_fv_reference`
+    return np.round(cover(0.0, delta) - cover(Delta, Delta + delta), 12)
+
+
+def slab_fv_reference(x_if, D, T2, kappa_if, gG, f, dt, x_eval, cells):
+    """Bloch-Torrey solution M(x_eval, K dt) in 1D, M(x, 0) = 1, by finite
+    volumes and exact matrix exponentials (an independent discretisation).
+
+    Compartment c spans [x_if[c], x_if[c+1]] with diffusivity D[c] and
+    relaxation T2[c]; the two outer ends are impermeable, interior interface
+    c+1 has permeability kappa_if[c] (flux kappa (M_right - M_left)).  The
+    gradient term is -i gG x f(t) M with f constant on each step.  `cells`
+    cells per compartment; second order in the cell width.
+    """
+    import scipy.linalg as sla
+
+    nc = len(D)
+    xs, hs, cid = [], [], []
+    for c in range(nc):
+        h = (x_if[c + 1] - x_if[c]) / cells
+        xs.append(x_if[c] + h * (np.arange(cells) + 0.5))
+        hs.append(np.full(cells, h))
+        cid.append(np.full(cells, c))
+    xs, hs, cid = np.concatenate(xs), np.concatenate(hs), np.concatenate(cid)
+    n = len(xs)
+    Ldiff = np.zeros((n, n))
+    for k in range(n - 1):
+        cl, cr = cid[k], cid[k + 1]
+        if cl == cr:
+            cond = D[cl] / hs[k]                       # h equal within a compartment
+        else:
+            kap = kappa_if[cl]
+            if kap == 0.0:
+                continue
+            cond = 1.0 / (hs[k] / (2 * D[cl]) + 1.0 / kap + hs[k + 1] / (2 * D[cr]))
+        Ldiff[k, k] -= cond / hs[k]
+        Ldiff[k, k + 1] += cond / hs[k]
+        Ldiff[k + 1, k + 1] -= cond / hs[k + 1]
+        Ldiff[k + 1, k] += cond / hs[k + 1]
+    relax = np.array([0.0 if math.isinf(T2[c]) else 1.0 / T2[c] for c in cid])
+    M = np.ones(n, np.complex128)
+    # runs of equal waveform values share one exponential
+    k = 0
+    f = np.asarray(f, np.float64)
+    while k < len(f):
+        e = k
+        while e < len(f) and f[e] == f[k]:
+            e += 1
+        A = Ldiff - np.diag(relax) - 1j * gG * f[k] * np.diag(xs)
+        M = sla.expm(A * ((e - k) * dt)) @ M
+        k = e
+    # linear interpolation between cell centres of the same compartment
+    out = np.zeros(len(x_eval), np.complex128)
+    for t, x in enumerate(x_eval):
+        c = int(np.searchsorted(x_if, x, side="right") - 1)
+        idx = np.nonzero(cid == c)[0]
+        xc = xs[idx]
+        j = int(np.clip(np.searchsorted(xc, x) - 1, 0, len(xc) - 2))
+        w_ = (x - xc[j]) / (xc[j + 1] - xc[j])
+        out[t] = (1 - w_) * M[idx[j]] + w_ * M[idx[j + 1]]
+    return out

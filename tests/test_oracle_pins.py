@@ -369,3 +369,136 @@ def test_hybrid_error_independent_of_domain_size_classical_not():
     assert abs(err[(20, 0)] - err[(100, 0)]) < 1e-12 and err[(20, 0)] < 1e-3
     assert err[(20, 1)] > 10 * err[(20, 0)]
     assert err[(100, 1)] > 10 * err[(20, 1)]
+
+
+# ---- general membrane condition with sub-link positions (theta = 0) -------
+
+EPSD = 0.25
+
+
+@pytest.mark.parametrize("kappa", [0.0, 0.004, 0.05, 0.7, 20.0])
+def test_memb_coeffs_reduce_to_half_link(kappa):
+    # Eq. B5: at Delta_m = 1/2 only A_1 = P/(1+P) and B_1 = 1/(1+P) survive
+    dx, dt = 0.3, 0.002
+    c = oracle.memb_coeffs(0.5, kappa * dt, EPSD * dx)
+    if kappa == 0.0:
+        ref = [1.0, 0, 0, 0, 0, 0]
+    else:
+        P = EPSD * dx / (2 * kappa * dt)
+        ref = [P / (1 + P), 0, 0, 1 / (1 + P), 0, 0]
+    assert np.max(np.abs(c - ref)) < 1e-15
+
+
+def test_memb_coeffs_impermeable_is_interpolated_bounce_back():
+    # kappa = 0: zero normal flux, the Neumann condition of Eq. c_n alone
+    for d in (0.05, 0.3, 0.5, 0.77, 0.99):
+        c = oracle.memb_coeffs(d, 0.0, EPSD * 0.5)
+        r = (2 * d - 1) / (2 * d + 1)
+        assert np.max(np.abs(c - [1.0, -r, r, 0, 0, 0])) < 1e-15
+
+
+def test_memb_coeffs_keep_uniform_states():
+    # a uniform equilibrium (all populations w M) must stream unchanged
+    # across any membrane: the six coefficients sum to one for every
+    # Delta_m and kappa (Dirichlet consistency sum c_dj = 1 - 2 c_d4 and
+    # sum c_nj = 1 carry through Eqs. B4a-B4c)
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        d = rng.uniform(1e-4, 1 - 1e-4)
+        kdt = 10 ** rng.uniform(-6, 1)
+        c = oracle.memb_coeffs(d, kdt, EPSD * rng.uniform(0.05, 2.0))
+        assert abs(c.sum() - 1.0) < 1e-13
+
+
+def _cyl_with_delta(bc_periodic=True):
+    g = w.cylinders_z((12, 11, 4), 0.25, seed=61, vf_target=0.5, periodic=bc_periodic)
+    return g, w.link_delta(g)
+
+
+def test_general_membrane_at_mid_link_equals_half_link():
+    g, _ = _cyl_with_delta()
+    ld = np.full((3,) + g.comp.shape, 0.5, np.float32)
+    f = w.pgse_waveform(0.3, 0.9, 0.004)
+    args = (g.comp, g.comp_phase, 2, [0, 0, 0], 0.25, 0.004, [2.0, 1.0], [90.0, 70.0],
+            [[INF, 0.03], [0.03, INF]], f, [3.0, -2.0, 1.0])
+    E0, M0 = _run(*args)
+    E1, M1 = _run(*args, link_delta=ld)
+    assert np.max(np.abs(E1 - E0)) < 1e-14
+    assert np.max(np.abs(M1 - M0)) < 1e-14
+
+
+@pytest.mark.parametrize("bc", [[0, 0, 0], [1, 1, 1]])
+def test_general_membrane_uniform_decay(bc):
+    # G = 0 and one T2: the uniform state only decays, E_k = exp(-k dt/T2),
+    # whatever the membrane positions
+    g, ld = _cyl_with_delta(bc[0] == 0)
+    f = np.zeros(80)
+    E, _ = _run(g.comp, g.comp_phase, 2, bc, 0.25, 0.004, [2.0, 1.0], [40.0, 40.0],
+                [[INF, 0.02], [0.02, INF]], f, [0, 0, 0], link_delta=ld)
+    k = np.arange(81)
+    assert np.max(np.abs(E - np.exp(-k * 0.004 / 40.0))) < 1e-13
+
+
+def test_general_membrane_mirror_rule_equals_doubling():
+    # axis-aligned gradient on mirrored faces: the paper's buffer rule and the
+    # reflected, doubled medium (with the reflected membrane positions) agree
+    g, ld = _cyl_with_delta(False)
+    f = w.pgse_waveform(0.3, 0.9, 0.004)
+    args = (g.comp, g.comp_phase, 2, [1, 1, 1], 0.25, 0.004, [2.0, 1.0], [90.0, 70.0],
+            [[INF, 0.03], [0.03, INF]], f, [0.0, 4.0, 0.0])
+    Ep, _ = _run(*args, mirror="paper", link_delta=ld)
+    Ed, _ = _run(*args, mirror="double", link_delta=ld)
+    assert np.max(np.abs(Ep - Ed)) < 1e-13
+
+
+_SLAB_X, _SLAB_ALPHA = 2.0, 0.3
+_SLAB_D, _SLAB_T2, _SLAB_G = [1.5, 1.0, 2.0], [60.0, 50.0, 80.0], 0.25
+_slab_refs = {}
+
+
+def _slab_case(m, general, kappa=0.05):
+    # 1D: outer compartment C, permeable pair A | B on [X, 3X] walled off from
+    # C by impermeable membranes; interfaces at X, 2X, 3X and spacing
+    # dx = X/(m + alpha), so every refinement sees the same sub-link
+    # positions frac(c alpha) = 0.3, 0.6, 0.9
+    X = _SLAB_X
+    dx = X / (m + _SLAB_ALPHA)
+    n = int(math.floor(3 * (m + _SLAB_ALPHA))) + 5
+    x = np.arange(n) * dx
+    comp = np.where(x < X, 0, np.where(x < 2 * X, 1, np.where(x < 3 * X, 2, 0)))
+    dt = 0.3 * EPSD * dx * dx / _SLAB_D[1]
+    K = int(math.ceil(8.0 / dt))
+    f = pins.step_average_pgse(2.0, 6.0, dt, K)
+    kap = [[INF, 0.0, 0.0], [0.0, INF, kappa], [0.0, kappa, INF]]
+    ld = np.full((3, 1, 1, n), 0.5, np.float32)
+    for c in (1, 2, 3):
+        j = int(math.floor(c * X / dx))
+        ld[0, 0, 0, j] = (c * X - j * dx) / dx
+    _, M = _run(comp.reshape(1, 1, n), [0, 1, 2], 3, [0, 0, 0], dx, dt, _SLAB_D, _SLAB_T2,
+                kap, f, [_SLAB_G, 0, 0], link_delta=ld if general else None)
+    inside = (x > X) & (x < 3 * X)
+    key = (m, kappa)
+    if key not in _slab_refs:
+        r = [pins.slab_fv_reference([X, 2 * X, 3 * X], _SLAB_D[1:], _SLAB_T2[1:], [kappa],
+                                    _SLAB_G, f, dt, x[inside], cells) for cells in (40, 80)]
+        _slab_refs[key] = (4 * r[1] - r[0]) / 3          # Richardson, O(h^4)
+    ref = _slab_refs[key]
+    return dx, np.linalg.norm(M.reshape(-1)[inside] - ref) / np.linalg.norm(ref)
+
+
+def test_general_membrane_second_order_off_lattice():
+    # Sec. 2.4.2 / App. B: with the membrane position on the link the
+    # condition is second order in dx against an independent finite-volume
+    # solution of the same Bloch-Torrey problem (permeable membrane between
+    # media of different D and T2, impermeable walls); the half-link rule,
+    # which moves every membrane to mid-link, is only first order there
+    res = {g: [_slab_case(m, g) for m in (4, 9, 19)] for g in (True, False)}
+    for g, r in res.items():
+        o = [math.log(r[i][1] / r[i + 1][1]) / math.log(r[i][0] / r[i + 1][0])
+             for i in range(2)]
+        print("general" if g else "half-link", [f"{e:.3e}" for _, e in r], o)
+        if g:
+            assert all(1.8 < v < 2.2 for v in o), o
+        else:
+            assert all(0.8 < v < 1.3 for v in o), o
+    assert res[False][-1][1] > 5 * res[True][-1][1]

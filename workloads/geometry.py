@@ -189,6 +189,11 @@ def cylinders_z(n, dx: float, seed: int, vf_target: float = 0.6,
     g = Geometry(comp, comp_phase, 2, float(dx),
                  {"kind": "cylinders_z", "seed": seed, "n_cyl": int(len(radii)),
                   "vf_target": vf_target, "periodic": periodic})
+    # analytic surfaces: (x-c)^T A (x-c) < 1 inside, A_zz = 0 for a z-cylinder
+    g.info["shapes"] = {"periodic": (periodic, periodic, False),
+                        "items": [(int(cid), np.array([cx, cy, 0.0]),
+                                   np.diag([1.0 / (r * r), 1.0 / (r * r), 0.0]))
+                                  for (cx, cy), r, cid in zip(pos, radii, ids)]}
     g.info["vf_voxel"] = float(g.phase_fractions()[1])
     return g
 
@@ -242,6 +247,10 @@ def cylinders_spheres(n, dx: float, seed: int, vf_cyl: float = 0.4,
     g = Geometry(comp, comp_phase, 3, float(dx),
                  {"kind": "cylinders_spheres", "seed": seed,
                   "n_cyl": base.info["n_cyl"], "n_sph": len(placed)})
+    g.info["shapes"] = {"periodic": (True, True, True),
+                        "items": list(base.info["shapes"]["items"])
+                        + [(nc + s, c.copy(), np.eye(3) / (r * r))
+                           for s, (c, r) in enumerate(placed)]}
     fr = g.phase_fractions()
     g.info["vf_voxel"] = [float(v) for v in fr]
     return g
@@ -274,6 +283,7 @@ def ellipsoid_cells(n, dx: float, seed: int, vf_target: float = 0.5,
     filled = 0
     ncell = 0
     tries = 0
+    shapes = []
     while filled < target and tries < max_tries:
         tries += 1
         ax = rng.uniform(semi[0], semi[1], 3)
@@ -315,11 +325,84 @@ def ellipsoid_cells(n, dx: float, seed: int, vf_target: float = 0.5,
         o |= dil
         occ[sub] = o
         filled += int(inside.sum())
+        shapes.append((2 * ncell + 1, c.copy(), A))
+        shapes.append((2 * ncell + 2, c.copy(), 4.0 * A))
         ncell += 1
     comp_phase = np.zeros(2 * ncell + 1, np.uint8)
     comp_phase[1::2] = 1
     comp_phase[2::2] = 2
     g = Geometry(comp, comp_phase, 3, float(dx),
-                 {"kind": "ellipsoid_cells", "seed": seed, "n_cell": ncell})
+                 {"kind": "ellipsoid_cells", "seed": seed, "n_cell": ncell,
+                  "shapes": {"periodic": (True, True, True), "items": shapes}})
     g.info["vf_voxel"] = [float(v) for v in g.phase_fractions()]
     return g
+
+
+def link_delta(g: Geometry) -> np.ndarray:
+    """Where each membrane cuts its lattice link, from the analytic surfaces
+    the geometry was rasterised from.
+
+    Returns float32 (3, n2, n1, n0): entry [a, j2, j1, j0] is the distance,
+    in units of dx, from node j to the surface on the link j -> j + e_a (the
+    last node of a periodic axis links to node 0).  Links that join two
+    compartments get the crossing of the surface that has exactly one of the
+    two nodes inside (clamped to [1e-4, 1 - 1e-4]); every other entry, and
+    every entry of a geometry without analytic surfaces, is 0.5 (the
+    mid-link position).
+    """
+    n2, n1, n0 = g.comp.shape
+    dims = (n0, n1, n2)
+    out = np.full((3, n2, n1, n0), 0.5, np.float32)
+    shp = g.info.get("shapes")
+    if not shp:
+        return out
+    dx = g.dx
+    L = np.array(dims, np.float64) * dx
+    per = np.array(shp["periodic"], bool)
+    items = shp["items"]
+    ncomp = len(g.comp_phase)
+    shape_of = np.full(ncomp, -1, np.int64)
+    for k, (cid, _, _) in enumerate(items):
+        shape_of[cid] = k
+    C = np.array([it[1] for it in items], np.float64).reshape(-1, 3)
+    A = np.array([it[2] for it in items], np.float64).reshape(-1, 3, 3)
+    for a in range(3):
+        nb = np.roll(g.comp, -1, axis=2 - a)             # comp of node j + e_a
+        link = g.comp != nb
+        if not per[a]:
+            # the link beyond the last node is not a lattice link
+            sl = [slice(None)] * 3
+            sl[2 - a] = slice(dims[a] - 1, dims[a])
+            link[tuple(sl)] = False
+        z, y, x = np.nonzero(link)
+        if len(x) == 0:
+            continue
+        p0 = np.stack([x, y, z], axis=1) * dx
+        best = np.full(len(x), 0.5)
+        found = np.zeros(len(x), bool)
+        for side in (g.comp[z, y, x], nb[z, y, x]):
+            k = shape_of[side]
+            ok = k >= 0
+            if not ok.any():
+                continue
+            kk = k[ok]
+            c = C[kk]
+            d = p0[ok] - c
+            d = np.where(per[None, :], d - L * np.round(d / L), d)   # nearest image
+            Ak = A[kk]
+            Ad = np.einsum("nij,nj->ni", Ak, d)
+            qa = dx * dx * Ak[:, a, a]
+            qb = 2.0 * dx * Ad[:, a]
+            qc = np.einsum("ni,ni->n", d, Ad) - 1.0
+            q1 = qa + qb + qc
+            in0, in1 = qc < 0.0, q1 < 0.0
+            one = (in0 != in1) & (qa > 0.0)
+            disc = np.sqrt(np.maximum(qb * qb - 4.0 * qa * qc, 0.0))
+            with np.errstate(divide="ignore", invalid="ignore"):
+                t = np.where(in0, (-qb + disc) / (2.0 * qa), (-qb - disc) / (2.0 * qa))
+            use = one & ~found[ok]
+            idx = np.nonzero(ok)[0][use]
+            best[idx] = t[use]
+            found[idx] = True
+        out[a, z, y, x] = np.clip(best, 1e-4, 1.0 - 1e-4).astype(np.float32)
+    return out
