@@ -55,9 +55,9 @@ WORKLOAD_NAMES = {
 }
 
 
-def workload(name: str, K: int):
+def workload(name: str, K: int, membranes: str = "half-link"):
     import workloads as w
-    cfg = w.make_config(name)
+    cfg = w.make_config(name, membranes=membranes)
     f = cfg["f"]
     if K > len(f):
         f = np.resize(f, K)
@@ -197,6 +197,9 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--membranes", default="half-link", choices=["half-link", "positions"],
+                    help="positions: exact membrane positions on the links and the "
+                         "general membrane condition (no adjoint)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -233,7 +236,10 @@ def main():
 
     K, W = args.steps, args.warmup
     log(f"building workload {args.workload}")
-    cfg = workload(args.workload, max(K, W, 0 if args.no_adjoint else args.adj_steps))
+    if args.membranes == "positions":
+        args.no_adjoint = True
+    cfg = workload(args.workload, max(K, W, 0 if args.no_adjoint else args.adj_steps),
+                   args.membranes)
     Q = len(cfg["gG0"])
     qs = q_sites(cfg)
     fs = field_sites(cfg)
@@ -258,7 +264,8 @@ def main():
     achieved = bytes_launch / (ms_step * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic_for(ms_step) if args.workload == "cfg2" and args.prec == "f32" else None,
+            "traffic": (traffic_for(ms_step) if args.workload == "cfg2" and args.prec == "f32"
+                        and args.membranes == "half-link" else None),
             "kernel": f"k_step<{'float2' if args.prec == 'f32' else 'double2'}>",
             "bytes_per_launch_algorithmic": bytes_launch}
     out = {"metric": METRIC, "value": value, "unit": "site-updates/s", "n_gpus": 1,
@@ -267,7 +274,8 @@ def main():
            "config": {"workload": f"{WORKLOAD_NAMES[args.workload]} ({args.workload})",
                       "q_sites": qs, "q_samples": Q, "field_sites": fs,
                       "geometries": len(cfg["geoms"]),
-                      "storage": args.prec, "steps_per_forward": K},
+                      "storage": args.prec, "steps_per_forward": K,
+                      "membranes": args.membranes},
            "roofline": roof}
     if not args.no_extras:
         log("FP64 comparison runs")

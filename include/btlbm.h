@@ -78,7 +78,25 @@ typedef struct {
     const uint32_t *comp_id;    /* host [n2][n1][n0], values < C */
     const uint8_t *comp_phase;  /* host [C], values < n_phase */
     int32_t n_phase;            /* number of material phases P, 1..8 */
+    const float *link_delta;    /* host [3][n2][n1][n0] or NULL: where each
+                                 * membrane cuts its link (see below) */
 } btl_geom;
+
+/* link_delta: entry [a][j] is the distance, in units of dx, from node j to
+ * the membrane on the link j -> j + e_a (the last node of a periodic axis
+ * links to node 0); it must lie in (0, 1) on every link that joins two
+ * compartments and is not read elsewhere.  With it, a membrane link whose
+ * stencil x - 2e_i .. x + e_i (i the direction entering x) lies inside the
+ * lattice, with x + e_i in x's compartment and x - 2e_i in the other one,
+ * takes the general membrane condition for a straight membrane normal to
+ * the link at that position (Sec. 2.4.2, Eqs. B2a_text/B2b_text with the
+ * theta = 0 coefficients of Eqs. B4a-B4c and the Dirichlet/Neumann
+ * coefficients of Eqs. c_d, c_n):
+ *   g'_i(x) = A_1 ghat_ibar(x) + A_2 ghat_ibar(x + e_i) + A_3 ghat_i(x)
+ *           + B_1 ghat_i(x - e_i) + B_2 ghat_i(x - 2e_i) + B_3 ghat_ibar(x - e_i);
+ * every other membrane link, and every link when link_delta is NULL, uses
+ * the half-link form (Eqs. B5, permeability_BC: the membrane at mid-link).
+ * btl_backward does not support simulators whose forward used link_delta. */
 
 /* Create a simulator for n_geom geometries (all with the same dx and
  * n_phase; sizes may differ: q-samples of all geometries run in one batch).

@@ -216,7 +216,8 @@ def simulate_config(cfg: dict, q=None, threads: int = 1, mirror: str = "auto",
         E, M = simulate(g.comp, g.comp_phase, g.n_phase, cfg["bc"], cfg["dx"], cfg["dt"],
                         cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"][i],
                         threads=threads, mirror=mirror, want_M=want_M,
-                        scheme=cfg.get("scheme", HYBRID) if scheme is None else scheme)
+                        scheme=cfg.get("scheme", HYBRID) if scheme is None else scheme,
+                        link_delta=getattr(g, "link_delta", None))
         Es.append(E)
         Ms.append(M)
     return np.array(Es), Ms

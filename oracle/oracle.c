@@ -203,7 +203,10 @@ int oracle_run(const int32_t n[3], const uint32_t *comp, const uint8_t *comp_pha
         for (int a = 0; a < 3; ++a)
             for (long s = 0; s < N; ++s) {
                 long j[3] = {s % n0, (s / n0) % n1, s / (n0 * n1)};
-                if (++j[a] == n[a]) j[a] = 0;
+                if (++j[a] == n[a]) {
+                    if (bc[a] == BC_MIRROR) continue;  /* not a lattice link */
+                    j[a] = 0;
+                }
                 if (comp[s] != comp[j[0] + n0 * (j[1] + n1 * j[2])] &&
                     !(link_delta[a * N + s] > 0.0 && link_delta[a * N + s] < 1.0))
                     return -1;

@@ -40,7 +40,7 @@ class btl_geom(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("dx", ctypes.c_double),
                 ("bc", ctypes.c_int32 * 3), ("n_comp", ctypes.c_int32),
                 ("comp_id", ctypes.c_void_p), ("comp_phase", ctypes.c_void_p),
-                ("n_phase", ctypes.c_int32)]
+                ("n_phase", ctypes.c_int32), ("link_delta", ctypes.c_void_p)]
 
 
 _lib = None
@@ -92,7 +92,9 @@ def _check(st, handle):
 
 def btl_create(geoms, prec: int):
     """geoms: list of objects with comp (n2,n1,n0) uint32, comp_phase uint8,
-    n_phase, dx and a `bc` list.  Returns (handle, keepalive)."""
+    n_phase, dx, a `bc` list and optionally link_delta (3, n2, n1, n0)
+    float32 membrane positions (None: half-link membranes).  Returns the
+    handle."""
     lib = load_library()
     arr = (btl_geom * len(geoms))()
     keep = []
@@ -108,6 +110,13 @@ def btl_create(geoms, prec: int):
         arr[i].comp_id = _np_ptr(comp)
         arr[i].comp_phase = _np_ptr(cp)
         arr[i].n_phase = int(g.n_phase)
+        ld = getattr(g, "link_delta", None)
+        if ld is not None:
+            ld = np.ascontiguousarray(ld, dtype=np.float32)
+            if ld.shape != (3,) + comp.shape:
+                raise ValueError("link_delta must have shape (3, n2, n1, n0)")
+            keep.append(ld)
+            arr[i].link_delta = _np_ptr(ld)
     h = ctypes.c_void_p()
     _check(lib.btl_create(arr, len(geoms), int(prec), ctypes.byref(h)), None)
     return h
@@ -163,6 +172,7 @@ class _GeomBC:
     def __init__(self, g, bc):
         self.comp, self.comp_phase = g.comp, g.comp_phase
         self.n_phase, self.dx, self.bc = g.n_phase, g.dx, list(bc)
+        self.link_delta = getattr(g, "link_delta", None)
 
 
 class Simulator:

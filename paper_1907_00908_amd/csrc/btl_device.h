@@ -65,6 +65,41 @@ __device__ __forceinline__ double2 block_sum(double2 v, double2* lds) {
     return r;
 }
 
+// Weights of the six populations that make up the population entering a
+// node across a membrane at distance d (units of dx) from it, for a straight
+// membrane normal to the link (Eqs. B2a_text/B2b_text with theta = 0,
+// Eqs. B4a-B4c).  The Dirichlet (c_d) and Neumann (c_n) coefficients of the
+// node's own side use d (Eqs. c_d, c_n), those of the far side 1 - d.
+// Output order: own side A[0..2] for ghat_ibar(x), ghat_ibar(x + e_i),
+// ghat_i(x); far side B[0..2] for ghat_i(x - e_i), ghat_i(x - 2 e_i),
+// ghat_ibar(x - e_i).  kdt = kappa dt, edx = eps_D dx.
+struct MembCoef {
+    double A[3], B[3];
+};
+__device__ __forceinline__ MembCoef membrane_coefficients(double d, double kdt, double edx) {
+    const double e = 1.0 - d;
+    const double ro = 1.0 / (2.0 * d + 1.0), rf = 1.0 / (2.0 * e + 1.0);
+    const double ho = 2.0 * d - 1.0, hf = 2.0 * e - 1.0;
+    // own side
+    const double n2 = -ho * ro, n3 = ho * ro, n4 = 2.0 * ro;
+    const double d1 = 2.0 * d - 2.0, d2 = -ho * ho * ro, d3 = 2.0 * ho * ro, d4 = (3.0 - 2.0 * d) * ro;
+    // far side
+    const double fn2 = -hf * rf, fn3 = hf * rf, fn4 = 2.0 * rf;
+    const double fd1 = 2.0 * e - 2.0, fd2 = -hf * hf * rf, fd3 = 2.0 * hf * rf, fd4 = (3.0 - 2.0 * e) * rf;
+    const double diff = d4 * fd4 * edx;
+    const double perm_own = fd4 * n4 * kdt, perm_far = fn4 * d4 * kdt;
+    const double rF = 1.0 / (diff + (d4 * fn4 + n4 * fd4) * kdt);
+    MembCoef c;
+    c.A[0] = (diff + perm_own * d1 + perm_far) * rF;
+    c.A[1] = (diff * n2 + perm_own * d2 + perm_far * n2) * rF;
+    c.A[2] = (diff * n3 + perm_own * d3 + perm_far * n3) * rF;
+    const double bk = d4 * n4 * kdt * rF;
+    c.B[0] = bk * (1.0 - fd1);
+    c.B[1] = bk * (fn2 - fd2);
+    c.B[2] = bk * (fn3 - fd3);
+    return c;
+}
+
 // exp(i th) in FP64 (library sincos; used only by the table kernel).
 __device__ __forceinline__ double2 expi(double th) {
     double sn, cs;

@@ -47,7 +47,8 @@ struct FieldDesc {
     int32_t adj_kind[6];
     int64_t adj_pop[6];
     int32_t adj_fac[6];
-    int32_t pad3[2];
+    int64_t gm;             // offset of the geometry's membrane-position table
+                            // ([6][nsites] floats, see StepArgs::gm), or -1
 };
 
 constexpr int kAdjMaxPhase = 4;
@@ -94,6 +95,13 @@ struct StepArgs {
     uint32_t* counter;      // [fields] arrival counters for the last-block reduction
     double* E;              // [Q][K+1][2]
     const double* rdt;      // [P] dt/T2 (classical scheme)
+    // General membrane condition (theta = 0, membrane anywhere on the link):
+    // gm[(d-1)*nsites + s] is, for the pull link of direction d into site s,
+    // 0 when the half-link rule applies, else the link's membrane position
+    // as given (v > 0: distance from s is v; v < 0: distance is 1 + v).
+    const float* gm;
+    const double* kdt;      // [P*P] kappa * dt
+    double edx;             // eps_D * dx
     double2* tab;           // phase table of step k (T entries); the table kernel
                             // fills kTabSteps consecutive steps from here
     const int32_t* tab_field;  // [T] field of each table entry

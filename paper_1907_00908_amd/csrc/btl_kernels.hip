@@ -23,6 +23,11 @@
 // direction per field).  Per-step constants enter only through forms that
 // keep sum_i g_i exact for any rounded constant (g + w(wM - g), a + t(b - a)).
 //
+// With membrane positions given, a membrane link whose six-node stencil lies
+// inside the field takes the general condition for a straight membrane at
+// that position (Eqs. B2a_text/B2b_text, B4a-B4c) instead of the half-link
+// form (GM = true; other links keep the half-link form).
+//
 // The signal of a step is reduced deterministically: each workgroup writes a
 // partial sum, and the last workgroup of a field to finish (arrival counter)
 // adds all partials of that field in a fixed order.
@@ -72,11 +77,12 @@ __global__ void __launch_bounds__(kBlock) k_tables(StepArgs a, int32_t nsteps) {
 // R = -i gamma (x.G0) f_{k+1} - 1/T2, the reaction term of the collision that
 // follows the moment M(t^{k+1}).  The last step stores the plain collision,
 // whose moment is M(t^K).
-template <typename V, int TX, bool CL>
+template <typename V, int TX, bool CL, bool GM>
 __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     constexpr int TY = kBlock / TX;
     __shared__ double2 lds[kBlock / 64];
     __shared__ double c_w[kMaxPhase], c_dec[kMaxPhase], c_tr[kMaxPhase * kMaxPhase];
+    __shared__ double c_kdt[GM ? kMaxPhase * kMaxPhase : 1];
     __shared__ int last_flag;
     // per-phase constants in LDS: lane-indexed lookups then go through the
     // LDS counter and never wait on outstanding global loads or stores
@@ -87,6 +93,7 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
             c_dec[t] = CL ? a.rdt[t] : a.decay[t];
         }
         if (t < P * P) c_tr[t] = a.trans[t];
+        if (GM && t < P * P) c_kdt[t] = a.kdt[t];
     }
     __syncthreads();
     const int fi = a.blk_field[blockIdx.x];
@@ -112,6 +119,7 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     const V* __restrict__ src = static_cast<const V*>(a.src) + fd.pop;
     V* __restrict__ dst = static_cast<V*>(a.dst) + fd.pop;
     const uint32_t* __restrict__ words = a.words + fd.words;
+    const float* __restrict__ gmt = GM && fd.gm >= 0 ? a.gm + fd.gm : nullptr;
     const int32_t pop = 0;
     const int32_t j0 = tx * TX + (int32_t)(threadIdx.x % TX);
     const int32_t j1 = ty * TY + (int32_t)(threadIdx.x / TX);
@@ -196,17 +204,67 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
             }
         }
         if (mask) {
-            // half-link membrane: g' = ghat_opp(x) + t (incoming - ghat_opp(x))
+            // membrane positions of the pulled links (0: half-link rule)
+            float gv[kQ - 1];
+#pragma unroll
+            for (int d = 1; d < kQ; ++d)
+                gv[d - 1] = (GM && gmt && ((mask >> (d - 1)) & 1u)) ? gmt[(d - 1) * ns + s] : 0.0f;
+            // half-link membrane: g' = ghat_opp(x) + t (incoming - ghat_opp(x));
+            // links with a position are collected in gen
+            uint32_t gen = 0;
 #pragma unroll
             for (int d = 1; d < kQ; ++d) {
                 if ((mask >> (d - 1)) & 1u) {
                     const int pn = (int)((word >> (10 + 3 * (d - 1))) & 0x7u);
                     const double t = c_tr[p * P + pn];
                     if (t < 1.0) {
-                        const double2 o = ld2(&L.own[d - 1]);
-                        g[d].x = o.x + t * (g[d].x - o.x);
-                        g[d].y = o.y + t * (g[d].y - o.y);
+                        if (GM && gv[d - 1] != 0.0f) {
+                            gen |= 1u << d;
+                        } else {
+                            const double2 o = ld2(&L.own[d - 1]);
+                            g[d].x = o.x + t * (g[d].x - o.x);
+                            g[d].y = o.y + t * (g[d].y - o.y);
+                        }
                     }
+                }
+            }
+            if (GM) {
+                // general condition, one link at a time (rolled: the code
+                // exists once); the stencil x - 2e_d .. x + e_d lies inside
+                // the field (checked on the host)
+                while (gen) {
+                    const int d = __builtin_ctz(gen);
+                    gen &= gen - 1;
+                    // L.own[k-1] holds ghat_{opp(k)}(x): both populations of x
+                    // on the link's axis are already loaded
+                    double2 b1 = g[1], o = ld2(&L.own[0]), a3 = ld2(&L.own[1]);
+                    float v = gv[0];
+#pragma unroll
+                    for (int k = 2; k < kQ; ++k)
+                        if (d == k) {
+                            const int ok = (k & 1) ? k + 1 : k - 1;
+                            b1 = g[k];
+                            o = ld2(&L.own[k - 1]);
+                            a3 = ld2(&L.own[ok - 1]);
+                            v = gv[k - 1];
+                        }
+                    const int pn = (int)((word >> (10 + 3 * (d - 1))) & 0x7u);
+                    const double dd = v > 0.0f ? (double)v : 1.0 + (double)v;
+                    const MembCoef c = membrane_coefficients(dd, c_kdt[p * P + pn], a.edx);
+                    const int od = (d & 1) ? d + 1 : d - 1;
+                    const int32_t sa = d <= 2 ? 1 : d <= 4 ? st1 : st2;
+                    const int32_t e = (d & 1) ? sa : -sa;
+                    const double2 a2 = ld2(src + od * ns + s + e);
+                    const double2 b2 = ld2(src + d * ns + s - 2 * e);
+                    const double2 b3 = ld2(src + od * ns + s - e);
+                    double2 r;
+                    r.x = c.A[0] * o.x + c.A[1] * a2.x + c.A[2] * a3.x
+                        + c.B[0] * b1.x + c.B[1] * b2.x + c.B[2] * b3.x;
+                    r.y = c.A[0] * o.y + c.A[1] * a2.y + c.A[2] * a3.y
+                        + c.B[0] * b1.y + c.B[1] * b2.y + c.B[2] * b3.y;
+#pragma unroll
+                    for (int k = 1; k < kQ; ++k)
+                        if (d == k) g[k] = r;
                 }
             }
         }
@@ -349,32 +407,41 @@ hipError_t launch_init(int prec, void* pop, int64_t, const FieldDesc*, int32_t n
     return hipGetLastError();
 }
 
-template <typename V, bool CL>
+template <typename V, bool CL, bool GM>
 static void launch_step_t(int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st) {
     switch (shape) {
         case kTile64x4:
-            hipLaunchKernelGGL((k_step<V, 64, CL>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL((k_step<V, 64, CL, GM>), dim3(n_blocks), dim3(kBlock), 0, st, a);
             break;
         case kTile32x8:
-            hipLaunchKernelGGL((k_step<V, 32, CL>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL((k_step<V, 32, CL, GM>), dim3(n_blocks), dim3(kBlock), 0, st, a);
             break;
         case kTile128x2:
-            hipLaunchKernelGGL((k_step<V, 128, CL>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL((k_step<V, 128, CL, GM>), dim3(n_blocks), dim3(kBlock), 0, st, a);
             break;
         default:
-            hipLaunchKernelGGL((k_step<V, 16, CL>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL((k_step<V, 16, CL, GM>), dim3(n_blocks), dim3(kBlock), 0, st, a);
             break;
     }
 }
 
-hipError_t launch_step(int prec, int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st) {
-    if (prec == 1) {
-        if (a.classical) launch_step_t<float2, true>(shape, a, n_blocks, st);
-        else launch_step_t<float2, false>(shape, a, n_blocks, st);
+template <typename V>
+static void launch_step_v(int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st) {
+    const bool gm = a.gm != nullptr;
+    if (a.classical) {
+        if (gm) launch_step_t<V, true, true>(shape, a, n_blocks, st);
+        else launch_step_t<V, true, false>(shape, a, n_blocks, st);
     } else {
-        if (a.classical) launch_step_t<double2, true>(shape, a, n_blocks, st);
-        else launch_step_t<double2, false>(shape, a, n_blocks, st);
+        if (gm) launch_step_t<V, false, true>(shape, a, n_blocks, st);
+        else launch_step_t<V, false, false>(shape, a, n_blocks, st);
     }
+}
+
+hipError_t launch_step(int prec, int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st) {
+    if (prec == 1)
+        launch_step_v<float2>(shape, a, n_blocks, st);
+    else
+        launch_step_v<double2>(shape, a, n_blocks, st);
     return hipGetLastError();
 }
 

@@ -28,6 +28,7 @@ struct GeomHost {
     int32_t bc[3];
     int64_t nsites;
     int64_t words_off;   // offset into the concatenated site-word array
+    int64_t gm_off = -1; // offset into the membrane-position tables, -1: none
 };
 
 template <typename T>
@@ -71,6 +72,7 @@ struct btl_sim {
     int32_t n_phase = 1;
     std::vector<GeomHost> geoms;
     DevBuf<uint32_t> words;
+    DevBuf<float> gm;            // [6][nsites] per geometry with membrane positions
     DevBuf<char> pop[2];
     DevBuf<FieldDesc> fields;
     DevBuf<int32_t> blk_field;
@@ -199,6 +201,50 @@ static void build_words(const btl_geom& g, std::vector<uint32_t>& out) {
             }
 }
 
+// Membrane-position table of one geometry for the general membrane
+// condition: for the pull link of direction d into site x (from x - e_d),
+// entry [(d-1)*nsites + x] is 0 when the link keeps the half-link rule, v > 0
+// when the membrane lies at distance v from x and v < 0 when it lies at
+// distance 1 + v (the link's value measured from its lower node x - e_d).
+// The general rule needs the stencil x - 2e_d .. x + e_d inside the lattice
+// (no outer face), x + e_d in x's compartment and x - 2e_d in that of
+// x - e_d.  Returns false when a membrane link's value is not in (0, 1).
+static bool build_gm(const btl_geom& g, std::vector<float>& out) {
+    const int64_t n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], N = n0 * n1 * n2;
+    const int64_t st[3] = {1, n0, n0 * n1};
+    const float* ld = g.link_delta;
+    out.assign((size_t)(6 * N), 0.0f);
+    for (int64_t j2 = 0; j2 < n2; ++j2)
+        for (int64_t j1 = 0; j1 < n1; ++j1)
+            for (int64_t j0 = 0; j0 < n0; ++j0) {
+                const int64_t s = j0 + n0 * (j1 + n1 * j2);
+                const int64_t jj[3] = {j0, j1, j2};
+                const uint32_t c = g.comp_id[s];
+                for (int a = 0; a < 3; ++a) {
+                    // every value a membrane link can be read from
+                    const bool last = jj[a] == g.n[a] - 1;
+                    if (last && g.bc[a] == BTL_MIRROR) continue;
+                    const int64_t up = last ? s - (g.n[a] - 1) * st[a] : s + st[a];
+                    if (g.comp_id[up] != c) {
+                        const float v = ld[a * N + s];
+                        if (!(v > 0.0f && v < 1.0f)) return false;
+                    }
+                }
+                for (int d = 1; d < 7; ++d) {
+                    const int a = (d - 1) / 2;
+                    const int sg = (d & 1) ? 1 : -1;        // e_d = sg e_a
+                    const int64_t j = jj[a];
+                    if (j - 2 * sg < 0 || j - 2 * sg >= g.n[a] || j + sg < 0 || j + sg >= g.n[a])
+                        continue;
+                    const int64_t sm1 = s - sg * st[a], sm2 = s - 2 * sg * st[a], sp1 = s + sg * st[a];
+                    const uint32_t cs = g.comp_id[sm1];
+                    if (cs == c || g.comp_id[sp1] != c || g.comp_id[sm2] != cs) continue;
+                    out[(size_t)((d - 1) * N + s)] = sg > 0 ? -ld[a * N + sm1] : ld[a * N + s];
+                }
+            }
+    return true;
+}
+
 extern "C" btl_status btl_create(const btl_geom* geoms, int32_t n_geom, int32_t prec,
                                  btl_sim** out) {
     if (!out) return fail(nullptr, BTL_E_INVAL, "out is NULL");
@@ -235,6 +281,7 @@ extern "C" btl_status btl_create(const btl_geom* geoms, int32_t n_geom, int32_t 
     s->n_phase = P;
     (void)hipGetDevice(&s->device);
     std::vector<uint32_t> all, one;
+    std::vector<float> gm_all, gm_one;
     for (int g = 0; g < n_geom; ++g) {
         GeomHost h;
         for (int a = 0; a < 3; ++a) {
@@ -245,11 +292,24 @@ extern "C" btl_status btl_create(const btl_geom* geoms, int32_t n_geom, int32_t 
         h.words_off = (int64_t)all.size();
         build_words(geoms[g], one);
         all.insert(all.end(), one.begin(), one.end());
+        if (geoms[g].link_delta) {
+            if (!build_gm(geoms[g], gm_one)) {
+                btl_destroy(s);
+                return fail(nullptr, BTL_E_INVAL, "link_delta must be in (0, 1) on membrane links");
+            }
+            h.gm_off = (int64_t)gm_all.size();
+            gm_all.insert(gm_all.end(), gm_one.begin(), gm_one.end());
+        }
         s->geoms.push_back(h);
     }
     hipError_t e = s->words.ensure(all.size());
     if (e == hipSuccess)
         e = hipMemcpy(s->words.p, all.data(), all.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !gm_all.empty()) {
+        e = s->gm.ensure(gm_all.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(s->gm.p, gm_all.data(), gm_all.size() * sizeof(float), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         btl_status st = hip_fail(nullptr, e, "uploading site words");
         btl_destroy(s);
@@ -330,7 +390,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     const double dx = s->dx;
 
     // per-phase and per-pair constants (FP64)
-    std::vector<double> consts(2 * P + P * P + P + P * P + P);
+    std::vector<double> consts(2 * P + P * P + P + P * P + P + P * P);
     for (int p = 0; p < P; ++p) {
         const double tau = 0.5 + dt * D[p] / (kEpsD * dx * dx);
         consts[p] = 1.0 / tau;
@@ -352,6 +412,9 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     for (int p = 0; p < P; ++p) consts[2 * P + P * P + p] = T2[p];
     for (int i = 0; i < P * P; ++i) consts[3 * P + P * P + i] = kappa[i];
     for (int p = 0; p < P; ++p) consts[3 * P + 2 * P * P + p] = isinf(T2[p]) ? 0.0 : dt / T2[p];
+    for (int i = 0; i < P * P; ++i) consts[4 * P + 2 * P * P + i] = kappa[i] * dt;
+    bool uses_gm = false;
+    for (int q = 0; q < Q; ++q) uses_gm |= s->geoms[q_geom[q]].gm_off >= 0;
     const bool classical = s->scheme == BTL_CLASSICAL;
     // per-step waveform tables
     std::vector<double> steps((size_t)K + (size_t)K + 1);
@@ -418,6 +481,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
             d.tiles[2] = (g.n[2] + ZC - 1) / ZC;
             d.nblk = d.tiles[0] * d.tiles[1] * d.tiles[2];
             d.q = fi == 0 ? q : -1;
+            d.gm = g.gm_off;
             d.cu = 0.0;
             for (int a = 0; a < 3; ++a) {
                 const int sig = (sg >> a) & 1;
@@ -578,6 +642,8 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     if (ckpt_every > 0 && K > 0) {
         if (P > kAdjMaxPhase) return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports n_phase <= 4");
         if (classical) return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports the hybrid scheme only");
+        if (uses_gm)
+            return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports the half-link membrane rule only");
         const int32_t C = std::min(ckpt_every, K);
         const int32_t nck = (K + C - 1) / C;
         if ((e = s->ckpt.ensure((size_t)nck * state_bytes)) != hipSuccess)
@@ -621,6 +687,9 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         a.decay = s->consts.p + P;
         a.trans = s->consts.p + 2 * P;
         a.rdt = s->consts.p + 3 * P + 2 * P * P;
+        a.gm = uses_gm ? s->gm.p : nullptr;
+        a.kdt = s->consts.p + 4 * P + 2 * P * P;
+        a.edx = kEpsD * dx;
         a.classical = classical ? 1 : 0;
         a.partial = s->partial.p;
         a.counter = s->counter.p;
@@ -974,6 +1043,7 @@ extern "C" void btl_destroy(btl_sim* s) {
     if (!s) return;
     (void)hipDeviceSynchronize();
     s->words.release();
+    s->gm.release();
     s->pop[0].release();
     s->pop[1].release();
     s->fields.release();

@@ -165,12 +165,25 @@ CONFIGS = {"cfg1": _cfg1, "cfg2": _cfg2, "cfg3a": _cfg3a, "cfg3b": _cfg3b,
            "cfg4": _cfg4, "cfg5": _cfg5}
 
 
-def make_config(name: str, n=None, K=None, n_q=None, seed=None) -> dict:
-    """Build a config; n/K/n_q/seed override the full-size defaults."""
+def make_config(name: str, n=None, K=None, n_q=None, seed=None,
+                membranes: str = "half-link") -> dict:
+    """Build a config; n/K/n_q/seed override the full-size defaults.
+
+    membranes="positions" attaches to every geometry the exact positions
+    where its analytic surfaces cut the lattice links (`geometry.link_delta`),
+    for the general membrane condition; the default leaves them out (every
+    membrane at mid-link)."""
     fn = CONFIGS[name]
     kw = {}
     if n is not None:
         kw["n"] = n
     if seed is not None:
         kw["seed"] = seed
-    return fn(K=K, n_q=n_q, **kw)
+    cfg = fn(K=K, n_q=n_q, **kw)
+    if membranes == "positions":
+        for g in cfg["geoms"]:
+            g.link_delta = geo.link_delta(g)
+        cfg["name"] += "+positions"
+    elif membranes != "half-link":
+        raise ValueError("membranes must be 'half-link' or 'positions'")
+    return cfg

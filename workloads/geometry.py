@@ -26,6 +26,9 @@ class Geometry:
     n_phase: int
     dx: float
     info: dict = field(default_factory=dict)
+    # optional membrane positions on the links, (3, n2, n1, n0) float32 (see
+    # `link_delta`); None: every membrane at mid-link
+    link_delta: np.ndarray | None = None
 
     @property
     def shape_xyz(self):
