@@ -115,7 +115,9 @@ btl_status btl_create(const btl_geom *geoms, int32_t n_geom, int32_t prec,
  *   q_geom  host [Q] geometry index of each q-sample
  *   gG0     host [Q][3] gamma*G0 of each q-sample
  *   f       host [K] waveform sample f_k applied on [k dt, (k+1) dt)
- *           (the same waveform for all q-samples)
+ *           (the same waveform for all q-samples); with m reaction
+ *           sub-steps (btl_set_substeps) host [K*m], sample f[k m + j]
+ *           applied on sub-step j of step k
  *   E       device [Q][K+1][2] doubles, caller-allocated: E[q][k] is the
  *           complex signal at t = k dt, E[q][0] = 1
  *   M_final device or NULL: the magnetization at t = K dt of every q-sample,
@@ -134,12 +136,23 @@ btl_status btl_forward(btl_sim *s, double dt, int32_t K, const double *D,
  * btl_forward that kept a tape (ckpt_every > 0).  dL_dE is device
  * [Q][K+1][2] with dL/dE = dL/dRe E + i dL/dIm E.  Outputs are device
  * doubles, overwritten (NULL = not wanted): dD [P], dT2 [P], dkappa [P*P],
- * df [K].  dkappa is the gradient per matrix entry: for a != b the entries
+ * df [K] (or [K*m] with m reaction sub-steps: dL per waveform sample).
+ * dkappa is the gradient per matrix entry: for a != b the entries
  * [a][b] and [b][a] each hold half of dL/dkappa_ab, so that a symmetric
  * parametrization (both entries set from one value) gets the full value.
  * Errors: BTL_E_INVAL (no tape), BTL_E_NOMEM, BTL_E_HIP. */
 btl_status btl_backward(btl_sim *s, const double *dL_dE, double *dD, double *dT2,
                         double *dkappa, double *df, void *stream);
+
+/* Reaction sub-stepping (Sec. 2.3: the reaction may run with its own time
+ * step dt' = dt/m while diffusion keeps dt).  Later btl_forward calls take
+ * m waveform samples per step; step k applies the m reaction sub-steps
+ * exp(-i gamma (x.G0) f[k m + j] dt') exp(-dt'/T2), j = 0..m-1, whose
+ * product is one phase factor with the summed angle, and the modified
+ * periodic and mirror phases use F advanced by the same sums.  m = 1 is the
+ * default (dt' = dt).  Hybrid scheme only: a classical forward with m > 1
+ * returns BTL_E_UNSUPPORTED.  Errors: BTL_E_INVAL (m outside 1..65536). */
+btl_status btl_set_substeps(btl_sim *s, int32_t m);
 
 /* Select the scheme of later btl_forward calls.  BTL_HYBRID (default) is
  * the paper's split scheme (Sec. 2.3).  BTL_CLASSICAL is the classical LBM

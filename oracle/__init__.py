@@ -51,7 +51,7 @@ def _load():
         lib.oracle_run.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_int32, P, P,
                                    ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                    P, P, P, P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32,
-                                   P, P]
+                                   P, P, ctypes.c_int32]
         lib.oracle_run.restype = ctypes.c_int
         lib.oracle_memb_coeffs.argtypes = [ctypes.c_double] * 3 + [P]
         lib.oracle_memb_coeffs.restype = None
@@ -66,7 +66,7 @@ def _ptr(a):
 
 
 def _run_core(comp, comp_phase, n_phase, bc, off, dx, dt, D, T2, kappa, f, gG0,
-              elo, ehi, threads, want_M, scheme=0, link_delta=None, tile=None):
+              elo, ehi, threads, want_M, scheme=0, link_delta=None, tile=None, substeps=1):
     lib = _load()
     comp = np.ascontiguousarray(comp, dtype=np.uint32)
     n2, n1, n0 = comp.shape
@@ -81,7 +81,9 @@ def _run_core(comp, comp_phase, n_phase, bc, off, dx, dt, D, T2, kappa, f, gG0,
     gG0 = np.ascontiguousarray(gG0, dtype=np.float64)
     elo = np.ascontiguousarray(elo, dtype=np.int32)
     ehi = np.ascontiguousarray(ehi, dtype=np.int32)
-    K = len(f)
+    if len(f) % substeps:
+        raise ValueError("len(f) must be a multiple of substeps")
+    K = len(f) // substeps
     E = np.zeros(2 * (K + 1), np.float64)
     M = np.zeros(2 * comp.size, np.float64) if want_M else None
     if link_delta is not None:
@@ -94,7 +96,7 @@ def _run_core(comp, comp_phase, n_phase, bc, off, dx, dt, D, T2, kappa, f, gG0,
                         _ptr(kappa), _ptr(f), _ptr(gG0), _ptr(elo), _ptr(ehi),
                         _ptr(E), _ptr(M) if want_M else None, int(threads), int(scheme),
                         _ptr(link_delta) if link_delta is not None else None,
-                        _ptr(tile) if tile is not None else None)
+                        _ptr(tile) if tile is not None else None, int(substeps))
     if rc == -2:
         raise NotImplementedError("oblique gradient on a mirrored axis")
     if rc != 0:
@@ -133,7 +135,7 @@ HYBRID, CLASSICAL = 0, 1
 
 def simulate(comp, comp_phase, n_phase, bc, dx, dt, D, T2, kappa, f, gG0,
              threads: int = 1, mirror: str = "auto", want_M: bool = True,
-             scheme: int = HYBRID, link_delta=None):
+             scheme: int = HYBRID, link_delta=None, substeps: int = 1):
     """Run the scheme for one gradient vector.
 
     comp (n2, n1, n0) compartment ids, comp_phase [C], bc[3] (0 periodic,
@@ -148,6 +150,8 @@ def simulate(comp, comp_phase, n_phase, bc, dx, dt, D, T2, kappa, f, gG0,
     link_delta: None (half-link membranes at mid-link) or (3, n2, n1, n0)
     membrane positions along the +x, +y, +z links from each node (units of
     dx) for the general theta = 0 membrane condition (oracle.c).
+    substeps: m reaction sub-steps per step; f then holds K*m samples at
+    dt/m (hybrid scheme only).
     Returns E [K+1] complex and M at t_K, complex (n2, n1, n0).
     """
     comp = np.asarray(comp)
@@ -162,7 +166,7 @@ def simulate(comp, comp_phase, n_phase, bc, dx, dt, D, T2, kappa, f, gG0,
         ld = None if link_delta is None else np.asarray(link_delta, np.float32)
         return _run_core(comp, comp_phase, n_phase, bc, [0.0, 0.0, 0.0], dx, dt,
                          D, T2, kappa, f, gG0, [0, 0, 0], [n0, n1, n2], threads, want_M,
-                         scheme, ld)
+                         scheme, ld, None, substeps)
     if mirror != "double":
         raise ValueError("mirror must be 'auto', 'paper' or 'double'")
     # reflect the REV across the lower face of every mirrored axis: the
@@ -200,7 +204,7 @@ def simulate(comp, comp_phase, n_phase, bc, dx, dt, D, T2, kappa, f, gG0,
         lo[a], hi[a] = na, 2 * na
     bce = [PERIODIC] * 3
     E, M = _run_core(ext, comp_phase, n_phase, bce, off, dx, dt, D, T2, kappa, f,
-                     gG0, lo, hi, threads, want_M, scheme, ld, tile)
+                     gG0, lo, hi, threads, want_M, scheme, ld, tile, substeps)
     if want_M:
         M = M[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].copy()
     return E, M
@@ -217,7 +221,8 @@ def simulate_config(cfg: dict, q=None, threads: int = 1, mirror: str = "auto",
                         cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"][i],
                         threads=threads, mirror=mirror, want_M=want_M,
                         scheme=cfg.get("scheme", HYBRID) if scheme is None else scheme,
-                        link_delta=getattr(g, "link_delta", None))
+                        link_delta=getattr(g, "link_delta", None),
+                        substeps=cfg.get("substeps", 1))
         Es.append(E)
         Ms.append(M)
     return np.array(Es), Ms

@@ -41,6 +41,12 @@
  * with x - e_i, lie in the same tile of the lattice as x (no outer face in
  * the stencil); otherwise the link falls back to the half-link rule.
  *
+ * With substeps = m > 1 the reaction of each step is taken as m sub-steps
+ * of length dt' = dt/m (the reaction time step of Sec. 2.3, dt = m dt'),
+ * each with its own waveform sample: f holds K*m samples, sub-step j of step
+ * k multiplies by exp(-i gamma (x.G0) f[k m + j] dt') exp(-dt'/T2), and F
+ * advances by f[k m + j] dt' per sub-step.  (Hybrid scheme only.)
+ *
  * Lattice: D3Q7 with eps_D = 1/4, w_0 = 1/4, w_{+-x,+-y,+-z} = 1/8.  The
  * paper leaves the 3D weights implicit; eps_D = 1/4 is what its Fig. 11
  * caption requires (tau = 0.58 at D = 2, dt = 0.01, dx = 1), and the weights
@@ -151,7 +157,8 @@ static cplx pairwise_sum(const cplx *v, long n) {
  * off[3]      coordinate of node j is (j + off_a) * dx  (origin x_o = 0)
  * D, T2       [n_phase]; T2 may be +inf
  * kappa       [n_phase * n_phase] symmetric, um/ms; +inf = no membrane
- * f           [K] waveform samples, gG0[3] = gamma * G0 in rad/(um ms)
+ * f           [K * substeps] waveform samples, gG0[3] = gamma * G0 in
+ *             rad/(um ms)
  * elo, ehi    the box [elo, ehi) over which the signal is averaged
  * link_delta  [3][n2][n1][n0] or NULL: for axis a, the distance (units of
  *             dx) from node j to the membrane on the link j -> j + e_a,
@@ -167,10 +174,14 @@ int oracle_run(const int32_t n[3], const uint32_t *comp, const uint8_t *comp_pha
                const double *D, const double *T2, const double *kappa,
                const double *f, const double gG0[3], const int32_t elo[3],
                const int32_t ehi[3], double *E, double *M_out, int32_t nthreads,
-               int32_t scheme, const double *link_delta, const int32_t *tile) {
+               int32_t scheme, const double *link_delta, const int32_t *tile,
+               int32_t substeps) {
     const long n0 = n[0], n1 = n[1], n2 = n[2];
     if (n0 < 1 || n1 < 1 || n2 < 1 || dx <= 0 || dt <= 0 || K < 0) return -1;
     if (scheme != 0 && scheme != 1) return -1;
+    if (substeps < 1 || (scheme == 1 && substeps != 1)) return -1;
+    const int m_sub = substeps;
+    const double dts = dt / m_sub;
     const long N = n0 * n1 * n2;
     for (int a = 0; a < 3; ++a) {
         if (bc[a] != BC_PERIODIC && bc[a] != BC_MIRROR) return -1;
@@ -345,7 +356,7 @@ int oracle_run(const int32_t n[3], const uint32_t *comp, const uint8_t *comp_pha
         }
 
         /* 4. streaming with membranes, then 5. reaction */
-        const double fk_dt = f[k] * dt;
+
 #pragma omp parallel for schedule(static)
         for (long j2 = 0; j2 < n2; ++j2)
             for (long j1 = 0; j1 < n1; ++j1)
@@ -357,7 +368,14 @@ int oracle_run(const int32_t n[3], const uint32_t *comp, const uint8_t *comp_pha
                     /* reaction factor: exp(-i gamma (x.G0) f_k dt) exp(-dt/T2) */
                     const double xg = gG0[0] * COORD(0, j0) + gG0[1] * COORD(1, j1)
                                     + gG0[2] * COORD(2, j2);
-                    const cplx react = scheme == 1 ? 1.0 : cexp(-I * xg * fk_dt) * decay[px];
+                    cplx react = 1.0;
+                    if (scheme == 0) {
+                        /* m reaction sub-steps of length dt/m; their decay
+                           factors multiply to exp(-dt/T2) */
+                        for (int j = 0; j < m_sub; ++j)
+                            react *= cexp(-I * xg * f[(long)k * m_sub + j] * dts);
+                        react *= decay[px];
+                    }
                     for (int i = 0; i < Q; ++i) {
                         long src[3];
                         int crossed = -1;
@@ -423,7 +441,7 @@ int oracle_run(const int32_t n[3], const uint32_t *comp, const uint8_t *comp_pha
                         g[i * N + s] = gp * react;
                     }
                 }
-        F += f[k] * dt;
+        for (int j = 0; j < m_sub; ++j) F += f[(long)k * m_sub + j] * dts;
     }
     if (M_out) {
         for (long s = 0; s < N; ++s) {

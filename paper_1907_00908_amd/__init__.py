@@ -2,8 +2,8 @@
 
 Argument marshalling only: every step of the computation runs in the HIP
 kernels of libbtlbm.so.  The functions `btl_create`, `btl_forward`,
-`btl_backward`, `btl_set_scheme`, `btl_autotune`, `btl_destroy` and
-`btl_last_error` mirror the
+`btl_backward`, `btl_set_scheme`, `btl_set_substeps`, `btl_autotune`,
+`btl_destroy` and `btl_last_error` mirror the
 C ABI of include/btlbm.h one to one.  `Simulator` wraps them with torch
 tensors for device memory and the current torch stream.
 
@@ -27,7 +27,7 @@ BTL_F64, BTL_F32 = 0, 1
 BTL_HYBRID, BTL_CLASSICAL = 0, 1
 
 EXPORTED = ("btl_create", "btl_forward", "btl_backward", "btl_set_scheme",
-            "btl_autotune", "btl_destroy", "btl_last_error")
+            "btl_set_substeps", "btl_autotune", "btl_destroy", "btl_last_error")
 
 
 class BtlError(RuntimeError):
@@ -68,6 +68,8 @@ def load_library(path: str = None):
     lib.btl_backward.restype = ctypes.c_int
     lib.btl_set_scheme.argtypes = [P, i32]
     lib.btl_set_scheme.restype = ctypes.c_int
+    lib.btl_set_substeps.argtypes = [P, i32]
+    lib.btl_set_substeps.restype = ctypes.c_int
     lib.btl_autotune.argtypes = [P, i32, i32, P]
     lib.btl_autotune.restype = ctypes.c_int
     lib.btl_destroy.argtypes = [P]
@@ -123,8 +125,11 @@ def btl_create(geoms, prec: int):
 
 
 def btl_forward(h, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E_ptr, M_ptr,
-                ckpt_every, stream_ptr):
+                ckpt_every, stream_ptr, substeps=1):
+    """f must hold K * substeps samples (substeps as set on the handle)."""
     lib = load_library()
+    if len(f) < int(K) * int(substeps):
+        raise ValueError("f needs K * substeps samples")
     D = np.ascontiguousarray(D, np.float64)
     T2 = np.ascontiguousarray(T2, np.float64)
     kappa = np.ascontiguousarray(kappa, np.float64).reshape(-1)
@@ -147,6 +152,10 @@ def btl_backward(h, dLdE_ptr, dD_ptr, dT2_ptr, dkappa_ptr, df_ptr, stream_ptr):
 
 def btl_set_scheme(h, scheme):
     _check(load_library().btl_set_scheme(h, int(scheme)), h)
+
+
+def btl_set_substeps(h, m):
+    _check(load_library().btl_set_substeps(h, int(m)), h)
 
 
 def btl_autotune(h, Q, K_probe, stream_ptr):
@@ -178,7 +187,8 @@ class _GeomBC:
 class Simulator:
     """Owns one btl_sim.  Device memory for E and M_final comes from torch."""
 
-    def __init__(self, geoms, bc, prec: str = "f32", scheme: int = BTL_HYBRID):
+    def __init__(self, geoms, bc, prec: str = "f32", scheme: int = BTL_HYBRID,
+                 substeps: int = 1):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Simulator needs a HIP device")
@@ -189,6 +199,9 @@ class Simulator:
         self._h = btl_create([_GeomBC(g, b) for g, b in zip(self.geoms, bcs)], self.prec)
         if scheme != BTL_HYBRID:
             btl_set_scheme(self._h, scheme)
+        self.substeps = int(substeps)
+        if self.substeps != 1:
+            btl_set_substeps(self._h, self.substeps)
 
     def close(self):
         if self._h is not None:
@@ -208,7 +221,9 @@ class Simulator:
         gG0 = np.ascontiguousarray(gG0, np.float64).reshape(-1, 3)
         Q = gG0.shape[0]
         q_geom = np.zeros(Q, np.int32) if q_geom is None else np.asarray(q_geom, np.int32)
-        K = len(f)
+        if len(f) % self.substeps:
+            raise ValueError("len(f) must be a multiple of the reaction sub-steps")
+        K = len(f) // self.substeps
         dev = torch.device("cuda", torch.cuda.current_device())
         E = torch.empty((Q, K + 1, 2), dtype=torch.float64, device=dev)
         M = None
@@ -218,7 +233,7 @@ class Simulator:
             M = torch.empty((tot, 2), dtype=dt_, device=dev)
         stream = torch.cuda.current_stream().cuda_stream
         btl_forward(self._h, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E.data_ptr(),
-                    M.data_ptr() if M is not None else 0, ckpt_every, stream)
+                    M.data_ptr() if M is not None else 0, ckpt_every, stream, self.substeps)
         Ec = torch.view_as_complex(E)
         if not want_M:
             return Ec
@@ -235,18 +250,21 @@ class Simulator:
     def backward(self, dLdE, P: int, K: int):
         """Gradients of a real loss from dL/dE (torch (Q, K+1, 2) float64 on
         the device: dL/dRe E, dL/dIm E) for the last forward that kept a tape.
-        Returns device tensors dD [P], dT2 [P], dkappa [P, P], df [K]."""
+        K is the number of steps of that forward.  Returns device tensors
+        dD [P], dT2 [P], dkappa [P, P], df [K * substeps] (one entry per
+        waveform sample)."""
         torch = self.torch
         dev = dLdE.device
         g = dLdE.detach().to(torch.float64).contiguous()
         dD = torch.empty(P, dtype=torch.float64, device=dev)
         dT2 = torch.empty(P, dtype=torch.float64, device=dev)
         dk = torch.empty((P, P), dtype=torch.float64, device=dev)
-        df = torch.empty(max(K, 1), dtype=torch.float64, device=dev)
+        nf = K * self.substeps
+        df = torch.empty(max(nf, 1), dtype=torch.float64, device=dev)
         stream = torch.cuda.current_stream().cuda_stream
         btl_backward(self._h, g.data_ptr(), dD.data_ptr(), dT2.data_ptr(), dk.data_ptr(),
                      df.data_ptr(), stream)
-        return dD, dT2, dk, df[:K]
+        return dD, dT2, dk, df[:nf]
 
 
 def _bt_function():
@@ -269,7 +287,7 @@ def _bt_function():
             E = sim.forward(dt, Dn, T2n, kn, fn, gG0, q_geom, ckpt_every=max(1, int(ckpt_every)))
             ctx.sim = sim
             ctx.P = len(Dn)
-            ctx.K = len(fn)
+            ctx.K = len(fn) // sim.substeps
             ctx.devs = (D.device, T2.device, kappa.device, f.device)
             return torch.view_as_real(E).clone()
 
@@ -299,10 +317,11 @@ def bloch_torrey_signal(D, T2, kappa, f, sim, dt, gG0, q_geom=None, ckpt_every=1
 
 def simulate_config(cfg: dict, prec: str = "f32", want_M: bool = False, scheme=None):
     """Run a workloads config on the GPU: returns E (Q, K+1) complex (and M).
-    The scheme is `scheme`, else the config's "scheme" entry, else hybrid."""
+    The scheme is `scheme`, else the config's "scheme" entry, else hybrid;
+    the config's "substeps" entry (default 1) sets reaction sub-steps."""
     if scheme is None:
         scheme = cfg.get("scheme", BTL_HYBRID)
-    sim = Simulator(cfg["geoms"], cfg["bc"], prec, scheme)
+    sim = Simulator(cfg["geoms"], cfg["bc"], prec, scheme, cfg.get("substeps", 1))
     try:
         out = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"],
                           cfg["gG0"], cfg["q_geom"], want_M=want_M)

@@ -343,10 +343,12 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
 //   dL/dkappa[a][b] = (G_t[a][b] + G_t[b][a]) / 2 * dt/dkappa (a != b),
 //                     t = 1/(1 + eps_D dx/(2 kappa dt))
 //   dL/df_m   = G_f[m] + dt * sum_{k>m} G_F[k]       (F_k = sum_{m<k} f_m dt)
+// With `sub` reaction sub-steps per step, f_m dt is the sum of `sub`
+// samples times dt/sub, so each sample of step m gets dL/df_m / sub.
 __global__ void k_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P,
                             double dt, double dx, const double* w, const double* T2,
                             const double* kappa, double* dD, double* dT2, double* dkappa,
-                            double* df) {
+                            double* df, int32_t sub) {
     const int NG = 2 * P + P * P + 2;
     const int t = threadIdx.x;
     auto total = [&](int g) {
@@ -383,7 +385,8 @@ __global__ void k_adj_final(const double* gfield, int32_t K, int32_t n_fields, i
         for (int m = K - 1; m >= 0; --m) {
             double gf = 0.0;
             for (int f = 0; f < n_fields; ++f) gf += gfield[((int64_t)m * n_fields + f) * NG + IF];
-            df[m] = gf + dt * suffix;
+            const double v = (gf + dt * suffix) / sub;
+            for (int j = 0; j < sub; ++j) df[(int64_t)m * sub + j] = v;
             double gF = 0.0;
             for (int f = 0; f < n_fields; ++f) gF += gfield[((int64_t)m * n_fields + f) * NG + IFF];
             suffix += gF;
@@ -420,9 +423,9 @@ hipError_t launch_adj(int prec, int shape, const AdjArgs& a, int32_t n_blocks, h
 hipError_t launch_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P,
                             double dt, double dx, const double* w, const double* T2,
                             const double* kappa, double* dD, double* dT2, double* dkappa,
-                            double* df, hipStream_t st) {
+                            double* df, int32_t sub, hipStream_t st) {
     hipLaunchKernelGGL(k_adj_final, dim3(1), dim3(64), 0, st, gfield, K, n_fields, P, dt, dx,
-                       w, T2, kappa, dD, dT2, dkappa, df);
+                       w, T2, kappa, dD, dT2, dkappa, df, sub);
     return hipGetLastError();
 }
 

@@ -125,7 +125,7 @@ hipError_t launch_adj(int prec, int shape, const AdjArgs& a, int32_t n_blocks, h
 hipError_t launch_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P,
                             double dt, double dx, const double* w, const double* T2,
                             const double* kappa, double* dD, double* dT2, double* dkappa,
-                            double* df, hipStream_t st);
+                            double* df, int32_t sub, hipStream_t st);
 hipError_t launch_init(int prec, void* pop, int64_t n_elem_per_dir_total,
                        const FieldDesc* d_fields, int32_t n_fields,
                        const FieldDesc* h_fields, double* E, int32_t Q, int32_t K,

@@ -67,6 +67,7 @@ struct GraphKey {
 struct btl_sim {
     int prec = BTL_F32;
     int scheme = BTL_HYBRID;
+    int substeps = 1;            // reaction sub-steps per step (waveform samples per step)
     int device = 0;
     double dx = 1.0;
     int32_t n_phase = 1;
@@ -109,7 +110,7 @@ struct btl_sim {
     // adjoint tape of the last forward that asked for one
     struct Tape {
         bool valid = false;
-        int32_t K = 0, C = 0, Q = 0, T = 0, n_fields = 0, nblk = 0, shape = 0;
+        int32_t K = 0, C = 0, Q = 0, T = 0, n_fields = 0, nblk = 0, shape = 0, sub = 1;
         double dt = 0;
         int64_t state_elems = 0;   // V elements of one full state (all fields)
     } tape;
@@ -378,7 +379,10 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
             if (!(k >= 0)) return fail(s, BTL_E_INVAL, "kappa must be >= 0");
             if (k != kappa[b * P + a]) return fail(s, BTL_E_INVAL, "kappa must be symmetric");
         }
-    for (int k = 0; k < K; ++k)
+    const int32_t msub = s->substeps;
+    if (msub > 1 && s->scheme == BTL_CLASSICAL)
+        return fail(s, BTL_E_UNSUPPORTED, "reaction sub-steps need the hybrid scheme");
+    for (int64_t k = 0; k < (int64_t)K * msub; ++k)
         if (!isfinite(f[k])) return fail(s, BTL_E_INVAL, "f must be finite");
     for (int q = 0; q < Q; ++q) {
         if (q_geom[q] < 0 || q_geom[q] >= (int)s->geoms.size())
@@ -416,14 +420,20 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     bool uses_gm = false;
     for (int q = 0; q < Q; ++q) uses_gm |= s->geoms[q_geom[q]].gm_off >= 0;
     const bool classical = s->scheme == BTL_CLASSICAL;
-    // per-step waveform tables
+    // per-step waveform tables: f_k dt and F_k.  With m reaction sub-steps
+    // of dt' = dt/m (Sec. 2.3) the reaction of step k is the product of m
+    // exact phase factors, i.e. one factor with the summed angle, so f_k dt
+    // becomes sum_j f[k m + j] dt'.
     std::vector<double> steps((size_t)K + (size_t)K + 1);
     {
+        const double dts = dt / msub;
         double F = 0.0;
         for (int k = 0; k < K; ++k) {
-            steps[k] = f[k] * dt;
+            double a = 0.0;
+            for (int j = 0; j < msub; ++j) a += f[(size_t)k * msub + j] * dts;
+            steps[k] = a;
             steps[(size_t)K + k] = F;
-            F += f[k] * dt;
+            F += a;
         }
         steps[(size_t)2 * K] = F;
     }
@@ -656,6 +666,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         s->tape.nblk = nblk_total;
         s->tape.shape = shape;
         s->tape.dt = dt;
+        s->tape.sub = msub;
         s->tape.state_elems = pop_elems;
     }
     // Everything a forward enqueues after the uploads: init, one table
@@ -808,7 +819,7 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
         s->last.T2.assign(T2, T2 + P);
         s->last.kappa.assign(kappa, kappa + P * P);
         s->last.gG0.assign(gG0, gG0 + 3 * Q);
-        s->last.f.assign(f, f + K);
+        s->last.f.assign(f, f + (size_t)K * s->substeps);
         s->last.q_geom.assign(q_geom, q_geom + Q);
     }
     // q-waves: when the two population copies of all q-samples do not fit
@@ -949,7 +960,7 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
     }
     if ((e = launch_adj_final(s->gfield.p, K, nf, P, tp.dt, s->dx, s->consts.p,
                               s->consts.p + 2 * P + P * P, s->consts.p + 3 * P + P * P, dD, dT2,
-                              dkappa, df, st)) != hipSuccess)
+                              dkappa, df, tp.sub, st)) != hipSuccess)
         return hip_fail(s, e, "adjoint final launch");
     return BTL_OK;
 }
@@ -968,8 +979,8 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
     if (K_probe < 1) return fail(s, BTL_E_INVAL, "K_probe must be >= 1");
     const btl_sim::SimLast& L = s->last;
     const int32_t Qr = std::min<int32_t>(Q > 0 ? Q : (int32_t)L.q_geom.size(), (int32_t)L.q_geom.size());
-    std::vector<double> f(K_probe);
-    for (int k = 0; k < K_probe; ++k) f[k] = L.f.empty() ? 1.0 : L.f[k % L.f.size()];
+    std::vector<double> f((size_t)K_probe * s->substeps);
+    for (size_t k = 0; k < f.size(); ++k) f[k] = L.f.empty() ? 1.0 : L.f[k % L.f.size()];
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e;
     if ((e = s->tune_E.ensure((size_t)Qr * (K_probe + 1) * 2)) != hipSuccess)
@@ -1027,6 +1038,14 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
     }
     s->tile_shape = best_shape;
     s->zc = best_zc;
+    return BTL_OK;
+}
+
+extern "C" btl_status btl_set_substeps(btl_sim* s, int32_t m) {
+    if (!s) return BTL_E_INVAL;
+    if (m < 1 || m > 65536) return fail(s, BTL_E_INVAL, "substeps must be in 1..65536");
+    s->substeps = m;
+    s->last.valid = false;
     return BTL_OK;
 }
 

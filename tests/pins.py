@@ -35,15 +35,17 @@ def dirichlet_mean(N, theta):
     return np.mean(np.exp(-1j * theta * n))
 
 
-def plane_wave_E(n, dx, dt, D, T2, f, gG0):
-    """Signal of the uniform-IC homogeneous periodic problem, all steps."""
+def plane_wave_E(n, dx, dt, D, T2, f, gG0, substeps=1):
+    """Signal of the uniform-IC homogeneous periodic problem, all steps.
+    With m sub-steps f holds m samples per step, each advancing the wave
+    vector over dt/m."""
     w = _w(D, dt, dx)
     decay = 1.0 if math.isinf(T2) else math.exp(-dt / T2)
     a = W.astype(np.complex128)
     kvec = np.zeros(3)
     gG0 = np.asarray(gG0, np.float64)
     out = []
-    K = len(f)
+    K = len(f) // substeps
     for k in range(K + 1):
         geo = 1.0 + 0j
         for ax in range(3):
@@ -53,7 +55,8 @@ def plane_wave_E(n, dx, dt, D, T2, f, gG0):
             break
         ah = a - w * (a - W * a.sum())
         a = ah * np.exp(1j * (E_DIR @ kvec) * dx) * decay
-        kvec = kvec + gG0 * f[k] * dt
+        for j in range(substeps):
+            kvec = kvec + gG0 * f[k * substeps + j] * (dt / substeps)
     return np.array(out)
 
 

@@ -272,3 +272,20 @@ def test_cfg2_full_length_T2_decay_fp32():
     rel = np.max(np.abs(Eg - ref) / ref)
     print(f"max rel err over 10^4 steps {rel:.3e}", flush=True)
     assert rel < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cfg2_64_full_length_vs_stored_oracle(prec):
+    # the axon workload's law at 64^3 (mirror faces, oblique directions with
+    # image fields), all 10^4 steps, against the oracle's signal stored by
+    # tests/golden/make_cfg2_full.py (every 10th step and the last)
+    import os
+    btl = _gpu()
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "cfg2_64_full_E.npz"))
+    cfg = w.make_config("cfg2", n=int(gold["n"]))
+    qs = [int(q) for q in gold["qs"]]
+    cfg["gG0"], cfg["q_geom"] = cfg["gG0"][qs], cfg["q_geom"][qs]
+    assert np.array_equal(cfg["gG0"], gold["gG0"])
+    print(f"GPU cfg2 64^3 K={len(cfg['f'])} q={qs} {prec}", flush=True)
+    Eg = btl.simulate_config(cfg, prec=prec).cpu().numpy()[:, gold["steps"]]
+    _check(Eg, gold["E"], prec, "cfg2 64^3 full length")

@@ -502,3 +502,33 @@ def test_general_membrane_second_order_off_lattice():
         else:
             assert all(0.8 < v < 1.3 for v in o), o
     assert res[False][-1][1] > 5 * res[True][-1][1]
+
+
+# ---- reaction sub-steps dt' = dt/m (Sec. 2.3) ------------------------------
+
+def test_substeps_plane_wave_varying_within_steps():
+    # cosine waveform sampled 5 times per step: the plane wave advances its
+    # wave vector sample by sample
+    g = w.uniform((6, 5, 4), 0.5)
+    m, dt = 5, 0.01
+    f = w.ogse_cosine_waveform(0.4, 2, 0.9, dt / m)
+    f = f[:len(f) // m * m]
+    gG0 = np.array([0.8, -0.6, 0.5])
+    E, _ = _run(g.comp, g.comp_phase, 1, [0, 0, 0], 0.5, dt, [2.2], [45.0], [[INF]], f,
+                gG0, substeps=m)
+    ref = pins.plane_wave_E((6, 5, 4), 0.5, dt, 2.2, 45.0, f, gG0, substeps=m)
+    assert len(E) == len(f) // m + 1
+    assert np.max(np.abs(E - ref)) < 1e-13
+
+
+@pytest.mark.parametrize("bc", [[0, 0, 0], [1, 1, 1], [1, 0, 1]])
+def test_substeps_of_a_step_constant_waveform_change_nothing(bc):
+    g = w.cylinders_z((12, 10, 4), 0.25, seed=71, vf_target=0.5, periodic=bc[0] == 0)
+    f = w.pgse_waveform(0.3, 0.9, 0.004)
+    args = (g.comp, g.comp_phase, 2, bc, 0.25, 0.004, [2.0, 1.0], [90.0, 70.0],
+            [[INF, 0.03], [0.03, INF]])
+    G = [0.0, 0.0, 4.0] if bc == [1, 1, 1] else [3.0, -2.0, 1.0]
+    E1, M1 = _run(*args, f, G)
+    E3, M3 = _run(*args, np.repeat(f, 3), G, substeps=3)
+    assert np.max(np.abs(E3 - E1)) < 1e-13
+    assert np.max(np.abs(M3 - M1)) < 1e-13
