@@ -51,11 +51,11 @@ def _load():
         lib.oracle_run.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_int32, P, P,
                                    ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                    P, P, P, P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32,
-                                   P, P, ctypes.c_int32]
+                                   P, P, ctypes.c_int32, ctypes.c_int32]
         lib.oracle_run.restype = ctypes.c_int
         lib.oracle_memb_coeffs.argtypes = [ctypes.c_double] * 3 + [P]
         lib.oracle_memb_coeffs.restype = None
-        lib.oracle_tau.argtypes = [ctypes.c_double] * 3
+        lib.oracle_tau.argtypes = [ctypes.c_double] * 3 + [ctypes.c_int32]
         lib.oracle_tau.restype = ctypes.c_double
         _lib = lib
     return _lib
@@ -66,7 +66,8 @@ def _ptr(a):
 
 
 def _run_core(comp, comp_phase, n_phase, bc, off, dx, dt, D, T2, kappa, f, gG0,
-              elo, ehi, threads, want_M, scheme=0, link_delta=None, tile=None, substeps=1):
+              elo, ehi, threads, want_M, scheme=0, link_delta=None, tile=None, substeps=1,
+              lattice=0):
     lib = _load()
     comp = np.ascontiguousarray(comp, dtype=np.uint32)
     n2, n1, n0 = comp.shape
@@ -96,7 +97,8 @@ def _run_core(comp, comp_phase, n_phase, bc, off, dx, dt, D, T2, kappa, f, gG0,
                         _ptr(kappa), _ptr(f), _ptr(gG0), _ptr(elo), _ptr(ehi),
                         _ptr(E), _ptr(M) if want_M else None, int(threads), int(scheme),
                         _ptr(link_delta) if link_delta is not None else None,
-                        _ptr(tile) if tile is not None else None, int(substeps))
+                        _ptr(tile) if tile is not None else None, int(substeps),
+                        int(lattice))
     if rc == -2:
         raise NotImplementedError("oblique gradient on a mirrored axis")
     if rc != 0:
@@ -115,9 +117,13 @@ def memb_coeffs(delta: float, kappa_dt: float, epsd_dx: float) -> np.ndarray:
     return out
 
 
-def tau(D: float, dt: float, dx: float) -> float:
-    """Relaxation time the oracle uses (Eq. tau_def, D3Q7 eps_D = 1/4)."""
-    return float(_load().oracle_tau(D, dt, dx))
+D3Q7, D2Q5 = 0, 1
+
+
+def tau(D: float, dt: float, dx: float, lattice: int = D3Q7) -> float:
+    """Relaxation time the oracle uses (Eq. tau_def; eps_D = 1/4 for D3Q7,
+    1/3 for D2Q5)."""
+    return float(_load().oracle_tau(D, dt, dx, int(lattice)))
 
 
 def needs_doubling(bc, gG0) -> bool:
@@ -135,7 +141,8 @@ HYBRID, CLASSICAL = 0, 1
 
 def simulate(comp, comp_phase, n_phase, bc, dx, dt, D, T2, kappa, f, gG0,
              threads: int = 1, mirror: str = "auto", want_M: bool = True,
-             scheme: int = HYBRID, link_delta=None, substeps: int = 1):
+             scheme: int = HYBRID, link_delta=None, substeps: int = 1,
+             lattice: int = D3Q7):
     """Run the scheme for one gradient vector.
 
     comp (n2, n1, n0) compartment ids, comp_phase [C], bc[3] (0 periodic,
@@ -152,10 +159,14 @@ def simulate(comp, comp_phase, n_phase, bc, dx, dt, D, T2, kappa, f, gG0,
     dx) for the general theta = 0 membrane condition (oracle.c).
     substeps: m reaction sub-steps per step; f then holds K*m samples at
     dt/m (hybrid scheme only).
+    lattice: D3Q7, or D2Q5 on a single layer (n2 = 1, gG0[2] = 0; the z
+    axis is not a lattice axis and its boundary kind is ignored).
     Returns E [K+1] complex and M at t_K, complex (n2, n1, n0).
     """
     comp = np.asarray(comp)
     bc = [int(b) for b in bc]
+    if lattice == D2Q5:
+        bc[2] = PERIODIC
     if mirror == "auto":
         g = np.asarray(gG0, np.float64)
         classical_mirror = scheme == CLASSICAL and any(
@@ -166,7 +177,7 @@ def simulate(comp, comp_phase, n_phase, bc, dx, dt, D, T2, kappa, f, gG0,
         ld = None if link_delta is None else np.asarray(link_delta, np.float32)
         return _run_core(comp, comp_phase, n_phase, bc, [0.0, 0.0, 0.0], dx, dt,
                          D, T2, kappa, f, gG0, [0, 0, 0], [n0, n1, n2], threads, want_M,
-                         scheme, ld, None, substeps)
+                         scheme, ld, None, substeps, lattice)
     if mirror != "double":
         raise ValueError("mirror must be 'auto', 'paper' or 'double'")
     # reflect the REV across the lower face of every mirrored axis: the
@@ -204,7 +215,7 @@ def simulate(comp, comp_phase, n_phase, bc, dx, dt, D, T2, kappa, f, gG0,
         lo[a], hi[a] = na, 2 * na
     bce = [PERIODIC] * 3
     E, M = _run_core(ext, comp_phase, n_phase, bce, off, dx, dt, D, T2, kappa, f,
-                     gG0, lo, hi, threads, want_M, scheme, ld, tile, substeps)
+                     gG0, lo, hi, threads, want_M, scheme, ld, tile, substeps, lattice)
     if want_M:
         M = M[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].copy()
     return E, M
@@ -222,7 +233,7 @@ def simulate_config(cfg: dict, q=None, threads: int = 1, mirror: str = "auto",
                         threads=threads, mirror=mirror, want_M=want_M,
                         scheme=cfg.get("scheme", HYBRID) if scheme is None else scheme,
                         link_delta=getattr(g, "link_delta", None),
-                        substeps=cfg.get("substeps", 1))
+                        substeps=cfg.get("substeps", 1), lattice=cfg.get("lattice", D3Q7))
         Es.append(E)
         Ms.append(M)
     return np.array(Es), Ms

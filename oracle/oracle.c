@@ -47,6 +47,10 @@
  * k multiplies by exp(-i gamma (x.G0) f[k m + j] dt') exp(-dt'/T2), and F
  * advances by f[k m + j] dt' per sub-step.  (Hybrid scheme only.)
  *
+ * lattice = 1 runs the two-dimensional D2Q5 lattice of Sec. 2.2 instead
+ * (Eq. omega_i: eps_D = 1/3, w_0 = 1/3, w_{1..4} = 1/6) on a single layer
+ * (n2 = 1, no gradient along z); every rule above is unchanged.
+ *
  * Lattice: D3Q7 with eps_D = 1/4, w_0 = 1/4, w_{+-x,+-y,+-z} = 1/8.  The
  * paper leaves the 3D weights implicit; eps_D = 1/4 is what its Fig. 11
  * caption requires (tau = 0.58 at D = 2, dt = 0.01, dx = 1), and the weights
@@ -84,14 +88,17 @@
 #include <omp.h>
 #endif
 
-#define Q 7
+#define QMAX 7
 typedef double complex cplx;
 
-static const int EX[Q][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0},
-                             {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
-static const int OPP[Q] = {0, 2, 1, 4, 3, 6, 5};
-static const double W[Q] = {0.25, 0.125, 0.125, 0.125, 0.125, 0.125, 0.125};
-static const double EPS_D = 0.25;
+static const int EX[QMAX][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0},
+                                {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+static const int OPP[QMAX] = {0, 2, 1, 4, 3, 6, 5};
+/* D3Q7: eps_D = 1/4, w_0 = 1/4, w_i = 1/8 (reading above) */
+static const double W7[7] = {0.25, 0.125, 0.125, 0.125, 0.125, 0.125, 0.125};
+/* D2Q5 (Eq. omega_i): eps_D = 1/3, w_0 = 1/3, w_{1..4} = 1/6; directions
+   +-x, +-y are the first five of the table above */
+static const double W5[5] = {1.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0};
 
 enum { BC_PERIODIC = 0, BC_MIRROR = 1 };
 
@@ -175,11 +182,17 @@ int oracle_run(const int32_t n[3], const uint32_t *comp, const uint8_t *comp_pha
                const double *f, const double gG0[3], const int32_t elo[3],
                const int32_t ehi[3], double *E, double *M_out, int32_t nthreads,
                int32_t scheme, const double *link_delta, const int32_t *tile,
-               int32_t substeps) {
+               int32_t substeps, int32_t lattice) {
     const long n0 = n[0], n1 = n[1], n2 = n[2];
     if (n0 < 1 || n1 < 1 || n2 < 1 || dx <= 0 || dt <= 0 || K < 0) return -1;
     if (scheme != 0 && scheme != 1) return -1;
     if (substeps < 1 || (scheme == 1 && substeps != 1)) return -1;
+    if (lattice != 0 && lattice != 1) return -1;
+    /* D2Q5 runs a single layer: n2 = 1, no gradient along z */
+    if (lattice == 1 && (n[2] != 1 || gG0[2] != 0.0)) return -1;
+    const int Q = lattice == 1 ? 5 : 7;
+    const double *W = lattice == 1 ? W5 : W7;
+    const double EPS_D = lattice == 1 ? 1.0 / 3.0 : 0.25;
     const int m_sub = substeps;
     const double dts = dt / m_sub;
     const long N = n0 * n1 * n2;
@@ -457,7 +470,9 @@ int oracle_run(const int32_t n[3], const uint32_t *comp, const uint8_t *comp_pha
 #undef COORD
 }
 
-/* relaxation time of Eq. tau_def for the D3Q7 lattice used above */
-double oracle_tau(double D, double dt, double dx) {
-    return 0.5 + dt * D / (EPS_D * dx * dx);
+/* relaxation time of Eq. tau_def: D3Q7 (lattice 0, eps_D = 1/4) or D2Q5
+   (lattice 1, eps_D = 1/3) */
+double oracle_tau(double D, double dt, double dx, int32_t lattice) {
+    const double eps = lattice == 1 ? 1.0 / 3.0 : 0.25;
+    return 0.5 + dt * D / (eps * dx * dx);
 }

@@ -23,10 +23,12 @@ W = np.array([0.25] + [0.125] * 6)
 E_DIR = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0],
                   [0, 0, 1], [0, 0, -1]])
 OPP = [0, 2, 1, 4, 3, 6, 5]
+# D2Q5 (Sec. 2.2, Eq. omega_i): eps_D = 1/3, rest weight 1/3, four moving 1/6
+LATTICES = {0: (EPS_D, W, 7), 1: (1.0 / 3.0, np.array([1.0 / 3.0] + [1.0 / 6.0] * 4), 5)}
 
 
-def _w(D, dt, dx):
-    return 1.0 / (0.5 + dt * D / (EPS_D * dx * dx))
+def _w(D, dt, dx, eps=EPS_D):
+    return 1.0 / (0.5 + dt * D / (eps * dx * dx))
 
 
 def dirichlet_mean(N, theta):
@@ -35,13 +37,14 @@ def dirichlet_mean(N, theta):
     return np.mean(np.exp(-1j * theta * n))
 
 
-def plane_wave_E(n, dx, dt, D, T2, f, gG0, substeps=1):
+def plane_wave_E(n, dx, dt, D, T2, f, gG0, substeps=1, lattice=0):
     """Signal of the uniform-IC homogeneous periodic problem, all steps.
     With m sub-steps f holds m samples per step, each advancing the wave
-    vector over dt/m."""
-    w = _w(D, dt, dx)
+    vector over dt/m.  lattice 1: D2Q5 on a single layer."""
+    eps, Wl, nq = LATTICES[lattice]
+    w = _w(D, dt, dx, eps)
     decay = 1.0 if math.isinf(T2) else math.exp(-dt / T2)
-    a = W.astype(np.complex128)
+    a = Wl.astype(np.complex128)
     kvec = np.zeros(3)
     gG0 = np.asarray(gG0, np.float64)
     out = []
@@ -53,8 +56,8 @@ def plane_wave_E(n, dx, dt, D, T2, f, gG0, substeps=1):
         out.append(a.sum() * geo)
         if k == K:
             break
-        ah = a - w * (a - W * a.sum())
-        a = ah * np.exp(1j * (E_DIR @ kvec) * dx) * decay
+        ah = a - w * (a - Wl * a.sum())
+        a = ah * np.exp(1j * (E_DIR[:nq] @ kvec) * dx) * decay
         for j in range(substeps):
             kvec = kvec + gG0 * f[k * substeps + j] * (dt / substeps)
     return np.array(out)
@@ -67,7 +70,8 @@ def _cblock(c, conj=False):
     return np.array([[cr, -ci], [ci, cr]])
 
 
-def dense_step_matrices(comp, comp_phase, bc, dx, dt, D, T2, kappa, f, gG0, scheme=0):
+def dense_step_matrices(comp, comp_phase, bc, dx, dt, D, T2, kappa, f, gG0, scheme=0,
+                        lattice=0):
     """Real step matrices A_k (one per step) for a tiny lattice.
 
     scheme 1: classical LBM, the reaction term dt w_i R M inside the
@@ -77,25 +81,26 @@ def dense_step_matrices(comp, comp_phase, bc, dx, dt, D, T2, kappa, f, gG0, sche
     index with x fastest.  Mirror faces use the paper's rule for gradients
     normal or parallel to the face only.
     """
+    eps, Wl, nq = LATTICES[lattice]
     comp = np.asarray(comp)
     n2, n1, n0 = comp.shape
     n = (n0, n1, n2)
     N = n0 * n1 * n2
-    S7 = 7 * N
+    S7 = nq * N
 
     def sidx(j):
         return j[0] + n0 * (j[1] + n1 * j[2])
 
     ph = np.asarray(comp_phase)[comp.reshape(-1)]
-    w = np.array([_w(D[p], dt, dx) for p in ph])
+    w = np.array([_w(D[p], dt, dx, eps) for p in ph])
     dec = np.array([1.0 if math.isinf(T2[p]) else math.exp(-dt / T2[p]) for p in ph])
     # collision (acts identically on Re and Im)
     C = np.zeros((S7, S7))
     for s in range(N):
-        for i in range(7):
+        for i in range(nq):
             C[i * N + s, i * N + s] += 1.0 - w[s]
-            for j in range(7):
-                C[i * N + s, j * N + s] += w[s] * W[i]
+            for j in range(nq):
+                C[i * N + s, j * N + s] += w[s] * Wl[i]
     Cr = np.kron(np.eye(2), C)
     inv_t2 = np.array([0.0 if math.isinf(T2[p]) else 1.0 / T2[p] for p in ph])
     mats = []
@@ -113,7 +118,7 @@ def dense_step_matrices(comp, comp_phase, bc, dx, dt, D, T2, kappa, f, gG0, sche
         for s in range(N):
             j = (s % n0, (s // n0) % n1, s // (n0 * n1))
             cx = comp.reshape(-1)[s]
-            for i in range(7):
+            for i in range(nq):
                 src = [j[a] - E_DIR[i][a] for a in range(3)]
                 crossed = [a for a in range(3) if not 0 <= src[a] < n[a]]
                 terms = []      # (source flat index, coefficient, conj)
@@ -144,7 +149,7 @@ def dense_step_matrices(comp, comp_phase, bc, dx, dt, D, T2, kappa, f, gG0, sche
                     if kap == 0.0:
                         t, r = 0.0, 1.0
                     else:
-                        P = EPS_D * dx / (2.0 * kap * dt)
+                        P = eps * dx / (2.0 * kap * dt)
                         t, r = 1.0 / (1.0 + P), P / (1.0 + P)
                     for (src_i, c, cj) in terms:
                         add(i * N + s, src_i, c, cj, t)
@@ -159,9 +164,9 @@ def dense_step_matrices(comp, comp_phase, bc, dx, dt, D, T2, kappa, f, gG0, sche
                 j = (s_ % n0, (s_ // n0) % n1, s_ // (n0 * n1))
                 xg = sum(gG0[a] * j[a] * dx for a in range(3))
                 Rc = (-1j * xg * f[k] - inv_t2[s_]) * dt
-                for i in range(7):
-                    for jj in range(7):
-                        blk = W[i] * _cblock(Rc)
+                for i in range(nq):
+                    for jj in range(nq):
+                        blk = Wl[i] * _cblock(Rc)
                         for pd in range(2):
                             for ps in range(2):
                                 Ck[pd * S7 + i * N + s_, ps * S7 + jj * N + s_] += blk[pd, ps]
@@ -175,7 +180,7 @@ def dense_step_matrices(comp, comp_phase, bc, dx, dt, D, T2, kappa, f, gG0, sche
             xg = sum(gG0[a] * j[a] * dx for a in range(3))
             c = np.exp(-1j * xg * f[k] * dt) * dec[s]
             blk = _cblock(c)
-            for i in range(7):
+            for i in range(nq):
                 for pd in range(2):
                     for ps in range(2):
                         R[pd * S7 + i * N + s, ps * S7 + i * N + s] = blk[pd, ps]
@@ -184,12 +189,13 @@ def dense_step_matrices(comp, comp_phase, bc, dx, dt, D, T2, kappa, f, gG0, sche
     return mats
 
 
-def dense_run(mats, N):
+def dense_run(mats, N, lattice=0):
     """E_k for the uniform initial state, all steps."""
-    S7 = 7 * N
+    _, Wl, nq = LATTICES[lattice]
+    S7 = nq * N
     v = np.zeros(2 * S7)
-    for i in range(7):
-        v[i * N:(i + 1) * N] = W[i]
+    for i in range(nq):
+        v[i * N:(i + 1) * N] = Wl[i]
     out = []
     for k in range(len(mats) + 1):
         out.append((v[:S7].sum() + 1j * v[S7:].sum()) / N)

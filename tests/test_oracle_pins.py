@@ -456,7 +456,7 @@ _SLAB_D, _SLAB_T2, _SLAB_G = [1.5, 1.0, 2.0], [60.0, 50.0, 80.0], 0.25
 _slab_refs = {}
 
 
-def _slab_case(m, general, kappa=0.05):
+def _slab_case(m, general, kappa=0.05, lattice=0):
     # 1D: outer compartment C, permeable pair A | B on [X, 3X] walled off from
     # C by impermeable membranes; interfaces at X, 2X, 3X and spacing
     # dx = X/(m + alpha), so every refinement sees the same sub-link
@@ -466,7 +466,7 @@ def _slab_case(m, general, kappa=0.05):
     n = int(math.floor(3 * (m + _SLAB_ALPHA))) + 5
     x = np.arange(n) * dx
     comp = np.where(x < X, 0, np.where(x < 2 * X, 1, np.where(x < 3 * X, 2, 0)))
-    dt = 0.3 * EPSD * dx * dx / _SLAB_D[1]
+    dt = 0.3 * (EPSD if lattice == 0 else 1.0 / 3.0) * dx * dx / _SLAB_D[1]
     K = int(math.ceil(8.0 / dt))
     f = pins.step_average_pgse(2.0, 6.0, dt, K)
     kap = [[INF, 0.0, 0.0], [0.0, INF, kappa], [0.0, kappa, INF]]
@@ -475,9 +475,9 @@ def _slab_case(m, general, kappa=0.05):
         j = int(math.floor(c * X / dx))
         ld[0, 0, 0, j] = (c * X - j * dx) / dx
     _, M = _run(comp.reshape(1, 1, n), [0, 1, 2], 3, [0, 0, 0], dx, dt, _SLAB_D, _SLAB_T2,
-                kap, f, [_SLAB_G, 0, 0], link_delta=ld if general else None)
+                kap, f, [_SLAB_G, 0, 0], link_delta=ld if general else None, lattice=lattice)
     inside = (x > X) & (x < 3 * X)
-    key = (m, kappa)
+    key = (m, kappa, lattice)
     if key not in _slab_refs:
         r = [pins.slab_fv_reference([X, 2 * X, 3 * X], _SLAB_D[1:], _SLAB_T2[1:], [kappa],
                                     _SLAB_G, f, dt, x[inside], cells) for cells in (40, 80)]
@@ -532,3 +532,105 @@ def test_substeps_of_a_step_constant_waveform_change_nothing(bc):
     E3, M3 = _run(*args, np.repeat(f, 3), G, substeps=3)
     assert np.max(np.abs(E3 - E1)) < 1e-13
     assert np.max(np.abs(M3 - M1)) < 1e-13
+
+
+# ---- D2Q5 lattice on a single layer (Sec. 2.2) ------------------------------
+
+D2Q5 = 1
+
+
+def test_d2q5_plane_wave():
+    g = w.uniform((7, 5, 1), 0.5)
+    f = w.pgse_waveform(0.05, 0.2, 0.01)
+    gG0 = np.array([0.9, -0.7, 0.0])
+    E, _ = _run(g.comp, g.comp_phase, 1, [0, 0, 0], 0.5, 0.01, [2.5], [30.0], [[INF]], f,
+                gG0, lattice=D2Q5)
+    ref = pins.plane_wave_E((7, 5, 1), 0.5, 0.01, 2.5, 30.0, f, gG0, lattice=D2Q5)
+    assert np.max(np.abs(E - ref)) < 1e-13
+    # mirrored faces with an axis-aligned gradient keep the plane wave exact
+    E, _ = _run(g.comp, g.comp_phase, 1, [1, 1, 1], 0.5, 0.01, [2.5], [30.0], [[INF]], f,
+                [0.0, 1.2, 0.0], lattice=D2Q5, mirror="paper")
+    ref = pins.plane_wave_E((7, 5, 1), 0.5, 0.01, 2.5, 30.0, f, [0.0, 1.2, 0.0],
+                            lattice=D2Q5)
+    assert np.max(np.abs(E - ref)) < 1e-13
+
+
+@pytest.mark.parametrize("bc,scheme", [([0, 0, 0], 0), ([1, 1, 0], 0), ([1, 0, 0], 0),
+                                       ([0, 0, 0], 1), ([1, 0, 0], 1)])
+def test_d2q5_dense_bruteforce(bc, scheme):
+    comp = np.zeros((1, 4, 5), np.uint32)
+    comp[0, 1:3, 1:4] = 1
+    comp[0, 3, 4] = 2
+    cp = np.array([0, 1, 1], np.uint8)
+    kap = np.array([[INF, 0.03], [0.03, 0.01]])
+    D, T2 = [2.0, 0.7], [30.0, 12.0]
+    dx, dt = 0.5, 0.01
+    f = np.array([1.0, 1.0, 0.3, 0.0, -0.5, -1.0, -1.0, 0.2])
+    # gradients normal to a mirrored face use the conjugate rule (hybrid);
+    # the classical scheme takes gradients parallel to mirrored faces
+    if bc == [1, 1, 0]:
+        gG0 = np.array([0.0, 0.9, 0.0])
+    elif bc == [1, 0, 0]:
+        gG0 = np.array([1.1, 0.0, 0.0]) if scheme == 0 else np.array([0.0, 0.9, 0.0])
+    else:
+        gG0 = np.array([1.1, -0.6, 0.0])
+    mats = pins.dense_step_matrices(comp, cp, bc, dx, dt, D, T2, kap, f, gG0, scheme=scheme,
+                                    lattice=D2Q5)
+    ref = pins.dense_run(mats, comp.size, lattice=D2Q5)
+    E, _ = _run(comp, cp, 2, bc, dx, dt, D, T2, kap, f, gG0, mirror="paper" if scheme == 0
+                else "double", scheme=scheme, lattice=D2Q5)
+    assert np.max(np.abs(E - ref)) < 1e-14
+
+
+def test_d2q5_uniform_ic_closed_form_and_diffusivity():
+    # Sec. 3.1 uniform initial condition: exp(-bD) exp(-TE/T2) to second
+    # order; the diffusivity recovered from the signal is the one put in only
+    # with the D2Q5 lattice constant eps_D = 1/3 in tau
+    gold = _load("uniform_ic_exact.json")
+    D, T2, delta, Delta = gold["D"], gold["T2"], gold["delta"], gold["Delta"]
+    gG = w.gamma_g_for_b_pgse(gold["b"], delta, Delta)
+    errs = []
+    for dx in (0.5, 0.25):
+        dt = 0.01 * (dx / 0.5) ** 2
+        f = w.pgse_waveform(delta, Delta, dt)
+        g = w.uniform((4, 3, 1), dx)
+        E, _ = _run(g.comp, g.comp_phase, 1, [0, 0, 0], dx, dt, [D], [T2], [[INF]], f,
+                    [gG, 0, 0], want_M=False, lattice=D2Q5)
+        errs.append(abs(E[-1].real - gold["E_TE"]) / gold["E_TE"])
+        D_app = -math.log(E[-1].real / math.exp(-gold["TE"] / T2)) / gold["b"]
+        assert D_app == pytest.approx(D, rel=2e-3)
+    assert errs[0] < 3e-3 and 3.5 < errs[0] / errs[1] < 4.5
+
+
+def test_d2q5_impermeable_plates_diffraction():
+    n, dx, dt = 20, 0.25, 0.002
+    g = w.slabs((2 * n, 1, 1), dx, [n])
+    f = np.zeros(40001)
+    f[0], f[-1] = 1.0, -1.0
+    a = n * dx
+    for qa in (0.5 * math.pi, 2 * math.pi):
+        q = qa / a
+        E, _ = _run(g.comp, g.comp_phase, 1, [0, 0, 0], dx, dt, [2.3], [INF], [[0.0]], f,
+                    [q / dt, 0, 0], want_M=False, lattice=D2Q5)
+        lat = abs(np.mean(np.exp(-1j * q * dx * np.arange(n)))) ** 2
+        assert abs(E[-1] - lat) < 1e-12
+
+
+def test_d2q5_rejects_3d_input():
+    g = w.uniform((4, 3, 2), 0.5)
+    with pytest.raises(ValueError):
+        _run(g.comp, g.comp_phase, 1, [0, 0, 0], 0.5, 0.01, [2.0], [INF], [[INF]],
+             np.zeros(3), [1.0, 0, 0], lattice=D2Q5)
+    g = w.uniform((4, 3, 1), 0.5)
+    with pytest.raises(ValueError):
+        _run(g.comp, g.comp_phase, 1, [0, 0, 0], 0.5, 0.01, [2.0], [INF], [[INF]],
+             np.zeros(3), [1.0, 0, 0.5], lattice=D2Q5)
+
+
+def test_d2q5_general_membrane_second_order_off_lattice():
+    # the slab problem above on the D2Q5 lattice (eps_D = 1/3 in tau, P and
+    # the membrane coefficients)
+    r = [_slab_case(m, True, lattice=D2Q5) for m in (4, 9, 19)]
+    o = [math.log(r[i][1] / r[i + 1][1]) / math.log(r[i][0] / r[i + 1][0]) for i in range(2)]
+    print([f"{e:.3e}" for _, e in r], o)
+    assert all(1.8 < v < 2.2 for v in o), o
