@@ -52,6 +52,7 @@ WORKLOAD_NAMES = {
     "cfg3b": "16 cylinder geometries 96^3..192^3 (ragged batch), 6 directions each",
     "cfg4": "two-phase cylinders 96^3 periodic, 30 directions",
     "cfg5": "three-phase ellipsoid cells 512^3 periodic, cosine OGSE, 32 directions",
+    "cfg2d": "2D axon cross-sections 512^2 on the D2Q5 lattice, 64 in-plane dirs x 4 b-values",
 }
 
 
@@ -118,15 +119,19 @@ def cpu_baseline(cfg, budget_s: float = 15.0):
     g = cfg["geoms"][0]
     args = (g.comp, g.comp_phase, g.n_phase, cfg["bc"], cfg["dx"], cfg["dt"], cfg["D"],
             cfg["T2"], cfg["kappa"])
+    lat = cfg.get("lattice", 0)
+
     def run(n):
         t0 = time.perf_counter()
-        oracle.simulate(*args, cfg["f"][:n], cfg["gG0"][0], threads=threads, want_M=False)
+        oracle.simulate(*args, cfg["f"][:n], cfg["gG0"][0], threads=threads, want_M=False,
+                        lattice=lat)
         return time.perf_counter() - t0
     # per-step cost from two short runs (their difference removes the setup)
     per = max((run(3) - run(1)) / 2.0, 1e-3)
     n = int(max(1, min(400, budget_s / per)))
     t0 = time.perf_counter()
-    oracle.simulate(*args, cfg["f"][:n], cfg["gG0"][0], threads=threads, want_M=False)
+    oracle.simulate(*args, cfg["f"][:n], cfg["gG0"][0], threads=threads, want_M=False,
+                    lattice=lat)
     t1 = time.perf_counter()
     sites = g.comp.size
     note = ("; the oracle steps the reflected, doubled domain"
@@ -236,16 +241,19 @@ def main():
 
     K, W = args.steps, args.warmup
     log(f"building workload {args.workload}")
-    if args.membranes == "positions":
-        args.no_adjoint = True
+    if args.membranes == "positions" or args.workload == "cfg2d":
+        args.no_adjoint = True          # the adjoint covers D3Q7 half-link runs
     cfg = workload(args.workload, max(K, W, 0 if args.no_adjoint else args.adj_steps),
                    args.membranes)
     Q = len(cfg["gG0"])
     qs = q_sites(cfg)
     fs = field_sites(cfg)
     sites = cfg["geoms"][0].comp.size
-    sim = btl.Simulator(cfg["geoms"], cfg["bc"], args.prec)
-    bpf = BYTES_PER_FIELD_SITE_F32 if args.prec == "f32" else BYTES_PER_FIELD_SITE_F64
+    lattice = cfg.get("lattice", 0)
+    nq = 5 if lattice == 1 else 7
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], args.prec, lattice=lattice)
+    # read nq complex populations + write nq, per field site
+    bpf = (BYTES_PER_FIELD_SITE_F32 if args.prec == "f32" else BYTES_PER_FIELD_SITE_F64) * nq // 7
     log("first forward")
     time_forward(sim, cfg, max(W, 1), bpf)
     if not args.no_autotune:
@@ -266,7 +274,7 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": (traffic_for(ms_step) if args.workload == "cfg2" and args.prec == "f32"
                         and args.membranes == "half-link" else None),
-            "kernel": f"k_step<{'float2' if args.prec == 'f32' else 'double2'}>",
+            "kernel": f"k_step<{'float2' if args.prec == 'f32' else 'double2'}, {'D2Q5' if nq == 5 else 'D3Q7'}>",
             "bytes_per_launch_algorithmic": bytes_launch}
     out = {"metric": METRIC, "value": value, "unit": "site-updates/s", "n_gpus": 1,
            "steps": K, "warmup": W, "ms_per_step": ms_step, "higher_is_better": True,
@@ -281,7 +289,7 @@ def main():
         log("FP64 comparison runs")
         # stated error vs FP64 storage over the same steps, and the plain FP64
         # one-sample-per-launch form as the speedup denominator
-        sim64 = btl.Simulator(cfg["geoms"], cfg["bc"], "f64")
+        sim64 = btl.Simulator(cfg["geoms"], cfg["bc"], "f64", lattice=lattice)
         ms64, E64 = time_forward(sim64, cfg, K, BYTES_PER_FIELD_SITE_F64)
         e32 = E.cpu().numpy()
         e64 = E64.cpu().numpy()

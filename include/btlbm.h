@@ -64,6 +64,7 @@ typedef enum {
 enum { BTL_PERIODIC = 0, BTL_MIRROR = 1 };   /* outer boundary per axis */
 enum { BTL_F64 = 0, BTL_F32 = 1 };           /* population storage precision */
 enum { BTL_HYBRID = 0, BTL_CLASSICAL = 1 };  /* time integration scheme */
+enum { BTL_D3Q7 = 0, BTL_D2Q5 = 1 };         /* lattice */
 
 /* One geometry: a compartment-label volume.  Every lattice link joining two
  * different compartments carries a membrane whose permeability is chosen by
@@ -71,7 +72,8 @@ enum { BTL_HYBRID = 0, BTL_CLASSICAL = 1 };  /* time integration scheme */
  * Sec. 3.6 are links between different compartments of one phase).  The
  * pointers are host memory and are copied by btl_create. */
 typedef struct {
-    int32_t n[3];               /* sites per axis, x fastest; each >= 2 */
+    int32_t n[3];               /* sites per axis, x fastest; n[0], n[1] >= 2,
+                                 * n[2] >= 1 (1: a single layer) */
     double dx;                  /* lattice spacing, um, > 0 */
     int32_t bc[3];              /* BTL_PERIODIC or BTL_MIRROR per axis */
     int32_t n_comp;             /* number of compartments C >= 1 */
@@ -143,6 +145,16 @@ btl_status btl_forward(btl_sim *s, double dt, int32_t K, const double *D,
  * Errors: BTL_E_INVAL (no tape), BTL_E_NOMEM, BTL_E_HIP. */
 btl_status btl_backward(btl_sim *s, const double *dL_dE, double *dD, double *dT2,
                         double *dkappa, double *df, void *stream);
+
+/* Select the lattice of later btl_forward calls.  BTL_D3Q7 (default):
+ * eps_D = 1/4, w_0 = 1/4, w_i = 1/8.  BTL_D2Q5: the two-dimensional lattice
+ * of Sec. 2.2 (Eq. omega_i: eps_D = 1/3, w_0 = 1/3, w_{1..4} = 1/6) on
+ * single-layer geometries (n[2] = 1) with no gradient along z; eps_D enters
+ * tau (Eq. tau_def) and the membrane number P (Eq. P_def), every other rule
+ * is unchanged.  A D2Q5 forward returns BTL_E_INVAL for a geometry with
+ * n[2] != 1 or a q-sample with gG0 z != 0, and BTL_E_UNSUPPORTED when it
+ * asks for an adjoint tape.  Errors: BTL_E_INVAL (unknown lattice). */
+btl_status btl_set_lattice(btl_sim *s, int32_t lattice);
 
 /* Reaction sub-stepping (Sec. 2.3: the reaction may run with its own time
  * step dt' = dt/m while diffusion keeps dt).  Later btl_forward calls take

@@ -2,8 +2,8 @@
 
 Argument marshalling only: every step of the computation runs in the HIP
 kernels of libbtlbm.so.  The functions `btl_create`, `btl_forward`,
-`btl_backward`, `btl_set_scheme`, `btl_set_substeps`, `btl_autotune`,
-`btl_destroy` and `btl_last_error` mirror the
+`btl_backward`, `btl_set_scheme`, `btl_set_lattice`, `btl_set_substeps`,
+`btl_autotune`, `btl_destroy` and `btl_last_error` mirror the
 C ABI of include/btlbm.h one to one.  `Simulator` wraps them with torch
 tensors for device memory and the current torch stream.
 
@@ -25,9 +25,11 @@ BTL_OK, BTL_E_INVAL, BTL_E_UNSUPPORTED, BTL_E_NOMEM, BTL_E_HIP, BTL_E_NONFINITE 
 BTL_PERIODIC, BTL_MIRROR = 0, 1
 BTL_F64, BTL_F32 = 0, 1
 BTL_HYBRID, BTL_CLASSICAL = 0, 1
+BTL_D3Q7, BTL_D2Q5 = 0, 1
 
 EXPORTED = ("btl_create", "btl_forward", "btl_backward", "btl_set_scheme",
-            "btl_set_substeps", "btl_autotune", "btl_destroy", "btl_last_error")
+            "btl_set_lattice", "btl_set_substeps", "btl_autotune", "btl_destroy",
+            "btl_last_error")
 
 
 class BtlError(RuntimeError):
@@ -68,6 +70,8 @@ def load_library(path: str = None):
     lib.btl_backward.restype = ctypes.c_int
     lib.btl_set_scheme.argtypes = [P, i32]
     lib.btl_set_scheme.restype = ctypes.c_int
+    lib.btl_set_lattice.argtypes = [P, i32]
+    lib.btl_set_lattice.restype = ctypes.c_int
     lib.btl_set_substeps.argtypes = [P, i32]
     lib.btl_set_substeps.restype = ctypes.c_int
     lib.btl_autotune.argtypes = [P, i32, i32, P]
@@ -154,6 +158,10 @@ def btl_set_scheme(h, scheme):
     _check(load_library().btl_set_scheme(h, int(scheme)), h)
 
 
+def btl_set_lattice(h, lattice):
+    _check(load_library().btl_set_lattice(h, int(lattice)), h)
+
+
 def btl_set_substeps(h, m):
     _check(load_library().btl_set_substeps(h, int(m)), h)
 
@@ -188,7 +196,7 @@ class Simulator:
     """Owns one btl_sim.  Device memory for E and M_final comes from torch."""
 
     def __init__(self, geoms, bc, prec: str = "f32", scheme: int = BTL_HYBRID,
-                 substeps: int = 1):
+                 substeps: int = 1, lattice: int = BTL_D3Q7):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Simulator needs a HIP device")
@@ -199,6 +207,8 @@ class Simulator:
         self._h = btl_create([_GeomBC(g, b) for g, b in zip(self.geoms, bcs)], self.prec)
         if scheme != BTL_HYBRID:
             btl_set_scheme(self._h, scheme)
+        if lattice != BTL_D3Q7:
+            btl_set_lattice(self._h, lattice)
         self.substeps = int(substeps)
         if self.substeps != 1:
             btl_set_substeps(self._h, self.substeps)
@@ -318,10 +328,12 @@ def bloch_torrey_signal(D, T2, kappa, f, sim, dt, gG0, q_geom=None, ckpt_every=1
 def simulate_config(cfg: dict, prec: str = "f32", want_M: bool = False, scheme=None):
     """Run a workloads config on the GPU: returns E (Q, K+1) complex (and M).
     The scheme is `scheme`, else the config's "scheme" entry, else hybrid;
-    the config's "substeps" entry (default 1) sets reaction sub-steps."""
+    the config's "substeps" entry (default 1) sets reaction sub-steps and its
+    "lattice" entry (default D3Q7) the lattice."""
     if scheme is None:
         scheme = cfg.get("scheme", BTL_HYBRID)
-    sim = Simulator(cfg["geoms"], cfg["bc"], prec, scheme, cfg.get("substeps", 1))
+    sim = Simulator(cfg["geoms"], cfg["bc"], prec, scheme, cfg.get("substeps", 1),
+                    cfg.get("lattice", BTL_D3Q7))
     try:
         out = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"],
                           cfg["gG0"], cfg["q_geom"], want_M=want_M)

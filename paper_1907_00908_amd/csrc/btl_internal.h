@@ -13,6 +13,13 @@ constexpr int kMaxZc = 4096;   // longest z column one thread walks
 constexpr int kTabSteps = 32;  // steps whose phase tables one table launch computes
 constexpr int kMaxPhase = 8;   // material phases (3-bit neighbour phase in the site word)
 
+// Lattices: D3Q7 (nq = 7: eps_D = 1/4, w_0 = 1/4, w_i = 1/8) and, on a single
+// layer, D2Q5 (nq = 5: the first five directions; Sec. 2.2, Eq. omega_i:
+// eps_D = 1/3, w_0 = 1/3, w_i = 1/6).
+__host__ __device__ constexpr double lattice_w0(int nq) { return nq == 5 ? 1.0 / 3.0 : 0.25; }
+__host__ __device__ constexpr double lattice_w1(int nq) { return nq == 5 ? 1.0 / 6.0 : 0.125; }
+__host__ __device__ constexpr double lattice_eps(int nq) { return nq == 5 ? 1.0 / 3.0 : 0.25; }
+
 // Face f = 2*a + h of axis a: h = 0 the low face (node 0, pulls direction
 // +a), h = 1 the high face (node n_a - 1, pulls direction -a).
 enum FaceKind : int32_t {
@@ -110,13 +117,19 @@ struct StepArgs {
     int32_t k;
     int32_t K;
     int32_t classical;      // 1: reaction term in the collision, no split
-    int32_t pad1;
+    int32_t nq;             // 7 (D3Q7) or 5 (D2Q5 on a single layer)
 };
 
 // Workgroup tile shapes (TX x TY threads, one site column along z each).
-enum TileShape : int32_t { kTile64x4 = 0, kTile32x8 = 1, kTile16x16 = 2, kTile128x2 = 3, kTileCount = 4 };
+// kTile256x1 serves single-layer (D2Q5) lattices only, whose rows are walked
+// as columns (see kernel_geom in the runtime).
+enum TileShape : int32_t {
+    kTile64x4 = 0, kTile32x8 = 1, kTile16x16 = 2, kTile128x2 = 3, kTile256x1 = 4,
+    kTileCount3D = 4, kTileCount = 5
+};
 inline void tile_dims(int shape, int* tx, int* ty) {
-    *tx = shape == kTile64x4 ? 64 : shape == kTile32x8 ? 32 : shape == kTile128x2 ? 128 : 16;
+    *tx = shape == kTile64x4 ? 64 : shape == kTile32x8 ? 32 : shape == kTile128x2 ? 128
+        : shape == kTile256x1 ? 256 : 16;
     *ty = kBlock / *tx;
 }
 
@@ -128,17 +141,17 @@ hipError_t launch_adj_final(const double* gfield, int32_t K, int32_t n_fields, i
                             double* df, int32_t sub, hipStream_t st);
 hipError_t launch_init(int prec, void* pop, int64_t n_elem_per_dir_total,
                        const FieldDesc* d_fields, int32_t n_fields,
-                       const FieldDesc* h_fields, double* E, int32_t Q, int32_t K,
+                       const FieldDesc* h_fields, double* E, int32_t Q, int32_t K, int32_t nq,
                        hipStream_t st);
 hipError_t launch_step(int prec, int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st);
 // initial post-collision state of the classical scheme (depends on R at t^0)
 // (fdt: the waveform table f_k dt, of which the kernel reads entry 0)
 hipError_t launch_init_classical(int prec, void* pop, const FieldDesc* h_fields, int32_t n_fields,
                                  const uint32_t* words, const double* fdt, const double* rdt,
-                                 hipStream_t st);
+                                 int32_t nq, hipStream_t st);
 // phase tables of steps a.k .. a.k + nsteps - 1 into a.tab[0 .. nsteps*T)
 hipError_t launch_tables(const StepArgs& a, int32_t nsteps, hipStream_t st);
 hipError_t launch_mfinal(int prec, const void* pop, const FieldDesc* h_fields,
-                         int32_t n_fields, void* M_out, hipStream_t st);
+                         int32_t n_fields, void* M_out, int32_t nq, hipStream_t st);
 
 }  // namespace btl

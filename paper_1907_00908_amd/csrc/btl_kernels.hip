@@ -37,11 +37,11 @@ namespace btl {
 
 template <typename V>
 __global__ void __launch_bounds__(kBlock) k_init(V* pop, int64_t nsites, double2* E,
-                                                  int32_t q, int32_t K) {
+                                                  int32_t q, int32_t K, int32_t nq) {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e < nsites * kQ) {
+    if (e < nsites * nq) {
         const int d = (int)(e / nsites);
-        store2(pop + e, make_double2(d == 0 ? 0.25 : 0.125, 0.0));
+        store2(pop + e, make_double2(d == 0 ? lattice_w0(nq) : lattice_w1(nq), 0.0));
     }
     if (E != nullptr && q >= 0 && e == 0) E[(int64_t)q * (K + 1)] = make_double2(1.0, 0.0);
 }
@@ -77,9 +77,15 @@ __global__ void __launch_bounds__(kBlock) k_tables(StepArgs a, int32_t nsteps) {
 // R = -i gamma (x.G0) f_{k+1} - 1/T2, the reaction term of the collision that
 // follows the moment M(t^{k+1}).  The last step stores the plain collision,
 // whose moment is M(t^K).
-template <typename V, int TX, bool CL, bool GM>
+template <typename V, int TX, bool CL, bool GM, int NQ>
 __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     constexpr int TY = kBlock / TX;
+    constexpr double W0 = lattice_w0(NQ), W1 = lattice_w1(NQ);
+    // Plane p >= 1 moves along kernel direction kd(p): D3Q7 p itself; the
+    // single-layer D2Q5 lattice runs with its y axis as the kernel's z axis
+    // (planes 3, 4 pull along z), while site words and membrane positions
+    // keep the geometry's own direction numbering, which is p.
+    auto face_of = [](int p) { return NQ == 7 ? p - 1 : (p <= 2 ? p - 1 : p + 1); };
     __shared__ double2 lds[kBlock / 64];
     __shared__ double c_w[kMaxPhase], c_dec[kMaxPhase], c_tr[kMaxPhase * kMaxPhase];
     __shared__ double c_kdt[GM ? kMaxPhase * kMaxPhase : 1];
@@ -154,8 +160,10 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     const int32_t o2 = fx1 ? face_off(1, 2, -(n0 - 1)) : pop + 2 * ns + 1;
     const int32_t o3 = fy0 ? face_off(2, 3, (n1 - 1) * st1) : pop + 3 * ns - st1;
     const int32_t o4 = fy1 ? face_off(3, 4, -(n1 - 1) * st1) : pop + 4 * ns + st1;
-    const int32_t o5i = pop + 5 * ns - st2, o5f = face_off(4, 5, (n2 - 1) * st2);
-    const int32_t o6i = pop + 6 * ns + st2, o6f = face_off(5, 6, -(n2 - 1) * st2);
+    // z pulls of planes pz (+z) and pz + 1 (-z): interior and face offsets
+    constexpr int pz = NQ == 7 ? 5 : 3;
+    const int32_t o5i = pop + pz * ns - st2, o5f = face_off(4, pz, (n2 - 1) * st2);
+    const int32_t o6i = pop + (pz + 1) * ns + st2, o6f = face_off(5, pz + 1, -(n2 - 1) * st2);
 
     // Loads of one site: the site word, the seven pulled populations, the
     // six outgoing populations of the node itself (reflected at membrane
@@ -164,8 +172,8 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     // waiting for a site's data never waits for earlier stores.
     struct SiteLoads {
         uint32_t word;
-        V g[kQ];
-        V own[kQ - 1];
+        V g[NQ];
+        V own[NQ - 1];
         double2 ez;
     };
     auto issue = [&](int32_t j2, SiteLoads& L) {
@@ -174,12 +182,14 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
         L.g[0] = src[pop + s];
         L.g[1] = src[o1 + s];
         L.g[2] = src[o2 + s];
-        L.g[3] = src[o3 + s];
-        L.g[4] = src[o4 + s];
-        L.g[5] = src[(j2 == 0 ? o5f : o5i) + s];
-        L.g[6] = src[(j2 == n2 - 1 ? o6f : o6i) + s];
+        if constexpr (NQ == 7) {
+            L.g[3] = src[o3 + s];
+            L.g[4] = src[o4 + s];
+        }
+        L.g[pz] = src[(j2 == 0 ? o5f : o5i) + s];
+        L.g[pz + 1] = src[(j2 == n2 - 1 ? o6f : o6i) + s];
 #pragma unroll
-        for (int d = 1; d < kQ; ++d) {
+        for (int d = 1; d < NQ; ++d) {
             const int od = (d & 1) ? d + 1 : d - 1;
             L.own[d - 1] = src[pop + od * ns + s];
         }
@@ -191,29 +201,30 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
         const uint32_t word = L.word;
         const int p = (int)(word & 0xfu);
         const uint32_t mask = (word >> 4) & 0x3fu;
-        double2 g[kQ];
+        double2 g[NQ];
 #pragma unroll
-        for (int d = 0; d < kQ; ++d) g[d] = ld2(&L.g[d]);
+        for (int d = 0; d < NQ; ++d) g[d] = ld2(&L.g[d]);
         const bool face[6] = {fx0, fx1, fy0, fy1, fz0, fz1};
 #pragma unroll
-        for (int f = 0; f < 6; ++f) {
+        for (int p = 1; p < NQ; ++p) {
+            const int f = face_of(p);
             if (face[f]) {
-                double2 v = g[f + 1];
+                double2 v = g[p];
                 if (kind[f] & kFaceConj) v.y = -v.y;
-                g[f + 1] = cmul(v, face_fac[f]);
+                g[p] = cmul(v, face_fac[f]);
             }
         }
         if (mask) {
             // membrane positions of the pulled links (0: half-link rule)
-            float gv[kQ - 1];
+            float gv[NQ - 1];
 #pragma unroll
-            for (int d = 1; d < kQ; ++d)
+            for (int d = 1; d < NQ; ++d)
                 gv[d - 1] = (GM && gmt && ((mask >> (d - 1)) & 1u)) ? gmt[(d - 1) * ns + s] : 0.0f;
             // half-link membrane: g' = ghat_opp(x) + t (incoming - ghat_opp(x));
             // links with a position are collected in gen
             uint32_t gen = 0;
 #pragma unroll
-            for (int d = 1; d < kQ; ++d) {
+            for (int d = 1; d < NQ; ++d) {
                 if ((mask >> (d - 1)) & 1u) {
                     const int pn = (int)((word >> (10 + 3 * (d - 1))) & 0x7u);
                     const double t = c_tr[p * P + pn];
@@ -240,7 +251,7 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
                     double2 b1 = g[1], o = ld2(&L.own[0]), a3 = ld2(&L.own[1]);
                     float v = gv[0];
 #pragma unroll
-                    for (int k = 2; k < kQ; ++k)
+                    for (int k = 2; k < NQ; ++k)
                         if (d == k) {
                             const int ok = (k & 1) ? k + 1 : k - 1;
                             b1 = g[k];
@@ -252,7 +263,7 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
                     const double dd = v > 0.0f ? (double)v : 1.0 + (double)v;
                     const MembCoef c = membrane_coefficients(dd, c_kdt[p * P + pn], a.edx);
                     const int od = (d & 1) ? d + 1 : d - 1;
-                    const int32_t sa = d <= 2 ? 1 : d <= 4 ? st1 : st2;
+                    const int32_t sa = d <= 2 ? 1 : (NQ == 7 && d <= 4) ? st1 : st2;
                     const int32_t e = (d & 1) ? sa : -sa;
                     const double2 a2 = ld2(src + od * ns + s + e);
                     const double2 b2 = ld2(src + d * ns + s - 2 * e);
@@ -263,7 +274,7 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
                     r.y = c.A[0] * o.y + c.A[1] * a2.y + c.A[2] * a3.y
                         + c.B[0] * b1.y + c.B[1] * b2.y + c.B[2] * b3.y;
 #pragma unroll
-                    for (int k = 1; k < kQ; ++k)
+                    for (int k = 1; k < NQ; ++k)
                         if (d == k) g[k] = r;
                 }
             }
@@ -275,10 +286,10 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
             const double dec = c_dec[p];
             const double2 rf = make_double2(e.x * dec, e.y * dec);
 #pragma unroll
-            for (int d = 0; d < kQ; ++d) g[d] = cmul(g[d], rf);
+            for (int d = 0; d < NQ; ++d) g[d] = cmul(g[d], rf);
         }
 #pragma unroll
-        for (int d = 0; d < kQ; ++d) {
+        for (int d = 0; d < NQ; ++d) {
             M.x += g[d].x;
             M.y += g[d].y;
         }
@@ -295,8 +306,8 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
         const double w = c_w[p];
         V* out = dst + s;
 #pragma unroll
-        for (int d = 0; d < kQ; ++d) {
-            const double wd = d == 0 ? 0.25 : 0.125;
+        for (int d = 0; d < NQ; ++d) {
+            const double wd = d == 0 ? W0 : W1;
             double2 h;
             h.x = g[d].x + w * (wd * M.x - g[d].x);
             h.y = g[d].y + w * (wd * M.y - g[d].y);
@@ -360,7 +371,7 @@ template <typename V>
 __global__ void __launch_bounds__(kBlock) k_init_classical(V* pop, FieldDesc fd,
                                                             const uint32_t* words,
                                                             const double* fdt,
-                                                            const double* rdt) {
+                                                            const double* rdt, int32_t nq) {
     const int32_t s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= fd.nsites) return;
     const int32_t n0 = fd.n[0], n1 = fd.n[1];
@@ -368,20 +379,19 @@ __global__ void __launch_bounds__(kBlock) k_init_classical(V* pop, FieldDesc fd,
     const int p = (int)(words[fd.words + s] & 0xfu);
     const double ra = 1.0 - rdt[p];
     const double rb = -fdt[0] * (fd.c[0] * j0 + fd.c[1] * j1 + fd.c[2] * j2 + fd.cu);
-#pragma unroll
-    for (int d = 0; d < kQ; ++d) {
-        const double wd = d == 0 ? 0.25 : 0.125;
+    for (int d = 0; d < nq; ++d) {
+        const double wd = d == 0 ? lattice_w0(nq) : lattice_w1(nq);
         store2(pop + fd.pop + (int64_t)d * fd.nsites + s, make_double2(wd * ra, wd * rb));
     }
 }
 
 template <typename V>
-__global__ void __launch_bounds__(kBlock) k_mfinal(const V* pop, int64_t nsites, V* out) {
+__global__ void __launch_bounds__(kBlock) k_mfinal(const V* pop, int64_t nsites, V* out,
+                                                    int32_t nq) {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= nsites) return;
     double2 m = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int d = 0; d < kQ; ++d) {
+    for (int d = 0; d < nq; ++d) {
         const double2 v = ld2(pop + (int64_t)d * nsites + s);
         m.x += v.x;
         m.y += v.y;
@@ -392,49 +402,62 @@ __global__ void __launch_bounds__(kBlock) k_mfinal(const V* pop, int64_t nsites,
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 hipError_t launch_init(int prec, void* pop, int64_t, const FieldDesc*, int32_t n_fields,
-                       const FieldDesc* h, double* E, int32_t, int32_t K, hipStream_t st) {
+                       const FieldDesc* h, double* E, int32_t, int32_t K, int32_t nq,
+                       hipStream_t st) {
     for (int f = 0; f < n_fields; ++f) {
         const int64_t ns = h[f].nsites;
         if (prec == 1)
-            hipLaunchKernelGGL(k_init<float2>, dim3(grid_for(ns * kQ)), dim3(kBlock), 0, st,
+            hipLaunchKernelGGL(k_init<float2>, dim3(grid_for(ns * nq)), dim3(kBlock), 0, st,
                                static_cast<float2*>(pop) + h[f].pop, ns,
-                               reinterpret_cast<double2*>(E), h[f].q, K);
+                               reinterpret_cast<double2*>(E), h[f].q, K, nq);
         else
-            hipLaunchKernelGGL(k_init<double2>, dim3(grid_for(ns * kQ)), dim3(kBlock), 0, st,
+            hipLaunchKernelGGL(k_init<double2>, dim3(grid_for(ns * nq)), dim3(kBlock), 0, st,
                                static_cast<double2*>(pop) + h[f].pop, ns,
-                               reinterpret_cast<double2*>(E), h[f].q, K);
+                               reinterpret_cast<double2*>(E), h[f].q, K, nq);
     }
     return hipGetLastError();
 }
 
-template <typename V, bool CL, bool GM>
+template <typename V, bool CL, bool GM, int NQ>
 static void launch_step_t(int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st) {
     switch (shape) {
         case kTile64x4:
-            hipLaunchKernelGGL((k_step<V, 64, CL, GM>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL((k_step<V, 64, CL, GM, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
             break;
         case kTile32x8:
-            hipLaunchKernelGGL((k_step<V, 32, CL, GM>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL((k_step<V, 32, CL, GM, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
             break;
         case kTile128x2:
-            hipLaunchKernelGGL((k_step<V, 128, CL, GM>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL((k_step<V, 128, CL, GM, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+            break;
+        case kTile256x1:
+            if constexpr (NQ == 5)
+                hipLaunchKernelGGL((k_step<V, 256, CL, GM, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
             break;
         default:
-            hipLaunchKernelGGL((k_step<V, 16, CL, GM>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL((k_step<V, 16, CL, GM, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
             break;
+    }
+}
+
+template <typename V, int NQ>
+static void launch_step_q(int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st) {
+    const bool gm = a.gm != nullptr;
+    if (a.classical) {
+        if (gm) launch_step_t<V, true, true, NQ>(shape, a, n_blocks, st);
+        else launch_step_t<V, true, false, NQ>(shape, a, n_blocks, st);
+    } else {
+        if (gm) launch_step_t<V, false, true, NQ>(shape, a, n_blocks, st);
+        else launch_step_t<V, false, false, NQ>(shape, a, n_blocks, st);
     }
 }
 
 template <typename V>
 static void launch_step_v(int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st) {
-    const bool gm = a.gm != nullptr;
-    if (a.classical) {
-        if (gm) launch_step_t<V, true, true>(shape, a, n_blocks, st);
-        else launch_step_t<V, true, false>(shape, a, n_blocks, st);
-    } else {
-        if (gm) launch_step_t<V, false, true>(shape, a, n_blocks, st);
-        else launch_step_t<V, false, false>(shape, a, n_blocks, st);
-    }
+    if (a.nq == 5)
+        launch_step_q<V, 5>(shape, a, n_blocks, st);
+    else
+        launch_step_q<V, 7>(shape, a, n_blocks, st);
 }
 
 hipError_t launch_step(int prec, int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st) {
@@ -447,16 +470,16 @@ hipError_t launch_step(int prec, int shape, const StepArgs& a, int32_t n_blocks,
 
 hipError_t launch_init_classical(int prec, void* pop, const FieldDesc* h, int32_t n_fields,
                                  const uint32_t* words, const double* fdt, const double* rdt,
-                                 hipStream_t st) {
+                                 int32_t nq, hipStream_t st) {
     for (int f = 0; f < n_fields; ++f) {
         if (prec == 1)
             hipLaunchKernelGGL(k_init_classical<float2>, dim3(grid_for(h[f].nsites)),
                                dim3(kBlock), 0, st, static_cast<float2*>(pop), h[f], words, fdt,
-                               rdt);
+                               rdt, nq);
         else
             hipLaunchKernelGGL(k_init_classical<double2>, dim3(grid_for(h[f].nsites)),
                                dim3(kBlock), 0, st, static_cast<double2*>(pop), h[f], words, fdt,
-                               rdt);
+                               rdt, nq);
     }
     return hipGetLastError();
 }
@@ -468,7 +491,7 @@ hipError_t launch_tables(const StepArgs& a, int32_t nsteps, hipStream_t st) {
 }
 
 hipError_t launch_mfinal(int prec, const void* pop, const FieldDesc* h, int32_t n_fields,
-                         void* M_out, hipStream_t st) {
+                         void* M_out, int32_t nq, hipStream_t st) {
     int64_t off = 0;
     for (int f = 0; f < n_fields; ++f) {
         if (h[f].q < 0) continue;
@@ -476,11 +499,11 @@ hipError_t launch_mfinal(int prec, const void* pop, const FieldDesc* h, int32_t 
         if (prec == 1)
             hipLaunchKernelGGL(k_mfinal<float2>, dim3(grid_for(ns)), dim3(kBlock), 0, st,
                                static_cast<const float2*>(pop) + h[f].pop, ns,
-                               static_cast<float2*>(M_out) + off);
+                               static_cast<float2*>(M_out) + off, nq);
         else
             hipLaunchKernelGGL(k_mfinal<double2>, dim3(grid_for(ns)), dim3(kBlock), 0, st,
                                static_cast<const double2*>(pop) + h[f].pop, ns,
-                               static_cast<double2*>(M_out) + off);
+                               static_cast<double2*>(M_out) + off, nq);
         off += ns;
     }
     return hipGetLastError();

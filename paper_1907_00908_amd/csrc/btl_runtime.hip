@@ -21,7 +21,6 @@ using namespace btl;
 
 namespace {
 
-constexpr double kEpsD = 0.25;   // D3Q7 lattice constant in tau = 1/2 + dt D/(eps_D dx^2)
 
 struct GeomHost {
     int32_t n[3];
@@ -58,7 +57,7 @@ constexpr int kGraphMinSteps = 16;   // forwards this long run from a cached hip
 // Everything a captured forward depends on besides the contents of its
 // buffers; a forward replays the cached graph only when this matches.
 struct GraphKey {
-    int32_t prec, K, Q, n_fields, nblk, shape, T, ckpt, scheme;
+    int32_t prec, K, Q, n_fields, nblk, shape, T, ckpt, scheme, nq;
     const void* ptr[16];
 };
 
@@ -68,6 +67,7 @@ struct btl_sim {
     int prec = BTL_F32;
     int scheme = BTL_HYBRID;
     int substeps = 1;            // reaction sub-steps per step (waveform samples per step)
+    int nq = 7;                  // lattice: 7 (D3Q7) or 5 (D2Q5 on single-layer geometries)
     int device = 0;
     double dx = 1.0;
     int32_t n_phase = 1;
@@ -125,13 +125,36 @@ struct btl_sim {
     std::string err;
 };
 
+// The lattice as the kernels see it.  A single-layer D2Q5 geometry
+// (n0, n1, 1) is run as (n0, 1, n1): its rows along y become the columns
+// that one thread walks (the memory order of sites is the same), the y
+// faces and gradient component move to the z slots, and the kernel maps its
+// planes 3 and 4 to the z pulls.  D3Q7 geometries are unchanged.
+static GeomHost kernel_geom(const GeomHost& g, int nq) {
+    GeomHost k = g;
+    if (nq == 5) {
+        k.n[1] = 1;
+        k.n[2] = g.n[1];
+        k.bc[1] = BTL_PERIODIC;
+        k.bc[2] = g.bc[1];
+    }
+    return k;
+}
+static void kernel_grad(const double* G, int nq, double* out) {
+    out[0] = G[0];
+    out[1] = nq == 5 ? 0.0 : G[1];
+    out[2] = nq == 5 ? G[1] : G[2];
+}
+
 // Tile shape with the fewest idle lanes over the geometries of a call
 // (ties go to the wider x extent: longer contiguous rows per wavefront).
-static int pick_shape(const std::vector<GeomHost>& gs, const int32_t* q_geom, int Q) {
-    static const int order[kTileCount] = {kTile128x2, kTile64x4, kTile32x8, kTile16x16};
+// Single-layer lattices always take 256 x 1 (their tiles are one row).
+static int pick_shape(const std::vector<GeomHost>& gs, const int32_t* q_geom, int Q, int nq) {
+    if (nq == 5) return kTile256x1;
+    static const int order[kTileCount3D] = {kTile128x2, kTile64x4, kTile32x8, kTile16x16};
     int best = kTile128x2;
     int64_t best_waste = -1;
-    for (int oi = 0; oi < kTileCount; ++oi) {
+    for (int oi = 0; oi < kTileCount3D; ++oi) {
         const int sh = order[oi];
         int tx, ty;
         tile_dims(sh, &tx, &ty);
@@ -262,7 +285,8 @@ extern "C" btl_status btl_create(const btl_geom* geoms, int32_t n_geom, int32_t 
             return fail(nullptr, BTL_E_INVAL, "all geometries must share dx and n_phase");
         int64_t ns = 1;
         for (int a = 0; a < 3; ++a) {
-            if (G.n[a] < 2) return fail(nullptr, BTL_E_INVAL, "each axis needs >= 2 sites");
+            if (G.n[a] < (a == 2 ? 1 : 2))
+                return fail(nullptr, BTL_E_INVAL, "x and y need >= 2 sites, z >= 1");
             if (G.bc[a] != BTL_PERIODIC && G.bc[a] != BTL_MIRROR)
                 return fail(nullptr, BTL_E_INVAL, "bc must be BTL_PERIODIC or BTL_MIRROR");
             ns *= G.n[a];
@@ -380,6 +404,13 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
             if (k != kappa[b * P + a]) return fail(s, BTL_E_INVAL, "kappa must be symmetric");
         }
     const int32_t msub = s->substeps;
+    const int32_t nq = s->nq;
+    const double eps = lattice_eps(nq);
+    if (nq == 5)
+        for (int q = 0; q < Q; ++q)
+            if (s->geoms[q_geom[q]].n[2] != 1 || gG0[3 * q + 2] != 0.0)
+                return fail(s, BTL_E_INVAL, "D2Q5 needs single-layer geometries (n[2] = 1) "
+                                             "and no gradient along z");
     if (msub > 1 && s->scheme == BTL_CLASSICAL)
         return fail(s, BTL_E_UNSUPPORTED, "reaction sub-steps need the hybrid scheme");
     for (int64_t k = 0; k < (int64_t)K * msub; ++k)
@@ -396,7 +427,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     // per-phase and per-pair constants (FP64)
     std::vector<double> consts(2 * P + P * P + P + P * P + P + P * P);
     for (int p = 0; p < P; ++p) {
-        const double tau = 0.5 + dt * D[p] / (kEpsD * dx * dx);
+        const double tau = 0.5 + dt * D[p] / (eps * dx * dx);
         consts[p] = 1.0 / tau;
         consts[P + p] = isinf(T2[p]) ? 1.0 : exp(-dt / T2[p]);
     }
@@ -408,7 +439,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         else if (k == 0.0)
             t = 0.0;
         else {
-            const double Pm = kEpsD * dx / (2.0 * k * dt);
+            const double Pm = eps * dx / (2.0 * k * dt);
             t = 1.0 / (1.0 + Pm);
         }
         consts[2 * P + i] = t;
@@ -439,13 +470,14 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     }
 
     // launch shape
-    const int shape = s->tile_shape >= 0 ? s->tile_shape : pick_shape(s->geoms, q_geom, Q);
+    int shape = s->tile_shape >= 0 ? s->tile_shape : pick_shape(s->geoms, q_geom, Q, nq);
+    if ((nq == 5) != (shape == kTile256x1)) shape = pick_shape(s->geoms, q_geom, Q, nq);
     int TX, TY;
     tile_dims(shape, &TX, &TY);
     int ZC = s->zc;
     if (ZC <= 0) {
         ZC = 1;
-        for (int q = 0; q < Q; ++q) ZC = std::max(ZC, s->geoms[q_geom[q]].n[2]);
+        for (int q = 0; q < Q; ++q) ZC = std::max(ZC, kernel_geom(s->geoms[q_geom[q]], nq).n[2]);
     }
     ZC = std::min(ZC, kMaxZc);
 
@@ -455,8 +487,9 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     int64_t pop_elems = 0;
     int32_t nblk_total = 0;
     for (int q = 0; q < Q; ++q) {
-        const GeomHost& g = s->geoms[q_geom[q]];
-        const double* G = gG0 + 3 * q;
+        const GeomHost g = kernel_geom(s->geoms[q_geom[q]], nq);
+        double G[3];
+        kernel_grad(gG0 + 3 * q, nq, G);
         QFields qf = plan_fields(g, G, s->scheme == BTL_CLASSICAL);
         const int base = (int)fl.size();
         auto slot_of = [&](int sg, int* cj) {
@@ -499,7 +532,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
                 if (sig) d.cu -= dx * G[a];
             }
             fl.push_back(d);
-            pop_elems += (int64_t)kQ * g.nsites;
+            pop_elems += (int64_t)nq * g.nsites;
             nblk_total += d.nblk;
         }
         // faces (needs all slots of this q allocated)
@@ -554,12 +587,12 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     // the kernels address a field's reads with 32-bit element offsets from
     // its own base: every plane it reads must lie within +-2^31 elements
     for (int i = 0; i < n_fields; ++i) {
-        int64_t lo = 0, hi = (int64_t)kQ * fl[i].nsites;
+        int64_t lo = 0, hi = (int64_t)nq * fl[i].nsites;
         for (int f = 0; f < 6; ++f) {
             lo = std::min(lo, fl[i].face_pop[f] - fl[i].pop);
-            hi = std::max(hi, fl[i].face_pop[f] - fl[i].pop + (int64_t)kQ * fl[i].nsites);
+            hi = std::max(hi, fl[i].face_pop[f] - fl[i].pop + (int64_t)nq * fl[i].nsites);
             lo = std::min(lo, fl[i].adj_pop[f] - fl[i].pop);
-            hi = std::max(hi, fl[i].adj_pop[f] - fl[i].pop + (int64_t)kQ * fl[i].nsites);
+            hi = std::max(hi, fl[i].adj_pop[f] - fl[i].pop + (int64_t)nq * fl[i].nsites);
         }
         if (lo < -(int64_t)INT32_MAX || hi > (int64_t)INT32_MAX)
             return fail(s, BTL_E_UNSUPPORTED, "geometry too large for the image fields of one q-sample");
@@ -652,6 +685,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     if (ckpt_every > 0 && K > 0) {
         if (P > kAdjMaxPhase) return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports n_phase <= 4");
         if (classical) return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports the hybrid scheme only");
+        if (nq != 7) return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports the D3Q7 lattice only");
         if (uses_gm)
             return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports the half-link membrane rule only");
         const int32_t C = std::min(ckpt_every, K);
@@ -676,11 +710,11 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     auto enqueue = [&](hipStream_t q, double* Eptr) -> btl_status {
         hipError_t err;
         if ((err = launch_init(s->prec, s->pop[0].p, pop_elems, s->fields.p, n_fields, fl.data(),
-                               Eptr, Q, K, q)) != hipSuccess)
+                               Eptr, Q, K, nq, q)) != hipSuccess)
             return hip_fail(s, err, "init launch");
         if (classical && K > 0 &&
             (err = launch_init_classical(s->prec, s->pop[0].p, fl.data(), n_fields, s->words.p,
-                                         s->steps.p, s->consts.p + 3 * P + 2 * P * P, q)) !=
+                                         s->steps.p, s->consts.p + 3 * P + 2 * P * P, nq, q)) !=
                 hipSuccess)
             return hip_fail(s, err, "init launch");
         if (ckpt_every > 0 && K > 0 &&
@@ -700,7 +734,8 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         a.rdt = s->consts.p + 3 * P + 2 * P * P;
         a.gm = uses_gm ? s->gm.p : nullptr;
         a.kdt = s->consts.p + 4 * P + 2 * P * P;
-        a.edx = kEpsD * dx;
+        a.edx = eps * dx;
+        a.nq = nq;
         a.classical = classical ? 1 : 0;
         a.partial = s->partial.p;
         a.counter = s->counter.p;
@@ -750,6 +785,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         key.T = T;
         key.ckpt = ckpt_every;
         key.scheme = s->scheme;
+        key.nq = nq;
         const void* ptrs[] = {s->pop[0].p, s->pop[1].p, s->fields.p, s->blk_field.p, s->steps.p,
                               s->consts.p, s->partial.p, s->counter.p, s->tab.p, s->tab_field.p,
                               s->E_int.p, s->ckpt.p, s->words.p};
@@ -788,7 +824,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     }
     if (ckpt_every > 0 && K > 0) s->tape.valid = true;
     if (M_final) {
-        if ((e = launch_mfinal(s->prec, s->pop[K & 1].p, fl.data(), n_fields, M_final, st)) !=
+        if ((e = launch_mfinal(s->prec, s->pop[K & 1].p, fl.data(), n_fields, M_final, nq, st)) !=
             hipSuccess)
             return hip_fail(s, e, "final magnetization launch");
     }
@@ -797,8 +833,10 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
 
 // Fields of one q-sample: 2^(k-1) or 2^k image fields, see plan_fields.
 static int64_t q_state_elems(const btl_sim* s, int32_t g, const double* G) {
-    const GeomHost& gh = s->geoms[g];
-    return (int64_t)plan_fields(gh, G, s->scheme == BTL_CLASSICAL).sigma.size() * kQ * gh.nsites;
+    const GeomHost gh = kernel_geom(s->geoms[g], s->nq);
+    double Gk[3];
+    kernel_grad(G, s->nq, Gk);
+    return (int64_t)plan_fields(gh, Gk, s->scheme == BTL_CLASSICAL).sigma.size() * s->nq * gh.nsites;
 }
 
 extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double* D,
@@ -972,6 +1010,8 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
     const char* ez = getenv("BTLBM_ZC");
     if (et || ez) {
         if (et) s->tile_shape = std::max(0, std::min(kTileCount - 1, atoi(et)));
+        if (s->nq == 5) s->tile_shape = kTile256x1;
+        else if (s->tile_shape == kTile256x1) s->tile_shape = kTile128x2;
         if (ez) s->zc = std::max(0, std::min(kMaxZc, atoi(ez)));
         return BTL_OK;
     }
@@ -989,7 +1029,8 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
     if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
         return hip_fail(s, e, "autotune events");
     int nz_max = 1;
-    for (int q = 0; q < Qr; ++q) nz_max = std::max(nz_max, s->geoms[L.q_geom[q]].n[2]);
+    for (int q = 0; q < Qr; ++q)
+        nz_max = std::max(nz_max, kernel_geom(s->geoms[L.q_geom[q]], s->nq).n[2]);
     // z-column lengths: whole columns, halves, thirds, quarters, and short
     // columns for small lattices that need more workgroups
     std::vector<int> zcs = {0};
@@ -1002,7 +1043,8 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
     float best = -1.0f;
     int best_shape = -1, best_zc = 0;
     btl_status rc = BTL_OK;
-    for (int sh = 0; sh < kTileCount && rc == BTL_OK; ++sh)
+    const int sh0 = s->nq == 5 ? kTile256x1 : 0, sh1 = s->nq == 5 ? kTileCount : kTileCount3D;
+    for (int sh = sh0; sh < sh1 && rc == BTL_OK; ++sh)
         for (int zc : zcs) {
             s->tile_shape = sh;
             s->zc = zc;
@@ -1038,6 +1080,16 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
     }
     s->tile_shape = best_shape;
     s->zc = best_zc;
+    return BTL_OK;
+}
+
+extern "C" btl_status btl_set_lattice(btl_sim* s, int32_t lattice) {
+    if (!s) return BTL_E_INVAL;
+    if (lattice != BTL_D3Q7 && lattice != BTL_D2Q5)
+        return fail(s, BTL_E_INVAL, "lattice must be BTL_D3Q7 or BTL_D2Q5");
+    s->nq = lattice == BTL_D2Q5 ? 5 : 7;
+    s->tape.valid = false;
+    s->last.valid = false;
     return BTL_OK;
 }
 

@@ -161,8 +161,36 @@ def _cfg5(n=512, K=None, n_q=None, seed=5):
                 desc="three-phase ellipsoid cells 512^3, cosine OGSE 50 Hz, 32 dirs")
 
 
+def _cfg2d(n=512, K=None, n_q=None, seed=6):
+    # two-dimensional axon cross-sections on the D2Q5 lattice (Sec. 2.2):
+    # a periodic 128^2 disk packing (the cfg2 law) tiled to n x n, in-plane
+    # gradient directions at four b-values
+    dx, dt = 0.25, 0.004
+    delta, Delta = 10.0, 30.0
+    base = geo.cylinders_z((min(n, 128), min(n, 128), 1), dx, seed, vf_target=0.6,
+                           periodic=True)
+    r = max(1, n // 128)
+    g = geo.tile_xy(base, r, r) if r > 1 else base
+    D, T2, kap = _axon_params()
+    f = seq.pgse_waveform(delta, Delta, dt)
+    if K is not None:
+        f = f[:K]
+    th = np.pi * (np.arange(64) + 0.5) / 64
+    dirs = np.stack([np.cos(th), np.sin(th), np.zeros_like(th)], axis=1)
+    bs = np.array([0.5, 1.0, 2.0, 3.0])
+    gG0 = np.concatenate([seq.gamma_g_for_b_pgse(bb, delta, Delta) * dirs for bb in bs])
+    bq = np.repeat(bs, len(dirs))
+    if n_q is not None:
+        sel = np.linspace(0, len(gG0) - 1, n_q).round().astype(int)
+        gG0, bq = gG0[sel], bq[sel]
+    return dict(name="cfg2d", geoms=[g], bc=[PERIODIC] * 3, dx=dx, dt=dt, D=D, T2=T2,
+                kappa=kap, f=f, gG0=gG0, q_geom=np.zeros(len(gG0), np.int32), b=bq,
+                TE=delta + Delta, lattice=1,
+                desc="2D axon cross-sections 512^2 (D2Q5), 64 in-plane dirs x 4 b = 256 q")
+
+
 CONFIGS = {"cfg1": _cfg1, "cfg2": _cfg2, "cfg3a": _cfg3a, "cfg3b": _cfg3b,
-           "cfg4": _cfg4, "cfg5": _cfg5}
+           "cfg4": _cfg4, "cfg5": _cfg5, "cfg2d": _cfg2d}
 
 
 def make_config(name: str, n=None, K=None, n_q=None, seed=None,

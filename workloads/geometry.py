@@ -341,6 +341,15 @@ def ellipsoid_cells(n, dx: float, seed: int, vf_target: float = 0.5,
     return g
 
 
+def tile_xy(g: Geometry, rx: int, ry: int) -> Geometry:
+    """rx x ry periodic copies of a geometry that is periodic in x and y
+    (compartment ids kept: a cell cut by the tile border continues in the
+    next copy as the same compartment)."""
+    comp = np.tile(g.comp, (1, ry, rx))
+    info = {"kind": g.info.get("kind", "?") + "_tiled", "tile_of": (g, rx, ry)}
+    return Geometry(comp, g.comp_phase.copy(), g.n_phase, g.dx, info)
+
+
 def link_delta(g: Geometry) -> np.ndarray:
     """Where each membrane cuts its lattice link, from the analytic surfaces
     the geometry was rasterised from.
@@ -353,6 +362,9 @@ def link_delta(g: Geometry) -> np.ndarray:
     every entry of a geometry without analytic surfaces, is 0.5 (the
     mid-link position).
     """
+    if "tile_of" in g.info:
+        base, rx, ry = g.info["tile_of"]
+        return np.tile(link_delta(base), (1, 1, ry, rx))
     n2, n1, n0 = g.comp.shape
     dims = (n0, n1, n2)
     out = np.full((3, n2, n1, n0), 0.5, np.float32)
