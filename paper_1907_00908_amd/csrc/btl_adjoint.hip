@@ -57,11 +57,13 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
     __syncthreads();
     double* my = acc + threadIdx.x * RS;
 
-    const int fi = a.blk_field[blockIdx.x];
+    const int32_t lb = a.xcd ? xcd_tile((int32_t)blockIdx.x, (int32_t)gridDim.x)
+                             : (int32_t)blockIdx.x;
+    const int fi = a.blk_field[lb];
     const FieldDesc& fd = a.fields[fi];
     const int32_t ns = fd.nsites;
     const int32_t n0 = fd.n[0], n1 = fd.n[1], n2 = fd.n[2];
-    const int32_t b = blockIdx.x - fd.blk0;
+    const int32_t b = lb - fd.blk0;
     const int32_t tx = b % fd.tiles[0];
     const int32_t rb = b / fd.tiles[0];
     const int32_t ty = rb % fd.tiles[1];
@@ -313,7 +315,7 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
     }
     __syncthreads();
     if (threadIdx.x < NG)
-        __hip_atomic_store(a.gpart + (int64_t)blockIdx.x * NG + threadIdx.x, red[threadIdx.x],
+        __hip_atomic_store(a.gpart + (int64_t)lb * NG + threadIdx.x, red[threadIdx.x],
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     if (threadIdx.x == 0) {

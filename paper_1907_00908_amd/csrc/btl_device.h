@@ -36,6 +36,18 @@ __device__ __forceinline__ double2 uniform2(double2 v) {
     return make_double2(uniform(v.x), uniform(v.y));
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup i to XCD
+// i mod 8), each XCD with its own L2.  xcd_tile renumbers them so that every
+// XCD walks one contiguous range of tiles: neighbouring tiles, which read
+// each other's edge rows, then run on the same XCD close in time and share
+// those rows through its L2.  A bijection of [0, G).
+constexpr int kXcd = 8;
+__device__ __forceinline__ int32_t xcd_tile(int32_t bid, int32_t G) {
+    const int32_t k = bid % kXcd, i = bid / kXcd;
+    const int32_t q = G / kXcd, r = G % kXcd;
+    return (k < r ? k * (q + 1) : r * (q + 1) + (k - r) * q) + i;
+}
+
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }

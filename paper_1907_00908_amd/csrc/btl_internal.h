@@ -85,6 +85,8 @@ struct AdjArgs {
     int32_t K;
     int32_t top;            // 1 when k = K (no adjoint from later steps)
     int32_t ng;
+    int32_t xcd;            // 1: XCD-contiguous workgroup order (xcd_tile)
+    int32_t pad;
 };
 
 struct StepArgs {
@@ -118,6 +120,8 @@ struct StepArgs {
     int32_t K;
     int32_t classical;      // 1: reaction term in the collision, no split
     int32_t nq;             // 7 (D3Q7) or 5 (D2Q5 on a single layer)
+    int32_t xcd;            // 1: XCD-contiguous workgroup order (xcd_tile)
+    int32_t pad2;
 };
 
 // Workgroup tile shapes (TX x TY threads, one site column along z each).

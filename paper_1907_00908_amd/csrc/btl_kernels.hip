@@ -102,11 +102,13 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
         if (GM && t < P * P) c_kdt[t] = a.kdt[t];
     }
     __syncthreads();
-    const int fi = a.blk_field[blockIdx.x];
+    const int32_t lb = a.xcd ? xcd_tile((int32_t)blockIdx.x, (int32_t)gridDim.x)
+                             : (int32_t)blockIdx.x;
+    const int fi = a.blk_field[lb];
     const FieldDesc& fd = a.fields[fi];
     const int32_t ns = fd.nsites;
     const int32_t n0 = fd.n[0], n1 = fd.n[1], n2 = fd.n[2];
-    const int32_t b = blockIdx.x - fd.blk0;
+    const int32_t b = lb - fd.blk0;
     const int32_t tx = b % fd.tiles[0];
     const int32_t rb = b / fd.tiles[0];
     const int32_t ty = rb % fd.tiles[1];
@@ -337,7 +339,7 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     if (fd.q < 0) return;   // image fields do not enter the signal
     const double2 bsum = block_sum(Mv, lds);
     if (threadIdx.x == 0) {
-        double* pp = &a.partial[blockIdx.x].x;
+        double* pp = &a.partial[lb].x;
         __hip_atomic_store(pp, bsum.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(pp + 1, bsum.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();

@@ -53,11 +53,12 @@ struct DevBuf {
 std::string g_create_error;
 
 constexpr int kGraphMinSteps = 16;   // forwards this long run from a cached hipGraph
+constexpr int kXcdMinBlocks = 2048;  // grids above this use the XCD-contiguous order
 
 // Everything a captured forward depends on besides the contents of its
 // buffers; a forward replays the cached graph only when this matches.
 struct GraphKey {
-    int32_t prec, K, Q, n_fields, nblk, shape, T, ckpt, scheme, nq;
+    int32_t prec, K, Q, n_fields, nblk, shape, T, ckpt, scheme, nq, xcd;
     const void* ptr[16];
 };
 
@@ -97,6 +98,7 @@ struct btl_sim {
     hipStream_t cap_stream = nullptr;
     DevBuf<double> E_int;
     int tile_shape = -1;        // -1: pick per call from the geometry sizes
+    int xcd = -1;               // workgroup order: -1 by grid size, 0 plain, 1 XCD-contiguous
     int zc = 0;                 // sites per thread along z; 0: whole column
     // inputs of the last forward call (the autotuner replays them)
     struct SimLastT {
@@ -110,7 +112,7 @@ struct btl_sim {
     // adjoint tape of the last forward that asked for one
     struct Tape {
         bool valid = false;
-        int32_t K = 0, C = 0, Q = 0, T = 0, n_fields = 0, nblk = 0, shape = 0, sub = 1;
+        int32_t K = 0, C = 0, Q = 0, T = 0, n_fields = 0, nblk = 0, shape = 0, sub = 1, xcd = 0;
         double dt = 0;
         int64_t state_elems = 0;   // V elements of one full state (all fields)
     } tape;
@@ -681,6 +683,11 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     s->stage_slot ^= 1;
 
     s->tape.valid = false;
+    // XCD-contiguous workgroup order pays off when the grid runs in several
+    // waves (tiles that share edge rows then meet in one XCD's L2); grids
+    // that fit on the chip at once keep the plain order.  The autotuner
+    // measures both.
+    const int xcd_on = s->xcd >= 0 ? s->xcd : (nblk_total > kXcdMinBlocks ? 1 : 0);
     const size_t state_bytes = (size_t)pop_elems * esz;
     if (ckpt_every > 0 && K > 0) {
         if (P > kAdjMaxPhase) return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports n_phase <= 4");
@@ -701,6 +708,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         s->tape.shape = shape;
         s->tape.dt = dt;
         s->tape.sub = msub;
+        s->tape.xcd = xcd_on;
         s->tape.state_elems = pop_elems;
     }
     // Everything a forward enqueues after the uploads: init, one table
@@ -736,6 +744,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         a.kdt = s->consts.p + 4 * P + 2 * P * P;
         a.edx = eps * dx;
         a.nq = nq;
+        a.xcd = xcd_on;
         a.classical = classical ? 1 : 0;
         a.partial = s->partial.p;
         a.counter = s->counter.p;
@@ -786,6 +795,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         key.ckpt = ckpt_every;
         key.scheme = s->scheme;
         key.nq = nq;
+        key.xcd = xcd_on;
         const void* ptrs[] = {s->pop[0].p, s->pop[1].p, s->fields.p, s->blk_field.p, s->steps.p,
                               s->consts.p, s->partial.p, s->counter.p, s->tab.p, s->tab_field.p,
                               s->E_int.p, s->ckpt.p, s->words.p};
@@ -942,6 +952,8 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
     fa.K = K;
     fa.tab_field = s->tab_field.p;
     fa.T = T;
+    fa.nq = 7;
+    fa.xcd = tp.xcd;
 
     AdjArgs aa;
     memset(&aa, 0, sizeof(aa));
@@ -956,6 +968,7 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
     aa.counter = s->adj_counter.p;
     aa.gfield = s->gfield.p;
     aa.dt = tp.dt;
+    aa.xcd = tp.xcd;
     aa.n_fields = nf;
     aa.n_phase = P;
     aa.K = K;
@@ -1043,6 +1056,7 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
     float best = -1.0f;
     int best_shape = -1, best_zc = 0;
     btl_status rc = BTL_OK;
+    s->xcd = -1;   // shapes are compared with the default workgroup order
     const int sh0 = s->nq == 5 ? kTile256x1 : 0, sh1 = s->nq == 5 ? kTileCount : kTileCount3D;
     for (int sh = sh0; sh < sh1 && rc == BTL_OK; ++sh)
         for (int zc : zcs) {
@@ -1070,16 +1084,45 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
                 best_zc = zc;
             }
         }
+    // workgroup order for the best shape: plain and XCD-contiguous
+    int best_xcd = -1;
+    for (int xo = 0; xo < 2 && rc == BTL_OK && best_shape >= 0; ++xo) {
+        s->tile_shape = best_shape;
+        s->zc = best_zc;
+        s->xcd = xo;
+        rc = btl_forward(s, saved.dt, K_probe, saved.D.data(), saved.T2.data(), saved.kappa.data(),
+                         Qr, saved.q_geom.data(), saved.gG0.data(), f.data(), s->tune_E.p,
+                         nullptr, 0, stream);   // warm
+        if (rc != BTL_OK) break;
+        (void)hipEventRecord(e0, st);
+        rc = btl_forward(s, saved.dt, K_probe, saved.D.data(), saved.T2.data(), saved.kappa.data(),
+                         Qr, saved.q_geom.data(), saved.gG0.data(), f.data(), s->tune_E.p,
+                         nullptr, 0, stream);
+        if (rc != BTL_OK) break;
+        (void)hipEventRecord(e1, st);
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+            rc = hip_fail(s, e, "autotune timing");
+            break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (best_xcd < 0 || ms < best) {
+            best = ms;
+            best_xcd = xo;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     s->last = saved;
     if (rc != BTL_OK) {
         s->tile_shape = -1;
         s->zc = 0;
+        s->xcd = -1;
         return rc;
     }
     s->tile_shape = best_shape;
     s->zc = best_zc;
+    s->xcd = best_xcd;
     return BTL_OK;
 }
 
