@@ -9,7 +9,7 @@ namespace btl {
 
 constexpr int kQ = 7;          // D3Q7: 0 rest, 1 +x, 2 -x, 3 +y, 4 -y, 5 +z, 6 -z
 constexpr int kBlock = 256;    // threads per workgroup (4 wavefronts of 64)
-constexpr int kMaxZc = 4096;   // longest z column one thread walks
+constexpr int kMaxZc = 1024;   // longest z column one thread walks (LDS z-phase row)
 constexpr int kTabSteps = 32;  // steps whose phase tables one table launch computes
 constexpr int kMaxPhase = 8;   // material phases (3-bit neighbour phase in the site word)
 

@@ -31,6 +31,8 @@
 // The signal of a step is reduced deterministically: each workgroup writes a
 // partial sum, and the last workgroup of a field to finish (arrival counter)
 // adds all partials of that field in a fixed order.
+#include <type_traits>
+
 #include "btl_device.h"
 
 namespace btl {
@@ -78,7 +80,7 @@ __global__ void __launch_bounds__(kBlock) k_tables(StepArgs a, int32_t nsteps) {
 // follows the moment M(t^{k+1}).  The last step stores the plain collision,
 // whose moment is M(t^K).
 template <typename V, int TX, bool CL, bool GM, int NQ>
-__global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
+__device__ __forceinline__ void step_body(const StepArgs& a) {
     constexpr int TY = kBlock / TX;
     constexpr double W0 = lattice_w0(NQ), W1 = lattice_w1(NQ);
     // Plane p >= 1 moves along kernel direction kd(p): D3Q7 p itself; the
@@ -89,6 +91,7 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     __shared__ double2 lds[kBlock / 64];
     __shared__ double c_w[kMaxPhase], c_dec[kMaxPhase], c_tr[kMaxPhase * kMaxPhase];
     __shared__ double c_kdt[GM ? kMaxPhase * kMaxPhase : 1];
+    __shared__ double2 c_ez[CL ? 1 : kMaxZc];   // z phase factors of this tile's column range
     __shared__ int last_flag;
     // per-phase constants in LDS: lane-indexed lookups then go through the
     // LDS counter and never wait on outstanding global loads or stores
@@ -101,7 +104,6 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
         if (t < P * P) c_tr[t] = a.trans[t];
         if (GM && t < P * P) c_kdt[t] = a.kdt[t];
     }
-    __syncthreads();
     const int32_t lb = a.xcd ? xcd_tile((int32_t)blockIdx.x, (int32_t)gridDim.x)
                              : (int32_t)blockIdx.x;
     const int fi = a.blk_field[lb];
@@ -116,6 +118,11 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     const int32_t z0 = tz * fd.zc;
     const double2* __restrict__ tab = a.tab + fd.tab;
     const double2* __restrict__ ez = tab + n0 + n1;
+    // the z phase factors of the column range [z0, z0 + zc) go to LDS once
+    // (zc <= kMaxZc), so that the pipelined per-site loads do not carry them
+    if (!CL)
+        for (int i = threadIdx.x; i < fd.zc && z0 + i < n2; i += kBlock) c_ez[i] = ez[z0 + i];
+    __syncthreads();
     double2 face_fac[6];
 #pragma unroll
     for (int f = 0; f < 6; ++f) face_fac[f] = uniform2(tab[n0 + n1 + n2 + f]);
@@ -167,16 +174,15 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     const int32_t o5i = pop + pz * ns - st2, o5f = face_off(4, pz, (n2 - 1) * st2);
     const int32_t o6i = pop + (pz + 1) * ns + st2, o6f = face_off(5, pz + 1, -(n2 - 1) * st2);
 
-    // Loads of one site: the site word, the seven pulled populations, the
+    // Loads of one site: the site word, the seven pulled populations and the
     // six outgoing populations of the node itself (reflected at membrane
-    // links) and the z phase factor.  The z column is software-pipelined:
+    // links).  The z column is software-pipelined:
     // the loads of site j2 + 1 are issued before the stores of site j2, so
     // waiting for a site's data never waits for earlier stores.
     struct SiteLoads {
         uint32_t word;
         V g[NQ];
         V own[NQ - 1];
-        double2 ez;
     };
     auto issue = [&](int32_t j2, SiteLoads& L) {
         const int32_t s = j0 + st1 * j1 + st2 * j2;
@@ -195,7 +201,6 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
             const int od = (d & 1) ? d + 1 : d - 1;
             L.own[d - 1] = src[pop + od * ns + s];
         }
-        if (!CL) L.ez = ez[j2];
     };
     auto compute = [&](int32_t j2, const SiteLoads& L, double2& Macc) {
         const int32_t s = j0 + st1 * j1 + st2 * j2;
@@ -284,7 +289,7 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
         double2 M = make_double2(0.0, 0.0);
         if (!CL) {
             // reaction: exp(-i fdt (c.j + cu)) exp(-dt/T2)
-            const double2 e = cmul(exy, L.ez);
+            const double2 e = cmul(exy, c_ez[j2 - z0]);
             const double dec = c_dec[p];
             const double2 rf = make_double2(e.x * dec, e.y * dec);
 #pragma unroll
@@ -366,6 +371,20 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     }
 }
 
+// Two entry points around the same body: FP32 storage without membrane
+// positions fits in 128 VGPRs when asked to, which raises the occupancy
+// from three to four waves per SIMD; the other variants need more registers
+// and keep the compiler's choice.
+template <typename V, int TX, bool CL, bool GM, int NQ>
+__global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
+    step_body<V, TX, CL, GM, NQ>(a);
+}
+template <typename V, int TX, bool CL, bool GM, int NQ>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_step_w4(StepArgs a) {
+    step_body<V, TX, CL, GM, NQ>(a);
+}
+
 // ghat^0 of the classical scheme: the collision of the equilibrium state
 // g_i = w_i (M = 1) with its reaction term, ghat_i = w_i (1 + dt R(x, t^0)),
 // dt R = -dt/T2 - i f_0 dt (c.j + cu).
@@ -420,25 +439,24 @@ hipError_t launch_init(int prec, void* pop, int64_t, const FieldDesc*, int32_t n
     return hipGetLastError();
 }
 
+template <typename V, bool CL, bool GM, int NQ, int TX>
+static void launch_tx(const StepArgs& a, int32_t n_blocks, hipStream_t st) {
+    if constexpr (std::is_same<V, float2>::value && !GM)
+        hipLaunchKernelGGL((k_step_w4<V, TX, CL, GM, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_step<V, TX, CL, GM, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+}
+
 template <typename V, bool CL, bool GM, int NQ>
 static void launch_step_t(int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st) {
     switch (shape) {
-        case kTile64x4:
-            hipLaunchKernelGGL((k_step<V, 64, CL, GM, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
-            break;
-        case kTile32x8:
-            hipLaunchKernelGGL((k_step<V, 32, CL, GM, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
-            break;
-        case kTile128x2:
-            hipLaunchKernelGGL((k_step<V, 128, CL, GM, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
-            break;
+        case kTile64x4: launch_tx<V, CL, GM, NQ, 64>(a, n_blocks, st); break;
+        case kTile32x8: launch_tx<V, CL, GM, NQ, 32>(a, n_blocks, st); break;
+        case kTile128x2: launch_tx<V, CL, GM, NQ, 128>(a, n_blocks, st); break;
         case kTile256x1:
-            if constexpr (NQ == 5)
-                hipLaunchKernelGGL((k_step<V, 256, CL, GM, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+            if constexpr (NQ == 5) launch_tx<V, CL, GM, NQ, 256>(a, n_blocks, st);
             break;
-        default:
-            hipLaunchKernelGGL((k_step<V, 16, CL, GM, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
-            break;
+        default: launch_tx<V, CL, GM, NQ, 16>(a, n_blocks, st); break;
     }
 }
 

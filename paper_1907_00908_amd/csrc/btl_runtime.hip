@@ -1018,9 +1018,12 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
 
 extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void* stream) {
     if (!s) return BTL_E_INVAL;
-    // fixed launch shape for measurements: BTLBM_TILE (0..3), BTLBM_ZC
+    // fixed launch shape for measurements: BTLBM_TILE (0..4), BTLBM_ZC,
+    // BTLBM_XCD (0 plain, 1 XCD-contiguous workgroup order)
     const char* et = getenv("BTLBM_TILE");
     const char* ez = getenv("BTLBM_ZC");
+    const char* ex = getenv("BTLBM_XCD");
+    if (ex) s->xcd = atoi(ex) ? 1 : 0;
     if (et || ez) {
         if (et) s->tile_shape = std::max(0, std::min(kTileCount - 1, atoi(et)));
         if (s->nq == 5) s->tile_shape = kTile256x1;
