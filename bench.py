@@ -110,7 +110,7 @@ def time_forward(sim, cfg, K, prec_bytes, reps=1):
     return best, E
 
 
-def cpu_baseline(cfg, budget_s: float = 15.0):
+def cpu_baseline(cfg, budget_s: float = 25.0):
     """The FP64 oracle on the host cores, a bounded number of full-size steps
     of q-sample 0 (oblique gradient on mirrored faces: the oracle runs the
     reflected, doubled domain)."""
