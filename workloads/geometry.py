@@ -421,3 +421,46 @@ def link_delta(g: Geometry) -> np.ndarray:
             found[idx] = True
         out[a, z, y, x] = np.clip(best, 1e-4, 1.0 - 1e-4).astype(np.float32)
     return out
+
+
+def angled_slabs_2d(n: int, dx: float, bounds, tan_phi=(1, 2), phases=None) -> Geometry:
+    """Single-layer (n x n x 1) periodic box crossed by straight membranes
+    along the lines x.nhat = s (mod P), nhat = (q, p)/sqrt(p^2 + q^2) for
+    tan_phi = (p, q) (the normal makes the angle atan(p/q) with x), P the
+    period of the pattern in the box (P = L / sqrt(p^2 + q^2), L = n dx).
+    bounds: increasing positions s_0 < s_1 < ... in [0, P); compartment c
+    spans [s_{c-1}, s_c) and compartment 0 the rest.  Carries the exact
+    membrane positions of every link (link_delta)."""
+    p, q = tan_phi
+    nrm = math.hypot(p, q)
+    nh = np.array([q / nrm, p / nrm])
+    L = n * dx
+    P = L / nrm
+    b = np.asarray(bounds, np.float64)
+    j = np.arange(n)
+    X, Y = np.meshgrid(j * dx, j * dx)            # (n1, n0): Y rows, X columns
+
+    def comp_at(s):
+        s = np.mod(s, P)
+        c = np.zeros(s.shape, np.uint32)
+        for k in range(1, len(b)):
+            c[(s >= b[k - 1]) & (s < b[k])] = k
+        return c
+
+    s0 = X * nh[0] + Y * nh[1]
+    comp2 = comp_at(s0)
+    comp = comp2[None, :, :].copy()
+    nc = len(b)
+    ph = np.arange(nc, dtype=np.uint8) if phases is None else np.asarray(phases, np.uint8)
+    ld = np.full((3, 1, n, n), 0.5, np.float32)
+    for a, step in ((0, np.array([dx, 0.0])), (1, np.array([0.0, dx]))):
+        ds = step @ nh                               # s increment along the link (> 0)
+        s_lo = np.mod(s0, P)
+        for k in range(len(b)):
+            # first crossing of the line s = b_k (mod P) in (0, ds]
+            t = np.mod(b[k] - s_lo, P) / ds
+            hit = (t > 0) & (t < 1)
+            ld[a, 0][hit] = np.clip(t[hit], 1e-4, 1 - 1e-4)
+    g = Geometry(comp, ph, int(ph.max()) + 1, float(dx), {"kind": "angled_slabs_2d"})
+    g.link_delta = ld
+    return g
