@@ -1,0 +1,82 @@
+"""The large workloads at their full sizes, in the launch configuration the
+benchmark uses (autotuned shape, q-waves where the state exceeds device
+memory), checked on sampled q-samples against the FP64 oracle over a few
+steps, and by properties that hold at any size.  FP32 storage, tolerances
+as in the other parity tests."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+
+from .test_gpu_parity import _check, _gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _forward_autotuned(btl, cfg, K, want_M=False, probe=2):
+    import torch
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], "f32", lattice=cfg.get("lattice", 0))
+    try:
+        stream = torch.cuda.current_stream().cuda_stream
+        sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:probe],
+                    cfg["gG0"], cfg["q_geom"])
+        btl.btl_autotune(sim._h, len(cfg["gG0"]), probe, stream)
+        out = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:K],
+                          cfg["gG0"], cfg["q_geom"], want_M=want_M)
+        torch.cuda.synchronize()
+        if want_M:
+            return out[0].cpu().numpy(), [m.cpu().numpy() for m in out[1]]
+        return out.cpu().numpy()
+    finally:
+        sim.close()
+
+
+def _sampled(cfg, qs, K):
+    print(f"  GPU done; oracle on q-samples {qs}", flush=True)
+    c = dict(cfg, f=cfg["f"][:K])
+    Eo, _ = oracle.simulate_config(c, q=qs, threads=16)
+    return Eo
+
+
+def test_cfg3a_full_size_256_q_sampled():
+    # 256^3 cylinders + spheres, 256 q-samples (more state than the device
+    # holds: the library runs them in q-waves)
+    btl = _gpu()
+    cfg = w.make_config("cfg3a")
+    K = 4
+    print("GPU cfg3a 256^3 x 256 q, K=4", flush=True)
+    Eg = _forward_autotuned(btl, cfg, K)
+    qs = [0, 97, 255]
+    Eo = _sampled(cfg, qs, K)
+    _check(Eg[qs], Eo, "f32", "cfg3a sampled q")
+
+
+def test_cfg3b_full_size_ragged_sampled():
+    btl = _gpu()
+    cfg = w.make_config("cfg3b")
+    K = 4
+    print("GPU cfg3b 16 geometries 96^3..192^3, K=4", flush=True)
+    Eg = _forward_autotuned(btl, cfg, K)
+    qs = [0, 40, 95]          # geometries 0, 6 and 15
+    Eo = _sampled(cfg, qs, K)
+    _check(Eg[qs], Eo, "f32", "cfg3b sampled q")
+
+
+def test_cfg5_full_size_sampled_and_decay():
+    btl = _gpu()
+    cfg = w.make_config("cfg5")
+    K = 3
+    print("GPU cfg5 512^3 x 32 q, K=3", flush=True)
+    Eg = _forward_autotuned(btl, cfg, K)
+    Eo = _sampled(cfg, [0], K)
+    _check(Eg[[0]], Eo, "f32", "cfg5 q=0")
+    # one T2 in every phase and no gradient: E_k = exp(-k dt / T2) for every
+    # q-sample, over 40 steps, whatever the cells and membranes
+    c = dict(cfg, T2=np.full(3, 70.0), gG0=np.zeros((4, 3)), q_geom=np.zeros(4, np.int32))
+    Eg = _forward_autotuned(btl, c, 40)
+    k = np.arange(41)
+    ref = np.exp(-k * cfg["dt"] / 70.0)
+    assert np.max(np.abs(Eg - ref[None, :])) < 1e-6
