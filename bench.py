@@ -66,20 +66,20 @@ def workload(name: str, K: int, membranes: str = "half-link"):
     return cfg
 
 
-def fields_of(G, bc) -> int:
+def fields_of(G, bc, classical=False) -> int:
     # fields per q-sample: 2^(k-1) for k mirrored axes with non-zero gradient
-    # (all non-zero axes mirrored), else 2^k
+    # (all non-zero axes mirrored, hybrid scheme: conjugate pairs), else 2^k
     nz = [a for a in range(3) if G[a] != 0.0]
     mir = [a for a in nz if bc[a] == 1]
     k = len(mir)
     if k == 0:
         return 1
-    return 2 ** (k - 1) if len(mir) == len(nz) else 2 ** k
+    return 2 ** (k - 1) if len(mir) == len(nz) and not classical else 2 ** k
 
 
-def field_sites(cfg) -> int:
+def field_sites(cfg, classical=False) -> int:
     """Sum over all fields of the batch of their site counts."""
-    return sum(fields_of(G, cfg["bc"]) * cfg["geoms"][int(g)].comp.size
+    return sum(fields_of(G, cfg["bc"], classical) * cfg["geoms"][int(g)].comp.size
                for G, g in zip(cfg["gG0"], cfg["q_geom"]))
 
 
@@ -202,6 +202,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--scheme", default="hybrid", choices=["hybrid", "classical"],
+                    help="classical: the classical LBM of Appendix A (no adjoint)")
     ap.add_argument("--membranes", default="half-link", choices=["half-link", "positions"],
                     help="positions: exact membrane positions on the links and the "
                          "general membrane condition (no adjoint)")
@@ -241,17 +243,18 @@ def main():
 
     K, W = args.steps, args.warmup
     log(f"building workload {args.workload}")
-    if args.membranes == "positions" or args.workload == "cfg2d":
-        args.no_adjoint = True          # the adjoint covers D3Q7 half-link runs
+    if args.membranes == "positions" or args.workload == "cfg2d" or args.scheme != "hybrid":
+        args.no_adjoint = True          # the adjoint covers D3Q7 hybrid half-link runs
+    scheme = 0 if args.scheme == "hybrid" else 1
     cfg = workload(args.workload, max(K, W, 0 if args.no_adjoint else args.adj_steps),
                    args.membranes)
     Q = len(cfg["gG0"])
     qs = q_sites(cfg)
-    fs = field_sites(cfg)
+    fs = field_sites(cfg, args.scheme == "classical")
     sites = cfg["geoms"][0].comp.size
     lattice = cfg.get("lattice", 0)
     nq = 5 if lattice == 1 else 7
-    sim = btl.Simulator(cfg["geoms"], cfg["bc"], args.prec, lattice=lattice)
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], args.prec, scheme=scheme, lattice=lattice)
     # read nq complex populations + write nq, per field site
     bpf = (BYTES_PER_FIELD_SITE_F32 if args.prec == "f32" else BYTES_PER_FIELD_SITE_F64) * nq // 7
     log("first forward")
@@ -273,7 +276,7 @@ def main():
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": (traffic_for(ms_step) if args.workload == "cfg2" and args.prec == "f32"
-                        and args.membranes == "half-link" else None),
+                        and args.membranes == "half-link" and scheme == 0 else None),
             "kernel": f"k_step<{'float2' if args.prec == 'f32' else 'double2'}, {'D2Q5' if nq == 5 else 'D3Q7'}>",
             "bytes_per_launch_algorithmic": bytes_launch}
     out = {"metric": METRIC, "value": value, "unit": "site-updates/s", "n_gpus": 1,
@@ -283,13 +286,13 @@ def main():
                       "q_sites": qs, "q_samples": Q, "field_sites": fs,
                       "geometries": len(cfg["geoms"]),
                       "storage": args.prec, "steps_per_forward": K,
-                      "membranes": args.membranes},
+                      "membranes": args.membranes, "scheme": args.scheme},
            "roofline": roof}
     if not args.no_extras:
         log("FP64 comparison runs")
         # stated error vs FP64 storage over the same steps, and the plain FP64
         # one-sample-per-launch form as the speedup denominator
-        sim64 = btl.Simulator(cfg["geoms"], cfg["bc"], "f64", lattice=lattice)
+        sim64 = btl.Simulator(cfg["geoms"], cfg["bc"], "f64", scheme=scheme, lattice=lattice)
         ms64, E64 = time_forward(sim64, cfg, K, BYTES_PER_FIELD_SITE_F64)
         e32 = E.cpu().numpy()
         e64 = E64.cpu().numpy()
