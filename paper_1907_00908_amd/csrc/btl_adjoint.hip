@@ -31,16 +31,45 @@
 
 namespace btl {
 
+// Per-site arithmetic runs in the precision of the stored populations (FP32
+// storage: FP32 products, which the stored adjoint rounds to anyway); every
+// sum over sites, steps and workgroups is FP64.
+template <typename V> struct AdjReal;
+template <> struct AdjReal<float2> { using R = float; };
+template <> struct AdjReal<double2> { using R = double; };
+
+__device__ __forceinline__ float2 cmulr(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmulr(double2 a, double2 b) { return cmul(a, b); }
+template <typename V> __device__ __forceinline__ V mk2(double x, double y);
+template <> __device__ __forceinline__ float2 mk2<float2>(double x, double y) {
+    return make_float2((float)x, (float)y);
+}
+template <> __device__ __forceinline__ double2 mk2<double2>(double x, double y) {
+    return make_double2(x, y);
+}
+__device__ __forceinline__ void store_stream(float2* p, float2 v) {
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+}
+__device__ __forceinline__ void store_stream(double2* p, double2 v) {
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+}
+
 template <typename V, int TX>
 __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
+    using R = typename AdjReal<V>::R;
     constexpr int TY = kBlock / TX;
     constexpr int NT = kAdjMaxPhase * kAdjMaxPhase;   // membrane pair sums per thread (LDS row)
     constexpr int RS = NT + 1;                         // odd row stride
-    __shared__ double c_w[kAdjMaxPhase], c_dec[kAdjMaxPhase], c_tr[kAdjMaxPhase * kAdjMaxPhase];
+    __shared__ double c_tr[kAdjMaxPhase * kAdjMaxPhase];
+    __shared__ R c_w[kAdjMaxPhase], c_dec[kAdjMaxPhase], c_rdec[kAdjMaxPhase];
     __shared__ double acc[kBlock * RS];
     __shared__ double red[kNGMax];
-    __shared__ double2 ffac[6], afac[6];   // forward / adjoint face factors of this field
-    __shared__ double beta[6];
+    __shared__ V ffac[6], afac[6];   // forward / adjoint face factors of this field
+    __shared__ R beta[6];
     __shared__ int last_flag;
     const int P = a.n_phase;
     const int NG = a.ng;
@@ -48,8 +77,9 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
     {
         const int t = threadIdx.x;
         if (t < P) {
-            c_w[t] = a.w[t];
-            c_dec[t] = a.decay[t];
+            c_w[t] = (R)a.w[t];
+            c_dec[t] = (R)a.decay[t];
+            c_rdec[t] = (R)(1.0 / a.decay[t]);
         }
         if (t < P * P) c_tr[t] = a.trans[t];
         for (int g = 0; g < RS; ++g) acc[t * RS + g] = 0.0;
@@ -84,9 +114,11 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
     const double2* __restrict__ tabp = a.tab_prev + fd.tab;
     if (threadIdx.x < 6) {
         const int f = threadIdx.x;
-        ffac[f] = tabp[n0 + n1 + n2 + f];
-        afac[f] = a.top ? make_double2(1.0, 0.0) : a.tab_cur[fd.adj_fac[f]];
-        beta[f] = fd.beta[f];
+        const double2 ff = tabp[n0 + n1 + n2 + f];
+        const double2 af = a.top ? make_double2(1.0, 0.0) : a.tab_cur[fd.adj_fac[f]];
+        ffac[f] = mk2<V>(ff.x, ff.y);
+        afac[f] = mk2<V>(af.x, af.y);
+        beta[f] = (R)fd.beta[f];
     }
     int32_t kind[6], akind[6];
     int32_t fpop[6], apop[6];
@@ -100,10 +132,10 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
     __syncthreads();
     const double cx0 = fd.c[0], cx1 = fd.c[1], cx2 = fd.c[2], cu = fd.cu;
     const double dt = a.dt;
-    double2 mu = make_double2(0.0, 0.0);
+    V mu = mk2<V>(0.0, 0.0);
     if (fd.q >= 0) {
         const double2 m = a.dLdE[(int64_t)fd.q * (a.K + 1) + a.k];
-        mu = make_double2(m.x / ns, m.y / ns);
+        mu = mk2<V>(m.x / ns, m.y / ns);
     }
     // register sums of the per-phase sensitivities (selected by phase)
     double sw[kAdjMaxPhase] = {0.0, 0.0, 0.0, 0.0};
@@ -111,7 +143,8 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
     double sf = 0.0, sF = 0.0;
 
     if (j0 < n0 && j1 < n1) {
-        const double2 exy = cmul(tabp[j0], tabp[n0 + j1]);
+        const double2 exyd = cmul(tabp[j0], tabp[n0 + j1]);
+        const V exy = mk2<V>(exyd.x, exyd.y);
         const bool fx0 = j0 == 0, fx1 = j0 == n0 - 1, fy0 = j1 == 0, fy1 = j1 == n1 - 1;
         // forward pull offsets (relative to the site index), as in k_step
         auto face_off = [&](int f, int d, int32_t wrap) -> int32_t {
@@ -154,10 +187,10 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
             const bool flo[3] = {fx0, fy0, fz0}, fhi[3] = {fx1, fy1, fz1};
 
             // ---- adjoint pull of Lambda^k ----
-            double2 lh[kQ];
+            V lh[kQ];
             if (a.top) {
 #pragma unroll
-                for (int d = 0; d < kQ; ++d) lh[d] = make_double2(0.0, 0.0);
+                for (int d = 0; d < kQ; ++d) lh[d] = mk2<V>(0.0, 0.0);
             } else {
                 V rl[kQ], rlown[kQ];
                 rl[0] = lam[pop + s];
@@ -172,26 +205,30 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
                     const int od = (d & 1) ? d + 1 : d - 1;
                     rlown[d] = lam[pop + od * ns + s];
                 }
-                lh[0] = ld2(&rl[0]);
+                lh[0] = rl[0];
 #pragma unroll
                 for (int d = 1; d < kQ; ++d) {
                     const int ax = (d - 1) >> 1;
                     const bool plus = (d & 1) != 0;      // destination y + e_d
                     const int od = plus ? d + 1 : d - 1;
-                    double2 x = ld2(&rl[d]);
+                    V x = rl[d];
                     if (plus ? fhi[ax] : flo[ax]) {
                         const int f = 2 * ax + (plus ? 1 : 0);
-                        if (akind[f] & kFaceConj)
-                            x = cmul(make_double2(x.x, -x.y), afac[f]);
-                        else
-                            x = cmul(make_double2(afac[f].x, -afac[f].y), x);
+                        const V af = afac[f];
+                        if (akind[f] & kFaceConj) {
+                            x.y = -x.y;
+                            x = cmulr(x, af);
+                        } else {
+                            x = cmulr(V{af.x, -af.y}, x);
+                        }
                     }
                     // membrane between this node and y + e_d: bit of the
                     // opposite pull direction at this node
                     if ((mask >> (od - 1)) & 1u) {
-                        const double t = c_tr[p * P + nbphase(od)];
-                        if (t < 1.0) {
-                            const double2 lo = ld2(&rlown[d]);
+                        const double td = c_tr[p * P + nbphase(od)];
+                        if (td < 1.0) {
+                            const R t = (R)td;
+                            const V lo = rlown[d];
                             x.x = lo.x + t * (x.x - lo.x);
                             x.y = lo.y + t * (x.y - lo.y);
                         }
@@ -199,10 +236,10 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
                     lh[d] = x;
                 }
             }
-            double2 sl = make_double2(0.0, 0.0);
+            V sl = mk2<V>(0.0, 0.0);
 #pragma unroll
             for (int d = 0; d < kQ; ++d) {
-                const double wd = d == 0 ? 0.25 : 0.125;
+                const R wd = d == 0 ? (R)0.25 : (R)0.125;
                 sl.x += wd * lh[d].x;
                 sl.y += wd * lh[d].y;
             }
@@ -222,63 +259,65 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
                 const int od = (d & 1) ? d + 1 : d - 1;
                 rown[d] = fwd[pop + od * ns + s];
             }
-            const double2 ezj = tabp[n0 + n1 + j2];
-            const double dec = c_dec[p];
-            const double w = c_w[p];
-            const double2 e = cmul(exy, ezj);
-            const double2 c = make_double2(e.x * dec, e.y * dec);
-            const double2 cc = make_double2(c.x, -c.y);
+            const double2 ezd = tabp[n0 + n1 + j2];
+            const R dec = c_dec[p];
+            const R w = c_w[p];
+            const V e = cmulr(exy, mk2<V>(ezd.x, ezd.y));
+            const V c = V{e.x * dec, e.y * dec};
+            const V cc = V{c.x, -c.y};
 
             // ---- per direction: forward step k-1 recomputed, transposed
             // collision and reaction, sensitivities ----
-            double2 M = make_double2(0.0, 0.0);
-            double glg = 0.0, gdec = 0.0, gim = 0.0;
+            V M = mk2<V>(0.0, 0.0);
+            R glg = 0, gdec = 0, gim = 0;
 #pragma unroll
             for (int d = 0; d < kQ; ++d) {
                 const int ax = d > 0 ? (d - 1) >> 1 : 0;
                 const bool plus = (d & 1) != 0;
                 const bool face = d > 0 && (plus ? flo[ax] : fhi[ax]);
                 const int f = 2 * ax + (plus ? 0 : 1);
-                double2 vv = ld2(&rg[d]);
+                V vv = rg[d];
                 if (face) {
                     if (kind[f] & kFaceConj) vv.y = -vv.y;
-                    vv = cmul(vv, ffac[f]);
+                    vv = cmulr(vv, ffac[f]);
                 }
-                double2 gpd = vv;
-                double tl = 1.0;
-                double2 dv = make_double2(0.0, 0.0);
+                V gpd = vv;
+                R tl = 1;
+                V dv = mk2<V>(0.0, 0.0);
                 if (d > 0 && ((mask >> (d - 1)) & 1u)) {
-                    const double t = c_tr[p * P + nbphase(d)];
-                    if (t < 1.0) {
-                        const double2 ow = ld2(&rown[d]);
+                    const double td = c_tr[p * P + nbphase(d)];
+                    if (td < 1.0) {
+                        const R t = (R)td;
+                        const V ow = rown[d];
                         tl = t;
-                        dv = make_double2(vv.x - ow.x, vv.y - ow.y);
+                        dv = V{vv.x - ow.x, vv.y - ow.y};
                         gpd.x = ow.x + t * dv.x;
                         gpd.y = ow.y + t * dv.y;
                     }
                 }
-                const double2 g = cmul(gpd, c);
+                const V g = cmulr(gpd, c);
                 M.x += g.x;
                 M.y += g.y;
                 glg += lh[d].x * g.x + lh[d].y * g.y;
-                double2 nu;
-                nu.x = (1.0 - w) * lh[d].x + w * sl.x + mu.x;
-                nu.y = (1.0 - w) * lh[d].y + w * sl.y + mu.y;
+                V nu;
+                nu.x = (1 - w) * lh[d].x + w * sl.x + mu.x;
+                nu.y = (1 - w) * lh[d].y + w * sl.y + mu.y;
                 gdec += nu.x * g.x + nu.y * g.y;
                 gim += nu.x * g.y - nu.y * g.x;
-                const double2 lo2 = cmul(cc, nu);
-                store2_stream(out + pop + d * ns + s, lo2);
-                if (tl < 1.0) my[p * P + nbphase(d)] += lo2.x * dv.x + lo2.y * dv.y;
-                if (face) sF += -beta[f] * tl * (lo2.x * vv.y - lo2.y * vv.x);
+                const V lo2 = cmulr(cc, nu);
+                store_stream(out + pop + d * ns + s, lo2);
+                if (tl < 1) my[p * P + nbphase(d)] += (double)(lo2.x * dv.x + lo2.y * dv.y);
+                if (face) sF += (double)(-beta[f] * tl * (lo2.x * vv.y - lo2.y * vv.x));
             }
             // collision: sum_d Re conj(lhat_d) (w_d M - g_d)
-            const double gw = sl.x * M.x + sl.y * M.y - glg;
+            const double gw = (double)(sl.x * M.x + sl.y * M.y - glg);
+            const double gd = (double)(gdec * c_rdec[p]);
 #pragma unroll
             for (int i = 0; i < kAdjMaxPhase; ++i) {
                 sw[i] += (p == i) ? gw : 0.0;
-                sdec[i] += (p == i) ? gdec / dec : 0.0;
+                sdec[i] += (p == i) ? gd : 0.0;
             }
-            sf += dt * (cx0 * j0 + cx1 * j1 + cx2 * j2 + cu) * gim;
+            sf += dt * (cx0 * j0 + cx1 * j1 + cx2 * j2 + cu) * (double)gim;
         }
     }
 
