@@ -100,9 +100,8 @@ struct StepArgs {
     const double* w;        // [P] 1/tau
     const double* decay;    // [P] exp(-dt/T2)
     const double* trans;    // [P*P] transmitted share 1/(1+P) of a membrane link
-    double2* partial;       // [blocks] per-workgroup signal partial sums
-    uint32_t* counter;      // [fields] arrival counters for the last-block reduction
-    double* E;              // [Q][K+1][2]
+    double2* partial;       // [kTabSteps][blocks][kBlock/64] per-wave signal partial sums
+                            // of step k in slot k mod kTabSteps (launch_esum adds them up)
     const double* rdt;      // [P] dt/T2 (classical scheme)
     // General membrane condition (theta = 0, membrane anywhere on the link):
     // gm[(d-1)*nsites + s] is, for the pull link of direction d into site s,
@@ -155,6 +154,11 @@ hipError_t launch_init_classical(int prec, void* pop, const FieldDesc* h_fields,
                                  int32_t nq, hipStream_t st);
 // phase tables of steps a.k .. a.k + nsteps - 1 into a.tab[0 .. nsteps*T)
 hipError_t launch_tables(const StepArgs& a, int32_t nsteps, hipStream_t st);
+// signal E_{k+1} of steps k = k0 .. k0 + nsteps - 1 (nsteps <= kTabSteps) from
+// the per-wave partial sums the step kernels left in partial
+hipError_t launch_esum(const double2* partial, const FieldDesc* d_fields, int32_t n_fields,
+                       int32_t nblk_total, int32_t k0, int32_t nsteps, double* E, int32_t K,
+                       hipStream_t st);
 hipError_t launch_mfinal(int prec, const void* pop, const FieldDesc* h_fields,
                          int32_t n_fields, void* M_out, int32_t nq, hipStream_t st);
 

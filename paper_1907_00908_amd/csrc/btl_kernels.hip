@@ -28,9 +28,9 @@
 // that position (Eqs. B2a_text/B2b_text, B4a-B4c) instead of the half-link
 // form (GM = true; other links keep the half-link form).
 //
-// The signal of a step is reduced deterministically: each workgroup writes a
-// partial sum, and the last workgroup of a field to finish (arrival counter)
-// adds all partials of that field in a fixed order.
+// The signal of a step is reduced deterministically: each wave writes its
+// partial sum to a per-step slot, and k_esum (one launch per 32 steps) adds
+// the partials of every field in a fixed order.
 #include <type_traits>
 
 #include "btl_device.h"
@@ -88,11 +88,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     // (planes 3, 4 pull along z), while site words and membrane positions
     // keep the geometry's own direction numbering, which is p.
     auto face_of = [](int p) { return NQ == 7 ? p - 1 : (p <= 2 ? p - 1 : p + 1); };
-    __shared__ double2 lds[kBlock / 64];
     __shared__ double c_w[kMaxPhase], c_dec[kMaxPhase], c_tr[kMaxPhase * kMaxPhase];
     __shared__ double c_kdt[GM ? kMaxPhase * kMaxPhase : 1];
     __shared__ double2 c_ez[CL ? 1 : kMaxZc];   // z phase factors of this tile's column range
-    __shared__ int last_flag;
     // per-phase constants in LDS: lane-indexed lookups then go through the
     // LDS counter and never wait on outstanding global loads or stores
     {
@@ -342,32 +340,42 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     }
 
     if (fd.q < 0) return;   // image fields do not enter the signal
-    const double2 bsum = block_sum(Mv, lds);
-    if (threadIdx.x == 0) {
-        double* pp = &a.partial[lb].x;
-        __hip_atomic_store(pp, bsum.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(pp + 1, bsum.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const uint32_t prev = __hip_atomic_fetch_add(a.counter + fi, 1u, __ATOMIC_ACQ_REL,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-        last_flag = (prev == (uint32_t)(fd.nblk - 1));
+    // Per-wave partial of the signal; k_esum adds them up in a fixed order
+    // after the step (no fence or atomic here: a device-scope release at the
+    // end of every workgroup stalled the whole step).
+    const double mx = wave_sum(Mv.x), my = wave_sum(Mv.y);
+    if ((threadIdx.x & 63) == 0)
+        a.partial[((size_t)(a.k % kTabSteps) * gridDim.x + lb) * (kBlock / 64) +
+                  (threadIdx.x >> 6)] = make_double2(mx, my);
+}
+
+// E_{k+1} = (1/N) sum of the per-wave partials of a primary field, one wave
+// per (field, step): lanes stride over the field's partials in order, then a
+// fixed shuffle tree, so the signal is bitwise reproducible.
+__global__ void __launch_bounds__(kBlock) k_esum(const double2* __restrict__ partial,
+                                                 const FieldDesc* __restrict__ fields,
+                                                 int32_t n_fields, int32_t nblk_total,
+                                                 int32_t k0, int32_t nsteps, double2* E,
+                                                 int32_t K) {
+    const int32_t pair = (int32_t)blockIdx.x * (kBlock / 64) + (int32_t)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (pair >= n_fields * nsteps) return;   // whole waves leave together
+    const int32_t fi = pair / nsteps, j = pair % nsteps;
+    const FieldDesc& fd = fields[fi];
+    if (fd.q < 0) return;
+    const int32_t k = k0 + j;
+    const double2* p = partial + ((size_t)(k % kTabSteps) * nblk_total + fd.blk0) * (kBlock / 64);
+    const int32_t n = fd.nblk * (kBlock / 64);
+    double sx = 0.0, sy = 0.0;
+    for (int32_t i = lane; i < n; i += 64) {
+        sx += p[i].x;
+        sy += p[i].y;
     }
-    __syncthreads();
-    if (!last_flag) return;
-    __threadfence();
-    double2 acc = make_double2(0.0, 0.0);
-    for (int i = threadIdx.x; i < fd.nblk; i += kBlock) {
-        double* pp = &a.partial[fd.blk0 + i].x;
-        acc.x += __hip_atomic_load(pp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        acc.y += __hip_atomic_load(pp + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    const double2 tot = block_sum(acc, lds);
-    if (threadIdx.x == 0) {
-        const double inv = 1.0 / (double)ns;
-        double2* E = reinterpret_cast<double2*>(a.E);
-        E[(int64_t)fd.q * (a.K + 1) + a.k + 1] = make_double2(tot.x * inv, tot.y * inv);
-        __hip_atomic_store(a.counter + fi, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    sx = wave_sum(sx);
+    sy = wave_sum(sy);
+    if (lane == 0) {
+        const double inv = 1.0 / (double)fd.nsites;
+        E[(int64_t)fd.q * (K + 1) + k + 1] = make_double2(sx * inv, sy * inv);
     }
 }
 
@@ -501,6 +509,17 @@ hipError_t launch_init_classical(int prec, void* pop, const FieldDesc* h, int32_
                                dim3(kBlock), 0, st, static_cast<double2*>(pop), h[f], words, fdt,
                                rdt, nq);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_esum(const double2* partial, const FieldDesc* d_fields, int32_t n_fields,
+                       int32_t nblk_total, int32_t k0, int32_t nsteps, double* E, int32_t K,
+                       hipStream_t st) {
+    const int64_t waves = (int64_t)n_fields * nsteps;
+    if (waves > 0)
+        hipLaunchKernelGGL(k_esum, dim3((unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64))),
+                           dim3(kBlock), 0, st, partial, d_fields, n_fields, nblk_total, k0,
+                           nsteps, reinterpret_cast<double2*>(E), K);
     return hipGetLastError();
 }
 

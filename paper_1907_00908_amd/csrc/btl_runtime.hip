@@ -80,8 +80,7 @@ struct btl_sim {
     DevBuf<int32_t> blk_field;
     DevBuf<double> steps;        // fdt [K] then Fk [K+1]
     DevBuf<double> consts;       // w [P], decay [P], trans [P*P], T2 [P], kappa [P*P], dt/T2 [P]
-    DevBuf<double2> partial;
-    DevBuf<uint32_t> counter;
+    DevBuf<double2> partial;     // per-wave signal partials of kTabSteps steps
     DevBuf<double2> tab;         // [kTabSteps][T] per-step phase tables
     DevBuf<int32_t> tab_field;   // [T]
     std::vector<FieldDesc> h_fields;
@@ -123,7 +122,6 @@ struct btl_sim {
     DevBuf<double> gpart;
     DevBuf<double> gfield;
     DevBuf<uint32_t> adj_counter;
-    DevBuf<double> scratch_E;
     std::string err;
 };
 
@@ -628,21 +626,14 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     if ((e = s->pop[0].ensure((size_t)pop_elems * esz)) != hipSuccess ||
         (e = s->pop[1].ensure((size_t)pop_elems * esz)) != hipSuccess)
         return hip_fail(s, e, "allocating populations");
-    const size_t old_counter_cap = s->counter.cap;
     if ((e = s->fields.ensure(n_fields)) != hipSuccess ||
         (e = s->blk_field.ensure(nblk_total)) != hipSuccess ||
         (e = s->steps.ensure(steps.size())) != hipSuccess ||
         (e = s->consts.ensure(consts.size())) != hipSuccess ||
-        (e = s->partial.ensure(nblk_total)) != hipSuccess ||
-        (e = s->counter.ensure(n_fields)) != hipSuccess ||
+        (e = s->partial.ensure((size_t)kTabSteps * nblk_total * (kBlock / 64))) != hipSuccess ||
         (e = s->tab.ensure((size_t)kTabSteps * T)) != hipSuccess ||
         (e = s->tab_field.ensure(T)) != hipSuccess)
         return hip_fail(s, e, "allocating tables");
-    if (s->counter.cap != old_counter_cap) {
-        // arrival counters start at zero; every step leaves them at zero
-        if ((e = hipMemset(s->counter.p, 0, s->counter.cap * sizeof(uint32_t))) != hipSuccess)
-            return hip_fail(s, e, "clearing counters");
-    }
     // stage all tables in pinned memory and upload asynchronously
     const size_t b_fields = (size_t)n_fields * sizeof(FieldDesc);
     const size_t b_blk = (size_t)nblk_total * sizeof(int32_t);
@@ -747,8 +738,6 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         a.xcd = xcd_on;
         a.classical = classical ? 1 : 0;
         a.partial = s->partial.p;
-        a.counter = s->counter.p;
-        a.E = Eptr;
         a.n_phase = P;
         a.K = K;
         a.tab_field = s->tab_field.p;
@@ -766,6 +755,12 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
             a.k = k;
             if ((err = launch_step(s->prec, shape, a, nblk_total, q)) != hipSuccess)
                 return hip_fail(s, err, "step launch");
+            if ((k + 1) % kTabSteps == 0 || k + 1 == K) {
+                const int32_t k0 = k - k % kTabSteps;
+                if ((err = launch_esum(s->partial.p, s->fields.p, n_fields, nblk_total, k0,
+                                       k + 1 - k0, Eptr, K, q)) != hipSuccess)
+                    return hip_fail(s, err, "signal launch");
+            }
             if (ckpt_every > 0 && (k + 1) % s->tape.C == 0 && k + 1 < K) {
                 const size_t m = (size_t)(k + 1) / s->tape.C;
                 if ((err = hipMemcpyAsync(s->ckpt.p + m * state_bytes, s->pop[(k + 1) & 1].p,
@@ -797,7 +792,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         key.nq = nq;
         key.xcd = xcd_on;
         const void* ptrs[] = {s->pop[0].p, s->pop[1].p, s->fields.p, s->blk_field.p, s->steps.p,
-                              s->consts.p, s->partial.p, s->counter.p, s->tab.p, s->tab_field.p,
+                              s->consts.p, s->partial.p, s->tab.p, s->tab_field.p,
                               s->E_int.p, s->ckpt.p, s->words.p};
         static_assert(sizeof(ptrs) / sizeof(ptrs[0]) <= sizeof(key.ptr) / sizeof(key.ptr[0]),
                       "graph key too small");
@@ -926,8 +921,7 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
         (e = s->lam[1].ensure(state_bytes)) != hipSuccess ||
         (e = s->tab_b.ensure((size_t)(C + 1) * T)) != hipSuccess ||
         (e = s->gpart.ensure((size_t)tp.nblk * NG)) != hipSuccess ||
-        (e = s->gfield.ensure((size_t)K * nf * NG)) != hipSuccess ||
-        (e = s->scratch_E.ensure((size_t)tp.Q * (K + 1) * 2)) != hipSuccess)
+        (e = s->gfield.ensure((size_t)K * nf * NG)) != hipSuccess)
         return hip_fail(s, e, "allocating adjoint buffers");
     const size_t old_cap = s->adj_counter.cap;
     if ((e = s->adj_counter.ensure(nf)) != hipSuccess) return hip_fail(s, e, "adjoint counters");
@@ -946,8 +940,6 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
     fa.decay = s->consts.p + P;
     fa.trans = s->consts.p + 2 * P;
     fa.partial = s->partial.p;
-    fa.counter = s->counter.p;
-    fa.E = s->scratch_E.p;
     fa.n_phase = P;
     fa.K = K;
     fa.tab_field = s->tab_field.p;
@@ -1168,7 +1160,6 @@ extern "C" void btl_destroy(btl_sim* s) {
     s->steps.release();
     s->consts.release();
     s->partial.release();
-    s->counter.release();
     s->tune_E.release();
     if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
@@ -1181,7 +1172,6 @@ extern "C" void btl_destroy(btl_sim* s) {
     s->gpart.release();
     s->gfield.release();
     s->adj_counter.release();
-    s->scratch_E.release();
     s->tab.release();
     s->tab_field.release();
     for (int i = 0; i < 2; ++i) {
