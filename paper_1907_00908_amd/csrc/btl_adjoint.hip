@@ -70,7 +70,6 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
     __shared__ double red[kNGMax];
     __shared__ V ffac[6], afac[6];   // forward / adjoint face factors of this field
     __shared__ R beta[6];
-    __shared__ int last_flag;
     const int P = a.n_phase;
     const int NG = a.ng;
     const int IW = 0, IDEC = P, IT = 2 * P, IF = 2 * P + P * P, IFF = IF + 1;
@@ -321,7 +320,9 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
         }
     }
 
-    // ---- workgroup sums (fixed order), then the last workgroup of the field ----
+    // ---- workgroup sums (fixed order) into this step's slot; k_adj_gsum adds
+    // the workgroups of each field after the segment (no fence or arrival
+    // counter at the end of every workgroup) ----
     if (threadIdx.x < NG) red[threadIdx.x] = 0.0;
     __syncthreads();
     // register sums: wave reduction, then the four waves in order
@@ -354,27 +355,26 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
     }
     __syncthreads();
     if (threadIdx.x < NG)
-        __hip_atomic_store(a.gpart + (int64_t)lb * NG + threadIdx.x, red[threadIdx.x],
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t prev = __hip_atomic_fetch_add(a.counter + fi, 1u, __ATOMIC_ACQ_REL,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-        last_flag = (prev == (uint32_t)(fd.nblk - 1));
-    }
-    __syncthreads();
-    if (!last_flag) return;
-    __threadfence();
-    if (threadIdx.x < NG) {
-        double sacc = 0.0;
-        for (int i = 0; i < fd.nblk; ++i)
-            sacc += __hip_atomic_load(a.gpart + (int64_t)(fd.blk0 + i) * NG + threadIdx.x,
-                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        a.gfield[((int64_t)(a.k - 1) * a.n_fields + fi) * NG + threadIdx.x] = sacc;
-    }
-    if (threadIdx.x == 0)
-        __hip_atomic_store(a.counter + fi, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a.gpart[((int64_t)a.slot * gridDim.x + lb) * NG + threadIdx.x] = red[threadIdx.x];
+}
+
+// One thread per (step slot, field, accumulator): the field's workgroup sums
+// in workgroup order.
+__global__ void __launch_bounds__(kBlock) k_adj_gsum(const double* __restrict__ gpart,
+                                                     const FieldDesc* __restrict__ fields,
+                                                     int32_t n_fields, int32_t nblk_total,
+                                                     int32_t ng, int32_t k_first, int32_t nsteps,
+                                                     double* gfield) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)nsteps * n_fields * ng) return;
+    const int32_t g = (int32_t)(t % ng);
+    const int32_t f = (int32_t)((t / ng) % n_fields);
+    const int32_t j = (int32_t)(t / ((int64_t)ng * n_fields));
+    const FieldDesc& fd = fields[f];
+    const double* p = gpart + ((int64_t)j * nblk_total + fd.blk0) * ng + g;
+    double sacc = 0.0;
+    for (int32_t i = 0; i < fd.nblk; ++i) sacc += p[(int64_t)i * ng];
+    gfield[((int64_t)(k_first + j) * n_fields + f) * ng + g] = sacc;
 }
 
 // Sums the per-step, per-field records in a fixed order and maps them to the
@@ -458,6 +458,17 @@ hipError_t launch_adj(int prec, int shape, const AdjArgs& a, int32_t n_blocks, h
         launch_adj_t<float2>(shape, a, n_blocks, st);
     else
         launch_adj_t<double2>(shape, a, n_blocks, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_gsum(const double* gpart, const FieldDesc* d_fields, int32_t n_fields,
+                           int32_t nblk_total, int32_t ng, int32_t k_first, int32_t nsteps,
+                           double* gfield, hipStream_t st) {
+    const int64_t n = (int64_t)nsteps * n_fields * ng;
+    if (n > 0)
+        hipLaunchKernelGGL(k_adj_gsum, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
+                           0, st, gpart, d_fields, n_fields, nblk_total, ng, k_first, nsteps,
+                           gfield);
     return hipGetLastError();
 }
 

@@ -75,9 +75,8 @@ struct AdjArgs {
     const double* decay;
     const double* trans;
     const double2* dLdE;    // [Q][K+1]
-    double* gpart;          // [blocks][NG] per-workgroup gradient sums
-    uint32_t* counter;      // [fields]
-    double* gfield;         // [K][fields][NG] per-step, per-field gradient sums
+    double* gpart;          // [segment slot][blocks][NG] per-workgroup gradient sums
+                            // (launch_adj_gsum adds them up per field)
     double dt;
     int32_t n_fields;
     int32_t n_phase;
@@ -86,7 +85,7 @@ struct AdjArgs {
     int32_t top;            // 1 when k = K (no adjoint from later steps)
     int32_t ng;
     int32_t xcd;            // 1: XCD-contiguous workgroup order (xcd_tile)
-    int32_t pad;
+    int32_t slot;           // slot of this step in gpart (k - 1 - first step of the segment)
 };
 
 struct StepArgs {
@@ -138,6 +137,11 @@ inline void tile_dims(int shape, int* tx, int* ty) {
 
 // Launchers (btl_kernels.hip, btl_adjoint.hip)
 hipError_t launch_adj(int prec, int shape, const AdjArgs& a, int32_t n_blocks, hipStream_t st);
+// gfield[(k_first + j) * n_fields + f][g] = sum over the workgroups of field f
+// of gpart[j][.][g], j = 0 .. nsteps - 1, in a fixed order
+hipError_t launch_adj_gsum(const double* gpart, const FieldDesc* d_fields, int32_t n_fields,
+                           int32_t nblk_total, int32_t ng, int32_t k_first, int32_t nsteps,
+                           double* gfield, hipStream_t st);
 hipError_t launch_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P,
                             double dt, double dx, const double* w, const double* T2,
                             const double* kappa, double* dD, double* dT2, double* dkappa,

@@ -121,7 +121,6 @@ struct btl_sim {
     DevBuf<double2> tab_b;         // [C+1][T] phase tables of a segment
     DevBuf<double> gpart;
     DevBuf<double> gfield;
-    DevBuf<uint32_t> adj_counter;
     std::string err;
 };
 
@@ -920,14 +919,9 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
         (e = s->lam[0].ensure(state_bytes)) != hipSuccess ||
         (e = s->lam[1].ensure(state_bytes)) != hipSuccess ||
         (e = s->tab_b.ensure((size_t)(C + 1) * T)) != hipSuccess ||
-        (e = s->gpart.ensure((size_t)tp.nblk * NG)) != hipSuccess ||
+        (e = s->gpart.ensure((size_t)C * tp.nblk * NG)) != hipSuccess ||
         (e = s->gfield.ensure((size_t)K * nf * NG)) != hipSuccess)
         return hip_fail(s, e, "allocating adjoint buffers");
-    const size_t old_cap = s->adj_counter.cap;
-    if ((e = s->adj_counter.ensure(nf)) != hipSuccess) return hip_fail(s, e, "adjoint counters");
-    if (s->adj_counter.cap != old_cap &&
-        (e = hipMemset(s->adj_counter.p, 0, s->adj_counter.cap * sizeof(uint32_t))) != hipSuccess)
-        return hip_fail(s, e, "clearing adjoint counters");
 
     StepArgs fa;   // forward recompute
     memset(&fa, 0, sizeof(fa));
@@ -957,8 +951,6 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
     aa.trans = s->consts.p + 2 * P;
     aa.dLdE = reinterpret_cast<const double2*>(dL_dE);
     aa.gpart = s->gpart.p;
-    aa.counter = s->adj_counter.p;
-    aa.gfield = s->gfield.p;
     aa.dt = tp.dt;
     aa.xcd = tp.xcd;
     aa.n_fields = nf;
@@ -996,10 +988,15 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
             aa.fwd = s->seg.p + (size_t)(k - 1 - k0) * state_bytes;
             aa.tab_prev = s->tab_b.p + (size_t)(k - 1 - k0) * T;
             aa.tab_cur = aa.top ? aa.tab_prev : s->tab_b.p + (size_t)(k - k0) * T;
+            aa.slot = k - 1 - k0;
             if ((e = launch_adj(s->prec, tp.shape, aa, tp.nblk, st)) != hipSuccess)
                 return hip_fail(s, e, "adjoint launch");
             lam_cur ^= 1;
         }
+        // per-step, per-field sums of this segment: gfield[k0 .. k1 - 1]
+        if ((e = launch_adj_gsum(s->gpart.p, s->fields.p, nf, tp.nblk, NG, k0, k1 - k0,
+                                 s->gfield.p, st)) != hipSuccess)
+            return hip_fail(s, e, "adjoint sum launch");
     }
     if ((e = launch_adj_final(s->gfield.p, K, nf, P, tp.dt, s->dx, s->consts.p,
                               s->consts.p + 2 * P + P * P, s->consts.p + 3 * P + P * P, dD, dT2,
@@ -1171,7 +1168,6 @@ extern "C" void btl_destroy(btl_sim* s) {
     s->tab_b.release();
     s->gpart.release();
     s->gfield.release();
-    s->adj_counter.release();
     s->tab.release();
     s->tab_field.release();
     for (int i = 0; i < 2; ++i) {
