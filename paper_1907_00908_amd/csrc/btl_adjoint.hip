@@ -101,7 +101,9 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
     const int32_t z1 = min(n2, z0 + fd.zc);
     const int32_t j0 = tx * TX + (int32_t)(threadIdx.x % TX);
     const int32_t j1 = ty * TY + (int32_t)(threadIdx.x / TX);
-    const int32_t st1 = n0, st2 = n0 * n1;
+    // site index s = j0 + st1 j1 + st2 j2 (site words); populations z-major:
+    // plane d of site (j0, j1, j2) at d ps + j0 + st1 j1 + zs j2
+    const int32_t st1 = n0, st2 = n0 * n1, ps = st2, zs = kQ * st2;
     // one base pointer per buffer for this field; every access is a 32-bit
     // element offset from it (image-field partners of the same q-sample
     // lie within +-2^31 elements, checked on the host)
@@ -148,34 +150,35 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
         // forward pull offsets (relative to the site index), as in k_step
         auto face_off = [&](int f, int d, int32_t wrap) -> int32_t {
             const int db = (d & 1) ? d + 1 : d - 1;
-            return (kind[f] & kFaceMirror) ? fpop[f] + db * ns : fpop[f] + d * ns + wrap;
+            return (kind[f] & kFaceMirror) ? fpop[f] + db * ps : fpop[f] + d * ps + wrap;
         };
         // adjoint pull offsets: destination y + e_d
         auto adj_off = [&](int f, int d, int32_t wrap) -> int32_t {
             const int db = (d & 1) ? d + 1 : d - 1;
-            return (akind[f] & kFaceMirror) ? apop[f] + db * ns : apop[f] + d * ns + wrap;
+            return (akind[f] & kFaceMirror) ? apop[f] + db * ps : apop[f] + d * ps + wrap;
         };
-        const int32_t o1 = fx0 ? face_off(0, 1, n0 - 1) : pop + 1 * ns - 1;
-        const int32_t o2 = fx1 ? face_off(1, 2, -(n0 - 1)) : pop + 2 * ns + 1;
-        const int32_t o3 = fy0 ? face_off(2, 3, (n1 - 1) * st1) : pop + 3 * ns - st1;
-        const int32_t o4 = fy1 ? face_off(3, 4, -(n1 - 1) * st1) : pop + 4 * ns + st1;
-        const int32_t q1 = fx1 ? adj_off(1, 1, -(n0 - 1)) : pop + 1 * ns + 1;
-        const int32_t q2 = fx0 ? adj_off(0, 2, n0 - 1) : pop + 2 * ns - 1;
-        const int32_t q3 = fy1 ? adj_off(3, 3, -(n1 - 1) * st1) : pop + 3 * ns + st1;
-        const int32_t q4 = fy0 ? adj_off(2, 4, (n1 - 1) * st1) : pop + 4 * ns - st1;
+        const int32_t o1 = fx0 ? face_off(0, 1, n0 - 1) : pop + 1 * ps - 1;
+        const int32_t o2 = fx1 ? face_off(1, 2, -(n0 - 1)) : pop + 2 * ps + 1;
+        const int32_t o3 = fy0 ? face_off(2, 3, (n1 - 1) * st1) : pop + 3 * ps - st1;
+        const int32_t o4 = fy1 ? face_off(3, 4, -(n1 - 1) * st1) : pop + 4 * ps + st1;
+        const int32_t q1 = fx1 ? adj_off(1, 1, -(n0 - 1)) : pop + 1 * ps + 1;
+        const int32_t q2 = fx0 ? adj_off(0, 2, n0 - 1) : pop + 2 * ps - 1;
+        const int32_t q3 = fy1 ? adj_off(3, 3, -(n1 - 1) * st1) : pop + 3 * ps + st1;
+        const int32_t q4 = fy0 ? adj_off(2, 4, (n1 - 1) * st1) : pop + 4 * ps - st1;
         // z offsets do not depend on the thread: wave-uniform
-        const int32_t o5i = pop + 5 * ns - st2;
-        const int32_t o6i = pop + 6 * ns + st2;
-        const int32_t q5i = pop + 5 * ns + st2;
-        const int32_t q6i = pop + 6 * ns - st2;
-        const int32_t o5f = face_off(4, 5, (n2 - 1) * st2);
-        const int32_t o6f = face_off(5, 6, -(n2 - 1) * st2);
-        const int32_t q5f = adj_off(5, 5, -(n2 - 1) * st2);
-        const int32_t q6f = adj_off(4, 6, (n2 - 1) * st2);
+        const int32_t o5i = pop + 5 * ps - zs;
+        const int32_t o6i = pop + 6 * ps + zs;
+        const int32_t q5i = pop + 5 * ps + zs;
+        const int32_t q6i = pop + 6 * ps - zs;
+        const int32_t o5f = face_off(4, 5, (n2 - 1) * zs);
+        const int32_t o6f = face_off(5, 6, -(n2 - 1) * zs);
+        const int32_t q5f = adj_off(5, 5, -(n2 - 1) * zs);
+        const int32_t q6f = adj_off(4, 6, (n2 - 1) * zs);
 
 #pragma nounroll
         for (int32_t j2 = z0; j2 < z1; ++j2) {
             const int32_t s = j0 + st1 * j1 + st2 * j2;
+            const int32_t sp = j0 + st1 * j1 + zs * j2;
             const bool fz0 = j2 == 0, fz1 = j2 == n2 - 1;
             // Two load phases per node keep the live register set small:
             // first the adjoint (consumed into lhat), then the forward state.
@@ -192,17 +195,17 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
                 for (int d = 0; d < kQ; ++d) lh[d] = mk2<V>(0.0, 0.0);
             } else {
                 V rl[kQ], rlown[kQ];
-                rl[0] = lam[pop + s];
-                rl[1] = lam[q1 + s];
-                rl[2] = lam[q2 + s];
-                rl[3] = lam[q3 + s];
-                rl[4] = lam[q4 + s];
-                rl[5] = lam[(fz1 ? q5f : q5i) + s];
-                rl[6] = lam[(fz0 ? q6f : q6i) + s];
+                rl[0] = lam[pop + sp];
+                rl[1] = lam[q1 + sp];
+                rl[2] = lam[q2 + sp];
+                rl[3] = lam[q3 + sp];
+                rl[4] = lam[q4 + sp];
+                rl[5] = lam[(fz1 ? q5f : q5i) + sp];
+                rl[6] = lam[(fz0 ? q6f : q6i) + sp];
 #pragma unroll
                 for (int d = 1; d < kQ; ++d) {
                     const int od = (d & 1) ? d + 1 : d - 1;
-                    rlown[d] = lam[pop + od * ns + s];
+                    rlown[d] = lam[pop + od * ps + sp];
                 }
                 lh[0] = rl[0];
 #pragma unroll
@@ -246,17 +249,17 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
 
             // ---- forward state of step k-1 around this node ----
             V rg[kQ], rown[kQ];
-            rg[0] = fwd[pop + s];
-            rg[1] = fwd[o1 + s];
-            rg[2] = fwd[o2 + s];
-            rg[3] = fwd[o3 + s];
-            rg[4] = fwd[o4 + s];
-            rg[5] = fwd[(fz0 ? o5f : o5i) + s];
-            rg[6] = fwd[(fz1 ? o6f : o6i) + s];
+            rg[0] = fwd[pop + sp];
+            rg[1] = fwd[o1 + sp];
+            rg[2] = fwd[o2 + sp];
+            rg[3] = fwd[o3 + sp];
+            rg[4] = fwd[o4 + sp];
+            rg[5] = fwd[(fz0 ? o5f : o5i) + sp];
+            rg[6] = fwd[(fz1 ? o6f : o6i) + sp];
 #pragma unroll
             for (int d = 1; d < kQ; ++d) {
                 const int od = (d & 1) ? d + 1 : d - 1;
-                rown[d] = fwd[pop + od * ns + s];
+                rown[d] = fwd[pop + od * ps + sp];
             }
             const double2 ezd = tabp[n0 + n1 + j2];
             const R dec = c_dec[p];
@@ -304,7 +307,7 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
                 gdec += nu.x * g.x + nu.y * g.y;
                 gim += nu.x * g.y - nu.y * g.x;
                 const V lo2 = cmulr(cc, nu);
-                store_stream(out + pop + d * ns + s, lo2);
+                store_stream(out + pop + d * ps + sp, lo2);
                 if (tl < 1) my[p * P + nbphase(d)] += (double)(lo2.x * dv.x + lo2.y * dv.y);
                 if (face) sF += (double)(-beta[f] * tl * (lo2.x * vv.y - lo2.y * vv.x));
             }

@@ -19,8 +19,9 @@
 // which is the paper's collide -> stream -> react cycle (Eq.
 // LBM_process_list_2) started at the stream.  The classical LBM of Appendix A
 // (Eq. A12) shares steps 1 and 3 and moves the reaction into step 4.  All arithmetic is FP64;
-// populations are stored as float2 or double2 (x fastest, one plane per
-// direction per field).  Per-step constants enter only through forms that
+// populations are stored as float2 or double2, per field z-major:
+// [z][direction][y][x] (the seven planes of one z layer lie together, so the
+// tiles that run at the same time read and write one compact region).  Per-step constants enter only through forms that
 // keep sum_i g_i exact for any rounded constant (g + w(wM - g), a + t(b - a)).
 //
 // With membrane positions given, a membrane link whose six-node stencil lies
@@ -38,11 +39,11 @@
 namespace btl {
 
 template <typename V>
-__global__ void __launch_bounds__(kBlock) k_init(V* pop, int64_t nsites, double2* E,
+__global__ void __launch_bounds__(kBlock) k_init(V* pop, int64_t nsites, int64_t st2, double2* E,
                                                   int32_t q, int32_t K, int32_t nq) {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e < nsites * nq) {
-        const int d = (int)(e / nsites);
+        const int d = (int)((e / st2) % nq);   // z-major layout: [z][plane][y][x]
         store2(pop + e, make_double2(d == 0 ? lattice_w0(nq) : lattice_w1(nq), 0.0));
     }
     if (E != nullptr && q >= 0 && e == 0) E[(int64_t)q * (K + 1)] = make_double2(1.0, 0.0);
@@ -137,7 +138,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     const int32_t j0 = tx * TX + (int32_t)(threadIdx.x % TX);
     const int32_t j1 = ty * TY + (int32_t)(threadIdx.x / TX);
     const int32_t z1 = min(n2, z0 + fd.zc);
-    const int32_t st1 = n0, st2 = n0 * n1;
+    // site index s = j0 + st1 j1 + st2 j2 (site words, membrane positions);
+    // populations: plane d of site (j0, j1, j2) at d ps + j0 + st1 j1 + zs j2
+    const int32_t st1 = n0, st2 = n0 * n1, ps = st2, zs = NQ * st2;
     const double2 exy = CL ? make_double2(0.0, 0.0)
                            : cmul(tab[min(j0, n0 - 1)], tab[n0 + min(j1, n1 - 1)]);
     // classical: dt R = ra + i rb with rb = -f_{k+1} dt (c.j + cu)
@@ -160,17 +163,17 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     }
     auto face_off = [&](int f, int d, int32_t wrap) -> int32_t {
         const int db = (d & 1) ? d + 1 : d - 1;
-        return (kind[f] & kFaceMirror) ? fpop[f] + db * ns : fpop[f] + d * ns + wrap;
+        return (kind[f] & kFaceMirror) ? fpop[f] + db * ps : fpop[f] + d * ps + wrap;
     };
     const bool fx0 = j0 == 0, fx1 = j0 == n0 - 1, fy0 = j1 == 0, fy1 = j1 == n1 - 1;
-    const int32_t o1 = fx0 ? face_off(0, 1, n0 - 1) : pop + 1 * ns - 1;
-    const int32_t o2 = fx1 ? face_off(1, 2, -(n0 - 1)) : pop + 2 * ns + 1;
-    const int32_t o3 = fy0 ? face_off(2, 3, (n1 - 1) * st1) : pop + 3 * ns - st1;
-    const int32_t o4 = fy1 ? face_off(3, 4, -(n1 - 1) * st1) : pop + 4 * ns + st1;
+    const int32_t o1 = fx0 ? face_off(0, 1, n0 - 1) : pop + 1 * ps - 1;
+    const int32_t o2 = fx1 ? face_off(1, 2, -(n0 - 1)) : pop + 2 * ps + 1;
+    const int32_t o3 = fy0 ? face_off(2, 3, (n1 - 1) * st1) : pop + 3 * ps - st1;
+    const int32_t o4 = fy1 ? face_off(3, 4, -(n1 - 1) * st1) : pop + 4 * ps + st1;
     // z pulls of planes pz (+z) and pz + 1 (-z): interior and face offsets
     constexpr int pz = NQ == 7 ? 5 : 3;
-    const int32_t o5i = pop + pz * ns - st2, o5f = face_off(4, pz, (n2 - 1) * st2);
-    const int32_t o6i = pop + (pz + 1) * ns + st2, o6f = face_off(5, pz + 1, -(n2 - 1) * st2);
+    const int32_t o5i = pop + pz * ps - zs, o5f = face_off(4, pz, (n2 - 1) * zs);
+    const int32_t o6i = pop + (pz + 1) * ps + zs, o6f = face_off(5, pz + 1, -(n2 - 1) * zs);
 
     // Loads of one site: the site word, the seven pulled populations and the
     // six outgoing populations of the node itself (reflected at membrane
@@ -184,24 +187,26 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     };
     auto issue = [&](int32_t j2, SiteLoads& L) {
         const int32_t s = j0 + st1 * j1 + st2 * j2;
+        const int32_t sp = j0 + st1 * j1 + zs * j2;
         L.word = words[s];
-        L.g[0] = src[pop + s];
-        L.g[1] = src[o1 + s];
-        L.g[2] = src[o2 + s];
+        L.g[0] = src[pop + sp];
+        L.g[1] = src[o1 + sp];
+        L.g[2] = src[o2 + sp];
         if constexpr (NQ == 7) {
-            L.g[3] = src[o3 + s];
-            L.g[4] = src[o4 + s];
+            L.g[3] = src[o3 + sp];
+            L.g[4] = src[o4 + sp];
         }
-        L.g[pz] = src[(j2 == 0 ? o5f : o5i) + s];
-        L.g[pz + 1] = src[(j2 == n2 - 1 ? o6f : o6i) + s];
+        L.g[pz] = src[(j2 == 0 ? o5f : o5i) + sp];
+        L.g[pz + 1] = src[(j2 == n2 - 1 ? o6f : o6i) + sp];
 #pragma unroll
         for (int d = 1; d < NQ; ++d) {
             const int od = (d & 1) ? d + 1 : d - 1;
-            L.own[d - 1] = src[pop + od * ns + s];
+            L.own[d - 1] = src[pop + od * ps + sp];
         }
     };
     auto compute = [&](int32_t j2, const SiteLoads& L, double2& Macc) {
         const int32_t s = j0 + st1 * j1 + st2 * j2;
+        const int32_t sp = j0 + st1 * j1 + zs * j2;
         const bool fz0 = j2 == 0, fz1 = j2 == n2 - 1;
         const uint32_t word = L.word;
         const int p = (int)(word & 0xfu);
@@ -268,11 +273,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                     const double dd = v > 0.0f ? (double)v : 1.0 + (double)v;
                     const MembCoef c = membrane_coefficients(dd, c_kdt[p * P + pn], a.edx);
                     const int od = (d & 1) ? d + 1 : d - 1;
-                    const int32_t sa = d <= 2 ? 1 : (NQ == 7 && d <= 4) ? st1 : st2;
+                    const int32_t sa = d <= 2 ? 1 : (NQ == 7 && d <= 4) ? st1 : zs;
                     const int32_t e = (d & 1) ? sa : -sa;
-                    const double2 a2 = ld2(src + od * ns + s + e);
-                    const double2 b2 = ld2(src + d * ns + s - 2 * e);
-                    const double2 b3 = ld2(src + od * ns + s - e);
+                    const double2 a2 = ld2(src + od * ps + sp + e);
+                    const double2 b2 = ld2(src + d * ps + sp - 2 * e);
+                    const double2 b3 = ld2(src + od * ps + sp - e);
                     double2 r;
                     r.x = c.A[0] * o.x + c.A[1] * a2.x + c.A[2] * a3.x
                         + c.B[0] * b1.x + c.B[1] * b2.x + c.B[2] * b3.x;
@@ -309,7 +314,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
         }
         // collision: ghat = g + w (w_d M - g)  [+ w_d dt R M]
         const double w = c_w[p];
-        V* out = dst + s;
+        V* out = dst + sp;
 #pragma unroll
         for (int d = 0; d < NQ; ++d) {
             const double wd = d == 0 ? W0 : W1;
@@ -320,7 +325,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 h.x += wd * RM.x;
                 h.y += wd * RM.y;
             }
-            store2_stream(out + d * ns, h);
+            store2_stream(out + d * ps, h);
         }
     };
 
@@ -408,20 +413,23 @@ __global__ void __launch_bounds__(kBlock) k_init_classical(V* pop, FieldDesc fd,
     const int p = (int)(words[fd.words + s] & 0xfu);
     const double ra = 1.0 - rdt[p];
     const double rb = -fdt[0] * (fd.c[0] * j0 + fd.c[1] * j1 + fd.c[2] * j2 + fd.cu);
+    const int64_t st2 = (int64_t)n0 * n1;
+    const int64_t sp = j0 + (int64_t)n0 * j1 + (int64_t)nq * st2 * j2;
     for (int d = 0; d < nq; ++d) {
         const double wd = d == 0 ? lattice_w0(nq) : lattice_w1(nq);
-        store2(pop + fd.pop + (int64_t)d * fd.nsites + s, make_double2(wd * ra, wd * rb));
+        store2(pop + fd.pop + d * st2 + sp, make_double2(wd * ra, wd * rb));
     }
 }
 
 template <typename V>
-__global__ void __launch_bounds__(kBlock) k_mfinal(const V* pop, int64_t nsites, V* out,
-                                                    int32_t nq) {
+__global__ void __launch_bounds__(kBlock) k_mfinal(const V* pop, int64_t nsites, int64_t st2,
+                                                    V* out, int32_t nq) {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= nsites) return;
+    const int64_t sp = s % st2 + (s / st2) * nq * st2;
     double2 m = make_double2(0.0, 0.0);
     for (int d = 0; d < nq; ++d) {
-        const double2 v = ld2(pop + (int64_t)d * nsites + s);
+        const double2 v = ld2(pop + d * st2 + sp);
         m.x += v.x;
         m.y += v.y;
     }
@@ -434,14 +442,14 @@ hipError_t launch_init(int prec, void* pop, int64_t, const FieldDesc*, int32_t n
                        const FieldDesc* h, double* E, int32_t, int32_t K, int32_t nq,
                        hipStream_t st) {
     for (int f = 0; f < n_fields; ++f) {
-        const int64_t ns = h[f].nsites;
+        const int64_t ns = h[f].nsites, st2 = (int64_t)h[f].n[0] * h[f].n[1];
         if (prec == 1)
             hipLaunchKernelGGL(k_init<float2>, dim3(grid_for(ns * nq)), dim3(kBlock), 0, st,
-                               static_cast<float2*>(pop) + h[f].pop, ns,
+                               static_cast<float2*>(pop) + h[f].pop, ns, st2,
                                reinterpret_cast<double2*>(E), h[f].q, K, nq);
         else
             hipLaunchKernelGGL(k_init<double2>, dim3(grid_for(ns * nq)), dim3(kBlock), 0, st,
-                               static_cast<double2*>(pop) + h[f].pop, ns,
+                               static_cast<double2*>(pop) + h[f].pop, ns, st2,
                                reinterpret_cast<double2*>(E), h[f].q, K, nq);
     }
     return hipGetLastError();
@@ -534,14 +542,14 @@ hipError_t launch_mfinal(int prec, const void* pop, const FieldDesc* h, int32_t 
     int64_t off = 0;
     for (int f = 0; f < n_fields; ++f) {
         if (h[f].q < 0) continue;
-        const int64_t ns = h[f].nsites;
+        const int64_t ns = h[f].nsites, st2 = (int64_t)h[f].n[0] * h[f].n[1];
         if (prec == 1)
             hipLaunchKernelGGL(k_mfinal<float2>, dim3(grid_for(ns)), dim3(kBlock), 0, st,
-                               static_cast<const float2*>(pop) + h[f].pop, ns,
+                               static_cast<const float2*>(pop) + h[f].pop, ns, st2,
                                static_cast<float2*>(M_out) + off, nq);
         else
             hipLaunchKernelGGL(k_mfinal<double2>, dim3(grid_for(ns)), dim3(kBlock), 0, st,
-                               static_cast<const double2*>(pop) + h[f].pop, ns,
+                               static_cast<const double2*>(pop) + h[f].pop, ns, st2,
                                static_cast<double2*>(M_out) + off, nq);
         off += ns;
     }
