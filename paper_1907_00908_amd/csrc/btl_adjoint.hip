@@ -27,6 +27,8 @@
 // Per-phase sums are kept in registers (selected by the node's phase), the
 // membrane-pair sums in one LDS row per thread; workgroup and field sums are
 // formed in a fixed order, so the gradients are bitwise reproducible.
+#include <type_traits>
+
 #include "btl_device.h"
 
 namespace btl {
@@ -59,7 +61,7 @@ __device__ __forceinline__ void store_stream(double2* p, double2 v) {
 }
 
 template <typename V, int TX>
-__global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
+__device__ __forceinline__ void adj_body(const AdjArgs& a) {
     using R = typename AdjReal<V>::R;
     constexpr int TY = kBlock / TX;
     constexpr int NT = kAdjMaxPhase * kAdjMaxPhase;   // membrane pair sums per thread (LDS row)
@@ -143,7 +145,7 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
     double sdec[kAdjMaxPhase] = {0.0, 0.0, 0.0, 0.0};
     double sf = 0.0, sF = 0.0;
 
-    if (j0 < n0 && j1 < n1) {
+    if (j0 < n0 && j1 < n1 && z0 < z1) {
         const double2 exyd = cmul(tabp[j0], tabp[n0 + j1]);
         const V exy = mk2<V>(exyd.x, exyd.y);
         const bool fx0 = j0 == 0, fx1 = j0 == n0 - 1, fy0 = j1 == 0, fy1 = j1 == n1 - 1;
@@ -175,6 +177,21 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
         const int32_t q5f = adj_off(5, 5, -(n2 - 1) * zs);
         const int32_t q6f = adj_off(4, 6, (n2 - 1) * zs);
 
+        // Four values are shared with the z neighbour and carried along the
+        // column instead of reloaded: adjoint plane 6 at z is rlown[5] here
+        // and rl[6] of z + 1, plane 5 at z + 1 is rl[5] here and rlown[6] of
+        // z + 1; forward plane 5 at z is rown[6] here and rg[5] of z + 1,
+        // plane 6 at z + 1 is rg[6] here and rown[5] of z + 1.
+        V c_rl6 = mk2<V>(0.0, 0.0), c_rlo6 = mk2<V>(0.0, 0.0), c_rg5, c_ro5;
+        {
+            const int32_t sp = j0 + st1 * j1 + zs * z0;
+            if (!a.top) {
+                c_rl6 = lam[(z0 == 0 ? q6f : q6i) + sp];
+                c_rlo6 = lam[pop + 5 * ps + sp];
+            }
+            c_rg5 = fwd[(z0 == 0 ? o5f : o5i) + sp];
+            c_ro5 = fwd[pop + 6 * ps + sp];
+        }
 #pragma nounroll
         for (int32_t j2 = z0; j2 < z1; ++j2) {
             const int32_t s = j0 + st1 * j1 + st2 * j2;
@@ -201,12 +218,15 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
                 rl[3] = lam[q3 + sp];
                 rl[4] = lam[q4 + sp];
                 rl[5] = lam[(fz1 ? q5f : q5i) + sp];
-                rl[6] = lam[(fz0 ? q6f : q6i) + sp];
+                rl[6] = c_rl6;
 #pragma unroll
-                for (int d = 1; d < kQ; ++d) {
+                for (int d = 1; d < 6; ++d) {
                     const int od = (d & 1) ? d + 1 : d - 1;
                     rlown[d] = lam[pop + od * ps + sp];
                 }
+                rlown[6] = c_rlo6;
+                c_rl6 = rlown[5];
+                c_rlo6 = rl[5];
                 lh[0] = rl[0];
 #pragma unroll
                 for (int d = 1; d < kQ; ++d) {
@@ -254,13 +274,16 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
             rg[2] = fwd[o2 + sp];
             rg[3] = fwd[o3 + sp];
             rg[4] = fwd[o4 + sp];
-            rg[5] = fwd[(fz0 ? o5f : o5i) + sp];
+            rg[5] = c_rg5;
             rg[6] = fwd[(fz1 ? o6f : o6i) + sp];
 #pragma unroll
             for (int d = 1; d < kQ; ++d) {
                 const int od = (d & 1) ? d + 1 : d - 1;
-                rown[d] = fwd[pop + od * ps + sp];
+                if (d != 5) rown[d] = fwd[pop + od * ps + sp];
             }
+            rown[5] = c_ro5;
+            c_rg5 = rown[6];
+            c_ro5 = rg[6];
             const double2 ezd = tabp[n0 + n1 + j2];
             const R dec = c_dec[p];
             const R w = c_w[p];
@@ -361,6 +384,18 @@ __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
         a.gpart[((int64_t)a.slot * gridDim.x + lb) * NG + threadIdx.x] = red[threadIdx.x];
 }
 
+template <typename V, int TX>
+__global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
+    adj_body<V, TX>(a);
+}
+// FP32 storage: held to 128 VGPRs (four waves per SIMD), which it fits
+// without spilling
+template <typename V, int TX>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_adj_w4(AdjArgs a) {
+    adj_body<V, TX>(a);
+}
+
 // One thread per (step slot, field, accumulator): the field's workgroup sums
 // in workgroup order.
 __global__ void __launch_bounds__(kBlock) k_adj_gsum(const double* __restrict__ gpart,
@@ -438,21 +473,21 @@ __global__ void k_adj_final(const double* gfield, int32_t K, int32_t n_fields, i
     }
 }
 
+template <typename V, int TX>
+static void launch_adj_tx(const AdjArgs& a, int32_t n_blocks, hipStream_t st) {
+    if constexpr (std::is_same<V, float2>::value)
+        hipLaunchKernelGGL((k_adj_w4<V, TX>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_adj<V, TX>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+}
+
 template <typename V>
 static void launch_adj_t(int shape, const AdjArgs& a, int32_t n_blocks, hipStream_t st) {
     switch (shape) {
-        case kTile64x4:
-            hipLaunchKernelGGL((k_adj<V, 64>), dim3(n_blocks), dim3(kBlock), 0, st, a);
-            break;
-        case kTile32x8:
-            hipLaunchKernelGGL((k_adj<V, 32>), dim3(n_blocks), dim3(kBlock), 0, st, a);
-            break;
-        case kTile128x2:
-            hipLaunchKernelGGL((k_adj<V, 128>), dim3(n_blocks), dim3(kBlock), 0, st, a);
-            break;
-        default:
-            hipLaunchKernelGGL((k_adj<V, 16>), dim3(n_blocks), dim3(kBlock), 0, st, a);
-            break;
+        case kTile64x4: launch_adj_tx<V, 64>(a, n_blocks, st); break;
+        case kTile32x8: launch_adj_tx<V, 32>(a, n_blocks, st); break;
+        case kTile128x2: launch_adj_tx<V, 128>(a, n_blocks, st); break;
+        default: launch_adj_tx<V, 16>(a, n_blocks, st); break;
     }
 }
 
