@@ -190,6 +190,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
         uint32_t word;
         V g[NQ];          // g[pz] is carried, not loaded
         V own[NQ - 1];    // own[pz - 1] is carried, not loaded
+        float gv[GM ? NQ - 1 : 1];   // membrane positions of the pull links
     };
     auto issue = [&](int32_t j2, SiteLoads& L) {
         const int32_t s = j0 + st1 * j1 + st2 * j2;
@@ -208,11 +209,68 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
             const int od = (d & 1) ? d + 1 : d - 1;
             if (d != pz) L.own[d - 1] = src[pop + od * ps + sp];
         }
+        if constexpr (GM) {
+#pragma unroll
+            for (int d = 1; d < NQ; ++d) L.gv[d - 1] = gmt ? gmt[(d - 1) * ns + s] : 0.0f;
+        }
+    };
+    // General membrane links of a site (GM): which links take the general
+    // condition, and the three stencil populations of the first two of them,
+    // loaded before the next site's loads are issued so that waiting for
+    // them never waits for those (a site with more general links loads the
+    // others when it computes them).
+    struct GmPre {
+        uint32_t gen;
+        int d0, d1;
+        V st0[3], st1[3];   // ghat_ibar(x + e_i), ghat_i(x - 2 e_i), ghat_ibar(x - e_i)
+    };
+    // plane offsets of the stencil of pull link d (relative to the site)
+    auto stencil_off = [&](int d, int32_t* o) {
+        const int od = (d & 1) ? d + 1 : d - 1;
+        const int32_t sa = d <= 2 ? 1 : (NQ == 7 && d <= 4) ? st1 : zs;
+        const int32_t e = (d & 1) ? sa : -sa;
+        o[0] = od * ps + e;
+        o[1] = d * ps - 2 * e;
+        o[2] = od * ps - e;
+    };
+    auto prep = [&](int32_t j2, const SiteLoads& L, GmPre& G) {
+        G.gen = 0;
+        G.d0 = 0;
+        G.d1 = 0;
+        if constexpr (GM) {
+            const uint32_t word = L.word;
+            const int p = (int)(word & 0xfu);
+            const uint32_t mask = (word >> 4) & 0x3fu;
+#pragma unroll
+            for (int d = 1; d < NQ; ++d) {
+                if (((mask >> (d - 1)) & 1u) && L.gv[d - 1] != 0.0f) {
+                    const int pn = (int)((word >> (10 + 3 * (d - 1))) & 0x7u);
+                    if (c_tr[p * P + pn] < 1.0) G.gen |= 1u << d;
+                }
+            }
+            const int32_t sp = j0 + st1 * j1 + zs * j2;
+            if (G.gen) {
+                int32_t o[3];
+                G.d0 = __builtin_ctz(G.gen);
+                stencil_off(G.d0, o);
+                G.st0[0] = src[sp + o[0]];
+                G.st0[1] = src[sp + o[1]];
+                G.st0[2] = src[sp + o[2]];
+                const uint32_t rest = G.gen & (G.gen - 1);
+                if (rest) {
+                    G.d1 = __builtin_ctz(rest);
+                    stencil_off(G.d1, o);
+                    G.st1[0] = src[sp + o[0]];
+                    G.st1[1] = src[sp + o[1]];
+                    G.st1[2] = src[sp + o[2]];
+                }
+            }
+        }
     };
     // carried along the column: the pz pull and the direction-pz own
     // population of the next site to compute (loaded for the first site)
     V cz_g, cz_o;
-    auto compute = [&](int32_t j2, const SiteLoads& L, double2& Macc) {
+    auto compute = [&](int32_t j2, const SiteLoads& L, const GmPre& G, double2& Macc) {
         const int32_t s = j0 + st1 * j1 + st2 * j2;
         const int32_t sp = j0 + st1 * j1 + zs * j2;
         const bool fz0 = j2 == 0, fz1 = j2 == n2 - 1;
@@ -238,27 +296,17 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
             }
         }
         if (mask) {
-            // membrane positions of the pulled links (0: half-link rule)
-            float gv[NQ - 1];
-#pragma unroll
-            for (int d = 1; d < NQ; ++d)
-                gv[d - 1] = (GM && gmt && ((mask >> (d - 1)) & 1u)) ? gmt[(d - 1) * ns + s] : 0.0f;
-            // half-link membrane: g' = ghat_opp(x) + t (incoming - ghat_opp(x));
-            // links with a position are collected in gen
-            uint32_t gen = 0;
+            // half-link membrane: g' = ghat_opp(x) + t (incoming - ghat_opp(x)),
+            // except on the links that take the general condition (G.gen)
 #pragma unroll
             for (int d = 1; d < NQ; ++d) {
-                if ((mask >> (d - 1)) & 1u) {
+                if (((mask >> (d - 1)) & 1u) && !((G.gen >> d) & 1u)) {
                     const int pn = (int)((word >> (10 + 3 * (d - 1))) & 0x7u);
                     const double t = c_tr[p * P + pn];
                     if (t < 1.0) {
-                        if (GM && gv[d - 1] != 0.0f) {
-                            gen |= 1u << d;
-                        } else {
-                            const double2 o = ld2(&own[d - 1]);
-                            g[d].x = o.x + t * (g[d].x - o.x);
-                            g[d].y = o.y + t * (g[d].y - o.y);
-                        }
+                        const double2 o = ld2(&own[d - 1]);
+                        g[d].x = o.x + t * (g[d].x - o.x);
+                        g[d].y = o.y + t * (g[d].y - o.y);
                     }
                 }
             }
@@ -266,13 +314,14 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 // general condition, one link at a time (rolled: the code
                 // exists once); the stencil x - 2e_d .. x + e_d lies inside
                 // the field (checked on the host)
+                uint32_t gen = G.gen;
                 while (gen) {
                     const int d = __builtin_ctz(gen);
                     gen &= gen - 1;
                     // own[k-1] holds ghat_{opp(k)}(x): both populations of x
                     // on the link's axis are already loaded
                     double2 b1 = g[1], o = ld2(&own[0]), a3 = ld2(&own[1]);
-                    float v = gv[0];
+                    float v = L.gv[0];
 #pragma unroll
                     for (int k = 2; k < NQ; ++k)
                         if (d == k) {
@@ -280,17 +329,27 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                             b1 = g[k];
                             o = ld2(&own[k - 1]);
                             a3 = ld2(&own[ok - 1]);
-                            v = gv[k - 1];
+                            v = L.gv[k - 1];
                         }
                     const int pn = (int)((word >> (10 + 3 * (d - 1))) & 0x7u);
                     const double dd = v > 0.0f ? (double)v : 1.0 + (double)v;
                     const MembCoef c = membrane_coefficients(dd, c_kdt[p * P + pn], a.edx);
-                    const int od = (d & 1) ? d + 1 : d - 1;
-                    const int32_t sa = d <= 2 ? 1 : (NQ == 7 && d <= 4) ? st1 : zs;
-                    const int32_t e = (d & 1) ? sa : -sa;
-                    const double2 a2 = ld2(src + od * ps + sp + e);
-                    const double2 b2 = ld2(src + d * ps + sp - 2 * e);
-                    const double2 b3 = ld2(src + od * ps + sp - e);
+                    double2 a2, b2, b3;
+                    if (d == G.d0) {
+                        a2 = ld2(&G.st0[0]);
+                        b2 = ld2(&G.st0[1]);
+                        b3 = ld2(&G.st0[2]);
+                    } else if (d == G.d1) {
+                        a2 = ld2(&G.st1[0]);
+                        b2 = ld2(&G.st1[1]);
+                        b3 = ld2(&G.st1[2]);
+                    } else {
+                        int32_t o3[3];
+                        stencil_off(d, o3);
+                        a2 = ld2(src + sp + o3[0]);
+                        b2 = ld2(src + sp + o3[1]);
+                        b3 = ld2(src + sp + o3[2]);
+                    }
                     double2 r;
                     r.x = c.A[0] * o.x + c.A[1] * a2.x + c.A[2] * a3.x
                         + c.B[0] * b1.x + c.B[1] * b2.x + c.B[2] * b3.x;
@@ -350,16 +409,22 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
             cz_o = src[pop + (pz + 1) * ps + sp];
         }
         SiteLoads A, B;
+        GmPre G;
         issue(z0, A);
         int32_t j2 = z0;
         // two sites per trip so that A and B swap roles without copies
         for (; j2 + 1 < z1; j2 += 2) {
+            prep(j2, A, G);
             issue(j2 + 1, B);
-            compute(j2, A, Mv);
+            compute(j2, A, G, Mv);
+            prep(j2 + 1, B, G);
             if (j2 + 2 < z1) issue(j2 + 2, A);
-            compute(j2 + 1, B, Mv);
+            compute(j2 + 1, B, G, Mv);
         }
-        if (j2 < z1) compute(j2, A, Mv);
+        if (j2 < z1) {
+            prep(j2, A, G);
+            compute(j2, A, G, Mv);
+        }
     }
 
     if (fd.q < 0) return;   // image fields do not enter the signal
