@@ -90,7 +90,15 @@ struct MembCoef {
 };
 __device__ __forceinline__ MembCoef membrane_coefficients(double d, double kdt, double edx) {
     const double e = 1.0 - d;
-    const double ro = 1.0 / (2.0 * d + 1.0), rf = 1.0 / (2.0 * e + 1.0);
+    // one division for the three reciprocals ro = 1/(2d + 1), rf = 1/(2e + 1)
+    // and rF below: with Do = 3 - 2d, Df = 3 - 2e the denominator of rF is
+    // ro rf Qd, Qd = Do Df edx + 2 (Do + Df) kdt
+    const double Ao = 2.0 * d + 1.0, Af = 2.0 * e + 1.0;
+    const double Do = 3.0 - 2.0 * d, Df = 3.0 - 2.0 * e;
+    const double Qd = Do * Df * edx + 2.0 * (Do + Df) * kdt;
+    const double AA = Ao * Af;
+    const double R = 1.0 / (AA * Qd);
+    const double ro = Af * Qd * R, rf = Ao * Qd * R;
     const double ho = 2.0 * d - 1.0, hf = 2.0 * e - 1.0;
     // own side
     const double n2 = -ho * ro, n3 = ho * ro, n4 = 2.0 * ro;
@@ -100,7 +108,7 @@ __device__ __forceinline__ MembCoef membrane_coefficients(double d, double kdt, 
     const double fd1 = 2.0 * e - 2.0, fd2 = -hf * hf * rf, fd3 = 2.0 * hf * rf, fd4 = (3.0 - 2.0 * e) * rf;
     const double diff = d4 * fd4 * edx;
     const double perm_own = fd4 * n4 * kdt, perm_far = fn4 * d4 * kdt;
-    const double rF = 1.0 / (diff + (d4 * fn4 + n4 * fd4) * kdt);
+    const double rF = AA * AA * R;   // 1 / (diff + (d4 fn4 + n4 fd4) kdt)
     MembCoef c;
     c.A[0] = (diff + perm_own * d1 + perm_far) * rF;
     c.A[1] = (diff * n2 + perm_own * d2 + perm_far * n2) * rF;
