@@ -1008,7 +1008,8 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
 extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void* stream) {
     if (!s) return BTL_E_INVAL;
     // fixed launch shape for measurements: BTLBM_TILE (0..4), BTLBM_ZC,
-    // BTLBM_XCD (0 plain, 1 XCD-contiguous workgroup order)
+    // BTLBM_XCD (0 plain, 1 XCD-contiguous workgroup order); BTLBM_VERBOSE
+    // prints the choice
     const char* et = getenv("BTLBM_TILE");
     const char* ez = getenv("BTLBM_ZC");
     const char* ex = getenv("BTLBM_XCD");
@@ -1115,6 +1116,9 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
     s->tile_shape = best_shape;
     s->zc = best_zc;
     s->xcd = best_xcd;
+    if (getenv("BTLBM_VERBOSE"))
+        fprintf(stderr, "btlbm autotune: tile shape %d, z-column %d, xcd order %d (%.3f ms per probe)\n",
+                best_shape, best_zc, best_xcd, best);
     return BTL_OK;
 }
 
