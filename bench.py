@@ -261,7 +261,7 @@ def main():
     time_forward(sim, cfg, max(W, 1), bpf)
     if not args.no_autotune:
         # launch shape chosen by timed probes of this workload (setup, untimed)
-        probe = 20 if fs < 5e7 else 2
+        probe = max(2, min(40, int(1.5e9 / fs)))   # about 1.5e9 field-site updates per candidate
         log(f"autotune ({probe} steps per candidate)")
         btl.btl_autotune(sim._h, Q, probe, torch.cuda.current_stream().cuda_stream)
     if W > 0:
