@@ -84,6 +84,10 @@ struct btl_sim {
     DevBuf<double2> tab;         // [kTabSteps][T] per-step phase tables
     DevBuf<int32_t> tab_field;   // [T]
     std::vector<FieldDesc> h_fields;
+    // launch geometry of the adjoint steps (the forward's tile shape with
+    // its own z-column length)
+    DevBuf<FieldDesc> adj_fields;
+    DevBuf<int32_t> adj_blk;
     // pinned staging for the per-call tables, two slots so that a call can
     // be prepared while the previous one's uploads are still queued
     char* stage[2] = {nullptr, nullptr};
@@ -112,6 +116,7 @@ struct btl_sim {
     struct Tape {
         bool valid = false;
         int32_t K = 0, C = 0, Q = 0, T = 0, n_fields = 0, nblk = 0, shape = 0, sub = 1, xcd = 0;
+        int32_t nblk_adj = 0;      // workgroups of one adjoint step (adj_fields)
         double dt = 0;
         int64_t state_elems = 0;   // V elements of one full state (all fields)
     } tape;
@@ -619,6 +624,48 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     std::vector<int32_t> blk(nblk_total);
     for (int i = 0; i < n_fields; ++i)
         for (int b = 0; b < fl[i].nblk; ++b) blk[fl[i].blk0 + b] = i;
+    // With a tape, the launch geometry of the adjoint steps: the same tile
+    // shape, whole z columns when all workgroups are resident at once,
+    // otherwise columns cut so that the grid runs in about eight rounds
+    // (BTLBM_ADJ_ZC sets the length).  The adjoint carries four values along
+    // the column and loads in two phases per site; on the benchmark workload
+    // it measured faster on whole columns than on the short chunks the
+    // forward step often prefers, but a grid slightly larger than one round
+    // of resident workgroups leaves most of the chip idle in its second.
+    const bool taping = ckpt_every > 0 && K > 0;
+    std::vector<FieldDesc> afl;
+    std::vector<int32_t> ablk;
+    int32_t nblk_adj = 0;
+    if (taping) {
+        const char* ez = getenv("BTLBM_ADJ_ZC");
+        int zc_adj = ez ? std::max(0, atoi(ez)) : 0;
+        if (!ez) {
+            // resident workgroups: 1024 SIMDs x (4 waves FP32, 2 FP64) / 4 waves each
+            const int64_t cap = s->prec == BTL_F32 ? 1024 : 512;
+            int64_t whole = 0;
+            int32_t nz = 1;
+            for (const FieldDesc& d : fl) {
+                whole += (int64_t)d.tiles[0] * d.tiles[1];
+                nz = std::max(nz, d.n[2]);
+            }
+            if (whole > cap) {
+                const int64_t split = (8 * cap + whole - 1) / whole;
+                zc_adj = std::max<int>(8, (int)((nz + split - 1) / split));
+            }
+        }
+        afl = fl;
+        for (FieldDesc& d : afl) {
+            const int32_t zc = zc_adj > 0 ? std::min(zc_adj, d.n[2]) : d.n[2];
+            d.zc = zc;
+            d.tiles[2] = (d.n[2] + zc - 1) / zc;
+            d.nblk = d.tiles[0] * d.tiles[1] * d.tiles[2];
+            d.blk0 = nblk_adj;
+            nblk_adj += d.nblk;
+        }
+        ablk.resize(nblk_adj);
+        for (int i = 0; i < n_fields; ++i)
+            for (int b = 0; b < afl[i].nblk; ++b) ablk[afl[i].blk0 + b] = i;
+    }
 
     const size_t esz = s->prec == BTL_F32 ? sizeof(float2) : sizeof(double2);
     hipError_t e;
@@ -631,7 +678,9 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         (e = s->consts.ensure(consts.size())) != hipSuccess ||
         (e = s->partial.ensure((size_t)kTabSteps * nblk_total * (kBlock / 64))) != hipSuccess ||
         (e = s->tab.ensure((size_t)kTabSteps * T)) != hipSuccess ||
-        (e = s->tab_field.ensure(T)) != hipSuccess)
+        (e = s->tab_field.ensure(T)) != hipSuccess ||
+        (taping && ((e = s->adj_fields.ensure(n_fields)) != hipSuccess ||
+                    (e = s->adj_blk.ensure(nblk_adj)) != hipSuccess)))
         return hip_fail(s, e, "allocating tables");
     // stage all tables in pinned memory and upload asynchronously
     const size_t b_fields = (size_t)n_fields * sizeof(FieldDesc);
@@ -642,7 +691,9 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t o_blk = al(b_fields), o_steps = o_blk + al(b_blk), o_consts = o_steps + al(b_steps);
     const size_t o_tabf = o_consts + al(b_consts);
-    const size_t total = o_tabf + al(b_tabf);
+    const size_t b_afl = taping ? b_fields : 0, b_ablk = (size_t)nblk_adj * sizeof(int32_t);
+    const size_t o_afl = o_tabf + al(b_tabf), o_ablk = o_afl + al(b_afl);
+    const size_t total = o_ablk + al(b_ablk);
     const int slot = s->stage_slot;
     if (!s->stage_ev[slot] && (e = hipEventCreateWithFlags(&s->stage_ev[slot], hipEventDisableTiming)) != hipSuccess)
         return hip_fail(s, e, "creating event");
@@ -662,11 +713,18 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     memcpy(stg + o_steps, steps.data(), b_steps);
     memcpy(stg + o_consts, consts.data(), b_consts);
     memcpy(stg + o_tabf, tabf.data(), b_tabf);
+    if (taping) {
+        memcpy(stg + o_afl, afl.data(), b_afl);
+        memcpy(stg + o_ablk, ablk.data(), b_ablk);
+    }
     if ((e = hipMemcpyAsync(s->fields.p, stg, b_fields, hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = hipMemcpyAsync(s->blk_field.p, stg + o_blk, b_blk, hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = hipMemcpyAsync(s->steps.p, stg + o_steps, b_steps, hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = hipMemcpyAsync(s->consts.p, stg + o_consts, b_consts, hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = hipMemcpyAsync(s->tab_field.p, stg + o_tabf, b_tabf, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (taping &&
+         ((e = hipMemcpyAsync(s->adj_fields.p, stg + o_afl, b_afl, hipMemcpyHostToDevice, st)) != hipSuccess ||
+          (e = hipMemcpyAsync(s->adj_blk.p, stg + o_ablk, b_ablk, hipMemcpyHostToDevice, st)) != hipSuccess)) ||
         (e = hipEventRecord(s->stage_ev[slot], st)) != hipSuccess)
         return hip_fail(s, e, "uploading tables");
     s->stage_used[slot] = true;
@@ -695,6 +753,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         s->tape.T = T;
         s->tape.n_fields = n_fields;
         s->tape.nblk = nblk_total;
+        s->tape.nblk_adj = nblk_adj;
         s->tape.shape = shape;
         s->tape.dt = dt;
         s->tape.sub = msub;
@@ -915,11 +974,12 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
     const size_t esz = s->prec == BTL_F32 ? sizeof(float2) : sizeof(double2);
     const size_t state_bytes = (size_t)tp.state_elems * esz;
     hipError_t e;
+    const int32_t nblk_adj = tp.nblk_adj;
     if ((e = s->seg.ensure((size_t)C * state_bytes)) != hipSuccess ||
         (e = s->lam[0].ensure(state_bytes)) != hipSuccess ||
         (e = s->lam[1].ensure(state_bytes)) != hipSuccess ||
         (e = s->tab_b.ensure((size_t)(C + 1) * T)) != hipSuccess ||
-        (e = s->gpart.ensure((size_t)C * tp.nblk * NG)) != hipSuccess ||
+        (e = s->gpart.ensure((size_t)C * nblk_adj * NG)) != hipSuccess ||
         (e = s->gfield.ensure((size_t)K * nf * NG)) != hipSuccess)
         return hip_fail(s, e, "allocating adjoint buffers");
 
@@ -944,15 +1004,15 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
     AdjArgs aa;
     memset(&aa, 0, sizeof(aa));
     aa.words = s->words.p;
-    aa.fields = s->fields.p;
-    aa.blk_field = s->blk_field.p;
+    aa.fields = s->adj_fields.p;
+    aa.blk_field = s->adj_blk.p;
     aa.w = s->consts.p;
     aa.decay = s->consts.p + P;
     aa.trans = s->consts.p + 2 * P;
     aa.dLdE = reinterpret_cast<const double2*>(dL_dE);
     aa.gpart = s->gpart.p;
     aa.dt = tp.dt;
-    aa.xcd = tp.xcd;
+    aa.xcd = nblk_adj > kXcdMinBlocks ? 1 : 0;
     aa.n_fields = nf;
     aa.n_phase = P;
     aa.K = K;
@@ -989,12 +1049,12 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
             aa.tab_prev = s->tab_b.p + (size_t)(k - 1 - k0) * T;
             aa.tab_cur = aa.top ? aa.tab_prev : s->tab_b.p + (size_t)(k - k0) * T;
             aa.slot = k - 1 - k0;
-            if ((e = launch_adj(s->prec, tp.shape, aa, tp.nblk, st)) != hipSuccess)
+            if ((e = launch_adj(s->prec, tp.shape, aa, nblk_adj, st)) != hipSuccess)
                 return hip_fail(s, e, "adjoint launch");
             lam_cur ^= 1;
         }
         // per-step, per-field sums of this segment: gfield[k0 .. k1 - 1]
-        if ((e = launch_adj_gsum(s->gpart.p, s->fields.p, nf, tp.nblk, NG, k0, k1 - k0,
+        if ((e = launch_adj_gsum(s->gpart.p, s->adj_fields.p, nf, nblk_adj, NG, k0, k1 - k0,
                                  s->gfield.p, st)) != hipSuccess)
             return hip_fail(s, e, "adjoint sum launch");
     }
@@ -1152,6 +1212,8 @@ extern "C" void btl_destroy(btl_sim* s) {
     s->pop[1].release();
     s->fields.release();
     s->blk_field.release();
+    s->adj_fields.release();
+    s->adj_blk.release();
     s->steps.release();
     s->consts.release();
     s->partial.release();
