@@ -146,6 +146,25 @@ def test_checkpoint_interval_does_not_change_gradients():
         assert np.allclose(x, y, rtol=1e-12, atol=1e-15)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adjoint_launch_geometry_does_not_change_gradients(prec, monkeypatch):
+    # the adjoint steps may walk whole z columns or short chunks (chosen
+    # when the tape is recorded; BTLBM_ADJ_ZC fixes the length): the
+    # gradients agree to rounding order, and with the mirror faces the
+    # chunks cross the image-field partners' face rows
+    cfg = _cfg_small([1, 1, 1], seed=57, K=70, n=(14, 12, 11))
+    Q, K = len(cfg["gG0"]), len(cfg["f"])
+    a, b = _loss_weights(Q, K, seed=5)
+    ref = _gpu_grads(cfg, prec, a, b, ckpt=20)
+    tol = 1e-12 if prec == "f64" else 1e-6
+    for zc in ("1", "3", "4"):
+        monkeypatch.setenv("BTLBM_ADJ_ZC", zc)
+        got = _gpu_grads(cfg, prec, a, b, ckpt=20)
+        for x, y in zip(ref, got):
+            scale = max(np.max(np.abs(x)), 1e-30)
+            assert np.max(np.abs(x - y)) <= tol * scale, (zc, x, y)
+
+
 def test_autograd_function():
     btl, torch = _gpu()
     cfg = _cfg_small([0, 0, 0], seed=54, K=80)
