@@ -102,8 +102,9 @@ typedef struct {
 
 /* Create a simulator for n_geom geometries (all with the same dx and
  * n_phase; sizes may differ: q-samples of all geometries run in one batch).
- * prec selects FP64 or FP32 population storage; arithmetic inside a step is
- * FP64 in both, and the signal sums are FP64.  On success *out owns all
+ * prec selects FP64 or FP32 population storage; the arithmetic of a forward
+ * step is FP64 in both (the FP32 adjoint step computes per site in FP32),
+ * and every sum (signal, gradients) is FP64.  On success *out owns all
  * device memory of the simulator; free it with btl_destroy.
  * Errors: BTL_E_INVAL (bad geometry), BTL_E_NOMEM, BTL_E_HIP. */
 btl_status btl_create(const btl_geom *geoms, int32_t n_geom, int32_t prec,
@@ -138,13 +139,19 @@ btl_status btl_forward(btl_sim *s, double dt, int32_t K, const double *D,
  * btl_forward that kept a tape (ckpt_every > 0).  dL_dE is device
  * [Q][K+1][2] with dL/dE = dL/dRe E + i dL/dIm E.  Outputs are device
  * doubles, overwritten (NULL = not wanted): dD [P], dT2 [P], dkappa [P*P],
- * df [K] (or [K*m] with m reaction sub-steps: dL per waveform sample).
+ * df [K] (or [K*m] with m reaction sub-steps: dL per waveform sample),
+ * dgG0 [Q][3] (dL/d(gamma G0) of each q-sample: through the reaction phase
+ * gamma G.x and the face phase factors of Eqs. periodic_phi, collision_BC
+ * and the mirror rule; asking for it runs a variant of the adjoint step with
+ * ten more accumulators per workgroup).
  * dkappa is the gradient per matrix entry: for a != b the entries
  * [a][b] and [b][a] each hold half of dL/dkappa_ab, so that a symmetric
  * parametrization (both entries set from one value) gets the full value.
- * Errors: BTL_E_INVAL (no tape), BTL_E_NOMEM, BTL_E_HIP. */
+ * Errors: BTL_E_INVAL (no tape), BTL_E_UNSUPPORTED (dgG0 asked of a tape
+ * whose field set is not the full one: see btl_set_grad_gG0), BTL_E_NOMEM,
+ * BTL_E_HIP. */
 btl_status btl_backward(btl_sim *s, const double *dL_dE, double *dD, double *dT2,
-                        double *dkappa, double *df, void *stream);
+                        double *dkappa, double *df, double *dgG0, void *stream);
 
 /* Select the lattice of later btl_forward calls.  BTL_D3Q7 (default):
  * eps_D = 1/4, w_0 = 1/4, w_i = 1/8.  BTL_D2Q5: the two-dimensional lattice
@@ -165,6 +172,18 @@ btl_status btl_set_lattice(btl_sim *s, int32_t lattice);
  * default (dt' = dt).  Hybrid scheme only: a classical forward with m > 1
  * returns BTL_E_UNSUPPORTED.  Errors: BTL_E_INVAL (m outside 1..65536). */
 btl_status btl_set_substeps(btl_sim *s, int32_t m);
+
+/* Plan the fields of later taped btl_forward calls (ckpt_every > 0) so that
+ * btl_backward can return dgG0 for every q-sample: every mirrored axis gets
+ * its reflected image fields even where the q-sample has no gradient
+ * component along it, and the conjugate pairing is kept only when all three
+ * axes are mirrored (Sec. 2.4.4's mirror rule is exact for any G only with
+ * the image fields a non-zero component would need).  Costs up to 2^3 fields
+ * per q-sample instead of 1-4; on = 0 (default) plans the minimal set, with
+ * which btl_backward returns dgG0 only where that set is already the full
+ * one.  The signal is the same either way (the extra fields are exact
+ * copies).  Errors: BTL_E_INVAL (on not 0 or 1). */
+btl_status btl_set_grad_gG0(btl_sim *s, int32_t on);
 
 /* Select the scheme of later btl_forward calls.  BTL_HYBRID (default) is
  * the paper's split scheme (Sec. 2.3).  BTL_CLASSICAL is the classical LBM

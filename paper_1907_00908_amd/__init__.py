@@ -3,7 +3,7 @@
 Argument marshalling only: every step of the computation runs in the HIP
 kernels of libbtlbm.so.  The functions `btl_create`, `btl_forward`,
 `btl_backward`, `btl_set_scheme`, `btl_set_lattice`, `btl_set_substeps`,
-`btl_autotune`, `btl_destroy` and `btl_last_error` mirror the
+`btl_set_grad_gG0`, `btl_autotune`, `btl_destroy` and `btl_last_error` mirror the
 C ABI of include/btlbm.h one to one.  `Simulator` wraps them with torch
 tensors for device memory and the current torch stream.
 
@@ -28,8 +28,8 @@ BTL_HYBRID, BTL_CLASSICAL = 0, 1
 BTL_D3Q7, BTL_D2Q5 = 0, 1
 
 EXPORTED = ("btl_create", "btl_forward", "btl_backward", "btl_set_scheme",
-            "btl_set_lattice", "btl_set_substeps", "btl_autotune", "btl_destroy",
-            "btl_last_error")
+            "btl_set_lattice", "btl_set_substeps", "btl_set_grad_gG0", "btl_autotune",
+            "btl_destroy", "btl_last_error")
 
 
 class BtlError(RuntimeError):
@@ -66,7 +66,7 @@ def load_library(path: str = None):
     lib.btl_create.restype = ctypes.c_int
     lib.btl_forward.argtypes = [P, d, i32, P, P, P, i32, P, P, P, P, P, i32, P]
     lib.btl_forward.restype = ctypes.c_int
-    lib.btl_backward.argtypes = [P, P, P, P, P, P, P]
+    lib.btl_backward.argtypes = [P, P, P, P, P, P, P, P]
     lib.btl_backward.restype = ctypes.c_int
     lib.btl_set_scheme.argtypes = [P, i32]
     lib.btl_set_scheme.restype = ctypes.c_int
@@ -74,6 +74,8 @@ def load_library(path: str = None):
     lib.btl_set_lattice.restype = ctypes.c_int
     lib.btl_set_substeps.argtypes = [P, i32]
     lib.btl_set_substeps.restype = ctypes.c_int
+    lib.btl_set_grad_gG0.argtypes = [P, i32]
+    lib.btl_set_grad_gG0.restype = ctypes.c_int
     lib.btl_autotune.argtypes = [P, i32, i32, P]
     lib.btl_autotune.restype = ctypes.c_int
     lib.btl_destroy.argtypes = [P]
@@ -147,11 +149,11 @@ def btl_forward(h, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E_ptr, M_ptr,
     _check(st, h)
 
 
-def btl_backward(h, dLdE_ptr, dD_ptr, dT2_ptr, dkappa_ptr, df_ptr, stream_ptr):
+def btl_backward(h, dLdE_ptr, dD_ptr, dT2_ptr, dkappa_ptr, df_ptr, dgG0_ptr, stream_ptr):
     lib = load_library()
     V = lambda p: ctypes.c_void_p(p) if p else None  # noqa: E731
     _check(lib.btl_backward(h, V(dLdE_ptr), V(dD_ptr), V(dT2_ptr), V(dkappa_ptr),
-                            V(df_ptr), V(stream_ptr)), h)
+                            V(df_ptr), V(dgG0_ptr), V(stream_ptr)), h)
 
 
 def btl_set_scheme(h, scheme):
@@ -164,6 +166,10 @@ def btl_set_lattice(h, lattice):
 
 def btl_set_substeps(h, m):
     _check(load_library().btl_set_substeps(h, int(m)), h)
+
+
+def btl_set_grad_gG0(h, on):
+    _check(load_library().btl_set_grad_gG0(h, int(on)), h)
 
 
 def btl_autotune(h, Q, K_probe, stream_ptr):
@@ -196,7 +202,7 @@ class Simulator:
     """Owns one btl_sim.  Device memory for E and M_final comes from torch."""
 
     def __init__(self, geoms, bc, prec: str = "f32", scheme: int = BTL_HYBRID,
-                 substeps: int = 1, lattice: int = BTL_D3Q7):
+                 substeps: int = 1, lattice: int = BTL_D3Q7, grad_gG0: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Simulator needs a HIP device")
@@ -212,6 +218,15 @@ class Simulator:
         self.substeps = int(substeps)
         if self.substeps != 1:
             btl_set_substeps(self._h, self.substeps)
+        self.grad_gG0 = bool(grad_gG0)
+        if self.grad_gG0:
+            btl_set_grad_gG0(self._h, 1)
+
+    def set_grad_gG0(self, on: bool):
+        """Plan taped forwards for the gamma G0 gradient (btl_set_grad_gG0)."""
+        if bool(on) != self.grad_gG0:
+            btl_set_grad_gG0(self._h, 1 if on else 0)
+            self.grad_gG0 = bool(on)
 
     def close(self):
         if self._h is not None:
@@ -257,12 +272,12 @@ class Simulator:
         return Ec, Ms
 
 
-    def backward(self, dLdE, P: int, K: int):
+    def backward(self, dLdE, P: int, K: int, grad_gG0: bool = False):
         """Gradients of a real loss from dL/dE (torch (Q, K+1, 2) float64 on
         the device: dL/dRe E, dL/dIm E) for the last forward that kept a tape.
         K is the number of steps of that forward.  Returns device tensors
         dD [P], dT2 [P], dkappa [P, P], df [K * substeps] (one entry per
-        waveform sample)."""
+        waveform sample), and with grad_gG0 also dgG0 [Q, 3]."""
         torch = self.torch
         dev = dLdE.device
         g = dLdE.detach().to(torch.float64).contiguous()
@@ -271,9 +286,12 @@ class Simulator:
         dk = torch.empty((P, P), dtype=torch.float64, device=dev)
         nf = K * self.substeps
         df = torch.empty(max(nf, 1), dtype=torch.float64, device=dev)
+        dG = torch.empty((g.shape[0], 3), dtype=torch.float64, device=dev) if grad_gG0 else None
         stream = torch.cuda.current_stream().cuda_stream
         btl_backward(self._h, g.data_ptr(), dD.data_ptr(), dT2.data_ptr(), dk.data_ptr(),
-                     df.data_ptr(), stream)
+                     df.data_ptr(), dG.data_ptr() if grad_gG0 else None, stream)
+        if grad_gG0:
+            return dD, dT2, dk, df[:nf], dG
         return dD, dT2, dk, df[:nf]
 
 
@@ -286,7 +304,8 @@ def _bt_function():
 
         forward(D [P], T2 [P], kappa [P, P], f [K], sim, dt, gG0 [Q, 3],
         q_geom [Q], ckpt_every).  The parameters may live on any device; the
-        returned gradients are placed on the parameter's device."""
+        returned gradients are placed on the parameter's device.  gG0 may be
+        a tensor: it gets a gradient when it requires one."""
 
         @staticmethod
         def forward(ctx, D, T2, kappa, f, sim, dt, gG0, q_geom, ckpt_every):
@@ -294,6 +313,14 @@ def _bt_function():
             T2n = T2.detach().cpu().double().numpy()
             kn = kappa.detach().cpu().double().numpy()
             fn = f.detach().cpu().double().numpy()
+            if torch.is_tensor(gG0):
+                ctx.gdev = gG0.device
+                if gG0.requires_grad:
+                    sim.set_grad_gG0(True)
+                gG0 = gG0.detach().cpu().double().numpy()
+            else:
+                ctx.gdev = None
+            gG0 = np.ascontiguousarray(gG0, np.float64).reshape(-1, 3)
             E = sim.forward(dt, Dn, T2n, kn, fn, gG0, q_geom, ckpt_every=max(1, int(ckpt_every)))
             ctx.sim = sim
             ctx.P = len(Dn)
@@ -303,10 +330,13 @@ def _bt_function():
 
         @staticmethod
         def backward(ctx, gE):
-            dD, dT2, dk, df = ctx.sim.backward(gE, ctx.P, ctx.K)
+            want_g = ctx.gdev is not None and ctx.needs_input_grad[6]
+            out = ctx.sim.backward(gE, ctx.P, ctx.K, grad_gG0=want_g)
+            dD, dT2, dk, df = out[:4]
+            dG = out[4].to(ctx.gdev) if want_g else None
             d0, d1, d2, d3 = ctx.devs
             return (dD.to(d0), dT2.to(d1), dk.to(d2), df.to(d3),
-                    None, None, None, None, None)
+                    None, None, dG, None, None)
 
     return BlochTorreySignal
 
@@ -319,7 +349,9 @@ def bloch_torrey_signal(D, T2, kappa, f, sim, dt, gG0, q_geom=None, ckpt_every=1
     global _BTS
     if _BTS is None:
         _BTS = _bt_function()
-    gG0 = np.ascontiguousarray(gG0, np.float64).reshape(-1, 3)
+    import torch
+    if not torch.is_tensor(gG0):
+        gG0 = np.ascontiguousarray(gG0, np.float64).reshape(-1, 3)
     if q_geom is None:
         q_geom = np.zeros(len(gG0), np.int32)
     return _BTS.apply(D, T2, kappa, f, sim, dt, gG0, q_geom, ckpt_every)

@@ -24,6 +24,12 @@
 //   d/dt_pair   sum Re conj(Lambda_i) (pulled - own)         membrane links
 //   d/df_{k-1}  sum dt (c.j + cu) Im( conj(nu_i) g_i )      reaction phase
 //   d/dF_{k-1}  sum -beta t Im( conj(Lambda_i) pulled )      face factors
+// and, when asked for (GG), what the gamma G0 gradient needs: the reaction
+// angle is -fdt (c.j + cu) with c_b = s_b G_b dx and cu = -dx sum_b sigma_b
+// G_b, so per step R_b = sum j_b Im(conj(nu_i) g_i) (b = x, y, z) and
+// R_0 = sum Im(conj(nu_i) g_i); every face factor is exp(i beta_f F) with
+// beta_f linear in G, so per step and face X_f = sum -t Im(conj(Lambda_i)
+// pulled).  k_adj_final combines them with d beta_f / d G_b.
 // Per-phase sums are kept in registers (selected by the node's phase), the
 // membrane-pair sums in one LDS row per thread; workgroup and field sums are
 // formed in a fixed order, so the gradients are bitwise reproducible.
@@ -60,7 +66,7 @@ __device__ __forceinline__ void store_stream(double2* p, double2 v) {
     __builtin_nontemporal_store(v.y, &p->y);
 }
 
-template <typename V, int TX>
+template <typename V, int TX, bool GG>
 __device__ __forceinline__ void adj_body(const AdjArgs& a) {
     using R = typename AdjReal<V>::R;
     constexpr int TY = kBlock / TX;
@@ -75,6 +81,7 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
     const int P = a.n_phase;
     const int NG = a.ng;
     const int IW = 0, IDEC = P, IT = 2 * P, IF = 2 * P + P * P, IFF = IF + 1;
+    const int IR = IFF + 1, IX = IR + 4;   // GG only
     {
         const int t = threadIdx.x;
         if (t < P) {
@@ -144,6 +151,7 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
     double sw[kAdjMaxPhase] = {0.0, 0.0, 0.0, 0.0};
     double sdec[kAdjMaxPhase] = {0.0, 0.0, 0.0, 0.0};
     double sf = 0.0, sF = 0.0;
+    double sR[GG ? 4 : 1] = {0.0}, sX[GG ? 6 : 1] = {0.0};
 
     if (j0 < n0 && j1 < n1 && z0 < z1) {
         const double2 exyd = cmul(tabp[j0], tabp[n0 + j1]);
@@ -332,7 +340,10 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
                 const V lo2 = cmulr(cc, nu);
                 store_stream(out + pop + d * ps + sp, lo2);
                 if (tl < 1) my[p * P + nbphase(d)] += (double)(lo2.x * dv.x + lo2.y * dv.y);
-                if (face) sF += (double)(-beta[f] * tl * (lo2.x * vv.y - lo2.y * vv.x));
+                if (face) {
+                    sF += (double)(-beta[f] * tl * (lo2.x * vv.y - lo2.y * vv.x));
+                    if constexpr (GG) sX[f] += (double)(-tl * (lo2.x * vv.y - lo2.y * vv.x));
+                }
             }
             // collision: sum_d Re conj(lhat_d) (w_d M - g_d)
             const double gw = (double)(sl.x * M.x + sl.y * M.y - glg);
@@ -343,6 +354,12 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
                 sdec[i] += (p == i) ? gd : 0.0;
             }
             sf += dt * (cx0 * j0 + cx1 * j1 + cx2 * j2 + cu) * (double)gim;
+            if constexpr (GG) {
+                sR[0] += (double)j0 * (double)gim;
+                sR[1] += (double)j1 * (double)gim;
+                sR[2] += (double)j2 * (double)gim;
+                sR[3] += (double)gim;
+            }
         }
     }
 
@@ -353,7 +370,7 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
     __syncthreads();
     // register sums: wave reduction, then the four waves in order
     {
-        double v[2 * kAdjMaxPhase + 2];
+        double v[2 * kAdjMaxPhase + 2 + (GG ? kNGGrad : 0)];
 #pragma unroll
         for (int i = 0; i < kAdjMaxPhase; ++i) {
             v[i] = wave_sum(sw[i]);
@@ -361,6 +378,12 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
         }
         v[2 * kAdjMaxPhase] = wave_sum(sf);
         v[2 * kAdjMaxPhase + 1] = wave_sum(sF);
+        if constexpr (GG) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[2 * kAdjMaxPhase + 2 + i] = wave_sum(sR[i]);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) v[2 * kAdjMaxPhase + 6 + i] = wave_sum(sX[i]);
+        }
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         for (int wave = 0; wave < kBlock / 64; ++wave) {
             if (wv == wave && lane == 0) {
@@ -370,6 +393,8 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
                 }
                 red[IF] += v[2 * kAdjMaxPhase];
                 red[IFF] += v[2 * kAdjMaxPhase + 1];
+                if constexpr (GG)
+                    for (int i = 0; i < kNGGrad; ++i) red[IR + i] += v[2 * kAdjMaxPhase + 2 + i];
             }
             __syncthreads();
         }
@@ -384,16 +409,16 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
         a.gpart[((int64_t)a.slot * gridDim.x + lb) * NG + threadIdx.x] = red[threadIdx.x];
 }
 
-template <typename V, int TX>
+template <typename V, int TX, bool GG>
 __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
-    adj_body<V, TX>(a);
+    adj_body<V, TX, GG>(a);
 }
 // FP32 storage: held to 128 VGPRs (four waves per SIMD), which it fits
 // without spilling
-template <typename V, int TX>
+template <typename V, int TX, bool GG>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_adj_w4(AdjArgs a) {
-    adj_body<V, TX>(a);
+    adj_body<V, TX, GG>(a);
 }
 
 // One thread per (step slot, field, accumulator): the field's workgroup sums
@@ -427,8 +452,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_gsum(const double* __restrict__ 
 __global__ void k_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P,
                             double dt, double dx, const double* w, const double* T2,
                             const double* kappa, double* dD, double* dT2, double* dkappa,
-                            double* df, int32_t sub) {
-    const int NG = 2 * P + P * P + 2;
+                            double* df, int32_t sub, int32_t NG, const double* gmeta,
+                            const double* fdt, const double* Fk, int32_t Q, double* dgG0) {
     const int t = threadIdx.x;
     auto total = [&](int g) {
         double s = 0.0;
@@ -471,14 +496,39 @@ __global__ void k_adj_final(const double* gfield, int32_t K, int32_t n_fields, i
             suffix += gF;
         }
     }
+    // dL/d(gamma G0)_b of q-sample q, summed over its fields and the steps:
+    //   fdt_k dx (s_b R_b - sigma_b R_0) + F_k sum_f (d beta_f / d G_b) X_f
+    if (dgG0) {
+        const int IR = 2 * P + P * P + 2, IX = IR + 4;
+        for (int i = t; i < 3 * Q; i += blockDim.x) {
+            const int q = i / 3, b = i % 3;
+            double acc = 0.0;
+            for (int f = 0; f < n_fields; ++f) {
+                const double* gm = gmeta + (int64_t)f * kGMeta;
+                if ((int)gm[0] != q) continue;
+                const double sb = gm[1 + b], sgb = gm[4 + b];
+                for (int k = 0; k < K; ++k) {
+                    const double* r = gfield + ((int64_t)k * n_fields + f) * NG;
+                    double xs = 0.0;
+                    for (int fc = 0; fc < 6; ++fc) xs += gm[7 + 3 * fc + b] * r[IX + fc];
+                    acc += fdt[k] * dx * (sb * r[IR + b] - sgb * r[IR + 3]) + Fk[k] * xs;
+                }
+            }
+            dgG0[i] = acc;
+        }
+    }
 }
 
 template <typename V, int TX>
 static void launch_adj_tx(const AdjArgs& a, int32_t n_blocks, hipStream_t st) {
-    if constexpr (std::is_same<V, float2>::value)
-        hipLaunchKernelGGL((k_adj_w4<V, TX>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+    // the gamma G0 sensitivities take their own instantiation (more
+    // accumulators); FP32 without them is held to four waves per SIMD
+    if (a.gradg)
+        hipLaunchKernelGGL((k_adj<V, TX, true>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+    else if constexpr (std::is_same<V, float2>::value)
+        hipLaunchKernelGGL((k_adj_w4<V, TX, false>), dim3(n_blocks), dim3(kBlock), 0, st, a);
     else
-        hipLaunchKernelGGL((k_adj<V, TX>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((k_adj<V, TX, false>), dim3(n_blocks), dim3(kBlock), 0, st, a);
 }
 
 template <typename V>
@@ -513,9 +563,11 @@ hipError_t launch_adj_gsum(const double* gpart, const FieldDesc* d_fields, int32
 hipError_t launch_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P,
                             double dt, double dx, const double* w, const double* T2,
                             const double* kappa, double* dD, double* dT2, double* dkappa,
-                            double* df, int32_t sub, hipStream_t st) {
+                            double* df, int32_t sub, int32_t ng, const double* gmeta,
+                            const double* fdt, const double* Fk, int32_t Q, double* dgG0,
+                            hipStream_t st) {
     hipLaunchKernelGGL(k_adj_final, dim3(1), dim3(64), 0, st, gfield, K, n_fields, P, dt, dx,
-                       w, T2, kappa, dD, dT2, dkappa, df, sub);
+                       w, T2, kappa, dD, dT2, dkappa, df, sub, ng, gmeta, fdt, Fk, Q, dgG0);
     return hipGetLastError();
 }
 

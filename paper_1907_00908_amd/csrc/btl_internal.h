@@ -60,7 +60,12 @@ struct FieldDesc {
 
 constexpr int kAdjMaxPhase = 4;
 // gradient accumulators per step: w[P], decay[P], trans[P*P], f, F
-constexpr int kNGMax = 2 * kAdjMaxPhase + kAdjMaxPhase * kAdjMaxPhase + 2;
+// with the gradient-strength sensitivities: + R_x, R_y, R_z, R_0, X_f[6]
+constexpr int kNGGrad = 10;
+constexpr int kNGMax = 2 * kAdjMaxPhase + kAdjMaxPhase * kAdjMaxPhase + 2 + kNGGrad;
+// per-field constants of the gamma G0 gradient: q-sample, s_b [3],
+// sigma_b [3], d beta_f / d G_b [6][3]
+constexpr int kGMeta = 25;
 
 struct AdjArgs {
     const void* lam_in;     // adjoint of the post-stream populations of step k (NULL: k = K)
@@ -86,6 +91,8 @@ struct AdjArgs {
     int32_t ng;
     int32_t xcd;            // 1: XCD-contiguous workgroup order (xcd_tile)
     int32_t slot;           // slot of this step in gpart (k - 1 - first step of the segment)
+    int32_t gradg;          // 1: also the gamma G0 sensitivities (ng includes kNGGrad)
+    int32_t pad;
 };
 
 struct StepArgs {
@@ -142,10 +149,14 @@ hipError_t launch_adj(int prec, int shape, const AdjArgs& a, int32_t n_blocks, h
 hipError_t launch_adj_gsum(const double* gpart, const FieldDesc* d_fields, int32_t n_fields,
                            int32_t nblk_total, int32_t ng, int32_t k_first, int32_t nsteps,
                            double* gfield, hipStream_t st);
+// dgG0 (device [Q][3] or NULL) needs gmeta (device [n_fields][kGMeta]) and
+// the per-step angles fdt [K] and F [K]
 hipError_t launch_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P,
                             double dt, double dx, const double* w, const double* T2,
                             const double* kappa, double* dD, double* dT2, double* dkappa,
-                            double* df, int32_t sub, hipStream_t st);
+                            double* df, int32_t sub, int32_t ng, const double* gmeta,
+                            const double* fdt, const double* Fk, int32_t Q, double* dgG0,
+                            hipStream_t st);
 hipError_t launch_init(int prec, void* pop, int64_t n_elem_per_dir_total,
                        const FieldDesc* d_fields, int32_t n_fields,
                        const FieldDesc* h_fields, double* E, int32_t Q, int32_t K, int32_t nq,

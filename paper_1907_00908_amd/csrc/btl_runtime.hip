@@ -68,6 +68,7 @@ struct btl_sim {
     int prec = BTL_F32;
     int scheme = BTL_HYBRID;
     int substeps = 1;            // reaction sub-steps per step (waveform samples per step)
+    int grad_g = 0;              // 1: taped forwards plan fields for the gamma G0 gradient
     int nq = 7;                  // lattice: 7 (D3Q7) or 5 (D2Q5 on single-layer geometries)
     int device = 0;
     double dx = 1.0;
@@ -88,6 +89,7 @@ struct btl_sim {
     // its own z-column length)
     DevBuf<FieldDesc> adj_fields;
     DevBuf<int32_t> adj_blk;
+    DevBuf<double> adj_gmeta;      // [fields][kGMeta] for the gamma G0 gradient
     // pinned staging for the per-call tables, two slots so that a call can
     // be prepared while the previous one's uploads are still queued
     char* stage[2] = {nullptr, nullptr};
@@ -117,6 +119,7 @@ struct btl_sim {
         bool valid = false;
         int32_t K = 0, C = 0, Q = 0, T = 0, n_fields = 0, nblk = 0, shape = 0, sub = 1, xcd = 0;
         int32_t nblk_adj = 0;      // workgroups of one adjoint step (adj_fields)
+        bool g_ok = false;         // the field set supports the gamma G0 gradient
         double dt = 0;
         int64_t state_elems = 0;   // V elements of one full state (all fields)
     } tape;
@@ -363,11 +366,24 @@ struct QFields {
     bool conj_pair = false;
 };
 
-static QFields plan_fields(const GeomHost& g, const double* G, bool classical) {
+// full: the set a gradient with respect to gamma G0 needs, valid for every
+// nearby G and not only for this one: every mirrored axis counts as carrying
+// a component, and the conjugate pairing is kept only when every axis is
+// mirrored (a periodic axis with a zero component would break it).
+static QFields plan_fields(const GeomHost& g, const double* G, bool classical, bool full = false) {
     QFields r;
     bool all_mirrored = true;
     int astar = -1;
     for (int a = 0; a < 3; ++a) {
+        if (full) {
+            if (g.bc[a] == BTL_MIRROR) {
+                r.amask |= 1 << a;
+                if (astar < 0) astar = a;
+            } else {
+                all_mirrored = false;
+            }
+            continue;
+        }
         if (G[a] == 0.0) continue;
         if (g.bc[a] == BTL_MIRROR) {
             r.amask |= 1 << a;
@@ -488,13 +504,22 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     // field table
     std::vector<FieldDesc>& fl = s->h_fields;
     fl.clear();
+    bool g_complete = true;   // every q-sample's field set is the full one
+    // per field: owning q-sample, s_b, sigma_b and d beta_f / d G_b (kGMeta)
+    std::vector<double> gmeta;
     int64_t pop_elems = 0;
     int32_t nblk_total = 0;
     for (int q = 0; q < Q; ++q) {
         const GeomHost g = kernel_geom(s->geoms[q_geom[q]], nq);
         double G[3];
         kernel_grad(gG0 + 3 * q, nq, G);
-        QFields qf = plan_fields(g, G, s->scheme == BTL_CLASSICAL);
+        const bool full = s->grad_g && ckpt_every > 0 && K > 0;
+        QFields qf = plan_fields(g, G, s->scheme == BTL_CLASSICAL, full);
+        {
+            const QFields qa = plan_fields(g, G, s->scheme == BTL_CLASSICAL, true);
+            if (!(qa.amask == qf.amask && qa.conj_pair == qf.conj_pair && qa.sigma == qf.sigma))
+                g_complete = false;
+        }
         const int base = (int)fl.size();
         auto slot_of = [&](int sg, int* cj) {
             for (size_t i = 0; i < qf.sigma.size(); ++i)
@@ -536,6 +561,16 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
                 if (sig) d.cu -= dx * G[a];
             }
             fl.push_back(d);
+            {
+                double gm[kGMeta] = {0.0};
+                gm[0] = q;
+                for (int a = 0; a < 3; ++a) {
+                    const int sig = (sg >> a) & 1;
+                    gm[1 + a] = sig ? -1.0 : 1.0;
+                    gm[4 + a] = sig;
+                }
+                gmeta.insert(gmeta.end(), gm, gm + kGMeta);
+            }
             pop_elems += (int64_t)nq * g.nsites;
             nblk_total += d.nblk;
         }
@@ -551,6 +586,9 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
                     d.face_pop[2 * a] = d.face_pop[2 * a + 1] = d.pop;
                     d.beta[2 * a] = La * G[a];
                     d.beta[2 * a + 1] = -La * G[a];
+                    double* gm = &gmeta[(size_t)(base + fi) * kGMeta + 7];
+                    gm[3 * (2 * a) + a] = La;
+                    gm[3 * (2 * a + 1) + a] = -La;
                 } else {
                     const int sa = ((sg >> a) & 1) ? -1 : 1;
                     const int sp = (qf.amask >> a) & 1 ? (sg ^ (1 << a)) : sg;
@@ -562,6 +600,11 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
                     d.face_pop[2 * a] = d.face_pop[2 * a + 1] = fl[slot].pop;
                     d.beta[2 * a] = gam;
                     d.beta[2 * a + 1] = -sa * 2.0 * La * G[a] + gam;
+                    double* gm = &gmeta[(size_t)(base + fi) * kGMeta + 7];
+                    for (int b = 0; b < 3; ++b) {
+                        gm[3 * (2 * a) + b] = cj ? dx : 0.0;
+                        gm[3 * (2 * a + 1) + b] = (cj ? dx : 0.0) + (b == a ? -sa * 2.0 * La : 0.0);
+                    }
                 }
             }
         }
@@ -680,7 +723,8 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         (e = s->tab.ensure((size_t)kTabSteps * T)) != hipSuccess ||
         (e = s->tab_field.ensure(T)) != hipSuccess ||
         (taping && ((e = s->adj_fields.ensure(n_fields)) != hipSuccess ||
-                    (e = s->adj_blk.ensure(nblk_adj)) != hipSuccess)))
+                    (e = s->adj_blk.ensure(nblk_adj)) != hipSuccess ||
+                    (e = s->adj_gmeta.ensure((size_t)n_fields * kGMeta)) != hipSuccess)))
         return hip_fail(s, e, "allocating tables");
     // stage all tables in pinned memory and upload asynchronously
     const size_t b_fields = (size_t)n_fields * sizeof(FieldDesc);
@@ -692,8 +736,10 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     const size_t o_blk = al(b_fields), o_steps = o_blk + al(b_blk), o_consts = o_steps + al(b_steps);
     const size_t o_tabf = o_consts + al(b_consts);
     const size_t b_afl = taping ? b_fields : 0, b_ablk = (size_t)nblk_adj * sizeof(int32_t);
+    const size_t b_agm = taping ? (size_t)n_fields * kGMeta * sizeof(double) : 0;
     const size_t o_afl = o_tabf + al(b_tabf), o_ablk = o_afl + al(b_afl);
-    const size_t total = o_ablk + al(b_ablk);
+    const size_t o_agm = o_ablk + al(b_ablk);
+    const size_t total = o_agm + al(b_agm);
     const int slot = s->stage_slot;
     if (!s->stage_ev[slot] && (e = hipEventCreateWithFlags(&s->stage_ev[slot], hipEventDisableTiming)) != hipSuccess)
         return hip_fail(s, e, "creating event");
@@ -716,6 +762,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     if (taping) {
         memcpy(stg + o_afl, afl.data(), b_afl);
         memcpy(stg + o_ablk, ablk.data(), b_ablk);
+        memcpy(stg + o_agm, gmeta.data(), b_agm);
     }
     if ((e = hipMemcpyAsync(s->fields.p, stg, b_fields, hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = hipMemcpyAsync(s->blk_field.p, stg + o_blk, b_blk, hipMemcpyHostToDevice, st)) != hipSuccess ||
@@ -724,7 +771,8 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         (e = hipMemcpyAsync(s->tab_field.p, stg + o_tabf, b_tabf, hipMemcpyHostToDevice, st)) != hipSuccess ||
         (taping &&
          ((e = hipMemcpyAsync(s->adj_fields.p, stg + o_afl, b_afl, hipMemcpyHostToDevice, st)) != hipSuccess ||
-          (e = hipMemcpyAsync(s->adj_blk.p, stg + o_ablk, b_ablk, hipMemcpyHostToDevice, st)) != hipSuccess)) ||
+          (e = hipMemcpyAsync(s->adj_blk.p, stg + o_ablk, b_ablk, hipMemcpyHostToDevice, st)) != hipSuccess ||
+          (e = hipMemcpyAsync(s->adj_gmeta.p, stg + o_agm, b_agm, hipMemcpyHostToDevice, st)) != hipSuccess)) ||
         (e = hipEventRecord(s->stage_ev[slot], st)) != hipSuccess)
         return hip_fail(s, e, "uploading tables");
     s->stage_used[slot] = true;
@@ -754,6 +802,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         s->tape.n_fields = n_fields;
         s->tape.nblk = nblk_total;
         s->tape.nblk_adj = nblk_adj;
+        s->tape.g_ok = g_complete;
         s->tape.shape = shape;
         s->tape.dt = dt;
         s->tape.sub = msub;
@@ -963,14 +1012,19 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
 }
 
 extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, double* dT2,
-                                   double* dkappa, double* df, void* stream) {
+                                   double* dkappa, double* df, double* dgG0, void* stream) {
     if (!s) return BTL_E_INVAL;
     if (!s->tape.valid) return fail(s, BTL_E_INVAL, "no adjoint tape: run btl_forward with ckpt_every > 0");
     if (!dL_dE) return fail(s, BTL_E_INVAL, "dL_dE is NULL");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const btl_sim::Tape& tp = s->tape;
     const int32_t K = tp.K, C = tp.C, T = tp.T, P = s->n_phase, nf = tp.n_fields;
-    const int NG = 2 * P + P * P + 2;
+    if (dgG0 && !tp.g_ok)
+        return fail(s, BTL_E_UNSUPPORTED,
+                    "dgG0 needs btl_set_grad_gG0(s, 1) before the taped forward (a mirrored axis "
+                    "without a gradient component, or the conjugate pairing next to a periodic "
+                    "axis, has no image fields to differentiate)");
+    const int NG = 2 * P + P * P + 2 + (dgG0 ? kNGGrad : 0);
     const size_t esz = s->prec == BTL_F32 ? sizeof(float2) : sizeof(double2);
     const size_t state_bytes = (size_t)tp.state_elems * esz;
     hipError_t e;
@@ -1017,6 +1071,7 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
     aa.n_phase = P;
     aa.K = K;
     aa.ng = NG;
+    aa.gradg = dgG0 ? 1 : 0;
 
     const int32_t nseg = (K + C - 1) / C;
     int lam_cur = 0;      // buffer holding Lambda^k on entry to adjoint step k
@@ -1060,7 +1115,8 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
     }
     if ((e = launch_adj_final(s->gfield.p, K, nf, P, tp.dt, s->dx, s->consts.p,
                               s->consts.p + 2 * P + P * P, s->consts.p + 3 * P + P * P, dD, dT2,
-                              dkappa, df, tp.sub, st)) != hipSuccess)
+                              dkappa, df, tp.sub, NG, s->adj_gmeta.p, s->steps.p,
+                              s->steps.p + K, tp.Q, dgG0, st)) != hipSuccess)
         return hip_fail(s, e, "adjoint final launch");
     return BTL_OK;
 }
@@ -1186,6 +1242,13 @@ extern "C" btl_status btl_set_lattice(btl_sim* s, int32_t lattice) {
     return BTL_OK;
 }
 
+extern "C" btl_status btl_set_grad_gG0(btl_sim* s, int32_t on) {
+    if (!s) return BTL_E_INVAL;
+    if (on != 0 && on != 1) return fail(s, BTL_E_INVAL, "btl_set_grad_gG0 takes 0 or 1");
+    s->grad_g = on;
+    return BTL_OK;
+}
+
 extern "C" btl_status btl_set_substeps(btl_sim* s, int32_t m) {
     if (!s) return BTL_E_INVAL;
     if (m < 1 || m > 65536) return fail(s, BTL_E_INVAL, "substeps must be in 1..65536");
@@ -1214,6 +1277,7 @@ extern "C" void btl_destroy(btl_sim* s) {
     s->blk_field.release();
     s->adj_fields.release();
     s->adj_blk.release();
+    s->adj_gmeta.release();
     s->steps.release();
     s->consts.release();
     s->partial.release();

@@ -165,6 +165,86 @@ def test_adjoint_launch_geometry_does_not_change_gradients(prec, monkeypatch):
             assert np.max(np.abs(x - y)) <= tol * scale, (zc, x, y)
 
 
+def _fd_gG0(cfg, a, b, q, ax, h=2e-4):
+    vals = []
+    for sgn in (1, -1):
+        c = dict(cfg)
+        g = np.array(cfg["gG0"], float).copy()
+        g[q, ax] += sgn * h
+        c["gG0"] = g
+        E, _ = oracle.simulate_config(c, threads=8)
+        vals.append(float(np.sum(a * E.real + b * E.imag)))
+    return (vals[0] - vals[1]) / (2 * h)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-6), ("f32", 1e-3)])
+@pytest.mark.parametrize("bc", [[0, 0, 0], [1, 1, 1], [1, 0, 1]])
+def test_adjoint_gG0_vs_oracle_fd(prec, tol, bc):
+    # dL/d(gamma G0) through the reaction phase and the face factors, for a
+    # fully oblique q-sample and one without a z component (on mirrored
+    # faces that one needs the full field set: btl_set_grad_gG0)
+    btl, torch = _gpu()
+    cfg = _cfg_small(bc, seed=61, K=80, n=(10, 9, 7))
+    Q, K = len(cfg["gG0"]), len(cfg["f"])
+    a, b = _loss_weights(Q, K, seed=9)
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], prec, grad_gG0=True)
+    try:
+        E = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"],
+                        cfg["q_geom"], ckpt_every=30)
+        g = torch.tensor(np.stack([a, b], axis=-1), dtype=torch.float64, device=E.device)
+        dG = sim.backward(g, 2, K, grad_gG0=True)[4].cpu().numpy()
+    finally:
+        sim.close()
+    fd = np.array([[_fd_gG0(cfg, a, b, q, ax) for ax in range(3)] for q in range(Q)])
+    scale = np.max(np.abs(fd))
+    for q in range(Q):
+        for ax in range(3):
+            err = abs(dG[q, ax] - fd[q, ax]) / scale
+            print(f"{prec} bc={bc} dgG0[{q},{ax}]: adjoint {dG[q, ax]:.9e} fd {fd[q, ax]:.9e} "
+                  f"rel {err:.2e}", flush=True)
+    assert np.max(np.abs(dG - fd)) <= tol * scale
+
+
+def test_gG0_gradient_field_set():
+    # the full field set leaves the signal unchanged; without it a mirrored
+    # axis with no gradient component has nothing to differentiate
+    btl, torch = _gpu()
+    cfg = _cfg_small([1, 1, 1], seed=62, K=60, n=(10, 9, 7))
+    Q, K = len(cfg["gG0"]), len(cfg["f"])
+    Es = []
+    for full in (False, True):
+        sim = btl.Simulator(cfg["geoms"], cfg["bc"], "f64", grad_gG0=full)
+        try:
+            E = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"],
+                            cfg["q_geom"], ckpt_every=20)
+            Es.append(E.cpu().numpy())
+            g = torch.zeros((Q, K + 1, 2), dtype=torch.float64, device=E.device)
+            if not full:
+                sim.backward(g, 2, K)        # the other gradients still work
+                with pytest.raises(btl.BtlError) as ei:
+                    sim.backward(g, 2, K, grad_gG0=True)
+                assert ei.value.status == btl.BTL_E_UNSUPPORTED
+        finally:
+            sim.close()
+    assert np.max(np.abs(Es[0] - Es[1])) < 1e-13
+
+
+def test_autograd_gG0_tensor():
+    btl, torch = _gpu()
+    cfg = _cfg_small([1, 1, 1], seed=63, K=50, n=(10, 9, 7))
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], "f64")
+    try:
+        D = torch.tensor(cfg["D"], requires_grad=True)
+        G = torch.tensor(cfg["gG0"], requires_grad=True)
+        E = btl.bloch_torrey_signal(D, torch.tensor(cfg["T2"]), torch.tensor(cfg["kappa"]),
+                                    torch.tensor(cfg["f"]), sim, cfg["dt"], G, ckpt_every=25)
+        (E[:, -1, 0] ** 2 + E[:, -1, 1] ** 2).sum().backward()
+    finally:
+        sim.close()
+    assert G.grad.shape == (2, 3) and torch.isfinite(G.grad).all()
+    assert D.grad is not None
+
+
 def test_autograd_function():
     btl, torch = _gpu()
     cfg = _cfg_small([0, 0, 0], seed=54, K=80)
