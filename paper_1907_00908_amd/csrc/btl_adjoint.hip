@@ -387,14 +387,19 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         for (int wave = 0; wave < kBlock / 64; ++wave) {
             if (wv == wave && lane == 0) {
-                for (int i = 0; i < P; ++i) {
-                    red[IW + i] += v[i];
-                    red[IDEC + i] += v[kAdjMaxPhase + i];
+#pragma unroll
+                for (int i = 0; i < kAdjMaxPhase; ++i) {
+                    if (i < P) {
+                        red[IW + i] += v[i];
+                        red[IDEC + i] += v[kAdjMaxPhase + i];
+                    }
                 }
                 red[IF] += v[2 * kAdjMaxPhase];
                 red[IFF] += v[2 * kAdjMaxPhase + 1];
-                if constexpr (GG)
+                if constexpr (GG) {
+#pragma unroll
                     for (int i = 0; i < kNGGrad; ++i) red[IR + i] += v[2 * kAdjMaxPhase + 2 + i];
+                }
             }
             __syncthreads();
         }
