@@ -224,6 +224,9 @@ def test_gG0_gradient_field_set():
                 with pytest.raises(btl.BtlError) as ei:
                     sim.backward(g, 2, K, grad_gG0=True)
                 assert ei.value.status == btl.BTL_E_UNSUPPORTED
+                with pytest.raises(btl.BtlError) as ei:
+                    btl.btl_set_grad_gG0(sim._h, 2)
+                assert ei.value.status == btl.BTL_E_INVAL
         finally:
             sim.close()
     assert np.max(np.abs(Es[0] - Es[1])) < 1e-13
