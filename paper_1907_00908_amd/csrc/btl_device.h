@@ -58,25 +58,6 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Fixed-order sum of v over the 256 threads of the workgroup; the result is
-// valid in thread 0.
-__device__ __forceinline__ double2 block_sum(double2 v, double2* lds) {
-    v.x = wave_sum(v.x);
-    v.y = wave_sum(v.y);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) lds[wv] = v;
-    __syncthreads();
-    double2 r = make_double2(0.0, 0.0);
-    if (threadIdx.x == 0) {
-        r = lds[0];
-        for (int i = 1; i < kBlock / 64; ++i) {
-            r.x += lds[i].x;
-            r.y += lds[i].y;
-        }
-    }
-    return r;
-}
-
 // Weights of the six populations that make up the population entering a
 // node across a membrane at distance d (units of dx) from it, for a straight
 // membrane normal to the link (Eqs. B2a_text/B2b_text with theta = 0,

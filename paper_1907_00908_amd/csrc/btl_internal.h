@@ -83,7 +83,6 @@ struct AdjArgs {
     double* gpart;          // [segment slot][blocks][NG] per-workgroup gradient sums
                             // (launch_adj_gsum adds them up per field)
     double dt;
-    int32_t n_fields;
     int32_t n_phase;
     int32_t k;
     int32_t K;
@@ -92,13 +91,13 @@ struct AdjArgs {
     int32_t xcd;            // 1: XCD-contiguous workgroup order (xcd_tile)
     int32_t slot;           // slot of this step in gpart (k - 1 - first step of the segment)
     int32_t gradg;          // 1: also the gamma G0 sensitivities (ng includes kNGGrad)
-    int32_t pad;
 };
 
 struct StepArgs {
     const void* src;        // post-collision populations of step k (T*)
     void* dst;              // post-collision populations of step k+1
-    const uint32_t* words;  // site words: bits 0-7 phase, bit 8+d-1 membrane on pull link d
+    const uint32_t* words;  // site words: bits 0-3 phase, bit 4+d-1 membrane on pull link d,
+                            // bits 10+3(d-1).. the phase across that link
     const FieldDesc* fields;
     const int32_t* blk_field;
     const double* fdt;      // [K] f_k * dt

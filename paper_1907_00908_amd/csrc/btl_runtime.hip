@@ -1067,7 +1067,6 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
     aa.gpart = s->gpart.p;
     aa.dt = tp.dt;
     aa.xcd = nblk_adj > kXcdMinBlocks ? 1 : 0;
-    aa.n_fields = nf;
     aa.n_phase = P;
     aa.K = K;
     aa.ng = NG;
