@@ -136,10 +136,24 @@ def cpu_baseline(cfg, budget_s: float = 25.0):
     sites = g.comp.size
     note = ("; the oracle steps the reflected, doubled domain"
             if oracle.needs_doubling(cfg["bc"], cfg["gG0"][0]) else "")
+    # the same oracle on one thread, a few steps (about a quarter of the
+    # budget); a one-step run's time is subtracted to remove the setup
+    def run1(n):
+        t = time.perf_counter()
+        oracle.simulate(*args, cfg["f"][:n], cfg["gG0"][0], threads=1, want_M=False,
+                        lattice=lat)
+        return time.perf_counter() - t
+    n1 = int(max(1, min(50, 0.25 * budget_s / (per * threads))))
+    t_setup = run1(1)
+    t_run = run1(1 + n1)
+    t2, t3 = 0.0, max(t_run - t_setup, 1e-9)
     return {"value": sites * n / (t1 - t0), "unit": "site-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": f"q-sample 0 of the workload, {n} full-size steps ({sites} REV sites"
-                      f"{note}), {t1 - t0:.1f} s"}
+                      f"{note}), {t1 - t0:.1f} s",
+            "single_thread": {"value": sites * n1 / (t3 - t2), "cores": 1,
+                              "sample": f"{n1} full-size steps beyond a 1-step run, "
+                                        f"{t3 - t2:.1f} s"}}
 
 
 def bench_adjoint(btl, torch, sim, cfg, args, fwd_ms_step, fs, qs, Q):
