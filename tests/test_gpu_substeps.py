@@ -87,6 +87,40 @@ def test_substeps_adjoint_vs_oracle_fd(prec, tol):
         assert err <= tol, (which, idx, gval, fd)
 
 
+def test_substeps_gG0_gradient_vs_oracle_fd():
+    # the gamma G0 gradient with m = 3 sub-steps: the reaction angle of a
+    # step is the sum of its sub-step angles, the face phases use F advanced
+    # by the same sums
+    import torch
+    btl = _gpu()
+    m = 3
+    cfg = _cfg([1, 1, 0], m, K=60, gG=np.array([[7.0, 4.0, 2.0], [0.0, 6.0, -3.0]]))
+    Q, K = len(cfg["gG0"]), len(cfg["f"]) // m
+    a, b = _loss_weights(Q, K)
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], "f64", substeps=m, grad_gG0=True)
+    try:
+        E = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"],
+                        cfg["q_geom"], ckpt_every=20)
+        g = torch.tensor(np.stack([a, b], axis=-1), dtype=torch.float64, device=E.device)
+        dG = sim.backward(g, 2, K, grad_gG0=True)[4].cpu().numpy()
+    finally:
+        sim.close()
+    h = 2e-4
+    fd = np.zeros((Q, 3))
+    for q in range(Q):
+        for ax in range(3):
+            vals = []
+            for sgn in (1, -1):
+                G = np.array(cfg["gG0"], float).copy()
+                G[q, ax] += sgn * h
+                E_o, _ = oracle.simulate_config(dict(cfg, gG0=G), threads=8)
+                vals.append(float(np.sum(a * E_o.real + b * E_o.imag)))
+            fd[q, ax] = (vals[0] - vals[1]) / (2 * h)
+    scale = np.max(np.abs(fd))
+    print("dgG0", dG, "fd", fd, flush=True)
+    assert np.max(np.abs(dG - fd)) <= 1e-6 * scale
+
+
 def test_substeps_errors():
     btl = _gpu()
     cfg = _cfg([0, 0, 0], 2, K=20)
