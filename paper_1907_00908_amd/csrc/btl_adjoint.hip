@@ -69,7 +69,7 @@ __device__ __forceinline__ void store_stream(double2* p, double2 v) {
 template <typename V, int TX, bool GG>
 __device__ __forceinline__ void adj_body(const AdjArgs& a) {
     using R = typename AdjReal<V>::R;
-    constexpr int TY = kBlock / TX;
+    constexpr int TY = TX > 0 ? kBlock / TX : 1;
     constexpr int NT = kAdjMaxPhase * kAdjMaxPhase;   // membrane pair sums per thread (LDS row)
     constexpr int RS = NT + 1;                         // odd row stride
     __shared__ double c_tr[kAdjMaxPhase * kAdjMaxPhase];
@@ -108,8 +108,15 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
     const int32_t tz = rb / fd.tiles[1];
     const int32_t z0 = tz * fd.zc;
     const int32_t z1 = min(n2, z0 + fd.zc);
-    const int32_t j0 = tx * TX + (int32_t)(threadIdx.x % TX);
-    const int32_t j1 = ty * TY + (int32_t)(threadIdx.x / TX);
+    int32_t j0, j1;
+    if constexpr (TX == 0) {   // kTileRows: kBlock consecutive sites of the x-y plane
+        const int32_t i = tx * kBlock + (int32_t)threadIdx.x;
+        j0 = i % n0;
+        j1 = i / n0;
+    } else {
+        j0 = tx * TX + (int32_t)(threadIdx.x % TX);
+        j1 = ty * TY + (int32_t)(threadIdx.x / TX);
+    }
     // site index s = j0 + st1 j1 + st2 j2 (site words); populations z-major:
     // plane d of site (j0, j1, j2) at d ps + j0 + st1 j1 + zs j2
     const int32_t st1 = n0, st2 = n0 * n1, ps = st2, zs = kQ * st2;
@@ -542,6 +549,7 @@ static void launch_adj_t(int shape, const AdjArgs& a, int32_t n_blocks, hipStrea
         case kTile64x4: launch_adj_tx<V, 64>(a, n_blocks, st); break;
         case kTile32x8: launch_adj_tx<V, 32>(a, n_blocks, st); break;
         case kTile128x2: launch_adj_tx<V, 128>(a, n_blocks, st); break;
+        case kTileRows: launch_adj_tx<V, 0>(a, n_blocks, st); break;
         default: launch_adj_tx<V, 16>(a, n_blocks, st); break;
     }
 }

@@ -130,15 +130,33 @@ struct StepArgs {
 
 // Workgroup tile shapes (TX x TY threads, one site column along z each).
 // kTile256x1 serves single-layer (D2Q5) lattices only, whose rows are walked
-// as columns (see kernel_geom in the runtime).
+// as columns (see kernel_geom in the runtime).  kTileRows (3D lattices) cuts
+// the x-y plane, read row after row, into runs of kBlock consecutive sites:
+// no idle lanes where n0 is not a multiple of a tile width (kernel template
+// TX = 0).
 enum TileShape : int32_t {
     kTile64x4 = 0, kTile32x8 = 1, kTile16x16 = 2, kTile128x2 = 3, kTile256x1 = 4,
-    kTileCount3D = 4, kTileCount = 5
+    kTileRows = 5, kTileCount = 6
 };
+// the shapes a 3D lattice may use, in the order ties are broken
+constexpr int kShapes3D[] = {kTile128x2, kTile64x4, kTile32x8, kTile16x16, kTileRows};
+constexpr int kShapeCount3D = 5;
 inline void tile_dims(int shape, int* tx, int* ty) {
     *tx = shape == kTile64x4 ? 64 : shape == kTile32x8 ? 32 : shape == kTile128x2 ? 128
-        : shape == kTile256x1 ? 256 : 16;
-    *ty = kBlock / *tx;
+        : shape == kTile256x1 ? 256 : shape == kTileRows ? 0 : 16;
+    *ty = *tx ? kBlock / *tx : 0;
+}
+// workgroups per z chunk of an n0 x n1 plane, as [x][y] tile counts
+inline void tile_grid(int shape, int32_t n0, int32_t n1, int32_t* t0, int32_t* t1) {
+    int tx, ty;
+    tile_dims(shape, &tx, &ty);
+    if (tx == 0) {
+        *t0 = (int32_t)(((int64_t)n0 * n1 + kBlock - 1) / kBlock);
+        *t1 = 1;
+    } else {
+        *t0 = (n0 + tx - 1) / tx;
+        *t1 = (n1 + ty - 1) / ty;
+    }
 }
 
 // Launchers (btl_kernels.hip, btl_adjoint.hip)

@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(kBlock) k_tables(StepArgs a, int32_t nsteps) {
 // whose moment is M(t^K).
 template <typename V, int TX, bool CL, bool GM, int NQ>
 __device__ __forceinline__ void step_body(const StepArgs& a) {
-    constexpr int TY = kBlock / TX;
+    constexpr int TY = TX > 0 ? kBlock / TX : 1;
     constexpr double W0 = lattice_w0(NQ), W1 = lattice_w1(NQ);
     // Plane p >= 1 moves along kernel direction kd(p): D3Q7 p itself; the
     // single-layer D2Q5 lattice runs with its y axis as the kernel's z axis
@@ -135,8 +135,15 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     const uint32_t* __restrict__ words = a.words + fd.words;
     const float* __restrict__ gmt = GM && fd.gm >= 0 ? a.gm + fd.gm : nullptr;
     const int32_t pop = 0;
-    const int32_t j0 = tx * TX + (int32_t)(threadIdx.x % TX);
-    const int32_t j1 = ty * TY + (int32_t)(threadIdx.x / TX);
+    int32_t j0, j1;
+    if constexpr (TX == 0) {   // kTileRows: kBlock consecutive sites of the x-y plane
+        const int32_t i = tx * kBlock + (int32_t)threadIdx.x;
+        j0 = i % n0;
+        j1 = i / n0;
+    } else {
+        j0 = tx * TX + (int32_t)(threadIdx.x % TX);
+        j1 = ty * TY + (int32_t)(threadIdx.x / TX);
+    }
     const int32_t z1 = min(n2, z0 + fd.zc);
     // site index s = j0 + st1 j1 + st2 j2 (site words, membrane positions);
     // populations: plane d of site (j0, j1, j2) at d ps + j0 + st1 j1 + zs j2
@@ -554,6 +561,9 @@ static void launch_step_t(int shape, const StepArgs& a, int32_t n_blocks, hipStr
         case kTile128x2: launch_tx<V, CL, GM, NQ, 128>(a, n_blocks, st); break;
         case kTile256x1:
             if constexpr (NQ == 5) launch_tx<V, CL, GM, NQ, 256>(a, n_blocks, st);
+            break;
+        case kTileRows:
+            if constexpr (NQ == 7) launch_tx<V, CL, GM, NQ, 0>(a, n_blocks, st);
             break;
         default: launch_tx<V, CL, GM, NQ, 16>(a, n_blocks, st); break;
     }

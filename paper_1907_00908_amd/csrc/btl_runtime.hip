@@ -158,19 +158,16 @@ static void kernel_grad(const double* G, int nq, double* out) {
 // Single-layer lattices always take 256 x 1 (their tiles are one row).
 static int pick_shape(const std::vector<GeomHost>& gs, const int32_t* q_geom, int Q, int nq) {
     if (nq == 5) return kTile256x1;
-    static const int order[kTileCount3D] = {kTile128x2, kTile64x4, kTile32x8, kTile16x16};
     int best = kTile128x2;
     int64_t best_waste = -1;
-    for (int oi = 0; oi < kTileCount3D; ++oi) {
-        const int sh = order[oi];
-        int tx, ty;
-        tile_dims(sh, &tx, &ty);
+    for (int oi = 0; oi < kShapeCount3D; ++oi) {
+        const int sh = kShapes3D[oi];
         int64_t waste = 0;
         for (int q = 0; q < Q; ++q) {
             const GeomHost& g = gs[q_geom[q]];
-            const int64_t cx = (g.n[0] + tx - 1) / tx * (int64_t)tx;
-            const int64_t cy = (g.n[1] + ty - 1) / ty * (int64_t)ty;
-            waste += (cx * cy - (int64_t)g.n[0] * g.n[1]) * g.n[2];
+            int32_t t0, t1;
+            tile_grid(sh, g.n[0], g.n[1], &t0, &t1);
+            waste += ((int64_t)t0 * t1 * kBlock - (int64_t)g.n[0] * g.n[1]) * g.n[2];
         }
         if (best_waste < 0 || waste < best_waste) {
             best = sh;
@@ -492,8 +489,6 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     // launch shape
     int shape = s->tile_shape >= 0 ? s->tile_shape : pick_shape(s->geoms, q_geom, Q, nq);
     if ((nq == 5) != (shape == kTile256x1)) shape = pick_shape(s->geoms, q_geom, Q, nq);
-    int TX, TY;
-    tile_dims(shape, &TX, &TY);
     int ZC = s->zc;
     if (ZC <= 0) {
         ZC = 1;
@@ -548,8 +543,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
             d.nsites = (int32_t)g.nsites;
             d.blk0 = nblk_total;
             d.zc = ZC;
-            d.tiles[0] = (g.n[0] + TX - 1) / TX;
-            d.tiles[1] = (g.n[1] + TY - 1) / TY;
+            tile_grid(shape, g.n[0], g.n[1], &d.tiles[0], &d.tiles[1]);
             d.tiles[2] = (g.n[2] + ZC - 1) / ZC;
             d.nblk = d.tiles[0] * d.tiles[1] * d.tiles[2];
             d.q = fi == 0 ? q : -1;
@@ -1122,7 +1116,7 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
 
 extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void* stream) {
     if (!s) return BTL_E_INVAL;
-    // fixed launch shape for measurements: BTLBM_TILE (0..4), BTLBM_ZC,
+    // fixed launch shape for measurements: BTLBM_TILE (0..5, see TileShape), BTLBM_ZC,
     // BTLBM_XCD (0 plain, 1 XCD-contiguous workgroup order); BTLBM_VERBOSE
     // prints the choice
     const char* et = getenv("BTLBM_TILE");
@@ -1187,8 +1181,13 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
     int best_shape = -1, best_zc = 0;
     btl_status rc = BTL_OK;
     s->xcd = -1;   // shapes are compared with the default workgroup order
-    const int sh0 = s->nq == 5 ? kTile256x1 : 0, sh1 = s->nq == 5 ? kTileCount : kTileCount3D;
-    for (int sh = sh0; sh < sh1 && rc == BTL_OK; ++sh)
+    std::vector<int> shapes;
+    if (s->nq == 5)
+        shapes.push_back(kTile256x1);
+    else
+        shapes.assign(kShapes3D, kShapes3D + kShapeCount3D);
+    for (int sh : shapes) {
+        if (rc != BTL_OK) break;
         for (int zc : zcs) {
             s->tile_shape = sh;
             s->zc = zc;
@@ -1200,6 +1199,7 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
                 best_zc = zc;
             }
         }
+    }
     // workgroup order for the best shape: plain and XCD-contiguous
     int best_xcd = -1;
     for (int xo = 0; xo < 2 && rc == BTL_OK && best_shape >= 0; ++xo) {

@@ -179,6 +179,45 @@ def test_autotune_keeps_results():
     _check(E2, Eo, "f64", "after autotune")
 
 
+@pytest.mark.parametrize("shape,zc", [(5, 0), (5, 3), (2, 4), (1, 0)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_every_tile_shape_matches_oracle(shape, zc, prec, monkeypatch):
+    # each launch shape (5: runs of 256 consecutive sites of the x-y plane,
+    # 2: 16x16, 1: 32x8) on a ragged lattice with mirrored faces, oblique
+    # gradients (image fields) and membranes, forward and adjoint
+    btl = _gpu()
+    import torch
+    cfg = w.make_config("cfg2", n=21, K=150)
+    cfg["geoms"][0] = w.cylinders_z((21, 19, 9), 0.25, seed=23, vf_target=0.5, periodic=False)
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], prec)
+    try:
+        args = (cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"])
+        sim.forward(*args[:4], cfg["f"][:2], cfg["gG0"])
+        monkeypatch.setenv("BTLBM_TILE", str(shape))
+        monkeypatch.setenv("BTLBM_ZC", str(zc))
+        btl.btl_autotune(sim._h, 1, 1, torch.cuda.current_stream().cuda_stream)
+        E = sim.forward(*args, ckpt_every=50)
+        Q, K = len(cfg["gG0"]), len(cfg["f"])
+        r = np.random.default_rng(3)
+        g = torch.tensor(r.normal(size=(Q, K + 1, 2)), dtype=torch.float64, device=E.device)
+        grads = [t.cpu().numpy() for t in sim.backward(g, 2, K)]
+        E = E.cpu().numpy()
+    finally:
+        sim.close()
+    Eo, _ = oracle.simulate_config(cfg)
+    _check(E, Eo, prec, f"shape {shape} zc {zc}")
+    # gradients against the default launch shape of a fresh simulator
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], prec)
+    try:
+        sim.forward(*args, ckpt_every=50)
+        ref = [t.cpu().numpy() for t in sim.backward(g, 2, K)]
+    finally:
+        sim.close()
+    tol = 1e-11 if prec == "f64" else 1e-5
+    for x, y in zip(grads, ref):
+        assert np.max(np.abs(x - y)) <= tol * max(np.max(np.abs(y)), 1e-30)
+
+
 def test_q_waves_match_single_batch(monkeypatch):
     # a device-memory budget below the batch's population size splits the
     # q-samples into consecutive waves; every field is computed exactly as
