@@ -232,8 +232,8 @@ def main():
                     help="only run a device copy of known size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is "
-                                   "described in DESIGN.md but not implemented",
+        print(json.dumps({"error": "bench.py runs on one GPU; splitting the q-samples "
+                                   "over several GPUs is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -54,10 +54,10 @@ typedef struct btl_sim btl_sim;
 typedef enum {
     BTL_OK = 0,
     BTL_E_INVAL = 1,        /* invalid argument (message says which) */
-    BTL_E_UNSUPPORTED = 2,  /* valid request this build does not implement */
+    BTL_E_UNSUPPORTED = 2,  /* valid request the library does not implement */
     BTL_E_NOMEM = 3,        /* device memory exhausted */
     BTL_E_HIP = 4,          /* a HIP runtime call failed */
-    BTL_E_NONFINITE = 5     /* reserved (calls are asynchronous; this build does not
+    BTL_E_NONFINITE = 5     /* reserved (calls are asynchronous; the library does not
                                inspect results, check E on the caller's side) */
 } btl_status;
 
