@@ -159,8 +159,9 @@ btl_status btl_backward(btl_sim *s, const double *dL_dE, double *dD, double *dT2
  * single-layer geometries (n[2] = 1) with no gradient along z; eps_D enters
  * tau (Eq. tau_def) and the membrane number P (Eq. P_def), every other rule
  * is unchanged.  A D2Q5 forward returns BTL_E_INVAL for a geometry with
- * n[2] != 1 or a q-sample with gG0 z != 0, and BTL_E_UNSUPPORTED when it
- * asks for an adjoint tape.  Errors: BTL_E_INVAL (unknown lattice). */
+ * n[2] != 1 or a q-sample with gG0 z != 0.  btl_backward works on either
+ * lattice; on D2Q5 the z component of dgG0 is 0 (not a parameter of the
+ * layer).  Errors: BTL_E_INVAL (unknown lattice). */
 btl_status btl_set_lattice(btl_sim *s, int32_t lattice);
 
 /* Reaction sub-stepping (Sec. 2.3: the reaction may run with its own time

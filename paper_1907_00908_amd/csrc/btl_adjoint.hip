@@ -66,9 +66,14 @@ __device__ __forceinline__ void store_stream(double2* p, double2 v) {
     __builtin_nontemporal_store(v.y, &p->y);
 }
 
-template <typename V, int TX, bool GG>
+template <typename V, int TX, bool GG, int NQ>
 __device__ __forceinline__ void adj_body(const AdjArgs& a) {
     using R = typename AdjReal<V>::R;
+    // planes pz (+z pull) and pz + 1 (-z pull); on the single-layer D2Q5
+    // lattice the kernel's z axis is the geometry's y axis and planes 3, 4
+    // pull along it (as in the forward step), site words keep plane numbers
+    constexpr int pz = NQ == 7 ? 5 : 3;
+    auto axis_of = [](int d) { return NQ == 7 ? (d - 1) >> 1 : (d <= 2 ? 0 : 2); };
     constexpr int TY = TX > 0 ? kBlock / TX : 1;
     constexpr int NT = kAdjMaxPhase * kAdjMaxPhase;   // membrane pair sums per thread (LDS row)
     constexpr int RS = NT + 1;                         // odd row stride
@@ -119,7 +124,7 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
     }
     // site index s = j0 + st1 j1 + st2 j2 (site words); populations z-major:
     // plane d of site (j0, j1, j2) at d ps + j0 + st1 j1 + zs j2
-    const int32_t st1 = n0, st2 = n0 * n1, ps = st2, zs = kQ * st2;
+    const int32_t st1 = n0, st2 = n0 * n1, ps = st2, zs = NQ * st2;
     // one base pointer per buffer for this field; every access is a 32-bit
     // element offset from it (image-field partners of the same q-sample
     // lie within +-2^31 elements, checked on the host)
@@ -176,36 +181,37 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
         };
         const int32_t o1 = fx0 ? face_off(0, 1, n0 - 1) : pop + 1 * ps - 1;
         const int32_t o2 = fx1 ? face_off(1, 2, -(n0 - 1)) : pop + 2 * ps + 1;
-        const int32_t o3 = fy0 ? face_off(2, 3, (n1 - 1) * st1) : pop + 3 * ps - st1;
-        const int32_t o4 = fy1 ? face_off(3, 4, -(n1 - 1) * st1) : pop + 4 * ps + st1;
+        const int32_t o3 = NQ == 5 ? 0 : fy0 ? face_off(2, 3, (n1 - 1) * st1) : pop + 3 * ps - st1;
+        const int32_t o4 = NQ == 5 ? 0 : fy1 ? face_off(3, 4, -(n1 - 1) * st1) : pop + 4 * ps + st1;
         const int32_t q1 = fx1 ? adj_off(1, 1, -(n0 - 1)) : pop + 1 * ps + 1;
         const int32_t q2 = fx0 ? adj_off(0, 2, n0 - 1) : pop + 2 * ps - 1;
-        const int32_t q3 = fy1 ? adj_off(3, 3, -(n1 - 1) * st1) : pop + 3 * ps + st1;
-        const int32_t q4 = fy0 ? adj_off(2, 4, (n1 - 1) * st1) : pop + 4 * ps - st1;
-        // z offsets do not depend on the thread: wave-uniform
-        const int32_t o5i = pop + 5 * ps - zs;
-        const int32_t o6i = pop + 6 * ps + zs;
-        const int32_t q5i = pop + 5 * ps + zs;
-        const int32_t q6i = pop + 6 * ps - zs;
-        const int32_t o5f = face_off(4, 5, (n2 - 1) * zs);
-        const int32_t o6f = face_off(5, 6, -(n2 - 1) * zs);
-        const int32_t q5f = adj_off(5, 5, -(n2 - 1) * zs);
-        const int32_t q6f = adj_off(4, 6, (n2 - 1) * zs);
+        const int32_t q3 = NQ == 5 ? 0 : fy1 ? adj_off(3, 3, -(n1 - 1) * st1) : pop + 3 * ps + st1;
+        const int32_t q4 = NQ == 5 ? 0 : fy0 ? adj_off(2, 4, (n1 - 1) * st1) : pop + 4 * ps - st1;
+        // z offsets (planes pz, pz + 1) do not depend on the thread: wave-uniform
+        const int32_t o5i = pop + pz * ps - zs;
+        const int32_t o6i = pop + (pz + 1) * ps + zs;
+        const int32_t q5i = pop + pz * ps + zs;
+        const int32_t q6i = pop + (pz + 1) * ps - zs;
+        const int32_t o5f = face_off(4, pz, (n2 - 1) * zs);
+        const int32_t o6f = face_off(5, pz + 1, -(n2 - 1) * zs);
+        const int32_t q5f = adj_off(5, pz, -(n2 - 1) * zs);
+        const int32_t q6f = adj_off(4, pz + 1, (n2 - 1) * zs);
 
         // Four values are shared with the z neighbour and carried along the
-        // column instead of reloaded: adjoint plane 6 at z is rlown[5] here
-        // and rl[6] of z + 1, plane 5 at z + 1 is rl[5] here and rlown[6] of
-        // z + 1; forward plane 5 at z is rown[6] here and rg[5] of z + 1,
-        // plane 6 at z + 1 is rg[6] here and rown[5] of z + 1.
+        // column instead of reloaded (D3Q7 plane numbers, pz = 5): adjoint
+        // plane 6 at z is rlown[5] here and rl[6] of z + 1, plane 5 at z + 1
+        // is rl[5] here and rlown[6] of z + 1; forward plane 5 at z is
+        // rown[6] here and rg[5] of z + 1, plane 6 at z + 1 is rg[6] here
+        // and rown[5] of z + 1.
         V c_rl6 = mk2<V>(0.0, 0.0), c_rlo6 = mk2<V>(0.0, 0.0), c_rg5, c_ro5;
         {
             const int32_t sp = j0 + st1 * j1 + zs * z0;
             if (!a.top) {
                 c_rl6 = lam[(z0 == 0 ? q6f : q6i) + sp];
-                c_rlo6 = lam[pop + 5 * ps + sp];
+                c_rlo6 = lam[pop + pz * ps + sp];
             }
             c_rg5 = fwd[(z0 == 0 ? o5f : o5i) + sp];
-            c_ro5 = fwd[pop + 6 * ps + sp];
+            c_ro5 = fwd[pop + (pz + 1) * ps + sp];
         }
 #pragma nounroll
         for (int32_t j2 = z0; j2 < z1; ++j2) {
@@ -221,31 +227,33 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
             const bool flo[3] = {fx0, fy0, fz0}, fhi[3] = {fx1, fy1, fz1};
 
             // ---- adjoint pull of Lambda^k ----
-            V lh[kQ];
+            V lh[NQ];
             if (a.top) {
 #pragma unroll
-                for (int d = 0; d < kQ; ++d) lh[d] = mk2<V>(0.0, 0.0);
+                for (int d = 0; d < NQ; ++d) lh[d] = mk2<V>(0.0, 0.0);
             } else {
-                V rl[kQ], rlown[kQ];
+                V rl[NQ], rlown[NQ];
                 rl[0] = lam[pop + sp];
                 rl[1] = lam[q1 + sp];
                 rl[2] = lam[q2 + sp];
-                rl[3] = lam[q3 + sp];
-                rl[4] = lam[q4 + sp];
-                rl[5] = lam[(fz1 ? q5f : q5i) + sp];
-                rl[6] = c_rl6;
+                if constexpr (NQ == 7) {
+                    rl[3] = lam[q3 + sp];
+                    rl[4] = lam[q4 + sp];
+                }
+                rl[pz] = lam[(fz1 ? q5f : q5i) + sp];
+                rl[pz + 1] = c_rl6;
 #pragma unroll
-                for (int d = 1; d < 6; ++d) {
+                for (int d = 1; d <= pz; ++d) {
                     const int od = (d & 1) ? d + 1 : d - 1;
                     rlown[d] = lam[pop + od * ps + sp];
                 }
-                rlown[6] = c_rlo6;
-                c_rl6 = rlown[5];
-                c_rlo6 = rl[5];
+                rlown[pz + 1] = c_rlo6;
+                c_rl6 = rlown[pz];
+                c_rlo6 = rl[pz];
                 lh[0] = rl[0];
 #pragma unroll
-                for (int d = 1; d < kQ; ++d) {
-                    const int ax = (d - 1) >> 1;
+                for (int d = 1; d < NQ; ++d) {
+                    const int ax = axis_of(d);
                     const bool plus = (d & 1) != 0;      // destination y + e_d
                     const int od = plus ? d + 1 : d - 1;
                     V x = rl[d];
@@ -275,30 +283,32 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
             }
             V sl = mk2<V>(0.0, 0.0);
 #pragma unroll
-            for (int d = 0; d < kQ; ++d) {
-                const R wd = d == 0 ? (R)0.25 : (R)0.125;
+            for (int d = 0; d < NQ; ++d) {
+                const R wd = d == 0 ? (R)lattice_w0(NQ) : (R)lattice_w1(NQ);
                 sl.x += wd * lh[d].x;
                 sl.y += wd * lh[d].y;
             }
             __builtin_amdgcn_sched_barrier(0);
 
             // ---- forward state of step k-1 around this node ----
-            V rg[kQ], rown[kQ];
+            V rg[NQ], rown[NQ];
             rg[0] = fwd[pop + sp];
             rg[1] = fwd[o1 + sp];
             rg[2] = fwd[o2 + sp];
-            rg[3] = fwd[o3 + sp];
-            rg[4] = fwd[o4 + sp];
-            rg[5] = c_rg5;
-            rg[6] = fwd[(fz1 ? o6f : o6i) + sp];
-#pragma unroll
-            for (int d = 1; d < kQ; ++d) {
-                const int od = (d & 1) ? d + 1 : d - 1;
-                if (d != 5) rown[d] = fwd[pop + od * ps + sp];
+            if constexpr (NQ == 7) {
+                rg[3] = fwd[o3 + sp];
+                rg[4] = fwd[o4 + sp];
             }
-            rown[5] = c_ro5;
-            c_rg5 = rown[6];
-            c_ro5 = rg[6];
+            rg[pz] = c_rg5;
+            rg[pz + 1] = fwd[(fz1 ? o6f : o6i) + sp];
+#pragma unroll
+            for (int d = 1; d < NQ; ++d) {
+                const int od = (d & 1) ? d + 1 : d - 1;
+                if (d != pz) rown[d] = fwd[pop + od * ps + sp];
+            }
+            rown[pz] = c_ro5;
+            c_rg5 = rown[pz + 1];
+            c_ro5 = rg[pz + 1];
             const double2 ezd = tabp[n0 + n1 + j2];
             const R dec = c_dec[p];
             const R w = c_w[p];
@@ -311,8 +321,8 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
             V M = mk2<V>(0.0, 0.0);
             R glg = 0, gdec = 0, gim = 0;
 #pragma unroll
-            for (int d = 0; d < kQ; ++d) {
-                const int ax = d > 0 ? (d - 1) >> 1 : 0;
+            for (int d = 0; d < NQ; ++d) {
+                const int ax = d > 0 ? axis_of(d) : 0;
                 const bool plus = (d & 1) != 0;
                 const bool face = d > 0 && (plus ? flo[ax] : fhi[ax]);
                 const int f = 2 * ax + (plus ? 0 : 1);
@@ -421,16 +431,16 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
         a.gpart[((int64_t)a.slot * gridDim.x + lb) * NG + threadIdx.x] = red[threadIdx.x];
 }
 
-template <typename V, int TX, bool GG>
+template <typename V, int TX, bool GG, int NQ>
 __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
-    adj_body<V, TX, GG>(a);
+    adj_body<V, TX, GG, NQ>(a);
 }
 // FP32 storage: held to 128 VGPRs (four waves per SIMD), which it fits
 // without spilling
-template <typename V, int TX, bool GG>
+template <typename V, int TX, bool GG, int NQ>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_adj_w4(AdjArgs a) {
-    adj_body<V, TX, GG>(a);
+    adj_body<V, TX, GG, NQ>(a);
 }
 
 // One thread per (step slot, field, accumulator): the field's workgroup sums
@@ -465,7 +475,8 @@ __global__ void k_adj_final(const double* gfield, int32_t K, int32_t n_fields, i
                             double dt, double dx, const double* w, const double* T2,
                             const double* kappa, double* dD, double* dT2, double* dkappa,
                             double* df, int32_t sub, int32_t NG, const double* gmeta,
-                            const double* fdt, const double* Fk, int32_t Q, double* dgG0) {
+                            const double* fdt, const double* Fk, int32_t Q, double* dgG0,
+                            double eps, int32_t yz_swap) {
     const int t = threadIdx.x;
     auto total = [&](int g) {
         double s = 0.0;
@@ -476,7 +487,7 @@ __global__ void k_adj_final(const double* gfield, int32_t K, int32_t n_fields, i
     if (t < P) {
         if (dD) {
             const double wp = w[t];
-            dD[t] = total(t) * (-wp * wp * dt / (0.25 * dx * dx));
+            dD[t] = total(t) * (-wp * wp * dt / (eps * dx * dx));
         }
         if (dT2) {
             const double T = T2[t];
@@ -491,9 +502,9 @@ __global__ void k_adj_final(const double* gfield, int32_t K, int32_t n_fields, i
         // pair's derivative equally, so that they sum to dL/dkappa_pair
         double g = total(2 * P + i * P + j);
         if (i != j) g = 0.5 * (g + total(2 * P + j * P + i));
-        // t = 8 k dt / (dx + 8 k dt) for eps_D = 1/4
-        const double den = dx + 8.0 * k * dt;
-        dkappa[t] = isinf(k) ? 0.0 : g * 8.0 * dt * dx / (den * den);
+        // t = 2 k dt / (eps_D dx + 2 k dt)
+        const double den = eps * dx + 2.0 * k * dt;
+        dkappa[t] = isinf(k) ? 0.0 : g * 2.0 * dt * eps * dx / (den * den);
     }
     if (t == 0 && df) {
         const int IF = 2 * P + P * P, IFF = IF + 1;
@@ -526,31 +537,40 @@ __global__ void k_adj_final(const double* gfield, int32_t K, int32_t n_fields, i
                     acc += fdt[k] * dx * (sb * r[IR + b] - sgb * r[IR + 3]) + Fk[k] * xs;
                 }
             }
-            dgG0[i] = acc;
+            // kernel axes back to the geometry's: the single-layer lattice
+            // runs with the geometry's y axis as the kernel's z axis
+            // (its z component is not a parameter there: the layer has no
+            // extent along z, and the input must be 0; reported as 0)
+            const int bg = yz_swap ? (b == 1 ? 2 : b == 2 ? 1 : 0) : b;
+            dgG0[3 * q + bg] = (yz_swap && bg == 2) ? 0.0 : acc;
         }
     }
 }
 
-template <typename V, int TX>
+template <typename V, int TX, int NQ>
 static void launch_adj_tx(const AdjArgs& a, int32_t n_blocks, hipStream_t st) {
     // the gamma G0 sensitivities take their own instantiation (more
     // accumulators); FP32 without them is held to four waves per SIMD
     if (a.gradg)
-        hipLaunchKernelGGL((k_adj<V, TX, true>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((k_adj<V, TX, true, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
     else if constexpr (std::is_same<V, float2>::value)
-        hipLaunchKernelGGL((k_adj_w4<V, TX, false>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((k_adj_w4<V, TX, false, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
     else
-        hipLaunchKernelGGL((k_adj<V, TX, false>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((k_adj<V, TX, false, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
 }
 
 template <typename V>
 static void launch_adj_t(int shape, const AdjArgs& a, int32_t n_blocks, hipStream_t st) {
+    if (a.nq == 5) {   // single layer: y rows walked as columns, 256 x 1 tiles
+        launch_adj_tx<V, 256, 5>(a, n_blocks, st);
+        return;
+    }
     switch (shape) {
-        case kTile64x4: launch_adj_tx<V, 64>(a, n_blocks, st); break;
-        case kTile32x8: launch_adj_tx<V, 32>(a, n_blocks, st); break;
-        case kTile128x2: launch_adj_tx<V, 128>(a, n_blocks, st); break;
-        case kTileRows: launch_adj_tx<V, 0>(a, n_blocks, st); break;
-        default: launch_adj_tx<V, 16>(a, n_blocks, st); break;
+        case kTile64x4: launch_adj_tx<V, 64, 7>(a, n_blocks, st); break;
+        case kTile32x8: launch_adj_tx<V, 32, 7>(a, n_blocks, st); break;
+        case kTile128x2: launch_adj_tx<V, 128, 7>(a, n_blocks, st); break;
+        case kTileRows: launch_adj_tx<V, 0, 7>(a, n_blocks, st); break;
+        default: launch_adj_tx<V, 16, 7>(a, n_blocks, st); break;
     }
 }
 
@@ -578,9 +598,10 @@ hipError_t launch_adj_final(const double* gfield, int32_t K, int32_t n_fields, i
                             const double* kappa, double* dD, double* dT2, double* dkappa,
                             double* df, int32_t sub, int32_t ng, const double* gmeta,
                             const double* fdt, const double* Fk, int32_t Q, double* dgG0,
-                            hipStream_t st) {
+                            double eps, int32_t yz_swap, hipStream_t st) {
     hipLaunchKernelGGL(k_adj_final, dim3(1), dim3(64), 0, st, gfield, K, n_fields, P, dt, dx,
-                       w, T2, kappa, dD, dT2, dkappa, df, sub, ng, gmeta, fdt, Fk, Q, dgG0);
+                       w, T2, kappa, dD, dT2, dkappa, df, sub, ng, gmeta, fdt, Fk, Q, dgG0,
+                       eps, yz_swap);
     return hipGetLastError();
 }
 

@@ -91,6 +91,7 @@ struct AdjArgs {
     int32_t xcd;            // 1: XCD-contiguous workgroup order (xcd_tile)
     int32_t slot;           // slot of this step in gpart (k - 1 - first step of the segment)
     int32_t gradg;          // 1: also the gamma G0 sensitivities (ng includes kNGGrad)
+    int32_t nq;             // 7 (D3Q7) or 5 (D2Q5 on a single layer)
 };
 
 struct StepArgs {
@@ -173,7 +174,7 @@ hipError_t launch_adj_final(const double* gfield, int32_t K, int32_t n_fields, i
                             const double* kappa, double* dD, double* dT2, double* dkappa,
                             double* df, int32_t sub, int32_t ng, const double* gmeta,
                             const double* fdt, const double* Fk, int32_t Q, double* dgG0,
-                            hipStream_t st);
+                            double eps, int32_t yz_swap, hipStream_t st);
 hipError_t launch_init(int prec, void* pop, int64_t n_elem_per_dir_total,
                        const FieldDesc* d_fields, int32_t n_fields,
                        const FieldDesc* h_fields, double* E, int32_t Q, int32_t K, int32_t nq,

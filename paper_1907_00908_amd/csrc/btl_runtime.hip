@@ -119,6 +119,7 @@ struct btl_sim {
         bool valid = false;
         int32_t K = 0, C = 0, Q = 0, T = 0, n_fields = 0, nblk = 0, shape = 0, sub = 1, xcd = 0;
         int32_t nblk_adj = 0;      // workgroups of one adjoint step (adj_fields)
+        int32_t nq = 7;            // lattice of the taped forward
         bool g_ok = false;         // the field set supports the gamma G0 gradient
         double dt = 0;
         int64_t state_elems = 0;   // V elements of one full state (all fields)
@@ -366,13 +367,16 @@ struct QFields {
 // full: the set a gradient with respect to gamma G0 needs, valid for every
 // nearby G and not only for this one: every mirrored axis counts as carrying
 // a component, and the conjugate pairing is kept only when every axis is
-// mirrored (a periodic axis with a zero component would break it).
+// mirrored (a periodic axis with a zero component would break it).  An axis
+// one site long (the single layer of the D2Q5 lattice) has no links and no
+// gradient component, and does not count.
 static QFields plan_fields(const GeomHost& g, const double* G, bool classical, bool full = false) {
     QFields r;
     bool all_mirrored = true;
     int astar = -1;
     for (int a = 0; a < 3; ++a) {
         if (full) {
+            if (g.n[a] == 1) continue;   // no links along it (the single layer)
             if (g.bc[a] == BTL_MIRROR) {
                 r.amask |= 1 << a;
                 if (astar < 0) astar = a;
@@ -782,7 +786,6 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     if (ckpt_every > 0 && K > 0) {
         if (P > kAdjMaxPhase) return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports n_phase <= 4");
         if (classical) return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports the hybrid scheme only");
-        if (nq != 7) return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports the D3Q7 lattice only");
         if (uses_gm)
             return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports the half-link membrane rule only");
         const int32_t C = std::min(ckpt_every, K);
@@ -802,6 +805,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         s->tape.sub = msub;
         s->tape.xcd = xcd_on;
         s->tape.state_elems = pop_elems;
+        s->tape.nq = nq;
     }
     // Everything a forward enqueues after the uploads: init, one table
     // launch per kTabSteps steps, one step launch per step, checkpoint
@@ -1046,7 +1050,7 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
     fa.K = K;
     fa.tab_field = s->tab_field.p;
     fa.T = T;
-    fa.nq = 7;
+    fa.nq = tp.nq;
     fa.xcd = tp.xcd;
 
     AdjArgs aa;
@@ -1065,6 +1069,7 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
     aa.K = K;
     aa.ng = NG;
     aa.gradg = dgG0 ? 1 : 0;
+    aa.nq = tp.nq;
 
     const int32_t nseg = (K + C - 1) / C;
     int lam_cur = 0;      // buffer holding Lambda^k on entry to adjoint step k
@@ -1109,7 +1114,8 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
     if ((e = launch_adj_final(s->gfield.p, K, nf, P, tp.dt, s->dx, s->consts.p,
                               s->consts.p + 2 * P + P * P, s->consts.p + 3 * P + P * P, dD, dT2,
                               dkappa, df, tp.sub, NG, s->adj_gmeta.p, s->steps.p,
-                              s->steps.p + K, tp.Q, dgG0, st)) != hipSuccess)
+                              s->steps.p + K, tp.Q, dgG0, lattice_eps(tp.nq),
+                              tp.nq == 5 ? 1 : 0, st)) != hipSuccess)
         return hip_fail(s, e, "adjoint final launch");
     return BTL_OK;
 }

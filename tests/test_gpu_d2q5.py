@@ -84,9 +84,6 @@ def test_d2q5_ragged_batch_and_errors():
             sim.forward(*args, np.array([[1.0, 0.0, 0.5]]))
         assert ei.value.status == btl.BTL_E_INVAL
         with pytest.raises(btl.BtlError) as ei:
-            sim.forward(*args, gG[:1], ckpt_every=5)
-        assert ei.value.status == btl.BTL_E_UNSUPPORTED
-        with pytest.raises(btl.BtlError) as ei:
             btl.btl_set_lattice(sim._h, 3)
         assert ei.value.status == btl.BTL_E_INVAL
     finally:
@@ -99,3 +96,60 @@ def test_d2q5_ragged_batch_and_errors():
         assert ei.value.status == btl.BTL_E_INVAL
     finally:
         sim.close()
+
+
+def _loss_fd(cfg, a, b, which, idx, h):
+    vals = []
+    for sgn in (1, -1):
+        c = dict(cfg)
+        arr = np.array(cfg[which], float).copy()
+        arr[idx] += sgn * h
+        if which == "kappa":
+            arr[idx[::-1]] = arr[idx]
+        c[which] = arr
+        E, _ = oracle.simulate_config(c, threads=8)
+        vals.append(float(np.sum(a * E.real + b * E.imag)))
+    return (vals[0] - vals[1]) / (2 * h)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-6), ("f32", 1e-3)])
+@pytest.mark.parametrize("bc", [[0, 0, 0], [1, 1, 1]])
+def test_d2q5_adjoint_vs_oracle_fd(prec, tol, bc):
+    # the adjoint on the D2Q5 lattice (eps_D = 1/3 in tau and in the
+    # membrane number), gradients of D, T2, kappa, f and gamma G0 (x, y)
+    import torch
+    btl = _gpu()
+    g = w.cylinders_z((18, 15, 1), 0.25, seed=93, vf_target=0.5, periodic=bc[0] == 0)
+    f = w.pgse_waveform(0.12, 0.36, 0.004)
+    gG = np.array([[7.0, 4.0, 0.0], [0.0, 6.0, 0.0]])
+    cfg = dict(name="d2q5-adj", geoms=[g], bc=bc, dx=0.25, dt=0.004,
+               D=np.array([2.0, 1.0]), T2=np.array([60.0, 40.0]),
+               kappa=np.array([[INF, 0.05], [0.05, INF]]), f=f, gG0=gG,
+               q_geom=np.zeros(len(gG), np.int32), lattice=D2Q5)
+    Q, K = len(gG), len(f)
+    r = np.random.default_rng(11)
+    a, b = r.normal(size=(Q, K + 1)), r.normal(size=(Q, K + 1))
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], prec, lattice=D2Q5, grad_gG0=True)
+    try:
+        E = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], f, gG, cfg["q_geom"],
+                        ckpt_every=25)
+        gt = torch.tensor(np.stack([a, b], axis=-1), dtype=torch.float64, device=E.device)
+        dD, dT2, dk, df, dG = [t.cpu().numpy() for t in sim.backward(gt, 2, K, grad_gG0=True)]
+    finally:
+        sim.close()
+    checks = [("D", 0, dD[0], 1e-5), ("D", 1, dD[1], 1e-5), ("T2", 0, dT2[0], 1e-3),
+              ("kappa", (0, 1), dk[0, 1] + dk[1, 0], 1e-6), ("f", 10, df[10], 1e-4),
+              ("f", 70, df[70], 1e-4), ("gG0", (0, 0), dG[0, 0], 2e-4),
+              ("gG0", (0, 1), dG[0, 1], 2e-4), ("gG0", (1, 1), dG[1, 1], 2e-4),
+              ("gG0", (1, 0), dG[1, 0], 2e-4)]
+    rows, scale = [], {}
+    for which, idx, gval, h in checks:
+        fd = _loss_fd(cfg, a, b, which, idx, h)
+        rows.append((which, idx, gval, fd))
+        scale[which] = max(scale.get(which, 0.0), abs(fd))
+    for which, idx, gval, fd in rows:
+        err = abs(gval - fd) / max(scale[which], 1e-30)
+        print(f"D2Q5 {prec} bc={bc} {which}{idx}: adjoint {gval:.9e} fd {fd:.9e} rel {err:.2e}",
+              flush=True)
+        assert err <= tol, (which, idx, gval, fd)
+    assert dG[0, 2] == 0.0 and dG[1, 2] == 0.0
