@@ -184,7 +184,9 @@ def bench_adjoint(btl, torch, sim, cfg, args, fwd_ms_step, fs, qs, Q):
     nseg = (Kb + C - 1) // C
     recompute_ms = (Kb - nseg) * fwd_ms_step
     adj_ms = max(ms - recompute_ms, 1e-9) / Kb
-    bpf = 168 if args.prec == "f32" else 336
+    # read the adjoint and the forward state, write the adjoint: 3 x nq complex
+    nq = 5 if cfg.get("lattice", 0) == 1 else 7
+    bpf = (168 if args.prec == "f32" else 336) * nq // 7
     ach = fs * bpf / (adj_ms * 1e-3) / 1e9
     finite = bool(torch.isfinite(dD).all() and torch.isfinite(df).all())
     return {"value": qs * Kb / (ms * 1e-3), "unit": "site-updates/s",
@@ -257,8 +259,8 @@ def main():
 
     K, W = args.steps, args.warmup
     log(f"building workload {args.workload}")
-    if args.membranes == "positions" or args.workload == "cfg2d" or args.scheme != "hybrid":
-        args.no_adjoint = True          # the adjoint covers D3Q7 hybrid half-link runs
+    if args.membranes == "positions" or args.scheme != "hybrid":
+        args.no_adjoint = True          # the adjoint covers hybrid half-link runs
     scheme = 0 if args.scheme == "hybrid" else 1
     cfg = workload(args.workload, max(K, W, 0 if args.no_adjoint else args.adj_steps),
                    args.membranes)
@@ -322,7 +324,7 @@ def main():
                                         "speedup_of_value": value / v1}
         out["fp64_batched"] = {"value": qs * K / (ms64 * 1e-3)}
         sim64.close()
-    state_gb = fs * (8 if args.prec == "f32" else 16) * 7 / 1e9
+    state_gb = fs * (8 if args.prec == "f32" else 16) * (5 if cfg.get("lattice", 0) == 1 else 7) / 1e9
     adj_states = min(args.adj_steps, K) / args.adj_ckpt + args.adj_ckpt + 4
     if not args.no_adjoint and state_gb * adj_states > 120.0:
         out["adjoint"] = {"skipped": f"tape would need {state_gb * adj_states:.0f} GB"}

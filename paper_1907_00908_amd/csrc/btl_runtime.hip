@@ -666,8 +666,9 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     for (int i = 0; i < n_fields; ++i)
         for (int b = 0; b < fl[i].nblk; ++b) blk[fl[i].blk0 + b] = i;
     // With a tape, the launch geometry of the adjoint steps: the same tile
-    // shape, whole z columns when all workgroups are resident at once,
-    // otherwise columns cut so that the grid runs in about eight rounds
+    // shape, whole z columns when all workgroups are resident at once (cut
+    // into as many pieces as still fit at once when that leaves SIMDs with
+    // room), otherwise columns cut so that the grid runs in about eight rounds
     // (BTLBM_ADJ_ZC sets the length).  The adjoint carries four values along
     // the column and loads in two phases per site; on the benchmark workload
     // it measured faster on whole columns than on the short chunks the
@@ -692,6 +693,12 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
             if (whole > cap) {
                 const int64_t split = (8 * cap + whole - 1) / whole;
                 zc_adj = std::max<int>(8, (int)((nz + split - 1) / split));
+            } else if (2 * whole <= cap) {
+                // cut the columns so that the grid still fits at once but
+                // fills the SIMDs (512 whole-column workgroups would leave
+                // two waves per SIMD)
+                const int64_t split = cap / whole;
+                zc_adj = (int)((nz + split - 1) / split);
             }
         }
         afl = fl;
