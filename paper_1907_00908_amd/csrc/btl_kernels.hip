@@ -13,16 +13,17 @@
 //        ghat_ibar(x)) with t = 1/(1+P), P = eps_D dx/(2 kappa dt)
 //        (half-link condition, Eqs. B5, P_def, permeability_BC)
 //   2. g_i = g'_i exp(-i gamma (x.G0) f_k dt) exp(-dt/T2)   (Eq. reaction_LBM)
-//   3. M = sum_i g_i; the workgroup adds M into the signal partial sum
+//   3. M = sum_i g_i; each wave adds M into its signal partial sum
 //      (Eq. M'summation; signal Sec. 2.1)
 //   4. ghat_i = g_i + w (w_i M - g_i), w = 1/tau       (Eq. collision_LBM)
 // which is the paper's collide -> stream -> react cycle (Eq.
 // LBM_process_list_2) started at the stream.  The classical LBM of Appendix A
-// (Eq. A12) shares steps 1 and 3 and moves the reaction into step 4.  All arithmetic is FP64;
-// populations are stored as float2 or double2, per field z-major:
-// [z][direction][y][x] (the seven planes of one z layer lie together, so the
-// tiles that run at the same time read and write one compact region).  Per-step constants enter only through forms that
-// keep sum_i g_i exact for any rounded constant (g + w(wM - g), a + t(b - a)).
+// (Eq. A12) shares steps 1 and 3 and moves the reaction into step 4.  All
+// arithmetic is FP64; populations are stored as float2 or double2, per field
+// z-major: [z][direction][y][x] (the seven planes of one z layer lie
+// together, so the tiles that run at the same time read and write one
+// compact region).  Per-step constants enter only through forms that keep
+// sum_i g_i exact for any rounded constant (g + w(wM - g), a + t(b - a)).
 //
 // With membrane positions given, a membrane link whose six-node stencil lies
 // inside the field takes the general condition for a straight membrane at
@@ -71,9 +72,10 @@ __global__ void __launch_bounds__(kBlock) k_tables(StepArgs a, int32_t nsteps) {
     a.tab[i] = table_entry(a, e, a.k + ks);
 }
 
-// One step for a tile of TX x TY site columns, each thread walking fd.zc
-// sites along z.  Workgroup -> (field, tile) via blk_field and the field's
-// tile counts; no per-site integer division.
+// One step for a tile of TX x TY site columns (TX = 0: a run of kBlock
+// consecutive sites of the x-y plane), each thread walking fd.zc sites along
+// z.  Workgroup -> (field, tile) via blk_field and the field's tile counts;
+// no per-site integer division.
 //
 // CL = true runs the classical LBM (Appendix A, Eq. A12) with the same
 // streaming: step 2 is skipped and step 4 adds dt w_i R M with
