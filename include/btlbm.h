@@ -199,8 +199,10 @@ btl_status btl_set_scheme(btl_sim *s, int32_t scheme);
 /* Choose the launch shape (workgroup tile and z-column length) of this
  * simulator by timing every candidate on the inputs of the last btl_forward
  * (its first Q q-samples, K_probe steps, waveform repeated if shorter) and
- * keeping the fastest.  Synchronizes the stream.  Without autotuning a
- * shape with the fewest idle lanes and whole z columns is used.
+ * keeping the fastest.  Synchronizes the stream.  The probes are forwards
+ * of their own: the adjoint tape of an earlier taped btl_forward is
+ * discarded.  Without autotuning a shape with the fewest idle lanes and
+ * whole z columns is used.
  * Errors: BTL_E_INVAL (no previous forward, K_probe < 1), BTL_E_NOMEM,
  * BTL_E_HIP. */
 btl_status btl_autotune(btl_sim *s, int32_t Q, int32_t K_probe, void *stream);

@@ -142,6 +142,8 @@ def btl_forward(h, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E_ptr, M_ptr,
     q_geom = np.ascontiguousarray(q_geom, np.int32)
     gG0 = np.ascontiguousarray(gG0, np.float64).reshape(-1)
     f = np.ascontiguousarray(f, np.float64)
+    if q_geom.size < int(Q) or gG0.size < 3 * int(Q):
+        raise ValueError("q_geom needs Q entries and gG0 Q x 3")
     st = lib.btl_forward(h, float(dt), int(K), _np_ptr(D), _np_ptr(T2), _np_ptr(kappa),
                          int(Q), _np_ptr(q_geom), _np_ptr(gG0), _np_ptr(f),
                          ctypes.c_void_p(E_ptr), ctypes.c_void_p(M_ptr) if M_ptr else None,
@@ -246,6 +248,11 @@ class Simulator:
         gG0 = np.ascontiguousarray(gG0, np.float64).reshape(-1, 3)
         Q = gG0.shape[0]
         q_geom = np.zeros(Q, np.int32) if q_geom is None else np.asarray(q_geom, np.int32)
+        P = self.geoms[0].n_phase
+        if q_geom.shape != (Q,):
+            raise ValueError("q_geom needs one geometry index per q-sample")
+        if np.size(D) != P or np.size(T2) != P or np.size(kappa) != P * P:
+            raise ValueError("D and T2 need n_phase values, kappa n_phase x n_phase")
         if len(f) % self.substeps:
             raise ValueError("len(f) must be a multiple of the reaction sub-steps")
         K = len(f) // self.substeps

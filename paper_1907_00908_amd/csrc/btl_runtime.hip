@@ -59,8 +59,37 @@ constexpr int kXcdMinBlocks = 2048;  // grids above this use the XCD-contiguous 
 // buffers; a forward replays the cached graph only when this matches.
 struct GraphKey {
     int32_t prec, K, Q, n_fields, nblk, shape, T, ckpt, scheme, nq, xcd;
+    uint64_t fields;     // hash of the per-field values the launches take by value
     const void* ptr[16];
 };
+
+// FNV-1a over the field-table entries that the captured launches take as
+// kernel arguments rather than read from the device table: the init
+// launches' range, plane stride and q-sample of every field, the geometry
+// (site words, membrane positions) behind it, and for the classical scheme
+// the gradient terms of its initial reaction.  Two calls that agree in
+// every other key entry but differ here (a permuted ragged batch, another
+// gradient under the classical scheme) must not share a graph.
+uint64_t field_hash(const std::vector<FieldDesc>& fl, bool classical) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](const void* p, size_t n) {
+        const unsigned char* b = static_cast<const unsigned char*>(p);
+        for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    };
+    for (const FieldDesc& d : fl) {
+        mix(&d.pop, sizeof(d.pop));
+        mix(&d.words, sizeof(d.words));
+        mix(&d.gm, sizeof(d.gm));
+        mix(d.n, sizeof(d.n));
+        mix(&d.nsites, sizeof(d.nsites));
+        mix(&d.q, sizeof(d.q));
+        if (classical) {
+            mix(d.c, sizeof(d.c));
+            mix(&d.cu, sizeof(d.cu));
+        }
+    }
+    return h;
+}
 
 }  // namespace
 
@@ -427,6 +456,12 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     const int32_t msub = s->substeps;
     const int32_t nq = s->nq;
     const double eps = lattice_eps(nq);
+    for (int q = 0; q < Q; ++q) {
+        if (q_geom[q] < 0 || q_geom[q] >= (int)s->geoms.size())
+            return fail(s, BTL_E_INVAL, "q_geom out of range");
+        for (int a = 0; a < 3; ++a)
+            if (!isfinite(gG0[3 * q + a])) return fail(s, BTL_E_INVAL, "gG0 must be finite");
+    }
     if (nq == 5)
         for (int q = 0; q < Q; ++q)
             if (s->geoms[q_geom[q]].n[2] != 1 || gG0[3 * q + 2] != 0.0)
@@ -436,12 +471,6 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         return fail(s, BTL_E_UNSUPPORTED, "reaction sub-steps need the hybrid scheme");
     for (int64_t k = 0; k < (int64_t)K * msub; ++k)
         if (!isfinite(f[k])) return fail(s, BTL_E_INVAL, "f must be finite");
-    for (int q = 0; q < Q; ++q) {
-        if (q_geom[q] < 0 || q_geom[q] >= (int)s->geoms.size())
-            return fail(s, BTL_E_INVAL, "q_geom out of range");
-        for (int a = 0; a < 3; ++a)
-            if (!isfinite(gG0[3 * q + a])) return fail(s, BTL_E_INVAL, "gG0 must be finite");
-    }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const double dx = s->dx;
 
@@ -903,6 +932,7 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         key.scheme = s->scheme;
         key.nq = nq;
         key.xcd = xcd_on;
+        key.fields = field_hash(fl, classical);
         const void* ptrs[] = {s->pop[0].p, s->pop[1].p, s->fields.p, s->blk_field.p, s->steps.p,
                               s->consts.p, s->partial.p, s->tab.p, s->tab_field.p,
                               s->E_int.p, s->ckpt.p, s->words.p};

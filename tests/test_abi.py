@@ -46,3 +46,17 @@ def test_create_rejects_bad_geometry_without_touching_the_gpu():
         assert "dx" in str(e)
     else:
         raise AssertionError("negative dx accepted")
+
+
+def test_binding_refuses_short_q_arrays_before_the_call():
+    # the C side reads Q geometry indices and Q x 3 gradients through plain
+    # pointers; the binding checks the arrays cover them
+    import numpy as np
+    import pytest
+    inf = float("inf")
+    with pytest.raises(ValueError):
+        btl.btl_forward(None, 0.01, 1, [1.0], [1.0], [[inf]], 2, [0], np.zeros(6),
+                        np.zeros(1), 0, 0, 0, 0)
+    with pytest.raises(ValueError):
+        btl.btl_forward(None, 0.01, 1, [1.0], [1.0], [[inf]], 2, [0, 0], np.zeros(3),
+                        np.zeros(1), 0, 0, 0, 0)

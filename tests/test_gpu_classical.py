@@ -113,6 +113,17 @@ def test_classical_K0_K1_and_graph_replay():
             del os.environ["BTLBM_NO_GRAPH"]
         for r in reps:
             assert np.array_equal(r, eager)
+        # the classical initial state depends on the gradient: another
+        # gradient of the same shape must not replay the cached graph's init
+        gG2 = np.asarray(cfg["gG0"]) * 1.7
+        Eg2 = sim.forward(*args, f, gG2).cpu().numpy()
+        os.environ["BTLBM_NO_GRAPH"] = "1"
+        try:
+            eager2 = sim.forward(*args, f, gG2).cpu().numpy()
+        finally:
+            del os.environ["BTLBM_NO_GRAPH"]
+        assert np.array_equal(Eg2, eager2)
+        assert not np.array_equal(Eg2, eager)
         # switching back to the hybrid scheme reproduces a fresh hybrid run
         btl.btl_set_scheme(sim._h, btl.BTL_HYBRID)
         Eh = sim.forward(*args, f, cfg["gG0"]).cpu().numpy()

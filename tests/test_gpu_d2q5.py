@@ -86,6 +86,12 @@ def test_d2q5_ragged_batch_and_errors():
         with pytest.raises(btl.BtlError) as ei:
             btl.btl_set_lattice(sim._h, 3)
         assert ei.value.status == btl.BTL_E_INVAL
+        # a geometry index out of range is refused before the D2Q5 checks
+        # read the geometry it names
+        with pytest.raises(btl.BtlError) as ei:
+            sim.forward(*args, np.array([[1.0, 0.0, 0.0]]), q_geom=[7])
+        assert ei.value.status == btl.BTL_E_INVAL
+        assert "q_geom" in str(ei.value)
     finally:
         sim.close()
     g3 = w.uniform((6, 5, 4), 0.5)

@@ -264,6 +264,32 @@ def test_graph_replays_match_eager(monkeypatch):
         sim.close()
 
 
+def test_graph_key_tracks_field_layout(monkeypatch):
+    # a cached forward graph takes each field's range, plane stride and
+    # q-sample as launch arguments: the same two geometries batched in the
+    # other order have the same sizes and must still not replay it
+    btl = _gpu()
+    geoms = [w.cylinders_z((11, 9, 6), 0.25, seed=71, vf_target=0.5),
+             w.cylinders_z((9, 12, 7), 0.25, seed=72, vf_target=0.5)]
+    f = w.pgse_waveform(0.12, 0.3, 0.004)
+    gG = np.array([[8.0, 2.0, 0.0], [-5.0, 0.0, 3.0]])
+    args = (0.004, np.array([2.0, 1.0]), np.array([40.0, 25.0]),
+            np.array([[INF, 0.05], [0.05, INF]]))
+    sim = btl.Simulator(geoms, [0, 0, 0], "f32")
+    try:
+        seen = []
+        for qg in ([0, 1], [1, 0]):
+            Eg = sim.forward(*args, f, gG, qg).cpu().numpy()
+            monkeypatch.setenv("BTLBM_NO_GRAPH", "1")
+            Ee = sim.forward(*args, f, gG, qg).cpu().numpy()
+            monkeypatch.delenv("BTLBM_NO_GRAPH")
+            assert np.array_equal(Eg, Ee), qg
+            seen.append(Eg)
+        assert not np.array_equal(seen[0], seen[1])
+    finally:
+        sim.close()
+
+
 def test_invalid_arguments_raise():
     btl = _gpu()
     cfg = w.make_config("cfg1", n=4, K=3)
