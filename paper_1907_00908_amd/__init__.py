@@ -223,6 +223,9 @@ class Simulator:
         self.grad_gG0 = bool(grad_gG0)
         if self.grad_gG0:
             btl_set_grad_gG0(self._h, 1)
+        # number of forwards so far, and which of them holds the adjoint tape
+        self._n_forward = 0
+        self.tape_id = None
 
     def set_grad_gG0(self, on: bool):
         """Plan taped forwards for the gamma G0 gradient (btl_set_grad_gG0)."""
@@ -264,8 +267,12 @@ class Simulator:
             dt_ = torch.float32 if self.prec == BTL_F32 else torch.float64
             M = torch.empty((tot, 2), dtype=dt_, device=dev)
         stream = torch.cuda.current_stream().cuda_stream
+        self.tape_id = None
         btl_forward(self._h, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E.data_ptr(),
                     M.data_ptr() if M is not None else 0, ckpt_every, stream, self.substeps)
+        self._n_forward += 1
+        if ckpt_every > 0 and K > 0:
+            self.tape_id = self._n_forward
         Ec = torch.view_as_complex(E)
         if not want_M:
             return Ec
@@ -330,6 +337,7 @@ def _bt_function():
             gG0 = np.ascontiguousarray(gG0, np.float64).reshape(-1, 3)
             E = sim.forward(dt, Dn, T2n, kn, fn, gG0, q_geom, ckpt_every=max(1, int(ckpt_every)))
             ctx.sim = sim
+            ctx.tape_id = sim.tape_id
             ctx.P = len(Dn)
             ctx.K = len(fn) // sim.substeps
             ctx.devs = (D.device, T2.device, kappa.device, f.device)
@@ -337,6 +345,9 @@ def _bt_function():
 
         @staticmethod
         def backward(ctx, gE):
+            if ctx.sim.tape_id is None or ctx.sim.tape_id != ctx.tape_id:
+                raise RuntimeError("the simulator ran another forward after this one: its "
+                                   "adjoint tape is gone (use one Simulator per pending backward)")
             want_g = ctx.gdev is not None and ctx.needs_input_grad[6]
             out = ctx.sim.backward(gE, ctx.P, ctx.K, grad_gG0=want_g)
             dD, dT2, dk, df = out[:4]

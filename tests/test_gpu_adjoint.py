@@ -291,6 +291,15 @@ def test_autograd_function():
         E = btl.bloch_torrey_signal(D, T2, kap, f, sim, cfg["dt"], cfg["gG0"], ckpt_every=25)
         loss = (E[:, -1, 0] ** 2 + E[:, -1, 1] ** 2).sum()
         loss.backward()
+        # a second taped forward on the same simulator replaces the tape: the
+        # first graph's backward is refused, the second's runs
+        E1 = btl.bloch_torrey_signal(D, T2, kap, f, sim, cfg["dt"], cfg["gG0"], ckpt_every=25)
+        E2 = btl.bloch_torrey_signal(D, T2, kap, f, sim, cfg["dt"], cfg["gG0"], ckpt_every=25)
+        with pytest.raises(RuntimeError, match="adjoint tape is gone"):
+            E1[:, -1, 0].sum().backward()
+        g0 = D.grad.clone()
+        E2[:, -1, 0].sum().backward()
+        assert not torch.equal(D.grad, g0)
     finally:
         sim.close()
     assert D.grad.shape == (2,) and torch.isfinite(D.grad).all()
