@@ -471,28 +471,47 @@ __global__ void __launch_bounds__(kBlock) k_adj_gsum(const double* __restrict__ 
 //   dL/df_m   = G_f[m] + dt * sum_{k>m} G_F[k]       (F_k = sum_{m<k} f_m dt)
 // With `sub` reaction sub-steps per step, f_m dt is the sum of `sub`
 // samples times dt/sub, so each sample of step m gets dL/df_m / sub.
-__global__ void k_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P,
-                            double dt, double dx, const double* w, const double* T2,
-                            const double* kappa, double* dD, double* dT2, double* dkappa,
-                            double* df, int32_t sub, int32_t NG, const double* gmeta,
-                            const double* fdt, const double* Fk, int32_t Q, double* dgG0,
-                            double eps, int32_t yz_swap) {
-    const int t = threadIdx.x;
-    auto total = [&](int g) {
-        double s = 0.0;
-        for (int k = 0; k < K; ++k)
-            for (int f = 0; f < n_fields; ++f) s += gfield[((int64_t)k * n_fields + f) * NG + g];
-        return s;
-    };
+// One workgroup: the totals are block sums over (step, field), the suffix
+// sums of G_F a chunked scan (thread t owns a contiguous range of steps),
+// and each gamma G0 component one wave striding over the steps; every sum
+// runs in a fixed order.
+constexpr int kFinalBlock = 1024;
+__global__ void __launch_bounds__(kFinalBlock)
+k_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P, double dt, double dx,
+            const double* w, const double* T2, const double* kappa, double* dD, double* dT2,
+            double* dkappa, double* df, int32_t sub, int32_t NG, const double* gmeta,
+            const double* fdt, const double* Fk, int32_t Q, double* dgG0, double eps,
+            int32_t yz_swap) {
+    constexpr int NW = kFinalBlock / 64;
+    __shared__ double red[NW];
+    __shared__ double tot[2 * kAdjMaxPhase + kAdjMaxPhase * kAdjMaxPhase];
+    __shared__ double scan[kFinalBlock];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t nkf = (int64_t)K * n_fields;
+    // per-phase and per-pair totals over all steps and fields
+    const int NT = 2 * P + P * P;
+    for (int g = 0; g < NT; ++g) {
+        double v = 0.0;
+        for (int64_t i = t; i < nkf; i += kFinalBlock) v += gfield[i * NG + g];
+        v = wave_sum(v);
+        if (lane == 0) red[wv] = v;
+        __syncthreads();
+        if (t == 0) {
+            double sacc = 0.0;
+            for (int i = 0; i < NW; ++i) sacc += red[i];
+            tot[g] = sacc;
+        }
+        __syncthreads();
+    }
     if (t < P) {
         if (dD) {
             const double wp = w[t];
-            dD[t] = total(t) * (-wp * wp * dt / (eps * dx * dx));
+            dD[t] = tot[t] * (-wp * wp * dt / (eps * dx * dx));
         }
         if (dT2) {
             const double T = T2[t];
             const double dec = isinf(T) ? 1.0 : exp(-dt / T);
-            dT2[t] = isinf(T) ? 0.0 : total(P + t) * dec * dt / (T * T);
+            dT2[t] = isinf(T) ? 0.0 : tot[P + t] * dec * dt / (T * T);
         }
     }
     if (t < P * P && dkappa) {
@@ -500,49 +519,64 @@ __global__ void k_adj_final(const double* gfield, int32_t K, int32_t n_fields, i
         const double k = kappa[t];
         // gradient per matrix entry: the two entries of a pair share the
         // pair's derivative equally, so that they sum to dL/dkappa_pair
-        double g = total(2 * P + i * P + j);
-        if (i != j) g = 0.5 * (g + total(2 * P + j * P + i));
+        double g = tot[2 * P + i * P + j];
+        if (i != j) g = 0.5 * (g + tot[2 * P + j * P + i]);
         // t = 2 k dt / (eps_D dx + 2 k dt)
         const double den = eps * dx + 2.0 * k * dt;
         dkappa[t] = isinf(k) ? 0.0 : g * 2.0 * dt * eps * dx / (den * den);
     }
-    if (t == 0 && df) {
+    if (df) {   // the same for every thread: the barriers below are uniform
         const int IF = 2 * P + P * P, IFF = IF + 1;
-        double suffix = 0.0;   // sum_{k > m} G_F[k]
-        for (int m = K - 1; m >= 0; --m) {
-            double gf = 0.0;
-            for (int f = 0; f < n_fields; ++f) gf += gfield[((int64_t)m * n_fields + f) * NG + IF];
-            const double v = (gf + dt * suffix) / sub;
+        auto field_sum = [&](int32_t m, int idx) {
+            double v = 0.0;
+            for (int f = 0; f < n_fields; ++f) v += gfield[((int64_t)m * n_fields + f) * NG + idx];
+            return v;
+        };
+        const int32_t chunk = (K + kFinalBlock - 1) / kFinalBlock;
+        const int32_t m0 = min(K, t * chunk), m1 = min(K, m0 + chunk);
+        double cF = 0.0;
+        for (int32_t m = m0; m < m1; ++m) cF += field_sum(m, IFF);
+        scan[t] = cF;
+        __syncthreads();
+        // scan[t] becomes the sum of the chunks t .. end
+        for (int off = 1; off < kFinalBlock; off <<= 1) {
+            const double v = t + off < kFinalBlock ? scan[t + off] : 0.0;
+            __syncthreads();
+            scan[t] += v;
+            __syncthreads();
+        }
+        double suffix = t + 1 < kFinalBlock ? scan[t + 1] : 0.0;   // sum_{k >= m1} G_F[k]
+        for (int32_t m = m1 - 1; m >= m0; --m) {
+            const double v = (field_sum(m, IF) + dt * suffix) / sub;
             for (int j = 0; j < sub; ++j) df[(int64_t)m * sub + j] = v;
-            double gF = 0.0;
-            for (int f = 0; f < n_fields; ++f) gF += gfield[((int64_t)m * n_fields + f) * NG + IFF];
-            suffix += gF;
+            suffix += field_sum(m, IFF);
         }
     }
     // dL/d(gamma G0)_b of q-sample q, summed over its fields and the steps:
     //   fdt_k dx (s_b R_b - sigma_b R_0) + F_k sum_f (d beta_f / d G_b) X_f
     if (dgG0) {
         const int IR = 2 * P + P * P + 2, IX = IR + 4;
-        for (int i = t; i < 3 * Q; i += blockDim.x) {
+        for (int i = wv; i < 3 * Q; i += NW) {
             const int q = i / 3, b = i % 3;
             double acc = 0.0;
             for (int f = 0; f < n_fields; ++f) {
                 const double* gm = gmeta + (int64_t)f * kGMeta;
                 if ((int)gm[0] != q) continue;
                 const double sb = gm[1 + b], sgb = gm[4 + b];
-                for (int k = 0; k < K; ++k) {
+                for (int32_t k = lane; k < K; k += 64) {
                     const double* r = gfield + ((int64_t)k * n_fields + f) * NG;
                     double xs = 0.0;
                     for (int fc = 0; fc < 6; ++fc) xs += gm[7 + 3 * fc + b] * r[IX + fc];
                     acc += fdt[k] * dx * (sb * r[IR + b] - sgb * r[IR + 3]) + Fk[k] * xs;
                 }
             }
+            acc = wave_sum(acc);
             // kernel axes back to the geometry's: the single-layer lattice
             // runs with the geometry's y axis as the kernel's z axis
             // (its z component is not a parameter there: the layer has no
             // extent along z, and the input must be 0; reported as 0)
             const int bg = yz_swap ? (b == 1 ? 2 : b == 2 ? 1 : 0) : b;
-            dgG0[3 * q + bg] = (yz_swap && bg == 2) ? 0.0 : acc;
+            if (lane == 0) dgG0[3 * q + bg] = (yz_swap && bg == 2) ? 0.0 : acc;
         }
     }
 }
@@ -599,7 +633,7 @@ hipError_t launch_adj_final(const double* gfield, int32_t K, int32_t n_fields, i
                             double* df, int32_t sub, int32_t ng, const double* gmeta,
                             const double* fdt, const double* Fk, int32_t Q, double* dgG0,
                             double eps, int32_t yz_swap, hipStream_t st) {
-    hipLaunchKernelGGL(k_adj_final, dim3(1), dim3(64), 0, st, gfield, K, n_fields, P, dt, dx,
+    hipLaunchKernelGGL(k_adj_final, dim3(1), dim3(kFinalBlock), 0, st, gfield, K, n_fields, P, dt, dx,
                        w, T2, kappa, dD, dT2, dkappa, df, sub, ng, gmeta, fdt, Fk, Q, dgG0,
                        eps, yz_swap);
     return hipGetLastError();
