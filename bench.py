@@ -200,13 +200,15 @@ def bench_adjoint(btl, torch, sim, cfg, args, fwd_ms_step, fs, qs, Q):
             "gradients_finite": finite}
 
 
-def traffic_for(kernel_avg_ms):
+def traffic_for(launch):
+    """Measured HBM bytes per step launch, when the committed counter
+    profile is of this kernel source and of this launch shape."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except OSError:
         return None
-    if t.get("kernel_sha") != kernel_hash():
+    if t.get("kernel_sha") != kernel_hash() or t.get("launch") != launch:
         return None
     return t["bytes_per_launch"]
 
@@ -280,6 +282,7 @@ def main():
         probe = max(2, min(40, int(1.5e9 / fs)))   # about 1.5e9 field-site updates per candidate
         log(f"autotune ({probe} steps per candidate)")
         btl.btl_autotune(sim._h, Q, probe, torch.cuda.current_stream().cuda_stream)
+    launch = dict(zip(("tile", "zc", "xcd"), btl.btl_get_launch(sim._h)))
     if W > 0:
         log("warmup")
         time_forward(sim, cfg, W, bpf)
@@ -291,7 +294,7 @@ def main():
     achieved = bytes_launch / (ms_step * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": (traffic_for(ms_step) if args.workload == "cfg2" and args.prec == "f32"
+            "traffic": (traffic_for(launch) if args.workload == "cfg2" and args.prec == "f32"
                         and args.membranes == "half-link" and scheme == 0 else None),
             "kernel": f"k_step<{'float2' if args.prec == 'f32' else 'double2'}, {'D2Q5' if nq == 5 else 'D3Q7'}>",
             "bytes_per_launch_algorithmic": bytes_launch}
@@ -302,7 +305,8 @@ def main():
                       "q_sites": qs, "q_samples": Q, "field_sites": fs,
                       "geometries": len(cfg["geoms"]),
                       "storage": args.prec, "steps_per_forward": K,
-                      "membranes": args.membranes, "scheme": args.scheme},
+                      "membranes": args.membranes, "scheme": args.scheme,
+                      "launch": launch},
            "roofline": roof}
     if not args.no_extras:
         log("FP64 comparison runs")

@@ -196,16 +196,24 @@ btl_status btl_set_grad_gG0(btl_sim *s, int32_t on);
  * only.  Errors: BTL_E_INVAL (unknown scheme). */
 btl_status btl_set_scheme(btl_sim *s, int32_t scheme);
 
-/* Choose the launch shape (workgroup tile and z-column length) of this
- * simulator by timing every candidate on the inputs of the last btl_forward
- * (its first Q q-samples, K_probe steps, waveform repeated if shorter) and
- * keeping the fastest.  Synchronizes the stream.  The probes are forwards
- * of their own: the adjoint tape of an earlier taped btl_forward is
- * discarded.  Without autotuning a shape with the fewest idle lanes and
- * whole z columns is used.
+/* Choose the launch shape (workgroup tile, z-column length and workgroup
+ * order) of this simulator by timing every combination on the inputs of
+ * the last btl_forward (its first Q q-samples, K_probe steps, waveform
+ * repeated if shorter) and keeping the fastest.  Synchronizes the stream.
+ * The probes are forwards of their own: the adjoint tape of an earlier
+ * taped btl_forward is discarded.  Without autotuning a shape with the
+ * fewest idle lanes and whole z columns is used.
  * Errors: BTL_E_INVAL (no previous forward, K_probe < 1), BTL_E_NOMEM,
  * BTL_E_HIP. */
 btl_status btl_autotune(btl_sim *s, int32_t Q, int32_t K_probe, void *stream);
+
+/* The launch shape the forwards of s use, as set by btl_autotune: the tile
+ * shape (0 64x4, 1 32x8, 2 16x16, 3 128x2, 4 256x1, 5 runs of 256
+ * consecutive sites; -1: chosen per call), the z-column length (0: whole
+ * columns) and the workgroup order (0 plain, 1 XCD-contiguous; -1: by grid
+ * size).  Host pointers, written on success.  Makes no device call.
+ * Errors: BTL_E_INVAL (a NULL argument). */
+btl_status btl_get_launch(const btl_sim *s, int32_t *tile_shape, int32_t *zc, int32_t *xcd);
 
 /* Release all memory of the simulator (synchronizes the device). */
 void btl_destroy(btl_sim *s);

@@ -3,7 +3,8 @@
 Argument marshalling only: every step of the computation runs in the HIP
 kernels of libbtlbm.so.  The functions `btl_create`, `btl_forward`,
 `btl_backward`, `btl_set_scheme`, `btl_set_lattice`, `btl_set_substeps`,
-`btl_set_grad_gG0`, `btl_autotune`, `btl_destroy` and `btl_last_error` mirror the
+`btl_set_grad_gG0`, `btl_autotune`, `btl_get_launch`, `btl_destroy` and
+`btl_last_error` mirror the
 C ABI of include/btlbm.h one to one.  `Simulator` wraps them with torch
 tensors for device memory and the current torch stream.
 
@@ -29,7 +30,7 @@ BTL_D3Q7, BTL_D2Q5 = 0, 1
 
 EXPORTED = ("btl_create", "btl_forward", "btl_backward", "btl_set_scheme",
             "btl_set_lattice", "btl_set_substeps", "btl_set_grad_gG0", "btl_autotune",
-            "btl_destroy", "btl_last_error")
+            "btl_get_launch", "btl_destroy", "btl_last_error")
 
 
 class BtlError(RuntimeError):
@@ -78,6 +79,9 @@ def load_library(path: str = None):
     lib.btl_set_grad_gG0.restype = ctypes.c_int
     lib.btl_autotune.argtypes = [P, i32, i32, P]
     lib.btl_autotune.restype = ctypes.c_int
+    lib.btl_get_launch.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                   ctypes.POINTER(i32)]
+    lib.btl_get_launch.restype = ctypes.c_int
     lib.btl_destroy.argtypes = [P]
     lib.btl_destroy.restype = None
     lib.btl_last_error.argtypes = [P]
@@ -178,6 +182,14 @@ def btl_autotune(h, Q, K_probe, stream_ptr):
     lib = load_library()
     _check(lib.btl_autotune(h, int(Q), int(K_probe),
                             ctypes.c_void_p(stream_ptr) if stream_ptr else None), h)
+
+
+def btl_get_launch(h):
+    """(tile_shape, zc, xcd) of the simulator's forwards (see the header)."""
+    lib = load_library()
+    v = [ctypes.c_int32(0) for _ in range(3)]
+    _check(lib.btl_get_launch(h, *[ctypes.byref(x) for x in v]), h)
+    return tuple(int(x.value) for x in v)
 
 
 def btl_destroy(h):

@@ -1221,40 +1221,33 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
         return BTL_OK;
     };
     float best = -1.0f;
-    int best_shape = -1, best_zc = 0;
+    int best_shape = -1, best_zc = 0, best_xcd = 0;
     btl_status rc = BTL_OK;
-    s->xcd = -1;   // shapes are compared with the default workgroup order
     std::vector<int> shapes;
     if (s->nq == 5)
         shapes.push_back(kTile256x1);
     else
         shapes.assign(kShapes3D, kShapes3D + kShapeCount3D);
+    // shape, z-column length and workgroup order are searched jointly: the
+    // best column length differs between the two orders
     for (int sh : shapes) {
-        if (rc != BTL_OK) break;
         for (int zc : zcs) {
-            s->tile_shape = sh;
-            s->zc = zc;
-            float ms = 0.0f;
-            if ((rc = time_probe(&ms)) != BTL_OK) break;
-            if (best < 0.0f || ms < best) {
-                best = ms;
-                best_shape = sh;
-                best_zc = zc;
+            for (int xo = 0; xo < 2 && rc == BTL_OK; ++xo) {
+                s->tile_shape = sh;
+                s->zc = zc;
+                s->xcd = xo;
+                float ms = 0.0f;
+                if ((rc = time_probe(&ms)) != BTL_OK) break;
+                if (best < 0.0f || ms < best) {
+                    best = ms;
+                    best_shape = sh;
+                    best_zc = zc;
+                    best_xcd = xo;
+                }
             }
+            if (rc != BTL_OK) break;
         }
-    }
-    // workgroup order for the best shape: plain and XCD-contiguous
-    int best_xcd = -1;
-    for (int xo = 0; xo < 2 && rc == BTL_OK && best_shape >= 0; ++xo) {
-        s->tile_shape = best_shape;
-        s->zc = best_zc;
-        s->xcd = xo;
-        float ms = 0.0f;
-        if ((rc = time_probe(&ms)) != BTL_OK) break;
-        if (best_xcd < 0 || ms < best) {
-            best = ms;
-            best_xcd = xo;
-        }
+        if (rc != BTL_OK) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1271,6 +1264,15 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
     if (getenv("BTLBM_VERBOSE"))
         fprintf(stderr, "btlbm autotune: tile shape %d, z-column %d, xcd order %d (%.3f ms per probe)\n",
                 best_shape, best_zc, best_xcd, best);
+    return BTL_OK;
+}
+
+extern "C" btl_status btl_get_launch(const btl_sim* s, int32_t* tile_shape, int32_t* zc,
+                                     int32_t* xcd) {
+    if (!s || !tile_shape || !zc || !xcd) return BTL_E_INVAL;
+    *tile_shape = s->tile_shape;
+    *zc = s->zc;
+    *xcd = s->xcd;
     return BTL_OK;
 }
 

@@ -170,7 +170,10 @@ def test_autotune_keeps_results():
     try:
         args = (cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"])
         E1 = sim.forward(*args).cpu().numpy()
+        assert btl.btl_get_launch(sim._h) == (-1, 0, -1)   # defaults before tuning
         btl.btl_autotune(sim._h, 3, 5, torch.cuda.current_stream().cuda_stream)
+        tile, zc, xcd = btl.btl_get_launch(sim._h)
+        assert tile in (0, 1, 2, 3, 5) and 0 <= zc < 24 and xcd in (0, 1)
         E2 = sim.forward(*args).cpu().numpy()
     finally:
         sim.close()
