@@ -1202,9 +1202,14 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
     // then the fastest of kTuneReps timed ones (single timings of a few
     // milliseconds are noisy at the percent level)
     constexpr int kTuneReps = 3;
+    // a candidate whose first timing is kTuneCut times the best so far is not
+    // timed again: it cannot win by noise, and most candidates are like that
+    constexpr float kTuneCut = 1.15f;
+    float best = -1.0f;
     auto time_probe = [&](float* best_ms) -> btl_status {
         *best_ms = -1.0f;
         for (int r = 0; r <= kTuneReps; ++r) {
+            if (r > 1 && best > 0.0f && *best_ms > kTuneCut * best) break;
             if (r > 0) (void)hipEventRecord(e0, st);
             const btl_status rr = btl_forward(s, saved.dt, K_probe, saved.D.data(), saved.T2.data(),
                                               saved.kappa.data(), Qr, saved.q_geom.data(),
@@ -1220,7 +1225,6 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
         }
         return BTL_OK;
     };
-    float best = -1.0f;
     int best_shape = -1, best_zc = 0, best_xcd = 0;
     btl_status rc = BTL_OK;
     std::vector<int> shapes;
