@@ -126,7 +126,10 @@ def cpu_baseline(cfg, budget_s: float = 25.0):
         oracle.simulate(*args, cfg["f"][:n], cfg["gG0"][0], threads=threads, want_M=False,
                         lattice=lat)
         return time.perf_counter() - t0
-    # per-step cost from two short runs (their difference removes the setup)
+    # per-step cost from two short runs (their difference removes the setup),
+    # after one run that pays the first touch of the buffers and the thread
+    # start-up
+    run(1)
     per = max((run(3) - run(1)) / 2.0, 1e-3)
     n = int(max(1, min(400, budget_s / per)))
     t0 = time.perf_counter()
@@ -143,7 +146,8 @@ def cpu_baseline(cfg, budget_s: float = 25.0):
         oracle.simulate(*args, cfg["f"][:n], cfg["gG0"][0], threads=1, want_M=False,
                         lattice=lat)
         return time.perf_counter() - t
-    n1 = int(max(1, min(50, 0.25 * budget_s / (per * threads))))
+    per_main = (t1 - t0) / n
+    n1 = int(max(2, min(50, 0.25 * budget_s / (per_main * threads))))
     t_setup = run1(1)
     t_run = run1(1 + n1)
     t2, t3 = 0.0, max(t_run - t_setup, 1e-9)
