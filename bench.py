@@ -241,6 +241,9 @@ def main():
                     help="skip the FP64 comparison runs (profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a device copy of known size (counter calibration)")
+    ap.add_argument("--copy-rate", action="store_true",
+                    help="only time torch's device-to-device copy of 1.41 GB (the step "
+                         "kernel's per-launch reads of the default workload), for scale")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py runs on one GPU; splitting the q-samples "
@@ -264,6 +267,27 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calib_copy_bytes": nbytes}), flush=True)
+        return
+
+    if args.copy_rate:
+        nbytes = 12 * 2097152 * 56          # 12 fields x 128^3 sites x 7 complex FP32
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 50
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        rate = 2 * nbytes / (us * 1e-6) / 1e9
+        print(json.dumps({"copy_bytes_each_way": nbytes, "us_per_copy": us,
+                          "GBs_read_plus_write": rate, "frac_of_peak": rate / HBM_PEAK_GBS}),
+              flush=True)
         return
 
     K, W = args.steps, args.warmup
