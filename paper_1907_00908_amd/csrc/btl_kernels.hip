@@ -417,6 +417,18 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
             cz_g = src[(z0 == 0 ? o5f : o5i) + sp];
             cz_o = src[pop + (pz + 1) * ps + sp];
         }
+        if constexpr (GM) {
+            // one site at a time: the general condition's stencil loads and
+            // coefficient arithmetic leave no registers for a second site in
+            // flight, and the occupancy this keeps pays more than the overlap
+            SiteLoads A;
+            GmPre G;
+            for (int32_t j2 = z0; j2 < z1; ++j2) {
+                issue(j2, A);
+                prep(j2, A, G);
+                compute(j2, A, G, Mv);
+            }
+        } else {
         SiteLoads A, B;
         GmPre G;
         issue(z0, A);
@@ -433,6 +445,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
         if (j2 < z1) {
             prep(j2, A, G);
             compute(j2, A, G, Mv);
+        }
         }
     }
 
