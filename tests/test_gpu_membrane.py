@@ -113,3 +113,28 @@ def test_positions_errors():
     with pytest.raises(btl.BtlError) as ei:
         btl.Simulator(cfg["geoms"], cfg["bc"], "f64")
     assert ei.value.status == btl.BTL_E_INVAL
+
+
+@pytest.mark.parametrize("shape,zc", [(5, 3), (1, 4), (3, 0)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_positions_every_launch_shape(shape, zc, prec, monkeypatch):
+    # the general condition walks each column chunk one site at a time: runs
+    # of 256 sites with 3-site chunks (a ragged last chunk), 32x8 tiles with
+    # 4-site chunks and 128x2 tiles over whole columns, against the oracle
+    btl = _gpu()
+    import torch
+    cfg = w.make_config("cfg2", n=20, K=150, membranes="positions")
+    print(f"GPU membranes shape={shape} zc={zc} prec={prec}", flush=True)
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], prec)
+    try:
+        args = (cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"])
+        sim.forward(*args, cfg["f"][:2], cfg["gG0"])
+        monkeypatch.setenv("BTLBM_TILE", str(shape))
+        monkeypatch.setenv("BTLBM_ZC", str(zc))
+        btl.btl_autotune(sim._h, 1, 1, torch.cuda.current_stream().cuda_stream)
+        assert btl.btl_get_launch(sim._h)[:2] == (shape, zc)
+        E = sim.forward(*args, cfg["f"], cfg["gG0"]).cpu().numpy()
+    finally:
+        sim.close()
+    Eo, _ = oracle.simulate_config(cfg, threads=8)
+    _check(E, Eo, prec, f"positions shape {shape} zc {zc}")
