@@ -192,9 +192,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     // pz + 1 pull of site j2 and the own population of direction pz of site
     // j2 + 1.  Each is loaded once and carried to the next site (cz_g, cz_o),
     // so a site issues NQ + 3 loads (D3Q7: 12 of the 14 values it uses).
-    // The z column is software-pipelined: the loads of site j2 + 1 are issued
-    // before the stores of site j2, so waiting for a site's data never waits
-    // for earlier stores.
+    // Without the general membrane condition the z column is
+    // software-pipelined: the loads of site j2 + 1 are issued before the
+    // stores of site j2, so waiting for a site's data never waits for
+    // earlier stores.
     struct SiteLoads {
         uint32_t word;
         V g[NQ];          // g[pz] is carried, not loaded
@@ -225,9 +226,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     };
     // General membrane links of a site (GM): which links take the general
     // condition, and the three stencil populations of the first two of them,
-    // loaded before the next site's loads are issued so that waiting for
-    // them never waits for those (a site with more general links loads the
-    // others when it computes them).
+    // loaded as soon as the site's own data have arrived (a site with more
+    // general links loads the others when it computes them).
     struct GmPre {
         uint32_t gen;
         int d0, d1;
@@ -429,23 +429,23 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 compute(j2, A, G, Mv);
             }
         } else {
-        SiteLoads A, B;
-        GmPre G;
-        issue(z0, A);
-        int32_t j2 = z0;
-        // two sites per trip so that A and B swap roles without copies
-        for (; j2 + 1 < z1; j2 += 2) {
-            prep(j2, A, G);
-            issue(j2 + 1, B);
-            compute(j2, A, G, Mv);
-            prep(j2 + 1, B, G);
-            if (j2 + 2 < z1) issue(j2 + 2, A);
-            compute(j2 + 1, B, G, Mv);
-        }
-        if (j2 < z1) {
-            prep(j2, A, G);
-            compute(j2, A, G, Mv);
-        }
+            SiteLoads A, B;
+            GmPre G;
+            issue(z0, A);
+            int32_t j2 = z0;
+            // two sites per trip so that A and B swap roles without copies
+            for (; j2 + 1 < z1; j2 += 2) {
+                prep(j2, A, G);
+                issue(j2 + 1, B);
+                compute(j2, A, G, Mv);
+                prep(j2 + 1, B, G);
+                if (j2 + 2 < z1) issue(j2 + 2, A);
+                compute(j2 + 1, B, G, Mv);
+            }
+            if (j2 < z1) {
+                prep(j2, A, G);
+                compute(j2, A, G, Mv);
+            }
         }
     }
 
