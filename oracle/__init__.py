@@ -8,8 +8,8 @@ library (paper_1907_00908_amd); both only consume the seeded inputs of the
 `simulate` runs the scheme one gradient direction at a time in the paper's
 buffer-row formulation (see oracle.c for the steps and the readings of the
 paper they take).  For a mirrored axis and a gradient that is neither normal
-nor parallel to its faces the paper gives no rule ("a more complicated
-rotation ... not considered", Sec. 2.4.4); the oracle then takes the plain
+nor parallel to its faces the paper gives no rule (Sec. 2.4.4 sets that
+case aside as needing a more involved rotation); the oracle then takes the plain
 definition of a mirroring boundary -- the REV reflected across the face,
 i.e. the medium doubled along that axis and tiled periodically -- and runs
 the modified periodic condition on the doubled domain, averaging the signal
