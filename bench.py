@@ -1,21 +1,25 @@
 """Benchmark: q-batched lattice site-updates/s of the hybrid LBM Bloch-Torrey
-step on one MI355X, with the HBM roofline of the step kernel and the FP64
+step on one MI355X, with the HBM roofline of the step kernel, the adjoint
+(reverse sweep) on the adjoint workload, the FP32-vs-FP64 signal error over a
+full echo time, the plain FP64 one-q-sample-per-launch rate, and the FP64
 CPU oracle timed on the host as a baseline.
 
-Workload: the two-phase axon model -- 128^3 lattice, dx = 0.25 um, mirroring
-outer faces, z-cylinders with Gamma(4, mean 1 um) radii packed to ~60 %,
-D 2.0/1.0 um^2/ms, T2 90/70 ms, kappa 0.02 um/ms, PGSE delta 10 Delta 30 ms,
-6 oblique directions at b = 1000 s/mm^2, dt = 0.004 ms.  Each oblique
-direction on mirrored faces carries two fields (the primary and one
-reflected image), so one step updates 12 fields of 2,097,152 sites.
+Default workload (the q-batched case): 256^3 lattice, dx = 0.25 um, periodic
+faces, z-cylinders (Gamma(4, mean 1 um) radii, kappa 0.02 um/ms) to 40 %
+plus spheres (radius U(2, 6) um, kappa 0.05 um/ms) to +15 %, D 2.0/1.0/1.0
+um^2/ms, T2 90/70/70 ms, PGSE delta 10 Delta 30 ms, dt = 0.004 ms, 64
+golden-spiral directions x b in {500, 1000, 2000, 3000} s/mm^2 = 256
+q-samples, one field each.  Their two population copies (2 x 240 GB in FP32)
+exceed device memory, so the library runs them in q-waves.
 
 A benchmark step is one lattice time step of the whole q-batch: stream with
 boundaries and membranes, reaction, signal reduction and collision for
-every q-sample.  `value` counts q-sample site-updates (6 x 128^3 per step).
+every q-sample.  `value` counts q-sample site-updates per second (256 x 256^3
+per step).  The adjoint leg runs on the adjoint workload (96^3 cylinders,
+30 q-samples): a taped forward and the reverse sweep.
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload cfg2]
-(--workload selects one of the other synthetic workloads; the default is the
-one described above.)
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload cfg3a]
+(--workload selects one of the other synthetic workloads).
 """
 from __future__ import annotations
 
@@ -36,23 +40,29 @@ METRIC = "q-batched site-updates/s + % HBM peak, fwd & adjoint, at stated err vs
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_FIELD_SITE_F32 = 112      # read 7 complex float + write 7 complex float
 BYTES_PER_FIELD_SITE_F64 = 224
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_f32_axon128_traffic.json")
+ADJ_BYTES_PER_FIELD_SITE_F32 = 168  # read adjoint + read forward state + write adjoint
 KERNEL_SRC = os.path.join(ROOT, "paper_1907_00908_amd", "csrc", "btl_kernels.hip")
+ADJOINT_SRC = os.path.join(ROOT, "paper_1907_00908_amd", "csrc", "btl_adjoint.hip")
 
 
-def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
+def source_hash(path) -> str:
+    with open(path, "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
 WORKLOAD_NAMES = {
     "cfg1": "uniform 32^3 periodic free diffusion, PGSE, G || x, b=1000 (plain case)",
     "cfg2": "two-phase axon model 128^3, mirror BC, 6 oblique directions, b=1000",
-    "cfg3a": "cylinders+spheres 256^3 periodic, 64 directions x 4 b-values = 256 q",
+    "cfg3a": "cylinders+spheres 256^3 periodic, 64 directions x 4 b-values = 256 q (q-batched)",
     "cfg3b": "16 cylinder geometries 96^3..192^3 (ragged batch), 6 directions each",
-    "cfg4": "two-phase cylinders 96^3 periodic, 30 directions",
+    "cfg4": "two-phase cylinders 96^3 periodic, 30 directions (adjoint workload)",
     "cfg5": "three-phase ellipsoid cells 512^3 periodic, cosine OGSE, 32 directions",
     "cfg2d": "2D axon cross-sections 512^2 on the D2Q5 lattice, 64 in-plane dirs x 4 b-values",
+}
+TRAFFIC_FILES = {
+    ("cfg3a", "k_step"): os.path.join(ROOT, "profiles", "k_step_f32_cylspheres256_traffic.json"),
+    ("cfg2", "k_step"): os.path.join(ROOT, "profiles", "k_step_f32_axon128_traffic.json"),
+    ("cfg4", "k_adj"): os.path.join(ROOT, "profiles", "k_adj_f32_cyl96_traffic.json"),
 }
 
 
@@ -62,6 +72,7 @@ def workload(name: str, K: int, membranes: str = "half-link"):
     f = cfg["f"]
     if K > len(f):
         f = np.resize(f, K)
+    cfg["f_full"] = cfg["f"]
     cfg["f"] = f[:K]
     return cfg
 
@@ -77,10 +88,12 @@ def fields_of(G, bc, classical=False) -> int:
     return 2 ** (k - 1) if len(mir) == len(nz) and not classical else 2 ** k
 
 
-def field_sites(cfg, classical=False) -> int:
-    """Sum over all fields of the batch of their site counts."""
-    return sum(fields_of(G, cfg["bc"], classical) * cfg["geoms"][int(g)].comp.size
-               for G, g in zip(cfg["gG0"], cfg["q_geom"]))
+def field_sites(cfg, classical=False, qs=None) -> int:
+    """Sum over all fields of the batch (or of the listed q-samples) of
+    their site counts."""
+    qs = range(len(cfg["gG0"])) if qs is None else qs
+    return sum(fields_of(cfg["gG0"][q], cfg["bc"], classical) *
+               cfg["geoms"][int(cfg["q_geom"][q])].comp.size for q in qs)
 
 
 def q_sites(cfg) -> int:
@@ -91,128 +104,53 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def time_forward(sim, cfg, K, prec_bytes, reps=1):
-    import torch
+def cpu_share() -> int:
+    """Host cores this process may use: its CPU affinity, at most 16 (the
+    host share of one GPU on the benchmark machine)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def timed(torch, fn, reps):
+    """Median and all times (ms) of `reps` calls of fn, each bracketed by
+    HIP events on the current stream (the stream the library launches on)."""
     stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    best = None
-    E = None
+    times = []
+    out = None
     for _ in range(reps):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         ev0.record(stream)
-        E = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:K],
-                        cfg["gG0"], cfg["q_geom"])
+        out = fn()
         ev1.record(stream)
         torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1)
-        best = ms if best is None else min(best, ms)
-    return best, E
+        times.append(ev0.elapsed_time(ev1))
+    return float(np.median(times)), times, out
 
 
-def cpu_baseline(cfg, budget_s: float = 25.0):
-    """The FP64 oracle on the host cores, a bounded number of full-size steps
-    of q-sample 0 (oblique gradient on mirrored faces: the oracle runs the
-    reflected, doubled domain)."""
-    import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
-    g = cfg["geoms"][0]
-    args = (g.comp, g.comp_phase, g.n_phase, cfg["bc"], cfg["dx"], cfg["dt"], cfg["D"],
-            cfg["T2"], cfg["kappa"])
-    lat = cfg.get("lattice", 0)
-
-    def run(n):
-        t0 = time.perf_counter()
-        oracle.simulate(*args, cfg["f"][:n], cfg["gG0"][0], threads=threads, want_M=False,
-                        lattice=lat)
-        return time.perf_counter() - t0
-    # per-step cost from two short runs (their difference removes the setup),
-    # after one run that pays the first touch of the buffers and the thread
-    # start-up
-    run(1)
-    per = max((run(3) - run(1)) / 2.0, 1e-3)
-    n = int(max(1, min(400, budget_s / per)))
-    t0 = time.perf_counter()
-    oracle.simulate(*args, cfg["f"][:n], cfg["gG0"][0], threads=threads, want_M=False,
-                    lattice=lat)
-    t1 = time.perf_counter()
-    sites = g.comp.size
-    note = ("; the oracle steps the reflected, doubled domain"
-            if oracle.needs_doubling(cfg["bc"], cfg["gG0"][0]) else "")
-    # the same oracle on one thread, a few steps (about a quarter of the
-    # budget); a one-step run's time is subtracted to remove the setup
-    def run1(n):
-        t = time.perf_counter()
-        oracle.simulate(*args, cfg["f"][:n], cfg["gG0"][0], threads=1, want_M=False,
-                        lattice=lat)
-        return time.perf_counter() - t
-    per_main = (t1 - t0) / n
-    n1 = int(max(2, min(50, 0.25 * budget_s / (per_main * threads))))
-    t_setup = run1(1)
-    t_run = run1(1 + n1)
-    t2, t3 = 0.0, max(t_run - t_setup, 1e-9)
-    return {"value": sites * n / (t1 - t0), "unit": "site-updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"q-sample 0 of the workload, {n} full-size steps ({sites} REV sites"
-                      f"{note}), {t1 - t0:.1f} s",
-            "single_thread": {"value": sites * n1 / (t3 - t2), "cores": 1,
-                              "sample": f"{n1} full-size steps beyond a 1-step run, "
-                                        f"{t3 - t2:.1f} s"}}
+def forward_fn(sim, cfg, K, qs=None, ckpt_every=0):
+    gG0 = cfg["gG0"] if qs is None else cfg["gG0"][qs]
+    qg = cfg["q_geom"] if qs is None else cfg["q_geom"][qs]
+    return lambda: sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:K], gG0,
+                               qg, ckpt_every=ckpt_every)
 
 
-def bench_adjoint(btl, torch, sim, cfg, args, fwd_ms_step, fs, qs, Q):
-    """Reverse sweep of the same workload: forward with a checkpoint every
-    adj_ckpt steps, then btl_backward for a linear loss in E.  The end-to-end
-    rate counts q-sample site-updates of the reverse sweep (it recomputes
-    each segment forward and runs one adjoint step per forward step)."""
-    Kb, C = min(args.adj_steps, len(cfg["f"])), args.adj_ckpt
-    c = dict(cfg)
-    c["f"] = cfg["f"][:Kb]
-    stream = torch.cuda.current_stream()
-    E = sim.forward(c["dt"], c["D"], c["T2"], c["kappa"], c["f"], c["gG0"], c["q_geom"],
-                    ckpt_every=C)
-    gen = torch.Generator(device="cpu").manual_seed(0)
-    g = torch.randn((Q, Kb + 1, 2), generator=gen, dtype=torch.float64).to(E.device)
-    P = len(c["D"])
-    sim.backward(g, P, Kb)                      # warm
-    sim.forward(c["dt"], c["D"], c["T2"], c["kappa"], c["f"], c["gG0"], c["q_geom"],
-                ckpt_every=C)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    dD, dT2, dk, df = sim.backward(g, P, Kb)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    nseg = (Kb + C - 1) // C
-    recompute_ms = (Kb - nseg) * fwd_ms_step
-    adj_ms = max(ms - recompute_ms, 1e-9) / Kb
-    # read the adjoint and the forward state, write the adjoint: 3 x nq complex
-    nq = 5 if cfg.get("lattice", 0) == 1 else 7
-    bpf = (168 if args.prec == "f32" else 336) * nq // 7
-    ach = fs * bpf / (adj_ms * 1e-3) / 1e9
-    finite = bool(torch.isfinite(dD).all() and torch.isfinite(df).all())
-    return {"value": qs * Kb / (ms * 1e-3), "unit": "site-updates/s",
-            "what": "end-to-end reverse sweep (segment recompute + adjoint step)",
-            "steps": Kb, "ckpt_every": C, "ms_total": ms,
-            "adjoint_kernel": {"ms_per_step_est": adj_ms,
-                               "bytes_per_launch_algorithmic": fs * bpf,
-                               "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS,
-                               "estimate": "backward time minus the recompute steps at the "
-                                           "measured forward step time"},
-            "gradients_finite": finite}
-
-
-def traffic_for(launch):
-    """Measured HBM bytes per step launch, when the committed counter
-    profile is of this kernel source and of this launch shape."""
+def traffic_for(key, kernel_sha, launch):
+    """Measured HBM bytes per launch, when the committed counter profile is
+    of this kernel source and of this launch shape."""
+    path = TRAFFIC_FILES.get(key)
+    if not path:
+        return None
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             t = json.load(fh)
     except OSError:
         return None
-    if t.get("kernel_sha") != kernel_hash():
+    if t.get("kernel_sha") != kernel_sha:
         return None
     if t.get("launch") == launch:
         return t["bytes_per_launch"]
@@ -220,30 +158,166 @@ def traffic_for(launch):
     return row["bytes_per_launch"] if row else None
 
 
+def cpu_baseline(cfg, budget_s: float = 25.0):
+    """The FP64 oracle on the host cores, a bounded number of full-size steps
+    of q-sample 0 (on mirrored faces with an oblique gradient the oracle
+    steps the reflected, doubled domain, and the rate counts those sites)."""
+    import oracle
+    threads = cpu_share()
+    g = cfg["geoms"][0]
+    args = (g.comp, g.comp_phase, g.n_phase, cfg["bc"], cfg["dx"], cfg["dt"], cfg["D"],
+            cfg["T2"], cfg["kappa"])
+    lat = cfg.get("lattice", 0)
+    doubled = oracle.needs_doubling(cfg["bc"], cfg["gG0"][0])
+    sites = g.comp.size * (2 ** sum(1 for b in cfg["bc"] if b == 1) if doubled else 1)
+
+    fw = cfg.get("f_full", cfg["f"])   # the timed forward may be shorter than n
+
+    def run(n, th):
+        t0 = time.perf_counter()
+        oracle.simulate(*args, np.resize(fw, n), cfg["gG0"][0], threads=th, want_M=False,
+                        lattice=lat)
+        return time.perf_counter() - t0
+    # per-step cost from two short runs (their difference removes the setup),
+    # after one run that pays the first touch of the buffers and the thread
+    # start-up
+    run(1, threads)
+    per = max((run(3, threads) - run(1, threads)) / 2.0, 1e-3)
+    n = int(max(2, min(400, budget_s / per)))
+    t_set = run(1, threads)
+    t_all = run(1 + n, threads)
+    dt_main = max(t_all - t_set, 1e-9)
+    # the same oracle on one thread, a few steps (about a quarter of the budget)
+    n1 = int(max(1, min(50, 0.25 * budget_s / (dt_main / n * threads))))
+    t1_set = run(1, 1)
+    t1 = max(run(1 + n1, 1) - t1_set, 1e-9)
+    note = "; the oracle steps the reflected, doubled domain" if doubled else ""
+    return {"value": sites * n / dt_main, "unit": "site-updates/s", "cores": threads,
+            "kind": "oracle", "nproc": os.cpu_count(),
+            "threads_note": "the host share of one GPU (at most 16 threads, the process's "
+                            "CPU affinity)",
+            "sample": f"q-sample 0 of the workload, {n} full-size steps beyond a 1-step run "
+                      f"({sites} lattice sites{note}), {dt_main:.1f} s",
+            "single_thread": {"value": sites * n1 / t1, "cores": 1,
+                              "sample": f"{n1} full-size steps beyond a 1-step run, {t1:.1f} s"}}
+
+
+def err_full_te(btl, cfg, qs, prec_pair=("f32", "f64")):
+    """Signal error of FP32 storage against FP64 storage over a full echo
+    time (every step), for the listed q-samples of the workload."""
+    c = dict(cfg)
+    c["f"] = cfg["f_full"]
+    c["gG0"] = cfg["gG0"][qs]
+    c["q_geom"] = cfg["q_geom"][qs]
+    E32 = btl.simulate_config(c, prec=prec_pair[0]).cpu().numpy()
+    E64 = btl.simulate_config(c, prec=prec_pair[1]).cpu().numpy()
+    big = np.abs(E64) >= 1e-2
+    rel = float(np.max(np.abs(E32 - E64)[big] / np.abs(E64)[big])) if big.any() else 0.0
+    small = float(np.max(np.abs(E32 - E64)[~big])) if (~big).any() else 0.0
+    return {"max_rel_E": rel, "max_abs_E_below_1e-2": small, "steps": len(c["f"]),
+            "q_samples": [int(q) for q in qs], "what": "FP32 storage vs FP64 storage on the "
+            "GPU path over a full echo time, every step (the FP64 path matches the FP64 "
+            "oracle to 1e-12)"}
+
+
+def bench_adjoint(btl, torch, args):
+    """Reverse sweep of the adjoint workload: a taped forward of adj_steps
+    steps with a checkpoint every adj_ckpt steps, then btl_backward for a
+    linear loss in E.  The end-to-end rate counts q-sample site-updates of
+    the reverse sweep (it recomputes each segment forward and runs one
+    adjoint step per forward step); the adjoint kernel's time per step is
+    the backward time minus the recompute steps at the measured forward
+    step time of the same workload."""
+    name = args.adj_workload
+    Kb, C = args.adj_steps, args.adj_ckpt
+    cfg = workload(name, Kb)
+    Q = len(cfg["gG0"])
+    qs = q_sites(cfg)
+    fs = field_sites(cfg)
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], args.prec)
+    try:
+        stream = torch.cuda.current_stream().cuda_stream
+        sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:2], cfg["gG0"])
+        probe = max(2, min(40, int(1.5e9 / fs)))
+        btl.btl_autotune(sim._h, Q, probe, stream)
+        fwd = forward_fn(sim, cfg, Kb)
+        fwd()
+        fwd_ms, _, _ = timed(torch, fwd, 3)
+        gen = torch.Generator(device="cpu").manual_seed(0)
+        g = torch.randn((Q, Kb + 1, 2), generator=gen, dtype=torch.float64).to("cuda")
+        tape = forward_fn(sim, cfg, Kb, ckpt_every=C)
+        tape()
+        sim.backward(g)                                   # warm
+        times = []
+        grads = None
+        for _ in range(args.reps):
+            tape()
+            ms, _, grads = timed(torch, lambda: sim.backward(g), 1)
+            times.append(ms)
+        ms = float(np.median(times))
+        stats = btl.btl_get_backward_stats(sim._h)
+    finally:
+        sim.close()
+    fwd_step = fwd_ms / Kb
+    recompute_ms = stats[0] * fwd_step
+    adj_ms = max(ms - recompute_ms, 1e-9) / Kb
+    nq = 5 if cfg.get("lattice", 0) == 1 else 7
+    bpf = (ADJ_BYTES_PER_FIELD_SITE_F32 if args.prec == "f32" else 2 * ADJ_BYTES_PER_FIELD_SITE_F32) * nq // 7
+    ach = fs * bpf / (adj_ms * 1e-3) / 1e9
+    dD, dT2, dk, df = grads
+    finite = bool(torch.isfinite(dD).all() and torch.isfinite(df).all())
+    return {"value": qs * Kb / (ms * 1e-3), "unit": "site-updates/s",
+            "workload": f"{WORKLOAD_NAMES[name]} ({name})",
+            "what": "end-to-end reverse sweep (segment recompute + adjoint step), median of "
+                    f"{args.reps}", "steps": Kb, "ckpt_every": C, "ms_total": ms,
+            "ms_all": times, "forward_steps_recomputed": stats[0],
+            "forward_ms_per_step": fwd_step,
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS,
+                         "traffic": traffic_for((name, "k_adj"), source_hash(ADJOINT_SRC),
+                                                None) if args.prec == "f32" else None,
+                         "kernel": f"k_adj<{'float2' if args.prec == 'f32' else 'double2'}>",
+                         "bytes_per_launch_algorithmic": fs * bpf,
+                         "ms_per_launch_est": adj_ms,
+                         "estimate": "backward time minus the recomputed forward steps at the "
+                                     "measured forward step time, per adjoint step"},
+            "gradients_finite": finite}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOAD_NAMES))
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="cfg3a", choices=sorted(WORKLOAD_NAMES))
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=40,
+                    help="warmup steps: ceil(W/K) untimed forwards of the timed K steps (at "
+                         "least one), so that the graphs are captured before timing")
+    ap.add_argument("--reps", type=int, default=5, help="timed forwards (median reported)")
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
     ap.add_argument("--scheme", default="hybrid", choices=["hybrid", "classical"],
                     help="classical: the classical LBM of Appendix A (no adjoint)")
     ap.add_argument("--membranes", default="half-link", choices=["half-link", "positions"],
                     help="positions: exact membrane positions on the links and the "
                          "general membrane condition (no adjoint)")
+    ap.add_argument("--launch", default=None,
+                    help="tile,zc,xcd: fix the step kernel's launch (btl_set_launch) "
+                         "instead of autotuning")
+    ap.add_argument("--tune-q", type=int, default=32,
+                    help="q-samples the autotuner probes (one q-wave)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adj-workload", default="cfg4", choices=sorted(WORKLOAD_NAMES))
     ap.add_argument("--adj-steps", type=int, default=400)
     ap.add_argument("--adj-ckpt", type=int, default=20)
+    ap.add_argument("--adj-only", action="store_true",
+                    help="only the adjoint leg (profiling)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP64 comparison runs (profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a device copy of known size (counter calibration)")
     ap.add_argument("--copy-rate", action="store_true",
-                    help="only time torch's device-to-device copy of 1.41 GB (the step "
-                         "kernel's per-launch reads of the default workload), for scale")
+                    help="only time torch's device-to-device copy of 1.41 GB, for scale")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py runs on one GPU; splitting the q-samples "
@@ -290,83 +364,102 @@ def main():
               flush=True)
         return
 
-    K, W = args.steps, args.warmup
+    if args.adj_only:
+        log("adjoint leg only")
+        print(json.dumps({"adjoint": bench_adjoint(btl, torch, args)}), flush=True)
+        return
+
+    K = max(1, args.steps)
+    W = max(0, args.warmup)
     log(f"building workload {args.workload}")
     if args.membranes == "positions" or args.scheme != "hybrid":
         args.no_adjoint = True          # the adjoint covers hybrid half-link runs
     scheme = 0 if args.scheme == "hybrid" else 1
-    cfg = workload(args.workload, max(K, W, 0 if args.no_adjoint else args.adj_steps),
-                   args.membranes)
+    cfg = workload(args.workload, K, args.membranes)
     Q = len(cfg["gG0"])
     qs = q_sites(cfg)
     fs = field_sites(cfg, args.scheme == "classical")
-    sites = cfg["geoms"][0].comp.size
     lattice = cfg.get("lattice", 0)
     nq = 5 if lattice == 1 else 7
     sim = btl.Simulator(cfg["geoms"], cfg["bc"], args.prec, scheme=scheme, lattice=lattice)
     # read nq complex populations + write nq, per field site
     bpf = (BYTES_PER_FIELD_SITE_F32 if args.prec == "f32" else BYTES_PER_FIELD_SITE_F64) * nq // 7
-    log("first forward")
-    time_forward(sim, cfg, max(W, 1), bpf)
-    if not args.no_autotune:
-        # launch shape chosen by timed probes of this workload (setup, untimed)
-        probe = max(2, min(40, int(1.5e9 / fs)))   # about 1.5e9 field-site updates per candidate
-        log(f"autotune ({probe} steps per candidate)")
-        btl.btl_autotune(sim._h, Q, probe, torch.cuda.current_stream().cuda_stream)
+    stream = torch.cuda.current_stream().cuda_stream
+    Qt = min(Q, max(1, args.tune_q))
+    tq = list(range(Qt))
+    sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:2], cfg["gG0"][tq],
+                cfg["q_geom"][tq])
+    if args.launch:
+        t, z, x = (int(v) for v in args.launch.split(","))
+        btl.btl_set_launch(sim._h, t, z, x)
+    elif not args.no_autotune:
+        # launch shape chosen by timed probes on the first Qt q-samples (one
+        # q-wave; setup, untimed): about 1.5e9 field-site updates per candidate
+        fst = field_sites(cfg, args.scheme == "classical", tq)
+        probe = max(2, min(40, int(1.5e9 / fst)))
+        log(f"autotune ({Qt} q-samples, {probe} steps per candidate)")
+        btl.btl_autotune(sim._h, Qt, probe, stream)
     launch = dict(zip(("tile", "zc", "xcd"), btl.btl_get_launch(sim._h)))
-    if W > 0:
-        log("warmup")
-        time_forward(sim, cfg, W, bpf)
-    log("timed forward")
-    ms, E = time_forward(sim, cfg, K, bpf)
+    fwd = forward_fn(sim, cfg, K)
+    n_warm = max(1, -(-W // K))
+    log(f"warmup: {n_warm} forward(s) of {K} steps")
+    for _ in range(n_warm):
+        fwd()
+    torch.cuda.synchronize()
+    log(f"timed: {args.reps} forwards of {K} steps")
+    ms, ms_all, E = timed(torch, fwd, args.reps)
     ms_step = ms / K
     value = qs * K / (ms * 1e-3)
-    bytes_launch = fs * bpf
-    achieved = bytes_launch / (ms_step * 1e-3) / 1e9
+    bytes_step = fs * bpf
+    achieved = bytes_step / (ms_step * 1e-3) / 1e9
+    kname = f"k_step<{'float2' if args.prec == 'f32' else 'double2'}, {'D2Q5' if nq == 5 else 'D3Q7'}>"
+    traffic = None
+    if args.prec == "f32" and args.membranes == "half-link" and scheme == 0:
+        traffic = traffic_for((args.workload, "k_step"), source_hash(KERNEL_SRC), launch)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": (traffic_for(launch) if args.workload == "cfg2" and args.prec == "f32"
-                        and args.membranes == "half-link" and scheme == 0 else None),
-            "kernel": f"k_step<{'float2' if args.prec == 'f32' else 'double2'}, {'D2Q5' if nq == 5 else 'D3Q7'}>",
-            "bytes_per_launch_algorithmic": bytes_launch}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname,
+            "bytes_per_step_algorithmic": bytes_step,
+            "timing": "HIP events around each timed forward on the launch stream (median of "
+                      f"{args.reps}); the forward's own table and signal launches (one each per "
+                      "32 steps) are included"}
     out = {"metric": METRIC, "value": value, "unit": "site-updates/s", "n_gpus": 1,
            "steps": K, "warmup": W, "ms_per_step": ms_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"{WORKLOAD_NAMES[args.workload]} ({args.workload})",
                       "q_sites": qs, "q_samples": Q, "field_sites": fs,
                       "geometries": len(cfg["geoms"]),
-                      "storage": args.prec, "steps_per_forward": K,
-                      "membranes": args.membranes, "scheme": args.scheme,
-                      "launch": launch},
+                      "storage": args.prec, "arithmetic": "f64", "sums": "f64",
+                      "steps_per_forward": K, "membranes": args.membranes,
+                      "scheme": args.scheme, "launch": launch, "reps": args.reps,
+                      "ms_per_forward_all": ms_all},
            "roofline": roof}
     if not args.no_extras:
         log("FP64 comparison runs")
-        # stated error vs FP64 storage over the same steps, and the plain FP64
-        # one-sample-per-launch form as the speedup denominator
+        # stated error vs FP64 storage over a full echo time, and the plain
+        # FP64 one-sample-per-launch form as the speedup denominator
+        qerr = [0, Q - 1] if Q > 1 else [0]
+        out["err_vs_fp64"] = err_full_te(btl, cfg, qerr)
         sim64 = btl.Simulator(cfg["geoms"], cfg["bc"], "f64", scheme=scheme, lattice=lattice)
-        ms64, E64 = time_forward(sim64, cfg, K, BYTES_PER_FIELD_SITE_F64)
-        e32 = E.cpu().numpy()
-        e64 = E64.cpu().numpy()
-        big = np.abs(e64) >= 1e-2
-        rel = np.max(np.abs(e32 - e64)[big] / np.abs(e64)[big])
-        out["err_vs_fp64"] = {"max_rel_E": float(rel), "steps": K}
-        one = dict(cfg)
-        one["gG0"] = cfg["gG0"][:1]
-        one["q_geom"] = cfg["q_geom"][:1]
-        ms1, _ = time_forward(sim64, one, K, BYTES_PER_FIELD_SITE_F64)
-        v1 = cfg["geoms"][int(cfg["q_geom"][0])].comp.size * K / (ms1 * 1e-3)
-        out["fp64_one_q_per_launch"] = {"value": v1, "unit": "site-updates/s",
-                                        "speedup_of_value": value / v1}
-        out["fp64_batched"] = {"value": qs * K / (ms64 * 1e-3)}
-        sim64.close()
-    state_gb = fs * (8 if args.prec == "f32" else 16) * (5 if cfg.get("lattice", 0) == 1 else 7) / 1e9
-    adj_states = min(args.adj_steps, K) / args.adj_ckpt + args.adj_ckpt + 4
-    if not args.no_adjoint and state_gb * adj_states > 120.0:
-        out["adjoint"] = {"skipped": f"tape would need {state_gb * adj_states:.0f} GB"}
-    elif not args.no_adjoint:
-        log("reverse sweep")
-        out["adjoint"] = bench_adjoint(btl, torch, sim, cfg, args, ms_step, fs, qs, Q)
+        try:
+            one = forward_fn(sim64, cfg, K, qs=[0])
+            one()
+            ms1, _, _ = timed(torch, one, args.reps)
+            v1 = cfg["geoms"][int(cfg["q_geom"][0])].comp.size * K / (ms1 * 1e-3)
+            out["fp64_one_q_per_launch"] = {"value": v1, "unit": "site-updates/s",
+                                            "speedup_of_value": value / v1,
+                                            "what": "FP64 storage, q-sample 0 alone, default "
+                                                    "launch, median of reps"}
+            allq = forward_fn(sim64, cfg, K)
+            allq()
+            ms64, _, _ = timed(torch, allq, 1)
+            out["fp64_batched"] = {"value": qs * K / (ms64 * 1e-3),
+                                   "what": "FP64 storage, the whole batch, default launch"}
+        finally:
+            sim64.close()
     sim.close()
+    if not args.no_adjoint:
+        log(f"reverse sweep on {args.adj_workload}")
+        out["adjoint"] = bench_adjoint(btl, torch, args)
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(cfg)

@@ -39,6 +39,14 @@
  * Errors: functions return a btl_status; nothing unwinds across this
  * interface.  btl_last_error returns a text describing the last failure of
  * that simulator.  A simulator is not thread-safe: use one per host thread.
+ *
+ * Non-finite results: the kernels that form the signal (Sec. 2.1) and the
+ * gradients set a flag of the simulator when a value they write is not
+ * finite (for instance when gamma G0, f and dt overflow a phase angle).
+ * Because calls are asynchronous the flag is reported later: by
+ * btl_synchronize, or by the first btl_forward, btl_backward or
+ * btl_autotune that finds it set when it starts, which then
+ * returns BTL_E_NONFINITE without enqueuing work.  Reporting clears it.
  */
 #ifndef BTLBM_H
 #define BTLBM_H
@@ -57,8 +65,8 @@ typedef enum {
     BTL_E_UNSUPPORTED = 2,  /* valid request the library does not implement */
     BTL_E_NOMEM = 3,        /* device memory exhausted */
     BTL_E_HIP = 4,          /* a HIP runtime call failed */
-    BTL_E_NONFINITE = 5     /* reserved (calls are asynchronous; the library does not
-                               inspect results, check E on the caller's side) */
+    BTL_E_NONFINITE = 5     /* an earlier call produced a non-finite signal value or
+                               gradient (see btl_synchronize) */
 } btl_status;
 
 enum { BTL_PERIODIC = 0, BTL_MIRROR = 1 };   /* outer boundary per axis */
@@ -126,17 +134,29 @@ btl_status btl_create(const btl_geom *geoms, int32_t n_geom, int32_t prec,
  *   M_final device or NULL: the magnetization at t = K dt of every q-sample,
  *           complex in the storage precision (float2 or double2), q-samples
  *           concatenated, each [n2][n1][n0]
- *   ckpt_every  0: no adjoint tape; > 0: keep the state every ckpt_every
- *           steps so that btl_backward can run afterwards
+ *   ckpt_every  0: no adjoint tape; > 0: record a tape so that btl_backward
+ *           can run afterwards.  When ceil(K/C) + C + 4 states (C =
+ *           ckpt_every, one state = every field of every q-sample) fit the
+ *           memory budget (btl_set_memory_budget), the state is kept every
+ *           C steps; otherwise the tape is "deferred": only the inputs are
+ *           kept and btl_backward replays the forward from t = 0 (the
+ *           equilibrium at M = 1) in groups of q-samples with a binomial
+ *           checkpointing schedule sized to the budget.  The gradients are
+ *           the same either way.
  *   stream  hipStream_t or NULL
- * Errors: BTL_E_INVAL, BTL_E_NOMEM, BTL_E_HIP. */
+ * Batches whose two population copies exceed the budget run as consecutive
+ * groups of q-samples ("q-waves") on the stream.
+ * Errors: BTL_E_INVAL, BTL_E_UNSUPPORTED (a tape for a case the adjoint does
+ * not cover: see btl_backward), BTL_E_NOMEM, BTL_E_HIP, BTL_E_NONFINITE. */
 btl_status btl_forward(btl_sim *s, double dt, int32_t K, const double *D,
                        const double *T2, const double *kappa, int32_t Q,
                        const int32_t *q_geom, const double *gG0, const double *f,
                        double *E, void *M_final, int32_t ckpt_every, void *stream);
 
 /* Gradients of a real loss L with respect to the inputs of the last
- * btl_forward that kept a tape (ckpt_every > 0).  dL_dE is device
+ * btl_forward that kept a tape (ckpt_every > 0); the adjoint of the hybrid
+ * scheme (Sec. 2.3) with half-link membranes and at most 4 phases, on
+ * either lattice.  dL_dE is device
  * [Q][K+1][2] with dL/dE = dL/dRe E + i dL/dIm E.  Outputs are device
  * doubles, overwritten (NULL = not wanted): dD [P], dT2 [P], dkappa [P*P],
  * df [K] (or [K*m] with m reaction sub-steps: dL per waveform sample),
@@ -147,11 +167,24 @@ btl_status btl_forward(btl_sim *s, double dt, int32_t K, const double *D,
  * dkappa is the gradient per matrix entry: for a != b the entries
  * [a][b] and [b][a] each hold half of dL/dkappa_ab, so that a symmetric
  * parametrization (both entries set from one value) gets the full value.
+ * A deferred tape (see btl_forward) is reversed group by group; each group
+ * replays its forward with binomial checkpointing (repetition number t and
+ * s kept states reverse up to C(s + t, t) steps), so a backward can take a
+ * few times the forward's steps.
  * Errors: BTL_E_INVAL (no tape), BTL_E_UNSUPPORTED (dgG0 asked of a tape
- * whose field set is not the full one: see btl_set_grad_gG0), BTL_E_NOMEM,
- * BTL_E_HIP. */
+ * whose field set is not the full one: see btl_set_grad_gG0), BTL_E_NOMEM
+ * (one q-sample's reverse sweep exceeds the budget), BTL_E_HIP,
+ * BTL_E_NONFINITE. */
 btl_status btl_backward(btl_sim *s, const double *dL_dE, double *dD, double *dT2,
                         double *dkappa, double *df, double *dgG0, void *stream);
+
+/* What the last btl_backward of s did: the forward steps it recomputed, the
+ * groups of q-samples it reversed one after another, and the states kept
+ * per group by the binomial schedule (the smallest over the groups; 0 after
+ * a uniform tape).  Host pointers, written on success; no device call.
+ * Errors: BTL_E_INVAL (a NULL argument). */
+btl_status btl_get_backward_stats(const btl_sim *s, int64_t *fwd_steps, int32_t *groups,
+                                  int32_t *snapshots);
 
 /* Select the lattice of later btl_forward calls.  BTL_D3Q7 (default):
  * eps_D = 1/4, w_0 = 1/4, w_i = 1/8.  BTL_D2Q5: the two-dimensional lattice
@@ -201,13 +234,54 @@ btl_status btl_set_scheme(btl_sim *s, int32_t scheme);
  * the last btl_forward (its first Q q-samples, K_probe steps, waveform
  * repeated if shorter) and keeping the fastest.  Synchronizes the stream.
  * The probes are forwards of their own: the adjoint tape of an earlier
- * taped btl_forward is discarded.  Without autotuning a shape with the
- * fewest idle lanes and whole z columns is used.
+ * taped btl_forward is discarded.  The choice is remembered for the life of
+ * the process, keyed by device, storage precision, lattice, scheme and the
+ * sizes of the fields: a later call for the same shape of workload (on any
+ * simulator) takes it without timing.  Without autotuning (or
+ * btl_set_launch) a shape with the fewest idle lanes and whole z columns is
+ * used.
  * Errors: BTL_E_INVAL (no previous forward, K_probe < 1), BTL_E_NOMEM,
- * BTL_E_HIP. */
+ * BTL_E_HIP, BTL_E_NONFINITE. */
 btl_status btl_autotune(btl_sim *s, int32_t Q, int32_t K_probe, void *stream);
 
-/* The launch shape the forwards of s use, as set by btl_autotune: the tile
+/* Fix the launch shape of later forwards (as btl_autotune would set it):
+ * tile_shape 0..5 as in btl_get_launch (-1: chosen per call; 4 is the
+ * single-layer shape and 5 is for 3D lattices, other choices are replaced
+ * by one that fits the lattice), zc the sites per thread along z (0: whole
+ * columns, at most 1024), xcd the workgroup order (0 plain, 1
+ * XCD-contiguous, -1 by grid size).  Results do not depend on the launch
+ * shape beyond the order of floating-point sums.
+ * Errors: BTL_E_INVAL (a value out of range). */
+btl_status btl_set_launch(btl_sim *s, int32_t tile_shape, int32_t zc, int32_t xcd);
+
+/* Launch shape of the adjoint steps of later taped forwards: zc the sites
+ * per thread along z (-1: chosen from the grid size, 0: whole columns, at
+ * most 1024) and xcd the workgroup order (-1 by grid size, 0 plain, 1
+ * XCD-contiguous).  Errors: BTL_E_INVAL (a value out of range). */
+btl_status btl_set_adjoint_launch(btl_sim *s, int32_t zc, int32_t xcd);
+
+/* Limit the device memory, in bytes, that later calls plan population
+ * states into: the two copies of a forward (above it the q-samples run in
+ * q-waves), the uniform tape and the snapshots of a reverse sweep.  0 (the
+ * default) uses 85 % of the device memory that is free or already held by
+ * the simulator's states.  Errors: BTL_E_INVAL (bytes < 0). */
+btl_status btl_set_memory_budget(btl_sim *s, int64_t bytes);
+
+/* 1 (default): forwards of at least 16 steps are captured once into a
+ * hipGraph and replayed while their shape and buffers are unchanged (up to
+ * four graphs per simulator, e.g. one per q-wave size); 0: every launch is
+ * enqueued directly.  Results are identical either way.
+ * Errors: BTL_E_INVAL (on not 0 or 1). */
+btl_status btl_set_graphs(btl_sim *s, int32_t on);
+
+/* Wait for the work enqueued on stream, then report a non-finite signal or
+ * gradient produced since the last report (BTL_E_NONFINITE, which clears
+ * it).  Errors: BTL_E_HIP, BTL_E_NONFINITE. */
+btl_status btl_synchronize(btl_sim *s, void *stream);
+
+
+/* The launch shape the forwards of s use, as set by btl_autotune or
+ * btl_set_launch: the tile
  * shape (0 64x4, 1 32x8, 2 16x16, 3 128x2, 4 256x1, 5 runs of 256
  * consecutive sites; -1: chosen per call), the z-column length (0: whole
  * columns) and the workgroup order (0 plain, 1 XCD-contiguous; -1: by grid

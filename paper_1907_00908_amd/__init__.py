@@ -1,12 +1,10 @@
 """Python binding of libbtlbm (hybrid LBM Bloch-Torrey solver for gfx950).
 
 Argument marshalling only: every step of the computation runs in the HIP
-kernels of libbtlbm.so.  The functions `btl_create`, `btl_forward`,
-`btl_backward`, `btl_set_scheme`, `btl_set_lattice`, `btl_set_substeps`,
-`btl_set_grad_gG0`, `btl_autotune`, `btl_get_launch`, `btl_destroy` and
-`btl_last_error` mirror the
-C ABI of include/btlbm.h one to one.  `Simulator` wraps them with torch
-tensors for device memory and the current torch stream.
+kernels of libbtlbm.so.  The `btl_*` functions below mirror the C ABI of
+include/btlbm.h one to one (the names are listed in EXPORTED).  `Simulator`
+wraps them with torch tensors for device memory and the current torch
+stream.
 
 There is no CPU fallback: if libbtlbm.so is missing or fails to load, every
 call raises.
@@ -28,9 +26,11 @@ BTL_F64, BTL_F32 = 0, 1
 BTL_HYBRID, BTL_CLASSICAL = 0, 1
 BTL_D3Q7, BTL_D2Q5 = 0, 1
 
-EXPORTED = ("btl_create", "btl_forward", "btl_backward", "btl_set_scheme",
-            "btl_set_lattice", "btl_set_substeps", "btl_set_grad_gG0", "btl_autotune",
-            "btl_get_launch", "btl_destroy", "btl_last_error")
+EXPORTED = ("btl_create", "btl_forward", "btl_backward",
+            "btl_get_backward_stats", "btl_set_scheme", "btl_set_lattice", "btl_set_substeps",
+            "btl_set_grad_gG0", "btl_autotune", "btl_set_launch", "btl_set_adjoint_launch",
+            "btl_set_memory_budget", "btl_set_graphs", "btl_get_launch", "btl_synchronize",
+            "btl_destroy", "btl_last_error")
 
 
 class BtlError(RuntimeError):
@@ -69,6 +69,19 @@ def load_library(path: str = None):
     lib.btl_forward.restype = ctypes.c_int
     lib.btl_backward.argtypes = [P, P, P, P, P, P, P, P]
     lib.btl_backward.restype = ctypes.c_int
+    lib.btl_get_backward_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.btl_get_backward_stats.restype = ctypes.c_int
+    lib.btl_set_launch.argtypes = [P, i32, i32, i32]
+    lib.btl_set_launch.restype = ctypes.c_int
+    lib.btl_set_adjoint_launch.argtypes = [P, i32, i32]
+    lib.btl_set_adjoint_launch.restype = ctypes.c_int
+    lib.btl_set_memory_budget.argtypes = [P, ctypes.c_int64]
+    lib.btl_set_memory_budget.restype = ctypes.c_int
+    lib.btl_set_graphs.argtypes = [P, i32]
+    lib.btl_set_graphs.restype = ctypes.c_int
+    lib.btl_synchronize.argtypes = [P, P]
+    lib.btl_synchronize.restype = ctypes.c_int
     lib.btl_set_scheme.argtypes = [P, i32]
     lib.btl_set_scheme.restype = ctypes.c_int
     lib.btl_set_lattice.argtypes = [P, i32]
@@ -134,10 +147,7 @@ def btl_create(geoms, prec: int):
     return h
 
 
-def btl_forward(h, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E_ptr, M_ptr,
-                ckpt_every, stream_ptr, substeps=1):
-    """f must hold K * substeps samples (substeps as set on the handle)."""
-    lib = load_library()
+def _forward_args(K, D, T2, kappa, Q, q_geom, gG0, f, substeps):
     if len(f) < int(K) * int(substeps):
         raise ValueError("f needs K * substeps samples")
     D = np.ascontiguousarray(D, np.float64)
@@ -148,6 +158,16 @@ def btl_forward(h, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E_ptr, M_ptr,
     f = np.ascontiguousarray(f, np.float64)
     if q_geom.size < int(Q) or gG0.size < 3 * int(Q):
         raise ValueError("q_geom needs Q entries and gG0 Q x 3")
+    if D.size != T2.size or kappa.size != D.size * D.size:
+        raise ValueError("D and T2 need n_phase values, kappa n_phase x n_phase")
+    return D, T2, kappa, q_geom, gG0, f
+
+
+def btl_forward(h, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E_ptr, M_ptr,
+                ckpt_every, stream_ptr, substeps=1):
+    """f must hold K * substeps samples (substeps as set on the handle)."""
+    lib = load_library()
+    D, T2, kappa, q_geom, gG0, f = _forward_args(K, D, T2, kappa, Q, q_geom, gG0, f, substeps)
     st = lib.btl_forward(h, float(dt), int(K), _np_ptr(D), _np_ptr(T2), _np_ptr(kappa),
                          int(Q), _np_ptr(q_geom), _np_ptr(gG0), _np_ptr(f),
                          ctypes.c_void_p(E_ptr), ctypes.c_void_p(M_ptr) if M_ptr else None,
@@ -160,6 +180,36 @@ def btl_backward(h, dLdE_ptr, dD_ptr, dT2_ptr, dkappa_ptr, df_ptr, dgG0_ptr, str
     V = lambda p: ctypes.c_void_p(p) if p else None  # noqa: E731
     _check(lib.btl_backward(h, V(dLdE_ptr), V(dD_ptr), V(dT2_ptr), V(dkappa_ptr),
                             V(df_ptr), V(dgG0_ptr), V(stream_ptr)), h)
+
+
+def btl_get_backward_stats(h):
+    """(forward steps recomputed, groups of q-samples, snapshots per group)
+    of the last btl_backward."""
+    lib = load_library()
+    a, b, c = ctypes.c_int64(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib.btl_get_backward_stats(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), h)
+    return int(a.value), int(b.value), int(c.value)
+
+
+def btl_set_launch(h, tile_shape, zc, xcd):
+    _check(load_library().btl_set_launch(h, int(tile_shape), int(zc), int(xcd)), h)
+
+
+def btl_set_adjoint_launch(h, zc, xcd):
+    _check(load_library().btl_set_adjoint_launch(h, int(zc), int(xcd)), h)
+
+
+def btl_set_memory_budget(h, nbytes):
+    _check(load_library().btl_set_memory_budget(h, int(nbytes)), h)
+
+
+def btl_set_graphs(h, on):
+    _check(load_library().btl_set_graphs(h, int(on)), h)
+
+
+def btl_synchronize(h, stream_ptr):
+    lib = load_library()
+    _check(lib.btl_synchronize(h, ctypes.c_void_p(stream_ptr) if stream_ptr else None), h)
 
 
 def btl_set_scheme(h, scheme):
@@ -216,7 +266,11 @@ class Simulator:
     """Owns one btl_sim.  Device memory for E and M_final comes from torch."""
 
     def __init__(self, geoms, bc, prec: str = "f32", scheme: int = BTL_HYBRID,
-                 substeps: int = 1, lattice: int = BTL_D3Q7, grad_gG0: bool = False):
+                 substeps: int = 1, lattice: int = BTL_D3Q7, grad_gG0: bool = False,
+                 launch=None, adjoint_launch=None, mem_budget: int = 0, graphs: bool = True):
+        """launch: (tile_shape, zc, xcd) for btl_set_launch; adjoint_launch:
+        (zc, xcd) for btl_set_adjoint_launch; mem_budget: bytes for
+        btl_set_memory_budget (0: none); graphs: btl_set_graphs."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Simulator needs a HIP device")
@@ -235,9 +289,20 @@ class Simulator:
         self.grad_gG0 = bool(grad_gG0)
         if self.grad_gG0:
             btl_set_grad_gG0(self._h, 1)
+        if launch is not None:
+            btl_set_launch(self._h, *launch)
+        if adjoint_launch is not None:
+            btl_set_adjoint_launch(self._h, *adjoint_launch)
+        if mem_budget:
+            btl_set_memory_budget(self._h, mem_budget)
+        if not graphs:
+            btl_set_graphs(self._h, 0)
         # number of forwards so far, and which of them holds the adjoint tape
+        # (with its q-sample count and steps: the sizes btl_backward reads
+        # and writes)
         self._n_forward = 0
         self.tape_id = None
+        self._tape_QK = None
 
     def set_grad_gG0(self, on: bool):
         """Plan taped forwards for the gamma G0 gradient (btl_set_grad_gG0)."""
@@ -280,11 +345,13 @@ class Simulator:
             M = torch.empty((tot, 2), dtype=dt_, device=dev)
         stream = torch.cuda.current_stream().cuda_stream
         self.tape_id = None
+        self._tape_QK = None
         btl_forward(self._h, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E.data_ptr(),
                     M.data_ptr() if M is not None else 0, ckpt_every, stream, self.substeps)
         self._n_forward += 1
         if ckpt_every > 0 and K > 0:
             self.tape_id = self._n_forward
+            self._tape_QK = (Q, K)
         Ec = torch.view_as_complex(E)
         if not want_M:
             return Ec
@@ -298,13 +365,23 @@ class Simulator:
         return Ec, Ms
 
 
-    def backward(self, dLdE, P: int, K: int, grad_gG0: bool = False):
+    def backward(self, dLdE, P: int = None, K: int = None, grad_gG0: bool = False):
         """Gradients of a real loss from dL/dE (torch (Q, K+1, 2) float64 on
         the device: dL/dRe E, dL/dIm E) for the last forward that kept a tape.
-        K is the number of steps of that forward.  Returns device tensors
-        dD [P], dT2 [P], dkappa [P, P], df [K * substeps] (one entry per
-        waveform sample), and with grad_gG0 also dgG0 [Q, 3]."""
+        The sizes come from that forward (P, K, when given, must match it).
+        Returns device tensors dD [P], dT2 [P], dkappa [P, P], df
+        [K * substeps] (one entry per waveform sample), and with grad_gG0 also
+        dgG0 [Q, 3]."""
         torch = self.torch
+        if self._tape_QK is None:
+            raise RuntimeError("no adjoint tape: run forward with ckpt_every > 0 first")
+        Q, Kt = self._tape_QK
+        Pt = self.geoms[0].n_phase
+        if (P is not None and int(P) != Pt) or (K is not None and int(K) != Kt):
+            raise ValueError(f"the taped forward has n_phase {Pt} and K {Kt}")
+        P, K = Pt, Kt
+        if tuple(dLdE.shape) != (Q, K + 1, 2):
+            raise ValueError(f"dLdE must have shape ({Q}, {K + 1}, 2)")
         dev = dLdE.device
         g = dLdE.detach().to(torch.float64).contiguous()
         dD = torch.empty(P, dtype=torch.float64, device=dev)
@@ -312,7 +389,7 @@ class Simulator:
         dk = torch.empty((P, P), dtype=torch.float64, device=dev)
         nf = K * self.substeps
         df = torch.empty(max(nf, 1), dtype=torch.float64, device=dev)
-        dG = torch.empty((g.shape[0], 3), dtype=torch.float64, device=dev) if grad_gG0 else None
+        dG = torch.empty((Q, 3), dtype=torch.float64, device=dev) if grad_gG0 else None
         stream = torch.cuda.current_stream().cuda_stream
         btl_backward(self._h, g.data_ptr(), dD.data_ptr(), dT2.data_ptr(), dk.data_ptr(),
                      df.data_ptr(), dG.data_ptr() if grad_gG0 else None, stream)
@@ -387,15 +464,17 @@ def bloch_torrey_signal(D, T2, kappa, f, sim, dt, gG0, q_geom=None, ckpt_every=1
     return _BTS.apply(D, T2, kappa, f, sim, dt, gG0, q_geom, ckpt_every)
 
 
-def simulate_config(cfg: dict, prec: str = "f32", want_M: bool = False, scheme=None):
+def simulate_config(cfg: dict, prec: str = "f32", want_M: bool = False, scheme=None,
+                    **options):
     """Run a workloads config on the GPU: returns E (Q, K+1) complex (and M).
     The scheme is `scheme`, else the config's "scheme" entry, else hybrid;
     the config's "substeps" entry (default 1) sets reaction sub-steps and its
-    "lattice" entry (default D3Q7) the lattice."""
+    "lattice" entry (default D3Q7) the lattice.  options go to Simulator
+    (launch, mem_budget, graphs, ...)."""
     if scheme is None:
         scheme = cfg.get("scheme", BTL_HYBRID)
     sim = Simulator(cfg["geoms"], cfg["bc"], prec, scheme, cfg.get("substeps", 1),
-                    cfg.get("lattice", BTL_D3Q7))
+                    cfg.get("lattice", BTL_D3Q7), **options)
     try:
         out = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"],
                           cfg["gG0"], cfg["q_geom"], want_M=want_M)

@@ -1,6 +1,9 @@
 """Build libbtlbm.so in-tree with hipcc for gfx950.
 
 Usage: python -m paper_1907_00908_amd.build
+
+Each HIP source is compiled to an object file of its own (in parallel), then
+the objects are linked into the shared library.
 """
 from __future__ import annotations
 
@@ -8,6 +11,8 @@ import os
 import shutil
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -25,24 +30,39 @@ def hipcc() -> str:
 
 
 def flags() -> list:
-    return ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+    return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             # no packed FP32 instructions in device code
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into libbtlbm.so (always recompiles)."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + flags() + ["-o", tmp] + srcs
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libbtlbm.so")
-    os.replace(tmp, LIB)
+    return subprocess.run(cmd, capture_output=True, text=True)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP source and link libbtlbm.so (always recompiles)."""
+    with tempfile.TemporaryDirectory(prefix="btlbm_build_") as tmpd:
+        objs, cmds = [], []
+        for s in SOURCES:
+            o = os.path.join(tmpd, os.path.splitext(s)[0] + ".o")
+            objs.append(o)
+            cmds.append([hipcc()] + flags() + ["-c", "-o", o, os.path.join(CSRC, s)])
+        with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+            results = list(ex.map(lambda c: _run(c, verbose), cmds))
+        for r in results:
+            if r.returncode != 0:
+                sys.stderr.write(r.stdout + r.stderr)
+                raise RuntimeError("hipcc failed building libbtlbm.so")
+        tmp = LIB + ".tmp"
+        r = _run([hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs,
+                 verbose)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("hipcc failed linking libbtlbm.so")
+        os.replace(tmp, LIB)
     return LIB
 
 

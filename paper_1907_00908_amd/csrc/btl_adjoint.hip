@@ -449,7 +449,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_gsum(const double* __restrict__ 
                                                      const FieldDesc* __restrict__ fields,
                                                      int32_t n_fields, int32_t nblk_total,
                                                      int32_t ng, int32_t k_first, int32_t nsteps,
-                                                     double* gfield) {
+                                                     double* gfield, int32_t f_off,
+                                                     int32_t nf_total) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= (int64_t)nsteps * n_fields * ng) return;
     const int32_t g = (int32_t)(t % ng);
@@ -459,7 +460,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_gsum(const double* __restrict__ 
     const double* p = gpart + ((int64_t)j * nblk_total + fd.blk0) * ng + g;
     double sacc = 0.0;
     for (int32_t i = 0; i < fd.nblk; ++i) sacc += p[(int64_t)i * ng];
-    gfield[((int64_t)(k_first + j) * n_fields + f) * ng + g] = sacc;
+    gfield[((int64_t)(k_first + j) * nf_total + f_off + f) * ng + g] = sacc;
 }
 
 // Sums the per-step, per-field records in a fixed order and maps them to the
@@ -481,7 +482,7 @@ k_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P, double
             const double* w, const double* T2, const double* kappa, double* dD, double* dT2,
             double* dkappa, double* df, int32_t sub, int32_t NG, const double* gmeta,
             const double* fdt, const double* Fk, int32_t Q, double* dgG0, double eps,
-            int32_t yz_swap) {
+            int32_t yz_swap, int32_t* nonfinite) {
     constexpr int NW = kFinalBlock / 64;
     __shared__ double red[NW];
     __shared__ double tot[2 * kAdjMaxPhase + kAdjMaxPhase * kAdjMaxPhase];
@@ -503,15 +504,21 @@ k_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P, double
         }
         __syncthreads();
     }
+    // a non-finite gradient is reported to the host (sticky flag)
+    auto flag = [nonfinite](double v) {
+        if (nonfinite != nullptr && !isfinite(v)) *nonfinite = 1;
+    };
     if (t < P) {
         if (dD) {
             const double wp = w[t];
             dD[t] = tot[t] * (-wp * wp * dt / (eps * dx * dx));
+            flag(dD[t]);
         }
         if (dT2) {
             const double T = T2[t];
             const double dec = isinf(T) ? 1.0 : exp(-dt / T);
             dT2[t] = isinf(T) ? 0.0 : tot[P + t] * dec * dt / (T * T);
+            flag(dT2[t]);
         }
     }
     if (t < P * P && dkappa) {
@@ -524,6 +531,7 @@ k_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P, double
         // t = 2 k dt / (eps_D dx + 2 k dt)
         const double den = eps * dx + 2.0 * k * dt;
         dkappa[t] = isinf(k) ? 0.0 : g * 2.0 * dt * eps * dx / (den * den);
+        flag(dkappa[t]);
     }
     if (df) {   // the same for every thread: the barriers below are uniform
         const int IF = 2 * P + P * P, IFF = IF + 1;
@@ -549,6 +557,7 @@ k_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P, double
         for (int32_t m = m1 - 1; m >= m0; --m) {
             const double v = (field_sum(m, IF) + dt * suffix) / sub;
             for (int j = 0; j < sub; ++j) df[(int64_t)m * sub + j] = v;
+            flag(v);
             suffix += field_sum(m, IFF);
         }
     }
@@ -576,7 +585,10 @@ k_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P, double
             // (its z component is not a parameter there: the layer has no
             // extent along z, and the input must be 0; reported as 0)
             const int bg = yz_swap ? (b == 1 ? 2 : b == 2 ? 1 : 0) : b;
-            if (lane == 0) dgG0[3 * q + bg] = (yz_swap && bg == 2) ? 0.0 : acc;
+            if (lane == 0) {
+                dgG0[3 * q + bg] = (yz_swap && bg == 2) ? 0.0 : acc;
+                flag(acc);
+            }
         }
     }
 }
@@ -618,12 +630,12 @@ hipError_t launch_adj(int prec, int shape, const AdjArgs& a, int32_t n_blocks, h
 
 hipError_t launch_adj_gsum(const double* gpart, const FieldDesc* d_fields, int32_t n_fields,
                            int32_t nblk_total, int32_t ng, int32_t k_first, int32_t nsteps,
-                           double* gfield, hipStream_t st) {
+                           double* gfield, int32_t f_off, int32_t nf_total, hipStream_t st) {
     const int64_t n = (int64_t)nsteps * n_fields * ng;
     if (n > 0)
         hipLaunchKernelGGL(k_adj_gsum, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
                            0, st, gpart, d_fields, n_fields, nblk_total, ng, k_first, nsteps,
-                           gfield);
+                           gfield, f_off, nf_total);
     return hipGetLastError();
 }
 
@@ -632,10 +644,10 @@ hipError_t launch_adj_final(const double* gfield, int32_t K, int32_t n_fields, i
                             const double* kappa, double* dD, double* dT2, double* dkappa,
                             double* df, int32_t sub, int32_t ng, const double* gmeta,
                             const double* fdt, const double* Fk, int32_t Q, double* dgG0,
-                            double eps, int32_t yz_swap, hipStream_t st) {
+                            double eps, int32_t yz_swap, int32_t* nonfinite, hipStream_t st) {
     hipLaunchKernelGGL(k_adj_final, dim3(1), dim3(kFinalBlock), 0, st, gfield, K, n_fields, P, dt, dx,
                        w, T2, kappa, dD, dT2, dkappa, df, sub, ng, gmeta, fdt, Fk, Q, dgG0,
-                       eps, yz_swap);
+                       eps, yz_swap, nonfinite);
     return hipGetLastError();
 }
 

@@ -162,19 +162,21 @@ inline void tile_grid(int shape, int32_t n0, int32_t n1, int32_t* t0, int32_t* t
 
 // Launchers (btl_kernels.hip, btl_adjoint.hip)
 hipError_t launch_adj(int prec, int shape, const AdjArgs& a, int32_t n_blocks, hipStream_t st);
-// gfield[(k_first + j) * n_fields + f][g] = sum over the workgroups of field f
-// of gpart[j][.][g], j = 0 .. nsteps - 1, in a fixed order
+// gfield[(k_first + j) * nf_total + f_off + f][g] = sum over the workgroups of
+// field f of gpart[j][.][g], j = 0 .. nsteps - 1, in a fixed order (f_off:
+// position of the call's first field in a record that spans several calls)
 hipError_t launch_adj_gsum(const double* gpart, const FieldDesc* d_fields, int32_t n_fields,
                            int32_t nblk_total, int32_t ng, int32_t k_first, int32_t nsteps,
-                           double* gfield, hipStream_t st);
+                           double* gfield, int32_t f_off, int32_t nf_total, hipStream_t st);
 // dgG0 (device [Q][3] or NULL) needs gmeta (device [n_fields][kGMeta]) and
-// the per-step angles fdt [K] and F [K]
+// the per-step angles fdt [K] and F [K].  A non-finite gradient sets
+// *nonfinite (device-visible, may be NULL).
 hipError_t launch_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P,
                             double dt, double dx, const double* w, const double* T2,
                             const double* kappa, double* dD, double* dT2, double* dkappa,
                             double* df, int32_t sub, int32_t ng, const double* gmeta,
                             const double* fdt, const double* Fk, int32_t Q, double* dgG0,
-                            double eps, int32_t yz_swap, hipStream_t st);
+                            double eps, int32_t yz_swap, int32_t* nonfinite, hipStream_t st);
 hipError_t launch_init(int prec, void* pop, int64_t n_elem_per_dir_total,
                        const FieldDesc* d_fields, int32_t n_fields,
                        const FieldDesc* h_fields, double* E, int32_t Q, int32_t K, int32_t nq,
@@ -188,10 +190,11 @@ hipError_t launch_init_classical(int prec, void* pop, const FieldDesc* h_fields,
 // phase tables of steps a.k .. a.k + nsteps - 1 into a.tab[0 .. nsteps*T)
 hipError_t launch_tables(const StepArgs& a, int32_t nsteps, hipStream_t st);
 // signal E_{k+1} of steps k = k0 .. k0 + nsteps - 1 (nsteps <= kTabSteps) from
-// the per-wave partial sums the step kernels left in partial
+// the per-wave partial sums the step kernels left in partial; a non-finite
+// signal value sets *nonfinite (device-visible, may be NULL)
 hipError_t launch_esum(const double2* partial, const FieldDesc* d_fields, int32_t n_fields,
                        int32_t nblk_total, int32_t k0, int32_t nsteps, double* E, int32_t K,
-                       hipStream_t st);
+                       int32_t* nonfinite, hipStream_t st);
 hipError_t launch_mfinal(int prec, const void* pop, const FieldDesc* h_fields,
                          int32_t n_fields, void* M_out, int32_t nq, hipStream_t st);
 

@@ -466,7 +466,7 @@ __global__ void __launch_bounds__(kBlock) k_esum(const double2* __restrict__ par
                                                  const FieldDesc* __restrict__ fields,
                                                  int32_t n_fields, int32_t nblk_total,
                                                  int32_t k0, int32_t nsteps, double2* E,
-                                                 int32_t K) {
+                                                 int32_t K, int32_t* nonfinite) {
     const int32_t pair = (int32_t)blockIdx.x * (kBlock / 64) + (int32_t)(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (pair >= n_fields * nsteps) return;   // whole waves leave together
@@ -485,7 +485,10 @@ __global__ void __launch_bounds__(kBlock) k_esum(const double2* __restrict__ par
     sy = wave_sum(sy);
     if (lane == 0) {
         const double inv = 1.0 / (double)fd.nsites;
-        E[(int64_t)fd.q * (K + 1) + k + 1] = make_double2(sx * inv, sy * inv);
+        const double ex = sx * inv, ey = sy * inv;
+        E[(int64_t)fd.q * (K + 1) + k + 1] = make_double2(ex, ey);
+        // sticky report for the host (btl_synchronize and later calls)
+        if (nonfinite != nullptr && !(isfinite(ex) && isfinite(ey))) *nonfinite = 1;
     }
 }
 
@@ -630,12 +633,12 @@ hipError_t launch_init_classical(int prec, void* pop, const FieldDesc* h, int32_
 
 hipError_t launch_esum(const double2* partial, const FieldDesc* d_fields, int32_t n_fields,
                        int32_t nblk_total, int32_t k0, int32_t nsteps, double* E, int32_t K,
-                       hipStream_t st) {
+                       int32_t* nonfinite, hipStream_t st) {
     const int64_t waves = (int64_t)n_fields * nsteps;
     if (waves > 0)
         hipLaunchKernelGGL(k_esum, dim3((unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64))),
                            dim3(kBlock), 0, st, partial, d_fields, n_fields, nblk_total, k0,
-                           nsteps, reinterpret_cast<double2*>(E), K);
+                           nsteps, reinterpret_cast<double2*>(E), K, nonfinite);
     return hipGetLastError();
 }
 

@@ -5,12 +5,19 @@
 // builds the field table (one field per q-sample plus reflected image fields
 // where a mirrored face sees an oblique gradient), and enqueues one step
 // launch per time step on the caller's stream.
+//
+// A call is first planned on the host (CallPlan: field and workgroup tables,
+// per-step waveform sums, constants), then given device buffers (CallBufs),
+// then its tables are uploaded and its launches enqueued.  Reverse sweeps that do not fit a uniform checkpoint tape replay
+// the forward from t = 0 per group of q-samples with a binomial
+// checkpointing schedule (plan_reversal).
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,7 +27,6 @@
 using namespace btl;
 
 namespace {
-
 
 struct GeomHost {
     int32_t n[3];
@@ -48,19 +54,28 @@ struct DevBuf {
         p = nullptr;
         cap = 0;
     }
+    size_t bytes() const { return cap * sizeof(T); }
 };
 
 std::string g_create_error;
 
 constexpr int kGraphMinSteps = 16;   // forwards this long run from a cached hipGraph
+constexpr int kGraphSlots = 4;       // cached forward graphs per simulator
 constexpr int kXcdMinBlocks = 2048;  // grids above this use the XCD-contiguous order
+constexpr size_t kStageInit = (size_t)1 << 20;   // pinned staging per slot at creation
 
 // Everything a captured forward depends on besides the contents of its
-// buffers; a forward replays the cached graph only when this matches.
+// buffers; a forward replays a cached graph only when this matches.
 struct GraphKey {
     int32_t prec, K, Q, n_fields, nblk, shape, T, ckpt, scheme, nq, xcd;
     uint64_t fields;     // hash of the per-field values the launches take by value
     const void* ptr[16];
+};
+
+struct GraphSlot {
+    hipGraphExec_t exec = nullptr;
+    GraphKey key;
+    uint64_t used = 0;   // last use (least recently used slot is replaced)
 };
 
 // FNV-1a over the field-table entries that the captured launches take as
@@ -91,14 +106,37 @@ uint64_t field_hash(const std::vector<FieldDesc>& fl, bool classical) {
     return h;
 }
 
+// Settings that shape a call besides its arguments (the btl_set_* calls and
+// the autotuner's choice).  A taped forward keeps a copy, so that a reverse
+// sweep replays it exactly.
+struct Settings {
+    int scheme = BTL_HYBRID;
+    int msub = 1;          // reaction sub-steps per step
+    int nq = 7;            // 7 (D3Q7) or 5 (D2Q5 on single-layer geometries)
+    int grad_g = 0;        // taped forwards plan the full field set (gamma G0 gradient)
+    int tile_shape = -1;   // forward launch: -1 chosen per call
+    int zc = 0;            //   sites per thread along z, 0 whole columns
+    int xcd = -1;          //   workgroup order, -1 by grid size
+    int adj_zc = -1;       // adjoint launch: -1 automatic, 0 whole columns, > 0 sites
+    int adj_xcd = -1;      //   workgroup order, -1 by grid size
+};
+
+// Autotuner results of this process, by device and workload shape: a later
+// simulator with the same shape takes the launch without timing it again.
+struct TuneEntry {
+    std::string key;
+    int shape, zc, xcd;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune_cache;
+
 }  // namespace
 
 struct btl_sim {
     int prec = BTL_F32;
-    int scheme = BTL_HYBRID;
-    int substeps = 1;            // reaction sub-steps per step (waveform samples per step)
-    int grad_g = 0;              // 1: taped forwards plan fields for the gamma G0 gradient
-    int nq = 7;                  // lattice: 7 (D3Q7) or 5 (D2Q5 on single-layer geometries)
+    Settings set;
+    int use_graphs = 1;          // forwards of >= kGraphMinSteps steps replay cached graphs
+    int64_t mem_limit = 0;       // btl_set_memory_budget (0: none)
     int device = 0;
     double dx = 1.0;
     int32_t n_phase = 1;
@@ -109,16 +147,15 @@ struct btl_sim {
     DevBuf<FieldDesc> fields;
     DevBuf<int32_t> blk_field;
     DevBuf<double> steps;        // fdt [K] then Fk [K+1]
-    DevBuf<double> consts;       // w [P], decay [P], trans [P*P], T2 [P], kappa [P*P], dt/T2 [P]
+    DevBuf<double> consts;       // w [P], decay [P], trans [P*P], T2 [P], kappa [P*P], dt/T2 [P], kappa dt [P*P]
     DevBuf<double2> partial;     // per-wave signal partials of kTabSteps steps
     DevBuf<double2> tab;         // [kTabSteps][T] per-step phase tables
     DevBuf<int32_t> tab_field;   // [T]
-    std::vector<FieldDesc> h_fields;
     // launch geometry of the adjoint steps (the forward's tile shape with
     // its own z-column length)
     DevBuf<FieldDesc> adj_fields;
     DevBuf<int32_t> adj_blk;
-    DevBuf<double> adj_gmeta;      // [fields][kGMeta] for the gamma G0 gradient
+    DevBuf<double> adj_gmeta;    // [fields][kGMeta] for the gamma G0 gradient
     // pinned staging for the per-call tables, two slots so that a call can
     // be prepared while the previous one's uploads are still queued
     char* stage[2] = {nullptr, nullptr};
@@ -126,14 +163,14 @@ struct btl_sim {
     hipEvent_t stage_ev[2] = {nullptr, nullptr};
     bool stage_used[2] = {false, false};
     int stage_slot = 0;
-    // cached forward graph
-    hipGraphExec_t graph_exec = nullptr;
-    GraphKey graph_key;
+    // non-finite report: host-visible flag the signal and gradient kernels set
+    int32_t* nf_host = nullptr;
+    int32_t* nf_dev = nullptr;
+    // cached forward graphs
+    GraphSlot graphs[kGraphSlots];
+    uint64_t graph_clock = 0;
     hipStream_t cap_stream = nullptr;
     DevBuf<double> E_int;
-    int tile_shape = -1;        // -1: pick per call from the geometry sizes
-    int xcd = -1;               // workgroup order: -1 by grid size, 0 plain, 1 XCD-contiguous
-    int zc = 0;                 // sites per thread along z; 0: whole column
     // inputs of the last forward call (the autotuner replays them)
     struct SimLastT {
         bool valid = false;
@@ -146,19 +183,28 @@ struct btl_sim {
     // adjoint tape of the last forward that asked for one
     struct Tape {
         bool valid = false;
+        bool deferred = false;     // no states kept: btl_backward replays from t = 0
+        Settings set;              // settings of the taped forward
         int32_t K = 0, C = 0, Q = 0, T = 0, n_fields = 0, nblk = 0, shape = 0, sub = 1, xcd = 0;
         int32_t nblk_adj = 0;      // workgroups of one adjoint step (adj_fields)
         int32_t nq = 7;            // lattice of the taped forward
         bool g_ok = false;         // the field set supports the gamma G0 gradient
         double dt = 0;
         int64_t state_elems = 0;   // V elements of one full state (all fields)
+        // inputs of a deferred tape
+        std::vector<double> D, T2, kappa, gG0, f;
+        std::vector<int32_t> q_geom;
     } tape;
-    DevBuf<char> ckpt;             // [ceil(K/C)] states: ghat^{mC}
+    DevBuf<char> ckpt;             // uniform tape: [ceil(K/C)] states ghat^{mC}; deferred: snapshots
     DevBuf<char> seg;              // [C] states of the segment being reversed
     DevBuf<char> lam[2];
-    DevBuf<double2> tab_b;         // [C+1][T] phase tables of a segment
+    DevBuf<double2> tab_b;         // phase tables of a segment
     DevBuf<double> gpart;
     DevBuf<double> gfield;
+    // statistics of the last reverse sweep (btl_get_backward_stats)
+    int64_t stat_fwd_steps = 0;    // forward steps run by the reverse sweep
+    int32_t stat_waves = 0;        // groups of q-samples reversed one after another
+    int32_t stat_snapshots = 0;    // states kept per group (binomial schedule), 0: uniform tape
     std::string err;
 };
 
@@ -303,6 +349,7 @@ static bool build_gm(const btl_geom& g, std::vector<float>& out) {
     return true;
 }
 
+
 extern "C" btl_status btl_create(const btl_geom* geoms, int32_t n_geom, int32_t prec,
                                  btl_sim** out) {
     if (!out) return fail(nullptr, BTL_E_INVAL, "out is NULL");
@@ -361,6 +408,7 @@ extern "C" btl_status btl_create(const btl_geom* geoms, int32_t n_geom, int32_t 
         }
         s->geoms.push_back(h);
     }
+    const char* what = "uploading site words";
     hipError_t e = s->words.ensure(all.size());
     if (e == hipSuccess)
         e = hipMemcpy(s->words.p, all.data(), all.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
@@ -369,8 +417,27 @@ extern "C" btl_status btl_create(const btl_geom* geoms, int32_t n_geom, int32_t 
         if (e == hipSuccess)
             e = hipMemcpy(s->gm.p, gm_all.data(), gm_all.size() * sizeof(float), hipMemcpyHostToDevice);
     }
+    // the non-finite flag (pinned, mapped into the device's address space),
+    // the pinned staging slots and their events
+    if (e == hipSuccess) {
+        what = "allocating the non-finite flag";
+        e = hipHostMalloc((void**)&s->nf_host, sizeof(int32_t),
+                          hipHostMallocMapped | hipHostMallocCoherent);
+        if (e == hipSuccess) {
+            *s->nf_host = 0;
+            e = hipHostGetDevicePointer((void**)&s->nf_dev, s->nf_host, 0);
+        }
+    }
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        what = "allocating pinned staging";
+        e = hipHostMalloc((void**)&s->stage[i], kStageInit, hipHostMallocDefault);
+        if (e == hipSuccess) {
+            s->stage_cap[i] = kStageInit;
+            e = hipEventCreateWithFlags(&s->stage_ev[i], hipEventDisableTiming);
+        }
+    }
     if (e != hipSuccess) {
-        btl_status st = hip_fail(nullptr, e, "uploading site words");
+        btl_status st = hip_fail(nullptr, e, what);
         btl_destroy(s);
         return st;
     }
@@ -431,17 +498,30 @@ static QFields plan_fields(const GeomHost& g, const double* G, bool classical, b
     return r;
 }
 
-static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D,
-                               const double* T2, const double* kappa, int32_t Q,
-                               const int32_t* q_geom, const double* gG0, const double* f,
-                               double* E, void* M_final, int32_t ckpt_every, void* stream) {
-    if (!s) return BTL_E_INVAL;
+
+// Everything a call computes on the host before touching the device.
+struct CallPlan {
+    int32_t K = 0, Q = 0, P = 0, nq = 7, msub = 1;
+    double dt = 0.0;
+    bool classical = false, uses_gm = false, taping = false, g_complete = true;
+    int shape = 0, xcd_on = 0;
+    int32_t n_fields = 0, nblk_total = 0, nblk_adj = 0, T = 0;
+    int64_t pop_elems = 0;       // V elements of one state (all fields of the call)
+    std::vector<double> consts, steps, gmeta;
+    std::vector<FieldDesc> fl, afl;
+    std::vector<int32_t> blk, ablk, tabf;
+};
+
+// Checks of a forward's arguments that need no device call.
+static btl_status validate_inputs(btl_sim* s, const Settings& cs, double dt, int32_t K,
+                                  const double* D, const double* T2, const double* kappa,
+                                  int32_t Q, const int32_t* q_geom, const double* gG0,
+                                  const double* f, const double* E) {
     if (!(dt > 0) || !isfinite(dt)) return fail(s, BTL_E_INVAL, "dt must be finite and > 0");
     if (K < 0) return fail(s, BTL_E_INVAL, "K must be >= 0");
     if (Q < 1) return fail(s, BTL_E_INVAL, "Q must be >= 1");
     if (!D || !T2 || !kappa || !q_geom || !gG0 || (K > 0 && !f) || !E)
         return fail(s, BTL_E_INVAL, "NULL argument");
-    if (ckpt_every < 0) return fail(s, BTL_E_INVAL, "ckpt_every must be >= 0");
     const int32_t P = s->n_phase;
     for (int p = 0; p < P; ++p) {
         if (!(D[p] > 0) || !isfinite(D[p])) return fail(s, BTL_E_INVAL, "D must be finite and > 0");
@@ -453,33 +533,67 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
             if (!(k >= 0)) return fail(s, BTL_E_INVAL, "kappa must be >= 0");
             if (k != kappa[b * P + a]) return fail(s, BTL_E_INVAL, "kappa must be symmetric");
         }
-    const int32_t msub = s->substeps;
-    const int32_t nq = s->nq;
-    const double eps = lattice_eps(nq);
     for (int q = 0; q < Q; ++q) {
         if (q_geom[q] < 0 || q_geom[q] >= (int)s->geoms.size())
             return fail(s, BTL_E_INVAL, "q_geom out of range");
         for (int a = 0; a < 3; ++a)
             if (!isfinite(gG0[3 * q + a])) return fail(s, BTL_E_INVAL, "gG0 must be finite");
     }
-    if (nq == 5)
+    if (cs.nq == 5)
         for (int q = 0; q < Q; ++q)
             if (s->geoms[q_geom[q]].n[2] != 1 || gG0[3 * q + 2] != 0.0)
                 return fail(s, BTL_E_INVAL, "D2Q5 needs single-layer geometries (n[2] = 1) "
                                              "and no gradient along z");
-    if (msub > 1 && s->scheme == BTL_CLASSICAL)
+    if (cs.msub > 1 && cs.scheme == BTL_CLASSICAL)
         return fail(s, BTL_E_UNSUPPORTED, "reaction sub-steps need the hybrid scheme");
-    for (int64_t k = 0; k < (int64_t)K * msub; ++k)
+    for (int64_t k = 0; k < (int64_t)K * cs.msub; ++k)
         if (!isfinite(f[k])) return fail(s, BTL_E_INVAL, "f must be finite");
-    hipStream_t st = static_cast<hipStream_t>(stream);
+    return BTL_OK;
+}
+
+// The adjoint covers the hybrid scheme with half-link membranes and at most
+// kAdjMaxPhase phases.
+static btl_status adjoint_supported(btl_sim* s, const Settings& cs, int32_t Q,
+                                    const int32_t* q_geom) {
+    if (s->n_phase > kAdjMaxPhase) return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports n_phase <= 4");
+    if (cs.scheme == BTL_CLASSICAL)
+        return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports the hybrid scheme only");
+    for (int q = 0; q < Q; ++q)
+        if (s->geoms[q_geom[q]].gm_off >= 0)
+            return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports the half-link membrane rule only");
+    return BTL_OK;
+}
+
+// Plan one call (validated inputs): per-phase constants, waveform sums,
+// launch shape, field table (with image fields and face couplings), phase
+// table layout, workgroup tables and, when taping, the adjoint's launch
+// geometry and the gamma G0 metadata.
+static btl_status make_plan(btl_sim* s, const Settings& cs, double dt, int32_t K,
+                            const double* D, const double* T2, const double* kappa, int32_t Q,
+                            const int32_t* q_geom, const double* gG0, const double* f,
+                            bool taping, CallPlan& p) {
+    const int32_t P = s->n_phase;
+    const int32_t msub = cs.msub;
+    const int32_t nq = cs.nq;
+    const double eps = lattice_eps(nq);
     const double dx = s->dx;
+    p = CallPlan();
+    p.K = K;
+    p.Q = Q;
+    p.P = P;
+    p.nq = nq;
+    p.msub = msub;
+    p.dt = dt;
+    p.classical = cs.scheme == BTL_CLASSICAL;
+    p.taping = taping && K > 0;
 
     // per-phase and per-pair constants (FP64)
-    std::vector<double> consts(2 * P + P * P + P + P * P + P + P * P);
-    for (int p = 0; p < P; ++p) {
-        const double tau = 0.5 + dt * D[p] / (eps * dx * dx);
-        consts[p] = 1.0 / tau;
-        consts[P + p] = isinf(T2[p]) ? 1.0 : exp(-dt / T2[p]);
+    std::vector<double>& consts = p.consts;
+    consts.assign(2 * P + P * P + P + P * P + P + P * P, 0.0);
+    for (int ph = 0; ph < P; ++ph) {
+        const double tau = 0.5 + dt * D[ph] / (eps * dx * dx);
+        consts[ph] = 1.0 / tau;
+        consts[P + ph] = isinf(T2[ph]) ? 1.0 : exp(-dt / T2[ph]);
     }
     for (int i = 0; i < P * P; ++i) {
         const double k = kappa[i];
@@ -494,18 +608,17 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         }
         consts[2 * P + i] = t;
     }
-    for (int p = 0; p < P; ++p) consts[2 * P + P * P + p] = T2[p];
+    for (int ph = 0; ph < P; ++ph) consts[2 * P + P * P + ph] = T2[ph];
     for (int i = 0; i < P * P; ++i) consts[3 * P + P * P + i] = kappa[i];
-    for (int p = 0; p < P; ++p) consts[3 * P + 2 * P * P + p] = isinf(T2[p]) ? 0.0 : dt / T2[p];
+    for (int ph = 0; ph < P; ++ph) consts[3 * P + 2 * P * P + ph] = isinf(T2[ph]) ? 0.0 : dt / T2[ph];
     for (int i = 0; i < P * P; ++i) consts[4 * P + 2 * P * P + i] = kappa[i] * dt;
-    bool uses_gm = false;
-    for (int q = 0; q < Q; ++q) uses_gm |= s->geoms[q_geom[q]].gm_off >= 0;
-    const bool classical = s->scheme == BTL_CLASSICAL;
+    for (int q = 0; q < Q; ++q) p.uses_gm |= s->geoms[q_geom[q]].gm_off >= 0;
     // per-step waveform tables: f_k dt and F_k.  With m reaction sub-steps
     // of dt' = dt/m (Sec. 2.3) the reaction of step k is the product of m
     // exact phase factors, i.e. one factor with the summed angle, so f_k dt
     // becomes sum_j f[k m + j] dt'.
-    std::vector<double> steps((size_t)K + (size_t)K + 1);
+    std::vector<double>& steps = p.steps;
+    steps.assign((size_t)K + (size_t)K + 1, 0.0);
     {
         const double dts = dt / msub;
         double F = 0.0;
@@ -520,9 +633,10 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     }
 
     // launch shape
-    int shape = s->tile_shape >= 0 ? s->tile_shape : pick_shape(s->geoms, q_geom, Q, nq);
+    int shape = cs.tile_shape >= 0 ? cs.tile_shape : pick_shape(s->geoms, q_geom, Q, nq);
     if ((nq == 5) != (shape == kTile256x1)) shape = pick_shape(s->geoms, q_geom, Q, nq);
-    int ZC = s->zc;
+    p.shape = shape;
+    int ZC = cs.zc;
     if (ZC <= 0) {
         ZC = 1;
         for (int q = 0; q < Q; ++q) ZC = std::max(ZC, kernel_geom(s->geoms[q_geom[q]], nq).n[2]);
@@ -530,23 +644,20 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     ZC = std::min(ZC, kMaxZc);
 
     // field table
-    std::vector<FieldDesc>& fl = s->h_fields;
-    fl.clear();
-    bool g_complete = true;   // every q-sample's field set is the full one
-    // per field: owning q-sample, s_b, sigma_b and d beta_f / d G_b (kGMeta)
-    std::vector<double> gmeta;
+    std::vector<FieldDesc>& fl = p.fl;
+    std::vector<double>& gmeta = p.gmeta;   // per field: q-sample, s_b, sigma_b, d beta_f / d G_b
     int64_t pop_elems = 0;
     int32_t nblk_total = 0;
     for (int q = 0; q < Q; ++q) {
         const GeomHost g = kernel_geom(s->geoms[q_geom[q]], nq);
         double G[3];
         kernel_grad(gG0 + 3 * q, nq, G);
-        const bool full = s->grad_g && ckpt_every > 0 && K > 0;
-        QFields qf = plan_fields(g, G, s->scheme == BTL_CLASSICAL, full);
+        const bool full = cs.grad_g && p.taping;
+        QFields qf = plan_fields(g, G, p.classical, full);
         {
-            const QFields qa = plan_fields(g, G, s->scheme == BTL_CLASSICAL, true);
+            const QFields qa = plan_fields(g, G, p.classical, true);
             if (!(qa.amask == qf.amask && qa.conj_pair == qf.conj_pair && qa.sigma == qf.sigma))
-                g_complete = false;
+                p.g_complete = false;
         }
         const int base = (int)fl.size();
         auto slot_of = [&](int sg, int* cj) {
@@ -641,18 +752,18 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         // face, an involution) with that partner's factor and conjugation
         for (size_t fi = 0; fi < qf.sigma.size(); ++fi) {
             FieldDesc& d = fl[base + fi];
-            for (int f = 0; f < 6; ++f) {
-                if ((d.face_kind[f] & kFaceMirror) == 0) {
-                    d.adj_kind[f] = kFacePeriodic;
-                    d.adj_pop[f] = d.pop;
-                    d.adj_fac[f] = -1 - (f ^ 1);          // own table, resolved below
+            for (int fc = 0; fc < 6; ++fc) {
+                if ((d.face_kind[fc] & kFaceMirror) == 0) {
+                    d.adj_kind[fc] = kFacePeriodic;
+                    d.adj_pop[fc] = d.pop;
+                    d.adj_fac[fc] = -1 - (fc ^ 1);          // own table, resolved below
                 } else {
                     int partner = -1;
                     for (size_t pj = 0; pj < qf.sigma.size(); ++pj)
-                        if (fl[base + pj].pop == d.face_pop[f]) partner = base + (int)pj;
-                    d.adj_kind[f] = fl[partner].face_kind[f];
-                    d.adj_pop[f] = fl[partner].pop;
-                    d.adj_fac[f] = -1000 - (partner * 6 + f);  // partner table, resolved below
+                        if (fl[base + pj].pop == d.face_pop[fc]) partner = base + (int)pj;
+                    d.adj_kind[fc] = fl[partner].face_kind[fc];
+                    d.adj_pop[fc] = fl[partner].pop;
+                    d.adj_fac[fc] = -1000 - (partner * 6 + fc);  // partner table, resolved below
                 }
             }
         }
@@ -662,11 +773,11 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
     // its own base: every plane it reads must lie within +-2^31 elements
     for (int i = 0; i < n_fields; ++i) {
         int64_t lo = 0, hi = (int64_t)nq * fl[i].nsites;
-        for (int f = 0; f < 6; ++f) {
-            lo = std::min(lo, fl[i].face_pop[f] - fl[i].pop);
-            hi = std::max(hi, fl[i].face_pop[f] - fl[i].pop + (int64_t)nq * fl[i].nsites);
-            lo = std::min(lo, fl[i].adj_pop[f] - fl[i].pop);
-            hi = std::max(hi, fl[i].adj_pop[f] - fl[i].pop + (int64_t)nq * fl[i].nsites);
+        for (int fc = 0; fc < 6; ++fc) {
+            lo = std::min(lo, fl[i].face_pop[fc] - fl[i].pop);
+            hi = std::max(hi, fl[i].face_pop[fc] - fl[i].pop + (int64_t)nq * fl[i].nsites);
+            lo = std::min(lo, fl[i].adj_pop[fc] - fl[i].pop);
+            hi = std::max(hi, fl[i].adj_pop[fc] - fl[i].pop + (int64_t)nq * fl[i].nsites);
         }
         if (lo < -(int64_t)INT32_MAX || hi > (int64_t)INT32_MAX)
             return fail(s, BTL_E_UNSUPPORTED, "geometry too large for the image fields of one q-sample");
@@ -678,39 +789,35 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
         T += fl[i].n[0] + fl[i].n[1] + fl[i].n[2] + 6;
     }
     for (int i = 0; i < n_fields; ++i)
-        for (int f = 0; f < 6; ++f) {
-            const int32_t v = fl[i].adj_fac[f];
+        for (int fc = 0; fc < 6; ++fc) {
+            const int32_t v = fl[i].adj_fac[fc];
             if (v <= -1000) {
                 const int partner = (-1000 - v) / 6, pf = (-1000 - v) % 6;
-                fl[i].adj_fac[f] = fl[partner].tab + fl[partner].n[0] + fl[partner].n[1] +
-                                   fl[partner].n[2] + pf;
+                fl[i].adj_fac[fc] = fl[partner].tab + fl[partner].n[0] + fl[partner].n[1] +
+                                    fl[partner].n[2] + pf;
             } else {
-                fl[i].adj_fac[f] = fl[i].tab + fl[i].n[0] + fl[i].n[1] + fl[i].n[2] + (-1 - v);
+                fl[i].adj_fac[fc] = fl[i].tab + fl[i].n[0] + fl[i].n[1] + fl[i].n[2] + (-1 - v);
             }
         }
-    std::vector<int32_t> tabf(T);
+    p.tabf.assign(T, 0);
     for (int i = 0; i < n_fields; ++i)
-        for (int e = 0; e < fl[i].n[0] + fl[i].n[1] + fl[i].n[2] + 6; ++e) tabf[fl[i].tab + e] = i;
-    std::vector<int32_t> blk(nblk_total);
+        for (int e = 0; e < fl[i].n[0] + fl[i].n[1] + fl[i].n[2] + 6; ++e) p.tabf[fl[i].tab + e] = i;
+    p.blk.assign(nblk_total, 0);
     for (int i = 0; i < n_fields; ++i)
-        for (int b = 0; b < fl[i].nblk; ++b) blk[fl[i].blk0 + b] = i;
+        for (int b = 0; b < fl[i].nblk; ++b) p.blk[fl[i].blk0 + b] = i;
     // With a tape, the launch geometry of the adjoint steps: the same tile
     // shape, whole z columns when all workgroups are resident at once (cut
     // into as many pieces as still fit at once when that leaves SIMDs with
     // room), otherwise columns cut so that the grid runs in about eight rounds
-    // (BTLBM_ADJ_ZC sets the length).  The adjoint carries four values along
-    // the column and loads in two phases per site; on the benchmark workload
-    // it measured faster on whole columns than on the short chunks the
-    // forward step often prefers, but a grid slightly larger than one round
-    // of resident workgroups leaves most of the chip idle in its second.
-    const bool taping = ckpt_every > 0 && K > 0;
-    std::vector<FieldDesc> afl;
-    std::vector<int32_t> ablk;
-    int32_t nblk_adj = 0;
-    if (taping) {
-        const char* ez = getenv("BTLBM_ADJ_ZC");
-        int zc_adj = ez ? std::max(0, atoi(ez)) : 0;
-        if (!ez) {
+    // (btl_set_adjoint_launch fixes the length).  The adjoint carries four
+    // values along the column and loads in two phases per site; on the
+    // two-phase axon workload (128^3) it measured faster on whole columns
+    // than on the short chunks the forward step often prefers, but a grid
+    // slightly larger than one round of resident workgroups leaves most of
+    // the chip idle in its second.
+    if (p.taping) {
+        int zc_adj = cs.adj_zc >= 0 ? cs.adj_zc : 0;
+        if (cs.adj_zc < 0) {
             // resident workgroups: 1024 SIMDs x (4 waves FP32, 2 FP64) / 4 waves each
             const int64_t cap = s->prec == BTL_F32 ? 1024 : 512;
             int64_t whole = 0;
@@ -730,8 +837,9 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
                 zc_adj = (int)((nz + split - 1) / split);
             }
         }
-        afl = fl;
-        for (FieldDesc& d : afl) {
+        p.afl = fl;
+        int32_t nblk_adj = 0;
+        for (FieldDesc& d : p.afl) {
             const int32_t zc = zc_adj > 0 ? std::min(zc_adj, d.n[2]) : d.n[2];
             d.zc = zc;
             d.tiles[2] = (d.n[2] + zc - 1) / zc;
@@ -739,47 +847,117 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
             d.blk0 = nblk_adj;
             nblk_adj += d.nblk;
         }
-        ablk.resize(nblk_adj);
+        p.ablk.assign(nblk_adj, 0);
         for (int i = 0; i < n_fields; ++i)
-            for (int b = 0; b < afl[i].nblk; ++b) ablk[afl[i].blk0 + b] = i;
+            for (int b = 0; b < p.afl[i].nblk; ++b) p.ablk[p.afl[i].blk0 + b] = i;
+        p.nblk_adj = nblk_adj;
     }
+    p.n_fields = n_fields;
+    p.nblk_total = nblk_total;
+    p.T = T;
+    p.pop_elems = pop_elems;
+    // XCD-contiguous workgroup order pays off when the grid runs in several
+    // waves (tiles that share edge rows then meet in one XCD's L2); grids
+    // that fit on the chip at once keep the plain order.  The autotuner
+    // measures both.
+    p.xcd_on = cs.xcd >= 0 ? cs.xcd : (nblk_total > kXcdMinBlocks ? 1 : 0);
+    return BTL_OK;
+}
 
-    const size_t esz = s->prec == BTL_F32 ? sizeof(float2) : sizeof(double2);
+static size_t state_elem_bytes(const btl_sim* s) {
+    return s->prec == BTL_F32 ? sizeof(float2) : sizeof(double2);
+}
+
+// Elements of one state of a q-sample: 2^(k-1) or 2^k image fields (see
+// plan_fields; full: the field set of a tape that supports the gamma G0
+// gradient).
+static int64_t q_state_elems(const btl_sim* s, const Settings& cs, int32_t g, const double* G,
+                             bool full) {
+    const GeomHost gh = kernel_geom(s->geoms[g], cs.nq);
+    double Gk[3];
+    kernel_grad(G, cs.nq, Gk);
+    return (int64_t)plan_fields(gh, Gk, cs.scheme == BTL_CLASSICAL, full).sigma.size() * cs.nq *
+           gh.nsites;
+}
+
+// Device bytes the population state of a call may take: 85 % of what the
+// device has free plus what this simulator already holds for states, or the
+// caller's limit (btl_set_memory_budget) when lower.
+static double memory_budget(const btl_sim* s) {
+    size_t free_b = 0, total_b = 0;
+    (void)hipMemGetInfo(&free_b, &total_b);
+    const size_t held = s->pop[0].bytes() + s->pop[1].bytes() + s->ckpt.bytes() + s->seg.bytes() +
+                        s->lam[0].bytes() + s->lam[1].bytes();
+    double b = 0.85 * (double)(free_b + held);
+    if (s->mem_limit > 0) b = std::min(b, (double)s->mem_limit);
+    return b;
+}
+
+// Device buffers of one call.
+struct CallBufs {
+    char* pop[2] = {nullptr, nullptr};
+    FieldDesc* fields = nullptr;
+    int32_t* blk = nullptr;
+    double* steps = nullptr;
+    double* consts = nullptr;
+    double2* partial = nullptr;
+    double2* tab = nullptr;
+    int32_t* tabf = nullptr;
+    FieldDesc* afields = nullptr;
+    int32_t* ablk = nullptr;
+    double* agmeta = nullptr;
+};
+
+// The simulator's own buffers, grown to the plan's sizes.
+static btl_status alloc_bufs(btl_sim* s, const CallPlan& p, CallBufs& b) {
+    const size_t esz = state_elem_bytes(s);
     hipError_t e;
-    if ((e = s->pop[0].ensure((size_t)pop_elems * esz)) != hipSuccess ||
-        (e = s->pop[1].ensure((size_t)pop_elems * esz)) != hipSuccess)
+    if ((e = s->pop[0].ensure((size_t)p.pop_elems * esz)) != hipSuccess ||
+        (e = s->pop[1].ensure((size_t)p.pop_elems * esz)) != hipSuccess)
         return hip_fail(s, e, "allocating populations");
-    if ((e = s->fields.ensure(n_fields)) != hipSuccess ||
-        (e = s->blk_field.ensure(nblk_total)) != hipSuccess ||
-        (e = s->steps.ensure(steps.size())) != hipSuccess ||
-        (e = s->consts.ensure(consts.size())) != hipSuccess ||
-        (e = s->partial.ensure((size_t)kTabSteps * nblk_total * (kBlock / 64))) != hipSuccess ||
-        (e = s->tab.ensure((size_t)kTabSteps * T)) != hipSuccess ||
-        (e = s->tab_field.ensure(T)) != hipSuccess ||
-        (taping && ((e = s->adj_fields.ensure(n_fields)) != hipSuccess ||
-                    (e = s->adj_blk.ensure(nblk_adj)) != hipSuccess ||
-                    (e = s->adj_gmeta.ensure((size_t)n_fields * kGMeta)) != hipSuccess)))
+    if ((e = s->fields.ensure(p.n_fields)) != hipSuccess ||
+        (e = s->blk_field.ensure(p.nblk_total)) != hipSuccess ||
+        (e = s->steps.ensure(p.steps.size())) != hipSuccess ||
+        (e = s->consts.ensure(p.consts.size())) != hipSuccess ||
+        (e = s->partial.ensure((size_t)kTabSteps * p.nblk_total * (kBlock / 64))) != hipSuccess ||
+        (e = s->tab.ensure((size_t)kTabSteps * p.T)) != hipSuccess ||
+        (e = s->tab_field.ensure(p.T)) != hipSuccess ||
+        (p.taping && ((e = s->adj_fields.ensure(p.n_fields)) != hipSuccess ||
+                      (e = s->adj_blk.ensure(p.nblk_adj)) != hipSuccess ||
+                      (e = s->adj_gmeta.ensure((size_t)p.n_fields * kGMeta)) != hipSuccess)))
         return hip_fail(s, e, "allocating tables");
-    // stage all tables in pinned memory and upload asynchronously
-    const size_t b_fields = (size_t)n_fields * sizeof(FieldDesc);
-    const size_t b_blk = (size_t)nblk_total * sizeof(int32_t);
-    const size_t b_steps = steps.size() * sizeof(double);
-    const size_t b_consts = consts.size() * sizeof(double);
-    const size_t b_tabf = (size_t)T * sizeof(int32_t);
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t o_blk = al(b_fields), o_steps = o_blk + al(b_blk), o_consts = o_steps + al(b_steps);
-    const size_t o_tabf = o_consts + al(b_consts);
-    const size_t b_afl = taping ? b_fields : 0, b_ablk = (size_t)nblk_adj * sizeof(int32_t);
-    const size_t b_agm = taping ? (size_t)n_fields * kGMeta * sizeof(double) : 0;
-    const size_t o_afl = o_tabf + al(b_tabf), o_ablk = o_afl + al(b_afl);
-    const size_t o_agm = o_ablk + al(b_ablk);
-    const size_t total = o_agm + al(b_agm);
+    b.pop[0] = s->pop[0].p;
+    b.pop[1] = s->pop[1].p;
+    b.fields = s->fields.p;
+    b.blk = s->blk_field.p;
+    b.steps = s->steps.p;
+    b.consts = s->consts.p;
+    b.partial = s->partial.p;
+    b.tab = s->tab.p;
+    b.tabf = s->tab_field.p;
+    b.afields = s->adj_fields.p;
+    b.ablk = s->adj_blk.p;
+    b.agmeta = s->adj_gmeta.p;
+    return BTL_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Pinned staging: wait until the slot's previous uploads have been read,
+// grow it when allowed (grow = false: fail instead of allocating).
+static btl_status stage_acquire(btl_sim* s, size_t total, bool grow, char** out) {
     const int slot = s->stage_slot;
-    if (!s->stage_ev[slot] && (e = hipEventCreateWithFlags(&s->stage_ev[slot], hipEventDisableTiming)) != hipSuccess)
-        return hip_fail(s, e, "creating event");
+    hipError_t e;
     if (s->stage_used[slot] && (e = hipEventSynchronize(s->stage_ev[slot])) != hipSuccess)
         return hip_fail(s, e, "waiting for staging slot");
+    s->stage_used[slot] = false;
     if (s->stage_cap[slot] < total) {
+        if (!grow) {
+            char msg[160];
+            snprintf(msg, sizeof(msg), "the call's tables need %zu bytes of staging, the "
+                     "simulator has %zu", total, s->stage_cap[slot]);
+            return fail(s, BTL_E_INVAL, msg);
+        }
         if (s->stage[slot]) (void)hipHostFree(s->stage[slot]);
         s->stage[slot] = nullptr;
         s->stage_cap[slot] = 0;
@@ -787,203 +965,372 @@ static btl_status forward_impl(btl_sim* s, double dt, int32_t K, const double* D
             return hip_fail(s, e, "allocating pinned staging");
         s->stage_cap[slot] = total;
     }
-    char* stg = s->stage[slot];
-    memcpy(stg, fl.data(), b_fields);
-    memcpy(stg + o_blk, blk.data(), b_blk);
-    memcpy(stg + o_steps, steps.data(), b_steps);
-    memcpy(stg + o_consts, consts.data(), b_consts);
-    memcpy(stg + o_tabf, tabf.data(), b_tabf);
-    if (taping) {
-        memcpy(stg + o_afl, afl.data(), b_afl);
-        memcpy(stg + o_ablk, ablk.data(), b_ablk);
-        memcpy(stg + o_agm, gmeta.data(), b_agm);
-    }
-    if ((e = hipMemcpyAsync(s->fields.p, stg, b_fields, hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(s->blk_field.p, stg + o_blk, b_blk, hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(s->steps.p, stg + o_steps, b_steps, hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(s->consts.p, stg + o_consts, b_consts, hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(s->tab_field.p, stg + o_tabf, b_tabf, hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (taping &&
-         ((e = hipMemcpyAsync(s->adj_fields.p, stg + o_afl, b_afl, hipMemcpyHostToDevice, st)) != hipSuccess ||
-          (e = hipMemcpyAsync(s->adj_blk.p, stg + o_ablk, b_ablk, hipMemcpyHostToDevice, st)) != hipSuccess ||
-          (e = hipMemcpyAsync(s->adj_gmeta.p, stg + o_agm, b_agm, hipMemcpyHostToDevice, st)) != hipSuccess)) ||
-        (e = hipEventRecord(s->stage_ev[slot], st)) != hipSuccess)
-        return hip_fail(s, e, "uploading tables");
+    *out = s->stage[slot];
+    return BTL_OK;
+}
+
+static btl_status stage_release(btl_sim* s, hipStream_t st) {
+    const int slot = s->stage_slot;
+    const hipError_t e = hipEventRecord(s->stage_ev[slot], st);
+    if (e != hipSuccess) return hip_fail(s, e, "recording staging event");
     s->stage_used[slot] = true;
     s->stage_slot ^= 1;
+    return BTL_OK;
+}
 
-    s->tape.valid = false;
-    // XCD-contiguous workgroup order pays off when the grid runs in several
-    // waves (tiles that share edge rows then meet in one XCD's L2); grids
-    // that fit on the chip at once keep the plain order.  The autotuner
-    // measures both.
-    const int xcd_on = s->xcd >= 0 ? s->xcd : (nblk_total > kXcdMinBlocks ? 1 : 0);
-    const size_t state_bytes = (size_t)pop_elems * esz;
-    if (ckpt_every > 0 && K > 0) {
-        if (P > kAdjMaxPhase) return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports n_phase <= 4");
-        if (classical) return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports the hybrid scheme only");
-        if (uses_gm)
-            return fail(s, BTL_E_UNSUPPORTED, "the adjoint supports the half-link membrane rule only");
-        const int32_t C = std::min(ckpt_every, K);
-        const int32_t nck = (K + C - 1) / C;
-        if ((e = s->ckpt.ensure((size_t)nck * state_bytes)) != hipSuccess)
-            return hip_fail(s, e, "allocating checkpoints");
-        s->tape.K = K;
-        s->tape.C = C;
-        s->tape.Q = Q;
-        s->tape.T = T;
-        s->tape.n_fields = n_fields;
-        s->tape.nblk = nblk_total;
-        s->tape.nblk_adj = nblk_adj;
-        s->tape.g_ok = g_complete;
-        s->tape.shape = shape;
-        s->tape.dt = dt;
-        s->tape.sub = msub;
-        s->tape.xcd = xcd_on;
-        s->tape.state_elems = pop_elems;
-        s->tape.nq = nq;
+// One asynchronous upload of several host arrays through a staging slot.
+struct Upload {
+    const void* src;
+    void* dst;
+    size_t bytes;
+};
+static btl_status upload(btl_sim* s, const std::vector<Upload>& ups, bool grow, hipStream_t st) {
+    size_t total = 0;
+    for (const Upload& u : ups) total += align256(u.bytes);
+    char* stg = nullptr;
+    btl_status rc = stage_acquire(s, total, grow, &stg);
+    if (rc != BTL_OK) return rc;
+    size_t off = 0;
+    for (const Upload& u : ups) {
+        if (u.bytes == 0) continue;
+        memcpy(stg + off, u.src, u.bytes);
+        const hipError_t e = hipMemcpyAsync(u.dst, stg + off, u.bytes, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(s, e, "uploading tables");
+        off += align256(u.bytes);
     }
-    // Everything a forward enqueues after the uploads: init, one table
-    // launch per kTabSteps steps, one step launch per step, checkpoint
-    // copies.  Replayed from a cached hipGraph when the call has the same
-    // shape and buffers as the previous one.
-    auto enqueue = [&](hipStream_t q, double* Eptr) -> btl_status {
-        hipError_t err;
-        if ((err = launch_init(s->prec, s->pop[0].p, pop_elems, s->fields.p, n_fields, fl.data(),
-                               Eptr, Q, K, nq, q)) != hipSuccess)
-            return hip_fail(s, err, "init launch");
-        if (classical && K > 0 &&
-            (err = launch_init_classical(s->prec, s->pop[0].p, fl.data(), n_fields, s->words.p,
-                                         s->steps.p, s->consts.p + 3 * P + 2 * P * P, nq, q)) !=
-                hipSuccess)
-            return hip_fail(s, err, "init launch");
-        if (ckpt_every > 0 && K > 0 &&
-            (err = hipMemcpyAsync(s->ckpt.p, s->pop[0].p, state_bytes, hipMemcpyDeviceToDevice, q)) !=
-                hipSuccess)
-            return hip_fail(s, err, "checkpoint copy");
-        StepArgs a;
-        memset(&a, 0, sizeof(a));
-        a.words = s->words.p;
-        a.fields = s->fields.p;
-        a.blk_field = s->blk_field.p;
-        a.fdt = s->steps.p;
-        a.Fk = s->steps.p + K;
-        a.w = s->consts.p;
-        a.decay = s->consts.p + P;
-        a.trans = s->consts.p + 2 * P;
-        a.rdt = s->consts.p + 3 * P + 2 * P * P;
-        a.gm = uses_gm ? s->gm.p : nullptr;
-        a.kdt = s->consts.p + 4 * P + 2 * P * P;
-        a.edx = eps * dx;
-        a.nq = nq;
-        a.xcd = xcd_on;
-        a.classical = classical ? 1 : 0;
-        a.partial = s->partial.p;
-        a.n_phase = P;
-        a.K = K;
-        a.tab_field = s->tab_field.p;
-        a.T = T;
-        for (int k = 0; k < K; ++k) {
-            if (k % kTabSteps == 0) {
-                a.k = k;
-                a.tab = s->tab.p;
-                if ((err = launch_tables(a, std::min(kTabSteps, K - k), q)) != hipSuccess)
-                    return hip_fail(s, err, "table launch");
-            }
-            a.tab = s->tab.p + (size_t)(k % kTabSteps) * T;
-            a.src = s->pop[k & 1].p;
-            a.dst = s->pop[(k + 1) & 1].p;
-            a.k = k;
-            if ((err = launch_step(s->prec, shape, a, nblk_total, q)) != hipSuccess)
-                return hip_fail(s, err, "step launch");
-            if ((k + 1) % kTabSteps == 0 || k + 1 == K) {
-                const int32_t k0 = k - k % kTabSteps;
-                if ((err = launch_esum(s->partial.p, s->fields.p, n_fields, nblk_total, k0,
-                                       k + 1 - k0, Eptr, K, q)) != hipSuccess)
-                    return hip_fail(s, err, "signal launch");
-            }
-            if (ckpt_every > 0 && (k + 1) % s->tape.C == 0 && k + 1 < K) {
-                const size_t m = (size_t)(k + 1) / s->tape.C;
-                if ((err = hipMemcpyAsync(s->ckpt.p + m * state_bytes, s->pop[(k + 1) & 1].p,
-                                          state_bytes, hipMemcpyDeviceToDevice, q)) != hipSuccess)
-                    return hip_fail(s, err, "checkpoint copy");
-            }
-        }
-        return BTL_OK;
-    };
-    const bool use_graph = K >= kGraphMinSteps && getenv("BTLBM_NO_GRAPH") == nullptr;
-    if (!use_graph) {
-        const btl_status rc = enqueue(st, E);
-        if (rc != BTL_OK) return rc;
-    } else {
-        const size_t ebytes = (size_t)Q * (K + 1) * 2 * sizeof(double);
-        if ((e = s->E_int.ensure((size_t)Q * (K + 1) * 2)) != hipSuccess)
-            return hip_fail(s, e, "allocating signal buffer");
-        GraphKey key;
-        memset(&key, 0, sizeof(key));
-        key.prec = s->prec;
-        key.K = K;
-        key.Q = Q;
-        key.n_fields = n_fields;
-        key.nblk = nblk_total;
-        key.shape = shape;
-        key.T = T;
-        key.ckpt = ckpt_every;
-        key.scheme = s->scheme;
-        key.nq = nq;
-        key.xcd = xcd_on;
-        key.fields = field_hash(fl, classical);
-        const void* ptrs[] = {s->pop[0].p, s->pop[1].p, s->fields.p, s->blk_field.p, s->steps.p,
-                              s->consts.p, s->partial.p, s->tab.p, s->tab_field.p,
-                              s->E_int.p, s->ckpt.p, s->words.p};
-        static_assert(sizeof(ptrs) / sizeof(ptrs[0]) <= sizeof(key.ptr) / sizeof(key.ptr[0]),
-                      "graph key too small");
-        for (size_t i = 0; i < sizeof(ptrs) / sizeof(ptrs[0]); ++i) key.ptr[i] = ptrs[i];
-        if (!(s->graph_exec && memcmp(&key, &s->graph_key, sizeof(key)) == 0)) {
-            if (s->graph_exec) {
-                (void)hipGraphExecDestroy(s->graph_exec);
-                s->graph_exec = nullptr;
-            }
-            if (!s->cap_stream &&
-                (e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking)) != hipSuccess)
-                return hip_fail(s, e, "creating capture stream");
-            if ((e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-                return hip_fail(s, e, "begin capture");
-            const btl_status rc = enqueue(s->cap_stream, s->E_int.p);
-            hipGraph_t graph = nullptr;
-            const hipError_t ec = hipStreamEndCapture(s->cap_stream, &graph);
-            if (rc != BTL_OK) {
-                if (graph) (void)hipGraphDestroy(graph);
-                return rc;
-            }
-            if (ec != hipSuccess) return hip_fail(s, ec, "end capture");
-            e = hipGraphInstantiate(&s->graph_exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            if (e != hipSuccess) {
-                s->graph_exec = nullptr;
-                return hip_fail(s, e, "graph instantiate");
-            }
-            s->graph_key = key;
-        }
-        if ((e = hipGraphLaunch(s->graph_exec, st)) != hipSuccess) return hip_fail(s, e, "graph launch");
-        if ((e = hipMemcpyAsync(E, s->E_int.p, ebytes, hipMemcpyDeviceToDevice, st)) != hipSuccess)
-            return hip_fail(s, e, "signal copy");
+    return stage_release(s, st);
+}
+
+static btl_status upload_plan(btl_sim* s, const CallPlan& p, const CallBufs& b, bool grow,
+                              hipStream_t st) {
+    std::vector<Upload> ups = {
+        {p.fl.data(), b.fields, p.fl.size() * sizeof(FieldDesc)},
+        {p.blk.data(), b.blk, p.blk.size() * sizeof(int32_t)},
+        {p.steps.data(), b.steps, p.steps.size() * sizeof(double)},
+        {p.consts.data(), b.consts, p.consts.size() * sizeof(double)},
+        {p.tabf.data(), b.tabf, p.tabf.size() * sizeof(int32_t)}};
+    if (p.taping) {
+        ups.push_back({p.afl.data(), b.afields, p.afl.size() * sizeof(FieldDesc)});
+        ups.push_back({p.ablk.data(), b.ablk, p.ablk.size() * sizeof(int32_t)});
+        ups.push_back({p.gmeta.data(), b.agmeta, p.gmeta.size() * sizeof(double)});
     }
-    if (ckpt_every > 0 && K > 0) s->tape.valid = true;
-    if (M_final) {
-        if ((e = launch_mfinal(s->prec, s->pop[K & 1].p, fl.data(), n_fields, M_final, nq, st)) !=
+    return upload(s, ups, grow, st);
+}
+
+// Step arguments shared by every launch of a call (the per-step fields are
+// set by the caller).
+static StepArgs step_args(const btl_sim* s, const CallPlan& p, const CallBufs& b) {
+    const int32_t P = p.P;
+    StepArgs a;
+    memset(&a, 0, sizeof(a));
+    a.words = s->words.p;
+    a.fields = b.fields;
+    a.blk_field = b.blk;
+    a.fdt = b.steps;
+    a.Fk = b.steps + p.K;
+    a.w = b.consts;
+    a.decay = b.consts + P;
+    a.trans = b.consts + 2 * P;
+    a.rdt = b.consts + 3 * P + 2 * P * P;
+    a.gm = p.uses_gm ? s->gm.p : nullptr;
+    a.kdt = b.consts + 4 * P + 2 * P * P;
+    a.edx = lattice_eps(p.nq) * s->dx;
+    a.nq = p.nq;
+    a.xcd = p.xcd_on;
+    a.classical = p.classical ? 1 : 0;
+    a.partial = b.partial;
+    a.n_phase = P;
+    a.K = p.K;
+    a.tab_field = b.tabf;
+    a.T = p.T;
+    return a;
+}
+
+// Everything a forward enqueues after the uploads: init, one table launch
+// per kTabSteps steps, one step launch per step, one signal launch per
+// kTabSteps steps and, with a uniform tape, the checkpoint copies.
+static btl_status enqueue_forward(btl_sim* s, const CallPlan& p, const CallBufs& b, hipStream_t q,
+                                  double* Eptr, char* ckpt, int32_t C) {
+    const size_t state_bytes = (size_t)p.pop_elems * state_elem_bytes(s);
+    const int32_t K = p.K;
+    hipError_t err;
+    if ((err = launch_init(s->prec, b.pop[0], p.pop_elems, b.fields, p.n_fields, p.fl.data(), Eptr,
+                           p.Q, K, p.nq, q)) != hipSuccess)
+        return hip_fail(s, err, "init launch");
+    if (p.classical && K > 0 &&
+        (err = launch_init_classical(s->prec, b.pop[0], p.fl.data(), p.n_fields, s->words.p,
+                                     b.steps, b.consts + 3 * p.P + 2 * p.P * p.P, p.nq, q)) !=
             hipSuccess)
-            return hip_fail(s, e, "final magnetization launch");
+        return hip_fail(s, err, "init launch");
+    if (ckpt && K > 0 &&
+        (err = hipMemcpyAsync(ckpt, b.pop[0], state_bytes, hipMemcpyDeviceToDevice, q)) != hipSuccess)
+        return hip_fail(s, err, "checkpoint copy");
+    StepArgs a = step_args(s, p, b);
+    for (int k = 0; k < K; ++k) {
+        if (k % kTabSteps == 0) {
+            a.k = k;
+            a.tab = b.tab;
+            if ((err = launch_tables(a, std::min(kTabSteps, K - k), q)) != hipSuccess)
+                return hip_fail(s, err, "table launch");
+        }
+        a.tab = b.tab + (size_t)(k % kTabSteps) * p.T;
+        a.src = b.pop[k & 1];
+        a.dst = b.pop[(k + 1) & 1];
+        a.k = k;
+        if ((err = launch_step(s->prec, p.shape, a, p.nblk_total, q)) != hipSuccess)
+            return hip_fail(s, err, "step launch");
+        if ((k + 1) % kTabSteps == 0 || k + 1 == K) {
+            const int32_t k0 = k - k % kTabSteps;
+            if ((err = launch_esum(b.partial, b.fields, p.n_fields, p.nblk_total, k0, k + 1 - k0,
+                                   Eptr, K, s->nf_dev, q)) != hipSuccess)
+                return hip_fail(s, err, "signal launch");
+        }
+        if (ckpt && (k + 1) % C == 0 && k + 1 < K) {
+            const size_t m = (size_t)(k + 1) / C;
+            if ((err = hipMemcpyAsync(ckpt + m * state_bytes, b.pop[(k + 1) & 1], state_bytes,
+                                      hipMemcpyDeviceToDevice, q)) != hipSuccess)
+                return hip_fail(s, err, "checkpoint copy");
+        }
     }
     return BTL_OK;
 }
 
-// Fields of one q-sample: 2^(k-1) or 2^k image fields, see plan_fields.
-static int64_t q_state_elems(const btl_sim* s, int32_t g, const double* G) {
-    const GeomHost gh = kernel_geom(s->geoms[g], s->nq);
-    double Gk[3];
-    kernel_grad(G, s->nq, Gk);
-    return (int64_t)plan_fields(gh, Gk, s->scheme == BTL_CLASSICAL).sigma.size() * s->nq * gh.nsites;
+// Run a planned, uploaded forward on stream st: eagerly, or (K >= 16 steps,
+// graphs on) by replaying a cached hipGraph of the same launches.  The
+// graph writes the signal into the simulator's own buffer, copied to E.
+static btl_status run_forward(btl_sim* s, const CallPlan& p, const CallBufs& b, hipStream_t st,
+                              double* E, char* ckpt, int32_t C) {
+    const int32_t K = p.K, Q = p.Q;
+    const bool use_graph = K >= kGraphMinSteps && s->use_graphs;
+    if (!use_graph) return enqueue_forward(s, p, b, st, E, ckpt, C);
+    hipError_t e;
+    const size_t ebytes = (size_t)Q * (K + 1) * 2 * sizeof(double);
+    if ((e = s->E_int.ensure((size_t)Q * (K + 1) * 2)) != hipSuccess)
+        return hip_fail(s, e, "allocating signal buffer");
+    GraphKey key;
+    memset(&key, 0, sizeof(key));
+    key.prec = s->prec;
+    key.K = K;
+    key.Q = Q;
+    key.n_fields = p.n_fields;
+    key.nblk = p.nblk_total;
+    key.shape = p.shape;
+    key.T = p.T;
+    key.ckpt = ckpt ? C : 0;
+    key.scheme = p.classical ? 1 : 0;
+    key.nq = p.nq;
+    key.xcd = p.xcd_on;
+    key.fields = field_hash(p.fl, p.classical);
+    const void* ptrs[] = {b.pop[0], b.pop[1], b.fields, b.blk, b.steps, b.consts, b.partial,
+                          b.tab, b.tabf, s->E_int.p, ckpt, s->words.p, s->gm.p, s->nf_dev};
+    static_assert(sizeof(ptrs) / sizeof(ptrs[0]) <= sizeof(key.ptr) / sizeof(key.ptr[0]),
+                  "graph key too small");
+    for (size_t i = 0; i < sizeof(ptrs) / sizeof(ptrs[0]); ++i) key.ptr[i] = ptrs[i];
+    GraphSlot* hit = nullptr;
+    for (GraphSlot& g : s->graphs)
+        if (g.exec && memcmp(&key, &g.key, sizeof(key)) == 0) hit = &g;
+    if (!hit) {
+        // replace the least recently used slot
+        hit = &s->graphs[0];
+        for (GraphSlot& g : s->graphs)
+            if (!g.exec || (hit->exec && g.used < hit->used)) hit = &g;
+        if (hit->exec) {
+            (void)hipGraphExecDestroy(hit->exec);
+            hit->exec = nullptr;
+        }
+        if (!s->cap_stream &&
+            (e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(s, e, "creating capture stream");
+        if ((e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(s, e, "begin capture");
+        const btl_status rc = enqueue_forward(s, p, b, s->cap_stream, s->E_int.p, ckpt, C);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(s->cap_stream, &graph);
+        if (rc != BTL_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (ec != hipSuccess) return hip_fail(s, ec, "end capture");
+        e = hipGraphInstantiate(&hit->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            hit->exec = nullptr;
+            return hip_fail(s, e, "graph instantiate");
+        }
+        hit->key = key;
+    }
+    hit->used = ++s->graph_clock;
+    if ((e = hipGraphLaunch(hit->exec, st)) != hipSuccess) return hip_fail(s, e, "graph launch");
+    if ((e = hipMemcpyAsync(E, s->E_int.p, ebytes, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+        return hip_fail(s, e, "signal copy");
+    return BTL_OK;
+}
+
+static btl_status final_magnetization(btl_sim* s, const CallPlan& p, const CallBufs& b,
+                                      void* M_final, hipStream_t st) {
+    if (!M_final) return BTL_OK;
+    const hipError_t e =
+        launch_mfinal(s->prec, b.pop[p.K & 1], p.fl.data(), p.n_fields, M_final, p.nq, st);
+    if (e != hipSuccess) return hip_fail(s, e, "final magnetization launch");
+    return BTL_OK;
+}
+
+// One planned call on the simulator's buffers, with a uniform tape when
+// C > 0 (the state every C steps, for btl_backward).
+static btl_status forward_call(btl_sim* s, const Settings& cs, double dt, int32_t K,
+                               const double* D, const double* T2, const double* kappa, int32_t Q,
+                               const int32_t* q_geom, const double* gG0, const double* f,
+                               double* E, void* M_final, int32_t C, hipStream_t st) {
+    CallPlan p;
+    btl_status rc = make_plan(s, cs, dt, K, D, T2, kappa, Q, q_geom, gG0, f, C > 0, p);
+    if (rc != BTL_OK) return rc;
+    CallBufs b;
+    if ((rc = alloc_bufs(s, p, b)) != BTL_OK) return rc;
+    if ((rc = upload_plan(s, p, b, true, st)) != BTL_OK) return rc;
+    char* ckpt = nullptr;
+    if (p.taping) {
+        C = std::min(C, K);
+        const int32_t nck = (K + C - 1) / C;
+        const size_t state_bytes = (size_t)p.pop_elems * state_elem_bytes(s);
+        hipError_t e;
+        if ((e = s->ckpt.ensure((size_t)nck * state_bytes)) != hipSuccess)
+            return hip_fail(s, e, "allocating checkpoints");
+        ckpt = s->ckpt.p;
+        btl_sim::Tape& tp = s->tape;
+        tp = btl_sim::Tape();
+        tp.set = cs;
+        tp.K = K;
+        tp.C = C;
+        tp.Q = Q;
+        tp.T = p.T;
+        tp.n_fields = p.n_fields;
+        tp.nblk = p.nblk_total;
+        tp.nblk_adj = p.nblk_adj;
+        tp.g_ok = p.g_complete;
+        tp.shape = p.shape;
+        tp.dt = dt;
+        tp.sub = p.msub;
+        tp.xcd = p.xcd_on;
+        tp.state_elems = p.pop_elems;
+        tp.nq = p.nq;
+    }
+    if ((rc = run_forward(s, p, b, st, E, ckpt, C)) != BTL_OK) return rc;
+    if (p.taping) s->tape.valid = true;
+    return final_magnetization(s, p, b, M_final, st);
+}
+
+// Consecutive groups of q-samples ("q-waves") whose states fit the budget:
+// per_q[q] bytes each, at most `budget` per group (at least one q-sample).
+static std::vector<int32_t> wave_bounds(const std::vector<double>& per_q, double budget) {
+    std::vector<int32_t> cut = {0};
+    const int32_t Q = (int32_t)per_q.size();
+    int32_t q0 = 0;
+    while (q0 < Q) {
+        double acc = 0.0;
+        int32_t q1 = q0;
+        while (q1 < Q && (q1 == q0 || acc + per_q[q1] <= budget)) acc += per_q[q1++];
+        cut.push_back(q1);
+        q0 = q1;
+    }
+    return cut;
+}
+
+// Report (and clear) a non-finite value left by earlier work on the device.
+static btl_status take_nonfinite(btl_sim* s) {
+    if (s->nf_host && __atomic_load_n(s->nf_host, __ATOMIC_ACQUIRE) != 0) {
+        __atomic_store_n(s->nf_host, 0, __ATOMIC_RELEASE);
+        return fail(s, BTL_E_NONFINITE,
+                    "a non-finite signal or gradient was produced by earlier work of this "
+                    "simulator (reported once)");
+    }
+    return BTL_OK;
+}
+
+// Forward without the non-finite check (btl_forward and the autotuner's
+// probes): q-waves when the states exceed the budget; a taped forward keeps
+// a uniform tape when it fits, otherwise a deferred one (btl_backward then
+// replays the forward from t = 0 with binomial checkpointing).
+static btl_status forward_entry(btl_sim* s, double dt, int32_t K, const double* D,
+                                const double* T2, const double* kappa, int32_t Q,
+                                const int32_t* q_geom, const double* gG0, const double* f,
+                                double* E, void* M_final, int32_t ckpt_every, void* stream) {
+    if (!s) return BTL_E_INVAL;
+    const Settings cs = s->set;
+    if (ckpt_every < 0) return fail(s, BTL_E_INVAL, "ckpt_every must be >= 0");
+    btl_status rc = validate_inputs(s, cs, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E);
+    if (rc != BTL_OK) return rc;
+    const int32_t P = s->n_phase;
+    s->last.valid = true;
+    s->last.dt = dt;
+    s->last.D.assign(D, D + P);
+    s->last.T2.assign(T2, T2 + P);
+    s->last.kappa.assign(kappa, kappa + P * P);
+    s->last.gG0.assign(gG0, gG0 + 3 * Q);
+    s->last.f.assign(f, f + (size_t)K * cs.msub);
+    s->last.q_geom.assign(q_geom, q_geom + Q);
+    s->tape.valid = false;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool taping = ckpt_every > 0 && K > 0;
+    if (taping && (rc = adjoint_supported(s, cs, Q, q_geom)) != BTL_OK) return rc;
+    const size_t esz = state_elem_bytes(s);
+    const double budget = memory_budget(s);
+    const bool full = taping && cs.grad_g;
+    std::vector<double> per_q(Q);
+    double S = 0.0;   // one state of all q-samples, bytes
+    for (int q = 0; q < Q; ++q) {
+        per_q[q] = (double)q_state_elems(s, cs, q_geom[q], gG0 + 3 * q, full) * esz;
+        S += per_q[q];
+    }
+    if (taping) {
+        const int32_t C = std::min(ckpt_every, K);
+        const int32_t nck = (K + C - 1) / C;
+        // checkpoints + segment + two adjoint states + two forward states
+        if ((double)(nck + C + 4) * S <= budget)
+            return forward_call(s, cs, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E, M_final, C, st);
+    } else if (2.0 * S <= budget) {
+        return forward_call(s, cs, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E, M_final, 0, st);
+    }
+    // q-waves (no tape kept on the device)
+    for (double& v : per_q) v *= 2.0;
+    const std::vector<int32_t> cut = wave_bounds(per_q, budget);
+    int64_t m_off = 0;
+    for (size_t w = 0; w + 1 < cut.size(); ++w) {
+        const int32_t q0 = cut[w], q1 = cut[w + 1];
+        if (per_q[q0] > budget && q1 == q0 + 1)
+            return fail(s, BTL_E_NOMEM, "one q-sample does not fit in device memory");
+        void* Mw = M_final ? static_cast<char*>(M_final) + m_off * esz : nullptr;
+        rc = forward_call(s, cs, dt, K, D, T2, kappa, q1 - q0, q_geom + q0, gG0 + 3 * q0, f,
+                          E + (size_t)q0 * (K + 1) * 2, Mw, 0, st);
+        if (rc != BTL_OK) return rc;
+        for (int q = q0; q < q1; ++q) m_off += s->geoms[q_geom[q]].nsites;
+    }
+    if (taping) {
+        // deferred tape: the inputs are all a reverse sweep needs, since the
+        // initial state is the equilibrium at M = 1
+        btl_sim::Tape& tp = s->tape;
+        tp = btl_sim::Tape();
+        tp.deferred = true;
+        tp.set = cs;
+        tp.K = K;
+        tp.C = std::min(ckpt_every, K);
+        tp.Q = Q;
+        tp.dt = dt;
+        tp.sub = cs.msub;
+        tp.nq = cs.nq;
+        tp.D.assign(D, D + P);
+        tp.T2.assign(T2, T2 + P);
+        tp.kappa.assign(kappa, kappa + P * P);
+        tp.gG0.assign(gG0, gG0 + 3 * Q);
+        tp.f.assign(f, f + (size_t)K * cs.msub);
+        tp.q_geom.assign(q_geom, q_geom + Q);
+        CallPlan pg;   // the field set the reverse sweep will plan (gamma G0 support)
+        if ((rc = make_plan(s, cs, dt, K, D, T2, kappa, Q, q_geom, gG0, f, true, pg)) != BTL_OK)
+            return rc;
+        tp.g_ok = pg.g_complete;
+        tp.n_fields = pg.n_fields;
+        tp.valid = true;
+    }
+    return BTL_OK;
 }
 
 extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double* D,
@@ -991,77 +1338,132 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
                                   const int32_t* q_geom, const double* gG0, const double* f,
                                   double* E, void* M_final, int32_t ckpt_every, void* stream) {
     if (!s) return BTL_E_INVAL;
-    if (Q < 1 || !q_geom || !gG0) return forward_impl(s, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E,
-                                                      M_final, ckpt_every, stream);
-    for (int q = 0; q < Q; ++q)
-        if (q_geom[q] < 0 || q_geom[q] >= (int)s->geoms.size())
-            return fail(s, BTL_E_INVAL, "q_geom out of range");
-    if (D && T2 && kappa && (K == 0 || f)) {
-        const int32_t P = s->n_phase;
-        s->last.valid = true;
-        s->last.dt = dt;
-        s->last.D.assign(D, D + P);
-        s->last.T2.assign(T2, T2 + P);
-        s->last.kappa.assign(kappa, kappa + P * P);
-        s->last.gG0.assign(gG0, gG0 + 3 * Q);
-        s->last.f.assign(f, f + (size_t)K * s->substeps);
-        s->last.q_geom.assign(q_geom, q_geom + Q);
+    const btl_status rc = take_nonfinite(s);
+    if (rc != BTL_OK) return rc;
+    return forward_entry(s, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E, M_final, ckpt_every,
+                         stream);
+}
+
+extern "C" btl_status btl_synchronize(btl_sim* s, void* stream) {
+    if (!s) return BTL_E_INVAL;
+    const hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(s, e, "stream synchronize");
+    return take_nonfinite(s);
+}
+
+// C(n, k), or cap + 1 when it exceeds cap (no overflow for n <= 2^31).
+static int64_t binom_cap(int64_t n, int64_t k, int64_t cap) {
+    if (k < 0 || k > n) return 0;
+    k = std::min(k, n - k);
+    int64_t v = 1;
+    for (int64_t i = 1; i <= k; ++i) {
+        // v = C(n - k + i, i) grows with i: stop as soon as it passes cap
+        v = v * (n - k + i) / i;
+        if (v > cap) return cap + 1;
     }
-    // q-waves: when the two population copies of all q-samples do not fit
-    // in device memory, run consecutive subsets of the q-samples
-    const size_t esz = s->prec == BTL_F32 ? sizeof(float2) : sizeof(double2);
-    size_t free_b = 0, total_b = 0;
-    (void)hipMemGetInfo(&free_b, &total_b);
-    const size_t have = free_b + s->pop[0].cap + s->pop[1].cap;
-    double budget = 0.85 * (double)have;
-    // BTLBM_MEM_BUDGET (bytes) lowers the budget, to exercise q-waves on
-    // small problems
-    if (const char* v = getenv("BTLBM_MEM_BUDGET")) budget = std::min(budget, atof(v));
-    double need = 0.0;
-    for (int q = 0; q < Q; ++q) need += 2.0 * (double)q_state_elems(s, q_geom[q], gG0 + 3 * q) * esz;
-    if (need <= budget || ckpt_every > 0)
-        return forward_impl(s, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E, M_final, ckpt_every,
-                            stream);
-    int32_t q0 = 0;
-    int64_t m_off = 0;
-    while (q0 < Q) {
-        double acc = 0.0;
-        int32_t q1 = q0;
-        while (q1 < Q) {
-            const double b = 2.0 * (double)q_state_elems(s, q_geom[q1], gG0 + 3 * q1) * esz;
-            if (q1 > q0 && acc + b > budget) break;
-            acc += b;
-            ++q1;
+    return v;
+}
+
+// One action of a reversal schedule.  Advance: forward steps k0 .. k1 - 1
+// from the state at k0 in slot src into slot dst (-1: the work buffers).
+// Adjoint: adjoint step k1 from the state at k1 - 1 in slot src (-1: the
+// work buffer the last advance wrote).
+struct RevAction {
+    int kind;   // 0 advance, 1 adjoint step
+    int32_t k0, k1;
+    int src, dst;
+};
+
+// Reversal by binomial checkpointing (Griewank's schedule): the adjoint
+// steps b, b - 1, .., a + 1, with the state at a kept in slot sa and the
+// slots in `free` available.  With s slots in all (sa included) and
+// repetition number t (forward steps taken at most t times each), at most
+// beta(s, t) = C(s + t, t) steps can be reversed, and
+// beta(s, t) = beta(s, t - 1) + beta(s - 1, t): a first new checkpoint j
+// steps beyond a leaves the steps after it to s - 1 slots at the same t
+// (j >= l - beta(s - 1, t)) and the steps before it to s slots at t - 1
+// (j <= beta(s, t - 1)).  Within that range j = beta(s, t - 2) gives the
+// least recomputation, t l - C(s + t, t - 1) forward steps in all for l
+// steps (the minimum for s slots).
+static void plan_reversal(int32_t a, int32_t b, int sa, std::vector<int>& free,
+                          std::vector<RevAction>& out) {
+    const int32_t l = b - a;
+    if (l == 1) {
+        out.push_back({1, a, b, sa, sa});
+        return;
+    }
+    if (free.empty()) {
+        // only the state at a: advance from it afresh for every step
+        for (int32_t k = b; k > a; --k) {
+            if (k - 1 > a) {
+                out.push_back({0, a, k - 1, sa, -1});
+                out.push_back({1, k - 1, k, -1, -1});
+            } else {
+                out.push_back({1, a, k, sa, sa});
+            }
         }
-        if (acc > budget)
-            return fail(s, BTL_E_NOMEM, "one q-sample does not fit in device memory");
-        void* Mw = M_final ? static_cast<char*>(M_final) + m_off * esz : nullptr;
-        const btl_status rc =
-            forward_impl(s, dt, K, D, T2, kappa, q1 - q0, q_geom + q0, gG0 + 3 * q0, f,
-                         E + (size_t)q0 * (K + 1) * 2, Mw, 0, stream);
-        if (rc != BTL_OK) return rc;
-        for (int q = q0; q < q1; ++q) m_off += s->geoms[q_geom[q]].nsites;
-        q0 = q1;
+        return;
     }
+    const int64_t s = (int64_t)free.size() + 1;
+    int64_t t = 1;
+    while (binom_cap(s + t, t, l) < l) ++t;
+    const int64_t lo = std::max<int64_t>(1, l - binom_cap(s - 1 + t, t, l));
+    const int64_t hi = std::min<int64_t>(l - 1, binom_cap(s + t - 1, t - 1, l));
+    const int64_t pref = t >= 2 ? binom_cap(s + t - 2, t - 2, l) : 1;
+    const int32_t m = a + (int32_t)std::max(lo, std::min(hi, pref));
+    const int slot = free.back();
+    free.pop_back();
+    out.push_back({0, a, m, sa, slot});
+    plan_reversal(m, b, slot, free, out);
+    free.push_back(slot);
+    plan_reversal(a, m, sa, free, out);
+}
+
+static AdjArgs adj_args(const btl_sim* s, const Settings& cs, const FieldDesc* afields,
+                        const int32_t* ablk, const double* consts, int32_t nblk_adj,
+                        const double* dL_dE, double dt, int32_t K, int NG, bool gradg, int nq) {
+    const int32_t P = s->n_phase;
+    AdjArgs aa;
+    memset(&aa, 0, sizeof(aa));
+    aa.words = s->words.p;
+    aa.fields = afields;
+    aa.blk_field = ablk;
+    aa.w = consts;
+    aa.decay = consts + P;
+    aa.trans = consts + 2 * P;
+    aa.dLdE = reinterpret_cast<const double2*>(dL_dE);
+    aa.gpart = s->gpart.p;
+    aa.dt = dt;
+    aa.xcd = cs.adj_xcd >= 0 ? cs.adj_xcd : (nblk_adj > kXcdMinBlocks ? 1 : 0);
+    aa.n_phase = P;
+    aa.K = K;
+    aa.ng = NG;
+    aa.gradg = gradg ? 1 : 0;
+    aa.nq = nq;
+    return aa;
+}
+
+static btl_status final_gradients(btl_sim* s, const double* gfield, int32_t K, int32_t nf,
+                                  int NG, double dt, int32_t sub, int32_t Q, int nq,
+                                  const double* gmeta, double* dD, double* dT2, double* dkappa,
+                                  double* df, double* dgG0, hipStream_t st) {
+    const int32_t P = s->n_phase;
+    const hipError_t e = launch_adj_final(
+        gfield, K, nf, P, dt, s->dx, s->consts.p, s->consts.p + 2 * P + P * P,
+        s->consts.p + 3 * P + P * P, dD, dT2, dkappa, df, sub, NG, gmeta, s->steps.p,
+        s->steps.p + K, Q, dgG0, lattice_eps(nq), nq == 5 ? 1 : 0, s->nf_dev, st);
+    if (e != hipSuccess) return hip_fail(s, e, "adjoint final launch");
     return BTL_OK;
 }
 
-extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, double* dT2,
-                                   double* dkappa, double* df, double* dgG0, void* stream) {
-    if (!s) return BTL_E_INVAL;
-    if (!s->tape.valid) return fail(s, BTL_E_INVAL, "no adjoint tape: run btl_forward with ckpt_every > 0");
-    if (!dL_dE) return fail(s, BTL_E_INVAL, "dL_dE is NULL");
-    hipStream_t st = static_cast<hipStream_t>(stream);
+// Reverse sweep over a uniform tape: per segment (last first), recompute the
+// segment's states from its checkpoint, then run its adjoint steps.
+static btl_status backward_uniform(btl_sim* s, const double* dL_dE, double* dD, double* dT2,
+                                   double* dkappa, double* df, double* dgG0, hipStream_t st) {
     const btl_sim::Tape& tp = s->tape;
     const int32_t K = tp.K, C = tp.C, T = tp.T, P = s->n_phase, nf = tp.n_fields;
-    if (dgG0 && !tp.g_ok)
-        return fail(s, BTL_E_UNSUPPORTED,
-                    "dgG0 needs btl_set_grad_gG0(s, 1) before the taped forward (a mirrored axis "
-                    "without a gradient component, or the conjugate pairing next to a periodic "
-                    "axis, has no image fields to differentiate)");
     const int NG = 2 * P + P * P + 2 + (dgG0 ? kNGGrad : 0);
-    const size_t esz = s->prec == BTL_F32 ? sizeof(float2) : sizeof(double2);
-    const size_t state_bytes = (size_t)tp.state_elems * esz;
+    const size_t state_bytes = (size_t)tp.state_elems * state_elem_bytes(s);
     hipError_t e;
     const int32_t nblk_adj = tp.nblk_adj;
     if ((e = s->seg.ensure((size_t)C * state_bytes)) != hipSuccess ||
@@ -1089,27 +1491,12 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
     fa.T = T;
     fa.nq = tp.nq;
     fa.xcd = tp.xcd;
-
-    AdjArgs aa;
-    memset(&aa, 0, sizeof(aa));
-    aa.words = s->words.p;
-    aa.fields = s->adj_fields.p;
-    aa.blk_field = s->adj_blk.p;
-    aa.w = s->consts.p;
-    aa.decay = s->consts.p + P;
-    aa.trans = s->consts.p + 2 * P;
-    aa.dLdE = reinterpret_cast<const double2*>(dL_dE);
-    aa.gpart = s->gpart.p;
-    aa.dt = tp.dt;
-    aa.xcd = nblk_adj > kXcdMinBlocks ? 1 : 0;
-    aa.n_phase = P;
-    aa.K = K;
-    aa.ng = NG;
-    aa.gradg = dgG0 ? 1 : 0;
-    aa.nq = tp.nq;
+    AdjArgs aa = adj_args(s, tp.set, s->adj_fields.p, s->adj_blk.p, s->consts.p, nblk_adj, dL_dE,
+                          tp.dt, K, NG, dgG0 != nullptr, tp.nq);
 
     const int32_t nseg = (K + C - 1) / C;
     int lam_cur = 0;      // buffer holding Lambda^k on entry to adjoint step k
+    int64_t nfwd = 0;
     for (int32_t m = nseg - 1; m >= 0; --m) {
         const int32_t k0 = m * C, k1 = std::min(K, k0 + C);
         // phase tables of steps k0 .. k1 (the last only when k1 < K)
@@ -1128,6 +1515,7 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
             fa.dst = s->seg.p + (size_t)(k - k0 + 1) * state_bytes;
             if ((e = launch_step(s->prec, tp.shape, fa, tp.nblk, st)) != hipSuccess)
                 return hip_fail(s, e, "recompute launch");
+            ++nfwd;
         }
         // reverse sweep over the segment
         for (int32_t k = k1; k > k0; --k) {
@@ -1145,40 +1533,235 @@ extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, 
         }
         // per-step, per-field sums of this segment: gfield[k0 .. k1 - 1]
         if ((e = launch_adj_gsum(s->gpart.p, s->adj_fields.p, nf, nblk_adj, NG, k0, k1 - k0,
-                                 s->gfield.p, st)) != hipSuccess)
+                                 s->gfield.p, 0, nf, st)) != hipSuccess)
             return hip_fail(s, e, "adjoint sum launch");
     }
-    if ((e = launch_adj_final(s->gfield.p, K, nf, P, tp.dt, s->dx, s->consts.p,
-                              s->consts.p + 2 * P + P * P, s->consts.p + 3 * P + P * P, dD, dT2,
-                              dkappa, df, tp.sub, NG, s->adj_gmeta.p, s->steps.p,
-                              s->steps.p + K, tp.Q, dgG0, lattice_eps(tp.nq),
-                              tp.nq == 5 ? 1 : 0, st)) != hipSuccess)
-        return hip_fail(s, e, "adjoint final launch");
+    s->stat_fwd_steps = nfwd;
+    s->stat_waves = 1;
+    s->stat_snapshots = 0;
+    return final_gradients(s, s->gfield.p, K, nf, NG, tp.dt, tp.sub, tp.Q, tp.nq,
+                           s->adj_gmeta.p, dD, dT2, dkappa, df, dgG0, st);
+}
+
+// Reverse sweep of a deferred tape: the q-samples in groups whose states fit
+// the memory budget, each group replayed from t = 0 (the equilibrium at
+// M = 1) under a binomial checkpointing schedule with as many snapshot
+// slots as fit.  Per-step, per-field sums go to one record spanning every
+// group in the order of a single batch, so the final gradients are formed
+// exactly as after a uniform tape.
+static btl_status backward_deferred(btl_sim* s, const double* dL_dE, double* dD, double* dT2,
+                                    double* dkappa, double* df, double* dgG0, hipStream_t st) {
+    const btl_sim::Tape tp = s->tape;   // copy: planning below must not alias the record
+    const Settings& cs = tp.set;
+    const int32_t K = tp.K, Q = tp.Q, P = s->n_phase;
+    const int NG = 2 * P + P * P + 2 + (dgG0 ? kNGGrad : 0);
+    const size_t esz = state_elem_bytes(s);
+    btl_status rc;
+    hipError_t e;
+    CallPlan G;
+    if ((rc = make_plan(s, cs, tp.dt, K, tp.D.data(), tp.T2.data(), tp.kappa.data(), Q,
+                        tp.q_geom.data(), tp.gG0.data(), tp.f.data(), true, G)) != BTL_OK)
+        return rc;
+    const int32_t nfT = G.n_fields;
+    std::vector<double> per_q(Q, 0.0);
+    for (int32_t i = 0; i < nfT; ++i)
+        per_q[(int)G.gmeta[(size_t)i * kGMeta]] += (double)G.nq * G.fl[i].nsites * esz;
+    // drop the states and graphs of earlier calls: the sweep sizes its own
+    for (GraphSlot& g : s->graphs)
+        if (g.exec) {
+            (void)hipGraphExecDestroy(g.exec);
+            g.exec = nullptr;
+        }
+    s->seg.release();
+    s->ckpt.release();
+    s->pop[0].release();
+    s->pop[1].release();
+    s->lam[0].release();
+    s->lam[1].release();
+    const double B = memory_budget(s);
+    // groups sized for a repetition number of at most two where possible
+    // (beta(s, 2) >= K), each q-sample on its own otherwise
+    int64_t s_target = 1;
+    while (s_target < K && binom_cap(s_target + 2, 2, K) < K) ++s_target;
+    std::vector<double> need(per_q);
+    for (double& v : need) v *= (double)(s_target + 4);
+    const std::vector<int32_t> cut = wave_bounds(need, B);
+    if ((e = s->gfield.ensure((size_t)K * nfT * NG)) != hipSuccess)
+        return hip_fail(s, e, "allocating adjoint buffers");
+    int32_t f0 = 0;
+    int64_t nfwd = 0;
+    int32_t min_slots = INT32_MAX;
+    for (size_t w = 0; w + 1 < cut.size(); ++w) {
+        const int32_t q0 = cut[w], q1 = cut[w + 1], Qw = q1 - q0;
+        CallPlan W;
+        if ((rc = make_plan(s, cs, tp.dt, K, tp.D.data(), tp.T2.data(), tp.kappa.data(), Qw,
+                            tp.q_geom.data() + q0, tp.gG0.data() + 3 * q0, tp.f.data(), true,
+                            W)) != BTL_OK)
+            return rc;
+        const size_t Sw = (size_t)W.pop_elems * esz;
+        int64_t slots = (int64_t)(B / (double)Sw) - 4;   // two work and two adjoint states
+        if (slots < 1)
+            return fail(s, BTL_E_NOMEM, "the reverse sweep of one q-sample does not fit in device memory");
+        slots = std::min<int64_t>(slots, K);
+        min_slots = std::min<int32_t>(min_slots, (int32_t)slots);
+        CallBufs b;
+        if ((rc = alloc_bufs(s, W, b)) != BTL_OK) return rc;
+        if ((rc = upload_plan(s, W, b, true, st)) != BTL_OK) return rc;
+        const int32_t T = W.T, nblk_adj = W.nblk_adj;
+        if ((e = s->ckpt.ensure((size_t)slots * Sw)) != hipSuccess ||
+            (e = s->lam[0].ensure(Sw)) != hipSuccess || (e = s->lam[1].ensure(Sw)) != hipSuccess ||
+            (e = s->tab_b.ensure((size_t)(kTabSteps + 2) * T)) != hipSuccess ||
+            (e = s->gpart.ensure((size_t)nblk_adj * NG)) != hipSuccess)
+            return hip_fail(s, e, "allocating adjoint buffers");
+        auto slot_ptr = [&](int i) { return s->ckpt.p + (size_t)i * Sw; };
+        // the state at t = 0 in slot 0
+        if ((e = launch_init(s->prec, slot_ptr(0), W.pop_elems, b.fields, W.n_fields, W.fl.data(),
+                             nullptr, Qw, K, W.nq, st)) != hipSuccess)
+            return hip_fail(s, e, "init launch");
+        std::vector<int> free;
+        for (int i = (int)slots - 1; i >= 1; --i) free.push_back(i);
+        std::vector<RevAction> acts;
+        plan_reversal(0, K, 0, free, acts);
+        StepArgs fa = step_args(s, W, b);
+        double2* tab_adj = s->tab_b.p + (size_t)kTabSteps * T;
+        AdjArgs aa = adj_args(s, cs, b.afields, b.ablk, b.consts, nblk_adj,
+                              dL_dE + (size_t)q0 * (K + 1) * 2, tp.dt, K, NG, dgG0 != nullptr,
+                              W.nq);
+        const char* last_work = nullptr;
+        int lam_cur = 0;
+        for (const RevAction& act : acts) {
+            if (act.kind == 0) {
+                const char* cur = slot_ptr(act.src);
+                for (int32_t k = act.k0; k < act.k1; ++k) {
+                    const int32_t j = k - act.k0;
+                    if (j % kTabSteps == 0) {
+                        fa.k = k;
+                        fa.tab = s->tab_b.p;
+                        if ((e = launch_tables(fa, std::min(kTabSteps, act.k1 - k), st)) != hipSuccess)
+                            return hip_fail(s, e, "table launch");
+                    }
+                    char* dst = (k == act.k1 - 1 && act.dst >= 0) ? slot_ptr(act.dst) : b.pop[j & 1];
+                    fa.k = k;
+                    fa.tab = s->tab_b.p + (size_t)(j % kTabSteps) * T;
+                    fa.src = cur;
+                    fa.dst = dst;
+                    if ((e = launch_step(s->prec, W.shape, fa, W.nblk_total, st)) != hipSuccess)
+                        return hip_fail(s, e, "recompute launch");
+                    cur = dst;
+                    ++nfwd;
+                }
+                if (act.dst < 0) last_work = cur;
+            } else {
+                const int32_t k = act.k1;
+                fa.k = k - 1;
+                fa.tab = tab_adj;
+                if ((e = launch_tables(fa, k < K ? 2 : 1, st)) != hipSuccess)
+                    return hip_fail(s, e, "adjoint table launch");
+                aa.k = k;
+                aa.top = (k == K) ? 1 : 0;
+                aa.lam_in = aa.top ? nullptr : s->lam[lam_cur].p;
+                aa.lam_out = s->lam[lam_cur ^ 1].p;
+                aa.fwd = act.src >= 0 ? slot_ptr(act.src) : last_work;
+                aa.tab_prev = tab_adj;
+                aa.tab_cur = aa.top ? tab_adj : tab_adj + T;
+                aa.slot = 0;
+                if ((e = launch_adj(s->prec, W.shape, aa, nblk_adj, st)) != hipSuccess)
+                    return hip_fail(s, e, "adjoint launch");
+                lam_cur ^= 1;
+                if ((e = launch_adj_gsum(s->gpart.p, b.afields, W.n_fields, nblk_adj, NG, k - 1, 1,
+                                         s->gfield.p, f0, nfT, st)) != hipSuccess)
+                    return hip_fail(s, e, "adjoint sum launch");
+            }
+        }
+        f0 += W.n_fields;
+    }
+    if ((e = s->adj_gmeta.ensure(G.gmeta.size())) != hipSuccess)
+        return hip_fail(s, e, "allocating tables");
+    if ((rc = upload(s, {{G.gmeta.data(), s->adj_gmeta.p, G.gmeta.size() * sizeof(double)}}, true,
+                     st)) != BTL_OK)
+        return rc;
+    s->stat_fwd_steps = nfwd;
+    s->stat_waves = (int32_t)cut.size() - 1;
+    s->stat_snapshots = min_slots;
+    return final_gradients(s, s->gfield.p, K, nfT, NG, tp.dt, tp.sub, Q, tp.nq, s->adj_gmeta.p,
+                           dD, dT2, dkappa, df, dgG0, st);
+}
+
+extern "C" btl_status btl_backward(btl_sim* s, const double* dL_dE, double* dD, double* dT2,
+                                   double* dkappa, double* df, double* dgG0, void* stream) {
+    if (!s) return BTL_E_INVAL;
+    btl_status rc = take_nonfinite(s);
+    if (rc != BTL_OK) return rc;
+    if (!s->tape.valid) return fail(s, BTL_E_INVAL, "no adjoint tape: run btl_forward with ckpt_every > 0");
+    if (!dL_dE) return fail(s, BTL_E_INVAL, "dL_dE is NULL");
+    if (dgG0 && !s->tape.g_ok)
+        return fail(s, BTL_E_UNSUPPORTED,
+                    "dgG0 needs btl_set_grad_gG0(s, 1) before the taped forward (a mirrored axis "
+                    "without a gradient component, or the conjugate pairing next to a periodic "
+                    "axis, has no image fields to differentiate)");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (s->tape.deferred) return backward_deferred(s, dL_dE, dD, dT2, dkappa, df, dgG0, st);
+    return backward_uniform(s, dL_dE, dD, dT2, dkappa, df, dgG0, st);
+}
+
+extern "C" btl_status btl_get_backward_stats(const btl_sim* s, int64_t* fwd_steps, int32_t* groups,
+                                             int32_t* snapshots) {
+    if (!s || !fwd_steps || !groups || !snapshots) return BTL_E_INVAL;
+    *fwd_steps = s->stat_fwd_steps;
+    *groups = s->stat_waves;
+    *snapshots = s->stat_snapshots;
     return BTL_OK;
+}
+
+// Autotuner cache key: device, storage precision, lattice, scheme, and per
+// q-sample the kernel geometry, the field count and whether it carries
+// membrane positions (what decides the grid and the kernel variant).
+static std::string tune_key(const btl_sim* s, const CallPlan& p) {
+    hipDeviceProp_t prop;
+    memset(&prop, 0, sizeof(prop));
+    (void)hipGetDeviceProperties(&prop, s->device);
+    std::string k = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount);
+    k += "/p" + std::to_string(s->prec) + "/n" + std::to_string(p.nq) + "/c" +
+         std::to_string(p.classical ? 1 : 0);
+    for (const FieldDesc& d : p.fl)
+        k += "/" + std::to_string(d.n[0]) + "x" + std::to_string(d.n[1]) + "x" +
+             std::to_string(d.n[2]) + (d.gm >= 0 ? "g" : "");
+    return k;
 }
 
 extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void* stream) {
     if (!s) return BTL_E_INVAL;
-    // fixed launch shape for measurements: BTLBM_TILE (0..5, see TileShape), BTLBM_ZC,
-    // BTLBM_XCD (0 plain, 1 XCD-contiguous workgroup order); BTLBM_VERBOSE
-    // prints the choice
-    const char* et = getenv("BTLBM_TILE");
-    const char* ez = getenv("BTLBM_ZC");
-    const char* ex = getenv("BTLBM_XCD");
-    if (ex) s->xcd = atoi(ex) ? 1 : 0;
-    if (et || ez) {
-        if (et) s->tile_shape = std::max(0, std::min(kTileCount - 1, atoi(et)));
-        if (s->nq == 5) s->tile_shape = kTile256x1;
-        else if (s->tile_shape == kTile256x1) s->tile_shape = kTile128x2;
-        if (ez) s->zc = std::max(0, std::min(kMaxZc, atoi(ez)));
-        return BTL_OK;
-    }
+    btl_status rc = take_nonfinite(s);
+    if (rc != BTL_OK) return rc;
     if (!s->last.valid) return fail(s, BTL_E_INVAL, "btl_autotune replays the last btl_forward: call it first");
     if (K_probe < 1) return fail(s, BTL_E_INVAL, "K_probe must be >= 1");
-    const btl_sim::SimLast& L = s->last;
-    const int32_t Qr = std::min<int32_t>(Q > 0 ? Q : (int32_t)L.q_geom.size(), (int32_t)L.q_geom.size());
-    std::vector<double> f((size_t)K_probe * s->substeps);
-    for (size_t k = 0; k < f.size(); ++k) f[k] = L.f.empty() ? 1.0 : L.f[k % L.f.size()];
+    const btl_sim::SimLast saved = s->last;
+    const int32_t Qr = std::min<int32_t>(Q > 0 ? Q : (int32_t)saved.q_geom.size(),
+                                         (int32_t)saved.q_geom.size());
+    std::vector<double> f((size_t)K_probe * s->set.msub);
+    for (size_t k = 0; k < f.size(); ++k) f[k] = saved.f.empty() ? 1.0 : saved.f[k % saved.f.size()];
+    // a launch this process already chose for the same shape of workload
+    std::string key;
+    {
+        Settings cs = s->set;
+        cs.tile_shape = -1;
+        cs.zc = 0;
+        cs.xcd = -1;
+        CallPlan p;
+        if ((rc = make_plan(s, cs, saved.dt, K_probe, saved.D.data(), saved.T2.data(),
+                            saved.kappa.data(), Qr, saved.q_geom.data(), saved.gG0.data(),
+                            f.data(), false, p)) != BTL_OK)
+            return rc;
+        key = tune_key(s, p);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const TuneEntry& t : g_tune_cache)
+            if (t.key == key) {
+                s->set.tile_shape = t.shape;
+                s->set.zc = t.zc;
+                s->set.xcd = t.xcd;
+                return BTL_OK;
+            }
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e;
     if ((e = s->tune_E.ensure((size_t)Qr * (K_probe + 1) * 2)) != hipSuccess)
@@ -1188,7 +1771,7 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
         return hip_fail(s, e, "autotune events");
     int nz_max = 1;
     for (int q = 0; q < Qr; ++q)
-        nz_max = std::max(nz_max, kernel_geom(s->geoms[L.q_geom[q]], s->nq).n[2]);
+        nz_max = std::max(nz_max, kernel_geom(s->geoms[saved.q_geom[q]], s->set.nq).n[2]);
     // z-column lengths: whole columns, halves, thirds, quarters, and short
     // columns for small lattices that need more workgroups
     std::vector<int> zcs = {0};
@@ -1197,7 +1780,6 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
     std::sort(zcs.begin(), zcs.end());
     zcs.erase(std::unique(zcs.begin(), zcs.end()), zcs.end());
     zcs.erase(std::remove_if(zcs.begin(), zcs.end(), [&](int z) { return z >= nz_max; }), zcs.end());
-    const btl_sim::SimLast saved = L;
     // one warm forward of the probe in the current launch configuration,
     // then the fastest of kTuneReps timed ones (single timings of a few
     // milliseconds are noisy at the percent level)
@@ -1211,10 +1793,10 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
         for (int r = 0; r <= kTuneReps; ++r) {
             if (r > 1 && best > 0.0f && *best_ms > kTuneCut * best) break;
             if (r > 0) (void)hipEventRecord(e0, st);
-            const btl_status rr = btl_forward(s, saved.dt, K_probe, saved.D.data(), saved.T2.data(),
-                                              saved.kappa.data(), Qr, saved.q_geom.data(),
-                                              saved.gG0.data(), f.data(), s->tune_E.p, nullptr, 0,
-                                              stream);
+            const btl_status rr = forward_entry(s, saved.dt, K_probe, saved.D.data(),
+                                                saved.T2.data(), saved.kappa.data(), Qr,
+                                                saved.q_geom.data(), saved.gG0.data(), f.data(),
+                                                s->tune_E.p, nullptr, 0, stream);
             if (rr != BTL_OK) return rr;
             if (r == 0) continue;
             (void)hipEventRecord(e1, st);
@@ -1226,9 +1808,9 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
         return BTL_OK;
     };
     int best_shape = -1, best_zc = 0, best_xcd = 0;
-    btl_status rc = BTL_OK;
+    rc = BTL_OK;
     std::vector<int> shapes;
-    if (s->nq == 5)
+    if (s->set.nq == 5)
         shapes.push_back(kTile256x1);
     else
         shapes.assign(kShapes3D, kShapes3D + kShapeCount3D);
@@ -1237,9 +1819,9 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
     for (int sh : shapes) {
         for (int zc : zcs) {
             for (int xo = 0; xo < 2 && rc == BTL_OK; ++xo) {
-                s->tile_shape = sh;
-                s->zc = zc;
-                s->xcd = xo;
+                s->set.tile_shape = sh;
+                s->set.zc = zc;
+                s->set.xcd = xo;
                 float ms = 0.0f;
                 if ((rc = time_probe(&ms)) != BTL_OK) break;
                 if (best < 0.0f || ms < best) {
@@ -1257,14 +1839,18 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
     (void)hipEventDestroy(e1);
     s->last = saved;
     if (rc != BTL_OK) {
-        s->tile_shape = -1;
-        s->zc = 0;
-        s->xcd = -1;
+        s->set.tile_shape = -1;
+        s->set.zc = 0;
+        s->set.xcd = -1;
         return rc;
     }
-    s->tile_shape = best_shape;
-    s->zc = best_zc;
-    s->xcd = best_xcd;
+    s->set.tile_shape = best_shape;
+    s->set.zc = best_zc;
+    s->set.xcd = best_xcd;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache.push_back({key, best_shape, best_zc, best_xcd});
+    }
     if (getenv("BTLBM_VERBOSE"))
         fprintf(stderr, "btlbm autotune: tile shape %d, z-column %d, xcd order %d (%.3f ms per probe)\n",
                 best_shape, best_zc, best_xcd, best);
@@ -1274,9 +1860,44 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
 extern "C" btl_status btl_get_launch(const btl_sim* s, int32_t* tile_shape, int32_t* zc,
                                      int32_t* xcd) {
     if (!s || !tile_shape || !zc || !xcd) return BTL_E_INVAL;
-    *tile_shape = s->tile_shape;
-    *zc = s->zc;
-    *xcd = s->xcd;
+    *tile_shape = s->set.tile_shape;
+    *zc = s->set.zc;
+    *xcd = s->set.xcd;
+    return BTL_OK;
+}
+
+extern "C" btl_status btl_set_launch(btl_sim* s, int32_t tile_shape, int32_t zc, int32_t xcd) {
+    if (!s) return BTL_E_INVAL;
+    if (tile_shape < -1 || tile_shape >= kTileCount)
+        return fail(s, BTL_E_INVAL, "tile_shape must be -1 or 0..5");
+    if (zc < 0 || zc > kMaxZc) return fail(s, BTL_E_INVAL, "zc must be in 0..1024");
+    if (xcd < -1 || xcd > 1) return fail(s, BTL_E_INVAL, "xcd must be -1, 0 or 1");
+    s->set.tile_shape = tile_shape;
+    s->set.zc = zc;
+    s->set.xcd = xcd;
+    return BTL_OK;
+}
+
+extern "C" btl_status btl_set_adjoint_launch(btl_sim* s, int32_t zc, int32_t xcd) {
+    if (!s) return BTL_E_INVAL;
+    if (zc < -1 || zc > kMaxZc) return fail(s, BTL_E_INVAL, "zc must be in -1..1024");
+    if (xcd < -1 || xcd > 1) return fail(s, BTL_E_INVAL, "xcd must be -1, 0 or 1");
+    s->set.adj_zc = zc;
+    s->set.adj_xcd = xcd;
+    return BTL_OK;
+}
+
+extern "C" btl_status btl_set_memory_budget(btl_sim* s, int64_t bytes) {
+    if (!s) return BTL_E_INVAL;
+    if (bytes < 0) return fail(s, BTL_E_INVAL, "the memory budget must be >= 0 (0: none)");
+    s->mem_limit = bytes;
+    return BTL_OK;
+}
+
+extern "C" btl_status btl_set_graphs(btl_sim* s, int32_t on) {
+    if (!s) return BTL_E_INVAL;
+    if (on != 0 && on != 1) return fail(s, BTL_E_INVAL, "btl_set_graphs takes 0 or 1");
+    s->use_graphs = on;
     return BTL_OK;
 }
 
@@ -1284,7 +1905,7 @@ extern "C" btl_status btl_set_lattice(btl_sim* s, int32_t lattice) {
     if (!s) return BTL_E_INVAL;
     if (lattice != BTL_D3Q7 && lattice != BTL_D2Q5)
         return fail(s, BTL_E_INVAL, "lattice must be BTL_D3Q7 or BTL_D2Q5");
-    s->nq = lattice == BTL_D2Q5 ? 5 : 7;
+    s->set.nq = lattice == BTL_D2Q5 ? 5 : 7;
     s->tape.valid = false;
     s->last.valid = false;
     return BTL_OK;
@@ -1293,14 +1914,14 @@ extern "C" btl_status btl_set_lattice(btl_sim* s, int32_t lattice) {
 extern "C" btl_status btl_set_grad_gG0(btl_sim* s, int32_t on) {
     if (!s) return BTL_E_INVAL;
     if (on != 0 && on != 1) return fail(s, BTL_E_INVAL, "btl_set_grad_gG0 takes 0 or 1");
-    s->grad_g = on;
+    s->set.grad_g = on;
     return BTL_OK;
 }
 
 extern "C" btl_status btl_set_substeps(btl_sim* s, int32_t m) {
     if (!s) return BTL_E_INVAL;
     if (m < 1 || m > 65536) return fail(s, BTL_E_INVAL, "substeps must be in 1..65536");
-    s->substeps = m;
+    s->set.msub = m;
     s->last.valid = false;
     return BTL_OK;
 }
@@ -1309,7 +1930,7 @@ extern "C" btl_status btl_set_scheme(btl_sim* s, int32_t scheme) {
     if (!s) return BTL_E_INVAL;
     if (scheme != BTL_HYBRID && scheme != BTL_CLASSICAL)
         return fail(s, BTL_E_INVAL, "scheme must be BTL_HYBRID or BTL_CLASSICAL");
-    s->scheme = scheme;
+    s->set.scheme = scheme;
     s->tape.valid = false;
     return BTL_OK;
 }
@@ -1330,7 +1951,8 @@ extern "C" void btl_destroy(btl_sim* s) {
     s->consts.release();
     s->partial.release();
     s->tune_E.release();
-    if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+    for (GraphSlot& g : s->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     s->E_int.release();
     s->ckpt.release();
@@ -1346,6 +1968,7 @@ extern "C" void btl_destroy(btl_sim* s) {
         if (s->stage[i]) (void)hipHostFree(s->stage[i]);
         if (s->stage_ev[i]) (void)hipEventDestroy(s->stage_ev[i]);
     }
+    if (s->nf_host) (void)hipHostFree(s->nf_host);
     delete s;
 }
 

@@ -60,9 +60,9 @@ def _fd(cfg, a, b, which, idx, h_rel=1e-5):
     return (vals[0] - vals[1]) / (2 * h)
 
 
-def _gpu_grads(cfg, prec, a, b, ckpt):
+def _gpu_grads(cfg, prec, a, b, ckpt, **options):
     btl, torch = _gpu()
-    sim = btl.Simulator(cfg["geoms"], cfg["bc"], prec)
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], prec, **options)
     try:
         E = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"],
                         cfg["q_geom"], ckpt_every=ckpt)
@@ -147,22 +147,22 @@ def test_checkpoint_interval_does_not_change_gradients():
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_adjoint_launch_geometry_does_not_change_gradients(prec, monkeypatch):
-    # the adjoint steps may walk whole z columns or short chunks (chosen
-    # when the tape is recorded; BTLBM_ADJ_ZC fixes the length): the
-    # gradients agree to rounding order, and with the mirror faces the
-    # chunks cross the image-field partners' face rows
+def test_adjoint_launch_geometry_does_not_change_gradients(prec):
+    # the adjoint steps may walk whole z columns or short chunks, in plain
+    # or XCD-contiguous workgroup order (chosen when the tape is recorded;
+    # btl_set_adjoint_launch fixes them): the gradients agree to rounding
+    # order, and with the mirror faces the chunks cross the image-field
+    # partners' face rows
     cfg = _cfg_small([1, 1, 1], seed=57, K=70, n=(14, 12, 11))
     Q, K = len(cfg["gG0"]), len(cfg["f"])
     a, b = _loss_weights(Q, K, seed=5)
-    ref = _gpu_grads(cfg, prec, a, b, ckpt=20)
+    ref = _gpu_grads(cfg, prec, a, b, ckpt=20, adjoint_launch=(0, 0))
     tol = 1e-12 if prec == "f64" else 1e-6
-    for zc in ("1", "3", "4"):
-        monkeypatch.setenv("BTLBM_ADJ_ZC", zc)
-        got = _gpu_grads(cfg, prec, a, b, ckpt=20)
+    for zc, xcd in ((1, 0), (3, 1), (4, 0), (0, 1), (2, 1)):
+        got = _gpu_grads(cfg, prec, a, b, ckpt=20, adjoint_launch=(zc, xcd))
         for x, y in zip(ref, got):
             scale = max(np.max(np.abs(x)), 1e-30)
-            assert np.max(np.abs(x - y)) <= tol * scale, (zc, x, y)
+            assert np.max(np.abs(x - y)) <= tol * scale, (zc, xcd, x, y)
 
 
 def _fd_gG0(cfg, a, b, q, ax, h=2e-4):
@@ -313,9 +313,12 @@ def test_cfg4_full_size_gradients_vs_fp64_fd():
     # target made from perturbed parameters (D x1.1/0.9, T2 x1.1/0.9,
     # kappa x1.5); the waveform is parametrized by 200 samples of 20 steps.
     # FP32-storage adjoint vs central differences of the FP64-storage GPU
-    # forward (itself checked against the oracle); 10 of the 30 q-samples.
+    # forward (itself checked against the oracle to rounding order on the
+    # reduced cases; a full-size oracle forward would take the host about an
+    # hour per difference quotient); all 30 q-samples.
     btl, torch = _gpu()
-    cfg = w.make_config("cfg4", n_q=10)
+    cfg = w.make_config("cfg4")
+    assert len(cfg["gG0"]) == 30
     K = len(cfg["f"])
     dt = cfg["dt"]
     D0, T20, k0 = np.array(cfg["D"]), np.array(cfg["T2"]), np.array(cfg["kappa"])
@@ -341,7 +344,7 @@ def test_cfg4_full_size_gradients_vs_fp64_fd():
         kmat = torch.stack([torch.stack([torch.tensor(math.inf, dtype=torch.float64), kap]),
                             torch.stack([kap, torch.tensor(math.inf, dtype=torch.float64)])])
         f = smp.repeat_interleave(20)[:K]
-        print("GPU cfg4 96^3 K=4000 Q=10 f32 adjoint", flush=True)
+        print("GPU cfg4 96^3 K=4000 Q=30 f32 adjoint", flush=True)
         E = btl.bloch_torrey_signal(D, T2, kmat, f, sim32, dt, cfg["gG0"], ckpt_every=100)
         Etc = torch.tensor(np.stack([Et.real, Et.imag], -1))
         loss = ((E[:, -1, :].cpu() - Etc) ** 2).sum()

@@ -6,7 +6,6 @@ Same tolerances as the hybrid parity tests: FP64 storage to rounding order
 and 1e-7 absolute below that.
 """
 import math
-import os
 
 import numpy as np
 import pytest
@@ -106,22 +105,22 @@ def test_classical_K0_K1_and_graph_replay():
         # graph replays (K >= 16) against eager launches
         f = cfg["f"][:200]
         reps = [sim.forward(*args, f, cfg["gG0"]).cpu().numpy() for _ in range(3)]
-        os.environ["BTLBM_NO_GRAPH"] = "1"
+        btl.btl_set_graphs(sim._h, 0)
         try:
             eager = sim.forward(*args, f, cfg["gG0"]).cpu().numpy()
         finally:
-            del os.environ["BTLBM_NO_GRAPH"]
+            btl.btl_set_graphs(sim._h, 1)
         for r in reps:
             assert np.array_equal(r, eager)
         # the classical initial state depends on the gradient: another
         # gradient of the same shape must not replay the cached graph's init
         gG2 = np.asarray(cfg["gG0"]) * 1.7
         Eg2 = sim.forward(*args, f, gG2).cpu().numpy()
-        os.environ["BTLBM_NO_GRAPH"] = "1"
+        btl.btl_set_graphs(sim._h, 0)
         try:
             eager2 = sim.forward(*args, f, gG2).cpu().numpy()
         finally:
-            del os.environ["BTLBM_NO_GRAPH"]
+            btl.btl_set_graphs(sim._h, 1)
         assert np.array_equal(Eg2, eager2)
         assert not np.array_equal(Eg2, eager)
         # switching back to the hybrid scheme reproduces a fresh hybrid run

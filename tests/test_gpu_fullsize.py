@@ -1,11 +1,12 @@
 """The large workloads at their full sizes, in the launch configuration the
-benchmark uses (autotuned shape, q-waves where the state exceeds device
-memory), checked on sampled q-samples against the FP64 oracle over a few
-steps, and by properties that hold at any size.  FP32 storage, tolerances
-as in the other parity tests.  The autotuner probes the first (at most 8)
-q-samples, which fit in one q-wave; the checked forward runs all of them."""
-import math
-
+benchmark uses (autotuned on the first 32 q-samples with the benchmark's
+probe length, q-waves where the state exceeds device memory), checked on
+sampled q-samples against the FP64 oracle -- the signal and the final
+magnetization element by element after 20 steps -- and by properties that
+hold at any size.  FP32 storage, tolerances as in the other parity tests.
+The full-length FP32 error on the largest lattice is measured against FP64
+storage on the same path (the FP64 path matches the oracle to rounding
+order on every reduced case)."""
 import numpy as np
 import pytest
 
@@ -16,64 +17,86 @@ from .test_gpu_parity import _check, _gpu
 
 pytestmark = pytest.mark.gpu
 
+_CFG = {}
 
-def _forward_autotuned(btl, cfg, K, want_M=False, probe=2):
+
+def _config(name):
+    # the 512^3 cell packing takes the host ~40 s to draw: built once
+    if name not in _CFG:
+        print(f"building {name}", flush=True)
+        _CFG[name] = w.make_config(name)
+    return _CFG[name]
+
+
+def _forward_autotuned(btl, cfg, K, want_M=False, keep_M=()):
+    """Forward of all q-samples in the benchmark's launch: autotuned on the
+    first min(32, Q) q-samples, about 1.5e9 field-site updates per probe."""
     import torch
     sim = btl.Simulator(cfg["geoms"], cfg["bc"], "f32", lattice=cfg.get("lattice", 0))
     try:
         stream = torch.cuda.current_stream().cuda_stream
-        sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:probe],
-                    cfg["gG0"], cfg["q_geom"])
-        btl.btl_autotune(sim._h, min(8, len(cfg["gG0"])), probe, stream)
+        Qt = min(32, len(cfg["gG0"]))
+        fst = sum(cfg["geoms"][int(g)].comp.size for g in cfg["q_geom"][:Qt])
+        probe = max(2, min(40, int(1.5e9 / fst)))
+        sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:2],
+                    cfg["gG0"][:Qt], cfg["q_geom"][:Qt])
+        btl.btl_autotune(sim._h, Qt, probe, stream)
+        print(f"  launch {btl.btl_get_launch(sim._h)}", flush=True)
         out = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:K],
                           cfg["gG0"], cfg["q_geom"], want_M=want_M)
         torch.cuda.synchronize()
         if want_M:
-            return out[0].cpu().numpy(), [m.cpu().numpy() for m in out[1]]
+            return out[0].cpu().numpy(), {q: out[1][q].cpu().numpy() for q in keep_M}
         return out.cpu().numpy()
     finally:
         sim.close()
 
 
-def _sampled(cfg, qs, K):
+def _sampled(cfg, qs, K, want_M=False):
     print(f"  GPU done; oracle on q-samples {qs}", flush=True)
     c = dict(cfg, f=cfg["f"][:K])
-    Eo, _ = oracle.simulate_config(c, q=qs, threads=16)
-    return Eo
+    return oracle.simulate_config(c, q=qs, threads=16, want_M=want_M)
 
 
 def test_cfg3a_full_size_256_q_sampled():
     # 256^3 cylinders + spheres, 256 q-samples (more state than the device
-    # holds: the library runs them in q-waves)
+    # holds: the library runs them in q-waves); b = 500 .. 3000 s/mm^2
     btl = _gpu()
-    cfg = w.make_config("cfg3a")
-    K = 4
-    print("GPU cfg3a 256^3 x 256 q, K=4", flush=True)
-    Eg = _forward_autotuned(btl, cfg, K)
+    cfg = _config("cfg3a")
+    K = 20
     qs = [0, 97, 255]
-    Eo = _sampled(cfg, qs, K)
+    print("GPU cfg3a 256^3 x 256 q, K=20, E and M_final", flush=True)
+    Eg, Mg = _forward_autotuned(btl, cfg, K, want_M=True, keep_M=qs)
+    Eo, Mo = _sampled(cfg, qs, K, want_M=True)
     _check(Eg[qs], Eo, "f32", "cfg3a sampled q")
+    for i, q in enumerate(qs):
+        _check(Mg[q], Mo[i], "f32", f"cfg3a M_final q={q}")
 
 
 def test_cfg3b_full_size_ragged_sampled():
     btl = _gpu()
-    cfg = w.make_config("cfg3b")
-    K = 4
-    print("GPU cfg3b 16 geometries 96^3..192^3, K=4", flush=True)
-    Eg = _forward_autotuned(btl, cfg, K)
+    cfg = _config("cfg3b")
+    K = 20
     qs = [0, 40, 95]          # geometries 0, 6 and 15
-    Eo = _sampled(cfg, qs, K)
+    print("GPU cfg3b 16 geometries 96^3..192^3, K=20, E and M_final", flush=True)
+    Eg, Mg = _forward_autotuned(btl, cfg, K, want_M=True, keep_M=qs)
+    Eo, Mo = _sampled(cfg, qs, K, want_M=True)
     _check(Eg[qs], Eo, "f32", "cfg3b sampled q")
+    for i, q in enumerate(qs):
+        _check(Mg[q], Mo[i], "f32", f"cfg3b M_final q={q}")
 
 
 def test_cfg5_full_size_sampled_and_decay():
     btl = _gpu()
-    cfg = w.make_config("cfg5")
-    K = 3
-    print("GPU cfg5 512^3 x 32 q, K=3", flush=True)
-    Eg = _forward_autotuned(btl, cfg, K)
-    Eo = _sampled(cfg, [0], K)
-    _check(Eg[[0]], Eo, "f32", "cfg5 q=0")
+    cfg = _config("cfg5")
+    K = 20
+    qs = [0, 31]
+    print("GPU cfg5 512^3 x 32 q, K=20, E and M_final", flush=True)
+    Eg, Mg = _forward_autotuned(btl, cfg, K, want_M=True, keep_M=qs)
+    Eo, Mo = _sampled(cfg, qs, K, want_M=True)
+    _check(Eg[qs], Eo, "f32", "cfg5 sampled q")
+    for i, q in enumerate(qs):
+        _check(Mg[q], Mo[i], "f32", f"cfg5 M_final q={q}")
     # one T2 in every phase and no gradient: E_k = exp(-k dt / T2) for every
     # q-sample, over 40 steps, whatever the cells and membranes
     c = dict(cfg, T2=np.full(3, 70.0), gG0=np.zeros((4, 3)), q_geom=np.zeros(4, np.int32))
@@ -83,11 +106,44 @@ def test_cfg5_full_size_sampled_and_decay():
     assert np.max(np.abs(Eg - ref[None, :])) < 1e-6
 
 
+_FULL = {}
+
+
+def test_cfg5_full_length_fp32():
+    # 512^3 three-phase cells, q-sample 0, all 22,500 steps (TE = 45 ms):
+    # the FP32-storage run, kept for the comparison below
+    btl = _gpu()
+    cfg = _config("cfg5")
+    c = dict(cfg, gG0=cfg["gG0"][:1], q_geom=cfg["q_geom"][:1])
+    assert len(c["f"]) == 22500
+    print("GPU cfg5 512^3 q=0, 22500 steps, f32", flush=True)
+    _FULL["f32"] = btl.simulate_config(c, prec="f32").cpu().numpy()
+    assert np.isfinite(_FULL["f32"]).all()
+
+
+def test_cfg5_full_length_fp64_storage_and_error():
+    # the same run with FP64 storage; the stated FP32 bound over the full
+    # echo time: |dE| <= 1e-5 |E| where |E| >= 1e-2, 1e-7 absolute below
+    btl = _gpu()
+    if "f32" not in _FULL:
+        pytest.skip("needs test_cfg5_full_length_fp32 first")
+    cfg = _config("cfg5")
+    c = dict(cfg, gG0=cfg["gG0"][:1], q_geom=cfg["q_geom"][:1])
+    print("GPU cfg5 512^3 q=0, 22500 steps, f64", flush=True)
+    E64 = btl.simulate_config(c, prec="f64").cpu().numpy()
+    E32 = _FULL["f32"]
+    big = np.abs(E64) >= 1e-2
+    rel = np.max(np.abs(E32 - E64)[big] / np.abs(E64)[big])
+    small = np.max(np.abs(E32 - E64)[~big]) if (~big).any() else 0.0
+    print(f"  cfg5 full length: max rel |dE| (|E| >= 1e-2) {rel:.3e}, max abs below {small:.3e}",
+          flush=True)
+    assert rel <= 1e-5 and small <= 1e-7
+
+
 def test_cfg2_full_length_fp32_against_fp64_storage():
-    # the benchmark workload at full size and full length (128^3, 6 oblique
+    # the axon workload at full size and full length (128^3, 6 oblique
     # q-samples on mirrored faces, 10^4 steps): FP32 storage against FP64
-    # storage on the same GPU path (which matches the FP64 oracle to 1e-12
-    # on the reduced and full-length 64^3 cases); the stated FP32 bound
+    # storage on the same GPU path; the stated FP32 bound
     btl = _gpu()
     cfg = w.make_config("cfg2")
     K = len(cfg["f"])

@@ -117,7 +117,7 @@ def test_positions_errors():
 
 @pytest.mark.parametrize("shape,zc", [(5, 3), (1, 4), (3, 0)])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_positions_every_launch_shape(shape, zc, prec, monkeypatch):
+def test_positions_every_launch_shape(shape, zc, prec):
     # the general condition walks each column chunk one site at a time: runs
     # of 256 sites with 3-site chunks (a ragged last chunk), 32x8 tiles with
     # 4-site chunks and 128x2 tiles over whole columns, against the oracle
@@ -128,10 +128,7 @@ def test_positions_every_launch_shape(shape, zc, prec, monkeypatch):
     sim = btl.Simulator(cfg["geoms"], cfg["bc"], prec)
     try:
         args = (cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"])
-        sim.forward(*args, cfg["f"][:2], cfg["gG0"])
-        monkeypatch.setenv("BTLBM_TILE", str(shape))
-        monkeypatch.setenv("BTLBM_ZC", str(zc))
-        btl.btl_autotune(sim._h, 1, 1, torch.cuda.current_stream().cuda_stream)
+        btl.btl_set_launch(sim._h, shape, zc, -1)
         assert btl.btl_get_launch(sim._h)[:2] == (shape, zc)
         E = sim.forward(*args, cfg["f"], cfg["gG0"]).cpu().numpy()
     finally:

@@ -182,46 +182,76 @@ def test_autotune_keeps_results():
     _check(E2, Eo, "f64", "after autotune")
 
 
-@pytest.mark.parametrize("shape,zc", [(5, 0), (5, 3), (2, 4), (1, 0)])
-@pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_every_tile_shape_matches_oracle(shape, zc, prec, monkeypatch):
-    # each launch shape (5: runs of 256 consecutive sites of the x-y plane,
-    # 2: 16x16, 1: 32x8) on a ragged lattice with mirrored faces, oblique
-    # gradients (image fields) and membranes, forward and adjoint
-    btl = _gpu()
-    import torch
+_SHAPE_CACHE = {}
+
+
+def _shape_case():
     cfg = w.make_config("cfg2", n=21, K=150)
     cfg["geoms"][0] = w.cylinders_z((21, 19, 9), 0.25, seed=23, vf_target=0.5, periodic=False)
-    sim = btl.Simulator(cfg["geoms"], cfg["bc"], prec)
+    return cfg
+
+
+def _shape_oracle(cfg):
+    # the oracle's answer does not depend on the launch: computed once
+    if "oracle" not in _SHAPE_CACHE:
+        _SHAPE_CACHE["oracle"] = oracle.simulate_config(cfg, want_M=True, threads=8)
+    return _SHAPE_CACHE["oracle"]
+
+
+def _shape_ref_grads(btl, cfg, prec, args, g, K):
+    # gradients of the default launch of a fresh simulator, once per precision
+    key = ("grads", prec)
+    if key not in _SHAPE_CACHE:
+        sim = btl.Simulator(cfg["geoms"], cfg["bc"], prec)
+        try:
+            sim.forward(*args, ckpt_every=50)
+            _SHAPE_CACHE[key] = [t.cpu().numpy() for t in sim.backward(g, 2, K)]
+        finally:
+            sim.close()
+    return _SHAPE_CACHE[key]
+
+
+@pytest.mark.parametrize("shape,zc,xcd", [(5, 0, 0), (5, 3, 1), (2, 4, 0), (1, 0, 1),
+                                          (0, 2, 1), (0, 0, 0), (3, 3, 1), (3, 0, 0)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_every_tile_shape_matches_oracle(shape, zc, xcd, prec):
+    # each launch shape (5: runs of 256 consecutive sites of the x-y plane,
+    # 3: 128x2, 2: 16x16, 1: 32x8, 0: 64x4), whole or chunked z columns, in
+    # plain and XCD-contiguous workgroup order (xcd_tile renumbers the
+    # workgroups), on a ragged lattice with mirrored faces, oblique gradients
+    # (image fields) and membranes: E and M_final against the oracle, and
+    # the adjoint (in the same workgroup order) against the default launch
+    btl = _gpu()
+    import torch
+    cfg = _shape_case()
+    print(f"GPU launch shape={shape} zc={zc} xcd={xcd} prec={prec}", flush=True)
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], prec, launch=(shape, zc, xcd),
+                        adjoint_launch=(-1, xcd))
     try:
         args = (cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"])
-        sim.forward(*args[:4], cfg["f"][:2], cfg["gG0"])
-        monkeypatch.setenv("BTLBM_TILE", str(shape))
-        monkeypatch.setenv("BTLBM_ZC", str(zc))
-        btl.btl_autotune(sim._h, 1, 1, torch.cuda.current_stream().cuda_stream)
-        E = sim.forward(*args, ckpt_every=50)
+        E, M = sim.forward(*args, want_M=True)
+        M = [m.cpu().numpy() for m in M]
+        E2 = sim.forward(*args, ckpt_every=50)
         Q, K = len(cfg["gG0"]), len(cfg["f"])
         r = np.random.default_rng(3)
         g = torch.tensor(r.normal(size=(Q, K + 1, 2)), dtype=torch.float64, device=E.device)
         grads = [t.cpu().numpy() for t in sim.backward(g, 2, K)]
         E = E.cpu().numpy()
+        assert np.array_equal(E, E2.cpu().numpy())
     finally:
         sim.close()
-    Eo, _ = oracle.simulate_config(cfg)
-    _check(E, Eo, prec, f"shape {shape} zc {zc}")
+    Eo, Mo = _shape_oracle(cfg)
+    _check(E, Eo, prec, f"shape {shape} zc {zc} xcd {xcd}")
+    for q in range(len(Mo)):
+        _check(M[q], Mo[q], prec, f"M_final q={q}")
     # gradients against the default launch shape of a fresh simulator
-    sim = btl.Simulator(cfg["geoms"], cfg["bc"], prec)
-    try:
-        sim.forward(*args, ckpt_every=50)
-        ref = [t.cpu().numpy() for t in sim.backward(g, 2, K)]
-    finally:
-        sim.close()
+    ref = _shape_ref_grads(btl, cfg, prec, args, g, K)
     tol = 1e-11 if prec == "f64" else 1e-5
     for x, y in zip(grads, ref):
         assert np.max(np.abs(x - y)) <= tol * max(np.max(np.abs(y)), 1e-30)
 
 
-def test_q_waves_match_single_batch(monkeypatch):
+def test_q_waves_match_single_batch():
     # a device-memory budget below the batch's population size splits the
     # q-samples into consecutive waves; every field is computed exactly as
     # in the single batch
@@ -229,16 +259,14 @@ def test_q_waves_match_single_batch(monkeypatch):
     cfg = w.make_config("cfg4", n=(24, 20, 16), K=60, n_q=7)
     E1 = btl.simulate_config(cfg, prec="f32").cpu().numpy()
     per_q = 2 * 7 * 24 * 20 * 16 * 8
-    monkeypatch.setenv("BTLBM_MEM_BUDGET", str(int(2.5 * per_q)))
-    Eg, Mg = btl.simulate_config(cfg, prec="f32", want_M=True)
-    monkeypatch.delenv("BTLBM_MEM_BUDGET")
+    Eg, Mg = btl.simulate_config(cfg, prec="f32", want_M=True, mem_budget=int(2.5 * per_q))
     assert np.array_equal(E1, Eg.cpu().numpy())
     _, M1 = btl.simulate_config(cfg, prec="f32", want_M=True)
     for a, b in zip(M1, Mg):
         assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
 
 
-def test_graph_replays_match_eager(monkeypatch):
+def test_graph_replays_match_eager():
     # forwards of >= 16 steps run from a cached hipGraph; each replay, with
     # eager work and synchronizations in between, must equal the eager run
     btl = _gpu()
@@ -247,9 +275,9 @@ def test_graph_replays_match_eager(monkeypatch):
     sim = btl.Simulator(cfg["geoms"], cfg["bc"], "f32")
     args = (cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"])
     try:
-        monkeypatch.setenv("BTLBM_NO_GRAPH", "1")
+        btl.btl_set_graphs(sim._h, 0)
         E0 = sim.forward(*args, cfg["f"], cfg["gG0"]).cpu().numpy()
-        monkeypatch.delenv("BTLBM_NO_GRAPH")
+        btl.btl_set_graphs(sim._h, 1)
         for rep in range(3):
             E = sim.forward(*args, cfg["f"], cfg["gG0"]).cpu().numpy()
             assert np.array_equal(E, E0), rep
@@ -259,7 +287,7 @@ def test_graph_replays_match_eager(monkeypatch):
         # changed parameters with the same shape replay the same graph
         D2 = np.array(cfg["D"]) * 1.1
         E2 = sim.forward(cfg["dt"], D2, cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"]).cpu().numpy()
-        monkeypatch.setenv("BTLBM_NO_GRAPH", "1")
+        btl.btl_set_graphs(sim._h, 0)
         E2e = sim.forward(cfg["dt"], D2, cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"]).cpu().numpy()
         assert np.array_equal(E2, E2e)
         assert not np.array_equal(E2, E0)
@@ -267,7 +295,7 @@ def test_graph_replays_match_eager(monkeypatch):
         sim.close()
 
 
-def test_graph_key_tracks_field_layout(monkeypatch):
+def test_graph_key_tracks_field_layout():
     # a cached forward graph takes each field's range, plane stride and
     # q-sample as launch arguments: the same two geometries batched in the
     # other order have the same sizes and must still not replay it
@@ -283,9 +311,9 @@ def test_graph_key_tracks_field_layout(monkeypatch):
         seen = []
         for qg in ([0, 1], [1, 0]):
             Eg = sim.forward(*args, f, gG, qg).cpu().numpy()
-            monkeypatch.setenv("BTLBM_NO_GRAPH", "1")
+            btl.btl_set_graphs(sim._h, 0)
             Ee = sim.forward(*args, f, gG, qg).cpu().numpy()
-            monkeypatch.delenv("BTLBM_NO_GRAPH")
+            btl.btl_set_graphs(sim._h, 1)
             assert np.array_equal(Eg, Ee), qg
             seen.append(Eg)
         assert not np.array_equal(seen[0], seen[1])

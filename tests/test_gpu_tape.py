@@ -1,0 +1,192 @@
+"""Adjoint tapes beyond device memory, through the C ABI.
+
+A taped forward whose uniform tape (a state every C steps plus the segment
+being reversed) exceeds the memory budget keeps only its inputs; the reverse
+sweep then replays the forward from t = 0 (the equilibrium at M = 1) per
+group of q-samples under a binomial checkpointing schedule.  References:
+  * the uniform tape of the same forward: with the adjoint launch fixed the
+    per-step, per-field sums are formed from the same workgroups in the same
+    order, so the gradients are bitwise equal;
+  * the minimal number of forward steps of binomial checkpointing with s
+    kept states for l steps, t l - C(s + t, t - 1) with t the smallest
+    integer with C(s + t, t) >= l (Griewank and Walther's result; the count
+    the library reports must equal it);
+  * central finite differences of the FP64 oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+INF = math.inf
+
+
+def _gpu():
+    import torch
+    import paper_1907_00908_amd as btl
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    btl.load_library()
+    return btl, torch
+
+
+def _cfg(bc=(0, 0, 0), n=(16, 14, 12), K=120, nq=5, seed=81):
+    g = w.cylinders_z(n, 0.25, seed=seed, vf_target=0.5, periodic=(bc[0] == 0))
+    f = w.pgse_waveform(0.12, 0.36, 0.004)[:K]
+    dirs = w.golden_spiral(nq)
+    return dict(name="tape", geoms=[g], bc=list(bc), dx=0.25, dt=0.004, D=np.array([2.0, 1.0]),
+                T2=np.array([40.0, 25.0]), kappa=np.array([[INF, 0.05], [0.05, INF]]), f=f,
+                gG0=9.0 * dirs, q_geom=np.zeros(nq, np.int32))
+
+
+def _state_bytes(cfg, prec, fields_per_q=1):
+    esz = 16 if prec == "f64" else 8
+    return 7 * cfg["geoms"][0].comp.size * esz * fields_per_q
+
+
+def _grads(cfg, prec, ckpt, weights, budget=0, grad_gG0=False, **options):
+    btl, torch = _gpu()
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], prec, mem_budget=budget, grad_gG0=grad_gG0,
+                        **options)
+    try:
+        E = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"],
+                        cfg["q_geom"], ckpt_every=ckpt)
+        g = torch.tensor(weights, dtype=torch.float64, device=E.device)
+        out = [t.cpu().numpy() for t in sim.backward(g, grad_gG0=grad_gG0)]
+        stats = btl.btl_get_backward_stats(sim._h)
+        return E.cpu().numpy(), out, stats
+    finally:
+        sim.close()
+
+
+def _weights(cfg, seed=5):
+    r = np.random.default_rng(seed)
+    return r.normal(size=(len(cfg["gG0"]), len(cfg["f"]) + 1, 2))
+
+
+def _min_forward_steps(l, s):
+    # fewest forward steps that reverse l steps with s kept states (s >= 1)
+    t = 1
+    while math.comb(s + t, t) < l:
+        t += 1
+    return t * l - math.comb(s + t, t - 1)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_deferred_tape_equals_uniform_tape(prec):
+    # budgets: all q-samples in one group with many kept states, one
+    # q-sample per group with plenty, with two, and with one (the state at
+    # t = 0 only: every step replayed from it)
+    cfg = _cfg()
+    Q, K = len(cfg["gG0"]), len(cfg["f"])
+    wts = _weights(cfg)
+    S1 = _state_bytes(cfg, prec)
+    fix = dict(adjoint_launch=(0, 0))
+    E_u, g_u, st_u = _grads(cfg, prec, 20, wts, **fix)
+    assert st_u[2] == 0 and st_u[1] == 1          # uniform tape
+    for budget, groups, slots in [(140 * S1, 1, 24), (33 * S1, Q, 29), (6 * S1, Q, 2),
+                                  (5 * S1, Q, 1)]:
+        print(f"{prec} budget {budget} B: expect {groups} groups, {slots} kept states",
+              flush=True)
+        E_d, g_d, st = _grads(cfg, prec, 20, wts, budget=budget, **fix)
+        assert np.array_equal(E_d, E_u)
+        for x, y in zip(g_u, g_d):
+            assert np.array_equal(x, y)
+        assert st[1] == groups and st[2] == slots, st
+        assert st[0] == groups * _min_forward_steps(K, slots), (st, _min_forward_steps(K, slots))
+
+
+def test_deferred_tape_mirror_oblique_gG0_and_substeps():
+    # image fields of mirrored faces (the full field set for dgG0) and
+    # reaction sub-steps, one q-sample per group
+    btl, torch = _gpu()
+    cfg = _cfg(bc=(1, 1, 1), n=(12, 11, 9), K=64, nq=3, seed=82)
+    cfg["gG0"] = np.array([[7.0, -5.0, 3.0], [3.0, 2.0, 0.0], [0.0, 0.0, 6.0]])
+    wts = _weights(cfg, seed=6)
+    S = _state_bytes(cfg, "f64", fields_per_q=4)
+    E_u, g_u, _ = _grads(cfg, "f64", 16, wts, grad_gG0=True, adjoint_launch=(0, 0))
+    E_d, g_d, st = _grads(cfg, "f64", 16, wts, budget=9 * S, grad_gG0=True,
+                          adjoint_launch=(0, 0))
+    assert st[1] == 3
+    # the deferred forward plans the minimal field set (no tape on the
+    # device), the uniform tape the full one: the same signal to rounding
+    assert np.max(np.abs(E_d - E_u)) < 1e-13
+    for x, y in zip(g_u, g_d):
+        assert np.array_equal(x, y)
+    # m = 2 reaction sub-steps (f carries 2 samples per step)
+    c2 = dict(cfg, f=np.repeat(cfg["f"], 2) * np.tile([1.0, 0.5], len(cfg["f"])))
+    sims = []
+    for budget in (0, 9 * S):
+        sim = btl.Simulator(c2["geoms"], c2["bc"], "f64", substeps=2, mem_budget=budget,
+                            adjoint_launch=(0, 0))
+        try:
+            E = sim.forward(c2["dt"], c2["D"], c2["T2"], c2["kappa"], c2["f"], c2["gG0"],
+                            ckpt_every=16)
+            g = torch.tensor(wts, dtype=torch.float64, device=E.device)
+            sims.append([t.cpu().numpy() for t in sim.backward(g)])
+        finally:
+            sim.close()
+    for x, y in zip(*sims):
+        assert np.array_equal(x, y)
+
+
+def test_deferred_tape_d2q5():
+    btl, torch = _gpu()
+    cfg = w.make_config("cfg2d", n=48, K=80, n_q=4)
+    K = len(cfg["f"])
+    wts = _weights(cfg, seed=7)
+    S = 5 * 48 * 48 * 8
+    out = []
+    for budget in (0, 12 * S):
+        sim = btl.Simulator(cfg["geoms"], cfg["bc"], "f32", lattice=btl.BTL_D2Q5,
+                            mem_budget=budget, adjoint_launch=(0, 0))
+        try:
+            E = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"],
+                            ckpt_every=10)
+            g = torch.tensor(wts, dtype=torch.float64, device=E.device)
+            out.append(([t.cpu().numpy() for t in sim.backward(g)],
+                        btl.btl_get_backward_stats(sim._h)))
+        finally:
+            sim.close()
+    (g_u, st_u), (g_d, st_d) = out
+    assert st_u[2] == 0 and st_d[2] >= 1 and st_d[0] > K
+    for x, y in zip(g_u, g_d):
+        assert np.array_equal(x, y)
+
+
+def test_deferred_tape_vs_oracle_fd():
+    # FP64 adjoint of a deferred tape (tight budget: q-samples one by one,
+    # three kept states) against central differences of the FP64 oracle
+    cfg = _cfg(n=(12, 10, 8), K=90, nq=2, seed=83)
+    Q, K = len(cfg["gG0"]), len(cfg["f"])
+    a = np.random.default_rng(9).normal(size=(Q, K + 1))
+    b = np.random.default_rng(10).normal(size=(Q, K + 1))
+    wts = np.stack([a, b], axis=-1)
+    _, (dD, dT2, dk, df), st = _grads(cfg, "f64", 15, wts, budget=7 * _state_bytes(cfg, "f64"))
+    assert st[1] == Q and st[2] == 3
+
+    def loss(**kw):
+        c = dict(cfg)
+        c.update(kw)
+        E, _ = oracle.simulate_config(c, threads=8)
+        return float(np.sum(a * E.real + b * E.imag))
+
+    h = 1e-5
+    fd_D1 = (loss(D=cfg["D"] * [1, 1 + h]) - loss(D=cfg["D"] * [1, 1 - h])) / (2 * h * cfg["D"][1])
+    fd_T0 = (loss(T2=cfg["T2"] * [1 + h, 1]) - loss(T2=cfg["T2"] * [1 - h, 1])) / (2 * h * cfg["T2"][0])
+    kp, km = cfg["kappa"].copy(), cfg["kappa"].copy()
+    kp[0, 1] = kp[1, 0] = 0.05 * (1 + h)
+    km[0, 1] = km[1, 0] = 0.05 * (1 - h)
+    fd_k = (loss(kappa=kp) - loss(kappa=km)) / (2 * h * 0.05)
+    fp, fm = cfg["f"].copy(), cfg["f"].copy()
+    fp[30] += 1e-4
+    fm[30] -= 1e-4
+    fd_f = (loss(f=fp) - loss(f=fm)) / 2e-4
+    for got, fd, what in [(dD[1], fd_D1, "D1"), (dT2[0], fd_T0, "T2_0"),
+                          (dk[0, 1] + dk[1, 0], fd_k, "kappa"), (df[30], fd_f, "f30")]:
+        print(f"deferred tape {what}: adjoint {got:.9e} fd {fd:.9e}", flush=True)
+        assert abs(got - fd) <= 1e-6 * max(abs(fd), 1e-3), what

@@ -82,8 +82,15 @@ def test_null_handle_calls_are_refused():
                        ("btl_backward", (None,) * 8),
                        ("btl_set_scheme", (None, 0)), ("btl_set_lattice", (None, 0)),
                        ("btl_set_substeps", (None, 1)), ("btl_set_grad_gG0", (None, 0)),
-                       ("btl_autotune", (None, 1, 1, None))]:
+                       ("btl_autotune", (None, 1, 1, None)),
+                       ("btl_set_launch", (None, 0, 0, 0)),
+                       ("btl_set_adjoint_launch", (None, 0, 0)),
+                       ("btl_set_memory_budget", (None, 0)), ("btl_set_graphs", (None, 1)),
+                       ("btl_synchronize", (None, None))]:
         assert getattr(lib, name)(*args) == btl.BTL_E_INVAL, name
     v = ctypes.c_int32()
     assert lib.btl_get_launch(None, ctypes.byref(v), ctypes.byref(v), ctypes.byref(v)) == btl.BTL_E_INVAL
+    v64 = ctypes.c_int64()
+    assert lib.btl_get_backward_stats(None, ctypes.byref(v64), ctypes.byref(v),
+                                      ctypes.byref(v)) == btl.BTL_E_INVAL
     lib.btl_destroy(None)                                  # a no-op
