@@ -417,10 +417,14 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
             cz_g = src[(z0 == 0 ? o5f : o5i) + sp];
             cz_o = src[pop + (pz + 1) * ps + sp];
         }
-        if constexpr (GM) {
+        if constexpr (GM || std::is_same<V, double2>::value) {
             // one site at a time: the general condition's stencil loads and
             // coefficient arithmetic leave no registers for a second site in
-            // flight, and the occupancy this keeps pays more than the overlap
+            // flight, and the occupancy this keeps pays more than the overlap.
+            // FP64 storage too: a site's loads are twice the bytes of an FP32
+            // site, and one site in flight (92 VGPRs, five waves per SIMD)
+            // ran at 0.769 of peak on the 256^3 batch against 0.744 with two
+            // (168 VGPRs, three waves)
             SiteLoads A;
             GmPre G;
             for (int32_t j2 = z0; j2 < z1; ++j2) {
@@ -494,8 +498,8 @@ __global__ void __launch_bounds__(kBlock) k_esum(const double2* __restrict__ par
 
 // Two entry points around the same body: FP32 storage without membrane
 // positions fits in 128 VGPRs when asked to, which raises the occupancy
-// from three to four waves per SIMD; the other variants need more registers
-// and keep the compiler's choice.
+// from three to four waves per SIMD; the other variants keep the compiler's
+// choice (FP64 storage, one site in flight: 92 VGPRs, five waves).
 template <typename V, int TX, bool CL, bool GM, int NQ>
 __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     step_body<V, TX, CL, GM, NQ>(a);
