@@ -44,8 +44,8 @@
  * gradients set a flag of the simulator when a value they write is not
  * finite (for instance when gamma G0, f and dt overflow a phase angle).
  * Because calls are asynchronous the flag is reported later: by
- * btl_synchronize, or by the first btl_forward, btl_backward or
- * btl_autotune that finds it set when it starts, which then
+ * btl_synchronize, or by the first btl_forward, btl_forward_noalloc,
+ * btl_backward or btl_autotune that finds it set when it starts, which then
  * returns BTL_E_NONFINITE without enqueuing work.  Reporting clears it.
  */
 #ifndef BTLBM_H
@@ -279,6 +279,26 @@ btl_status btl_set_graphs(btl_sim *s, int32_t on);
  * it).  Errors: BTL_E_HIP, BTL_E_NONFINITE. */
 btl_status btl_synchronize(btl_sim *s, void *stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, serving loops, harnesses that forbid hipMalloc): btl_forward
+ * without tape (ckpt_every = 0), computed by the same kernels, with every
+ * device buffer beyond E and M_final -- the two population copies, the
+ * signal partials, the phase tables and the call's small tables -- in a
+ * fixed device scratch array of 128 MiB that the library holds per device
+ * for the life of the process.  Neither this call nor its kernels allocate
+ * device or pinned memory: the tables travel through the pinned staging
+ * that btl_create set up (1 MiB per slot, or larger after bigger btl_forward
+ * calls); no q-waves and no hipGraph.  The scratch is shared by every call
+ * on one device and keeps the last call's contents: calls that overlap on
+ * one device (several streams or host threads) race and must be ordered by
+ * the caller.  Arguments and results as btl_forward.
+ * Errors: BTL_E_INVAL (also when the call needs more than the scratch --
+ * about 1.1e6 field-site states in FP32 storage -- or than the staging
+ * holds; the message gives the sizes), BTL_E_HIP, BTL_E_NONFINITE. */
+btl_status btl_forward_noalloc(btl_sim *s, double dt, int32_t K, const double *D,
+                               const double *T2, const double *kappa, int32_t Q,
+                               const int32_t *q_geom, const double *gG0, const double *f,
+                               double *E, void *M_final, void *stream);
 
 /* The launch shape the forwards of s use, as set by btl_autotune or
  * btl_set_launch: the tile

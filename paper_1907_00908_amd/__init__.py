@@ -26,7 +26,7 @@ BTL_F64, BTL_F32 = 0, 1
 BTL_HYBRID, BTL_CLASSICAL = 0, 1
 BTL_D3Q7, BTL_D2Q5 = 0, 1
 
-EXPORTED = ("btl_create", "btl_forward", "btl_backward",
+EXPORTED = ("btl_create", "btl_forward", "btl_forward_noalloc", "btl_backward",
             "btl_get_backward_stats", "btl_set_scheme", "btl_set_lattice", "btl_set_substeps",
             "btl_set_grad_gG0", "btl_autotune", "btl_set_launch", "btl_set_adjoint_launch",
             "btl_set_memory_budget", "btl_set_graphs", "btl_get_launch", "btl_synchronize",
@@ -67,6 +67,8 @@ def load_library(path: str = None):
     lib.btl_create.restype = ctypes.c_int
     lib.btl_forward.argtypes = [P, d, i32, P, P, P, i32, P, P, P, P, P, i32, P]
     lib.btl_forward.restype = ctypes.c_int
+    lib.btl_forward_noalloc.argtypes = [P, d, i32, P, P, P, i32, P, P, P, P, P, P]
+    lib.btl_forward_noalloc.restype = ctypes.c_int
     lib.btl_backward.argtypes = [P, P, P, P, P, P, P, P]
     lib.btl_backward.restype = ctypes.c_int
     lib.btl_get_backward_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64),
@@ -172,6 +174,20 @@ def btl_forward(h, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E_ptr, M_ptr,
                          int(Q), _np_ptr(q_geom), _np_ptr(gG0), _np_ptr(f),
                          ctypes.c_void_p(E_ptr), ctypes.c_void_p(M_ptr) if M_ptr else None,
                          int(ckpt_every), ctypes.c_void_p(stream_ptr) if stream_ptr else None)
+    _check(st, h)
+
+
+def btl_forward_noalloc(h, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E_ptr, M_ptr,
+                        stream_ptr, substeps=1):
+    """btl_forward without tape, all internal device buffers in the
+    library's fixed device scratch (no allocation)."""
+    lib = load_library()
+    D, T2, kappa, q_geom, gG0, f = _forward_args(K, D, T2, kappa, Q, q_geom, gG0, f, substeps)
+    st = lib.btl_forward_noalloc(h, float(dt), int(K), _np_ptr(D), _np_ptr(T2),
+                                 _np_ptr(kappa), int(Q), _np_ptr(q_geom), _np_ptr(gG0),
+                                 _np_ptr(f), ctypes.c_void_p(E_ptr),
+                                 ctypes.c_void_p(M_ptr) if M_ptr else None,
+                                 ctypes.c_void_p(stream_ptr) if stream_ptr else None)
     _check(st, h)
 
 
@@ -322,8 +338,10 @@ class Simulator:
             pass
 
     def forward(self, dt, D, T2, kappa, f, gG0, q_geom=None, want_M=False,
-                ckpt_every=0):
-        """Returns E (Q, K+1) complex128 torch tensor on the device (and M)."""
+                ckpt_every=0, noalloc=False):
+        """Returns E (Q, K+1) complex128 torch tensor on the device (and M).
+        noalloc: run through btl_forward_noalloc (no tape, the library's
+        fixed device scratch; E and M still come from torch)."""
         torch = self.torch
         gG0 = np.ascontiguousarray(gG0, np.float64).reshape(-1, 3)
         Q = gG0.shape[0]
@@ -344,14 +362,21 @@ class Simulator:
             dt_ = torch.float32 if self.prec == BTL_F32 else torch.float64
             M = torch.empty((tot, 2), dtype=dt_, device=dev)
         stream = torch.cuda.current_stream().cuda_stream
-        self.tape_id = None
-        self._tape_QK = None
-        btl_forward(self._h, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E.data_ptr(),
-                    M.data_ptr() if M is not None else 0, ckpt_every, stream, self.substeps)
-        self._n_forward += 1
-        if ckpt_every > 0 and K > 0:
-            self.tape_id = self._n_forward
-            self._tape_QK = (Q, K)
+        if noalloc:
+            if ckpt_every:
+                raise ValueError("btl_forward_noalloc keeps no adjoint tape")
+            btl_forward_noalloc(self._h, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E.data_ptr(),
+                                M.data_ptr() if M is not None else 0, stream, self.substeps)
+        else:
+            self.tape_id = None
+            self._tape_QK = None
+            btl_forward(self._h, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E.data_ptr(),
+                        M.data_ptr() if M is not None else 0, ckpt_every, stream,
+                        self.substeps)
+            self._n_forward += 1
+            if ckpt_every > 0 and K > 0:
+                self.tape_id = self._n_forward
+                self._tape_QK = (Q, K)
         Ec = torch.view_as_complex(E)
         if not want_M:
             return Ec

@@ -7,8 +7,10 @@
 // launch per time step on the caller's stream.
 //
 // A call is first planned on the host (CallPlan: field and workgroup tables,
-// per-step waveform sums, constants), then given device buffers (CallBufs),
-// then its tables are uploaded and its launches enqueued.  Reverse sweeps that do not fit a uniform checkpoint tape replay
+// per-step waveform sums, constants), then given device buffers (CallBufs:
+// the simulator's own allocations, or the fixed device scratch of
+// btl_forward_noalloc), then its tables are uploaded and its launches
+// enqueued.  Reverse sweeps that do not fit a uniform checkpoint tape replay
 // the forward from t = 0 per group of q-samples with a binomial
 // checkpointing schedule (plan_reversal).
 #include <math.h>
@@ -26,7 +28,33 @@
 
 using namespace btl;
 
+// Device scratch of btl_forward_noalloc, for callers that cannot allocate:
+// populations, signal partials, phase tables and the call's small tables all
+// live here.  Each device holds its own copy for the life of the process;
+// host code reaches it only through the address hipGetSymbolAddress returns
+// for that device (scratch_address), never through the array's name.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on the current device (looked up once per device).
+hipError_t scratch_address(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 struct GeomHost {
     int32_t n[3];
@@ -166,6 +194,7 @@ struct btl_sim {
     // non-finite report: host-visible flag the signal and gradient kernels set
     int32_t* nf_host = nullptr;
     int32_t* nf_dev = nullptr;
+    char* scratch = nullptr;     // this device's copy of `scratch`
     // cached forward graphs
     GraphSlot graphs[kGraphSlots];
     uint64_t graph_clock = 0;
@@ -417,8 +446,9 @@ extern "C" btl_status btl_create(const btl_geom* geoms, int32_t n_geom, int32_t 
         if (e == hipSuccess)
             e = hipMemcpy(s->gm.p, gm_all.data(), gm_all.size() * sizeof(float), hipMemcpyHostToDevice);
     }
-    // the non-finite flag (pinned, mapped into the device's address space),
-    // the pinned staging slots and their events
+    // set-up that later calls rely on without allocating: the non-finite
+    // flag (pinned, mapped into the device's address space), the pinned
+    // staging slots and their events, and this device's scratch address
     if (e == hipSuccess) {
         what = "allocating the non-finite flag";
         e = hipHostMalloc((void**)&s->nf_host, sizeof(int32_t),
@@ -435,6 +465,12 @@ extern "C" btl_status btl_create(const btl_geom* geoms, int32_t n_geom, int32_t 
             s->stage_cap[i] = kStageInit;
             e = hipEventCreateWithFlags(&s->stage_ev[i], hipEventDisableTiming);
         }
+    }
+    if (e == hipSuccess) {
+        what = "looking up the device scratch";
+        void* p = nullptr;
+        e = scratch_address(s->device, &p);
+        s->scratch = static_cast<char*>(p);
     }
     if (e != hipSuccess) {
         btl_status st = hip_fail(nullptr, e, what);
@@ -943,6 +979,47 @@ static btl_status alloc_bufs(btl_sim* s, const CallPlan& p, CallBufs& b) {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Bytes of device scratch a call without tape takes (populations first).
+static size_t scratch_need(const btl_sim* s, const CallPlan& p) {
+    const size_t esz = state_elem_bytes(s);
+    return 2 * align256((size_t)p.pop_elems * esz) + align256(p.n_fields * sizeof(FieldDesc)) +
+           align256(p.nblk_total * sizeof(int32_t)) + align256(p.steps.size() * sizeof(double)) +
+           align256(p.consts.size() * sizeof(double)) +
+           align256((size_t)kTabSteps * p.nblk_total * (kBlock / 64) * sizeof(double2)) +
+           align256((size_t)kTabSteps * p.T * sizeof(double2)) + align256(p.T * sizeof(int32_t));
+}
+
+// Buffers of a call carved out of this device's scratch (no allocation).
+static btl_status scratch_bufs(btl_sim* s, const CallPlan& p, CallBufs& b) {
+    const size_t need = scratch_need(s, p);
+    if (p.taping) return fail(s, BTL_E_INVAL, "btl_forward_noalloc keeps no adjoint tape");
+    if (!s->scratch) return fail(s, BTL_E_HIP, "device scratch unavailable");
+    if (need > kScratchBytes) {
+        char msg[160];
+        snprintf(msg, sizeof(msg), "btl_forward_noalloc: the call needs %zu bytes of device scratch, "
+                 "the maximum is %zu", need, kScratchBytes);
+        return fail(s, BTL_E_INVAL, msg);
+    }
+    const size_t esz = state_elem_bytes(s);
+    char* c = s->scratch;
+    auto take = [&c](size_t n) {
+        char* r = c;
+        c += align256(n);
+        return r;
+    };
+    b.pop[0] = take((size_t)p.pop_elems * esz);
+    b.pop[1] = take((size_t)p.pop_elems * esz);
+    b.fields = reinterpret_cast<FieldDesc*>(take(p.n_fields * sizeof(FieldDesc)));
+    b.blk = reinterpret_cast<int32_t*>(take(p.nblk_total * sizeof(int32_t)));
+    b.steps = reinterpret_cast<double*>(take(p.steps.size() * sizeof(double)));
+    b.consts = reinterpret_cast<double*>(take(p.consts.size() * sizeof(double)));
+    b.partial = reinterpret_cast<double2*>(
+        take((size_t)kTabSteps * p.nblk_total * (kBlock / 64) * sizeof(double2)));
+    b.tab = reinterpret_cast<double2*>(take((size_t)kTabSteps * p.T * sizeof(double2)));
+    b.tabf = reinterpret_cast<int32_t*>(take(p.T * sizeof(int32_t)));
+    return BTL_OK;
+}
+
 // Pinned staging: wait until the slot's previous uploads have been read,
 // grow it when allowed (grow = false: fail instead of allocating).
 static btl_status stage_acquire(btl_sim* s, size_t total, bool grow, char** out) {
@@ -954,8 +1031,8 @@ static btl_status stage_acquire(btl_sim* s, size_t total, bool grow, char** out)
     if (s->stage_cap[slot] < total) {
         if (!grow) {
             char msg[160];
-            snprintf(msg, sizeof(msg), "the call's tables need %zu bytes of staging, the "
-                     "simulator has %zu", total, s->stage_cap[slot]);
+            snprintf(msg, sizeof(msg), "btl_forward_noalloc: the call's tables need %zu bytes of "
+                     "staging, the simulator has %zu", total, s->stage_cap[slot]);
             return fail(s, BTL_E_INVAL, msg);
         }
         if (s->stage[slot]) (void)hipHostFree(s->stage[slot]);
@@ -1342,6 +1419,28 @@ extern "C" btl_status btl_forward(btl_sim* s, double dt, int32_t K, const double
     if (rc != BTL_OK) return rc;
     return forward_entry(s, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E, M_final, ckpt_every,
                          stream);
+}
+
+extern "C" btl_status btl_forward_noalloc(btl_sim* s, double dt, int32_t K, const double* D,
+                                          const double* T2, const double* kappa, int32_t Q,
+                                          const int32_t* q_geom, const double* gG0,
+                                          const double* f, double* E, void* M_final,
+                                          void* stream) {
+    if (!s) return BTL_E_INVAL;
+    btl_status rc = take_nonfinite(s);
+    if (rc != BTL_OK) return rc;
+    const Settings cs = s->set;
+    if ((rc = validate_inputs(s, cs, dt, K, D, T2, kappa, Q, q_geom, gG0, f, E)) != BTL_OK)
+        return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    CallPlan p;
+    if ((rc = make_plan(s, cs, dt, K, D, T2, kappa, Q, q_geom, gG0, f, false, p)) != BTL_OK)
+        return rc;
+    CallBufs b;
+    if ((rc = scratch_bufs(s, p, b)) != BTL_OK) return rc;
+    if ((rc = upload_plan(s, p, b, false, st)) != BTL_OK) return rc;
+    if ((rc = enqueue_forward(s, p, b, st, E, nullptr, 0)) != BTL_OK) return rc;
+    return final_magnetization(s, p, b, M_final, st);
 }
 
 extern "C" btl_status btl_synchronize(btl_sim* s, void* stream) {

@@ -83,6 +83,8 @@ def test_null_handle_calls_are_refused():
                        ("btl_set_scheme", (None, 0)), ("btl_set_lattice", (None, 0)),
                        ("btl_set_substeps", (None, 1)), ("btl_set_grad_gG0", (None, 0)),
                        ("btl_autotune", (None, 1, 1, None)),
+                       ("btl_forward_noalloc", (None, 0.01, 1, None, None, None, 1, None, None,
+                                                None, None, None, None)),
                        ("btl_set_launch", (None, 0, 0, 0)),
                        ("btl_set_adjoint_launch", (None, 0, 0)),
                        ("btl_set_memory_budget", (None, 0)), ("btl_set_graphs", (None, 1)),
