@@ -231,6 +231,8 @@ def bench_adjoint(btl, torch, args):
     name = args.adj_workload
     Kb, C = args.adj_steps, args.adj_ckpt
     cfg = workload(name, Kb)
+    if args.adj_q:
+        cfg["gG0"], cfg["q_geom"] = cfg["gG0"][:args.adj_q], cfg["q_geom"][:args.adj_q]
     Q = len(cfg["gG0"])
     qs = q_sites(cfg)
     fs = field_sites(cfg)
@@ -240,25 +242,32 @@ def bench_adjoint(btl, torch, args):
         sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:2], cfg["gG0"])
         probe = max(2, min(40, int(1.5e9 / fs)))
         btl.btl_autotune(sim._h, Q, probe, stream)
-        fwd = forward_fn(sim, cfg, Kb)
+        # forward step time on the same workload (for the adjoint kernel's
+        # share of the sweep); at most 200 steps
+        Kf = min(Kb, 200)
+        fwd = forward_fn(sim, cfg, Kf)
         fwd()
         fwd_ms, _, _ = timed(torch, fwd, 3)
         gen = torch.Generator(device="cpu").manual_seed(0)
         g = torch.randn((Q, Kb + 1, 2), generator=gen, dtype=torch.float64).to("cuda")
         tape = forward_fn(sim, cfg, Kb, ckpt_every=C)
+        log(f"adjoint: taped forward of {Kb} steps")
         tape()
-        sim.backward(g)                                   # warm
+        if not args.adj_cold:
+            sim.backward(g)                               # warm
         times = []
         grads = None
-        for _ in range(args.reps):
-            tape()
+        for r in range(1 if args.adj_cold else args.reps):
+            if r > 0 or not args.adj_cold:
+                tape()
+            log(f"adjoint: timed reverse sweep {r + 1}")
             ms, _, grads = timed(torch, lambda: sim.backward(g), 1)
             times.append(ms)
         ms = float(np.median(times))
         stats = btl.btl_get_backward_stats(sim._h)
     finally:
         sim.close()
-    fwd_step = fwd_ms / Kb
+    fwd_step = fwd_ms / Kf
     recompute_ms = stats[0] * fwd_step
     adj_ms = max(ms - recompute_ms, 1e-9) / Kb
     nq = 5 if cfg.get("lattice", 0) == 1 else 7
@@ -268,9 +277,12 @@ def bench_adjoint(btl, torch, args):
     finite = bool(torch.isfinite(dD).all() and torch.isfinite(df).all())
     return {"value": qs * Kb / (ms * 1e-3), "unit": "site-updates/s",
             "workload": f"{WORKLOAD_NAMES[name]} ({name})",
-            "what": "end-to-end reverse sweep (segment recompute + adjoint step), median of "
-                    f"{args.reps}", "steps": Kb, "ckpt_every": C, "ms_total": ms,
-            "ms_all": times, "forward_steps_recomputed": stats[0],
+            "what": "end-to-end reverse sweep (forward recompute + adjoint steps), "
+                    + ("one cold sweep" if args.adj_cold else f"median of {args.reps}"),
+            "steps": Kb, "ckpt_every": C, "ms_total": ms,
+            "ms_all": times, "q_samples": Q, "forward_steps_recomputed": stats[0],
+            "groups": stats[1], "kept_states_per_group": stats[2],
+            "tape": "deferred (binomial checkpointing)" if stats[2] > 0 else "uniform",
             "forward_ms_per_step": fwd_step,
             "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": ach / HBM_PEAK_GBS,
@@ -312,6 +324,10 @@ def main():
     ap.add_argument("--adj-ckpt", type=int, default=20)
     ap.add_argument("--adj-only", action="store_true",
                     help="only the adjoint leg (profiling)")
+    ap.add_argument("--adj-q", type=int, default=0,
+                    help="the adjoint leg on the first N q-samples only (0: all)")
+    ap.add_argument("--adj-cold", action="store_true",
+                    help="one timed reverse sweep without a warm one (long sweeps)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP64 comparison runs (profiling)")
     ap.add_argument("--calib-copy", action="store_true",

@@ -66,7 +66,10 @@ __device__ __forceinline__ void store_stream(double2* p, double2 v) {
     __builtin_nontemporal_store(v.y, &p->y);
 }
 
-template <typename V, int TX, bool GG, int NQ>
+// NP: phases the per-thread sums are sized for (2 or kAdjMaxPhase); a
+// smaller NP shrinks the per-thread LDS row of membrane-pair sums from
+// 17 to 5 doubles and the per-phase register sums.
+template <typename V, int TX, bool GG, int NQ, int NP>
 __device__ __forceinline__ void adj_body(const AdjArgs& a) {
     using R = typename AdjReal<V>::R;
     // planes pz (+z pull) and pz + 1 (-z pull); on the single-layer D2Q5
@@ -75,7 +78,7 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
     constexpr int pz = NQ == 7 ? 5 : 3;
     auto axis_of = [](int d) { return NQ == 7 ? (d - 1) >> 1 : (d <= 2 ? 0 : 2); };
     constexpr int TY = TX > 0 ? kBlock / TX : 1;
-    constexpr int NT = kAdjMaxPhase * kAdjMaxPhase;   // membrane pair sums per thread (LDS row)
+    constexpr int NT = NP * NP;                        // membrane pair sums per thread (LDS row)
     constexpr int RS = NT + 1;                         // odd row stride
     __shared__ double c_tr[kAdjMaxPhase * kAdjMaxPhase];
     __shared__ R c_w[kAdjMaxPhase], c_dec[kAdjMaxPhase], c_rdec[kAdjMaxPhase];
@@ -160,8 +163,9 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
         mu = mk2<V>(m.x / ns, m.y / ns);
     }
     // register sums of the per-phase sensitivities (selected by phase)
-    double sw[kAdjMaxPhase] = {0.0, 0.0, 0.0, 0.0};
-    double sdec[kAdjMaxPhase] = {0.0, 0.0, 0.0, 0.0};
+    double sw[NP], sdec[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) sw[i] = sdec[i] = 0.0;
     double sf = 0.0, sF = 0.0;
     double sR[GG ? 4 : 1] = {0.0}, sX[GG ? 6 : 1] = {0.0};
 
@@ -366,7 +370,7 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
             const double gw = (double)(sl.x * M.x + sl.y * M.y - glg);
             const double gd = (double)(gdec * c_rdec[p]);
 #pragma unroll
-            for (int i = 0; i < kAdjMaxPhase; ++i) {
+            for (int i = 0; i < NP; ++i) {
                 sw[i] += (p == i) ? gw : 0.0;
                 sdec[i] += (p == i) ? gd : 0.0;
             }
@@ -387,35 +391,35 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
     __syncthreads();
     // register sums: wave reduction, then the four waves in order
     {
-        double v[2 * kAdjMaxPhase + 2 + (GG ? kNGGrad : 0)];
+        double v[2 * NP + 2 + (GG ? kNGGrad : 0)];
 #pragma unroll
-        for (int i = 0; i < kAdjMaxPhase; ++i) {
+        for (int i = 0; i < NP; ++i) {
             v[i] = wave_sum(sw[i]);
-            v[kAdjMaxPhase + i] = wave_sum(sdec[i]);
+            v[NP + i] = wave_sum(sdec[i]);
         }
-        v[2 * kAdjMaxPhase] = wave_sum(sf);
-        v[2 * kAdjMaxPhase + 1] = wave_sum(sF);
+        v[2 * NP] = wave_sum(sf);
+        v[2 * NP + 1] = wave_sum(sF);
         if constexpr (GG) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) v[2 * kAdjMaxPhase + 2 + i] = wave_sum(sR[i]);
+            for (int i = 0; i < 4; ++i) v[2 * NP + 2 + i] = wave_sum(sR[i]);
 #pragma unroll
-            for (int i = 0; i < 6; ++i) v[2 * kAdjMaxPhase + 6 + i] = wave_sum(sX[i]);
+            for (int i = 0; i < 6; ++i) v[2 * NP + 6 + i] = wave_sum(sX[i]);
         }
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         for (int wave = 0; wave < kBlock / 64; ++wave) {
             if (wv == wave && lane == 0) {
 #pragma unroll
-                for (int i = 0; i < kAdjMaxPhase; ++i) {
+                for (int i = 0; i < NP; ++i) {
                     if (i < P) {
                         red[IW + i] += v[i];
-                        red[IDEC + i] += v[kAdjMaxPhase + i];
+                        red[IDEC + i] += v[NP + i];
                     }
                 }
-                red[IF] += v[2 * kAdjMaxPhase];
-                red[IFF] += v[2 * kAdjMaxPhase + 1];
+                red[IF] += v[2 * NP];
+                red[IFF] += v[2 * NP + 1];
                 if constexpr (GG) {
 #pragma unroll
-                    for (int i = 0; i < kNGGrad; ++i) red[IR + i] += v[2 * kAdjMaxPhase + 2 + i];
+                    for (int i = 0; i < kNGGrad; ++i) red[IR + i] += v[2 * NP + 2 + i];
                 }
             }
             __syncthreads();
@@ -431,16 +435,16 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
         a.gpart[((int64_t)a.slot * gridDim.x + lb) * NG + threadIdx.x] = red[threadIdx.x];
 }
 
-template <typename V, int TX, bool GG, int NQ>
+template <typename V, int TX, bool GG, int NQ, int NP>
 __global__ void __launch_bounds__(kBlock) k_adj(AdjArgs a) {
-    adj_body<V, TX, GG, NQ>(a);
+    adj_body<V, TX, GG, NQ, NP>(a);
 }
 // FP32 storage: held to 128 VGPRs (four waves per SIMD), which it fits
 // without spilling
-template <typename V, int TX, bool GG, int NQ>
+template <typename V, int TX, bool GG, int NQ, int NP>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_adj_w4(AdjArgs a) {
-    adj_body<V, TX, GG, NQ>(a);
+    adj_body<V, TX, GG, NQ, NP>(a);
 }
 
 // One thread per (step slot, field, accumulator): the field's workgroup sums
@@ -593,16 +597,25 @@ k_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P, double
     }
 }
 
-template <typename V, int TX, int NQ>
-static void launch_adj_tx(const AdjArgs& a, int32_t n_blocks, hipStream_t st) {
+template <typename V, int TX, int NQ, int NP>
+static void launch_adj_np(const AdjArgs& a, int32_t n_blocks, hipStream_t st) {
     // the gamma G0 sensitivities take their own instantiation (more
     // accumulators); FP32 without them is held to four waves per SIMD
     if (a.gradg)
-        hipLaunchKernelGGL((k_adj<V, TX, true, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((k_adj<V, TX, true, NQ, NP>), dim3(n_blocks), dim3(kBlock), 0, st, a);
     else if constexpr (std::is_same<V, float2>::value)
-        hipLaunchKernelGGL((k_adj_w4<V, TX, false, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((k_adj_w4<V, TX, false, NQ, NP>), dim3(n_blocks), dim3(kBlock), 0, st,
+                           a);
     else
-        hipLaunchKernelGGL((k_adj<V, TX, false, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((k_adj<V, TX, false, NQ, NP>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+}
+
+template <typename V, int TX, int NQ>
+static void launch_adj_tx(const AdjArgs& a, int32_t n_blocks, hipStream_t st) {
+    if (a.n_phase <= 2)
+        launch_adj_np<V, TX, NQ, 2>(a, n_blocks, st);
+    else
+        launch_adj_np<V, TX, NQ, kAdjMaxPhase>(a, n_blocks, st);
 }
 
 template <typename V>

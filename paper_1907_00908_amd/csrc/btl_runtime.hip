@@ -1728,6 +1728,13 @@ static btl_status backward_deferred(btl_sim* s, const double* dL_dE, double* dD,
                               W.nq);
         const char* last_work = nullptr;
         int lam_cur = 0;
+        // BTLBM_VERBOSE: a line per group and every 2000 adjoint steps as
+        // they are enqueued (launches block once the queue is full, so this
+        // follows the device within the queue's depth)
+        const bool verbose = getenv("BTLBM_VERBOSE") != nullptr;
+        if (verbose)
+            fprintf(stderr, "btlbm reverse sweep: group %zu of %zu, %d q-samples, %lld kept states, "
+                    "%zu actions\n", w + 1, cut.size() - 1, Qw, (long long)slots, acts.size());
         for (const RevAction& act : acts) {
             if (act.kind == 0) {
                 const char* cur = slot_ptr(act.src);
@@ -1770,6 +1777,9 @@ static btl_status backward_deferred(btl_sim* s, const double* dL_dE, double* dD,
                 if ((e = launch_adj_gsum(s->gpart.p, b.afields, W.n_fields, nblk_adj, NG, k - 1, 1,
                                          s->gfield.p, f0, nfT, st)) != hipSuccess)
                     return hip_fail(s, e, "adjoint sum launch");
+                if (verbose && (K - k + 1) % 2000 == 0)
+                    fprintf(stderr, "btlbm reverse sweep: %d of %d adjoint steps enqueued, %lld forward "
+                            "steps\n", K - k + 1, K, (long long)nfwd);
             }
         }
         f0 += W.n_fields;
