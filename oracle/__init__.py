@@ -51,7 +51,7 @@ def _load():
         lib.oracle_run.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_int32, P, P,
                                    ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                    P, P, P, P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32,
-                                   P, P, ctypes.c_int32, ctypes.c_int32]
+                                   P, P, ctypes.c_int32, ctypes.c_int32, P]
         lib.oracle_run.restype = ctypes.c_int
         lib.oracle_memb_coeffs.argtypes = [ctypes.c_double] * 3 + [P]
         lib.oracle_memb_coeffs.restype = None
@@ -67,7 +67,7 @@ def _ptr(a):
 
 def _run_core(comp, comp_phase, n_phase, bc, off, dx, dt, D, T2, kappa, f, gG0,
               elo, ehi, threads, want_M, scheme=0, link_delta=None, tile=None, substeps=1,
-              lattice=0):
+              lattice=0, link_normal=None):
     lib = _load()
     comp = np.ascontiguousarray(comp, dtype=np.uint32)
     n2, n1, n0 = comp.shape
@@ -91,6 +91,12 @@ def _run_core(comp, comp_phase, n_phase, bc, off, dx, dt, D, T2, kappa, f, gG0,
         link_delta = np.ascontiguousarray(link_delta, dtype=np.float64)
         if link_delta.shape != (3,) + comp.shape:
             raise ValueError("link_delta must have shape (3, n2, n1, n0)")
+    if link_normal is not None:
+        if link_delta is None:
+            raise ValueError("link_normal needs link_delta")
+        link_normal = np.ascontiguousarray(link_normal, dtype=np.float64)
+        if link_normal.shape != (3, 3) + comp.shape:
+            raise ValueError("link_normal must have shape (3, 3, n2, n1, n0)")
     tile = None if tile is None else np.ascontiguousarray(tile, dtype=np.int32)
     rc = lib.oracle_run(_ptr(n), _ptr(comp), _ptr(cp), len(cp), int(n_phase), _ptr(bc),
                         _ptr(off), float(dx), float(dt), K, _ptr(D), _ptr(T2),
@@ -98,7 +104,7 @@ def _run_core(comp, comp_phase, n_phase, bc, off, dx, dt, D, T2, kappa, f, gG0,
                         _ptr(E), _ptr(M) if want_M else None, int(threads), int(scheme),
                         _ptr(link_delta) if link_delta is not None else None,
                         _ptr(tile) if tile is not None else None, int(substeps),
-                        int(lattice))
+                        int(lattice), _ptr(link_normal) if link_normal is not None else None)
     if rc == -2:
         raise NotImplementedError("oblique gradient on a mirrored axis")
     if rc != 0:
@@ -142,7 +148,7 @@ HYBRID, CLASSICAL = 0, 1
 def simulate(comp, comp_phase, n_phase, bc, dx, dt, D, T2, kappa, f, gG0,
              threads: int = 1, mirror: str = "auto", want_M: bool = True,
              scheme: int = HYBRID, link_delta=None, substeps: int = 1,
-             lattice: int = D3Q7):
+             lattice: int = D3Q7, link_normal=None):
     """Run the scheme for one gradient vector.
 
     comp (n2, n1, n0) compartment ids, comp_phase [C], bc[3] (0 periodic,
@@ -157,6 +163,9 @@ def simulate(comp, comp_phase, n_phase, bc, dx, dt, D, T2, kappa, f, gG0,
     link_delta: None (half-link membranes at mid-link) or (3, n2, n1, n0)
     membrane positions along the +x, +y, +z links from each node (units of
     dx) for the general theta = 0 membrane condition (oracle.c).
+    link_normal: None, or (3, 3, n2, n1, n0) unit normals of the membrane on
+    each link (axis, component; either orientation) for the general
+    condition at any angle (oracle.c; needs link_delta).
     substeps: m reaction sub-steps per step; f then holds K*m samples at
     dt/m (hybrid scheme only).
     lattice: D3Q7, or D2Q5 on a single layer (n2 = 1, gG0[2] = 0; the z
@@ -175,9 +184,10 @@ def simulate(comp, comp_phase, n_phase, bc, dx, dt, D, T2, kappa, f, gG0,
     if mirror == "paper" or MIRROR not in bc:
         n2, n1, n0 = comp.shape
         ld = None if link_delta is None else np.asarray(link_delta, np.float32)
+        ln = None if link_normal is None else np.asarray(link_normal, np.float32)
         return _run_core(comp, comp_phase, n_phase, bc, [0.0, 0.0, 0.0], dx, dt,
                          D, T2, kappa, f, gG0, [0, 0, 0], [n0, n1, n2], threads, want_M,
-                         scheme, ld, None, substeps, lattice)
+                         scheme, ld, None, substeps, lattice, ln)
     if mirror != "double":
         raise ValueError("mirror must be 'auto', 'paper' or 'double'")
     # reflect the REV across the lower face of every mirrored axis: the
@@ -187,6 +197,7 @@ def simulate(comp, comp_phase, n_phase, bc, dx, dt, D, T2, kappa, f, gG0,
     # positions are single precision on input (as the HIP library stores
     # them); complements 1 - d of the reflected copies are exact in FP64
     ld = None if link_delta is None else np.asarray(link_delta, np.float32).astype(np.float64)
+    ln = None if link_normal is None else np.asarray(link_normal, np.float32).astype(np.float64)
     off = [0.0, 0.0, 0.0]
     lo = [0, 0, 0]
     hi = list(comp.shape[::-1])
@@ -211,11 +222,28 @@ def simulate(comp, comp_phase, n_phase, bc, dx, dt, D, T2, kappa, f, gG0,
             sl[ax + 1] = slice(na - 1, na)
             img[tuple(sl)] = 0.5     # image of node 0 -> node 0: no membrane
             ld = np.concatenate([img, ld], axis=ax + 1)
+        if ln is not None:
+            # the reflected copy: normals mirrored in axis a (component a
+            # negated), links indexed as for the positions above
+            imn = np.flip(ln, axis=ax + 2).copy()
+            imn[:, a] *= -1.0
+            src = imn.copy()
+            dst = [slice(None)] * 5
+            dst[0] = a
+            dst[ax + 2] = slice(0, na - 1)
+            srs = [slice(None)] * 5
+            srs[0] = a
+            srs[ax + 2] = slice(1, na)
+            imn[tuple(dst)] = src[tuple(srs)]
+            # the image of node 0 -> node 0 joins one compartment: not read
+            dst[ax + 2] = slice(na - 1, na)
+            imn[tuple(dst)] = 0.0
+            ln = np.concatenate([imn, ln], axis=ax + 2)
         off[a] = -float(na)
         lo[a], hi[a] = na, 2 * na
     bce = [PERIODIC] * 3
     E, M = _run_core(ext, comp_phase, n_phase, bce, off, dx, dt, D, T2, kappa, f,
-                     gG0, lo, hi, threads, want_M, scheme, ld, tile, substeps, lattice)
+                     gG0, lo, hi, threads, want_M, scheme, ld, tile, substeps, lattice, ln)
     if want_M:
         M = M[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].copy()
     return E, M
@@ -233,7 +261,8 @@ def simulate_config(cfg: dict, q=None, threads: int = 1, mirror: str = "auto",
                         threads=threads, mirror=mirror, want_M=want_M,
                         scheme=cfg.get("scheme", HYBRID) if scheme is None else scheme,
                         link_delta=getattr(g, "link_delta", None),
-                        substeps=cfg.get("substeps", 1), lattice=cfg.get("lattice", D3Q7))
+                        substeps=cfg.get("substeps", 1), lattice=cfg.get("lattice", D3Q7),
+                        link_normal=getattr(g, "link_normal", None))
         Es.append(E)
         Ms.append(M)
     return np.array(Es), Ms

@@ -41,6 +41,26 @@
  * with x - e_i, lie in the same tile of the lattice as x (no outer face in
  * the stencil); otherwise the link falls back to the half-link rule.
  *
+ * With membrane normals given as well (link_normal != NULL) a membrane link
+ * takes the general condition for a membrane at any angle (Sec. 2.4.2 and
+ * Appendix B, theta != 0): on each side the Dirichlet and Neumann link
+ * relations (Eqs. dirichlet_1/2, neumann_1/2 with the coefficients of Eqs.
+ * c_d, c_n at the side's distance) give the value at the membrane and the
+ * inflow flux along the link; the flux along each lattice direction
+ * orthogonal to the link comes from the same two relations with the
+ * coefficients for Delta_m = 0 on the lattice line through the membrane
+ * point (Eqs. phi_1, phi_2: populations at the membrane point x' and at
+ * x' + e_betabar); the normal inflow is their combination with the
+ * direction cosines of the normal (two terms in 2D as printed, three in 3D),
+ * and the permeability condition with flux continuity (Eqs. B1, B1.5)
+ * closes the two sides' values.  The populations at the off-lattice points
+ * are interpolated (quadratically) along the link direction from the three
+ * nodes of the side's own compartment nearest to each point (a reading: the
+ * paper does not say how they are obtained).
+ * Stencils may reach through periodic faces (with the modified periodic
+ * phase factor), not through mirroring faces or stencil tiles.  Where a
+ * stencil node is missing the link takes the theta = 0 rule.
+ *
  * With substeps = m > 1 the reaction of each step is taken as m sub-steps
  * of length dt' = dt/m (the reaction time step of Sec. 2.3, dt = m dt'),
  * each with its own waveform sample: f holds K*m samples, sub-step j of step
@@ -155,6 +175,153 @@ static cplx pairwise_sum(const cplx *v, long n) {
     return pairwise_sum(v, h) + pairwise_sum(v + h, n - h);
 }
 
+/* Dirichlet and Neumann coefficients c_d1..c_d4, c_n1..c_n4 (Eqs. c_d, c_n)
+   for a node at distance d from the membrane */
+static void cdn(double d, double cd[4], double cn[4]) {
+    const double q = 2.0 * d + 1.0, r = 2.0 * d - 1.0;
+    cd[0] = 2.0 * (d - 1.0);
+    cd[1] = -r * r / q;
+    cd[2] = 2.0 * r / q;
+    cd[3] = (3.0 - 2.0 * d) / q;
+    cn[0] = 1.0;
+    cn[1] = -r / q;
+    cn[2] = r / q;
+    cn[3] = 2.0 / q;
+}
+
+/* Geometry and state one side of a curved membrane link sees.  The side's
+   node xs receives populations along e_s (direction ds) from the membrane
+   at distance dist; ok(j) says whether node j belongs to the side's
+   compartment and lies in its stencil tile. */
+typedef struct {
+    const cplx *gh;
+    long PN, p0, p1;
+    const uint32_t *comp;
+    long n[3], tl[3], t0[3];   /* sizes, tile sizes, the side's tile origin */
+    int wrap[3];               /* axis periodic over its whole length */
+    double phi[3];             /* modified periodic phase L_a (gamma G0)_a F_k */
+    uint32_t c;
+    int lattice;
+} side_ctx;
+
+/* node j of the side (periodic axes wrap, with w the number of wraps) */
+static int side_node(const side_ctx *sc, const long j[3], long jw[3], long w[3]) {
+    for (int a = 0; a < 3; ++a) {
+        jw[a] = j[a];
+        w[a] = 0;
+        if (sc->wrap[a]) {
+            while (jw[a] < 0) { jw[a] += sc->n[a]; --w[a]; }
+            while (jw[a] >= sc->n[a]) { jw[a] -= sc->n[a]; ++w[a]; }
+        } else if (j[a] < sc->t0[a] || j[a] >= sc->t0[a] + sc->tl[a]) {
+            return 0;
+        }
+    }
+    return sc->comp[jw[0] + sc->n[0] * (jw[1] + sc->n[1] * jw[2])] == sc->c;
+}
+
+static int side_node_ok(const side_ctx *sc, const long j[3]) {
+    long jw[3], w[3];
+    return side_node(sc, j, jw, w);
+}
+
+/* post-collision population dir at node j; across a periodic face the
+   modified periodic condition (Eq. collision_BC): the image of node j - N
+   carries the factor exp(+i phi), of j + N exp(-i phi) */
+static cplx side_val(const side_ctx *sc, int dir, const long j[3]) {
+    long jw[3], w[3];
+    side_node(sc, j, jw, w);
+    cplx v = sc->gh[dir * sc->PN + ((jw[0] + 1) + sc->p0 * ((jw[1] + 1) + sc->p1 * (jw[2] + 1)))];
+    for (int a = 0; a < 3; ++a)
+        if (w[a] != 0) v *= cexp(-I * (double)w[a] * sc->phi[a]);
+    return v;
+}
+
+/* population dir at the point base + t e, by quadratic (Lagrange)
+   interpolation through the three nodes base + u e, u = -3 .. 3, of the
+   side that lie nearest to the point (ties: the smaller u) */
+static int side_interp(const side_ctx *sc, int dir, const long base[3], const int e[3],
+                       double t, cplx *out) {
+    int use[3], nu = 0;
+    int taken[7] = {0};
+    while (nu < 3) {
+        int best = -100;
+        for (int u = -3; u <= 3; ++u) {
+            if (taken[u + 3]) continue;
+            if (best == -100 || fabs(u - t) < fabs(best - t)) best = u;
+        }
+        if (best == -100) return 0;
+        taken[best + 3] = 1;
+        long j[3];
+        for (int a = 0; a < 3; ++a) j[a] = base[a] + best * e[a];
+        if (side_node_ok(sc, j)) use[nu++] = best;
+    }
+    cplx v = 0;
+    for (int m = 0; m < 3; ++m) {
+        double lw = 1.0;
+        for (int l = 0; l < 3; ++l)
+            if (l != m) lw *= (t - use[l]) / (double)(use[m] - use[l]);
+        long j[3];
+        for (int a = 0; a < 3; ++a) j[a] = base[a] + use[m] * e[a];
+        v += lw * side_val(sc, dir, j);
+    }
+    *out = v;
+    return 1;
+}
+
+/* One side: the inflow flux normal to the membrane as L + A m (m the side's
+   value at the membrane), and D, the Dirichlet part of the arriving
+   population (g' = D + c_d4 eps m).  nrm is the unit normal into the side.
+   Returns 0 when a stencil node is missing. */
+static int curved_side(const side_ctx *sc, const long xs[3], int ds, double dist,
+                       const double nrm[3], double eps, double h, cplx *L, double *A,
+                       cplx *Dp, double *cd4) {
+    const int es[3] = {EX[ds][0], EX[ds][1], EX[ds][2]};
+    const int dout = OPP[ds];
+    long x2[3];
+    for (int a = 0; a < 3; ++a) x2[a] = xs[a] + es[a];
+    if (!side_node_ok(sc, xs) || !side_node_ok(sc, x2)) return 0;
+    double cd[4], cn[4];
+    cdn(dist, cd, cn);
+    /* link relations (Eqs. dirichlet_1, neumann_1 of this side) */
+    const cplx st[3] = {side_val(sc, dout, xs), side_val(sc, dout, x2), side_val(sc, ds, xs)};
+    cplx Dl = 0, Nl = 0;
+    for (int j = 0; j < 3; ++j) {
+        Dl += cd[j] * st[j];
+        Nl += cn[j] * st[j];
+    }
+    /* inflow flux along e_s: (D - N + c_d4 eps m) / (c_n4 h) */
+    const int ax = (ds - 1) / 2;
+    const double cth = fabs(nrm[ax]);
+    *L = cth * (Dl - Nl) / (cn[3] * h);
+    *A = cth * cd[3] * eps / (cn[3] * h);
+    /* each orthogonal lattice direction with a normal component: the same
+       relations at Delta_m = 0 on the line through the membrane point */
+    double c0d[4], c0n[4];
+    cdn(0.0, c0d, c0n);
+    for (int b = 0; b < 3; ++b) {
+        if (b == ax || (sc->lattice == 1 && b == 2)) continue;
+        const double sb = fabs(nrm[b]);
+        if (sb == 0.0) continue;
+        const int sgn = nrm[b] > 0 ? 1 : -1;
+        const int dbb = 1 + 2 * b + (sgn > 0 ? 0 : 1);   /* e_betabar: into the side */
+        const int db = OPP[dbb];
+        long base2[3];
+        for (int a = 0; a < 3; ++a) base2[a] = xs[a] + (a == b ? sgn : 0);
+        cplx b_p1, b_p2, bb_p1;
+        if (!side_interp(sc, db, xs, es, -dist, &b_p1) ||
+            !side_interp(sc, db, base2, es, -dist, &b_p2) ||
+            !side_interp(sc, dbb, xs, es, -dist, &bb_p1))
+            return 0;
+        const cplx DN = (c0d[0] - c0n[0]) * b_p1 + (c0d[1] - c0n[1]) * b_p2 +
+                        (c0d[2] - c0n[2]) * bb_p1;
+        *L += sb * DN / (c0n[3] * h);
+        *A += sb * c0d[3] * eps / (c0n[3] * h);
+    }
+    *Dp = Dl;
+    *cd4 = cd[3];
+    return 1;
+}
+
 /*
  * Run K steps of the scheme for one gradient direction.
  *
@@ -171,6 +338,9 @@ static cplx pairwise_sum(const cplx *v, long n) {
  *             dx) from node j to the membrane on the link j -> j + e_a,
  *             0 < value < 1; read only on links joining two compartments
  * tile[3]     stencil tiles of the general membrane rule (NULL: whole axes)
+ * link_normal [3][3][n2][n1][n0] or NULL (needs link_delta): for axis a,
+ *             components c = 0..2 of a unit normal of the membrane on the
+ *             link j -> j + e_a (either orientation)
  * E           out [K+1] complex (interleaved re, im)
  * M_out       out [n2][n1][n0] complex or NULL
  * returns 0, or -1 for invalid input, -2 for an unsupported case, -3 OOM
@@ -182,12 +352,13 @@ int oracle_run(const int32_t n[3], const uint32_t *comp, const uint8_t *comp_pha
                const double *f, const double gG0[3], const int32_t elo[3],
                const int32_t ehi[3], double *E, double *M_out, int32_t nthreads,
                int32_t scheme, const double *link_delta, const int32_t *tile,
-               int32_t substeps, int32_t lattice) {
+               int32_t substeps, int32_t lattice, const double *link_normal) {
     const long n0 = n[0], n1 = n[1], n2 = n[2];
     if (n0 < 1 || n1 < 1 || n2 < 1 || dx <= 0 || dt <= 0 || K < 0) return -1;
     if (scheme != 0 && scheme != 1) return -1;
     if (substeps < 1 || (scheme == 1 && substeps != 1)) return -1;
     if (lattice != 0 && lattice != 1) return -1;
+    if (link_normal && !link_delta) return -1;
     /* D2Q5 runs a single layer: n2 = 1, no gradient along z */
     if (lattice == 1 && (n[2] != 1 || gG0[2] != 0.0)) return -1;
     const int Q = lattice == 1 ? 5 : 7;
@@ -411,7 +582,57 @@ int oracle_run(const int32_t n[3], const uint32_t *comp, const uint8_t *comp_pha
                         cplx gp;
                         const int pair = px * n_phase + comp_phase[cs];
                         int general = 0;
-                        if (link_delta && cs != cx && has_mem[pair] && crossed < 0) {
+                        if (link_normal && cs != cx && has_mem[pair] &&
+                            (crossed < 0 || (bc[crossed] == BC_PERIODIC && tl[crossed] == n[crossed]))) {
+                            const int ax = (i - 1) / 2, sg = EX[i][ax];
+                            long sw[3] = {src[0], src[1], src[2]};   /* src, wrapped */
+                            if (crossed >= 0) sw[crossed] = (sw[crossed] + n[crossed]) % n[crossed];
+                            const long lower = sg > 0 ? IDX(sw[0], sw[1], sw[2]) : s;
+                            const double dl = link_delta[ax * N + lower];
+                            const double d = sg > 0 ? 1.0 - dl : dl;
+                            double nv[3];
+                            for (int c = 0; c < 3; ++c) nv[c] = link_normal[(ax * 3 + c) * N + lower];
+                            /* the normal into x's side has a positive component along e_i */
+                            const double o = nv[ax] * sg > 0 ? 1.0 : -1.0;
+                            double nown[3], nfar[3];
+                            for (int c = 0; c < 3; ++c) {
+                                nown[c] = o * nv[c];
+                                nfar[c] = -nown[c];
+                            }
+                            side_ctx own = {gh, PN, p0, p1, comp, {n0, n1, n2},
+                                            {tl[0], tl[1], tl[2]},
+                                            {j0 / tl[0] * tl[0], j1 / tl[1] * tl[1], j2 / tl[2] * tl[2]},
+                                            {bc[0] == BC_PERIODIC && tl[0] == n0,
+                                             bc[1] == BC_PERIODIC && tl[1] == n1,
+                                             bc[2] == BC_PERIODIC && tl[2] == n2},
+                                            {n0 * dx * gG0[0] * F, n1 * dx * gG0[1] * F,
+                                             n2 * dx * gG0[2] * F},
+                                            cx, lattice};
+                            side_ctx far = own;
+                            far.c = cs;
+                            const double h = dt / dx;
+                            cplx Lo, Lf, Do, Df;
+                            double Ao, Af, cdo, cdf;
+                            if (nv[ax] != 0.0 &&
+                                curved_side(&own, jj, i, d, nown, EPS_D, h, &Lo, &Ao, &Do, &cdo) &&
+                                curved_side(&far, src, OPP[i], 1.0 - d, nfar, EPS_D, h, &Lf, &Af,
+                                            &Df, &cdf)) {
+                                /* inflow into each side kappa (m_other - m_side) (Eqs. B1,
+                                   B1.5): L_o + A_o m_o = kappa (m_f - m_o),
+                                   L_f + A_f m_f = kappa (m_o - m_f) */
+                                const double kap = kappa[pair];
+                                cplx mo;
+                                if (kap == 0.0) {
+                                    mo = -Lo / Ao;
+                                } else {
+                                    const double det = Ao * Af + kap * (Ao + Af);
+                                    mo = (-(Af + kap) * Lo - kap * Lf) / det;
+                                }
+                                gp = Do + cdo * EPS_D * mo;
+                                general = 1;
+                            }
+                        }
+                        if (!general && link_delta && cs != cx && has_mem[pair] && crossed < 0) {
                             /* stencil x - 2e_i .. x + e_i along axis ax, in x's tile */
                             const int ax = (i - 1) / 2, sg = EX[i][ax];
                             const long j = jj[ax], t0 = j / tl[ax] * tl[ax];

@@ -11,13 +11,13 @@ permeability kappa in um/ms, b in ms/um^2 (1000 s/mm^2 = 1 ms/um^2), and the
 gradient is carried as gamma*G0 in rad/(um*ms).
 """
 from .geometry import (Geometry, uniform, slabs, cylinders_z, cylinders_spheres,
-                       ellipsoid_cells, link_delta, tile_xy, angled_slabs_2d)
+                       ellipsoid_cells, link_delta, link_normal, tile_xy, angled_slabs_2d)
 from .sequences import (pgse_waveform, ogse_cosine_waveform, gamma_g_for_b_pgse,
                         b_of_waveform, golden_spiral, axon_directions, GAMMA_H1)
 from .configs import CONFIGS, make_config
 
 __all__ = ["Geometry", "uniform", "slabs", "cylinders_z", "cylinders_spheres",
-           "ellipsoid_cells", "link_delta", "tile_xy", "angled_slabs_2d", "pgse_waveform",
+           "ellipsoid_cells", "link_delta", "link_normal", "tile_xy", "angled_slabs_2d", "pgse_waveform",
            "ogse_cosine_waveform", "gamma_g_for_b_pgse", "b_of_waveform",
            "golden_spiral", "axon_directions", "GAMMA_H1", "CONFIGS",
            "make_config"]

@@ -199,8 +199,10 @@ def make_config(name: str, n=None, K=None, n_q=None, seed=None,
 
     membranes="positions" attaches to every geometry the exact positions
     where its analytic surfaces cut the lattice links (`geometry.link_delta`),
-    for the general membrane condition; the default leaves them out (every
-    membrane at mid-link)."""
+    for the general membrane condition with the membrane taken normal to the
+    link; "curved" also attaches the surface normals at those points
+    (`geometry.link_normal`) for the condition at any angle; the default
+    leaves them out (every membrane at mid-link)."""
     fn = CONFIGS[name]
     kw = {}
     if n is not None:
@@ -208,10 +210,12 @@ def make_config(name: str, n=None, K=None, n_q=None, seed=None,
     if seed is not None:
         kw["seed"] = seed
     cfg = fn(K=K, n_q=n_q, **kw)
-    if membranes == "positions":
+    if membranes in ("positions", "curved"):
         for g in cfg["geoms"]:
             g.link_delta = geo.link_delta(g)
-        cfg["name"] += "+positions"
+            if membranes == "curved":
+                g.link_normal = geo.link_normal(g)
+        cfg["name"] += "+" + membranes
     elif membranes != "half-link":
-        raise ValueError("membranes must be 'half-link' or 'positions'")
+        raise ValueError("membranes must be 'half-link', 'positions' or 'curved'")
     return cfg

@@ -350,27 +350,18 @@ def tile_xy(g: Geometry, rx: int, ry: int) -> Geometry:
     return Geometry(comp, g.comp_phase.copy(), g.n_phase, g.dx, info)
 
 
-def link_delta(g: Geometry) -> np.ndarray:
-    """Where each membrane cuts its lattice link, from the analytic surfaces
-    the geometry was rasterised from.
-
-    Returns float32 (3, n2, n1, n0): entry [a, j2, j1, j0] is the distance,
-    in units of dx, from node j to the surface on the link j -> j + e_a (the
-    last node of a periodic axis links to node 0).  Links that join two
-    compartments get the crossing of the surface that has exactly one of the
-    two nodes inside (clamped to [1e-4, 1 - 1e-4]); every other entry, and
-    every entry of a geometry without analytic surfaces, is 0.5 (the
-    mid-link position).
-    """
-    if "tile_of" in g.info:
-        base, rx, ry = g.info["tile_of"]
-        return np.tile(link_delta(base), (1, 1, ry, rx))
+def _link_crossings(g: Geometry):
+    """Crossing positions and unit normals of the analytic surfaces on the
+    lattice links (see link_delta and link_normal)."""
     n2, n1, n0 = g.comp.shape
     dims = (n0, n1, n2)
     out = np.full((3, n2, n1, n0), 0.5, np.float32)
+    nrm = np.zeros((3, 3, n2, n1, n0), np.float32)
+    for a in range(3):
+        nrm[a, a] = 1.0
     shp = g.info.get("shapes")
     if not shp:
-        return out
+        return out, nrm
     dx = g.dx
     L = np.array(dims, np.float64) * dx
     per = np.array(shp["periodic"], bool)
@@ -394,6 +385,8 @@ def link_delta(g: Geometry) -> np.ndarray:
             continue
         p0 = np.stack([x, y, z], axis=1) * dx
         best = np.full(len(x), 0.5)
+        bestn = np.zeros((len(x), 3))
+        bestn[:, a] = 1.0
         found = np.zeros(len(x), bool)
         for side in (g.comp[z, y, x], nb[z, y, x]):
             k = shape_of[side]
@@ -415,12 +408,52 @@ def link_delta(g: Geometry) -> np.ndarray:
             disc = np.sqrt(np.maximum(qb * qb - 4.0 * qa * qc, 0.0))
             with np.errstate(divide="ignore", invalid="ignore"):
                 t = np.where(in0, (-qb + disc) / (2.0 * qa), (-qb - disc) / (2.0 * qa))
-            use = one & ~found[ok]
+            # the surface (p - c).A(p - c) = 1 has the normal A (p - c)
+            pc = d + np.where(np.isfinite(t), t, 0.0)[:, None] * dx * np.eye(3)[a][None, :]
+            gn = np.einsum("nij,nj->ni", Ak, pc)
+            gl = np.linalg.norm(gn, axis=1)
+            use = one & ~found[ok] & (gl > 0.0)
             idx = np.nonzero(ok)[0][use]
             best[idx] = t[use]
+            bestn[idx] = gn[use] / gl[use][:, None]
             found[idx] = True
         out[a, z, y, x] = np.clip(best, 1e-4, 1.0 - 1e-4).astype(np.float32)
-    return out
+        nrm[a, :, z, y, x] = bestn.astype(np.float32)   # advanced index first: (links, 3)
+    return out, nrm
+
+
+def link_delta(g: Geometry) -> np.ndarray:
+    """Where each membrane cuts its lattice link, from the analytic surfaces
+    the geometry was rasterised from.
+
+    Returns float32 (3, n2, n1, n0): entry [a, j2, j1, j0] is the distance,
+    in units of dx, from node j to the surface on the link j -> j + e_a (the
+    last node of a periodic axis links to node 0).  Links that join two
+    compartments get the crossing of the surface that has exactly one of the
+    two nodes inside (clamped to [1e-4, 1 - 1e-4]); every other entry, and
+    every entry of a geometry without analytic surfaces, is 0.5 (the
+    mid-link position).
+    """
+    if "tile_of" in g.info:
+        base, rx, ry = g.info["tile_of"]
+        return np.tile(link_delta(base), (1, 1, ry, rx))
+    return _link_crossings(g)[0]
+
+
+def link_normal(g: Geometry) -> np.ndarray:
+    """Unit normals of the analytic surfaces where they cut the lattice
+    links (the gradient of the quadric at the crossing of link_delta).
+
+    Returns float32 (3, 3, n2, n1, n0): entry [a, c, j2, j1, j0] is
+    component c of the normal on the link j -> j + e_a, pointing out of the
+    shape; links without a crossing (and geometries without analytic
+    surfaces) get e_a, i.e. a membrane normal to the link."""
+    if "tile_of" in g.info:
+        base, rx, ry = g.info["tile_of"]
+        return np.tile(link_normal(base), (1, 1, 1, ry, rx))
+    if "link_normal" in g.info:
+        return g.info["link_normal"]
+    return _link_crossings(g)[1]
 
 
 def angled_slabs_2d(n: int, dx: float, bounds, tan_phi=(1, 2), phases=None) -> Geometry:
@@ -461,6 +494,10 @@ def angled_slabs_2d(n: int, dx: float, bounds, tan_phi=(1, 2), phases=None) -> G
             t = np.mod(b[k] - s_lo, P) / ds
             hit = (t > 0) & (t < 1)
             ld[a, 0][hit] = np.clip(t[hit], 1e-4, 1 - 1e-4)
-    g = Geometry(comp, ph, int(ph.max()) + 1, float(dx), {"kind": "angled_slabs_2d"})
+    nrm3 = np.zeros((3, 3, 1, n, n), np.float32)
+    nrm3[:, 0] = nh[0]
+    nrm3[:, 1] = nh[1]
+    g = Geometry(comp, ph, int(ph.max()) + 1, float(dx),
+                 {"kind": "angled_slabs_2d", "link_normal": nrm3})
     g.link_delta = ld
     return g
