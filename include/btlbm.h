@@ -90,6 +90,9 @@ typedef struct {
     int32_t n_phase;            /* number of material phases P, 1..8 */
     const float *link_delta;    /* host [3][n2][n1][n0] or NULL: where each
                                  * membrane cuts its link (see below) */
+    const float *link_normal;   /* host [3][3][n2][n1][n0] or NULL (needs
+                                 * link_delta): the membrane's unit normal
+                                 * where it cuts each link (see below) */
 } btl_geom;
 
 /* link_delta: entry [a][j] is the distance, in units of dx, from node j to
@@ -106,6 +109,27 @@ typedef struct {
  *           + B_1 ghat_i(x - e_i) + B_2 ghat_i(x - 2e_i) + B_3 ghat_ibar(x - e_i);
  * every other membrane link, and every link when link_delta is NULL, uses
  * the half-link form (Eqs. B5, permeability_BC: the membrane at mid-link).
+ *
+ * link_normal: entry [a][c][j] is component c of a unit normal (either
+ * orientation) of the membrane on the link j -> j + e_a.  With it, a
+ * membrane link takes the general condition for a membrane at any angle to
+ * the link (Sec. 2.4.2, Appendix B): on each side the Dirichlet and Neumann
+ * link relations (Eqs. dirichlet_1/2, neumann_1/2; coefficients Eqs. c_d,
+ * c_n) give the value at the membrane and the inflow flux along the link;
+ * the flux along each orthogonal lattice direction (one in 2D, two in 3D)
+ * comes from the same relations with the coefficients for Delta_m = 0 on the
+ * lattice line through the membrane point (Eqs. phi_1, phi_2), whose
+ * populations at x' (the membrane point and one spacing from it along
+ * e_betabar) are interpolated quadratically along the link direction from
+ * the three nearest nodes of the same compartment; the normal inflow, their
+ * combination with the normal's direction cosines, satisfies the
+ * permeability condition with flux continuity on both sides (Eqs. B1, B1.5).
+ * Stencils may reach through periodic faces (with the modified periodic
+ * phase) but not through mirroring faces; a link without a complete stencil
+ * keeps the rule above.  The weights depend on kappa, dt and the lattice;
+ * they are built on the host (about 45 weights per link) when a forward's
+ * constants differ from the last ones, after the work queued on its stream
+ * has finished.
  * btl_backward does not support simulators whose forward used link_delta. */
 
 /* Create a simulator for n_geom geometries (all with the same dx and
@@ -291,10 +315,15 @@ btl_status btl_synchronize(btl_sim *s, void *stream);
  * calls); no q-waves and no hipGraph.  The scratch is shared by every call
  * on one device and keeps the last call's contents: calls that overlap on
  * one device (several streams or host threads) race and must be ordered by
- * the caller.  Arguments and results as btl_forward.
+ * the caller.  Arguments and results as btl_forward.  Geometries with
+ * link_normal take the term tables of their membrane links from the device
+ * buffers btl_forward made: new dt, kappa or lattice rebuild them in place
+ * (the call then waits for the stream) when they fit, else the call fails.
  * Errors: BTL_E_INVAL (also when the call needs more than the scratch --
  * about 1.1e6 field-site states in FP32 storage -- or than the staging
- * holds; the message gives the sizes), BTL_E_HIP, BTL_E_NONFINITE. */
+ * holds; the message gives the sizes), BTL_E_UNSUPPORTED (membrane term
+ * tables larger than those a btl_forward of this simulator built),
+ * BTL_E_HIP, BTL_E_NONFINITE. */
 btl_status btl_forward_noalloc(btl_sim *s, double dt, int32_t K, const double *D,
                                const double *T2, const double *kappa, int32_t Q,
                                const int32_t *q_geom, const double *gG0, const double *f,

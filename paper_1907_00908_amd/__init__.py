@@ -43,7 +43,8 @@ class btl_geom(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("dx", ctypes.c_double),
                 ("bc", ctypes.c_int32 * 3), ("n_comp", ctypes.c_int32),
                 ("comp_id", ctypes.c_void_p), ("comp_phase", ctypes.c_void_p),
-                ("n_phase", ctypes.c_int32), ("link_delta", ctypes.c_void_p)]
+                ("n_phase", ctypes.c_int32), ("link_delta", ctypes.c_void_p),
+                ("link_normal", ctypes.c_void_p)]
 
 
 _lib = None
@@ -120,8 +121,9 @@ def _check(st, handle):
 def btl_create(geoms, prec: int):
     """geoms: list of objects with comp (n2,n1,n0) uint32, comp_phase uint8,
     n_phase, dx, a `bc` list and optionally link_delta (3, n2, n1, n0)
-    float32 membrane positions (None: half-link membranes).  Returns the
-    handle."""
+    float32 membrane positions (None: half-link membranes) and link_normal
+    (3, 3, n2, n1, n0) float32 membrane normals (None: membranes normal to
+    the links).  Returns the handle."""
     lib = load_library()
     arr = (btl_geom * len(geoms))()
     keep = []
@@ -144,6 +146,13 @@ def btl_create(geoms, prec: int):
                 raise ValueError("link_delta must have shape (3, n2, n1, n0)")
             keep.append(ld)
             arr[i].link_delta = _np_ptr(ld)
+        ln = getattr(g, "link_normal", None)
+        if ln is not None:
+            ln = np.ascontiguousarray(ln, dtype=np.float32)
+            if ln.shape != (3, 3) + comp.shape:
+                raise ValueError("link_normal must have shape (3, 3, n2, n1, n0)")
+            keep.append(ln)
+            arr[i].link_normal = _np_ptr(ln)
     h = ctypes.c_void_p()
     _check(lib.btl_create(arr, len(geoms), int(prec), ctypes.byref(h)), None)
     return h
@@ -276,6 +285,7 @@ class _GeomBC:
         self.comp, self.comp_phase = g.comp, g.comp_phase
         self.n_phase, self.dx, self.bc = g.n_phase, g.dx, list(bc)
         self.link_delta = getattr(g, "link_delta", None)
+        self.link_normal = getattr(g, "link_normal", None)
 
 
 class Simulator:

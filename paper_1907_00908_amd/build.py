@@ -17,7 +17,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["btl_kernels.hip", "btl_adjoint.hip", "btl_runtime.hip"]
+SOURCES = ["btl_kernels.hip", "btl_adjoint.hip", "btl_runtime.hip", "btl_curved.hip"]
 LIB = os.path.join(HERE, "libbtlbm.so")
 ARCH = "gfx950"
 

@@ -56,6 +56,20 @@ struct FieldDesc {
     int32_t adj_fac[6];
     int64_t gm;             // offset of the geometry's membrane-position table
                             // ([6][nsites] floats, see StepArgs::gm), or -1
+    int64_t cv;             // offset of the geometry's curved-link index table
+                            // ([6][nsites] int32, see StepArgs::cvi), or -1
+};
+
+// One term of a curved membrane link: the arriving population is
+// sum_k w_k ghat(site + off_k) (off: element offset from the receiving
+// site's direction-0 element, plane included), each times the factors of
+// the periodic faces its node lies beyond: bits 2f, 2f + 1 of wrap count
+// how often the factor of face f applies (a node one period below the
+// lattice along kernel axis a takes face 2a once, one above takes 2a + 1).
+struct CvTerm {
+    double w;
+    int32_t off;
+    int32_t wrap;
 };
 
 constexpr int kAdjMaxPhase = 4;
@@ -115,6 +129,11 @@ struct StepArgs {
     // as given (v > 0: distance from s is v; v < 0: distance is 1 + v).
     const float* gm;
     const double* kdt;      // [P*P] kappa * dt
+    // Membrane condition at any angle (curved membranes): cvi[f.cv + (d-1)*nsites
+    // + s] is -1 or the link's entry in cvh; cvh[k] = (first term, count) in cvt
+    const int32_t* cvi;
+    const int2* cvh;
+    const CvTerm* cvt;
     double edx;             // eps_D * dx
     double2* tab;           // phase table of step k (T entries); the table kernel
                             // fills kTabSteps consecutive steps from here

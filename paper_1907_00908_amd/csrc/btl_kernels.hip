@@ -28,7 +28,11 @@
 // With membrane positions given, a membrane link whose six-node stencil lies
 // inside the field takes the general condition for a straight membrane at
 // that position (Eqs. B2a_text/B2b_text, B4a-B4c) instead of the half-link
-// form (GM = true; other links keep the half-link form).
+// form (GM = true; other links keep the half-link form).  With membrane
+// normals as well (CV = true), links whose stencil for the condition at any
+// angle exists (Appendix B, Eqs. phi_1, phi_2) apply the term list the host
+// built for them: the arriving population as a weighted sum of
+// post-collision populations around the link.
 //
 // The signal of a step is reduced deterministically: each wave writes its
 // partial sum to a per-step slot, and k_esum (one launch per 32 steps) adds
@@ -82,7 +86,7 @@ __global__ void __launch_bounds__(kBlock) k_tables(StepArgs a, int32_t nsteps) {
 // R = -i gamma (x.G0) f_{k+1} - 1/T2, the reaction term of the collision that
 // follows the moment M(t^{k+1}).  The last step stores the plain collision,
 // whose moment is M(t^K).
-template <typename V, int TX, bool CL, bool GM, int NQ>
+template <typename V, int TX, bool CL, bool GM, int NQ, bool CV>
 __device__ __forceinline__ void step_body(const StepArgs& a) {
     constexpr int TY = TX > 0 ? kBlock / TX : 1;
     constexpr double W0 = lattice_w0(NQ), W1 = lattice_w1(NQ);
@@ -136,6 +140,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     V* __restrict__ dst = static_cast<V*>(a.dst) + fd.pop;
     const uint32_t* __restrict__ words = a.words + fd.words;
     const float* __restrict__ gmt = GM && fd.gm >= 0 ? a.gm + fd.gm : nullptr;
+    // curved membranes (CV): per pull link -1 or the link's term list
+    const int32_t* __restrict__ cvp = CV && fd.cv >= 0 ? a.cvi + fd.cv : nullptr;
     const int32_t pop = 0;
     int32_t j0, j1;
     if constexpr (TX == 0) {   // kTileRows: kBlock consecutive sites of the x-y plane
@@ -201,6 +207,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
         V g[NQ];          // g[pz] is carried, not loaded
         V own[NQ - 1];    // own[pz - 1] is carried, not loaded
         float gv[GM ? NQ - 1 : 1];   // membrane positions of the pull links
+        int32_t cv[CV ? NQ - 1 : 1];  // curved-link entries of the pull links
+    };
+    auto cv_of = [](const SiteLoads& L, int d) -> int32_t {
+        if constexpr (CV) return L.cv[d - 1];
+        else return -1;
     };
     auto issue = [&](int32_t j2, SiteLoads& L) {
         const int32_t s = j0 + st1 * j1 + st2 * j2;
@@ -223,6 +234,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
 #pragma unroll
             for (int d = 1; d < NQ; ++d) L.gv[d - 1] = gmt ? gmt[(d - 1) * ns + s] : 0.0f;
         }
+        if constexpr (CV) {
+#pragma unroll
+            for (int d = 1; d < NQ; ++d) L.cv[d - 1] = cvp ? cvp[(d - 1) * ns + s] : -1;
+        }
     };
     // General membrane links of a site (GM): which links take the general
     // condition, and the three stencil populations of the first two of them,
@@ -230,6 +245,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     // general links loads the others when it computes them).
     struct GmPre {
         uint32_t gen;
+        uint32_t cvb;       // the general links that take the curved rule
         int d0, d1;
         V st0[3], st1[3];   // ghat_ibar(x + e_i), ghat_i(x - 2 e_i), ghat_ibar(x - e_i)
     };
@@ -244,6 +260,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     };
     auto prep = [&](int32_t j2, const SiteLoads& L, GmPre& G) {
         G.gen = 0;
+        G.cvb = 0;
         G.d0 = 0;
         G.d1 = 0;
         if constexpr (GM) {
@@ -252,20 +269,26 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
             const uint32_t mask = (word >> 4) & 0x3fu;
 #pragma unroll
             for (int d = 1; d < NQ; ++d) {
-                if (((mask >> (d - 1)) & 1u) && L.gv[d - 1] != 0.0f) {
+                const bool cvd = cv_of(L, d) >= 0;
+                if (((mask >> (d - 1)) & 1u) && (L.gv[d - 1] != 0.0f || cvd)) {
                     const int pn = (int)((word >> (10 + 3 * (d - 1))) & 0x7u);
-                    if (c_tr[p * P + pn] < 1.0) G.gen |= 1u << d;
+                    if (c_tr[p * P + pn] < 1.0) {
+                        G.gen |= 1u << d;
+                        if (cvd) G.cvb |= 1u << d;
+                    }
                 }
             }
             const int32_t sp = j0 + st1 * j1 + zs * j2;
-            if (G.gen) {
+            // stencils of the first two links with the theta = 0 rule
+            const uint32_t g0 = G.gen & ~G.cvb;
+            if (g0) {
                 int32_t o[3];
-                G.d0 = __builtin_ctz(G.gen);
+                G.d0 = __builtin_ctz(g0);
                 stencil_off(G.d0, o);
                 G.st0[0] = src[sp + o[0]];
                 G.st0[1] = src[sp + o[1]];
                 G.st0[2] = src[sp + o[2]];
-                const uint32_t rest = G.gen & (G.gen - 1);
+                const uint32_t rest = g0 & (g0 - 1);
                 if (rest) {
                     G.d1 = __builtin_ctz(rest);
                     stencil_off(G.d1, o);
@@ -327,6 +350,32 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 while (gen) {
                     const int d = __builtin_ctz(gen);
                     gen &= gen - 1;
+                    if (CV && ((G.cvb >> d) & 1u)) {
+                        // membrane at an angle: the link's term list (weights
+                        // from the host, nodes possibly beyond periodic faces)
+                        int32_t ci = 0;
+#pragma unroll
+                        for (int k = 1; k < NQ; ++k)
+                            if (d == k) ci = cv_of(L, k);
+                        const int2 hd = a.cvh[ci];
+                        double2 r = make_double2(0.0, 0.0);
+                        for (int t = hd.x; t < hd.x + hd.y; ++t) {
+                            const CvTerm tm = a.cvt[t];
+                            double2 v = ld2(src + sp + tm.off);
+                            if (tm.wrap) {
+#pragma unroll
+                                for (int fc = 0; fc < 6; ++fc)
+                                    for (int r = (tm.wrap >> (2 * fc)) & 3; r > 0; --r)
+                                        v = cmul(v, face_fac[fc]);
+                            }
+                            r.x += tm.w * v.x;
+                            r.y += tm.w * v.y;
+                        }
+#pragma unroll
+                        for (int k = 1; k < NQ; ++k)
+                            if (d == k) g[k] = r;
+                        continue;
+                    }
                     // own[k-1] holds ghat_{opp(k)}(x): both populations of x
                     // on the link's axis are already loaded
                     double2 b1 = g[1], o = ld2(&own[0]), a3 = ld2(&own[1]);
@@ -500,14 +549,14 @@ __global__ void __launch_bounds__(kBlock) k_esum(const double2* __restrict__ par
 // positions fits in 128 VGPRs when asked to, which raises the occupancy
 // from three to four waves per SIMD; the other variants keep the compiler's
 // choice (FP64 storage, one site in flight: 92 VGPRs, five waves).
-template <typename V, int TX, bool CL, bool GM, int NQ>
+template <typename V, int TX, bool CL, bool GM, int NQ, bool CV>
 __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
-    step_body<V, TX, CL, GM, NQ>(a);
+    step_body<V, TX, CL, GM, NQ, CV>(a);
 }
-template <typename V, int TX, bool CL, bool GM, int NQ>
+template <typename V, int TX, bool CL, bool GM, int NQ, bool CV>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_step_w4(StepArgs a) {
-    step_body<V, TX, CL, GM, NQ>(a);
+    step_body<V, TX, CL, GM, NQ, CV>(a);
 }
 
 // ghat^0 of the classical scheme: the collision of the equilibrium state
@@ -567,39 +616,43 @@ hipError_t launch_init(int prec, void* pop, int64_t, const FieldDesc*, int32_t n
     return hipGetLastError();
 }
 
-template <typename V, bool CL, bool GM, int NQ, int TX>
+template <typename V, bool CL, bool GM, int NQ, bool CV, int TX>
 static void launch_tx(const StepArgs& a, int32_t n_blocks, hipStream_t st) {
     if constexpr (std::is_same<V, float2>::value && !GM)
-        hipLaunchKernelGGL((k_step_w4<V, TX, CL, GM, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((k_step_w4<V, TX, CL, GM, NQ, CV>), dim3(n_blocks), dim3(kBlock), 0, st,
+                           a);
     else
-        hipLaunchKernelGGL((k_step<V, TX, CL, GM, NQ>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((k_step<V, TX, CL, GM, NQ, CV>), dim3(n_blocks), dim3(kBlock), 0, st, a);
 }
 
-template <typename V, bool CL, bool GM, int NQ>
+template <typename V, bool CL, bool GM, int NQ, bool CV>
 static void launch_step_t(int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st) {
     switch (shape) {
-        case kTile64x4: launch_tx<V, CL, GM, NQ, 64>(a, n_blocks, st); break;
-        case kTile32x8: launch_tx<V, CL, GM, NQ, 32>(a, n_blocks, st); break;
-        case kTile128x2: launch_tx<V, CL, GM, NQ, 128>(a, n_blocks, st); break;
+        case kTile64x4: launch_tx<V, CL, GM, NQ, CV, 64>(a, n_blocks, st); break;
+        case kTile32x8: launch_tx<V, CL, GM, NQ, CV, 32>(a, n_blocks, st); break;
+        case kTile128x2: launch_tx<V, CL, GM, NQ, CV, 128>(a, n_blocks, st); break;
         case kTile256x1:
-            if constexpr (NQ == 5) launch_tx<V, CL, GM, NQ, 256>(a, n_blocks, st);
+            if constexpr (NQ == 5) launch_tx<V, CL, GM, NQ, CV, 256>(a, n_blocks, st);
             break;
         case kTileRows:
-            if constexpr (NQ == 7) launch_tx<V, CL, GM, NQ, 0>(a, n_blocks, st);
+            if constexpr (NQ == 7) launch_tx<V, CL, GM, NQ, CV, 0>(a, n_blocks, st);
             break;
-        default: launch_tx<V, CL, GM, NQ, 16>(a, n_blocks, st); break;
+        default: launch_tx<V, CL, GM, NQ, CV, 16>(a, n_blocks, st); break;
     }
 }
 
 template <typename V, int NQ>
 static void launch_step_q(int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st) {
     const bool gm = a.gm != nullptr;
+    const bool cv = gm && a.cvi != nullptr;
     if (a.classical) {
-        if (gm) launch_step_t<V, true, true, NQ>(shape, a, n_blocks, st);
-        else launch_step_t<V, true, false, NQ>(shape, a, n_blocks, st);
+        if (cv) launch_step_t<V, true, true, NQ, true>(shape, a, n_blocks, st);
+        else if (gm) launch_step_t<V, true, true, NQ, false>(shape, a, n_blocks, st);
+        else launch_step_t<V, true, false, NQ, false>(shape, a, n_blocks, st);
     } else {
-        if (gm) launch_step_t<V, false, true, NQ>(shape, a, n_blocks, st);
-        else launch_step_t<V, false, false, NQ>(shape, a, n_blocks, st);
+        if (cv) launch_step_t<V, false, true, NQ, true>(shape, a, n_blocks, st);
+        else if (gm) launch_step_t<V, false, true, NQ, false>(shape, a, n_blocks, st);
+        else launch_step_t<V, false, false, NQ, false>(shape, a, n_blocks, st);
     }
 }
 

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "../../include/btlbm.h"
+#include "btl_curved.h"
 #include "btl_internal.h"
 
 using namespace btl;
@@ -62,6 +63,7 @@ struct GeomHost {
     int64_t nsites;
     int64_t words_off;   // offset into the concatenated site-word array
     int64_t gm_off = -1; // offset into the membrane-position tables, -1: none
+    int64_t cv_off = -1; // offset into the curved-link index tables, -1: none
 };
 
 template <typename T>
@@ -97,7 +99,7 @@ constexpr size_t kStageInit = (size_t)1 << 20;   // pinned staging per slot at c
 struct GraphKey {
     int32_t prec, K, Q, n_fields, nblk, shape, T, ckpt, scheme, nq, xcd;
     uint64_t fields;     // hash of the per-field values the launches take by value
-    const void* ptr[16];
+    const void* ptr[20];
 };
 
 struct GraphSlot {
@@ -123,6 +125,7 @@ uint64_t field_hash(const std::vector<FieldDesc>& fl, bool classical) {
         mix(&d.pop, sizeof(d.pop));
         mix(&d.words, sizeof(d.words));
         mix(&d.gm, sizeof(d.gm));
+        mix(&d.cv, sizeof(d.cv));
         mix(d.n, sizeof(d.n));
         mix(&d.nsites, sizeof(d.nsites));
         mix(&d.q, sizeof(d.q));
@@ -171,6 +174,14 @@ struct btl_sim {
     std::vector<GeomHost> geoms;
     DevBuf<uint32_t> words;
     DevBuf<float> gm;            // [6][nsites] per geometry with membrane positions
+    // membranes at an angle (link_normal): the membrane links of each such
+    // geometry, and the term tables of the constants in cv_key
+    std::vector<CurvedGeom> curved;
+    DevBuf<int32_t> cvi;         // [6][nsites] per curved geometry: -1 or entry in cvh
+    DevBuf<int2> cvh;            // (first term, count) per link
+    DevBuf<CvTerm> cvt;
+    std::vector<double> cv_key;  // (lattice, dt, kappa) the tables hold, empty: none
+    size_t cvi_elems = 0;
     DevBuf<char> pop[2];
     DevBuf<FieldDesc> fields;
     DevBuf<int32_t> blk_field;
@@ -427,6 +438,10 @@ extern "C" btl_status btl_create(const btl_geom* geoms, int32_t n_geom, int32_t 
         h.words_off = (int64_t)all.size();
         build_words(geoms[g], one);
         all.insert(all.end(), one.begin(), one.end());
+        if (geoms[g].link_normal && !geoms[g].link_delta) {
+            btl_destroy(s);
+            return fail(nullptr, BTL_E_INVAL, "link_normal needs link_delta");
+        }
         if (geoms[g].link_delta) {
             if (!build_gm(geoms[g], gm_one)) {
                 btl_destroy(s);
@@ -434,6 +449,17 @@ extern "C" btl_status btl_create(const btl_geom* geoms, int32_t n_geom, int32_t 
             }
             h.gm_off = (int64_t)gm_all.size();
             gm_all.insert(gm_all.end(), gm_one.begin(), gm_one.end());
+        }
+        if (geoms[g].link_normal) {
+            CurvedGeom cg;
+            if (!curved_collect(geoms[g], cg)) {
+                btl_destroy(s);
+                return fail(nullptr, BTL_E_INVAL,
+                            "link_normal must be a finite non-zero vector on membrane links");
+            }
+            h.cv_off = cg.cv_off = (int64_t)s->cvi_elems;
+            s->cvi_elems += (size_t)6 * h.nsites;
+            s->curved.push_back(std::move(cg));
         }
         s->geoms.push_back(h);
     }
@@ -539,7 +565,7 @@ static QFields plan_fields(const GeomHost& g, const double* G, bool classical, b
 struct CallPlan {
     int32_t K = 0, Q = 0, P = 0, nq = 7, msub = 1;
     double dt = 0.0;
-    bool classical = false, uses_gm = false, taping = false, g_complete = true;
+    bool classical = false, uses_gm = false, uses_cv = false, taping = false, g_complete = true;
     int shape = 0, xcd_on = 0;
     int32_t n_fields = 0, nblk_total = 0, nblk_adj = 0, T = 0;
     int64_t pop_elems = 0;       // V elements of one state (all fields of the call)
@@ -648,7 +674,10 @@ static btl_status make_plan(btl_sim* s, const Settings& cs, double dt, int32_t K
     for (int i = 0; i < P * P; ++i) consts[3 * P + P * P + i] = kappa[i];
     for (int ph = 0; ph < P; ++ph) consts[3 * P + 2 * P * P + ph] = isinf(T2[ph]) ? 0.0 : dt / T2[ph];
     for (int i = 0; i < P * P; ++i) consts[4 * P + 2 * P * P + i] = kappa[i] * dt;
-    for (int q = 0; q < Q; ++q) p.uses_gm |= s->geoms[q_geom[q]].gm_off >= 0;
+    for (int q = 0; q < Q; ++q) {
+        p.uses_gm |= s->geoms[q_geom[q]].gm_off >= 0;
+        p.uses_cv |= s->geoms[q_geom[q]].cv_off >= 0;
+    }
     // per-step waveform tables: f_k dt and F_k.  With m reaction sub-steps
     // of dt' = dt/m (Sec. 2.3) the reaction of step k is the product of m
     // exact phase factors, i.e. one factor with the summed angle, so f_k dt
@@ -728,6 +757,7 @@ static btl_status make_plan(btl_sim* s, const Settings& cs, double dt, int32_t K
             d.nblk = d.tiles[0] * d.tiles[1] * d.tiles[2];
             d.q = fi == 0 ? q : -1;
             d.gm = g.gm_off;
+            d.cv = g.cv_off;
             d.cu = 0.0;
             for (int a = 0; a < 3; ++a) {
                 const int sig = (sg >> a) & 1;
@@ -1110,6 +1140,9 @@ static StepArgs step_args(const btl_sim* s, const CallPlan& p, const CallBufs& b
     a.trans = b.consts + 2 * P;
     a.rdt = b.consts + 3 * P + 2 * P * P;
     a.gm = p.uses_gm ? s->gm.p : nullptr;
+    a.cvi = p.uses_cv ? s->cvi.p : nullptr;
+    a.cvh = s->cvh.p;
+    a.cvt = s->cvt.p;
     a.kdt = b.consts + 4 * P + 2 * P * P;
     a.edx = lattice_eps(p.nq) * s->dx;
     a.nq = p.nq;
@@ -1199,7 +1232,8 @@ static btl_status run_forward(btl_sim* s, const CallPlan& p, const CallBufs& b, 
     key.xcd = p.xcd_on;
     key.fields = field_hash(p.fl, p.classical);
     const void* ptrs[] = {b.pop[0], b.pop[1], b.fields, b.blk, b.steps, b.consts, b.partial,
-                          b.tab, b.tabf, s->E_int.p, ckpt, s->words.p, s->gm.p, s->nf_dev};
+                          b.tab, b.tabf, s->E_int.p, ckpt, s->words.p, s->gm.p, s->nf_dev,
+                          s->cvi.p, s->cvh.p, s->cvt.p};
     static_assert(sizeof(ptrs) / sizeof(ptrs[0]) <= sizeof(key.ptr) / sizeof(key.ptr[0]),
                   "graph key too small");
     for (size_t i = 0; i < sizeof(ptrs) / sizeof(ptrs[0]); ++i) key.ptr[i] = ptrs[i];
@@ -1254,6 +1288,48 @@ static btl_status final_magnetization(btl_sim* s, const CallPlan& p, const CallB
 
 // One planned call on the simulator's buffers, with a uniform tape when
 // C > 0 (the state every C steps, for btl_backward).
+// Term tables of the membranes at an angle for this call's lattice, dt and
+// permeabilities (built when these differ from the tables' constants).
+// Work still queued on st may read the old tables: it finishes first.
+// Without may_alloc the tables must fit the device buffers they have.
+static btl_status ensure_curved(btl_sim* s, const CallPlan& p, const double* kappa, hipStream_t st,
+                                bool may_alloc) {
+    if (!p.uses_cv) return BTL_OK;
+    std::vector<double> key = {(double)p.nq, p.dt};
+    key.insert(key.end(), kappa, kappa + p.P * p.P);
+    if (key.size() == s->cv_key.size() &&
+        memcmp(key.data(), s->cv_key.data(), key.size() * sizeof(double)) == 0)
+        return BTL_OK;
+    std::vector<int32_t> idx(s->curved.empty() ? 0 : (size_t)s->curved.back().cv_off +
+                                                         6 * s->curved.back().comp.size(), -1);
+    std::vector<int2> heads;
+    std::vector<CvTerm> terms;
+    for (const CurvedGeom& cg : s->curved)
+        curved_terms(cg, p.nq, p.dt, s->dx, kappa, p.P, idx.data() + cg.cv_off, heads, terms);
+    if (heads.empty()) heads.push_back(make_int2(0, 0));
+    if (terms.empty()) terms.push_back(CvTerm{0.0, 0, 0});
+    if (!may_alloc && (idx.size() > s->cvi.cap || heads.size() > s->cvh.cap ||
+                       terms.size() > s->cvt.cap))
+        return fail(s, BTL_E_UNSUPPORTED,
+                    "the membrane term tables for these constants need device memory: run "
+                    "btl_forward with them first");
+    s->cv_key.clear();
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = s->cvi.ensure(idx.size());
+    if (e == hipSuccess) e = s->cvh.ensure(heads.size());
+    if (e == hipSuccess) e = s->cvt.ensure(terms.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(s->cvi.p, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(s->cvh.p, heads.data(), heads.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(s->cvt.p, terms.data(), terms.size() * sizeof(CvTerm),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(s, e, "membrane term tables");
+    s->cv_key = key;
+    return BTL_OK;
+}
+
 static btl_status forward_call(btl_sim* s, const Settings& cs, double dt, int32_t K,
                                const double* D, const double* T2, const double* kappa, int32_t Q,
                                const int32_t* q_geom, const double* gG0, const double* f,
@@ -1261,6 +1337,7 @@ static btl_status forward_call(btl_sim* s, const Settings& cs, double dt, int32_
     CallPlan p;
     btl_status rc = make_plan(s, cs, dt, K, D, T2, kappa, Q, q_geom, gG0, f, C > 0, p);
     if (rc != BTL_OK) return rc;
+    if ((rc = ensure_curved(s, p, kappa, st, true)) != BTL_OK) return rc;
     CallBufs b;
     if ((rc = alloc_bufs(s, p, b)) != BTL_OK) return rc;
     if ((rc = upload_plan(s, p, b, true, st)) != BTL_OK) return rc;
@@ -1436,6 +1513,7 @@ extern "C" btl_status btl_forward_noalloc(btl_sim* s, double dt, int32_t K, cons
     CallPlan p;
     if ((rc = make_plan(s, cs, dt, K, D, T2, kappa, Q, q_geom, gG0, f, false, p)) != BTL_OK)
         return rc;
+    if ((rc = ensure_curved(s, p, kappa, st, false)) != BTL_OK) return rc;
     CallBufs b;
     if ((rc = scratch_bufs(s, p, b)) != BTL_OK) return rc;
     if ((rc = upload_plan(s, p, b, false, st)) != BTL_OK) return rc;
@@ -1834,7 +1912,7 @@ static std::string tune_key(const btl_sim* s, const CallPlan& p) {
          std::to_string(p.classical ? 1 : 0);
     for (const FieldDesc& d : p.fl)
         k += "/" + std::to_string(d.n[0]) + "x" + std::to_string(d.n[1]) + "x" +
-             std::to_string(d.n[2]) + (d.gm >= 0 ? "g" : "");
+             std::to_string(d.n[2]) + (d.gm >= 0 ? "g" : "") + (d.cv >= 0 ? "c" : "");
     return k;
 }
 
@@ -2073,6 +2151,9 @@ extern "C" void btl_destroy(btl_sim* s) {
     s->gfield.release();
     s->tab.release();
     s->tab_field.release();
+    s->cvi.release();
+    s->cvh.release();
+    s->cvt.release();
     for (int i = 0; i < 2; ++i) {
         if (s->stage[i]) (void)hipHostFree(s->stage[i]);
         if (s->stage_ev[i]) (void)hipEventDestroy(s->stage_ev[i]);

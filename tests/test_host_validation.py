@@ -23,6 +23,7 @@ def _geom(n=(4, 4, 4), dx=0.5, bc=(0, 0, 0), comp=None, comp_phase=None, n_phase
     g.comp_phase = comp_phase.ctypes.data
     g.n_phase = n_phase
     g.link_delta = None
+    g.link_normal = None
     return g
 
 
