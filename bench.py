@@ -308,9 +308,11 @@ def main():
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
     ap.add_argument("--scheme", default="hybrid", choices=["hybrid", "classical"],
                     help="classical: the classical LBM of Appendix A (no adjoint)")
-    ap.add_argument("--membranes", default="half-link", choices=["half-link", "positions"],
+    ap.add_argument("--membranes", default="half-link", choices=["half-link", "positions", "curved"],
                     help="positions: exact membrane positions on the links and the "
-                         "general membrane condition (no adjoint)")
+                         "general membrane condition taken normal to the link; curved: "
+                         "also the membrane normals, the condition at any angle "
+                         "(neither has an adjoint)")
     ap.add_argument("--launch", default=None,
                     help="tile,zc,xcd: fix the step kernel's launch (btl_set_launch) "
                          "instead of autotuning")
@@ -388,7 +390,7 @@ def main():
     K = max(1, args.steps)
     W = max(0, args.warmup)
     log(f"building workload {args.workload}")
-    if args.membranes == "positions" or args.scheme != "hybrid":
+    if args.membranes != "half-link" or args.scheme != "hybrid":
         args.no_adjoint = True          # the adjoint covers hybrid half-link runs
     scheme = 0 if args.scheme == "hybrid" else 1
     cfg = workload(args.workload, K, args.membranes)

@@ -40,7 +40,8 @@ bool curved_collect(const btl_geom& g, CurvedGeom& out);
 // for each link that takes the condition the index of its entry in heads
 // ({first term, number of terms}); the terms are appended to terms, with
 // population offsets and face wraps in the kernel's layout of the lattice.
-void curved_terms(const CurvedGeom& cg, int nq, double dt, double dx, const double* kappa,
+// False when the tables would pass 2^31 - 1 entries.
+bool curved_terms(const CurvedGeom& cg, int nq, double dt, double dx, const double* kappa,
                   int P, int32_t* idx, std::vector<int2>& heads, std::vector<CvTerm>& terms);
 
 }  // namespace btl

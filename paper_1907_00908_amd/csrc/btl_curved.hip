@@ -31,6 +31,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <thread>
 
 namespace btl {
 namespace {
@@ -114,9 +115,18 @@ bool in_comp(const CurvedGeom& g, const int32_t j[3], uint32_t c) {
 // compartment c nearest to the point (equal distances: the smaller u first).
 bool add_interp(const CurvedGeom& g, uint32_t c, int q, const int32_t base[3], const int e[3],
                 double t, double coef, Form& f) {
+    // candidates by distance to the point; insertion sort keeps equal
+    // distances in ascending u
     int order[7] = {-3, -2, -1, 0, 1, 2, 3};
-    std::stable_sort(order, order + 7,
-                     [t](int u, int v) { return fabs(u - t) < fabs(v - t); });
+    for (int k = 1; k < 7; ++k) {
+        const int u = order[k];
+        int m = k;
+        while (m > 0 && fabs(u - t) < fabs(order[m - 1] - t)) {
+            order[m] = order[m - 1];
+            --m;
+        }
+        order[m] = u;
+    }
     int use[3], nu = 0;
     for (int k = 0; k < 7 && nu < 3; ++k) {
         int32_t j[3];
@@ -237,8 +247,21 @@ bool curved_collect(const btl_geom& g, CurvedGeom& out) {
     return true;
 }
 
-void curved_terms(const CurvedGeom& cg, int nq, double dt, double dx, const double* kappa,
-                  int P, int32_t* idx, std::vector<int2>& heads, std::vector<CvTerm>& terms) {
+namespace {
+
+// The term lists of the links [l0, l1) of cg: per link that takes the
+// condition its index-table position, its (first term, count) within
+// `terms`, and its terms.
+struct Chunk {
+    std::vector<int64_t> pos;
+    std::vector<int2> heads;
+    std::vector<CvTerm> terms;
+};
+
+void terms_range(const CurvedGeom& cg, int nq, double dt, double dx, const double* kappa, int P,
+                 size_t l0, size_t l1, Chunk& out) {
+    std::vector<int2>& heads = out.heads;
+    std::vector<CvTerm>& terms = out.terms;
     const Ctx cx{cg, nq, lattice_eps(nq), dt / dx};
     const int64_t n0 = cg.n[0], n1 = cg.n[1];
     const int64_t N = n0 * n1 * cg.n[2];
@@ -252,7 +275,8 @@ void curved_terms(const CurvedGeom& cg, int nq, double dt, double dx, const doub
         for (int a = 0; a < 3; ++a) k[kax[a]] = j[a];
         return k[0] + kn0 * k[1] + zs * k[2];
     };
-    for (const CurvedGeom::Link& lk : cg.links) {
+    for (size_t li = l0; li < l1; ++li) {
+        const CurvedGeom::Link& lk = cg.links[li];
         const int d = lk.d;
         if (nq == 5 && d > 4) continue;
         const int64_t s = lk.s;
@@ -333,9 +357,49 @@ void curved_terms(const CurvedGeom& cg, int nq, double dt, double dx, const doub
             terms.resize((size_t)first);
             continue;
         }
-        idx[(size_t)(d - 1) * N + s] = (int32_t)heads.size();
+        out.pos.push_back((d - 1) * N + s);
         heads.push_back(make_int2(first, (int32_t)terms.size() - first));
     }
+}
+
+}  // namespace
+
+bool curved_terms(const CurvedGeom& cg, int nq, double dt, double dx, const double* kappa,
+                  int P, int32_t* idx, std::vector<int2>& heads, std::vector<CvTerm>& terms) {
+    // links are independent: chunks on up to 16 host threads, joined in order
+    const size_t L = cg.links.size();
+    size_t T = std::min<size_t>(16, std::max(1u, std::thread::hardware_concurrency()));
+    if (L < 16384) T = 1;
+    std::vector<Chunk> ch(T);
+    std::vector<std::thread> th;
+    for (size_t t = 1; t < T; ++t)
+        th.emplace_back(terms_range, std::cref(cg), nq, dt, dx, kappa, P, L * t / T,
+                        L * (t + 1) / T, std::ref(ch[t]));
+    terms_range(cg, nq, dt, dx, kappa, P, 0, L / T, ch[0]);
+    for (std::thread& x : th) x.join();
+    // place the chunks one after another (each copied by its own thread)
+    std::vector<size_t> h0(T + 1, heads.size()), t0(T + 1, terms.size());
+    for (size_t t = 0; t < T; ++t) {
+        h0[t + 1] = h0[t] + ch[t].heads.size();
+        t0[t + 1] = t0[t] + ch[t].terms.size();
+    }
+    if (h0[T] > (size_t)INT32_MAX || t0[T] > (size_t)INT32_MAX) return false;
+    heads.resize(h0[T]);
+    terms.resize(t0[T]);
+    auto place = [&](size_t t) {
+        Chunk& c = ch[t];
+        for (size_t k = 0; k < c.heads.size(); ++k) {
+            idx[c.pos[k]] = (int32_t)(h0[t] + k);
+            heads[h0[t] + k] = make_int2((int32_t)t0[t] + c.heads[k].x, c.heads[k].y);
+        }
+        std::copy(c.terms.begin(), c.terms.end(), terms.begin() + t0[t]);
+        c = Chunk();
+    };
+    th.clear();
+    for (size_t t = 1; t < T; ++t) th.emplace_back(place, t);
+    place(0);
+    for (std::thread& x : th) x.join();
+    return true;
 }
 
 }  // namespace btl

@@ -1305,7 +1305,9 @@ static btl_status ensure_curved(btl_sim* s, const CallPlan& p, const double* kap
     std::vector<int2> heads;
     std::vector<CvTerm> terms;
     for (const CurvedGeom& cg : s->curved)
-        curved_terms(cg, p.nq, p.dt, s->dx, kappa, p.P, idx.data() + cg.cv_off, heads, terms);
+        if (!curved_terms(cg, p.nq, p.dt, s->dx, kappa, p.P, idx.data() + cg.cv_off, heads,
+                          terms))
+            return fail(s, BTL_E_UNSUPPORTED, "more than 2^31 - 1 membrane terms");
     if (heads.empty()) heads.push_back(make_int2(0, 0));
     if (terms.empty()) terms.push_back(CvTerm{0.0, 0, 0});
     if (!may_alloc && (idx.size() > s->cvi.cap || heads.size() > s->cvh.cap ||
