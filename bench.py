@@ -100,6 +100,18 @@ def q_sites(cfg) -> int:
     return sum(cfg["geoms"][int(g)].comp.size for g in cfg["q_geom"])
 
 
+def tune_probe(cfg, tune_q, classical=False):
+    """q-samples and steps of the autotuner's probe: at most tune_q q-samples
+    and about 1.2e9 field sites (so that large lattices probe on fewer
+    q-samples), and about 6e9 field-site updates per candidate, 4 to 40
+    steps (short probes time the forward's set-up as much as its steps)."""
+    Q = len(cfg["gG0"])
+    per_q = field_sites(cfg, classical, [0])
+    Qt = max(1, min(Q, tune_q, int(1.2e9 // per_q)))
+    fst = field_sites(cfg, classical, range(Qt))
+    return Qt, max(4, min(40, int(6e9 / fst)))
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -239,9 +251,10 @@ def bench_adjoint(btl, torch, args):
     sim = btl.Simulator(cfg["geoms"], cfg["bc"], args.prec)
     try:
         stream = torch.cuda.current_stream().cuda_stream
-        sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:2], cfg["gG0"])
-        probe = max(2, min(40, int(1.5e9 / fs)))
-        btl.btl_autotune(sim._h, Q, probe, stream)
+        Qt, probe = tune_probe(cfg, 32)
+        sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:2], cfg["gG0"][:Qt],
+                    cfg["q_geom"][:Qt])
+        btl.btl_autotune(sim._h, Qt, probe, stream)
         # forward step time on the same workload (for the adjoint kernel's
         # share of the sweep); at most 200 steps
         Kf = min(Kb, 200)
@@ -403,7 +416,7 @@ def main():
     # read nq complex populations + write nq, per field site
     bpf = (BYTES_PER_FIELD_SITE_F32 if args.prec == "f32" else BYTES_PER_FIELD_SITE_F64) * nq // 7
     stream = torch.cuda.current_stream().cuda_stream
-    Qt = min(Q, max(1, args.tune_q))
+    Qt, probe = tune_probe(cfg, max(1, args.tune_q), args.scheme == "classical")
     tq = list(range(Qt))
     sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:2], cfg["gG0"][tq],
                 cfg["q_geom"][tq])
@@ -412,9 +425,7 @@ def main():
         btl.btl_set_launch(sim._h, t, z, x)
     elif not args.no_autotune:
         # launch shape chosen by timed probes on the first Qt q-samples (one
-        # q-wave; setup, untimed): about 1.5e9 field-site updates per candidate
-        fst = field_sites(cfg, args.scheme == "classical", tq)
-        probe = max(2, min(40, int(1.5e9 / fst)))
+        # q-wave; setup, untimed)
         log(f"autotune ({Qt} q-samples, {probe} steps per candidate)")
         btl.btl_autotune(sim._h, Qt, probe, stream)
     launch = dict(zip(("tile", "zc", "xcd"), btl.btl_get_launch(sim._h)))

@@ -71,11 +71,14 @@ def _cblock(c, conj=False):
 
 
 def dense_step_matrices(comp, comp_phase, bc, dx, dt, D, T2, kappa, f, gG0, scheme=0,
-                        lattice=0):
+                        lattice=0, factors=False):
     """Real step matrices A_k (one per step) for a tiny lattice.
 
     scheme 1: classical LBM, the reaction term dt w_i R M inside the
     collision and no reaction split.
+
+    factors=True returns each step as its factors (applied right to left:
+    collision, streaming, reaction) instead of their product.
 
     State vector: index part*7N + i*N + s, part 0 = Re, 1 = Im, s the site
     index with x fastest.  Mirror faces use the paper's rule for gradients
@@ -170,7 +173,7 @@ def dense_step_matrices(comp, comp_phase, bc, dx, dt, D, T2, kappa, f, gG0, sche
                         for pd in range(2):
                             for ps in range(2):
                                 Ck[pd * S7 + i * N + s_, ps * S7 + jj * N + s_] += blk[pd, ps]
-            mats.append(S @ Ck)
+            mats.append((S, Ck) if factors else S @ Ck)
             F += f[k] * dt
             continue
         # reaction
@@ -184,7 +187,7 @@ def dense_step_matrices(comp, comp_phase, bc, dx, dt, D, T2, kappa, f, gG0, sche
                 for pd in range(2):
                     for ps in range(2):
                         R[pd * S7 + i * N + s, ps * S7 + i * N + s] = blk[pd, ps]
-        mats.append(R @ S @ Cr)
+        mats.append((R, S, Cr) if factors else R @ S @ Cr)
         F += f[k] * dt
     return mats
 
@@ -200,7 +203,12 @@ def dense_run(mats, N, lattice=0):
     for k in range(len(mats) + 1):
         out.append((v[:S7].sum() + 1j * v[S7:].sum()) / N)
         if k < len(mats):
-            v = mats[k] @ v
+            m = mats[k]
+            if isinstance(m, tuple):
+                for fac in reversed(m):
+                    v = fac @ v
+            else:
+                v = m @ v
     return np.array(out)
 
 

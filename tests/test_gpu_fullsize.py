@@ -10,6 +10,7 @@ order on every reduced case)."""
 import numpy as np
 import pytest
 
+import bench
 import oracle
 import workloads as w
 
@@ -29,15 +30,13 @@ def _config(name):
 
 
 def _forward_autotuned(btl, cfg, K, want_M=False, keep_M=()):
-    """Forward of all q-samples in the benchmark's launch: autotuned on the
-    first min(32, Q) q-samples, about 1.5e9 field-site updates per probe."""
+    """Forward of all q-samples in the benchmark's launch: autotuned with the
+    benchmark's probe (bench.tune_probe)."""
     import torch
     sim = btl.Simulator(cfg["geoms"], cfg["bc"], "f32", lattice=cfg.get("lattice", 0))
     try:
         stream = torch.cuda.current_stream().cuda_stream
-        Qt = min(32, len(cfg["gG0"]))
-        fst = sum(cfg["geoms"][int(g)].comp.size for g in cfg["q_geom"][:Qt])
-        probe = max(2, min(40, int(1.5e9 / fst)))
+        Qt, probe = bench.tune_probe(cfg, 32)
         sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:2],
                     cfg["gG0"][:Qt], cfg["q_geom"][:Qt])
         btl.btl_autotune(sim._h, Qt, probe, stream)
@@ -53,9 +52,16 @@ def _forward_autotuned(btl, cfg, K, want_M=False, keep_M=()):
 
 
 def _sampled(cfg, qs, K, want_M=False):
-    print(f"  GPU done; oracle on q-samples {qs}", flush=True)
+    # one q-sample at a time, each announced (a 512^3 oracle run takes the
+    # host about two minutes)
     c = dict(cfg, f=cfg["f"][:K])
-    return oracle.simulate_config(c, q=qs, threads=16, want_M=want_M)
+    Es, Ms = [], []
+    for q in qs:
+        print(f"  oracle on q-sample {q}", flush=True)
+        E, M = oracle.simulate_config(c, q=[q], threads=16, want_M=want_M)
+        Es.append(E[0])
+        Ms.append(M[0])
+    return np.array(Es), Ms
 
 
 def test_cfg3a_full_size_256_q_sampled():
