@@ -61,7 +61,6 @@ WORKLOAD_NAMES = {
 }
 TRAFFIC_FILES = {
     ("cfg3a", "k_step"): os.path.join(ROOT, "profiles", "k_step_f32_cylspheres256_traffic.json"),
-    ("cfg2", "k_step"): os.path.join(ROOT, "profiles", "k_step_f32_axon128_traffic.json"),
     ("cfg4", "k_adj"): os.path.join(ROOT, "profiles", "k_adj_f32_cyl96_traffic.json"),
 }
 
@@ -152,8 +151,10 @@ def forward_fn(sim, cfg, K, qs=None, ckpt_every=0):
 
 
 def traffic_for(key, kernel_sha, launch):
-    """Measured HBM bytes per launch, when the committed counter profile is
-    of this kernel source and of this launch shape."""
+    """Measured HBM bytes per step (calibrated FETCH_SIZE + WRITE_SIZE over
+    the step's launches), when the committed counter profile is of this
+    kernel source and of this launch shape (the forward launch, for the
+    adjoint, whose tile shape follows it)."""
     path = TRAFFIC_FILES.get(key)
     if not path:
         return None
@@ -164,10 +165,9 @@ def traffic_for(key, kernel_sha, launch):
         return None
     if t.get("kernel_sha") != kernel_sha:
         return None
-    if t.get("launch") == launch:
-        return t["bytes_per_launch"]
-    row = t.get("by_launch", {}).get(f"{launch['tile']},{launch['zc']},{launch['xcd']}")
-    return row["bytes_per_launch"] if row else None
+    if launch is not None and t.get("launch", t.get("forward_launch")) != launch:
+        return None
+    return t.get("bytes_per_step")
 
 
 def cpu_baseline(cfg, budget_s: float = 25.0):
@@ -254,7 +254,11 @@ def bench_adjoint(btl, torch, args):
         Qt, probe = tune_probe(cfg, 32)
         sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:2], cfg["gG0"][:Qt],
                     cfg["q_geom"][:Qt])
-        btl.btl_autotune(sim._h, Qt, probe, stream)
+        if args.adj_launch:
+            btl.btl_set_launch(sim._h, *(int(v) for v in args.adj_launch.split(",")))
+        else:
+            btl.btl_autotune(sim._h, Qt, probe, stream)
+        fwd_launch = dict(zip(("tile", "zc", "xcd"), btl.btl_get_launch(sim._h)))
         # forward step time on the same workload (for the adjoint kernel's
         # share of the sweep); at most 200 steps
         Kf = min(Kb, 200)
@@ -278,11 +282,24 @@ def bench_adjoint(btl, torch, args):
             times.append(ms)
         ms = float(np.median(times))
         stats = btl.btl_get_backward_stats(sim._h)
+        # the adjoint-step launches of the last sweep, timed by the library
+        # with HIP events on this stream (uniform tapes only)
+        try:
+            adj_timed = btl.btl_get_backward_timing(sim._h)
+        except btl.BtlError:
+            adj_timed = None
     finally:
         sim.close()
     fwd_step = fwd_ms / Kf
     recompute_ms = stats[0] * fwd_step
-    adj_ms = max(ms - recompute_ms, 1e-9) / Kb
+    if adj_timed is not None and adj_timed[1] > 0:
+        adj_ms = adj_timed[0] / adj_timed[1]
+        how = ("HIP events the library records on the launch stream around each segment's run "
+               "of adjoint steps (last timed sweep), per adjoint step")
+    else:
+        adj_ms = max(ms - recompute_ms, 1e-9) / Kb
+        how = ("estimate: backward time minus the recomputed forward steps at the measured "
+               "forward step time, per adjoint step")
     nq = 5 if cfg.get("lattice", 0) == 1 else 7
     bpf = (ADJ_BYTES_PER_FIELD_SITE_F32 if args.prec == "f32" else 2 * ADJ_BYTES_PER_FIELD_SITE_F32) * nq // 7
     ach = fs * bpf / (adj_ms * 1e-3) / 1e9
@@ -296,16 +313,14 @@ def bench_adjoint(btl, torch, args):
             "ms_all": times, "q_samples": Q, "forward_steps_recomputed": stats[0],
             "groups": stats[1], "kept_states_per_group": stats[2],
             "tape": "deferred (binomial checkpointing)" if stats[2] > 0 else "uniform",
-            "forward_ms_per_step": fwd_step,
+            "forward_ms_per_step": fwd_step, "forward_launch": fwd_launch,
             "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": ach / HBM_PEAK_GBS,
                          "traffic": traffic_for((name, "k_adj"), source_hash(ADJOINT_SRC),
-                                                None) if args.prec == "f32" else None,
+                                                fwd_launch) if args.prec == "f32" else None,
                          "kernel": f"k_adj<{'float2' if args.prec == 'f32' else 'double2'}>",
                          "bytes_per_launch_algorithmic": fs * bpf,
-                         "ms_per_launch_est": adj_ms,
-                         "estimate": "backward time minus the recomputed forward steps at the "
-                                     "measured forward step time, per adjoint step"},
+                         "ms_per_launch": adj_ms, "timing": how},
             "gradients_finite": finite}
 
 
@@ -339,6 +354,9 @@ def main():
     ap.add_argument("--adj-ckpt", type=int, default=20)
     ap.add_argument("--adj-only", action="store_true",
                     help="only the adjoint leg (profiling)")
+    ap.add_argument("--adj-launch", default=None,
+                    help="tile,zc,xcd: the forward launch of the adjoint leg (its tile shape "
+                         "is also the adjoint's) instead of autotuning")
     ap.add_argument("--adj-q", type=int, default=0,
                     help="the adjoint leg on the first N q-samples only (0: all)")
     ap.add_argument("--adj-cold", action="store_true",
@@ -406,7 +424,7 @@ def main():
     if args.membranes != "half-link" or args.scheme != "hybrid":
         args.no_adjoint = True          # the adjoint covers hybrid half-link runs
     scheme = 0 if args.scheme == "hybrid" else 1
-    cfg = workload(args.workload, K, args.membranes)
+    cfg = workload(args.workload, 2 * K, args.membranes)
     Q = len(cfg["gG0"])
     qs = q_sites(cfg)
     fs = field_sites(cfg, args.scheme == "classical")
@@ -430,17 +448,24 @@ def main():
         btl.btl_autotune(sim._h, Qt, probe, stream)
     launch = dict(zip(("tile", "zc", "xcd"), btl.btl_get_launch(sim._h)))
     fwd = forward_fn(sim, cfg, K)
+    fwd2 = forward_fn(sim, cfg, 2 * K)
     n_warm = max(1, -(-W // K))
-    log(f"warmup: {n_warm} forward(s) of {K} steps")
+    log(f"warmup: {n_warm} forward(s) of {K} steps, one of {2 * K}")
     for _ in range(n_warm):
         fwd()
+    fwd2()
     torch.cuda.synchronize()
     log(f"timed: {args.reps} forwards of {K} steps")
     ms, ms_all, E = timed(torch, fwd, args.reps)
     ms_step = ms / K
     value = qs * K / (ms * 1e-3)
     bytes_step = fs * bpf
-    achieved = bytes_step / (ms_step * 1e-3) / 1e9
+    # the step launches alone: a forward of 2K steps less one of K steps
+    # (same q-waves, initial states, tables and signal launches per call)
+    log(f"timed: {args.reps} forwards of {2 * K} steps")
+    ms2, ms2_all, _ = timed(torch, fwd2, args.reps)
+    kern_ms_step = max(ms2 - ms, 1e-9) / K
+    achieved = bytes_step / (kern_ms_step * 1e-3) / 1e9
     kname = f"k_step<{'float2' if args.prec == 'f32' else 'double2'}, {'D2Q5' if nq == 5 else 'D3Q7'}>"
     traffic = None
     if args.prec == "f32" and args.membranes == "half-link" and scheme == 0:
@@ -448,9 +473,12 @@ def main():
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname,
             "bytes_per_step_algorithmic": bytes_step,
-            "timing": "HIP events around each timed forward on the launch stream (median of "
-                      f"{args.reps}); the forward's own table and signal launches (one each per "
-                      "32 steps) are included"}
+            "ms_per_step_launches": kern_ms_step,
+            "frac_whole_forward": bytes_step / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "timing": "HIP events on the launch stream around forwards of K and of 2K steps "
+                      f"(medians of {args.reps}); the step launches of one step (one per "
+                      "q-wave) take the difference over K; frac_whole_forward divides by the "
+                      "whole K-step forward (initial states, tables, signal sums included)"}
     out = {"metric": METRIC, "value": value, "unit": "site-updates/s", "n_gpus": 1,
            "steps": K, "warmup": W, "ms_per_step": ms_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -460,7 +488,7 @@ def main():
                       "storage": args.prec, "arithmetic": "f64", "sums": "f64",
                       "steps_per_forward": K, "membranes": args.membranes,
                       "scheme": args.scheme, "launch": launch, "reps": args.reps,
-                      "ms_per_forward_all": ms_all},
+                      "ms_per_forward_all": ms_all, "ms_per_forward_2K_all": ms2_all},
            "roofline": roof}
     if not args.no_extras:
         log("FP64 comparison runs")
@@ -472,17 +500,30 @@ def main():
         try:
             one = forward_fn(sim64, cfg, K, qs=[0])
             one()
+            if not args.no_autotune:
+                c1 = dict(cfg, gG0=cfg["gG0"][:1], q_geom=cfg["q_geom"][:1])
+                btl.btl_autotune(sim64._h, 1, tune_probe(c1, 1)[1], stream)
+                one()
             ms1, _, _ = timed(torch, one, args.reps)
             v1 = cfg["geoms"][int(cfg["q_geom"][0])].comp.size * K / (ms1 * 1e-3)
             out["fp64_one_q_per_launch"] = {"value": v1, "unit": "site-updates/s",
                                             "speedup_of_value": value / v1,
-                                            "what": "FP64 storage, q-sample 0 alone, default "
+                                            "launch": dict(zip(("tile", "zc", "xcd"),
+                                                               btl.btl_get_launch(sim64._h))),
+                                            "what": "FP64 storage, q-sample 0 alone, autotuned "
                                                     "launch, median of reps"}
             allq = forward_fn(sim64, cfg, K)
+            Qt64, probe64 = tune_probe(cfg, 8)
+            sim64.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:2],
+                          cfg["gG0"][:Qt64], cfg["q_geom"][:Qt64])
+            if not args.no_autotune:
+                btl.btl_autotune(sim64._h, Qt64, probe64, stream)
             allq()
             ms64, _, _ = timed(torch, allq, 1)
             out["fp64_batched"] = {"value": qs * K / (ms64 * 1e-3),
-                                   "what": "FP64 storage, the whole batch, default launch"}
+                                   "launch": dict(zip(("tile", "zc", "xcd"),
+                                                      btl.btl_get_launch(sim64._h))),
+                                   "what": "FP64 storage, the whole batch, autotuned launch"}
         finally:
             sim64.close()
     sim.close()

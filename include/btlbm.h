@@ -210,6 +210,17 @@ btl_status btl_backward(btl_sim *s, const double *dL_dE, double *dD, double *dT2
 btl_status btl_get_backward_stats(const btl_sim *s, int64_t *fwd_steps, int32_t *groups,
                                   int32_t *snapshots);
 
+/* Device time of the adjoint steps of the last btl_backward of s (a uniform
+ * tape): the elapsed time between HIP events recorded on its stream before
+ * and after each segment's run of adjoint-step launches (the segment's
+ * forward recompute and the gradient sums are outside them), summed over the
+ * segments, and the number of adjoint steps they bracket.  Waits for those
+ * events.  Host pointers, written on success.
+ * Errors: BTL_E_INVAL (a NULL argument; no backward ran, or it replayed a
+ * deferred tape, whose adjoint steps interleave with recomputes and are not
+ * timed), BTL_E_HIP. */
+btl_status btl_get_backward_timing(btl_sim *s, double *ms_adjoint, int64_t *adjoint_steps);
+
 /* Select the lattice of later btl_forward calls.  BTL_D3Q7 (default):
  * eps_D = 1/4, w_0 = 1/4, w_i = 1/8.  BTL_D2Q5: the two-dimensional lattice
  * of Sec. 2.2 (Eq. omega_i: eps_D = 1/3, w_0 = 1/3, w_{1..4} = 1/6) on

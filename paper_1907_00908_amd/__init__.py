@@ -27,7 +27,7 @@ BTL_HYBRID, BTL_CLASSICAL = 0, 1
 BTL_D3Q7, BTL_D2Q5 = 0, 1
 
 EXPORTED = ("btl_create", "btl_forward", "btl_forward_noalloc", "btl_backward",
-            "btl_get_backward_stats", "btl_set_scheme", "btl_set_lattice", "btl_set_substeps",
+            "btl_get_backward_stats", "btl_get_backward_timing", "btl_set_scheme", "btl_set_lattice", "btl_set_substeps",
             "btl_set_grad_gG0", "btl_autotune", "btl_set_launch", "btl_set_adjoint_launch",
             "btl_set_memory_budget", "btl_set_graphs", "btl_get_launch", "btl_synchronize",
             "btl_destroy", "btl_last_error")
@@ -75,6 +75,9 @@ def load_library(path: str = None):
     lib.btl_get_backward_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64),
                                            ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.btl_get_backward_stats.restype = ctypes.c_int
+    lib.btl_get_backward_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_int64)]
+    lib.btl_get_backward_timing.restype = ctypes.c_int
     lib.btl_set_launch.argtypes = [P, i32, i32, i32]
     lib.btl_set_launch.restype = ctypes.c_int
     lib.btl_set_adjoint_launch.argtypes = [P, i32, i32]
@@ -214,6 +217,15 @@ def btl_get_backward_stats(h):
     a, b, c = ctypes.c_int64(0), ctypes.c_int32(0), ctypes.c_int32(0)
     _check(lib.btl_get_backward_stats(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), h)
     return int(a.value), int(b.value), int(c.value)
+
+
+def btl_get_backward_timing(h):
+    """(milliseconds, steps) of the adjoint-step launches of the last
+    btl_backward (uniform tape)."""
+    lib = load_library()
+    ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
+    _check(lib.btl_get_backward_timing(h, ctypes.byref(ms), ctypes.byref(n)), h)
+    return float(ms.value), int(n.value)
 
 
 def btl_set_launch(h, tile_shape, zc, xcd):

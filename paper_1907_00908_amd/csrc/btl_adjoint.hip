@@ -217,6 +217,9 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
             c_rg5 = fwd[(z0 == 0 ? o5f : o5i) + sp];
             c_ro5 = fwd[pop + (pz + 1) * ps + sp];
         }
+        // the site word of the next site is loaded one site ahead: the
+        // first use of a word then never waits a memory round trip of its own
+        uint32_t word_next = words[j0 + st1 * j1 + st2 * z0];
 #pragma nounroll
         for (int32_t j2 = z0; j2 < z1; ++j2) {
             const int32_t s = j0 + st1 * j1 + st2 * j2;
@@ -224,7 +227,8 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
             const bool fz0 = j2 == 0, fz1 = j2 == n2 - 1;
             // Two load phases per node keep the live register set small:
             // first the adjoint (consumed into lhat), then the forward state.
-            const uint32_t word = words[s];
+            const uint32_t word = word_next;
+            if (j2 + 1 < z1) word_next = words[s + st2];
             const int p = (int)(word & 0xfu);
             const uint32_t mask = (word >> 4) & 0x3fu;
             auto nbphase = [&](int d) { return (int)((word >> (10 + 3 * (d - 1))) & 0x7u); };

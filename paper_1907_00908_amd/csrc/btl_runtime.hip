@@ -245,6 +245,11 @@ struct btl_sim {
     int64_t stat_fwd_steps = 0;    // forward steps run by the reverse sweep
     int32_t stat_waves = 0;        // groups of q-samples reversed one after another
     int32_t stat_snapshots = 0;    // states kept per group (binomial schedule), 0: uniform tape
+    // events around each segment's run of adjoint steps (uniform tape), read
+    // by btl_get_backward_timing; created on first use and reused
+    std::vector<hipEvent_t> tev;
+    int32_t tev_used = 0;          // events recorded by the last backward (pairs)
+    int32_t tev_steps = 0;         // adjoint steps they bracket
     std::string err;
 };
 
@@ -1676,6 +1681,13 @@ static btl_status backward_uniform(btl_sim* s, const double* dL_dE, double* dD, 
     const int32_t nseg = (K + C - 1) / C;
     int lam_cur = 0;      // buffer holding Lambda^k on entry to adjoint step k
     int64_t nfwd = 0;
+    s->tev_used = 0;
+    s->tev_steps = 0;
+    while ((int32_t)s->tev.size() < 2 * nseg) {
+        hipEvent_t ev;
+        if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail(s, e, "timing events");
+        s->tev.push_back(ev);
+    }
     for (int32_t m = nseg - 1; m >= 0; --m) {
         const int32_t k0 = m * C, k1 = std::min(K, k0 + C);
         // phase tables of steps k0 .. k1 (the last only when k1 < K)
@@ -1697,6 +1709,8 @@ static btl_status backward_uniform(btl_sim* s, const double* dL_dE, double* dD, 
             ++nfwd;
         }
         // reverse sweep over the segment
+        if ((e = hipEventRecord(s->tev[s->tev_used], st)) != hipSuccess)
+            return hip_fail(s, e, "timing event");
         for (int32_t k = k1; k > k0; --k) {
             aa.k = k;
             aa.top = (k == K) ? 1 : 0;
@@ -1710,6 +1724,10 @@ static btl_status backward_uniform(btl_sim* s, const double* dL_dE, double* dD, 
                 return hip_fail(s, e, "adjoint launch");
             lam_cur ^= 1;
         }
+        if ((e = hipEventRecord(s->tev[s->tev_used + 1], st)) != hipSuccess)
+            return hip_fail(s, e, "timing event");
+        s->tev_used += 2;
+        s->tev_steps += k1 - k0;
         // per-step, per-field sums of this segment: gfield[k0 .. k1 - 1]
         if ((e = launch_adj_gsum(s->gpart.p, s->adj_fields.p, nf, nblk_adj, NG, k0, k1 - k0,
                                  s->gfield.p, 0, nf, st)) != hipSuccess)
@@ -1872,6 +1890,8 @@ static btl_status backward_deferred(btl_sim* s, const double* dL_dE, double* dD,
     s->stat_fwd_steps = nfwd;
     s->stat_waves = (int32_t)cut.size() - 1;
     s->stat_snapshots = min_slots;
+    s->tev_used = 0;          // adjoint steps interleave with recomputes: not timed
+    s->tev_steps = 0;
     return final_gradients(s, s->gfield.p, K, nfT, NG, tp.dt, tp.sub, Q, tp.nq, s->adj_gmeta.p,
                            dD, dT2, dkappa, df, dgG0, st);
 }
@@ -1899,6 +1919,26 @@ extern "C" btl_status btl_get_backward_stats(const btl_sim* s, int64_t* fwd_step
     *fwd_steps = s->stat_fwd_steps;
     *groups = s->stat_waves;
     *snapshots = s->stat_snapshots;
+    return BTL_OK;
+}
+
+extern "C" btl_status btl_get_backward_timing(btl_sim* s, double* ms_adjoint,
+                                              int64_t* adjoint_steps) {
+    if (!s || !ms_adjoint || !adjoint_steps) return BTL_E_INVAL;
+    if (s->tev_used == 0)
+        return fail(s, BTL_E_INVAL, "no timed reverse sweep: the last btl_backward replayed a "
+                                    "deferred tape, or none ran");
+    hipError_t e = hipEventSynchronize(s->tev[s->tev_used - 1]);
+    if (e != hipSuccess) return hip_fail(s, e, "timing events");
+    double ms = 0.0;
+    for (int32_t i = 0; i < s->tev_used; i += 2) {
+        float t = 0.0f;
+        if ((e = hipEventElapsedTime(&t, s->tev[i], s->tev[i + 1])) != hipSuccess)
+            return hip_fail(s, e, "timing events");
+        ms += t;
+    }
+    *ms_adjoint = ms;
+    *adjoint_steps = s->tev_steps;
     return BTL_OK;
 }
 
@@ -2161,6 +2201,7 @@ extern "C" void btl_destroy(btl_sim* s) {
         if (s->stage_ev[i]) (void)hipEventDestroy(s->stage_ev[i]);
     }
     if (s->nf_host) (void)hipHostFree(s->nf_host);
+    for (hipEvent_t ev : s->tev) (void)hipEventDestroy(ev);
     delete s;
 }
 

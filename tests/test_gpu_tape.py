@@ -58,6 +58,13 @@ def _grads(cfg, prec, ckpt, weights, budget=0, grad_gG0=False, **options):
         g = torch.tensor(weights, dtype=torch.float64, device=E.device)
         out = [t.cpu().numpy() for t in sim.backward(g, grad_gG0=grad_gG0)]
         stats = btl.btl_get_backward_stats(sim._h)
+        if stats[2] == 0:
+            # a uniform tape: its adjoint steps are timed, one per forward step
+            ms, n = btl.btl_get_backward_timing(sim._h)
+            assert n == E.shape[1] - 1 and ms > 0.0
+        else:
+            with pytest.raises(btl.BtlError):
+                btl.btl_get_backward_timing(sim._h)
         return E.cpu().numpy(), out, stats
     finally:
         sim.close()

@@ -96,4 +96,6 @@ def test_null_handle_calls_are_refused():
     v64 = ctypes.c_int64()
     assert lib.btl_get_backward_stats(None, ctypes.byref(v64), ctypes.byref(v),
                                       ctypes.byref(v)) == btl.BTL_E_INVAL
+    vd = ctypes.c_double()
+    assert lib.btl_get_backward_timing(None, ctypes.byref(vd), ctypes.byref(v64)) == btl.BTL_E_INVAL
     lib.btl_destroy(None)                                  # a no-op
