@@ -283,9 +283,12 @@ btl_status btl_autotune(btl_sim *s, int32_t Q, int32_t K_probe, void *stream);
  * tile_shape 0..5 as in btl_get_launch (-1: chosen per call; 4 is the
  * single-layer shape and 5 is for 3D lattices, other choices are replaced
  * by one that fits the lattice), zc the sites per thread along z (0: whole
- * columns, at most 1024), xcd the workgroup order (0 plain, 1
- * XCD-contiguous, -1 by grid size).  Results do not depend on the launch
- * shape beyond the order of floating-point sums.
+ * columns, at most 1024), xcd the workgroup order: bit 0 the XCD-contiguous
+ * numbering (neighbouring tiles of a field on one XCD), bit 1 the fields
+ * that share a geometry interleaved block by block (so that the workgroups
+ * running together read one block's site words, membrane positions and
+ * term lists once for all those fields); 0..3, -1 by grid size.  Results do
+ * not depend on the launch shape beyond the order of floating-point sums.
  * Errors: BTL_E_INVAL (a value out of range). */
 btl_status btl_set_launch(btl_sim *s, int32_t tile_shape, int32_t zc, int32_t xcd);
 
@@ -344,7 +347,7 @@ btl_status btl_forward_noalloc(btl_sim *s, double dt, int32_t K, const double *D
  * btl_set_launch: the tile
  * shape (0 64x4, 1 32x8, 2 16x16, 3 128x2, 4 256x1, 5 runs of 256
  * consecutive sites; -1: chosen per call), the z-column length (0: whole
- * columns) and the workgroup order (0 plain, 1 XCD-contiguous; -1: by grid
+ * columns) and the workgroup order (0..3 as in btl_set_launch; -1: by grid
  * size).  Host pointers, written on success.  Makes no device call.
  * Errors: BTL_E_INVAL (a NULL argument). */
 btl_status btl_get_launch(const btl_sim *s, int32_t *tile_shape, int32_t *zc, int32_t *xcd);

@@ -105,11 +105,12 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
 
     const int32_t lb = a.xcd ? xcd_tile((int32_t)blockIdx.x, (int32_t)gridDim.x)
                              : (int32_t)blockIdx.x;
-    const int fi = a.blk_field[lb];
+    const int2 fbk = a.blk_field[lb];   // field, block of the field
+    const int fi = fbk.x;
     const FieldDesc& fd = a.fields[fi];
     const int32_t ns = fd.nsites;
     const int32_t n0 = fd.n[0], n1 = fd.n[1], n2 = fd.n[2];
-    const int32_t b = lb - fd.blk0;
+    const int32_t b = fbk.y;
     const int32_t tx = b % fd.tiles[0];
     const int32_t rb = b / fd.tiles[0];
     const int32_t ty = rb % fd.tiles[1];
@@ -436,7 +437,7 @@ __device__ __forceinline__ void adj_body(const AdjArgs& a) {
     }
     __syncthreads();
     if (threadIdx.x < NG)
-        a.gpart[((int64_t)a.slot * gridDim.x + lb) * NG + threadIdx.x] = red[threadIdx.x];
+        a.gpart[((int64_t)a.slot * gridDim.x + fd.blk0 + b) * NG + threadIdx.x] = red[threadIdx.x];
 }
 
 template <typename V, int TX, bool GG, int NQ, int NP>

@@ -28,6 +28,7 @@ struct CurvedGeom {
     };
     std::vector<Link> links;
     int64_t cv_off = 0;            // offset of the geometry's index table
+    int32_t h0 = 0, nh = 0;        // its links in the head table of the last build
 };
 
 // Collects the membrane links of g (g.link_normal and g.link_delta set).
@@ -38,10 +39,11 @@ bool curved_collect(const btl_geom& g, CurvedGeom& out);
 // single layer), time step dt (ms), spacing dx (um) and permeabilities kappa
 // [P*P] (um/ms).  idx ([6][nsites], filled with -1 by the caller) receives
 // for each link that takes the condition the index of its entry in heads
-// ({first term, number of terms}); the terms are appended to terms, with
-// population offsets and face wraps in the kernel's layout of the lattice.
-// False when the tables would pass 2^31 - 1 entries.
+// ({first term, number of terms, receiving site's direction-0 element, pull
+// direction}); the terms are appended to terms, with population offsets and
+// face wraps in the kernel's layout of the lattice.  False when the tables
+// would pass 2^31 - 1 entries.
 bool curved_terms(const CurvedGeom& cg, int nq, double dt, double dx, const double* kappa,
-                  int P, int32_t* idx, std::vector<int2>& heads, std::vector<CvTerm>& terms);
+                  int P, int32_t* idx, std::vector<int4>& heads, std::vector<CvTerm>& terms);
 
 }  // namespace btl

@@ -254,13 +254,13 @@ namespace {
 // `terms`, and its terms.
 struct Chunk {
     std::vector<int64_t> pos;
-    std::vector<int2> heads;
+    std::vector<int4> heads;
     std::vector<CvTerm> terms;
 };
 
 void terms_range(const CurvedGeom& cg, int nq, double dt, double dx, const double* kappa, int P,
                  size_t l0, size_t l1, Chunk& out) {
-    std::vector<int2>& heads = out.heads;
+    std::vector<int4>& heads = out.heads;
     std::vector<CvTerm>& terms = out.terms;
     const Ctx cx{cg, nq, lattice_eps(nq), dt / dx};
     const int64_t n0 = cg.n[0], n1 = cg.n[1];
@@ -358,14 +358,14 @@ void terms_range(const CurvedGeom& cg, int nq, double dt, double dx, const doubl
             continue;
         }
         out.pos.push_back((d - 1) * N + s);
-        heads.push_back(make_int2(first, (int32_t)terms.size() - first));
+        heads.push_back(make_int4(first, (int32_t)terms.size() - first, (int32_t)base, d));
     }
 }
 
 }  // namespace
 
 bool curved_terms(const CurvedGeom& cg, int nq, double dt, double dx, const double* kappa,
-                  int P, int32_t* idx, std::vector<int2>& heads, std::vector<CvTerm>& terms) {
+                  int P, int32_t* idx, std::vector<int4>& heads, std::vector<CvTerm>& terms) {
     // links are independent: chunks on up to 16 host threads, joined in order
     const size_t L = cg.links.size();
     size_t T = std::min<size_t>(16, std::max(1u, std::thread::hardware_concurrency()));
@@ -390,7 +390,8 @@ bool curved_terms(const CurvedGeom& cg, int nq, double dt, double dx, const doub
         Chunk& c = ch[t];
         for (size_t k = 0; k < c.heads.size(); ++k) {
             idx[c.pos[k]] = (int32_t)(h0[t] + k);
-            heads[h0[t] + k] = make_int2((int32_t)t0[t] + c.heads[k].x, c.heads[k].y);
+            heads[h0[t] + k] = make_int4((int32_t)t0[t] + c.heads[k].x, c.heads[k].y,
+                                         c.heads[k].z, c.heads[k].w);
         }
         std::copy(c.terms.begin(), c.terms.end(), terms.begin() + t0[t]);
         c = Chunk();

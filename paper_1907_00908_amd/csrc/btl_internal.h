@@ -56,8 +56,9 @@ struct FieldDesc {
     int32_t adj_fac[6];
     int64_t gm;             // offset of the geometry's membrane-position table
                             // ([6][nsites] floats, see StepArgs::gm), or -1
-    int64_t cv;             // offset of the geometry's curved-link index table
-                            // ([6][nsites] int32, see StepArgs::cvi), or -1
+    int64_t cv;             // offset of the geometry's curved-link masks
+                            // ([nsites] bytes, see StepArgs::cvm), or -1
+    int32_t cv_h0, cv_nh;   // the geometry's curved links in cvh: first entry, count
 };
 
 // One term of a curved membrane link: the arriving population is
@@ -87,7 +88,7 @@ struct AdjArgs {
     const void* fwd;        // post-collision populations entering step k-1
     const uint32_t* words;
     const FieldDesc* fields;
-    const int32_t* blk_field;
+    const int2* blk_field;    // per workgroup: field, block of the field (tile and z chunk)
     const double2* tab_prev;  // phase tables of step k-1
     const double2* tab_cur;   // phase tables of step k (face factors of its stream)
     const double* w;
@@ -114,7 +115,7 @@ struct StepArgs {
     const uint32_t* words;  // site words: bits 0-3 phase, bit 4+d-1 membrane on pull link d,
                             // bits 10+3(d-1).. the phase across that link
     const FieldDesc* fields;
-    const int32_t* blk_field;
+    const int2* blk_field;  // per workgroup: field, block of the field (tile and z chunk)
     const double* fdt;      // [K] f_k * dt
     const double* Fk;       // [K+1] sum_{m<k} f_m dt
     const double* w;        // [P] 1/tau
@@ -129,10 +130,14 @@ struct StepArgs {
     // as given (v > 0: distance from s is v; v < 0: distance is 1 + v).
     const float* gm;
     const double* kdt;      // [P*P] kappa * dt
-    // Membrane condition at any angle (curved membranes): cvi[f.cv + (d-1)*nsites
-    // + s] is -1 or the link's entry in cvh; cvh[k] = (first term, count) in cvt
-    const int32_t* cvi;
-    const int2* cvh;
+    // Membrane condition at any angle (curved membranes): bit d-1 of
+    // cvm[f.cv + s] marks the pull link d of site s as one; cvh[k] = (first
+    // term, count in cvt, receiving site's direction-0 element, pull
+    // direction d) of link k.  k_links evaluates every such link of a field
+    // into the destination state at (site, d) before the step, which then
+    // reads it there.
+    const uint8_t* cvm;
+    const int4* cvh;
     const CvTerm* cvt;
     double edx;             // eps_D * dx
     double2* tab;           // phase table of step k (T entries); the table kernel
@@ -201,6 +206,11 @@ hipError_t launch_init(int prec, void* pop, int64_t n_elem_per_dir_total,
                        const FieldDesc* h_fields, double* E, int32_t Q, int32_t K, int32_t nq,
                        hipStream_t st);
 hipError_t launch_step(int prec, int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st);
+// The arriving populations of the curved membrane links of every field into
+// the destination state (a.dst), from a.src, for step a.k (face factors from
+// a.tab); max_links bounds the links of one geometry.
+hipError_t launch_links(int prec, const StepArgs& a, int32_t max_links, int32_t n_fields,
+                        hipStream_t st);
 // initial post-collision state of the classical scheme (depends on R at t^0)
 // (fdt: the waveform table f_k dt, of which the kernel reads entry 0)
 hipError_t launch_init_classical(int prec, void* pop, const FieldDesc* h_fields, int32_t n_fields,

@@ -30,9 +30,10 @@
 // that position (Eqs. B2a_text/B2b_text, B4a-B4c) instead of the half-link
 // form (GM = true; other links keep the half-link form).  With membrane
 // normals as well (CV = true), links whose stencil for the condition at any
-// angle exists (Appendix B, Eqs. phi_1, phi_2) apply the term list the host
-// built for them: the arriving population as a weighted sum of
-// post-collision populations around the link.
+// angle exists (Appendix B, Eqs. phi_1, phi_2) take the population k_links
+// evaluated for them from the host-built term list (a weighted sum of
+// post-collision populations around the link), link-parallel, before the
+// step.
 //
 // The signal of a step is reduced deterministically: each wave writes its
 // partial sum to a per-step slot, and k_esum (one launch per 32 steps) adds
@@ -78,8 +79,9 @@ __global__ void __launch_bounds__(kBlock) k_tables(StepArgs a, int32_t nsteps) {
 
 // One step for a tile of TX x TY site columns (TX = 0: a run of kBlock
 // consecutive sites of the x-y plane), each thread walking fd.zc sites along
-// z.  Workgroup -> (field, tile) via blk_field and the field's tile counts;
-// no per-site integer division.
+// z.  Workgroup -> (field, block) via blk_field, whose order the host picks,
+// and the field's tile counts; no per-site integer division.  The signal
+// partials go to the field-major slot of the block, whatever the order.
 //
 // CL = true runs the classical LBM (Appendix A, Eq. A12) with the same
 // streaming: step 2 is skipped and step 4 adds dt w_i R M with
@@ -111,11 +113,12 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     }
     const int32_t lb = a.xcd ? xcd_tile((int32_t)blockIdx.x, (int32_t)gridDim.x)
                              : (int32_t)blockIdx.x;
-    const int fi = a.blk_field[lb];
+    const int2 fbk = a.blk_field[lb];   // field, block of the field
+    const int fi = fbk.x;
     const FieldDesc& fd = a.fields[fi];
     const int32_t ns = fd.nsites;
     const int32_t n0 = fd.n[0], n1 = fd.n[1], n2 = fd.n[2];
-    const int32_t b = lb - fd.blk0;
+    const int32_t b = fbk.y;
     const int32_t tx = b % fd.tiles[0];
     const int32_t rb = b / fd.tiles[0];
     const int32_t ty = rb % fd.tiles[1];
@@ -141,7 +144,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     const uint32_t* __restrict__ words = a.words + fd.words;
     const float* __restrict__ gmt = GM && fd.gm >= 0 ? a.gm + fd.gm : nullptr;
     // curved membranes (CV): per pull link -1 or the link's term list
-    const int32_t* __restrict__ cvp = CV && fd.cv >= 0 ? a.cvi + fd.cv : nullptr;
+    const uint8_t* __restrict__ cvmp = CV && fd.cv >= 0 ? a.cvm + fd.cv : nullptr;
     const int32_t pop = 0;
     int32_t j0, j1;
     if constexpr (TX == 0) {   // kTileRows: kBlock consecutive sites of the x-y plane
@@ -207,11 +210,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
         V g[NQ];          // g[pz] is carried, not loaded
         V own[NQ - 1];    // own[pz - 1] is carried, not loaded
         float gv[GM ? NQ - 1 : 1];   // membrane positions of the pull links
-        int32_t cv[CV ? NQ - 1 : 1];  // curved-link entries of the pull links
+        uint32_t cvm;                 // pull links under the curved rule (bit d - 1)
     };
-    auto cv_of = [](const SiteLoads& L, int d) -> int32_t {
-        if constexpr (CV) return L.cv[d - 1];
-        else return -1;
+    auto cv_of = [](const SiteLoads& L, int d) -> bool {
+        if constexpr (CV) return ((L.cvm >> (d - 1)) & 1u) != 0;
+        else return false;
     };
     auto issue = [&](int32_t j2, SiteLoads& L) {
         const int32_t s = j0 + st1 * j1 + st2 * j2;
@@ -234,10 +237,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
 #pragma unroll
             for (int d = 1; d < NQ; ++d) L.gv[d - 1] = gmt ? gmt[(d - 1) * ns + s] : 0.0f;
         }
-        if constexpr (CV) {
-#pragma unroll
-            for (int d = 1; d < NQ; ++d) L.cv[d - 1] = cvp ? cvp[(d - 1) * ns + s] : -1;
-        }
+        if constexpr (CV) L.cvm = cvmp ? (uint32_t)cvmp[s] : 0u;
     };
     // General membrane links of a site (GM): which links take the general
     // condition, and the three stencil populations of the first two of them,
@@ -248,6 +248,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
         uint32_t cvb;       // the general links that take the curved rule
         int d0, d1;
         V st0[3], st1[3];   // ghat_ibar(x + e_i), ghat_i(x - 2 e_i), ghat_ibar(x - e_i)
+        int c0;             // the first curved link
+        V cvv;              // its arriving population (left by k_links)
     };
     // plane offsets of the stencil of pull link d (relative to the site)
     auto stencil_off = [&](int d, int32_t* o) {
@@ -263,13 +265,14 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
         G.cvb = 0;
         G.d0 = 0;
         G.d1 = 0;
+        G.c0 = 0;
         if constexpr (GM) {
             const uint32_t word = L.word;
             const int p = (int)(word & 0xfu);
             const uint32_t mask = (word >> 4) & 0x3fu;
 #pragma unroll
             for (int d = 1; d < NQ; ++d) {
-                const bool cvd = cv_of(L, d) >= 0;
+                const bool cvd = cv_of(L, d);
                 if (((mask >> (d - 1)) & 1u) && (L.gv[d - 1] != 0.0f || cvd)) {
                     const int pn = (int)((word >> (10 + 3 * (d - 1))) & 0x7u);
                     if (c_tr[p * P + pn] < 1.0) {
@@ -279,6 +282,13 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 }
             }
             const int32_t sp = j0 + st1 * j1 + zs * j2;
+            if constexpr (CV) {
+                // the arriving population of the first curved link
+                if (G.cvb) {
+                    G.c0 = __builtin_ctz(G.cvb);
+                    G.cvv = dst[sp + G.c0 * ps];
+                }
+            }
             // stencils of the first two links with the theta = 0 rule
             const uint32_t g0 = G.gen & ~G.cvb;
             if (g0) {
@@ -351,26 +361,12 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                     const int d = __builtin_ctz(gen);
                     gen &= gen - 1;
                     if (CV && ((G.cvb >> d) & 1u)) {
-                        // membrane at an angle: the link's term list (weights
-                        // from the host, nodes possibly beyond periodic faces)
-                        int32_t ci = 0;
-#pragma unroll
-                        for (int k = 1; k < NQ; ++k)
-                            if (d == k) ci = cv_of(L, k);
-                        const int2 hd = a.cvh[ci];
-                        double2 r = make_double2(0.0, 0.0);
-                        for (int t = hd.x; t < hd.x + hd.y; ++t) {
-                            const CvTerm tm = a.cvt[t];
-                            double2 v = ld2(src + sp + tm.off);
-                            if (tm.wrap) {
-#pragma unroll
-                                for (int fc = 0; fc < 6; ++fc)
-                                    for (int r = (tm.wrap >> (2 * fc)) & 3; r > 0; --r)
-                                        v = cmul(v, face_fac[fc]);
-                            }
-                            r.x += tm.w * v.x;
-                            r.y += tm.w * v.y;
-                        }
+                        // membrane at an angle: k_links left the link's
+                        // arriving population at (site, d) of the
+                        // destination state before this step
+                        double2 r;
+                        if (d == G.c0) r = ld2(&G.cvv);
+                        else r = ld2(dst + sp + d * ps);
 #pragma unroll
                         for (int k = 1; k < NQ; ++k)
                             if (d == k) g[k] = r;
@@ -508,8 +504,102 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     // end of every workgroup stalled the whole step).
     const double mx = wave_sum(Mv.x), my = wave_sum(Mv.y);
     if ((threadIdx.x & 63) == 0)
-        a.partial[((size_t)(a.k % kTabSteps) * gridDim.x + lb) * (kBlock / 64) +
+        a.partial[((size_t)(a.k % kTabSteps) * gridDim.x + fd.blk0 + b) * (kBlock / 64) +
                   (threadIdx.x >> 6)] = make_double2(mx, my);
+}
+
+// The arriving population of every curved membrane link (a membrane at an
+// angle to the link, Appendix B) of every field, one thread per (link, group
+// of fields): the host-built term list of the link -- a weighted sum of
+// post-collision populations of step k around it, each times the periodic
+// face factors its node lies beyond -- evaluated in FP64 and stored at
+// (receiving site, pull direction) of the destination state, where the step
+// kernel then reads it.  Workgroup -> (run of kBlock consecutive links,
+// group of kLinkFields consecutive fields), the groups of a run on
+// consecutive workgroups.  A thread reads its link's term list once for the
+// fields of its group that share the geometry of the first of them (their
+// populations then load together, four terms at a time: a link waits two
+// memory round trips per four terms, not per term and field), and evaluates
+// any other field of the group on its own.
+constexpr int kLinkFields = 4;
+
+template <typename V>
+__global__ void __launch_bounds__(kBlock) k_links(StepArgs a, int32_t n_fields) {
+    const int32_t ngrp = (n_fields + kLinkFields - 1) / kLinkFields;
+    const int32_t grp = (int32_t)(blockIdx.x % (unsigned)ngrp);
+    const int64_t l = (int64_t)(blockIdx.x / (unsigned)ngrp) * kBlock + threadIdx.x;
+    const int32_t f0 = grp * kLinkFields, f1 = min(n_fields, f0 + kLinkFields);
+    int lead = -1;
+    for (int f = f0; f < f1; ++f)
+        if (a.fields[f].cv >= 0 && l < a.fields[f].cv_nh) {
+            lead = f;
+            break;
+        }
+    if (lead < 0) return;
+    const int64_t lead_cv = a.fields[lead].cv;
+    int nf = 0;
+    int32_t fs[kLinkFields];
+    for (int f = lead; f < f1; ++f)
+        if (a.fields[f].cv == lead_cv) fs[nf++] = f;
+    auto eval = [&](const int32_t* fl, int n) {
+        const FieldDesc& fd = a.fields[fl[0]];
+        const int4 hd = a.cvh[fd.cv_h0 + l];
+        const int tend = hd.x + hd.y;
+        double2 acc[kLinkFields];
+        const V* srcs[kLinkFields];
+        const double2* ftab[kLinkFields];
+#pragma unroll
+        for (int j = 0; j < kLinkFields; ++j) {
+            acc[j] = make_double2(0.0, 0.0);
+            const FieldDesc& fj = a.fields[fl[j < n ? j : 0]];
+            srcs[j] = static_cast<const V*>(a.src) + fj.pop + hd.z;
+            ftab[j] = a.tab + fj.tab + fj.n[0] + fj.n[1] + fj.n[2];
+        }
+        for (int t0 = hd.x; t0 < tend; t0 += 4) {
+            CvTerm tm[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (t0 + u < tend) tm[u] = a.cvt[t0 + u];
+            V pv[kLinkFields][4];
+#pragma unroll
+            for (int j = 0; j < kLinkFields; ++j)
+                if (j < n) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (t0 + u < tend) pv[j][u] = srcs[j][tm[u].off];
+                }
+#pragma unroll
+            for (int j = 0; j < kLinkFields; ++j) {
+                if (j >= n) break;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (t0 + u >= tend) break;
+                    double2 v = ld2(&pv[j][u]);
+                    if (tm[u].wrap) {
+                        for (int fc = 0; fc < 6; ++fc)
+                            for (int rp = (tm[u].wrap >> (2 * fc)) & 3; rp > 0; --rp)
+                                v = cmul(v, ftab[j][fc]);
+                    }
+                    acc[j].x += tm[u].w * v.x;
+                    acc[j].y += tm[u].w * v.y;
+                }
+            }
+        }
+        const int32_t ps = fd.n[0] * fd.n[1];
+#pragma unroll
+        for (int j = 0; j < kLinkFields; ++j)
+            if (j < n)
+                store2(static_cast<V*>(a.dst) + a.fields[fl[j]].pop + hd.z + hd.w * ps, acc[j]);
+    };
+    eval(fs, nf);
+    // the group's fields on other geometries, one by one (ragged batches)
+    for (int f = lead + 1; f < f1; ++f) {
+        const FieldDesc& fd = a.fields[f];
+        if (fd.cv >= 0 && fd.cv != lead_cv && l < fd.cv_nh) {
+            const int32_t one[1] = {f};
+            eval(one, 1);
+        }
+    }
 }
 
 // E_{k+1} = (1/N) sum of the per-wave partials of a primary field, one wave
@@ -556,6 +646,12 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
 template <typename V, int TX, bool CL, bool GM, int NQ, bool CV>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_step_w4(StepArgs a) {
+    step_body<V, TX, CL, GM, NQ, CV>(a);
+}
+// curved links in FP32 storage: held to three waves per SIMD
+template <typename V, int TX, bool CL, bool GM, int NQ, bool CV>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8)))
+k_step_w3(StepArgs a) {
     step_body<V, TX, CL, GM, NQ, CV>(a);
 }
 
@@ -621,6 +717,9 @@ static void launch_tx(const StepArgs& a, int32_t n_blocks, hipStream_t st) {
     if constexpr (std::is_same<V, float2>::value && !GM)
         hipLaunchKernelGGL((k_step_w4<V, TX, CL, GM, NQ, CV>), dim3(n_blocks), dim3(kBlock), 0, st,
                            a);
+    else if constexpr (std::is_same<V, float2>::value && CV)
+        hipLaunchKernelGGL((k_step_w3<V, TX, CL, GM, NQ, CV>), dim3(n_blocks), dim3(kBlock), 0, st,
+                           a);
     else
         hipLaunchKernelGGL((k_step<V, TX, CL, GM, NQ, CV>), dim3(n_blocks), dim3(kBlock), 0, st, a);
 }
@@ -644,7 +743,7 @@ static void launch_step_t(int shape, const StepArgs& a, int32_t n_blocks, hipStr
 template <typename V, int NQ>
 static void launch_step_q(int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st) {
     const bool gm = a.gm != nullptr;
-    const bool cv = gm && a.cvi != nullptr;
+    const bool cv = gm && a.cvm != nullptr;
     if (a.classical) {
         if (cv) launch_step_t<V, true, true, NQ, true>(shape, a, n_blocks, st);
         else if (gm) launch_step_t<V, true, true, NQ, false>(shape, a, n_blocks, st);
@@ -669,6 +768,21 @@ hipError_t launch_step(int prec, int shape, const StepArgs& a, int32_t n_blocks,
         launch_step_v<float2>(shape, a, n_blocks, st);
     else
         launch_step_v<double2>(shape, a, n_blocks, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_links(int prec, const StepArgs& a, int32_t max_links, int32_t n_fields,
+                        hipStream_t st) {
+    if (max_links <= 0 || n_fields <= 0) return hipSuccess;
+    const int64_t blocks = (int64_t)((max_links + kBlock - 1) / kBlock) *
+                           ((n_fields + kLinkFields - 1) / kLinkFields);
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    if (prec == 1)
+        hipLaunchKernelGGL(k_links<float2>, dim3((unsigned)blocks), dim3(kBlock), 0, st, a,
+                           n_fields);
+    else
+        hipLaunchKernelGGL(k_links<double2>, dim3((unsigned)blocks), dim3(kBlock), 0, st, a,
+                           n_fields);
     return hipGetLastError();
 }
 

@@ -177,14 +177,15 @@ struct btl_sim {
     // membranes at an angle (link_normal): the membrane links of each such
     // geometry, and the term tables of the constants in cv_key
     std::vector<CurvedGeom> curved;
-    DevBuf<int32_t> cvi;         // [6][nsites] per curved geometry: -1 or entry in cvh
-    DevBuf<int2> cvh;            // (first term, count) per link
+    DevBuf<uint8_t> cvm;         // [nsites] per curved geometry: its curved links (bit d-1)
+    DevBuf<int4> cvh;            // (first term, count, site element, direction) per link
     DevBuf<CvTerm> cvt;
     std::vector<double> cv_key;  // (lattice, dt, kappa) the tables hold, empty: none
-    size_t cvi_elems = 0;
+    size_t cvm_elems = 0;
+    int32_t cv_max_links = 0;    // most membrane links of one curved geometry (k_links grid)
     DevBuf<char> pop[2];
     DevBuf<FieldDesc> fields;
-    DevBuf<int32_t> blk_field;
+    DevBuf<int2> blk_field;
     DevBuf<double> steps;        // fdt [K] then Fk [K+1]
     DevBuf<double> consts;       // w [P], decay [P], trans [P*P], T2 [P], kappa [P*P], dt/T2 [P], kappa dt [P*P]
     DevBuf<double2> partial;     // per-wave signal partials of kTabSteps steps
@@ -193,7 +194,7 @@ struct btl_sim {
     // launch geometry of the adjoint steps (the forward's tile shape with
     // its own z-column length)
     DevBuf<FieldDesc> adj_fields;
-    DevBuf<int32_t> adj_blk;
+    DevBuf<int2> adj_blk;
     DevBuf<double> adj_gmeta;    // [fields][kGMeta] for the gamma G0 gradient
     // pinned staging for the per-call tables, two slots so that a call can
     // be prepared while the previous one's uploads are still queued
@@ -462,8 +463,9 @@ extern "C" btl_status btl_create(const btl_geom* geoms, int32_t n_geom, int32_t 
                 return fail(nullptr, BTL_E_INVAL,
                             "link_normal must be a finite non-zero vector on membrane links");
             }
-            h.cv_off = cg.cv_off = (int64_t)s->cvi_elems;
-            s->cvi_elems += (size_t)6 * h.nsites;
+            h.cv_off = cg.cv_off = (int64_t)s->cvm_elems;
+            s->cvm_elems += (size_t)h.nsites;
+            s->cv_max_links = std::max<int32_t>(s->cv_max_links, (int32_t)cg.links.size());
             s->curved.push_back(std::move(cg));
         }
         s->geoms.push_back(h);
@@ -571,12 +573,13 @@ struct CallPlan {
     int32_t K = 0, Q = 0, P = 0, nq = 7, msub = 1;
     double dt = 0.0;
     bool classical = false, uses_gm = false, uses_cv = false, taping = false, g_complete = true;
-    int shape = 0, xcd_on = 0;
+    int shape = 0, xcd_on = 0, order = 0;   // order: 2 = fields interleaved per block
     int32_t n_fields = 0, nblk_total = 0, nblk_adj = 0, T = 0;
     int64_t pop_elems = 0;       // V elements of one state (all fields of the call)
     std::vector<double> consts, steps, gmeta;
     std::vector<FieldDesc> fl, afl;
-    std::vector<int32_t> blk, ablk, tabf;
+    std::vector<int2> blk, ablk;
+    std::vector<int32_t> tabf;
 };
 
 // Checks of a forward's arguments that need no device call.
@@ -873,9 +876,33 @@ static btl_status make_plan(btl_sim* s, const Settings& cs, double dt, int32_t K
     p.tabf.assign(T, 0);
     for (int i = 0; i < n_fields; ++i)
         for (int e = 0; e < fl[i].n[0] + fl[i].n[1] + fl[i].n[2] + 6; ++e) p.tabf[fl[i].tab + e] = i;
-    p.blk.assign(nblk_total, 0);
-    for (int i = 0; i < n_fields; ++i)
-        for (int b = 0; b < fl[i].nblk; ++b) p.blk[fl[i].blk0 + b] = i;
+    // workgroup order: field after field, or (order bit 1) the fields that
+    // share a geometry and grid interleaved block by block, so that the
+    // workgroups running together read one block's geometry tables (site
+    // words, membrane positions and term lists, the same for every field of
+    // the geometry) once instead of once per field
+    const int32_t order = cs.xcd >= 0 ? cs.xcd : 0;
+    p.order = order & 2;
+    p.blk.clear();
+    p.blk.reserve(nblk_total);
+    if (order & 2) {
+        std::vector<bool> done(n_fields, false);
+        for (int i = 0; i < n_fields; ++i) {
+            if (done[i]) continue;
+            std::vector<int> grp;
+            for (int j = i; j < n_fields; ++j)
+                if (!done[j] && fl[j].words == fl[i].words && fl[j].nblk == fl[i].nblk &&
+                    fl[j].tiles[0] == fl[i].tiles[0] && fl[j].tiles[1] == fl[i].tiles[1]) {
+                    grp.push_back(j);
+                    done[j] = true;
+                }
+            for (int b = 0; b < fl[i].nblk; ++b)
+                for (int j : grp) p.blk.push_back(make_int2(j, b));
+        }
+    } else {
+        for (int i = 0; i < n_fields; ++i)
+            for (int b = 0; b < fl[i].nblk; ++b) p.blk.push_back(make_int2(i, b));
+    }
     // With a tape, the launch geometry of the adjoint steps: the same tile
     // shape, whole z columns when all workgroups are resident at once (cut
     // into as many pieces as still fit at once when that leaves SIMDs with
@@ -918,9 +945,10 @@ static btl_status make_plan(btl_sim* s, const Settings& cs, double dt, int32_t K
             d.blk0 = nblk_adj;
             nblk_adj += d.nblk;
         }
-        p.ablk.assign(nblk_adj, 0);
+        p.ablk.clear();
+        p.ablk.reserve(nblk_adj);
         for (int i = 0; i < n_fields; ++i)
-            for (int b = 0; b < p.afl[i].nblk; ++b) p.ablk[p.afl[i].blk0 + b] = i;
+            for (int b = 0; b < p.afl[i].nblk; ++b) p.ablk.push_back(make_int2(i, b));
         p.nblk_adj = nblk_adj;
     }
     p.n_fields = n_fields;
@@ -931,7 +959,7 @@ static btl_status make_plan(btl_sim* s, const Settings& cs, double dt, int32_t K
     // waves (tiles that share edge rows then meet in one XCD's L2); grids
     // that fit on the chip at once keep the plain order.  The autotuner
     // measures both.
-    p.xcd_on = cs.xcd >= 0 ? cs.xcd : (nblk_total > kXcdMinBlocks ? 1 : 0);
+    p.xcd_on = cs.xcd >= 0 ? (cs.xcd & 1) : (nblk_total > kXcdMinBlocks ? 1 : 0);
     return BTL_OK;
 }
 
@@ -968,14 +996,14 @@ static double memory_budget(const btl_sim* s) {
 struct CallBufs {
     char* pop[2] = {nullptr, nullptr};
     FieldDesc* fields = nullptr;
-    int32_t* blk = nullptr;
+    int2* blk = nullptr;
     double* steps = nullptr;
     double* consts = nullptr;
     double2* partial = nullptr;
     double2* tab = nullptr;
     int32_t* tabf = nullptr;
     FieldDesc* afields = nullptr;
-    int32_t* ablk = nullptr;
+    int2* ablk = nullptr;
     double* agmeta = nullptr;
 };
 
@@ -1018,7 +1046,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static size_t scratch_need(const btl_sim* s, const CallPlan& p) {
     const size_t esz = state_elem_bytes(s);
     return 2 * align256((size_t)p.pop_elems * esz) + align256(p.n_fields * sizeof(FieldDesc)) +
-           align256(p.nblk_total * sizeof(int32_t)) + align256(p.steps.size() * sizeof(double)) +
+           align256(p.nblk_total * sizeof(int2)) + align256(p.steps.size() * sizeof(double)) +
            align256(p.consts.size() * sizeof(double)) +
            align256((size_t)kTabSteps * p.nblk_total * (kBlock / 64) * sizeof(double2)) +
            align256((size_t)kTabSteps * p.T * sizeof(double2)) + align256(p.T * sizeof(int32_t));
@@ -1045,7 +1073,7 @@ static btl_status scratch_bufs(btl_sim* s, const CallPlan& p, CallBufs& b) {
     b.pop[0] = take((size_t)p.pop_elems * esz);
     b.pop[1] = take((size_t)p.pop_elems * esz);
     b.fields = reinterpret_cast<FieldDesc*>(take(p.n_fields * sizeof(FieldDesc)));
-    b.blk = reinterpret_cast<int32_t*>(take(p.nblk_total * sizeof(int32_t)));
+    b.blk = reinterpret_cast<int2*>(take(p.nblk_total * sizeof(int2)));
     b.steps = reinterpret_cast<double*>(take(p.steps.size() * sizeof(double)));
     b.consts = reinterpret_cast<double*>(take(p.consts.size() * sizeof(double)));
     b.partial = reinterpret_cast<double2*>(
@@ -1117,13 +1145,13 @@ static btl_status upload_plan(btl_sim* s, const CallPlan& p, const CallBufs& b, 
                               hipStream_t st) {
     std::vector<Upload> ups = {
         {p.fl.data(), b.fields, p.fl.size() * sizeof(FieldDesc)},
-        {p.blk.data(), b.blk, p.blk.size() * sizeof(int32_t)},
+        {p.blk.data(), b.blk, p.blk.size() * sizeof(int2)},
         {p.steps.data(), b.steps, p.steps.size() * sizeof(double)},
         {p.consts.data(), b.consts, p.consts.size() * sizeof(double)},
         {p.tabf.data(), b.tabf, p.tabf.size() * sizeof(int32_t)}};
     if (p.taping) {
         ups.push_back({p.afl.data(), b.afields, p.afl.size() * sizeof(FieldDesc)});
-        ups.push_back({p.ablk.data(), b.ablk, p.ablk.size() * sizeof(int32_t)});
+        ups.push_back({p.ablk.data(), b.ablk, p.ablk.size() * sizeof(int2)});
         ups.push_back({p.gmeta.data(), b.agmeta, p.gmeta.size() * sizeof(double)});
     }
     return upload(s, ups, grow, st);
@@ -1145,7 +1173,7 @@ static StepArgs step_args(const btl_sim* s, const CallPlan& p, const CallBufs& b
     a.trans = b.consts + 2 * P;
     a.rdt = b.consts + 3 * P + 2 * P * P;
     a.gm = p.uses_gm ? s->gm.p : nullptr;
-    a.cvi = p.uses_cv ? s->cvi.p : nullptr;
+    a.cvm = p.uses_cv ? s->cvm.p : nullptr;
     a.cvh = s->cvh.p;
     a.cvt = s->cvt.p;
     a.kdt = b.consts + 4 * P + 2 * P * P;
@@ -1192,6 +1220,9 @@ static btl_status enqueue_forward(btl_sim* s, const CallPlan& p, const CallBufs&
         a.src = b.pop[k & 1];
         a.dst = b.pop[(k + 1) & 1];
         a.k = k;
+        if (p.uses_cv &&
+            (err = launch_links(s->prec, a, s->cv_max_links, p.n_fields, q)) != hipSuccess)
+            return hip_fail(s, err, "membrane link launch");
         if ((err = launch_step(s->prec, p.shape, a, p.nblk_total, q)) != hipSuccess)
             return hip_fail(s, err, "step launch");
         if ((k + 1) % kTabSteps == 0 || k + 1 == K) {
@@ -1234,11 +1265,11 @@ static btl_status run_forward(btl_sim* s, const CallPlan& p, const CallBufs& b, 
     key.ckpt = ckpt ? C : 0;
     key.scheme = p.classical ? 1 : 0;
     key.nq = p.nq;
-    key.xcd = p.xcd_on;
+    key.xcd = p.xcd_on | p.order;
     key.fields = field_hash(p.fl, p.classical);
     const void* ptrs[] = {b.pop[0], b.pop[1], b.fields, b.blk, b.steps, b.consts, b.partial,
                           b.tab, b.tabf, s->E_int.p, ckpt, s->words.p, s->gm.p, s->nf_dev,
-                          s->cvi.p, s->cvh.p, s->cvt.p};
+                          s->cvm.p, s->cvh.p, s->cvt.p};
     static_assert(sizeof(ptrs) / sizeof(ptrs[0]) <= sizeof(key.ptr) / sizeof(key.ptr[0]),
                   "graph key too small");
     for (size_t i = 0; i < sizeof(ptrs) / sizeof(ptrs[0]); ++i) key.ptr[i] = ptrs[i];
@@ -1297,38 +1328,59 @@ static btl_status final_magnetization(btl_sim* s, const CallPlan& p, const CallB
 // permeabilities (built when these differ from the tables' constants).
 // Work still queued on st may read the old tables: it finishes first.
 // Without may_alloc the tables must fit the device buffers they have.
-static btl_status ensure_curved(btl_sim* s, const CallPlan& p, const double* kappa, hipStream_t st,
+// The fields' ranges in the head table of the current build.
+static void curved_ranges(const btl_sim* s, CallPlan& p) {
+    for (FieldDesc& d : p.fl) {
+        d.cv_h0 = d.cv_nh = 0;
+        for (const CurvedGeom& cg : s->curved)
+            if (d.cv >= 0 && cg.cv_off == d.cv) {
+                d.cv_h0 = cg.h0;
+                d.cv_nh = cg.nh;
+            }
+    }
+}
+
+static btl_status ensure_curved(btl_sim* s, CallPlan& p, const double* kappa, hipStream_t st,
                                 bool may_alloc) {
     if (!p.uses_cv) return BTL_OK;
     std::vector<double> key = {(double)p.nq, p.dt};
     key.insert(key.end(), kappa, kappa + p.P * p.P);
     if (key.size() == s->cv_key.size() &&
-        memcmp(key.data(), s->cv_key.data(), key.size() * sizeof(double)) == 0)
+        memcmp(key.data(), s->cv_key.data(), key.size() * sizeof(double)) == 0) {
+        curved_ranges(s, p);
         return BTL_OK;
-    std::vector<int32_t> idx(s->curved.empty() ? 0 : (size_t)s->curved.back().cv_off +
-                                                         6 * s->curved.back().comp.size(), -1);
-    std::vector<int2> heads;
+    }
+    std::vector<uint8_t> mask(s->cvm_elems, 0);
+    std::vector<int4> heads;
     std::vector<CvTerm> terms;
-    for (const CurvedGeom& cg : s->curved)
-        if (!curved_terms(cg, p.nq, p.dt, s->dx, kappa, p.P, idx.data() + cg.cv_off, heads,
-                          terms))
+    for (CurvedGeom& cg : s->curved) {
+        const size_t ns = cg.comp.size();
+        std::vector<int32_t> idx(6 * ns, -1);
+        cg.h0 = (int32_t)heads.size();
+        if (!curved_terms(cg, p.nq, p.dt, s->dx, kappa, p.P, idx.data(), heads, terms))
             return fail(s, BTL_E_UNSUPPORTED, "more than 2^31 - 1 membrane terms");
-    if (heads.empty()) heads.push_back(make_int2(0, 0));
+        cg.nh = (int32_t)heads.size() - cg.h0;
+        for (int d = 0; d < 6; ++d)
+            for (size_t j = 0; j < ns; ++j)
+                if (idx[d * ns + j] >= 0) mask[cg.cv_off + j] |= (uint8_t)(1u << d);
+    }
+    curved_ranges(s, p);
+    if (heads.empty()) heads.push_back(make_int4(0, 0, 0, 0));
     if (terms.empty()) terms.push_back(CvTerm{0.0, 0, 0});
-    if (!may_alloc && (idx.size() > s->cvi.cap || heads.size() > s->cvh.cap ||
+    if (!may_alloc && (mask.size() > s->cvm.cap || heads.size() > s->cvh.cap ||
                        terms.size() > s->cvt.cap))
         return fail(s, BTL_E_UNSUPPORTED,
                     "the membrane term tables for these constants need device memory: run "
                     "btl_forward with them first");
     s->cv_key.clear();
     hipError_t e = hipStreamSynchronize(st);
-    if (e == hipSuccess) e = s->cvi.ensure(idx.size());
+    if (e == hipSuccess) e = s->cvm.ensure(mask.size());
     if (e == hipSuccess) e = s->cvh.ensure(heads.size());
     if (e == hipSuccess) e = s->cvt.ensure(terms.size());
     if (e == hipSuccess)
-        e = hipMemcpy(s->cvi.p, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        e = hipMemcpy(s->cvm.p, mask.data(), mask.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(s->cvh.p, heads.data(), heads.size() * sizeof(int2), hipMemcpyHostToDevice);
+        e = hipMemcpy(s->cvh.p, heads.data(), heads.size() * sizeof(int4), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(s->cvt.p, terms.data(), terms.size() * sizeof(CvTerm),
                       hipMemcpyHostToDevice);
@@ -1604,7 +1656,7 @@ static void plan_reversal(int32_t a, int32_t b, int sa, std::vector<int>& free,
 }
 
 static AdjArgs adj_args(const btl_sim* s, const Settings& cs, const FieldDesc* afields,
-                        const int32_t* ablk, const double* consts, int32_t nblk_adj,
+                        const int2* ablk, const double* consts, int32_t nblk_adj,
                         const double* dL_dE, double dt, int32_t K, int NG, bool gradg, int nq) {
     const int32_t P = s->n_phase;
     AdjArgs aa;
@@ -1971,6 +2023,7 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
     for (size_t k = 0; k < f.size(); ++k) f[k] = saved.f.empty() ? 1.0 : saved.f[k % saved.f.size()];
     // a launch this process already chose for the same shape of workload
     std::string key;
+    bool shared_geom = false, geom_tables = false;
     {
         Settings cs = s->set;
         cs.tile_shape = -1;
@@ -1982,6 +2035,15 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
                             f.data(), false, p)) != BTL_OK)
             return rc;
         key = tune_key(s, p);
+        // fields sharing a geometry (several q-samples, or image fields):
+        // the field-interleaved orders are candidates too
+        for (int i = 0; i < p.n_fields && !shared_geom; ++i)
+            for (int j = i + 1; j < p.n_fields; ++j)
+                if (p.fl[j].words == p.fl[i].words) {
+                    shared_geom = true;
+                    break;
+                }
+        geom_tables = p.uses_gm || p.uses_cv;
         std::lock_guard<std::mutex> lk(g_tune_mu);
         for (const TuneEntry& t : g_tune_cache)
             if (t.key == key) {
@@ -2044,25 +2106,83 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
     else
         shapes.assign(kShapes3D, kShapes3D + kShapeCount3D);
     // shape, z-column length and workgroup order are searched jointly: the
-    // best column length differs between the two orders
+    // best column length differs between the orders.  Orders: bit 0 the
+    // XCD-contiguous numbering, bit 1 the fields of a geometry interleaved
+    // block by block (searched with the others when the geometry carries
+    // membrane positions or term lists, which every field reads; otherwise
+    // tried on the best shape and column length found)
+    const int n_orders = shared_geom && geom_tables ? 4 : 2;
+    struct Cand {
+        float ms;
+        int sh, zc, xo;
+    };
+    std::vector<Cand> timed;
+    auto consider = [&](int sh, int zc, int xo) -> btl_status {
+        s->set.tile_shape = sh;
+        s->set.zc = zc;
+        s->set.xcd = xo;
+        float ms = 0.0f;
+        const btl_status r = time_probe(&ms);
+        if (r == BTL_OK) timed.push_back({ms, sh, zc, xo});
+        if (r == BTL_OK && (best < 0.0f || ms < best)) {
+            best = ms;
+            best_shape = sh;
+            best_zc = zc;
+            best_xcd = xo;
+        }
+        return r;
+    };
     for (int sh : shapes) {
         for (int zc : zcs) {
-            for (int xo = 0; xo < 2 && rc == BTL_OK; ++xo) {
-                s->set.tile_shape = sh;
-                s->set.zc = zc;
-                s->set.xcd = xo;
-                float ms = 0.0f;
-                if ((rc = time_probe(&ms)) != BTL_OK) break;
-                if (best < 0.0f || ms < best) {
-                    best = ms;
-                    best_shape = sh;
-                    best_zc = zc;
-                    best_xcd = xo;
-                }
-            }
+            for (int xo = 0; xo < n_orders && rc == BTL_OK; ++xo) rc = consider(sh, zc, xo);
             if (rc != BTL_OK) break;
         }
         if (rc != BTL_OK) break;
+    }
+    if (rc == BTL_OK && shared_geom && n_orders == 2) {
+        const int sh = best_shape, zc = best_zc;
+        for (int xo = 2; xo < 4 && rc == BTL_OK; ++xo) rc = consider(sh, zc, xo);
+    }
+    // the few candidates within 4 % of the best are timed again, in turns,
+    // and the fastest of all their timings wins: single probes of a busy
+    // device differ by a few per cent, as much as these candidates do
+    if (rc == BTL_OK && timed.size() > 1) {
+        std::sort(timed.begin(), timed.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+        std::vector<Cand> top;
+        for (const Cand& c : timed)
+            if (top.size() < 4 && c.ms <= 1.04f * timed[0].ms) top.push_back(c);
+        if (top.size() > 1) {
+            std::vector<float> bestv(top.size(), -1.0f);
+            for (int r = 0; r < kTuneReps && rc == BTL_OK; ++r)
+                for (size_t i = 0; i < top.size() && rc == BTL_OK; ++i) {
+                    s->set.tile_shape = top[i].sh;
+                    s->set.zc = top[i].zc;
+                    s->set.xcd = top[i].xo;
+                    (void)hipEventRecord(e0, st);
+                    rc = forward_entry(s, saved.dt, K_probe, saved.D.data(), saved.T2.data(),
+                                       saved.kappa.data(), Qr, saved.q_geom.data(),
+                                       saved.gG0.data(), f.data(), s->tune_E.p, nullptr, 0,
+                                       stream);
+                    if (rc != BTL_OK) break;
+                    (void)hipEventRecord(e1, st);
+                    if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+                        rc = hip_fail(s, e, "autotune timing");
+                        break;
+                    }
+                    float ms = 0.0f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    if (bestv[i] < 0.0f || ms < bestv[i]) bestv[i] = ms;
+                }
+            if (rc == BTL_OK) {
+                size_t w = 0;
+                for (size_t i = 0; i < top.size(); ++i)
+                    if (std::min(bestv[i], top[i].ms) < std::min(bestv[w], top[w].ms)) w = i;
+                best = std::min(bestv[w], top[w].ms);
+                best_shape = top[w].sh;
+                best_zc = top[w].zc;
+                best_xcd = top[w].xo;
+            }
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -2100,7 +2220,7 @@ extern "C" btl_status btl_set_launch(btl_sim* s, int32_t tile_shape, int32_t zc,
     if (tile_shape < -1 || tile_shape >= kTileCount)
         return fail(s, BTL_E_INVAL, "tile_shape must be -1 or 0..5");
     if (zc < 0 || zc > kMaxZc) return fail(s, BTL_E_INVAL, "zc must be in 0..1024");
-    if (xcd < -1 || xcd > 1) return fail(s, BTL_E_INVAL, "xcd must be -1, 0 or 1");
+    if (xcd < -1 || xcd > 3) return fail(s, BTL_E_INVAL, "xcd must be -1 or 0..3");
     s->set.tile_shape = tile_shape;
     s->set.zc = zc;
     s->set.xcd = xcd;
@@ -2193,7 +2313,7 @@ extern "C" void btl_destroy(btl_sim* s) {
     s->gfield.release();
     s->tab.release();
     s->tab_field.release();
-    s->cvi.release();
+    s->cvm.release();
     s->cvh.release();
     s->cvt.release();
     for (int i = 0; i < 2; ++i) {

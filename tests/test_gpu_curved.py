@@ -150,13 +150,13 @@ def test_curved_tables_follow_the_constants():
         sim.close()
 
 
-@pytest.mark.parametrize("shape,zc", [(0, 0), (1, 3), (2, 0), (3, 7), (5, 1)])
-def test_curved_every_launch_shape(shape, zc):
+@pytest.mark.parametrize("shape,zc,order", [(0, 0, 1), (1, 3, 3), (2, 0, 2), (3, 7, 1), (5, 1, 3)])
+def test_curved_every_launch_shape(shape, zc, order):
     btl = _gpu()
     cfg = _strong(w.make_config("cfg2", n=20, K=120, membranes="curved"))
     Eo, _ = oracle.simulate_config(cfg, threads=8)
-    print(f"GPU curved shape {shape} zc {zc}", flush=True)
-    sim = btl.Simulator(cfg["geoms"], cfg["bc"], "f32", launch=(shape, zc, 1))
+    print(f"GPU curved shape {shape} zc {zc} order {order}", flush=True)
+    sim = btl.Simulator(cfg["geoms"], cfg["bc"], "f32", launch=(shape, zc, order))
     try:
         E = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"],
                         cfg["q_geom"]).cpu().numpy()

@@ -129,6 +129,18 @@ def test_ragged_multi_geometry_batch(prec):
     cfg["gG0"], cfg["q_geom"] = cfg["gG0"][sel], cfg["q_geom"][sel]
     Eg, _, Eo, _ = _run_both(cfg, prec)
     _check(Eg, Eo, prec, "cfg3b ragged")
+    # the q-samples of each geometry interleaved block by block (groups of
+    # unequal sizes and grids), in both XCD orders
+    btl = _gpu()
+    for order in (2, 3):
+        print(f"GPU ragged batch, workgroup order {order}", flush=True)
+        sim = btl.Simulator(cfg["geoms"], cfg["bc"], prec, launch=(5, 4, order))
+        try:
+            E = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"],
+                            cfg["q_geom"]).cpu().numpy()
+        finally:
+            sim.close()
+        _check(E, Eo, prec, f"cfg3b ragged, order {order}")
 
 
 def test_three_phase_cells_ogse():
@@ -173,7 +185,7 @@ def test_autotune_keeps_results():
         assert btl.btl_get_launch(sim._h) == (-1, 0, -1)   # defaults before tuning
         btl.btl_autotune(sim._h, 3, 5, torch.cuda.current_stream().cuda_stream)
         tile, zc, xcd = btl.btl_get_launch(sim._h)
-        assert tile in (0, 1, 2, 3, 5) and 0 <= zc < 24 and xcd in (0, 1)
+        assert tile in (0, 1, 2, 3, 5) and 0 <= zc < 24 and xcd in (0, 1, 2, 3)
         E2 = sim.forward(*args).cpu().numpy()
     finally:
         sim.close()
@@ -212,21 +224,24 @@ def _shape_ref_grads(btl, cfg, prec, args, g, K):
 
 
 @pytest.mark.parametrize("shape,zc,xcd", [(5, 0, 0), (5, 3, 1), (2, 4, 0), (1, 0, 1),
-                                          (0, 2, 1), (0, 0, 0), (3, 3, 1), (3, 0, 0)])
+                                          (0, 2, 1), (0, 0, 0), (3, 3, 1), (3, 0, 0),
+                                          (5, 3, 3), (3, 0, 2), (0, 2, 2), (1, 4, 3)])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_every_tile_shape_matches_oracle(shape, zc, xcd, prec):
     # each launch shape (5: runs of 256 consecutive sites of the x-y plane,
     # 3: 128x2, 2: 16x16, 1: 32x8, 0: 64x4), whole or chunked z columns, in
     # plain and XCD-contiguous workgroup order (xcd_tile renumbers the
-    # workgroups), on a ragged lattice with mirrored faces, oblique gradients
-    # (image fields) and membranes: E and M_final against the oracle, and
-    # the adjoint (in the same workgroup order) against the default launch
+    # workgroups), field after field or the image fields of a q-sample
+    # interleaved block by block (order bit 1), on a ragged lattice with
+    # mirrored faces, oblique gradients (image fields) and membranes: E and
+    # M_final against the oracle, and the adjoint (in the same XCD order)
+    # against the default launch
     btl = _gpu()
     import torch
     cfg = _shape_case()
     print(f"GPU launch shape={shape} zc={zc} xcd={xcd} prec={prec}", flush=True)
     sim = btl.Simulator(cfg["geoms"], cfg["bc"], prec, launch=(shape, zc, xcd),
-                        adjoint_launch=(-1, xcd))
+                        adjoint_launch=(-1, xcd & 1))
     try:
         args = (cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"], cfg["gG0"])
         E, M = sim.forward(*args, want_M=True)
