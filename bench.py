@@ -99,16 +99,25 @@ def q_sites(cfg) -> int:
     return sum(cfg["geoms"][int(g)].comp.size for g in cfg["q_geom"])
 
 
-def tune_probe(cfg, tune_q, classical=False):
-    """q-samples and steps of the autotuner's probe: at most tune_q q-samples
-    and about 1.2e9 field sites (so that large lattices probe on fewer
-    q-samples), and about 6e9 field-site updates per candidate, 4 to 40
-    steps (short probes time the forward's set-up as much as its steps)."""
+TUNE_Q = 256
+
+
+def tune_probe(cfg, tune_q, classical=False, prec="f32"):
+    """q-samples and steps of the autotuner's probe: the first tune_q
+    q-samples, of which the library probes one q-wave (those whose two
+    states fit 85 % of device memory), and about 6e9 field-site updates per
+    candidate over that wave, 3 to 40 steps (short probes time the forward's
+    set-up as much as its steps)."""
+    import torch
     Q = len(cfg["gG0"])
-    per_q = field_sites(cfg, classical, [0])
-    Qt = max(1, min(Q, tune_q, int(1.2e9 // per_q)))
-    fst = field_sites(cfg, classical, range(Qt))
-    return Qt, max(4, min(40, int(6e9 / fst)))
+    Qt = max(1, min(Q, tune_q))
+    nq = 5 if cfg.get("lattice", 0) == 1 else 7
+    esz = 8 if prec == "f32" else 16
+    mem = (torch.cuda.get_device_properties(0).total_memory if torch.cuda.is_available()
+           else 288e9)
+    wave = 0.85 * mem / (2 * nq * esz)          # field sites of one q-wave
+    fst = min(field_sites(cfg, classical, range(Qt)), wave)
+    return Qt, max(3, min(40, int(6e9 / fst)))
 
 
 def log(msg):
@@ -251,7 +260,7 @@ def bench_adjoint(btl, torch, args):
     sim = btl.Simulator(cfg["geoms"], cfg["bc"], args.prec)
     try:
         stream = torch.cuda.current_stream().cuda_stream
-        Qt, probe = tune_probe(cfg, 32)
+        Qt, probe = tune_probe(cfg, TUNE_Q, prec=args.prec)
         sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:2], cfg["gG0"][:Qt],
                     cfg["q_geom"][:Qt])
         if args.adj_launch:
@@ -344,8 +353,8 @@ def main():
     ap.add_argument("--launch", default=None,
                     help="tile,zc,xcd: fix the step kernel's launch (btl_set_launch) "
                          "instead of autotuning")
-    ap.add_argument("--tune-q", type=int, default=32,
-                    help="q-samples the autotuner probes (one q-wave)")
+    ap.add_argument("--tune-q", type=int, default=TUNE_Q,
+                    help="q-samples the autotuner may probe (it takes one q-wave of them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -434,7 +443,7 @@ def main():
     # read nq complex populations + write nq, per field site
     bpf = (BYTES_PER_FIELD_SITE_F32 if args.prec == "f32" else BYTES_PER_FIELD_SITE_F64) * nq // 7
     stream = torch.cuda.current_stream().cuda_stream
-    Qt, probe = tune_probe(cfg, max(1, args.tune_q), args.scheme == "classical")
+    Qt, probe = tune_probe(cfg, max(1, args.tune_q), args.scheme == "classical", args.prec)
     tq = list(range(Qt))
     sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:2], cfg["gG0"][tq],
                 cfg["q_geom"][tq])
@@ -442,9 +451,9 @@ def main():
         t, z, x = (int(v) for v in args.launch.split(","))
         btl.btl_set_launch(sim._h, t, z, x)
     elif not args.no_autotune:
-        # launch shape chosen by timed probes on the first Qt q-samples (one
-        # q-wave; setup, untimed)
-        log(f"autotune ({Qt} q-samples, {probe} steps per candidate)")
+        # launch shape chosen by timed probes on the first q-wave of the
+        # batch (setup, untimed)
+        log(f"autotune (one q-wave of the first {Qt} q-samples, {probe} steps per candidate)")
         btl.btl_autotune(sim._h, Qt, probe, stream)
     launch = dict(zip(("tile", "zc", "xcd"), btl.btl_get_launch(sim._h)))
     fwd = forward_fn(sim, cfg, K)
@@ -502,7 +511,7 @@ def main():
             one()
             if not args.no_autotune:
                 c1 = dict(cfg, gG0=cfg["gG0"][:1], q_geom=cfg["q_geom"][:1])
-                btl.btl_autotune(sim64._h, 1, tune_probe(c1, 1)[1], stream)
+                btl.btl_autotune(sim64._h, 1, tune_probe(c1, 1, prec="f64")[1], stream)
                 one()
             ms1, _, _ = timed(torch, one, args.reps)
             v1 = cfg["geoms"][int(cfg["q_geom"][0])].comp.size * K / (ms1 * 1e-3)
@@ -513,7 +522,7 @@ def main():
                                             "what": "FP64 storage, q-sample 0 alone, autotuned "
                                                     "launch, median of reps"}
             allq = forward_fn(sim64, cfg, K)
-            Qt64, probe64 = tune_probe(cfg, 8)
+            Qt64, probe64 = tune_probe(cfg, 8, prec="f64")
             sim64.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:2],
                           cfg["gG0"][:Qt64], cfg["q_geom"][:Qt64])
             if not args.no_autotune:

@@ -266,7 +266,8 @@ btl_status btl_set_scheme(btl_sim *s, int32_t scheme);
 
 /* Choose the launch shape (workgroup tile, z-column length and workgroup
  * order) of this simulator by timing every combination on the inputs of
- * the last btl_forward (its first Q q-samples, K_probe steps, waveform
+ * the last btl_forward (its first Q q-samples, at most those whose states
+ * fit device memory together -- one q-wave --, K_probe steps, waveform
  * repeated if shorter) and keeping the fastest.  Synchronizes the stream.
  * The probes are forwards of their own: the adjoint tape of an earlier
  * taped btl_forward is discarded.  The choice is remembered for the life of

@@ -657,6 +657,13 @@ hipError_t launch_adj_gsum(const double* gpart, const FieldDesc* d_fields, int32
     return hipGetLastError();
 }
 
+__global__ void k_mark() {}
+
+hipError_t launch_mark(hipStream_t st) {
+    hipLaunchKernelGGL(k_mark, dim3(1), dim3(64), 0, st);
+    return hipGetLastError();
+}
+
 hipError_t launch_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P,
                             double dt, double dx, const double* w, const double* T2,
                             const double* kappa, double* dD, double* dT2, double* dkappa,

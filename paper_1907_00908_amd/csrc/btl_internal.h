@@ -195,6 +195,10 @@ hipError_t launch_adj_gsum(const double* gpart, const FieldDesc* d_fields, int32
 // dgG0 (device [Q][3] or NULL) needs gmeta (device [n_fields][kGMeta]) and
 // the per-step angles fdt [K] and F [K].  A non-finite gradient sets
 // *nonfinite (device-visible, may be NULL).
+// An empty one-wave kernel.  A timing event recorded right after it takes
+// its timestamp from a launch that lasts a few microseconds, whatever time
+// the runtime gives a marker (the end of the previous launch or its start).
+hipError_t launch_mark(hipStream_t st);
 hipError_t launch_adj_final(const double* gfield, int32_t K, int32_t n_fields, int32_t P,
                             double dt, double dx, const double* w, const double* T2,
                             const double* kappa, double* dD, double* dT2, double* dkappa,

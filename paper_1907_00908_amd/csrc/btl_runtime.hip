@@ -1760,8 +1760,11 @@ static btl_status backward_uniform(btl_sim* s, const double* dL_dE, double* dD, 
                 return hip_fail(s, e, "recompute launch");
             ++nfwd;
         }
-        // reverse sweep over the segment
-        if ((e = hipEventRecord(s->tev[s->tev_used], st)) != hipSuccess)
+        // reverse sweep over the segment, bracketed by timing events (each
+        // after an empty launch, so that the interval holds the adjoint
+        // launches alone)
+        if ((e = launch_mark(st)) != hipSuccess ||
+            (e = hipEventRecord(s->tev[s->tev_used], st)) != hipSuccess)
             return hip_fail(s, e, "timing event");
         for (int32_t k = k1; k > k0; --k) {
             aa.k = k;
@@ -1776,7 +1779,8 @@ static btl_status backward_uniform(btl_sim* s, const double* dL_dE, double* dD, 
                 return hip_fail(s, e, "adjoint launch");
             lam_cur ^= 1;
         }
-        if ((e = hipEventRecord(s->tev[s->tev_used + 1], st)) != hipSuccess)
+        if ((e = launch_mark(st)) != hipSuccess ||
+            (e = hipEventRecord(s->tev[s->tev_used + 1], st)) != hipSuccess)
             return hip_fail(s, e, "timing event");
         s->tev_used += 2;
         s->tev_steps += k1 - k0;
@@ -2017,8 +2021,20 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
     if (!s->last.valid) return fail(s, BTL_E_INVAL, "btl_autotune replays the last btl_forward: call it first");
     if (K_probe < 1) return fail(s, BTL_E_INVAL, "K_probe must be >= 1");
     const btl_sim::SimLast saved = s->last;
-    const int32_t Qr = std::min<int32_t>(Q > 0 ? Q : (int32_t)saved.q_geom.size(),
-                                         (int32_t)saved.q_geom.size());
+    int32_t Qr = std::min<int32_t>(Q > 0 ? Q : (int32_t)saved.q_geom.size(),
+                                   (int32_t)saved.q_geom.size());
+    // the probe covers at most one q-wave: a batch whose states exceed the
+    // budget runs wave after wave in one launch shape, and probes of a part
+    // of a wave rank the shapes differently (32 q-samples of a 128-sample
+    // wave put the wave's fastest shape 8 % behind)
+    if (Qr > 0) {
+        const size_t esz = state_elem_bytes(s);
+        std::vector<double> per_q(Qr);
+        for (int32_t q = 0; q < Qr; ++q)
+            per_q[q] = 2.0 * (double)q_state_elems(s, s->set, saved.q_geom[q],
+                                                   saved.gG0.data() + 3 * q, false) * esz;
+        Qr = wave_bounds(per_q, memory_budget(s))[1];
+    }
     std::vector<double> f((size_t)K_probe * s->set.msub);
     for (size_t k = 0; k < f.size(); ++k) f[k] = saved.f.empty() ? 1.0 : saved.f[k % saved.f.size()];
     // a launch this process already chose for the same shape of workload
@@ -2099,6 +2115,7 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
         return BTL_OK;
     };
     int best_shape = -1, best_zc = 0, best_xcd = 0;
+    const bool verbose = getenv("BTLBM_VERBOSE") != nullptr;
     rc = BTL_OK;
     std::vector<int> shapes;
     if (s->set.nq == 5)
@@ -2124,6 +2141,8 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
         float ms = 0.0f;
         const btl_status r = time_probe(&ms);
         if (r == BTL_OK) timed.push_back({ms, sh, zc, xo});
+        if (r == BTL_OK && verbose)
+            fprintf(stderr, "btlbm autotune: shape %d, z-column %d, order %d: %.3f ms\n", sh, zc, xo, ms);
         if (r == BTL_OK && (best < 0.0f || ms < best)) {
             best = ms;
             best_shape = sh;
@@ -2173,6 +2192,10 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
                     (void)hipEventElapsedTime(&ms, e0, e1);
                     if (bestv[i] < 0.0f || ms < bestv[i]) bestv[i] = ms;
                 }
+            if (rc == BTL_OK && verbose)
+                for (size_t i = 0; i < top.size(); ++i)
+                    fprintf(stderr, "btlbm autotune: again shape %d, z-column %d, order %d: %.3f ms\n",
+                            top[i].sh, top[i].zc, top[i].xo, bestv[i]);
             if (rc == BTL_OK) {
                 size_t w = 0;
                 for (size_t i = 0; i < top.size(); ++i)
@@ -2200,7 +2223,7 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache.push_back({key, best_shape, best_zc, best_xcd});
     }
-    if (getenv("BTLBM_VERBOSE"))
+    if (verbose)
         fprintf(stderr, "btlbm autotune: tile shape %d, z-column %d, xcd order %d (%.3f ms per probe)\n",
                 best_shape, best_zc, best_xcd, best);
     return BTL_OK;

@@ -36,7 +36,7 @@ def _forward_autotuned(btl, cfg, K, want_M=False, keep_M=()):
     sim = btl.Simulator(cfg["geoms"], cfg["bc"], "f32", lattice=cfg.get("lattice", 0))
     try:
         stream = torch.cuda.current_stream().cuda_stream
-        Qt, probe = bench.tune_probe(cfg, 32)
+        Qt, probe = bench.tune_probe(cfg, bench.TUNE_Q)
         sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:2],
                     cfg["gG0"][:Qt], cfg["q_geom"][:Qt])
         btl.btl_autotune(sim._h, Qt, probe, stream)
