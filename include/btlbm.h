@@ -270,7 +270,9 @@ btl_status btl_set_scheme(btl_sim *s, int32_t scheme);
  * fit device memory together -- one q-wave --, K_probe steps, waveform
  * repeated if shorter) and keeping the fastest.  Synchronizes the stream.
  * The probes are forwards of their own: the adjoint tape of an earlier
- * taped btl_forward is discarded.  The choice is remembered for the life of
+ * taped btl_forward is discarded, and the device memory of the probes'
+ * states is freed before the call returns (the next forward allocates its
+ * own).  The choice is remembered for the life of
  * the process, keyed by device, storage precision, lattice, scheme and the
  * sizes of the fields: a later call for the same shape of workload (on any
  * simulator) takes it without timing.  Without autotuning (or

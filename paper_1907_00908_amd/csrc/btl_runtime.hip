@@ -1448,6 +1448,23 @@ static std::vector<int32_t> wave_bounds(const std::vector<double>& per_q, double
     return cut;
 }
 
+// Free the population states, checkpoints and adjoint states of earlier
+// calls, and the cached graphs that capture their addresses (the next call
+// allocates what it needs).
+static void drop_states(btl_sim* s) {
+    for (GraphSlot& g : s->graphs)
+        if (g.exec) {
+            (void)hipGraphExecDestroy(g.exec);
+            g.exec = nullptr;
+        }
+    s->seg.release();
+    s->ckpt.release();
+    s->pop[0].release();
+    s->pop[1].release();
+    s->lam[0].release();
+    s->lam[1].release();
+}
+
 // Report (and clear) a non-finite value left by earlier work on the device.
 static btl_status take_nonfinite(btl_sim* s) {
     if (s->nf_host && __atomic_load_n(s->nf_host, __ATOMIC_ACQUIRE) != 0) {
@@ -1820,17 +1837,7 @@ static btl_status backward_deferred(btl_sim* s, const double* dL_dE, double* dD,
     for (int32_t i = 0; i < nfT; ++i)
         per_q[(int)G.gmeta[(size_t)i * kGMeta]] += (double)G.nq * G.fl[i].nsites * esz;
     // drop the states and graphs of earlier calls: the sweep sizes its own
-    for (GraphSlot& g : s->graphs)
-        if (g.exec) {
-            (void)hipGraphExecDestroy(g.exec);
-            g.exec = nullptr;
-        }
-    s->seg.release();
-    s->ckpt.release();
-    s->pop[0].release();
-    s->pop[1].release();
-    s->lam[0].release();
-    s->lam[1].release();
+    drop_states(s);
     const double B = memory_budget(s);
     // groups sized for a repetition number of at most two where possible
     // (beta(s, 2) >= K), each q-sample on its own otherwise
@@ -2210,6 +2217,9 @@ extern "C" btl_status btl_autotune(btl_sim* s, int32_t Q, int32_t K_probe, void*
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     s->last = saved;
+    // the probes' states span a whole q-wave: freed, so that memory the
+    // caller allocates next (outputs, M_final) does not compete with them
+    drop_states(s);
     if (rc != BTL_OK) {
         s->set.tile_shape = -1;
         s->set.zc = 0;

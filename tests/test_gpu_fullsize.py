@@ -29,23 +29,27 @@ def _config(name):
     return _CFG[name]
 
 
-def _forward_autotuned(btl, cfg, K, want_M=False, keep_M=()):
+def _forward_autotuned(btl, cfg, K, want_M=False, keep_M=(), launch=None):
     """Forward of all q-samples in the benchmark's launch: autotuned with the
-    benchmark's probe (bench.tune_probe)."""
+    benchmark's probe (bench.tune_probe), or the given launch."""
     import torch
     sim = btl.Simulator(cfg["geoms"], cfg["bc"], "f32", lattice=cfg.get("lattice", 0))
     try:
         stream = torch.cuda.current_stream().cuda_stream
-        Qt, probe = bench.tune_probe(cfg, bench.TUNE_Q)
-        sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:2],
-                    cfg["gG0"][:Qt], cfg["q_geom"][:Qt])
-        btl.btl_autotune(sim._h, Qt, probe, stream)
-        print(f"  launch {btl.btl_get_launch(sim._h)}", flush=True)
+        if launch is None:
+            Qt, probe = bench.tune_probe(cfg, bench.TUNE_Q)
+            sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:2],
+                        cfg["gG0"][:Qt], cfg["q_geom"][:Qt])
+            btl.btl_autotune(sim._h, Qt, probe, stream)
+        else:
+            btl.btl_set_launch(sim._h, *launch)
+        launch = btl.btl_get_launch(sim._h)
+        print(f"  launch {launch}", flush=True)
         out = sim.forward(cfg["dt"], cfg["D"], cfg["T2"], cfg["kappa"], cfg["f"][:K],
                           cfg["gG0"], cfg["q_geom"], want_M=want_M)
         torch.cuda.synchronize()
         if want_M:
-            return out[0].cpu().numpy(), {q: out[1][q].cpu().numpy() for q in keep_M}
+            return out[0].cpu().numpy(), {q: out[1][q].cpu().numpy() for q in keep_M}, launch
         return out.cpu().numpy()
     finally:
         sim.close()
@@ -72,7 +76,7 @@ def test_cfg3a_full_size_256_q_sampled():
     K = 20
     qs = [0, 97, 255]
     print("GPU cfg3a 256^3 x 256 q, K=20, E and M_final", flush=True)
-    Eg, Mg = _forward_autotuned(btl, cfg, K, want_M=True, keep_M=qs)
+    Eg, Mg, _ = _forward_autotuned(btl, cfg, K, want_M=True, keep_M=qs)
     Eo, Mo = _sampled(cfg, qs, K, want_M=True)
     _check(Eg[qs], Eo, "f32", "cfg3a sampled q")
     for i, q in enumerate(qs):
@@ -85,7 +89,7 @@ def test_cfg3b_full_size_ragged_sampled():
     K = 20
     qs = [0, 40, 95]          # geometries 0, 6 and 15
     print("GPU cfg3b 16 geometries 96^3..192^3, K=20, E and M_final", flush=True)
-    Eg, Mg = _forward_autotuned(btl, cfg, K, want_M=True, keep_M=qs)
+    Eg, Mg, _ = _forward_autotuned(btl, cfg, K, want_M=True, keep_M=qs)
     Eo, Mo = _sampled(cfg, qs, K, want_M=True)
     _check(Eg[qs], Eo, "f32", "cfg3b sampled q")
     for i, q in enumerate(qs):
@@ -98,7 +102,7 @@ def test_cfg5_full_size_sampled_and_decay():
     K = 20
     qs = [0, 31]
     print("GPU cfg5 512^3 x 32 q, K=20, E and M_final", flush=True)
-    Eg, Mg = _forward_autotuned(btl, cfg, K, want_M=True, keep_M=qs)
+    Eg, Mg, launch = _forward_autotuned(btl, cfg, K, want_M=True, keep_M=qs)
     Eo, Mo = _sampled(cfg, qs, K, want_M=True)
     _check(Eg[qs], Eo, "f32", "cfg5 sampled q")
     for i, q in enumerate(qs):
@@ -106,7 +110,7 @@ def test_cfg5_full_size_sampled_and_decay():
     # one T2 in every phase and no gradient: E_k = exp(-k dt / T2) for every
     # q-sample, over 40 steps, whatever the cells and membranes
     c = dict(cfg, T2=np.full(3, 70.0), gG0=np.zeros((4, 3)), q_geom=np.zeros(4, np.int32))
-    Eg = _forward_autotuned(btl, c, 40)
+    Eg = _forward_autotuned(btl, c, 40, launch=launch)
     k = np.arange(41)
     ref = np.exp(-k * cfg["dt"] / 70.0)
     assert np.max(np.abs(Eg - ref[None, :])) < 1e-6
