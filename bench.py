@@ -479,15 +479,21 @@ def main():
     traffic = None
     if args.prec == "f32" and args.membranes == "half-link" and scheme == 0:
         traffic = traffic_for((args.workload, "k_step"), source_hash(KERNEL_SRC), launch)
+    # the first step of an untaped hybrid forward without curved links starts
+    # from the equilibrium constants: it writes its state but reads none
+    fused = scheme == 0 and args.membranes != "curved"
+    bytes_fwd = K * bytes_step - (bytes_step / 2 if fused else 0)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname,
             "bytes_per_step_algorithmic": bytes_step,
             "ms_per_step_launches": kern_ms_step,
-            "frac_whole_forward": bytes_step / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "bytes_per_forward_algorithmic": bytes_fwd,
+            "frac_whole_forward": bytes_fwd / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "timing": "HIP events on the launch stream around forwards of K and of 2K steps "
                       f"(medians of {args.reps}); the step launches of one step (one per "
-                      "q-wave) take the difference over K; frac_whole_forward divides by the "
-                      "whole K-step forward (initial states, tables, signal sums included)"}
+                      "q-wave) take the difference over K; frac_whole_forward divides the "
+                      "forward's algorithmic bytes (K steps, the first of which reads no "
+                      "state) by the whole K-step forward (tables, signal sums included)"}
     out = {"metric": METRIC, "value": value, "unit": "site-updates/s", "n_gpus": 1,
            "steps": K, "warmup": W, "ms_per_step": ms_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",

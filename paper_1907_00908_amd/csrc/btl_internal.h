@@ -150,7 +150,9 @@ struct StepArgs {
     int32_t classical;      // 1: reaction term in the collision, no split
     int32_t nq;             // 7 (D3Q7) or 5 (D2Q5 on a single layer)
     int32_t xcd;            // 1: XCD-contiguous workgroup order (xcd_tile)
-    int32_t pad2;
+    int32_t first;          // 1: the step starts from the equilibrium state at M = 1,
+                            // which src does not hold (hybrid scheme without curved
+                            // links only; the step kernel uses the constants)
 };
 
 // Workgroup tile shapes (TX x TY threads, one site column along z each).
@@ -205,10 +207,12 @@ hipError_t launch_adj_final(const double* gfield, int32_t K, int32_t n_fields, i
                             double* df, int32_t sub, int32_t ng, const double* gmeta,
                             const double* fdt, const double* Fk, int32_t Q, double* dgG0,
                             double eps, int32_t yz_swap, int32_t* nonfinite, hipStream_t st);
+// The equilibrium state at M = 1 in pop and E_0 = 1 of every q-sample;
+// with pops false only E_0 (the first step then starts from the constants).
 hipError_t launch_init(int prec, void* pop, int64_t n_elem_per_dir_total,
                        const FieldDesc* d_fields, int32_t n_fields,
                        const FieldDesc* h_fields, double* E, int32_t Q, int32_t K, int32_t nq,
-                       hipStream_t st);
+                       hipStream_t st, bool pops = true);
 hipError_t launch_step(int prec, int shape, const StepArgs& a, int32_t n_blocks, hipStream_t st);
 // The arriving populations of the curved membrane links of every field into
 // the destination state (a.dst), from a.src, for step a.k (face factors from

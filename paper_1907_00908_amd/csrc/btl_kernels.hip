@@ -88,10 +88,12 @@ __global__ void __launch_bounds__(kBlock) k_tables(StepArgs a, int32_t nsteps) {
 // R = -i gamma (x.G0) f_{k+1} - 1/T2, the reaction term of the collision that
 // follows the moment M(t^{k+1}).  The last step stores the plain collision,
 // whose moment is M(t^K).
-template <typename V, int TX, bool CL, bool GM, int NQ, bool CV>
+template <typename V, int TX, bool CL, bool GM, int NQ, bool CV, bool FIRST>
 __device__ __forceinline__ void step_body(const StepArgs& a) {
     constexpr int TY = TX > 0 ? kBlock / TX : 1;
     constexpr double W0 = lattice_w0(NQ), W1 = lattice_w1(NQ);
+    static_assert(!FIRST || (!CL && !CV), "the first-step form is for the hybrid scheme "
+                                          "without curved links");
     // Plane p >= 1 moves along kernel direction kd(p): D3Q7 p itself; the
     // single-layer D2Q5 lattice runs with its y axis as the kernel's z axis
     // (planes 3, 4 pull along z), while site words and membrane positions
@@ -141,6 +143,22 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     // within +-2^31 elements, checked on the host)
     const V* __restrict__ src = static_cast<const V*>(a.src) + fd.pop;
     V* __restrict__ dst = static_cast<V*>(a.dst) + fd.pop;
+    // FIRST: the first step of a forward starts from the equilibrium at
+    // M = 1, where plane 0 holds w0 and every other plane w1 at every site;
+    // those constants, rounded to the storage type as a stored state would
+    // be, stand in for the loads (no initial state is written or read)
+    V cw0, cw1;
+    store2(&cw0, make_double2(W0, 0.0));
+    store2(&cw1, make_double2(W1, 0.0));
+    auto lds = [&](int32_t off, const V& c) -> V {
+        if constexpr (FIRST) {
+            (void)off;
+            return c;
+        } else {
+            (void)c;
+            return src[off];
+        }
+    };
     const uint32_t* __restrict__ words = a.words + fd.words;
     const float* __restrict__ gmt = GM && fd.gm >= 0 ? a.gm + fd.gm : nullptr;
     // curved membranes (CV): per pull link -1 or the link's term list
@@ -220,18 +238,18 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
         const int32_t s = j0 + st1 * j1 + st2 * j2;
         const int32_t sp = j0 + st1 * j1 + zs * j2;
         L.word = words[s];
-        L.g[0] = src[pop + sp];
-        L.g[1] = src[o1 + sp];
-        L.g[2] = src[o2 + sp];
+        L.g[0] = lds(pop + sp, cw0);
+        L.g[1] = lds(o1 + sp, cw1);
+        L.g[2] = lds(o2 + sp, cw1);
         if constexpr (NQ == 7) {
-            L.g[3] = src[o3 + sp];
-            L.g[4] = src[o4 + sp];
+            L.g[3] = lds(o3 + sp, cw1);
+            L.g[4] = lds(o4 + sp, cw1);
         }
-        L.g[pz + 1] = src[(j2 == n2 - 1 ? o6f : o6i) + sp];
+        L.g[pz + 1] = lds((j2 == n2 - 1 ? o6f : o6i) + sp, cw1);
 #pragma unroll
         for (int d = 1; d < NQ; ++d) {
             const int od = (d & 1) ? d + 1 : d - 1;
-            if (d != pz) L.own[d - 1] = src[pop + od * ps + sp];
+            if (d != pz) L.own[d - 1] = lds(pop + od * ps + sp, cw1);
         }
         if constexpr (GM) {
 #pragma unroll
@@ -295,16 +313,16 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 int32_t o[3];
                 G.d0 = __builtin_ctz(g0);
                 stencil_off(G.d0, o);
-                G.st0[0] = src[sp + o[0]];
-                G.st0[1] = src[sp + o[1]];
-                G.st0[2] = src[sp + o[2]];
+                G.st0[0] = lds(sp + o[0], cw1);
+                G.st0[1] = lds(sp + o[1], cw1);
+                G.st0[2] = lds(sp + o[2], cw1);
                 const uint32_t rest = g0 & (g0 - 1);
                 if (rest) {
                     G.d1 = __builtin_ctz(rest);
                     stencil_off(G.d1, o);
-                    G.st1[0] = src[sp + o[0]];
-                    G.st1[1] = src[sp + o[1]];
-                    G.st1[2] = src[sp + o[2]];
+                    G.st1[0] = lds(sp + o[0], cw1);
+                    G.st1[1] = lds(sp + o[1], cw1);
+                    G.st1[2] = lds(sp + o[2], cw1);
                 }
             }
         }
@@ -400,9 +418,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                     } else {
                         int32_t o3[3];
                         stencil_off(d, o3);
-                        a2 = ld2(src + sp + o3[0]);
-                        b2 = ld2(src + sp + o3[1]);
-                        b3 = ld2(src + sp + o3[2]);
+                        const V s0 = lds(sp + o3[0], cw1), s1 = lds(sp + o3[1], cw1),
+                                s2 = lds(sp + o3[2], cw1);
+                        a2 = ld2(&s0);
+                        b2 = ld2(&s1);
+                        b3 = ld2(&s2);
                     }
                     double2 r;
                     r.x = c.A[0] * o.x + c.A[1] * a2.x + c.A[2] * a3.x
@@ -459,8 +479,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     if (j0 < n0 && j1 < n1 && z0 < z1) {
         {
             const int32_t sp = j0 + st1 * j1 + zs * z0;
-            cz_g = src[(z0 == 0 ? o5f : o5i) + sp];
-            cz_o = src[pop + (pz + 1) * ps + sp];
+            cz_g = lds((z0 == 0 ? o5f : o5i) + sp, cw1);
+            cz_o = lds(pop + (pz + 1) * ps + sp, cw1);
         }
         if constexpr (GM || std::is_same<V, double2>::value) {
             // one site at a time: the general condition's stencil loads and
@@ -642,20 +662,20 @@ __global__ void __launch_bounds__(kBlock) k_esum(const double2* __restrict__ par
 // positions fits in 128 VGPRs when asked to, which raises the occupancy
 // from three to four waves per SIMD; the other variants keep the compiler's
 // choice (FP64 storage, one site in flight: 92 VGPRs, five waves).
-template <typename V, int TX, bool CL, bool GM, int NQ, bool CV>
+template <typename V, int TX, bool CL, bool GM, int NQ, bool CV, bool FIRST>
 __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
-    step_body<V, TX, CL, GM, NQ, CV>(a);
+    step_body<V, TX, CL, GM, NQ, CV, FIRST>(a);
 }
-template <typename V, int TX, bool CL, bool GM, int NQ, bool CV>
+template <typename V, int TX, bool CL, bool GM, int NQ, bool CV, bool FIRST>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_step_w4(StepArgs a) {
-    step_body<V, TX, CL, GM, NQ, CV>(a);
+    step_body<V, TX, CL, GM, NQ, CV, FIRST>(a);
 }
 // curved links in FP32 storage: held to three waves per SIMD
-template <typename V, int TX, bool CL, bool GM, int NQ, bool CV>
+template <typename V, int TX, bool CL, bool GM, int NQ, bool CV, bool FIRST>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_step_w3(StepArgs a) {
-    step_body<V, TX, CL, GM, NQ, CV>(a);
+    step_body<V, TX, CL, GM, NQ, CV, FIRST>(a);
 }
 
 // ghat^0 of the classical scheme: the collision of the equilibrium state
@@ -698,33 +718,60 @@ __global__ void __launch_bounds__(kBlock) k_mfinal(const V* pop, int64_t nsites,
 
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-hipError_t launch_init(int prec, void* pop, int64_t, const FieldDesc*, int32_t n_fields,
+// E_0 = 1 of the q-sample of every primary field (one thread per field).
+__global__ void __launch_bounds__(kBlock) k_e0(const FieldDesc* __restrict__ fields,
+                                               int32_t n_fields, double2* E, int32_t K) {
+    const int32_t f = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (f < n_fields && fields[f].q >= 0)
+        E[(int64_t)fields[f].q * (K + 1)] = make_double2(1.0, 0.0);
+}
+
+hipError_t launch_init(int prec, void* pop, int64_t, const FieldDesc* d_fields, int32_t n_fields,
                        const FieldDesc* h, double* E, int32_t, int32_t K, int32_t nq,
-                       hipStream_t st) {
+                       hipStream_t st, bool pops) {
+    if (!pops) {
+        if (E != nullptr && n_fields > 0)
+            hipLaunchKernelGGL(k_e0, dim3(grid_for(n_fields)), dim3(kBlock), 0, st, d_fields,
+                               n_fields, reinterpret_cast<double2*>(E), K);
+        return hipGetLastError();
+    }
     for (int f = 0; f < n_fields; ++f) {
         const int64_t ns = h[f].nsites, st2 = (int64_t)h[f].n[0] * h[f].n[1];
+        const dim3 grid(grid_for(ns * nq));
         if (prec == 1)
-            hipLaunchKernelGGL(k_init<float2>, dim3(grid_for(ns * nq)), dim3(kBlock), 0, st,
+            hipLaunchKernelGGL(k_init<float2>, grid, dim3(kBlock), 0, st,
                                static_cast<float2*>(pop) + h[f].pop, ns, st2,
                                reinterpret_cast<double2*>(E), h[f].q, K, nq);
         else
-            hipLaunchKernelGGL(k_init<double2>, dim3(grid_for(ns * nq)), dim3(kBlock), 0, st,
+            hipLaunchKernelGGL(k_init<double2>, grid, dim3(kBlock), 0, st,
                                static_cast<double2*>(pop) + h[f].pop, ns, st2,
                                reinterpret_cast<double2*>(E), h[f].q, K, nq);
     }
     return hipGetLastError();
 }
 
+template <typename V, bool CL, bool GM, int NQ, bool CV, int TX, bool FIRST>
+static void launch_txf(const StepArgs& a, int32_t n_blocks, hipStream_t st) {
+    if constexpr (std::is_same<V, float2>::value && !GM)
+        hipLaunchKernelGGL((k_step_w4<V, TX, CL, GM, NQ, CV, FIRST>), dim3(n_blocks), dim3(kBlock),
+                           0, st, a);
+    else if constexpr (std::is_same<V, float2>::value && CV)
+        hipLaunchKernelGGL((k_step_w3<V, TX, CL, GM, NQ, CV, FIRST>), dim3(n_blocks), dim3(kBlock),
+                           0, st, a);
+    else
+        hipLaunchKernelGGL((k_step<V, TX, CL, GM, NQ, CV, FIRST>), dim3(n_blocks), dim3(kBlock), 0,
+                           st, a);
+}
+
 template <typename V, bool CL, bool GM, int NQ, bool CV, int TX>
 static void launch_tx(const StepArgs& a, int32_t n_blocks, hipStream_t st) {
-    if constexpr (std::is_same<V, float2>::value && !GM)
-        hipLaunchKernelGGL((k_step_w4<V, TX, CL, GM, NQ, CV>), dim3(n_blocks), dim3(kBlock), 0, st,
-                           a);
-    else if constexpr (std::is_same<V, float2>::value && CV)
-        hipLaunchKernelGGL((k_step_w3<V, TX, CL, GM, NQ, CV>), dim3(n_blocks), dim3(kBlock), 0, st,
-                           a);
-    else
-        hipLaunchKernelGGL((k_step<V, TX, CL, GM, NQ, CV>), dim3(n_blocks), dim3(kBlock), 0, st, a);
+    if constexpr (!CL && !CV) {
+        if (a.first) {
+            launch_txf<V, CL, GM, NQ, CV, TX, true>(a, n_blocks, st);
+            return;
+        }
+    }
+    launch_txf<V, CL, GM, NQ, CV, TX, false>(a, n_blocks, st);
 }
 
 template <typename V, bool CL, bool GM, int NQ, bool CV>

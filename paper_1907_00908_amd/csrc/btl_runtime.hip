@@ -1197,8 +1197,12 @@ static btl_status enqueue_forward(btl_sim* s, const CallPlan& p, const CallBufs&
     const size_t state_bytes = (size_t)p.pop_elems * state_elem_bytes(s);
     const int32_t K = p.K;
     hipError_t err;
+    // without a tape, the classical scheme's initial collision or curved
+    // links (whose pass reads the state), the first step starts from the
+    // equilibrium constants and no initial state is written
+    const bool fused = K > 0 && !ckpt && !p.classical && !p.uses_cv;
     if ((err = launch_init(s->prec, b.pop[0], p.pop_elems, b.fields, p.n_fields, p.fl.data(), Eptr,
-                           p.Q, K, p.nq, q)) != hipSuccess)
+                           p.Q, K, p.nq, q, !fused)) != hipSuccess)
         return hip_fail(s, err, "init launch");
     if (p.classical && K > 0 &&
         (err = launch_init_classical(s->prec, b.pop[0], p.fl.data(), p.n_fields, s->words.p,
@@ -1220,6 +1224,7 @@ static btl_status enqueue_forward(btl_sim* s, const CallPlan& p, const CallBufs&
         a.src = b.pop[k & 1];
         a.dst = b.pop[(k + 1) & 1];
         a.k = k;
+        a.first = fused && k == 0 ? 1 : 0;
         if (p.uses_cv &&
             (err = launch_links(s->prec, a, s->cv_max_links, p.n_fields, q)) != hipSuccess)
             return hip_fail(s, err, "membrane link launch");
