@@ -174,9 +174,13 @@ def traffic_for(key, kernel_sha, launch):
         return None
     if t.get("kernel_sha") != kernel_sha:
         return None
-    if launch is not None and t.get("launch", t.get("forward_launch")) != launch:
-        return None
-    return t.get("bytes_per_step")
+    if launch is None or t.get("launch", t.get("forward_launch")) == launch:
+        return t.get("bytes_per_step")
+    # counters taken for other launches of the same kernel source
+    for o in t.get("other_launches", []):
+        if o.get("launch") == launch:
+            return o.get("bytes_per_step")
+    return None
 
 
 def cpu_baseline(cfg, budget_s: float = 25.0):
